@@ -1,0 +1,739 @@
+/*
+ * rmo.c -- plain, slow FP64 CPU oracle for the outer-region R-matrix energy loop.
+ *
+ * TEST INFRASTRUCTURE ONLY (see rmo.h).  Written for readability: every stage is
+ * the textbook definition or a published algorithm in its plain form, computed
+ * in long double.  No blocking, no fusion, no reordering beyond what the
+ * definitions state.
+ *
+ * Stage map (PSTGF paper):
+ *   form_R            eq. (rmatrix)
+ *   channel split     eps_i = E - e_i, open iff eps_i > 0 (text after eq. (radial))
+ *   open_channel      Coulomb F, G at r = a (section "Overview", asymptotic form)
+ *   closed_channel    exponentially decaying Whittaker function at r = a (Glossary)
+ *   match_and_solve   eq. (match) with the asymptotic forms substituted
+ *   s_and_omega       Glossary: T-matrix, collision strength
+ */
+#include "rmo.h"
+
+#include <complex.h>
+#include <float.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef long double ld;
+typedef long double _Complex cld;
+
+#define CF_TOL 1e-17L        /* relative agreement of successive depths */
+#define CF_MAXDEPTH (1 << 22) /* iteration cap -> RMO_PT_NOCONV */
+
+static double nan_value(void) { return (double)NAN; }
+
+/* ------------------------------------------------------------------------- */
+/* Stage 1: R-matrix, eq. (rmatrix): R_ij = (1/2a) sum_k w_ik w_jk / (E_k - E) */
+/* ------------------------------------------------------------------------- */
+static int32_t form_R_one(const rmo_pw *pw, double E, double *R) {
+  const int n = pw->nchan, M = pw->npole;
+  for (int k = 0; k < M; ++k)
+    if (pw->Ek[k] == E) {
+      for (long t = 0; t < (long)n * n; ++t) R[t] = nan_value();
+      return RMO_PT_POLE;
+    }
+  /* lower triangle, row i holds columns 0..i */
+  ld *acc = (ld *)calloc((size_t)n * (n + 1) / 2, sizeof(ld));
+  for (int k = 0; k < M; ++k) {
+    const double *wk = pw->w + (size_t)k * n;
+    const ld d = 1.0L / ((ld)pw->Ek[k] - (ld)E);
+    for (int i = 0; i < n; ++i) {
+      const ld wi = (ld)wk[i] * d;
+      ld *row = acc + (size_t)i * (i + 1) / 2;
+      for (int j = 0; j <= i; ++j) row[j] += wi * (ld)wk[j];
+    }
+  }
+  const ld scale = 1.0L / (2.0L * (ld)pw->a);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j <= i; ++j) {
+      const double v = (double)(acc[(size_t)i * (i + 1) / 2 + j] * scale);
+      R[(size_t)i * n + j] = v;
+      R[(size_t)j * n + i] = v;
+    }
+  free(acc);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Radial ODE u'' = (l(l+1)/r^2 - 2z/r - eps) u, Taylor-series steps inward.   */
+/* The only singular point is r = 0, so a series about r0 converges for       */
+/* |h| < r0; steps use |h| <= r0/2 and at most ~1.5 local wavelengths/decay    */
+/* lengths.  Coefficients follow from (r0+x)^2 u'' = (L2 - 2z(r0+x) -          */
+/* eps (r0+x)^2) u, written for d_n = c_n h^n.                                */
+/* ------------------------------------------------------------------------- */
+static int taylor_inward(ld z, ld eps, ld L2, ld r0, ld r1, ld *u, ld *up, int renorm) {
+  ld r = r0, U = *u, Up = *up;
+  long steps = 0;
+  enum { NT = 400 };
+  ld d[NT + 3];
+  while (r > r1) {
+    ld kl = sqrtl(fabsl(eps + 2.0L * z / r - L2 / (r * r))) + 1e-3L;
+    ld h = -fminl(0.5L * r, 1.5L / kl);
+    if (r + h < r1) h = r1 - r;
+    const ld A = L2 - 2.0L * z * r - eps * r * r;
+    const ld B = -(2.0L * z + 2.0L * eps * r);
+    const ld C = -eps;
+    d[0] = U;
+    d[1] = Up * h;
+    ld su = d[0] + d[1], sd = d[1];
+    int small = 0, n;
+    for (n = 0; n < NT; ++n) {
+      const ld dm1 = n >= 1 ? d[n - 1] : 0.0L;
+      const ld dm2 = n >= 2 ? d[n - 2] : 0.0L;
+      const ld num = (A - (ld)n * (n - 1)) * d[n] * h * h - 2.0L * r * (ld)n * (n + 1) * d[n + 1] * h +
+                     B * dm1 * h * h * h + C * dm2 * h * h * h * h;
+      d[n + 2] = num / (r * r * (ld)(n + 1) * (n + 2));
+      su += d[n + 2];
+      sd += (ld)(n + 2) * d[n + 2];
+      if (fabsl(d[n + 2]) < 1e-22L * (fabsl(su) + fabsl(sd))) {
+        if (++small >= 3) break;
+      } else {
+        small = 0;
+      }
+    }
+    if (n >= NT) return -1;
+    U = su;
+    Up = sd / h;
+    if (renorm) {
+      const ld s = 1.0L / fmaxl(fabsl(U), fabsl(Up));
+      U *= s;
+      Up *= s;
+    }
+    r += h;
+    if (++steps > 50000000L) return -1;
+  }
+  *u = U;
+  *up = Up;
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Coulomb functions by Steed's method (Barnett, Feng, Steed & Goldfarb,      */
+/* Comput. Phys. Commun. 8 (1974) 377), with two changes of evaluation order:  */
+/*  - CF1 (F'/F) is summed backward from a depth that is doubled until the    */
+/*    value is stable; the sign of F_l follows from the signs of the          */
+/*    denominators (F_L > 0 at large L).                                      */
+/*  - CF2 ((G'+iF')/(G+iF)) is rewritten so that the large leading term       */
+/*    i(1 - eta/rho) cancels analytically: with beta_n = rho - eta + i n and   */
+/*    c_n = rho^2 - 2 eta rho - l(l+1) + i rho (2n-1), the tails               */
+/*    v_n = (c_n + beta_n v_{n+1}) / (beta_n - i + v_{n+1}) give              */
+/*    (G'+iF')/(G+iF) = (1 + i v_1) / rho.                                    */
+/* ------------------------------------------------------------------------- */
+static ld cf1_at_depth(ld eta, ld rho, int l, int Lmax, int *sign) {
+  ld f = (ld)(Lmax + 1) / rho;
+  int sg = 1;
+  for (int L = Lmax - 1; L >= l; --L) {
+    const ld Lp = (ld)(L + 1);
+    const ld S = Lp / rho + eta / Lp;
+    const ld R2 = 1.0L + eta * eta / (Lp * Lp);
+    const ld den = S + f;
+    if (den < 0) sg = -sg;
+    f = S - R2 / den;
+  }
+  *sign = sg;
+  return f;
+}
+
+static int cf1(ld eta, ld rho, int l, ld *f, int *sign) {
+  const ld Ltp = sqrtl(rho * rho + 2.0L * fabsl(eta) * rho);
+  int extra = 2 * (int)Ltp + 60;
+  ld prev = cf1_at_depth(eta, rho, l, l + extra, sign);
+  for (int it = 0; it < 20; ++it) {
+    extra *= 2;
+    int sg;
+    const ld cur = cf1_at_depth(eta, rho, l, l + extra, &sg);
+    if (fabsl(cur - prev) <= CF_TOL * fabsl(cur)) {
+      *f = cur;
+      *sign = sg;
+      return 0;
+    }
+    prev = cur;
+  }
+  return -1;
+}
+
+static cld cf2_at_depth(ld eta, ld rho, int l, long N) {
+  const ld L2 = (ld)l * (l + 1);
+  const ld cre = rho * rho - 2.0L * eta * rho - L2;
+  /* tail estimate: fixed point of the last map, v^2 - i v - c = 0 */
+  const cld cN = cre + I * rho * (ld)(2 * (N + 1) - 1);
+  cld v = (I + csqrtl(-1.0L + 4.0L * cN)) / 2.0L;
+  for (long n = N; n >= 1; --n) {
+    const cld c = cre + I * rho * (ld)(2 * n - 1);
+    const cld beta = (rho - eta) + I * (ld)n;
+    v = (c + beta * v) / (beta - I + v);
+  }
+  return (1.0L + I * v) / rho;
+}
+
+static int cf2(ld eta, ld rho, int l, ld *p, ld *q) {
+  long N = 32;
+  cld prev = cf2_at_depth(eta, rho, l, N);
+  while (N < CF_MAXDEPTH) {
+    N *= 2;
+    const cld cur = cf2_at_depth(eta, rho, l, N);
+    if (cabsl(cur - prev) <= CF_TOL * cabsl(cur)) {
+      *p = creall(cur);
+      *q = cimagl(cur);
+      return 0;
+    }
+    prev = cur;
+  }
+  return -1;
+}
+
+/* F, F', G, G' (derivatives w.r.t. rho) at rho; returns -1 if a series or
+   continued fraction did not converge. */
+static int coulomb_fg(ld eta, ld rho, int l, ld out[4]) {
+  const ld L2 = (ld)l * (l + 1);
+  /* outer turning point rho_tp = eta + sqrt(eta^2 + l(l+1)), written without
+     cancellation for eta < 0 */
+  ld rtp;
+  if (L2 == 0)
+    rtp = eta > 0 ? 2.0L * eta : 0.0L;
+  else
+    rtp = eta <= 0 ? L2 / (sqrtl(eta * eta + L2) - eta) : eta + sqrtl(eta * eta + L2);
+  const ld rm = rho >= rtp ? rho : rtp;
+  ld p, q, fm;
+  int sg;
+  if (cf2(eta, rm, l, &p, &q) || cf1(eta, rm, l, &fm, &sg)) return -1;
+  ld F = (ld)sg / sqrtl((fm - p) * (fm - p) / q + q);
+  ld Fp = fm * F;
+  ld G = (fm - p) * F / q;
+  ld Gp = p * G - q * F;
+  if (rm > rho) {
+    /* inside the turning point G grows inward: integrate it from rm to rho,
+       then F from CF1 at rho and the Wronskian F'G - FG' = 1 */
+    ld g = G, gp = Gp;
+    if (taylor_inward(1.0L * -eta, 1.0L, L2, rm, rho, &g, &gp, 0)) return -1;
+    ld f;
+    if (cf1(eta, rho, l, &f, &sg)) return -1;
+    G = g;
+    Gp = gp;
+    F = 1.0L / (f * G - Gp);
+    Fp = f * F;
+  }
+  out[0] = F;
+  out[1] = Fp;
+  out[2] = G;
+  out[3] = Gp;
+  return 0;
+}
+/* note: in the rho variable the Coulomb equation reads
+   u'' = (l(l+1)/rho^2 + 2 eta/rho - 1) u, i.e. the radial ODE above with
+   z -> -eta and eps -> 1, which is how taylor_inward is called. */
+
+/* ------------------------------------------------------------------------- */
+/* Closed channels.  The decaying solution is W_{nu,l+1/2}(2 kappa r),         */
+/* nu = z/kappa.  Continuing CF2 to k = i kappa (rho = i kappa r, eta = i nu)  */
+/* makes the v-recursion real: with b_n = kappa r - nu + n and                 */
+/* c_n = 2 z r - kappa^2 r^2 - l(l+1) - kappa r (2n-1),                        */
+/* w_n = (b_n w_{n+1} - c_n) / (b_n - 1 + w_{n+1}) and W'/W = (1 - w_1)/r.     */
+/* The backward recursion is stable only where b_1 > 0, i.e. r > (nu-1)/kappa; */
+/* it is evaluated at rs = max(a, (nu+2)/kappa) and the solution is carried    */
+/* inward to a with Taylor steps (W grows inward beyond the turning point and  */
+/* oscillates inside it, so inward integration is stable).                    */
+/* ------------------------------------------------------------------------- */
+static ld closed_cf_at_depth(ld z, ld kap, ld r, int l, long N) {
+  const ld nu = z / kap, L2 = (ld)l * (l + 1);
+  const ld base = 2.0L * z * r - kap * kap * r * r - L2;
+  const ld cN = base - kap * r * (ld)(2 * (N + 1) - 1);
+  const ld disc = 1.0L - 4.0L * cN;
+  ld w = disc > 0 ? (1.0L + sqrtl(disc)) / 2.0L : 0.0L;
+  for (long n = N; n >= 1; --n) {
+    const ld c = base - kap * r * (ld)(2 * n - 1);
+    const ld b = kap * r - nu + (ld)n;
+    w = (b * w - c) / (b - 1.0L + w);
+  }
+  return (1.0L - w) / r;
+}
+
+static int closed_logderiv_at(ld z, ld kap, ld r, int l, ld *L) {
+  long N = 32;
+  ld prev = closed_cf_at_depth(z, kap, r, l, N);
+  while (N < CF_MAXDEPTH) {
+    N *= 2;
+    const ld cur = closed_cf_at_depth(z, kap, r, l, N);
+    if (fabsl(cur - prev) <= CF_TOL * fabsl(cur) + 1e-300L) {
+      *L = cur;
+      return 0;
+    }
+    prev = cur;
+  }
+  return -1;
+}
+
+/* (W, W') at r = a up to a common positive or negative factor */
+static int closed_uw(ld z, ld eps, ld a, int l, ld *u, ld *up) {
+  const ld kap = sqrtl(-eps), nu = z / kap;
+  const ld rs = fmaxl(a, (nu + 2.0L) / kap);
+  ld L;
+  if (closed_logderiv_at(z, kap, rs, l, &L)) return -1;
+  ld U = 1.0L, Up = L;
+  if (rs > a && taylor_inward(z, eps, (ld)l * (l + 1), rs, a, &U, &Up, 1)) return -1;
+  *u = U;
+  *up = Up;
+  return 0;
+}
+
+/* channel functions at r = a */
+static int channel_fn(ld z, ld eps, ld a, int l, ld out[4]) {
+  if (eps > 0) {
+    const ld k = sqrtl(eps), eta = -z / k, rho = k * a;
+    ld fg[4];
+    if (coulomb_fg(eta, rho, l, fg)) return -1;
+    const ld sk = sqrtl(k);
+    out[0] = fg[0] / sk; /* s  */
+    out[1] = fg[1] * sk; /* s' (d/dr = k d/drho) */
+    out[2] = fg[2] / sk; /* c  */
+    out[3] = fg[3] * sk; /* c' */
+    return 0;
+  }
+  ld u, up;
+  if (closed_uw(z, eps, a, l, &u, &up)) return -1;
+  ld nrm = sqrtl(u * u + a * a * up * up);
+  if (u < 0 || (u == 0 && up < 0)) nrm = -nrm;
+  out[0] = 0;
+  out[1] = 0;
+  out[2] = u / nrm;
+  out[3] = up / nrm;
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Dense linear algebra (long double, plain Gaussian elimination).            */
+/* ------------------------------------------------------------------------- */
+/* LU with partial pivoting in place, row-major n x n; piv[i] = row swapped in */
+static int lu_factor(ld *A, int n, int *piv) {
+  for (int c = 0; c < n; ++c) {
+    int p = c;
+    ld best = fabsl(A[(size_t)c * n + c]);
+    for (int r = c + 1; r < n; ++r)
+      if (fabsl(A[(size_t)r * n + c]) > best) {
+        best = fabsl(A[(size_t)r * n + c]);
+        p = r;
+      }
+    piv[c] = p;
+    if (best == 0) return -1;
+    if (p != c)
+      for (int j = 0; j < n; ++j) {
+        ld t = A[(size_t)c * n + j];
+        A[(size_t)c * n + j] = A[(size_t)p * n + j];
+        A[(size_t)p * n + j] = t;
+      }
+    const ld inv = 1.0L / A[(size_t)c * n + c];
+    for (int r = c + 1; r < n; ++r) {
+      const ld m = A[(size_t)r * n + c] * inv;
+      A[(size_t)r * n + c] = m;
+      if (m != 0)
+        for (int j = c + 1; j < n; ++j) A[(size_t)r * n + j] -= m * A[(size_t)c * n + j];
+    }
+  }
+  return 0;
+}
+
+/* solve A x = b (trans = 0) or A^T x = b (trans = 1) with the LU above */
+static void lu_solve(const ld *LU, int n, const int *piv, ld *x, int trans) {
+  if (!trans) {
+    for (int c = 0; c < n; ++c)
+      if (piv[c] != c) {
+        ld t = x[c];
+        x[c] = x[piv[c]];
+        x[piv[c]] = t;
+      }
+    for (int r = 0; r < n; ++r)
+      for (int j = 0; j < r; ++j) x[r] -= LU[(size_t)r * n + j] * x[j];
+    for (int r = n - 1; r >= 0; --r) {
+      for (int j = r + 1; j < n; ++j) x[r] -= LU[(size_t)r * n + j] * x[j];
+      x[r] /= LU[(size_t)r * n + r];
+    }
+  } else {
+    /* A = P^T L U  ->  A^T = U^T L^T P */
+    for (int r = 0; r < n; ++r) {
+      for (int j = 0; j < r; ++j) x[r] -= LU[(size_t)j * n + r] * x[j];
+      x[r] /= LU[(size_t)r * n + r];
+    }
+    for (int r = n - 1; r >= 0; --r)
+      for (int j = r + 1; j < n; ++j) x[r] -= LU[(size_t)j * n + r] * x[j];
+    for (int c = n - 1; c >= 0; --c)
+      if (piv[c] != c) {
+        ld t = x[c];
+        x[c] = x[piv[c]];
+        x[piv[c]] = t;
+      }
+  }
+}
+
+/* Hager's 1-norm estimate of ||A^-1||_1 (Hager 1984, with Higham's 1988
+   refinements as used in LAPACK xLACON) times ||A||_1. */
+static ld cond1_estimate(const ld *A, const ld *LU, int n, const int *piv) {
+  ld anorm = 0;
+  for (int j = 0; j < n; ++j) {
+    ld s = 0;
+    for (int i = 0; i < n; ++i) s += fabsl(A[(size_t)i * n + j]);
+    if (s > anorm) anorm = s;
+  }
+  ld *x = (ld *)malloc(sizeof(ld) * n), *y = (ld *)malloc(sizeof(ld) * n);
+  for (int i = 0; i < n; ++i) x[i] = 1.0L / n;
+  ld est = 0;
+  int jlast = -1;
+  for (int it = 0; it < 5; ++it) {
+    memcpy(y, x, sizeof(ld) * n);
+    lu_solve(LU, n, piv, y, 0);
+    ld ny = 0;
+    for (int i = 0; i < n; ++i) ny += fabsl(y[i]);
+    if (it > 0 && ny <= est) break;
+    est = ny;
+    for (int i = 0; i < n; ++i) y[i] = y[i] >= 0 ? 1.0L : -1.0L;
+    lu_solve(LU, n, piv, y, 1);
+    int j = 0;
+    for (int i = 1; i < n; ++i)
+      if (fabsl(y[i]) > fabsl(y[j])) j = i;
+    if (j == jlast) break;
+    jlast = j;
+    for (int i = 0; i < n; ++i) x[i] = 0;
+    x[j] = 1;
+  }
+  /* alternative vector x_i = (-1)^i (1 + i/(n-1)) */
+  for (int i = 0; i < n; ++i) x[i] = (i % 2 ? -1.0L : 1.0L) * (1.0L + (n > 1 ? (ld)i / (n - 1) : 0));
+  lu_solve(LU, n, piv, x, 0);
+  ld alt = 0;
+  for (int i = 0; i < n; ++i) alt += fabsl(x[i]);
+  alt = 2.0L * alt / (3.0L * n);
+  if (alt > est) est = alt;
+  free(x);
+  free(y);
+  return anorm * est;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Matching, eq. (match): F(a) = R (a F'(a) - b F(a)), with F_ij = s_i d_ij +  */
+/* c_i K_ij on open rows and e_i X_ij on closed rows.  Writing C_i = c_i (open) */
+/* or e_i (closed) and Y = [K; X] gives A Y = B with                          */
+/*   A_im = d_im C_i - R_im (a C'_m - b C_m)                                   */
+/*   B_ij = R_{i,o_j} (a s'_{o_j} - b s_{o_j}) - d_{i,o_j} s_{o_j}             */
+/* ------------------------------------------------------------------------- */
+static int open_list(const rmo_pw *pw, double E, int *idx);
+
+static int32_t solve_K_one(const rmo_pw *pw, double E, const double *R, const double *fg, double *K,
+                           double *cond) {
+  const int n = pw->nchan;
+  const ld a = pw->a, b = pw->b;
+  int *open_idx = (int *)malloc(sizeof(int) * (n + 1));
+  const int no = open_list(pw, E, open_idx);
+  for (long t = 0; t < (long)n * n; ++t) K[t] = 0.0;
+  if (cond) *cond = 0;
+  if (no == 0) {
+    free(open_idx);
+    return 0;
+  }
+  ld *A = (ld *)malloc(sizeof(ld) * (size_t)n * n);
+  ld *LU = (ld *)malloc(sizeof(ld) * (size_t)n * n);
+  ld *Y = (ld *)malloc(sizeof(ld) * (size_t)n * no);
+  int *piv = (int *)malloc(sizeof(int) * n);
+  for (int i = 0; i < n; ++i)
+    for (int m = 0; m < n; ++m) {
+      const ld Cm = fg[4 * m + 2], Cpm = fg[4 * m + 3];
+      A[(size_t)i * n + m] = (i == m ? (ld)fg[4 * i + 2] : 0.0L) - (ld)R[(size_t)i * n + m] * (a * Cpm - b * Cm);
+    }
+  memcpy(LU, A, sizeof(ld) * (size_t)n * n);
+  int32_t st = 0;
+  if (lu_factor(LU, n, piv)) {
+    st = RMO_PT_SINGULAR;
+  } else {
+    ld *col = (ld *)malloc(sizeof(ld) * n);
+    for (int j = 0; j < no; ++j) {
+      const int oj = open_idx[j];
+      const ld s = fg[4 * oj + 0], sp = fg[4 * oj + 1];
+      for (int i = 0; i < n; ++i) col[i] = (ld)R[(size_t)i * n + oj] * (a * sp - b * s) - (i == oj ? s : 0.0L);
+      lu_solve(LU, n, piv, col, 0);
+      for (int i = 0; i < n; ++i) Y[(size_t)i * no + j] = col[i];
+    }
+    free(col);
+    for (int i = 0; i < no; ++i)
+      for (int j = 0; j < no; ++j) K[(size_t)i * n + j] = (double)Y[(size_t)open_idx[i] * no + j];
+    if (cond) *cond = (double)cond1_estimate(A, LU, n, piv);
+  }
+  free(A);
+  free(LU);
+  free(Y);
+  free(piv);
+  free(open_idx);
+  return st;
+}
+
+/* ------------------------------------------------------------------------- */
+/* S = (1 + iK)(1 - iK)^-1 by complex Gaussian elimination, T = S - 1,         */
+/* Omega_pq = (g/2) sum_{i in p, j in q, open} |T_ij|^2.                       */
+/* ------------------------------------------------------------------------- */
+static int32_t s_and_omega_one(const rmo_pw *pw, const double *K, int no, const int *open_idx,
+                               double *omega, double *S) {
+  const int n = pw->nchan, nt = pw->ntarget;
+  for (long t = 0; t < (long)nt * nt; ++t) omega[t] = 0.0;
+  if (S)
+    for (long t = 0; t < 2L * n * n; ++t) S[t] = 0.0;
+  if (no == 0) return 0;
+  /* M = (1 - iK), augmented with (1 + iK)^T so that solving M^T X^T = (1+iK)^T
+     gives X = (1 + iK) M^-1 */
+  cld *Mt = (cld *)malloc(sizeof(cld) * (size_t)no * no);
+  cld *rhs = (cld *)malloc(sizeof(cld) * (size_t)no * no);
+  for (int i = 0; i < no; ++i)
+    for (int j = 0; j < no; ++j) {
+      const ld kij = K[(size_t)i * n + j], kji = K[(size_t)j * n + i];
+      Mt[(size_t)i * no + j] = (i == j ? 1.0L : 0.0L) - I * kji;  /* (1 - iK)^T */
+      rhs[(size_t)i * no + j] = (i == j ? 1.0L : 0.0L) + I * kji; /* (1 + iK)^T */
+      (void)kij;
+    }
+  /* Gaussian elimination with partial pivoting on Mt, applied to rhs columns */
+  int32_t st = 0;
+  for (int c = 0; c < no && !st; ++c) {
+    int p = c;
+    ld best = cabsl(Mt[(size_t)c * no + c]);
+    for (int r = c + 1; r < no; ++r)
+      if (cabsl(Mt[(size_t)r * no + c]) > best) {
+        best = cabsl(Mt[(size_t)r * no + c]);
+        p = r;
+      }
+    if (best == 0) {
+      st = RMO_PT_SINGULAR;
+      break;
+    }
+    if (p != c)
+      for (int j = 0; j < no; ++j) {
+        cld t = Mt[(size_t)c * no + j];
+        Mt[(size_t)c * no + j] = Mt[(size_t)p * no + j];
+        Mt[(size_t)p * no + j] = t;
+        t = rhs[(size_t)c * no + j];
+        rhs[(size_t)c * no + j] = rhs[(size_t)p * no + j];
+        rhs[(size_t)p * no + j] = t;
+      }
+    for (int r = c + 1; r < no; ++r) {
+      const cld m = Mt[(size_t)r * no + c] / Mt[(size_t)c * no + c];
+      if (m == 0) continue;
+      for (int j = c; j < no; ++j) Mt[(size_t)r * no + j] -= m * Mt[(size_t)c * no + j];
+      for (int j = 0; j < no; ++j) rhs[(size_t)r * no + j] -= m * rhs[(size_t)c * no + j];
+    }
+  }
+  if (!st) {
+    for (int r = no - 1; r >= 0; --r)
+      for (int j = 0; j < no; ++j) {
+        cld acc = rhs[(size_t)r * no + j];
+        for (int q = r + 1; q < no; ++q) acc -= Mt[(size_t)r * no + q] * rhs[(size_t)q * no + j];
+        rhs[(size_t)r * no + j] = acc / Mt[(size_t)r * no + r];
+      }
+    /* rhs now holds X^T with X = S */
+    const ld half_g = 0.5L * (ld)pw->g;
+    ld *om = (ld *)calloc((size_t)nt * nt, sizeof(ld));
+    for (int i = 0; i < no; ++i)
+      for (int j = 0; j < no; ++j) {
+        const cld Sij = rhs[(size_t)j * no + i];
+        const cld Tij = Sij - (i == j ? 1.0L : 0.0L);
+        const ld t2 = creall(Tij) * creall(Tij) + cimagl(Tij) * cimagl(Tij);
+        om[(size_t)pw->target[open_idx[i]] * nt + pw->target[open_idx[j]]] += half_g * t2;
+        if (S) {
+          S[2 * ((size_t)i * n + j) + 0] = (double)creall(Sij);
+          S[2 * ((size_t)i * n + j) + 1] = (double)cimagl(Sij);
+        }
+      }
+    for (long t = 0; t < (long)nt * nt; ++t) omega[t] = (double)om[t];
+    free(om);
+  }
+  free(Mt);
+  free(rhs);
+  return st;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Per-energy drivers                                                         */
+/* ------------------------------------------------------------------------- */
+static int32_t asym_one(const rmo_pw *pw, double E, double thr_guard, double *fg, int8_t *open,
+                        int32_t *nopen) {
+  const int n = pw->nchan;
+  int32_t st = 0;
+  int no = 0;
+  for (int i = 0; i < n; ++i) {
+    const ld eps = (ld)E - (ld)pw->e_thr[i];
+    double *o = fg + 4 * i;
+    open[i] = eps > 0;
+    if (eps > 0) no++;
+    if (fabsl(eps) < (ld)thr_guard) {
+      st |= RMO_PT_THRESHOLD;
+      o[0] = o[1] = o[2] = o[3] = nan_value();
+      continue;
+    }
+    ld v[4];
+    if (channel_fn((ld)pw->z, eps, (ld)pw->a, pw->l[i], v)) {
+      st |= RMO_PT_NOCONV;
+      o[0] = o[1] = o[2] = o[3] = nan_value();
+      continue;
+    }
+    for (int t = 0; t < 4; ++t) o[t] = (double)v[t];
+  }
+  *nopen = no;
+  return st;
+}
+
+static void fill_nan(double *x, long count) {
+  for (long t = 0; t < count; ++t) x[t] = nan_value();
+}
+
+static int all_finite(const double *x, long count) {
+  for (long t = 0; t < count; ++t)
+    if (!isfinite(x[t])) return 0;
+  return 1;
+}
+
+static void set_threads(int32_t nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+}
+
+int rmo_form_R(const rmo_pw *pw, const double *E, int32_t ne, double *R, int32_t *status,
+               int32_t nthreads) {
+  const long nn = (long)pw->nchan * pw->nchan;
+  set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int e = 0; e < ne; ++e) status[e] = form_R_one(pw, E[e], R + e * nn);
+  return 0;
+}
+
+int rmo_asymptotic(const rmo_pw *pw, const double *E, int32_t ne, double thr_guard, double *fg,
+                   int8_t *open, int32_t *nopen, int32_t *status, int32_t nthreads) {
+  const int n = pw->nchan;
+  set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int e = 0; e < ne; ++e)
+    status[e] = asym_one(pw, E[e], thr_guard, fg + (long)e * n * 4, open + (long)e * n, nopen + e);
+  return 0;
+}
+
+int rmo_solve_K(const rmo_pw *pw, const double *E, int32_t ne, const double *R, const double *fg,
+                double thr_guard, double *K, double *cond, int32_t *status, int32_t nthreads) {
+  const int n = pw->nchan;
+  const long nn = (long)n * n;
+  set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int e = 0; e < ne; ++e) {
+    int32_t st = 0;
+    for (int k = 0; k < pw->npole; ++k)
+      if (pw->Ek[k] == E[e]) st |= RMO_PT_POLE;
+    for (int i = 0; i < n; ++i)
+      if (fabs(E[e] - pw->e_thr[i]) < thr_guard) st |= RMO_PT_THRESHOLD;
+    if (!all_finite(R + e * nn, nn) || !all_finite(fg + (long)e * n * 4, 4L * n)) st |= RMO_PT_NONFINITE;
+    if (st) {
+      fill_nan(K + e * nn, nn);
+      if (cond) cond[e] = nan_value();
+    } else {
+      st = solve_K_one(pw, E[e], R + e * nn, fg + (long)e * n * 4, K + e * nn, cond ? cond + e : NULL);
+      if (st) fill_nan(K + e * nn, nn);
+    }
+    status[e] = st;
+  }
+  return 0;
+}
+
+static int open_list(const rmo_pw *pw, double E, int *idx) {
+  int no = 0;
+  for (int i = 0; i < pw->nchan; ++i)
+    if ((ld)E - (ld)pw->e_thr[i] > 0) idx[no++] = i;
+  return no;
+}
+
+int rmo_collision_strengths(const rmo_pw *pw, const double *E, int32_t ne, const double *K,
+                            double thr_guard, double *omega, double *S, int32_t *status,
+                            int32_t nthreads) {
+  const int n = pw->nchan, nt = pw->ntarget;
+  const long nn = (long)n * n;
+  set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int e = 0; e < ne; ++e) {
+    int *idx = (int *)malloc(sizeof(int) * (n + 1));
+    const int no = open_list(pw, E[e], idx);
+    int32_t st = 0;
+    for (int i = 0; i < n; ++i)
+      if (fabs(E[e] - pw->e_thr[i]) < thr_guard) st |= RMO_PT_THRESHOLD;
+    for (int i = 0; i < no && !st; ++i)
+      for (int j = 0; j < no; ++j)
+        if (!isfinite(K[e * nn + (long)i * n + j])) st |= RMO_PT_NONFINITE;
+    if (!st) st = s_and_omega_one(pw, K + e * nn, no, idx, omega + (long)e * nt * nt, S ? S + 2 * e * nn : NULL);
+    if (st) {
+      fill_nan(omega + (long)e * nt * nt, (long)nt * nt);
+      if (S) fill_nan(S + 2 * e * nn, 2 * nn);
+    }
+    status[e] = st;
+    free(idx);
+  }
+  return 0;
+}
+
+int rmo_run(const rmo_pw *pw, const double *E, int32_t ne, double thr_guard, double *omega,
+            double *K, double *S, double *cond, int32_t *status, int32_t nthreads) {
+  const int n = pw->nchan, nt = pw->ntarget;
+  const long nn = (long)n * n;
+  set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int e = 0; e < ne; ++e) {
+    double *R = (double *)malloc(sizeof(double) * nn);
+    double *fg = (double *)malloc(sizeof(double) * 4 * n);
+    double *Kl = K ? K + e * nn : (double *)malloc(sizeof(double) * nn);
+    int8_t *op = (int8_t *)malloc(n);
+    int *idx = (int *)malloc(sizeof(int) * (n + 1));
+    int32_t no = 0;
+    int32_t st = form_R_one(pw, E[e], R);
+    st |= asym_one(pw, E[e], thr_guard, fg, op, &no);
+    if (!st && (!all_finite(R, nn) || !all_finite(fg, 4L * n))) st |= RMO_PT_NONFINITE;
+    if (!st) st = solve_K_one(pw, E[e], R, fg, Kl, cond ? cond + e : NULL);
+    if (!st) {
+      const int no2 = open_list(pw, E[e], idx);
+      st = s_and_omega_one(pw, Kl, no2, idx, omega + (long)e * nt * nt, S ? S + 2 * e * nn : NULL);
+    }
+    if (st) {
+      fill_nan(Kl, nn);
+      fill_nan(omega + (long)e * nt * nt, (long)nt * nt);
+      if (S) fill_nan(S + 2 * e * nn, 2 * nn);
+      if (cond) cond[e] = nan_value();
+    }
+    status[e] = st;
+    if (!K) free(Kl);
+    free(R);
+    free(fg);
+    free(op);
+    free(idx);
+  }
+  return 0;
+}
+
+int rmo_coulomb(double eta, double rho, int32_t l, double out[4]) {
+  ld v[4];
+  if (coulomb_fg(eta, rho, l, v)) return -1;
+  for (int t = 0; t < 4; ++t) out[t] = (double)v[t];
+  return 0;
+}
+
+int rmo_closed_logderiv(double z, double eps, double r, int32_t l, double *L) {
+  ld u, up;
+  if (closed_uw(z, eps, r, l, &u, &up)) return -1;
+  *L = (double)(up / u);
+  return 0;
+}
+
+int rmo_channel(double z, double eps, double a, int32_t l, double out[4]) {
+  ld v[4];
+  if (channel_fn(z, eps, a, l, v)) return -1;
+  for (int t = 0; t < 4; ++t) out[t] = (double)v[t];
+  return 0;
+}

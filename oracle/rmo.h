@@ -1,0 +1,89 @@
+/*
+ * rmo.h -- FP64 CPU oracle for the outer-region R-matrix energy loop.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this code; only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark do.  It shares no source with the HIP library.
+ *
+ * Everything is computed in long double (x87 80-bit) and returned as double.
+ * Physics follows the PSTGF paper (Fernandez-Menchero et al.):
+ *   - R-matrix at the boundary:       section "Overview", eq. (rmatrix)
+ *   - open/closed channel split:      section "Overview", text after eq. (radial)
+ *   - asymptotic functions at r = a:  section "Overview" (Coulomb functions for
+ *                                     open channels) and the Glossary (closed
+ *                                     channels decay exponentially)
+ *   - matching condition:             section "Overview", eq. (match)
+ *   - T-matrix and collision strength: Glossary items "Transitions matrix" and
+ *                                     "Collision strength"
+ * Conventions the paper leaves open are fixed as follows (one reading each):
+ *   outer equation   F'' + (eps - l(l+1)/r^2 + 2z/r) F = 0   (Rydberg units, U = 0)
+ *   open channel     s = F_l(eta,ka)/sqrt(k), c = G_l(eta,ka)/sqrt(k), eta = -z/k,
+ *                    primes are d/dr, so s'c - sc' = 1 (unit Wronskian in r)
+ *   closed channel   direction of (W, dW/dr) for W = W_{z/kappa, l+1/2}(2 kappa r),
+ *                    normalised so that e^2 + (a e')^2 = 1 and e >= 0
+ *   K convention     F ~ s + c K on open channels, open channels in ascending order
+ *   S                S = (1 + iK)(1 - iK)^-1, T = S - 1
+ *   Omega            Omega_pq = (g/2) sum_{i in p, j in q, both open} |T_ij|^2
+ */
+#ifndef RMO_H
+#define RMO_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* per-energy status bits (same meaning as the library's) */
+#define RMO_PT_POLE 1
+#define RMO_PT_THRESHOLD 2
+#define RMO_PT_NOCONV 4
+#define RMO_PT_SINGULAR 8
+#define RMO_PT_NONFINITE 16
+
+typedef struct {
+  int32_t nchan, npole, ntarget;
+  double a, b, z, g;
+  const double *e_thr;   /* [nchan] channel threshold energies (Ry) */
+  const int32_t *l;      /* [nchan] channel angular momentum */
+  const int32_t *target; /* [nchan] target index in [0, ntarget) */
+  const double *Ek;      /* [npole] R-matrix poles (Ry) */
+  const double *w;       /* [npole*nchan] w[k*nchan + i] = w_ik */
+} rmo_pw;
+
+/* R_ij(E) = (1/2a) sum_k w_ik w_jk / (E_k - E), full n x n per energy. */
+int rmo_form_R(const rmo_pw *pw, const double *E, int32_t ne, double *R, int32_t *status,
+               int32_t nthreads);
+
+/* fg[e][i][0..3] = (s, s', c, c') for open channels, (0, 0, e, e') for closed
+   ones; open[e][i] = 1/0; nopen[e] = number of open channels. */
+int rmo_asymptotic(const rmo_pw *pw, const double *E, int32_t ne, double thr_guard, double *fg,
+                   int8_t *open, int32_t *nopen, int32_t *status, int32_t nthreads);
+
+/* K[e] (row stride n, leading nopen x nopen block) from R and fg; cond[e] is a
+   1-norm condition estimate of the matching matrix (may be NULL). */
+int rmo_solve_K(const rmo_pw *pw, const double *E, int32_t ne, const double *R, const double *fg,
+                double thr_guard, double *K, double *cond, int32_t *status, int32_t nthreads);
+
+/* Omega[e] (ntarget x ntarget) and optionally S[e] (n x n complex, interleaved
+   re/im, leading nopen x nopen block) from K. */
+int rmo_collision_strengths(const rmo_pw *pw, const double *E, int32_t ne, const double *K,
+                            double thr_guard, double *omega, double *S, int32_t *status,
+                            int32_t nthreads);
+
+/* All stages for each energy without storing intermediate R for all energies.
+   Any of K, S, cond may be NULL. */
+int rmo_run(const rmo_pw *pw, const double *E, int32_t ne, double thr_guard, double *omega,
+            double *K, double *S, double *cond, int32_t *status, int32_t nthreads);
+
+/* Special functions, exposed for pinning against independent references. */
+/* F, dF/drho, G, dG/drho of the Coulomb functions F_l(eta, rho), G_l(eta, rho). */
+int rmo_coulomb(double eta, double rho, int32_t l, double out[4]);
+/* Closed channel: d/dr log W_{z/kappa, l+1/2}(2 kappa r) at r, kappa = sqrt(-eps). */
+int rmo_closed_logderiv(double z, double eps, double r, int32_t l, double *L);
+/* Channel functions at r = a: open -> (s, s', c, c'); closed -> (0, 0, e, e'). */
+int rmo_channel(double z, double eps, double a, int32_t l, double out[4]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

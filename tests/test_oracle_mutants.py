@@ -1,0 +1,64 @@
+"""The oracle's pins must catch plausible mistakes.  Each case plants one
+mistake in a copy of oracle/rmo.c (on the CPU), builds it, and runs the pins
+that should notice against the mutant: they must fail."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "rmo.c")
+
+MUTANTS = {
+    "R_prefactor": ("const ld scale = 1.0L / (2.0L * (ld)pw->a);", "const ld scale = 1.0L / ((ld)pw->a);",
+                    "test_oracle_R.py::test_rank_one_single_pole"),
+    "R_pole_sign": ("const ld d = 1.0L / ((ld)pw->Ek[k] - (ld)E);", "const ld d = 1.0L / ((ld)E - (ld)pw->Ek[k]);",
+                    "test_oracle_R.py::test_exact_rational"),
+    "R_index": ("for (int j = 0; j <= i; ++j) row[j] += wi * (ld)wk[j];",
+                "for (int j = 0; j <= i; ++j) row[j] += wi * (ld)wk[i];",
+                "test_oracle_R.py::test_exact_rational"),
+    "cf2_sign": ("return (1.0L + I * v) / rho;", "return (1.0L - I * v) / rho;",
+                 "test_oracle_asymptotics.py::test_wronskian_sample"),
+    "cf1_sign_tracking": ("if (den < 0) sg = -sg;", "if (den < 0) sg = sg;",
+                          "test_oracle_asymptotics.py::test_coulomb_vs_mpmath"),
+    "taylor_term": ("B * dm1 * h * h * h + C * dm2 * h * h * h * h;", "B * dm1 * h * h * h;",
+                    "test_oracle_asymptotics.py::test_coulomb_vs_mpmath"),
+    "closed_sign": ("return (1.0L - w) / r;", "return (1.0L + w) / r;",
+                    "test_oracle_asymptotics.py::test_closed_neutral_s_wave"),
+    "match_b_sign": ("(a * Cpm - b * Cm);", "(a * Cpm + b * Cm);",
+                     "test_oracle_K_S.py::test_single_channel_ion_closed_form"),
+    "match_rhs_sign": ("- (i == oj ? s : 0.0L);", "+ (i == oj ? s : 0.0L);",
+                       "test_oracle_K_S.py::test_neutral_s_wave_closed_form"),
+    "lu_back_sub": ("for (int j = r + 1; j < n; ++j) x[r] -= LU[(size_t)r * n + j] * x[j];",
+                    "for (int j = r + 2; j < n; ++j) x[r] -= LU[(size_t)r * n + j] * x[j];",
+                    "test_oracle_K_S.py::test_full_and_reduced_formulations_agree"),
+    "K_rows": ("K[(size_t)i * n + j] = (double)Y[(size_t)open_idx[i] * no + j];",
+               "K[(size_t)i * n + j] = (double)Y[(size_t)i * no + j];",
+               "test_oracle_K_S.py::test_channel_permutation_covariance"),
+    "S_formula": ("rhs[(size_t)i * no + j] = (i == j ? 1.0L : 0.0L) + I * kji;",
+                  "rhs[(size_t)i * no + j] = (i == j ? 1.0L : 0.0L) - I * kji;",
+                  "test_oracle_K_S.py::test_S_unitary_symmetric_and_T_identity"),
+    "omega_target_index": ("pw->target[open_idx[j]]] += half_g * t2;", "pw->target[open_idx[i]]] += half_g * t2;",
+                           "test_oracle_K_S.py::test_omega_from_T_identity_by_target"),
+    "omega_half_g": ("const ld half_g = 0.5L * (ld)pw->g;", "const ld half_g = (ld)pw->g;",
+                     "test_oracle_K_S.py::test_single_channel_ion_closed_form"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path):
+    old, new, pin = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) >= 1, f"mutation anchor not found: {old}"
+    mut = src.replace(old, new, 1)
+    c = tmp_path / "rmo_mut.c"
+    c.write_text(mut)
+    so = tmp_path / "librmo_mut.so"
+    subprocess.check_call(["gcc", "-O1", "-fopenmp", "-std=c11", "-fPIC", "-shared", "-I",
+                           os.path.join(ROOT, "oracle"), str(c), "-o", str(so), "-lm"])
+    env = dict(os.environ, RMO_SO=str(so))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", pin.split("::")[0]), "-k", pin.split("::")[1]],
+                       env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 1, f"mutant {name} survived {pin}:\n{r.stdout[-2000:]}"

@@ -1,0 +1,136 @@
+#!/usr/bin/env python3
+"""Energy points/s of the fused outer-region R-matrix loop on one MI355X.
+
+One step = the whole hot path (R-matrix contraction, near-pole FP64 correction
+in split mode, channel split + asymptotic functions, matching + LU K solve,
+S/T/Omega) over every energy of the workload, with the partial wave's poles and
+amplitudes resident in HBM and the energies already on the device.
+
+Workload: one partial wave with 1500 channels (375 targets), 60000 poles in
+[-2, 60] Ry, z = 5, a = 12 bohr, 1000 energies uniform in [0.01, 8] Ry, seeded
+synthetic data.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"f32": 157.3, "f64": 78.6}  # MI355X dense MFMA TFLOP/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--prec", choices=["split", "fp64", "both"], default="both",
+                    help="headline mode is FP32-split; 'both' also times FP64")
+    ap.add_argument("--nenergy", type=int, default=1000)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-threads", type=int, default=16)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(each partial wave and energy is independent; see DESIGN.md for how it would shard)",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_1909_07321_amd import rm, synth
+
+    t0 = time.time()
+    pw, E = synth.config4(args.nenergy)
+    log(f"workload generated in {time.time() - t0:.1f}s: n={pw.nchan} M={pw.npole} ne={E.size}")
+    ctx = rm.Context(0)
+    pid = ctx.pw_upload(pw)
+    dev = torch.device("cuda", 0)
+    Ed = torch.tensor(E, dtype=torch.float64, device=dev)
+    om = torch.empty((E.size, pw.ntarget, pw.ntarget), dtype=torch.float64, device=dev)
+    st = torch.empty(E.size, dtype=torch.int32, device=dev)
+    flops_R = float(pw.nchan) * (pw.nchan + 1) * pw.npole  # per energy: n(n+1)M, symmetric half
+
+    modes = {"split": [("split", rm.FP32_SPLIT)], "fp64": [("fp64", rm.FP64)],
+             "both": [("split", rm.FP32_SPLIT), ("fp64", rm.FP64)]}[args.prec]
+    results = {}
+    for name, prec in modes:
+        for _ in range(args.warmup):
+            ctx.run(pid, Ed, prec=prec, want_K=False, out=(om, None, st))
+        torch.cuda.synchronize()
+        for s in ("rform", "nearpole", "asym", "ksolve", "somega"):
+            ctx.prof_read(s)
+        ctx.prof_enable(True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.run(pid, Ed, prec=prec, want_K=False, out=(om, None, st))
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        ctx.prof_enable(False)
+        stages = {s: ctx.prof_read(s) for s in ("rform", "nearpole", "asym", "ksolve", "somega")}
+        stat = st.cpu().numpy()
+        ms_step = (t2 - t1) * 1e3 / args.steps
+        rf_ms, rf_n, rf_e = stages["rform"]
+        achieved = flops_R * rf_e / (rf_ms * 1e-3) / 1e12 if rf_ms > 0 else None
+        dt = "f32" if prec == rm.FP32_SPLIT else "f64"
+        results[name] = dict(
+            value=E.size * args.steps / (t2 - t1), ms_per_step=ms_step,
+            flagged_energies=int((stat != 0).sum()),
+            stage_ms_per_step={s: v[0] / args.steps for s, v in stages.items()},
+            roofline=dict(bound="mfma", achieved=achieved, peak=PEAK[dt], unit="TFLOP/s",
+                          frac=(achieved / PEAK[dt]) if achieved else None, traffic=None,
+                          kernel=f"k_rform<{'float' if dt == 'f32' else 'double'}>",
+                          launches=rf_n, avg_launch_ms=rf_ms / max(rf_n, 1),
+                          flops_per_launch=flops_R * rf_e / max(rf_n, 1)))
+        log(f"{name}: {results[name]['value']:.1f} points/s, {ms_step:.1f} ms/step, stages "
+            + ", ".join(f"{s}={v[0] / args.steps:.1f}ms" for s, v in stages.items())
+            + (f", R contraction {achieved:.1f} TFLOP/s" if achieved else ""))
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        threads = max(1, min(args.cpu_threads, os.cpu_count() or 1))
+        sample = E[[E.size // 2]]
+        o = oracle.Oracle(pw, nthreads=threads)
+        t3 = time.perf_counter()
+        o.run(sample, want_K=False)
+        t4 = time.perf_counter()
+        cpu = dict(value=sample.size / (t4 - t3), unit="energy points/s", cores=threads, kind="oracle",
+                   sample=f"{sample.size} energy (E = {sample[0]:.3f} Ry, mid-grid) of the same workload, "
+                          f"full path R -> asymptotics -> K -> Omega in long double, {t4 - t3:.1f} s")
+        log(f"cpu oracle: {cpu['value']:.4f} points/s on {threads} threads")
+
+    head = results.get("split") or results.get("fp64")
+    head_name = "split" if "split" in results else "fp64"
+    line = {
+        "metric": "energy points/s at 1500 ch (FP64 vs FP32-split); MFMA %; p99 latency",
+        "value": head["value"], "unit": "energy points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if head_name == "split" else "f64", "data": "synthetic",
+        "config": {"workload": "one partial wave, 1500 channels, 60000 poles, 1000 energies in [0.01, 8] Ry "
+                               "(z=5, a=12)", "nchan": pw.nchan, "npole": pw.npole, "nenergy": int(E.size),
+                   "precision": "fp32-split (delta=0.05 Ry)" if head_name == "split" else "fp64"},
+        "roofline": head["roofline"],
+        "cpu_baseline": cpu,
+        "modes": results,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

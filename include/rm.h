@@ -1,0 +1,205 @@
+/*
+ * rm.h -- C ABI of librm, an MI355X (gfx950) implementation of the outer-region
+ * energy loop of the R-matrix method for electron-impact excitation described in
+ * "PSTGF: time-independent R-Matrix atomic electron-impact code"
+ * (Fernandez-Menchero, Conroy, Ballance, Badnell, Mitnik, Gorczyca, Seaton).
+ *
+ * For one partial wave (the paper's "Overview" section: target thresholds e_i,
+ * channel angular momenta l_i, R-matrix poles E_k and surface amplitudes w_ik)
+ * and every incident energy E the library computes, on the GPU:
+ *
+ *   1. the boundary R-matrix, eq. (rmatrix):
+ *        R_ij(E) = 1/(2a) sum_k w_ik w_jk / (E_k - E)
+ *   2. the channel split eps_i = E - e_i (open iff eps_i > 0, text after
+ *      eq. (radial)) and the asymptotic functions at r = a: Coulomb functions
+ *      for open channels (section "Overview": the asymptotic form is a Coulomb
+ *      function for a charged target) and the exponentially decaying Whittaker
+ *      function for closed channels (Glossary, "Closed");
+ *   3. the open-open K-matrix from the matching condition, eq. (match);
+ *   4. S = (1 + iK)(1 - iK)^-1, T = S - 1 and the partial collision strengths
+ *      Omega (Glossary, "Transitions matrix", "Collision strength").
+ *
+ * Conventions (the paper leaves them to its references; one reading each):
+ *   - units: energies in Rydberg, lengths in bohr, k = sqrt(eps);
+ *   - outer equation F'' + (eps - l(l+1)/r^2 + 2z/r) F = 0 with the multipole
+ *     potentials dropped, so the outer solution is exactly Coulombic and the
+ *     asymptotic functions are evaluated at r = a;
+ *   - open channel:  s = F_l(eta,ka)/sqrt(k), c = G_l(eta,ka)/sqrt(k), eta = -z/k,
+ *     primes are d/dr (unit Wronskian s'c - sc' = 1);
+ *   - closed channel: the direction (e, e') of (W, dW/dr) for
+ *     W = W_{z/kappa, l+1/2}(2 kappa r), kappa = sqrt(-eps), with
+ *     e^2 + (a e')^2 = 1 and e >= 0 (K does not depend on this scale);
+ *   - K: F ~ s + c K on open channels, open channels in ascending channel order;
+ *   - Omega_pq = (g/2) sum_{i in p, j in q, both open} |T_ij|^2 with g the
+ *     partial wave's statistical weight.
+ *
+ * Layout: row-major C arrays; every output buffer is caller-allocated with the
+ * size stated at each call.  Pointers to energies and outputs are host memory
+ * unless rm_opts.device_ptrs = 1, in which case they are device memory of the
+ * context's GPU and the work is ordered on rm_opts.stream.  No exception crosses
+ * this interface; every call returns an rm_status.
+ *
+ * Threading: a context may be used from one thread at a time, except that
+ * rm_submit and rm_poll may be called from any single thread while the
+ * context's scheduler thread runs the admitted work.
+ */
+#ifndef RM_H
+#define RM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rm_ctx rm_ctx;
+typedef int32_t rm_status;
+
+/* call status: negative = error, 0 = OK, positive = informational */
+#define RM_OK 0
+#define RM_PENDING 1
+#define RM_E_ARG (-1)      /* bad argument (null pointer, size, layout) */
+#define RM_E_NOMEM (-2)    /* host allocation failed or the HBM budget is exceeded */
+#define RM_E_DEVICE (-3)   /* a HIP call failed; rm_last_error() has the text */
+#define RM_E_NOTFOUND (-4) /* unknown partial-wave id or ticket */
+#define RM_E_BUSY (-5)     /* serving admission queue full */
+
+/* per-energy status bits; a flagged energy never fails its call, its outputs
+   are NaN (R is NaN only for RM_PT_POLE) */
+#define RM_PT_POLE 1        /* E equals a pole E_k exactly */
+#define RM_PT_THRESHOLD 2   /* |E - e_i| < thr_guard for some channel */
+#define RM_PT_NOCONV 4      /* an asymptotic series or continued fraction hit its cap */
+#define RM_PT_SINGULAR 8    /* exact zero pivot in a factorisation */
+#define RM_PT_NONFINITE 16  /* a non-finite value reached K or Omega */
+
+typedef enum {
+  RM_FP64 = 0,       /* R contraction on FP64 MFMA */
+  RM_FP32_SPLIT = 1  /* FP32 MFMA with FP32 accumulation for |E_k - E| >= split_delta,
+                        the remaining poles added in FP64 */
+} rm_precision;
+
+typedef struct {
+  rm_precision prec;
+  double split_delta; /* Ry; width of the FP64 window in RM_FP32_SPLIT (default 0.05) */
+  double thr_guard;   /* Ry; energies this close to a threshold are flagged (default 1e-10) */
+  void *stream;       /* hipStream_t used when device_ptrs = 1; NULL = the null stream */
+  int32_t device_ptrs;/* 1: E and outputs are device pointers */
+} rm_opts;
+
+/* Fills *o with the defaults above. */
+void rm_opts_default(rm_opts *o);
+
+/* ---------------------------------------------------------------- context */
+/* Creates a context on HIP device `device`.  hbm_budget_bytes bounds the device
+   memory the context holds at once (resident partial waves plus workspaces);
+   0 means 90% of the device's free memory.  The context keeps one HIP stream of
+   default priority and one scheduler thread for rm_submit. */
+rm_status rm_create(int device, size_t hbm_budget_bytes, rm_ctx **out);
+rm_status rm_destroy(rm_ctx *ctx);
+/* Text of the last error on this context (never NULL; "" if none). */
+const char *rm_last_error(const rm_ctx *ctx);
+
+/* ----------------------------------------------------------- partial waves */
+/* The logical content of one partial wave's H.DAT symmetry record (PSTGF paper,
+   section "Input files", H.DAT table: VALUE = Ek, WMAT = w written pole by pole,
+   L2P = l, NCONAT expanded to a channel -> target map). */
+typedef struct {
+  int32_t nchan;        /* n >= 1 channels */
+  int32_t npole;        /* M >= 1 poles */
+  int32_t ntarget;      /* targets; target[i] in [0, ntarget) */
+  double a;             /* R-matrix box radius (bohr) */
+  double b;             /* logarithmic-derivative constant of eq. (match); usually 0 */
+  double z;             /* residual charge Z - N_e (>= 0) */
+  double g;             /* statistical weight of the partial wave (1 for synthetic data) */
+  const double *e_thr;  /* [nchan] channel threshold energies (Ry) */
+  const int32_t *l;     /* [nchan] channel angular momenta, 0 <= l <= 200 */
+  const int32_t *target;/* [nchan] target index of each channel */
+  const double *Ek;     /* [npole] poles (Ry), ascending */
+  const double *w;      /* [npole*nchan] surface amplitudes, w[k*nchan + i] = w_ik */
+} rm_pw_desc;
+
+/* Copies the partial wave to the device (host pointers; the caller keeps
+   ownership).  W and E_k stay resident in HBM in the library's tile-padded
+   layouts (FP64 and an FP32 copy) until rm_pw_release.  Returns RM_E_NOMEM if
+   the HBM budget would be exceeded, RM_E_ARG for inconsistent sizes or unsorted
+   poles. */
+rm_status rm_pw_upload(rm_ctx *ctx, const rm_pw_desc *desc, int32_t *pw_id);
+rm_status rm_pw_release(rm_ctx *ctx, int32_t pw_id);
+/* Device bytes a partial wave of this shape occupies when resident. */
+size_t rm_pw_footprint(int32_t nchan, int32_t npole);
+
+/* ---------------------------------------------------------- staged calls */
+/* Stage 1, eq. (rmatrix).  R: [ne][n][n] doubles (full symmetric matrices);
+   status: [ne] int32 (RM_PT_POLE only). */
+rm_status rm_form_R(rm_ctx *ctx, int32_t pw, const double *E, int32_t ne, const rm_opts *opts,
+                    double *R, int32_t *status);
+
+/* Stage 2, channel split and asymptotic functions at r = a.
+   fg: [ne][n][4] doubles, (s, s', c, c') for open channels and (0, 0, e, e')
+   for closed ones; open: [ne][n] int8 (1 = open); nopen: [ne] int32;
+   status: [ne] (RM_PT_THRESHOLD, RM_PT_NOCONV). */
+rm_status rm_asymptotic(rm_ctx *ctx, int32_t pw, const double *E, int32_t ne, const rm_opts *opts,
+                        double *fg, int8_t *open, int32_t *nopen, int32_t *status);
+
+/* Stage 3, eq. (match): from R [ne][n][n] and fg [ne][n][4] (as produced by the
+   two calls above, or by any other source), the K-matrix K: [ne][n][n] with the
+   leading nopen x nopen block filled (row stride n) and the rest zero. */
+rm_status rm_solve_K(rm_ctx *ctx, int32_t pw, const double *E, int32_t ne, const double *R,
+                     const double *fg, const rm_opts *opts, double *K, int32_t *status);
+
+/* Stage 4: from K [ne][n][n] (leading nopen x nopen block), the collision
+   strengths omega: [ne][ntarget][ntarget] and, if S != NULL, S: [ne][n][n][2]
+   (re, im; leading nopen x nopen block). */
+rm_status rm_collision_strengths(rm_ctx *ctx, int32_t pw, const double *E, int32_t ne,
+                                 const double *K, const rm_opts *opts, double *omega, double *S,
+                                 int32_t *status);
+
+/* All four stages fused for a block of energies: omega [ne][nt][nt]; K as in
+   rm_solve_K or NULL; status [ne].  Runs the same kernels as the staged calls. */
+rm_status rm_run(rm_ctx *ctx, int32_t pw, const double *E, int32_t ne, const rm_opts *opts,
+                 double *omega, double *K, int32_t *status);
+
+/* ------------------------------------------------------------------ serving */
+typedef struct {
+  int32_t pw_id;
+  const double *E;   /* host; copied by rm_submit */
+  int32_t ne;
+  rm_opts opts;      /* device_ptrs must be 0 and stream NULL */
+  double *omega;     /* host [ne][nt][nt]; must stay valid until rm_poll returns RM_OK */
+  double *K;         /* host [ne][n][n] or NULL */
+  int32_t *status;   /* host [ne] */
+} rm_request;
+
+typedef struct {
+  int64_t t_arrive_ns, t_admit_ns, t_start_ns, t_done_ns; /* CLOCK_MONOTONIC */
+  int32_t nblocks;   /* energy chunks the request was split into */
+} rm_req_stats;
+
+/* Non-blocking: copies E, queues the request and returns a ticket.  The
+   scheduler admits (partial wave, energy chunk) items while the HBM budget and
+   the in-flight slots allow, so requests that arrive while others run are
+   interleaved with them on the device.  RM_E_BUSY if the queue is full. */
+rm_status rm_submit(rm_ctx *ctx, const rm_request *req, uint64_t *ticket);
+/* RM_OK (done; outputs written, ticket retired), RM_PENDING, or an error.  st
+   may be NULL. */
+rm_status rm_poll(rm_ctx *ctx, uint64_t ticket, rm_req_stats *st);
+/* Blocks until every submitted request is done. */
+rm_status rm_drain(rm_ctx *ctx);
+
+/* ---------------------------------------------------------------- profiling */
+/* Stage timing: while enabled, every launch of the named stage is bracketed by
+   HIP events on the stream it runs on.  Stages: "rform" (R contraction kernel,
+   either precision), "nearpole" (FP64 window correction), "asym" (channel split
+   and asymptotic functions), "ksolve" (matching assembly, LU, back
+   substitution), "somega" (S, T and Omega).  rm_prof_read synchronises the
+   recorded events and returns the summed milliseconds, the launch count and
+   the energies those launches covered, then clears the records of that stage. */
+rm_status rm_prof_enable(rm_ctx *ctx, int32_t on);
+rm_status rm_prof_read(rm_ctx *ctx, const char *stage, double *total_ms, int64_t *launches,
+                       int64_t *energies);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RM_H */

@@ -43,11 +43,20 @@ static int32_t form_R_one(const rmo_pw *pw, double E, double *R) {
       for (long t = 0; t < (long)n * n; ++t) R[t] = nan_value();
       return RMO_PT_POLE;
     }
-  /* lower triangle, row i holds columns 0..i */
+  /* lower triangle, row i holds columns 0..i.  When called outside a parallel
+     region (one energy at a time) the rows are shared among threads; each row's
+     sum still runs over k in ascending order. */
   ld *acc = (ld *)calloc((size_t)n * (n + 1) / 2, sizeof(ld));
+#ifdef _OPENMP
+  const int par = !omp_in_parallel() && n >= 128;
+#pragma omp parallel if (par)
+#endif
   for (int k = 0; k < M; ++k) {
     const double *wk = pw->w + (size_t)k * n;
     const ld d = 1.0L / ((ld)pw->Ek[k] - (ld)E);
+#ifdef _OPENMP
+#pragma omp for schedule(static, 1)
+#endif
     for (int i = 0; i < n; ++i) {
       const ld wi = (ld)wk[i] * d;
       ld *row = acc + (size_t)i * (i + 1) / 2;
@@ -606,7 +615,7 @@ int rmo_form_R(const rmo_pw *pw, const double *E, int32_t ne, double *R, int32_t
                int32_t nthreads) {
   const long nn = (long)pw->nchan * pw->nchan;
   set_threads(nthreads);
-#pragma omp parallel for schedule(dynamic, 1)
+#pragma omp parallel for schedule(dynamic, 1) if (ne > 1)
   for (int e = 0; e < ne; ++e) status[e] = form_R_one(pw, E[e], R + e * nn);
   return 0;
 }
@@ -615,7 +624,7 @@ int rmo_asymptotic(const rmo_pw *pw, const double *E, int32_t ne, double thr_gua
                    int8_t *open, int32_t *nopen, int32_t *status, int32_t nthreads) {
   const int n = pw->nchan;
   set_threads(nthreads);
-#pragma omp parallel for schedule(dynamic, 1)
+#pragma omp parallel for schedule(dynamic, 1) if (ne > 1)
   for (int e = 0; e < ne; ++e)
     status[e] = asym_one(pw, E[e], thr_guard, fg + (long)e * n * 4, open + (long)e * n, nopen + e);
   return 0;
@@ -626,7 +635,7 @@ int rmo_solve_K(const rmo_pw *pw, const double *E, int32_t ne, const double *R, 
   const int n = pw->nchan;
   const long nn = (long)n * n;
   set_threads(nthreads);
-#pragma omp parallel for schedule(dynamic, 1)
+#pragma omp parallel for schedule(dynamic, 1) if (ne > 1)
   for (int e = 0; e < ne; ++e) {
     int32_t st = 0;
     for (int k = 0; k < pw->npole; ++k)
@@ -659,7 +668,7 @@ int rmo_collision_strengths(const rmo_pw *pw, const double *E, int32_t ne, const
   const int n = pw->nchan, nt = pw->ntarget;
   const long nn = (long)n * n;
   set_threads(nthreads);
-#pragma omp parallel for schedule(dynamic, 1)
+#pragma omp parallel for schedule(dynamic, 1) if (ne > 1)
   for (int e = 0; e < ne; ++e) {
     int *idx = (int *)malloc(sizeof(int) * (n + 1));
     const int no = open_list(pw, E[e], idx);
@@ -685,7 +694,7 @@ int rmo_run(const rmo_pw *pw, const double *E, int32_t ne, double thr_guard, dou
   const int n = pw->nchan, nt = pw->ntarget;
   const long nn = (long)n * n;
   set_threads(nthreads);
-#pragma omp parallel for schedule(dynamic, 1)
+#pragma omp parallel for schedule(dynamic, 1) if (ne > 1)
   for (int e = 0; e < ne; ++e) {
     double *R = (double *)malloc(sizeof(double) * nn);
     double *fg = (double *)malloc(sizeof(double) * 4 * n);

@@ -1,0 +1,588 @@
+// k_linalg.hip -- matching, K solve and S/Omega, FP64 on the GPU.
+//
+// Matching (PSTGF paper, eq. (match)): with the asymptotic form F_ij = s_i d_ij +
+// c_i K_ij on open rows and e_i X_ij on closed rows, F(a) = R (a F'(a) - b F(a))
+// becomes A Y = B with C_i = c_i (open) or e_i (closed) and
+//   A_im = d_im C_i - R_im (a C'_m - b C_m)
+//   B_ij = R_{i,o_j} (a s'_{o_j} - b s_{o_j}) - d_{i,o_j} s_{o_j}
+// and K = Y restricted to the open rows.  A Y = B is solved by a batched,
+// blocked, right-looking LU with partial pivoting applied to [A | B] followed by
+// a blocked back substitution.
+//
+// S and Omega (Glossary): S = (1 + iK)(1 - iK)^-1 = (2Y - 1) + 2iKY with
+// Y = (1 + K^2)^-1, so with X = (1 + K^2)^-1 K (same LU, on [1 + K^2 | K]):
+//   T = S - 1,  T_ij = -2 (XK)_ij + 2i X_ij,  |T_ij|^2 = 4 [(XK)_ij^2 + X_ij^2]
+//   Omega_pq = (g/2) sum_{i in p, j in q, both open} |T_ij|^2
+//
+// Augmented layout per energy: rows [0, rows), A in columns [0, rows), the
+// right-hand sides in columns [roff, roff + rhs), row stride ldaug.
+#include "rm.h"
+#include "rm_internal.h"
+
+namespace rm {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// assembly of B (reads R) and then A (in place over R)
+// ---------------------------------------------------------------------------
+__global__ void k_buildB(int n, double a, double b, const double *__restrict__ fg,
+                         const int *__restrict__ nopen, const int *__restrict__ openidx, long ldo,
+                         double *__restrict__ aug, long ldaug, long strideA, long roff) {
+  const int e = blockIdx.z;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;  // open column
+  const int i = blockIdx.y;                             // row
+  const int no = nopen[e];
+  if (j >= no || i >= n) return;
+  const int oj = openidx[(size_t)e * ldo + j];
+  const double *f = fg + ((size_t)e * n + oj) * 4;
+  const double s = f[0], sp = f[1];
+  double *Ae = aug + (size_t)e * strideA;
+  const double v = Ae[(size_t)i * ldaug + oj] * (a * sp - b * s) - (i == oj ? s : 0.0);
+  Ae[(size_t)i * ldaug + roff + j] = v;
+}
+
+__global__ void k_buildA(int n, double a, double b, const double *__restrict__ fg,
+                         double *__restrict__ aug, long ldaug, long strideA) {
+  const int e = blockIdx.z;
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (m >= n || i >= n) return;
+  const double *fm = fg + ((size_t)e * n + m) * 4;
+  const double lam = a * fm[3] - b * fm[2];
+  double *p = aug + (size_t)e * strideA + (size_t)i * ldaug + m;
+  double v = -(*p) * lam;
+  if (i == m) v += fm[2];
+  *p = v;
+}
+
+void launch_build(hipStream_t s, const DevPW &pw, int ne, const double *fg, const int *nopen,
+                  const int *openidx, long ldo, double *aug, long ldaug, long strideA, long roff) {
+  dim3 gB((pw.n + 63) / 64, pw.n, ne);
+  hipLaunchKernelGGL(k_buildB, gB, dim3(64), 0, s, pw.n, pw.a, pw.b, fg, nopen, openidx, ldo, aug, ldaug,
+                     strideA, roff);
+  hipLaunchKernelGGL(k_buildA, gB, dim3(64), 0, s, pw.n, pw.a, pw.b, fg, aug, ldaug, strideA);
+}
+
+// ---------------------------------------------------------------------------
+// LU building blocks.  dims[2e] = rows, dims[2e+1] = rhs.  Virtual column v of
+// the part right of the panel maps to a real column: v < rows - c0 -> c0 + v,
+// otherwise roff + (v - (rows - c0)).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ long vcol(int v, int rows, int c0, long roff) {
+  return v < rows - c0 ? (long)(c0 + v) : roff + (v - (rows - c0));
+}
+
+// Panel factorisation: columns [j0, j0 + jb) over rows [j0, rows), with row
+// interchanges applied to every column right of j0 (A and right-hand sides).
+__global__ __launch_bounds__(256) void k_lu_panel(int j0, const int *__restrict__ dims,
+                                                  double *__restrict__ aug, long ldaug, long strideA,
+                                                  long roff, int *__restrict__ status) {
+  const int e = blockIdx.x;
+  const int rows = dims[2 * e], rhs = dims[2 * e + 1];
+  if (j0 >= rows) return;
+  const int jb = min(NB, rows - j0);
+  double *A = aug + (size_t)e * strideA;
+  const int t = threadIdx.x;
+  __shared__ double sval[256];
+  __shared__ int sidx[256];
+  __shared__ int spiv;
+  __shared__ double spv;
+  const int ncol_right = (rows - j0) + rhs;  // virtual columns from j0
+  for (int c = j0; c < j0 + jb; ++c) {
+    // pivot search over rows c..rows-1 (ties -> smallest row)
+    double best = -1.0;
+    int bidx = c;
+    for (int r = c + t; r < rows; r += 256) {
+      const double v = fabs(A[(size_t)r * ldaug + c]);
+      if (v > best) { best = v; bidx = r; }
+    }
+    sval[t] = best;
+    sidx[t] = bidx;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if (t < off) {
+        const double vo = sval[t + off];
+        const int io = sidx[t + off];
+        if (vo > sval[t] || (vo == sval[t] && io < sidx[t])) { sval[t] = vo; sidx[t] = io; }
+      }
+      __syncthreads();
+    }
+    if (t == 0) {
+      spiv = sidx[0];
+      spv = sval[0];
+      if (!(sval[0] > 0.0)) atomicOr(status + e, RM_PT_SINGULAR);
+    }
+    __syncthreads();
+    const int p = spiv;
+    if (p != c) {
+      for (int v = t; v < ncol_right; v += 256) {
+        const long col = vcol(v, rows, j0, roff);
+        const double x = A[(size_t)c * ldaug + col];
+        A[(size_t)c * ldaug + col] = A[(size_t)p * ldaug + col];
+        A[(size_t)p * ldaug + col] = x;
+      }
+    }
+    __syncthreads();
+    const double piv = A[(size_t)c * ldaug + c];
+    const double inv = piv != 0.0 ? 1.0 / piv : 0.0;
+    for (int r = c + 1 + t; r < rows; r += 256) {
+      double *row = A + (size_t)r * ldaug;
+      const double m = row[c] * inv;
+      row[c] = m;
+      for (int q = c + 1; q < j0 + jb; ++q) row[q] -= m * A[(size_t)c * ldaug + q];
+    }
+    __syncthreads();
+  }
+}
+
+// U12 = L11^-1 A12 for rows [j0, j0 + jb) and every column right of the panel.
+// One thread per column; the column is kept in LDS (its own slot) so the solve
+// needs no large per-thread register array.
+constexpr int TRSM_T = 128;
+__global__ __launch_bounds__(TRSM_T) void k_lu_trsm(int j0, const int *__restrict__ dims,
+                                                    double *__restrict__ aug, long ldaug, long strideA,
+                                                    long roff) {
+  const int e = blockIdx.y;
+  const int rows = dims[2 * e], rhs = dims[2 * e + 1];
+  if (j0 >= rows) return;
+  const int jb = min(NB, rows - j0);
+  const int c0 = j0 + jb;
+  const int ncols = (rows - c0) + rhs;
+  if ((int)(blockIdx.x * TRSM_T) >= ncols) return;
+  double *A = aug + (size_t)e * strideA;
+  __shared__ double L[NB][NB + 1];
+  __shared__ double sx[NB][TRSM_T];
+  const int t = threadIdx.x;
+  for (int idx = t; idx < jb * jb; idx += TRSM_T) {
+    const int r = idx / jb, c = idx % jb;
+    L[r][c] = A[(size_t)(j0 + r) * ldaug + j0 + c];
+  }
+  const int v = blockIdx.x * TRSM_T + t;
+  const bool valid = v < ncols;
+  const long col = valid ? vcol(v, rows, c0, roff) : 0;
+  for (int r = 0; r < jb; ++r) sx[r][t] = valid ? A[(size_t)(j0 + r) * ldaug + col] : 0.0;
+  __syncthreads();
+  for (int r = 1; r < jb; ++r) {
+    double acc = sx[r][t];
+    for (int c = 0; c < r; ++c) acc -= L[r][c] * sx[c][t];
+    sx[r][t] = acc;
+  }
+  if (valid)
+    for (int r = 0; r < jb; ++r) A[(size_t)(j0 + r) * ldaug + col] = sx[r][t];
+}
+
+// Trailing update A22 -= L21 U12 over rows [c0, rows) and all virtual columns
+// right of the panel; 64 x 64 output tiles, K = jb, FP64 MFMA.
+__global__ __launch_bounds__(256) void k_lu_update(int j0, const int *__restrict__ dims,
+                                                   double *__restrict__ aug, long ldaug, long strideA,
+                                                   long roff, int tiles_n) {
+  const int e = blockIdx.y;
+  const int rows = dims[2 * e], rhs = dims[2 * e + 1];
+  if (j0 >= rows) return;
+  const int jb = min(NB, rows - j0);
+  const int c0 = j0 + jb;
+  const int m = rows - c0;
+  const int ncols = (rows - c0) + rhs;
+  const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+  const int r0 = tm * TILE, v0 = tn * TILE;
+  if (r0 >= m || v0 >= ncols) return;
+  double *A = aug + (size_t)e * strideA;
+  __shared__ double sL[NB][TILE];  // sL[k][i] = L21[r0 + i][k]
+  __shared__ double sU[NB][TILE];  // sU[k][j] = U12[k][v0 + j]
+  const int t = threadIdx.x;
+  for (int idx = t; idx < NB * TILE; idx += 256) {
+    const int i = idx / NB, k = idx % NB;
+    sL[k][i] = (r0 + i < m && k < jb) ? A[(size_t)(c0 + r0 + i) * ldaug + j0 + k] : 0.0;
+  }
+  for (int idx = t; idx < NB * TILE; idx += 256) {
+    const int k = idx / TILE, j = idx % TILE;
+    sU[k][j] = (v0 + j < ncols && k < jb) ? A[(size_t)(j0 + k) * ldaug + vcol(v0 + j, rows, c0, roff)] : 0.0;
+  }
+  __syncthreads();
+  const int lane = t & 63, wave = t >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int kk = lane >> 4, ii = lane & 15;
+  d4 acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = d4{0, 0, 0, 0};
+#pragma unroll
+  for (int ks = 0; ks < NB; ks += 4) {
+    const double a0 = sL[ks + kk][wr * 32 + ii], a1 = sL[ks + kk][wr * 32 + 16 + ii];
+    const double b0 = sU[ks + kk][wc * 32 + ii], b1 = sU[ks + kk][wc * 32 + 16 + ii];
+    acc[0] = mfma64(a0, b0, acc[0]);
+    acc[1] = mfma64(a0, b1, acc[1]);
+    acc[2] = mfma64(a1, b0, acc[2]);
+    acc[3] = mfma64(a1, b1, acc[3]);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int jv = v0 + wc * 32 + (q & 1) * 16 + ii;
+    if (jv >= ncols) continue;
+    const long col = vcol(jv, rows, c0, roff);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = r0 + wr * 32 + (q >> 1) * 16 + 4 * v + kk;
+      if (i < m) A[(size_t)(c0 + i) * ldaug + col] -= acc[q][v];
+    }
+  }
+}
+
+// Back substitution, diagonal block: Y_b = U_bb^-1 B_b for the right-hand sides
+// (one thread per right-hand side, its column kept in LDS).
+__global__ __launch_bounds__(TRSM_T) void k_bs_block(int j0, const int *__restrict__ dims,
+                                                     double *__restrict__ aug, long ldaug, long strideA,
+                                                     long roff) {
+  const int e = blockIdx.y;
+  const int rows = dims[2 * e], rhs = dims[2 * e + 1];
+  if (j0 >= rows) return;
+  if ((int)(blockIdx.x * TRSM_T) >= rhs) return;
+  const int jb = min(NB, rows - j0);
+  double *A = aug + (size_t)e * strideA;
+  __shared__ double U[NB][NB + 1];
+  __shared__ double sx[NB][TRSM_T];
+  const int t = threadIdx.x;
+  for (int idx = t; idx < jb * jb; idx += TRSM_T) {
+    const int r = idx / jb, c = idx % jb;
+    U[r][c] = A[(size_t)(j0 + r) * ldaug + j0 + c];
+  }
+  const int q = blockIdx.x * TRSM_T + t;
+  const bool valid = q < rhs;
+  const long col = roff + (valid ? q : 0);
+  for (int r = 0; r < jb; ++r) sx[r][t] = valid ? A[(size_t)(j0 + r) * ldaug + col] : 0.0;
+  __syncthreads();
+  for (int r = jb - 1; r >= 0; --r) {
+    double acc = sx[r][t];
+    for (int c = r + 1; c < jb; ++c) acc -= U[r][c] * sx[c][t];
+    sx[r][t] = U[r][r] != 0.0 ? acc / U[r][r] : 0.0;
+  }
+  if (valid)
+    for (int r = 0; r < jb; ++r) A[(size_t)(j0 + r) * ldaug + col] = sx[r][t];
+}
+
+// Back substitution, update above the block: B[0:j0] -= U[0:j0, j0:j0+jb] Y_b.
+__global__ __launch_bounds__(256) void k_bs_update(int j0, const int *__restrict__ dims,
+                                                   double *__restrict__ aug, long ldaug, long strideA,
+                                                   long roff, int tiles_n) {
+  const int e = blockIdx.y;
+  const int rows = dims[2 * e], rhs = dims[2 * e + 1];
+  if (j0 >= rows || j0 == 0) return;
+  const int jb = min(NB, rows - j0);
+  const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+  const int r0 = tm * TILE, q0 = tn * TILE;
+  if (r0 >= j0 || q0 >= rhs) return;
+  double *A = aug + (size_t)e * strideA;
+  __shared__ double sU[NB][TILE];  // sU[k][i] = U[r0 + i][j0 + k]
+  __shared__ double sY[NB][TILE];  // sY[k][j] = Y[j0 + k][q0 + j]
+  const int t = threadIdx.x;
+  for (int idx = t; idx < NB * TILE; idx += 256) {
+    const int i = idx / NB, k = idx % NB;
+    sU[k][i] = (r0 + i < j0 && k < jb) ? A[(size_t)(r0 + i) * ldaug + j0 + k] : 0.0;
+  }
+  for (int idx = t; idx < NB * TILE; idx += 256) {
+    const int k = idx / TILE, j = idx % TILE;
+    sY[k][j] = (q0 + j < rhs && k < jb) ? A[(size_t)(j0 + k) * ldaug + roff + q0 + j] : 0.0;
+  }
+  __syncthreads();
+  const int lane = t & 63, wave = t >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int kk = lane >> 4, ii = lane & 15;
+  d4 acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = d4{0, 0, 0, 0};
+#pragma unroll
+  for (int ks = 0; ks < NB; ks += 4) {
+    const double a0 = sU[ks + kk][wr * 32 + ii], a1 = sU[ks + kk][wr * 32 + 16 + ii];
+    const double b0 = sY[ks + kk][wc * 32 + ii], b1 = sY[ks + kk][wc * 32 + 16 + ii];
+    acc[0] = mfma64(a0, b0, acc[0]);
+    acc[1] = mfma64(a0, b1, acc[1]);
+    acc[2] = mfma64(a1, b0, acc[2]);
+    acc[3] = mfma64(a1, b1, acc[3]);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int j = q0 + wc * 32 + (q & 1) * 16 + ii;
+    if (j >= rhs) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = r0 + wr * 32 + (q >> 1) * 16 + 4 * v + kk;
+      if (i < j0) A[(size_t)i * ldaug + roff + j] -= acc[q][v];
+    }
+  }
+}
+
+void launch_lu_solve(hipStream_t s, int ne, int maxrows, int maxrhs, const int *dims, double *aug,
+                     long ldaug, long strideA, long roff, int *status) {
+  for (int j0 = 0; j0 < maxrows; j0 += NB) {
+    hipLaunchKernelGGL(k_lu_panel, dim3(ne), dim3(256), 0, s, j0, dims, aug, ldaug, strideA, roff, status);
+    const int c0 = min(maxrows, j0 + NB);
+    const int ncols = (maxrows - c0) + maxrhs;
+    if (ncols <= 0) continue;
+    hipLaunchKernelGGL(k_lu_trsm, dim3((ncols + TRSM_T - 1) / TRSM_T, ne), dim3(TRSM_T), 0, s, j0, dims, aug,
+                       ldaug, strideA, roff);
+    const int m = maxrows - c0;
+    if (m <= 0) continue;
+    const int tm = (m + TILE - 1) / TILE, tn = (ncols + TILE - 1) / TILE;
+    hipLaunchKernelGGL(k_lu_update, dim3(tm * tn, ne), dim3(256), 0, s, j0, dims, aug, ldaug, strideA,
+                       roff, tn);
+  }
+  if (maxrhs <= 0) return;
+  for (int j0 = (maxrows - 1) / NB * NB; j0 >= 0; j0 -= NB) {
+    hipLaunchKernelGGL(k_bs_block, dim3((maxrhs + TRSM_T - 1) / TRSM_T, ne), dim3(TRSM_T), 0, s, j0, dims, aug,
+                       ldaug, strideA, roff);
+    if (j0 == 0) break;
+    const int tm = (j0 + TILE - 1) / TILE, tn = (maxrhs + TILE - 1) / TILE;
+    hipLaunchKernelGGL(k_bs_update, dim3(tm * tn, ne), dim3(256), 0, s, j0, dims, aug, ldaug, strideA,
+                       roff, tn);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Small batched GEMM, C = A B (square no x no per energy), FP64 MFMA.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gemm_sq(const int *__restrict__ nopen, const double *__restrict__ A,
+                                                 long lda, long sA, const double *__restrict__ B, long ldb,
+                                                 long sB, double *__restrict__ C, long ldc, long sC,
+                                                 int tiles_n) {
+  const int e = blockIdx.y;
+  const int n = nopen[e];
+  const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+  const int r0 = tm * TILE, q0 = tn * TILE;
+  if (r0 >= n || q0 >= n) return;
+  const double *Ae = A + (size_t)e * sA;
+  const double *Be = B + (size_t)e * sB;
+  double *Ce = C + (size_t)e * sC;
+  __shared__ double sa[16][TILE];  // sa[k][i] = A[r0 + i][k0 + k]
+  __shared__ double sb[16][TILE];  // sb[k][j] = B[k0 + k][q0 + j]
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int kk = lane >> 4, ii = lane & 15;
+  d4 acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = d4{0, 0, 0, 0};
+  for (int k0 = 0; k0 < n; k0 += 16) {
+    for (int idx = t; idx < 16 * TILE; idx += 256) {
+      const int i = idx / 16, k = idx % 16;
+      sa[k][i] = (r0 + i < n && k0 + k < n) ? Ae[(size_t)(r0 + i) * lda + k0 + k] : 0.0;
+    }
+    for (int idx = t; idx < 16 * TILE; idx += 256) {
+      const int k = idx / TILE, j = idx % TILE;
+      sb[k][j] = (q0 + j < n && k0 + k < n) ? Be[(size_t)(k0 + k) * ldb + q0 + j] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 16; ks += 4) {
+      const double a0 = sa[ks + kk][wr * 32 + ii], a1 = sa[ks + kk][wr * 32 + 16 + ii];
+      const double b0 = sb[ks + kk][wc * 32 + ii], b1 = sb[ks + kk][wc * 32 + 16 + ii];
+      acc[0] = mfma64(a0, b0, acc[0]);
+      acc[1] = mfma64(a0, b1, acc[1]);
+      acc[2] = mfma64(a1, b0, acc[2]);
+      acc[3] = mfma64(a1, b1, acc[3]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int j = q0 + wc * 32 + (q & 1) * 16 + ii;
+    if (j >= n) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = r0 + wr * 32 + (q >> 1) * 16 + 4 * v + kk;
+      if (i < n) Ce[(size_t)i * ldc + j] = acc[q][v];
+    }
+  }
+}
+
+void launch_gemm_sq(hipStream_t s, int ne, int maxn, const int *nopen, const double *A, long lda, long sA,
+                    const double *B, long ldb, long sB, double *C, long ldc, long sC) {
+  if (maxn <= 0) return;
+  const int tn = (maxn + TILE - 1) / TILE;
+  hipLaunchKernelGGL(k_gemm_sq, dim3(tn * tn, ne), dim3(256), 0, s, nopen, A, lda, sA, B, ldb, sB, C, ldc,
+                     sC, tn);
+}
+
+// ---------------------------------------------------------------------------
+// K gather, P = 1 + K^2 set-up, collision strengths
+// ---------------------------------------------------------------------------
+__global__ void k_gatherK(int n, const int *__restrict__ nopen, const int *__restrict__ openidx, long ldo,
+                          const double *__restrict__ aug, long ldaug, long strideA, long roff,
+                          double *__restrict__ Kw, long ldk, long strideK) {
+  const int e = blockIdx.z, i = blockIdx.y;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || j >= n) return;
+  const int no = nopen[e];
+  double v = 0.0;
+  if (i < no && j < no) v = aug[(size_t)e * strideA + (size_t)openidx[(size_t)e * ldo + i] * ldaug + roff + j];
+  Kw[(size_t)e * strideK + (size_t)i * ldk + j] = v;
+}
+
+void launch_gatherK(hipStream_t s, int ne, int n, const int *nopen, const int *openidx, long ldo,
+                    const double *aug, long ldaug, long strideA, long roff, double *Kw, long ldk,
+                    long strideK) {
+  hipLaunchKernelGGL(k_gatherK, dim3((n + 63) / 64, n, ne), dim3(64), 0, s, n, nopen, openidx, ldo, aug,
+                     ldaug, strideA, roff, Kw, ldk, strideK);
+}
+
+// aug rows [0, no): columns [0, no) hold K K (already written); add 1 on the
+// diagonal and copy K into the right-hand-side columns; dims = {no, no}.
+__global__ void k_formP(const int *__restrict__ nopen, const double *__restrict__ Kw, long ldk, long strideK,
+                        double *__restrict__ aug, long ldaug, long strideA, long roff, int *__restrict__ dims) {
+  const int e = blockIdx.z, i = blockIdx.y;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int no = nopen[e];
+  if (i == 0 && j == 0) {
+    dims[2 * e] = no;
+    dims[2 * e + 1] = no;
+  }
+  if (i >= no || j >= no) return;
+  double *row = aug + (size_t)e * strideA + (size_t)i * ldaug;
+  if (i == j) row[j] += 1.0;
+  row[roff + j] = Kw[(size_t)e * strideK + (size_t)i * ldk + j];
+}
+
+void launch_formP(hipStream_t s, int ne, int maxno, const int *nopen, const double *Kw, long ldk,
+                  long strideK, double *aug, long ldaug, long strideA, long roff, int *dims) {
+  hipLaunchKernelGGL(k_formP, dim3((maxno + 63) / 64 + 1, maxno + 1, ne), dim3(64), 0, s, nopen, Kw, ldk,
+                     strideK, aug, ldaug, strideA, roff, dims);
+}
+
+// Omega_pq for one energy and one target row p per wave; lanes stride over q.
+// Each entry sums its channel pairs in a fixed order (no atomics), so results
+// do not depend on scheduling.
+__global__ __launch_bounds__(64) void k_omega(int nt, double half_g, const int *__restrict__ tptr,
+                                              const int *__restrict__ tch, const int *__restrict__ openpos,
+                                              long ldo, const double *__restrict__ X, long ldx, long sX,
+                                              const double *__restrict__ XK, long ldxk, long sXK,
+                                              double *__restrict__ omega) {
+  const int p = blockIdx.x, e = blockIdx.y;
+  const int *pos = openpos + (size_t)e * ldo;
+  const double *Xe = X + (size_t)e * sX;
+  const double *Ye = XK + (size_t)e * sXK;
+  for (int q = threadIdx.x; q < nt; q += 64) {
+    double acc = 0.0;
+    for (int a = tptr[p]; a < tptr[p + 1]; ++a) {
+      const int i = pos[tch[a]];
+      if (i < 0) continue;
+      for (int b = tptr[q]; b < tptr[q + 1]; ++b) {
+        const int j = pos[tch[b]];
+        if (j < 0) continue;
+        const double x = Xe[(size_t)i * ldx + j], y = Ye[(size_t)i * ldxk + j];
+        acc += 4.0 * (y * y + x * x);
+      }
+    }
+    omega[((size_t)e * nt + p) * nt + q] = half_g * acc;
+  }
+}
+
+// S_ij = d_ij - 2 (XK)_ij + 2i X_ij on the leading no x no block, zero elsewhere
+__global__ void k_smatrix(int n, const int *__restrict__ nopen, const double *__restrict__ X, long ldx, long sX,
+                          const double *__restrict__ XK, long ldxk, long sXK, double *__restrict__ S) {
+  const int e = blockIdx.z, i = blockIdx.y;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int no = nopen[e];
+  double re = 0.0, im = 0.0;
+  if (i < no && j < no) {
+    re = (i == j ? 1.0 : 0.0) - 2.0 * XK[(size_t)e * sXK + (size_t)i * ldxk + j];
+    im = 2.0 * X[(size_t)e * sX + (size_t)i * ldx + j];
+  }
+  double *o = S + (((size_t)e * n + i) * n + j) * 2;
+  o[0] = re;
+  o[1] = im;
+}
+
+void launch_omega(hipStream_t s, const DevPW &pw, int ne, const int *openpos, long ldo, const int *nopen,
+                  const double *X, long ldx, long sX, const double *XK, long ldxk, long sXK, double *omega,
+                  double *S) {
+  hipLaunchKernelGGL(k_omega, dim3(pw.nt, ne), dim3(64), 0, s, pw.nt, 0.5 * pw.g, pw.tptr, pw.tch, openpos,
+                     ldo, X, ldx, sX, XK, ldxk, sXK, omega);
+  if (S)
+    hipLaunchKernelGGL(k_smatrix, dim3((pw.n + 63) / 64, pw.n, ne), dim3(64), 0, s, pw.n, nopen, X, ldx, sX,
+                       XK, ldxk, sXK, S);
+}
+
+// Flag non-finite results and overwrite the outputs of flagged energies with NaN.
+__global__ __launch_bounds__(256) void k_finalize(int n, int nt, int *__restrict__ status,
+                                                  double *__restrict__ omega, double *__restrict__ K, long ldk,
+                                                  long strideK, double *__restrict__ S) {
+  const int e = blockIdx.x;
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  int mine = 0;
+  for (int t = threadIdx.x; t < nt * nt; t += 256)
+    if (!isfinite(omega[(size_t)e * nt * nt + t])) mine = 1;
+  if (mine) atomicOr(&bad, 1);
+  __syncthreads();
+  if (threadIdx.x == 0 && bad) status[e] |= RM_PT_NONFINITE;
+  __syncthreads();
+  if (status[e] == 0) return;
+  const double nan = __builtin_nan("");
+  for (int t = threadIdx.x; t < nt * nt; t += 256) omega[(size_t)e * nt * nt + t] = nan;
+  if (K)
+    for (long t = threadIdx.x; t < (long)n * n; t += 256) K[(size_t)e * strideK + (t / n) * ldk + t % n] = nan;
+  if (S)
+    for (long t = threadIdx.x; t < 2L * n * n; t += 256) S[(size_t)e * 2 * n * n + t] = nan;
+}
+
+void launch_finalize(hipStream_t s, int ne, int n, int nt, int *status, double *omega, double *K, long ldk,
+                     long strideK, double *S) {
+  hipLaunchKernelGGL(k_finalize, dim3(ne), dim3(256), 0, s, n, nt, status, omega, K, ldk, strideK, S);
+}
+
+__global__ void k_setdims(int ne, int rows, const int *__restrict__ nopen, int *__restrict__ dims) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  dims[2 * e] = rows;
+  dims[2 * e + 1] = nopen[e];
+}
+
+void launch_setdims(hipStream_t s, int ne, int rows, const int *nopen, int *dims) {
+  hipLaunchKernelGGL(k_setdims, dim3((ne + 127) / 128), dim3(128), 0, s, ne, rows, nopen, dims);
+}
+
+// Flags of the staged calls that take R, fg or K from the caller: energies within
+// thr of a threshold, and non-finite inputs.
+__global__ __launch_bounds__(256) void k_check_inputs(int n, const double *__restrict__ E,
+                                                      const double *__restrict__ ethr, double thr,
+                                                      const double *__restrict__ R, long ldr, long strideR,
+                                                      const double *__restrict__ fg, const double *__restrict__ K,
+                                                      long ldk, long strideK, const int *__restrict__ nopen,
+                                                      int *__restrict__ status) {
+  const int e = blockIdx.x;
+  __shared__ int flags;
+  if (threadIdx.x == 0) flags = 0;
+  __syncthreads();
+  int f = 0;
+  const double Ev = E[e];
+  for (int i = threadIdx.x; i < n; i += 256)
+    if (fabs(Ev - ethr[i]) < thr) f |= RM_PT_THRESHOLD;
+  if (R)
+    for (long t = threadIdx.x; t < (long)n * n; t += 256)
+      if (!isfinite(R[(size_t)e * strideR + (t / n) * ldr + t % n])) f |= RM_PT_NONFINITE;
+  if (fg)
+    for (long t = threadIdx.x; t < 4L * n; t += 256)
+      if (!isfinite(fg[(size_t)e * n * 4 + t])) f |= RM_PT_NONFINITE;
+  if (K) {
+    const int no = nopen[e];
+    for (long t = threadIdx.x; t < (long)no * no; t += 256)
+      if (!isfinite(K[(size_t)e * strideK + (t / no) * ldk + t % no])) f |= RM_PT_NONFINITE;
+  }
+  if (f) atomicOr(&flags, f);
+  __syncthreads();
+  if (threadIdx.x == 0 && flags) atomicOr(status + e, flags);
+}
+
+void launch_check_inputs(hipStream_t s, int ne, int n, const double *E, const double *ethr, double thr,
+                         const double *R, long ldr, long strideR, const double *fg, const double *K, long ldk,
+                         long strideK, const int *nopen, int *status) {
+  hipLaunchKernelGGL(k_check_inputs, dim3(ne), dim3(256), 0, s, n, E, ethr, thr, R, ldr, strideR, fg, K, ldk,
+                     strideK, nopen, status);
+}
+
+}  // namespace rm

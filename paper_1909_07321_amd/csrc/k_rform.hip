@@ -1,0 +1,313 @@
+// k_rform.hip -- boundary R-matrix, eq. (rmatrix) of the PSTGF paper:
+//   R_ij(E) = 1/(2a) sum_k w_ik w_jk / (E_k - E)
+// for a batch of energies, as the symmetric contraction W diag(d(E)) W^T on
+// MFMA, plus the FP64 near-pole correction of the split-precision mode.
+#include "rm_internal.h"
+#include "rm.h"
+
+namespace rm {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// d_k(E) = 1/(2a (E_k - E)).  FP64 mode stores it in FP64.  Split mode stores
+// it rounded to FP32 and zero where |E_k - E| < delta (those poles are added
+// back in FP64 by k_nearpole).  The predicate is evaluated on the rounded
+// difference fl(E_k - E), which is monotone in E_k, so the masked poles form
+// one contiguous window [lo, hi) of the ascending pole list.
+// ---------------------------------------------------------------------------
+__global__ void k_dvec(const double *__restrict__ Ek, int M, int Mpad, const double *__restrict__ E,
+                       double inv2a, int split, double delta, double *__restrict__ D64,
+                       float *__restrict__ D32) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int e = blockIdx.y;
+  if (k >= Mpad) return;
+  const double Ev = E[e];
+  double d = 0.0;
+  if (k < M) {
+    const double diff = Ek[k] - Ev;
+    d = diff != 0.0 ? inv2a / diff : 0.0;  // exact pole: flagged, value unused
+    if (split && fabs(diff) < delta) d = 0.0;
+  }
+  if (split)
+    D32[(size_t)e * Mpad + k] = (float)d;
+  else
+    D64[(size_t)e * Mpad + k] = d;
+}
+
+// Window [lo, hi) of poles with |fl(E_k - E)| < delta, and the pole flag.
+__global__ void k_window(const double *__restrict__ Ek, int M, const double *__restrict__ E, int ne,
+                         double delta, int *__restrict__ win, int *__restrict__ status) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  const double Ev = E[e];
+  // first k with fl(E_k - E) > -delta
+  int lo = 0, hi = M;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (Ek[mid] - Ev > -delta) hi = mid; else lo = mid + 1;
+  }
+  const int wlo = lo;
+  lo = wlo; hi = M;
+  // first k with fl(E_k - E) >= delta
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (Ek[mid] - Ev >= delta) hi = mid; else lo = mid + 1;
+  }
+  win[2 * e] = wlo;
+  win[2 * e + 1] = lo;
+  // exact pole: first k with E_k >= E
+  lo = 0; hi = M;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (Ek[mid] >= Ev) hi = mid; else lo = mid + 1;
+  }
+  if (lo < M && Ek[lo] == Ev) atomicOr(status + e, RM_PT_POLE);
+}
+
+void launch_dvec(hipStream_t s, const DevPW &pw, const double *E, int ne, int split, double delta,
+                 double *D64, float *D32, int *win, int *status) {
+  dim3 grid((pw.Mpad + 255) / 256, ne);
+  hipLaunchKernelGGL(k_dvec, grid, dim3(256), 0, s, pw.Ek, pw.M, pw.Mpad, E, 0.5 / pw.a, split, delta,
+                     D64, D32);
+  hipLaunchKernelGGL(k_window, dim3((ne + 127) / 128), dim3(128), 0, s, pw.Ek, pw.M, E, ne,
+                     split ? delta : 0.0, win, status);
+}
+
+// ---------------------------------------------------------------------------
+// Contraction kernel.  One workgroup (4 waves) owns a 64 x 64 tile (bi, bj),
+// bi >= bj, of the lower triangle for EB energies.  Per stage it copies a
+// KC x 64 panel of W rows for the tile's channels i and j into LDS (one panel
+// when bi == bj), then every wave computes its 32 x 32 quarter with 2 x 2
+// MFMA 16x16x4 tiles per energy, scaling the A fragment by d_k(E) in
+// registers.  MFMA operand layout (16x16x4): lane l holds A[l%16][l/16] and
+// B[l/16][l%16]; the result rows are given by MfmaRow.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma16(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Result element v of lane l (kk = l/16) sits in row 4*kk + v for the FP32
+// 16x16x4 MFMA but in row 4*v + kk for the FP64 one; the column is l%16 in both.
+template <typename T> struct MfmaRow;
+template <> struct MfmaRow<float> {
+  static __device__ __forceinline__ int row(int kk, int v) { return 4 * kk + v; }
+};
+template <> struct MfmaRow<double> {
+  static __device__ __forceinline__ int row(int kk, int v) { return 4 * v + kk; }
+};
+
+template <typename T> struct Vec4;
+template <> struct Vec4<double> { typedef d4 type; };
+template <> struct Vec4<float> { typedef f4 type; };
+
+__device__ __forceinline__ void tri_tile(int t, int &bi, int &bj) {
+  int r = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+  while (r * (r + 1) / 2 > t) --r;
+  while ((r + 1) * (r + 2) / 2 <= t) ++r;
+  bi = r;
+  bj = t - r * (r + 1) / 2;
+}
+
+template <typename T, int KC>
+__global__ __launch_bounds__(256) void k_rform(const T *__restrict__ W, int ldw, int Mpad,
+                                               const T *__restrict__ D, int ne, int n,
+                                               double *__restrict__ R, long ldr, long strideR) {
+  typedef typename Vec4<T>::type V4;
+  __shared__ T sA[2][KC][TILE];
+  __shared__ T sB[2][KC][TILE];
+  __shared__ T sD[2][EB][KC];
+
+  int bi, bj;
+  tri_tile(blockIdx.x, bi, bj);
+  const bool diag = bi == bj;
+  const int e0 = blockIdx.y * EB;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int kk = lane >> 4, ii = lane & 15;
+  const int i0 = bi * TILE, j0 = bj * TILE;
+
+  V4 acc[EB][4];
+#pragma unroll
+  for (int e = 0; e < EB; ++e)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) acc[e][m] = V4{0, 0, 0, 0};
+
+  // global -> LDS copy of one stage: KC rows x 64 columns in 16-byte vectors
+  constexpr int VEC = 16 / sizeof(T);            // elements per 16-byte load
+  constexpr int PER_ROW = TILE / VEC;            // vectors per row
+  constexpr int NVEC = KC * PER_ROW / 256;       // vectors per thread per panel
+  typedef T TV __attribute__((ext_vector_type(VEC)));
+
+  // register-staged double buffering: the next stage's global loads are in
+  // flight while the current stage is multiplied out of LDS
+  TV ra[NVEC], rb[NVEC];
+  T rd = T(0);
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < NVEC; ++r) {
+      const int idx = tid + 256 * r;
+      const int row = idx / PER_ROW, col = (idx % PER_ROW) * VEC;
+      ra[r] = *reinterpret_cast<const TV *>(W + (size_t)(k0 + row) * ldw + i0 + col);
+      if (!diag) rb[r] = *reinterpret_cast<const TV *>(W + (size_t)(k0 + row) * ldw + j0 + col);
+    }
+    if (tid < EB * KC) {
+      const int e = tid / KC, k = tid % KC;
+      rd = (e0 + e < ne) ? D[(size_t)(e0 + e) * Mpad + k0 + k] : T(0);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < NVEC; ++r) {
+      const int idx = tid + 256 * r;
+      const int row = idx / PER_ROW, col = (idx % PER_ROW) * VEC;
+      *reinterpret_cast<TV *>(&sA[buf][row][col]) = ra[r];
+      if (!diag) *reinterpret_cast<TV *>(&sB[buf][row][col]) = rb[r];
+    }
+    if (tid < EB * KC) sD[buf][tid / KC][tid % KC] = rd;
+  };
+
+  const int nstage = Mpad / KC;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int st = 0; st < nstage; ++st) {
+    const int buf = st & 1;
+    if (st + 1 < nstage) gload((st + 1) * KC);
+    const T(*pA)[TILE] = sA[buf];
+    const T(*pB)[TILE] = diag ? sA[buf] : sB[buf];
+#pragma unroll 4
+    for (int ks = 0; ks < KC; ks += 4) {
+      const T a0 = pA[ks + kk][wr * 32 + ii];
+      const T a1 = pA[ks + kk][wr * 32 + 16 + ii];
+      const T b0 = pB[ks + kk][wc * 32 + ii];
+      const T b1 = pB[ks + kk][wc * 32 + 16 + ii];
+#pragma unroll
+      for (int e = 0; e < EB; ++e) {
+        const T d = sD[buf][e][ks + kk];
+        const T x0 = a0 * d, x1 = a1 * d;
+        acc[e][0] = mfma16(x0, b0, acc[e][0]);
+        acc[e][1] = mfma16(x0, b1, acc[e][1]);
+        acc[e][2] = mfma16(x1, b0, acc[e][2]);
+        acc[e][3] = mfma16(x1, b1, acc[e][3]);
+      }
+    }
+    if (st + 1 < nstage) sstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  // epilogue: lower-triangle elements are written to (i, j) and mirrored to (j, i)
+#pragma unroll
+  for (int e = 0; e < EB; ++e) {
+    if (e0 + e >= ne) break;
+    double *Re = R + (size_t)(e0 + e) * strideR;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int j = j0 + wc * 32 + (m & 1) * 16 + ii;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + wr * 32 + (m >> 1) * 16 + MfmaRow<T>::row(kk, v);
+        if (i < n && j < n && i >= j) {
+          const double val = (double)acc[e][m][v];
+          Re[(size_t)i * ldr + j] = val;
+          Re[(size_t)j * ldr + i] = val;
+        }
+      }
+    }
+  }
+}
+
+void launch_rform(hipStream_t s, const DevPW &pw, int ne, int split, const double *D64,
+                  const float *D32, double *R, long ldr, long strideR) {
+  const int nt = pw.npad / TILE;
+  dim3 grid(nt * (nt + 1) / 2, (ne + EB - 1) / EB);
+  if (split)
+    hipLaunchKernelGGL((k_rform<float, KC32>), grid, dim3(256), 0, s, pw.W32, pw.npad, pw.Mpad, D32,
+                       ne, pw.n, R, ldr, strideR);
+  else
+    hipLaunchKernelGGL((k_rform<double, KC64>), grid, dim3(256), 0, s, pw.W64, pw.npad, pw.Mpad, D64,
+                       ne, pw.n, R, ldr, strideR);
+}
+
+// ---------------------------------------------------------------------------
+// Near-pole correction of the split mode: R += 1/(2a) W[:, lo:hi] diag(1/(E_k - E))
+// W[:, lo:hi]^T in FP64, one workgroup per (lower tile, energy).  The window is
+// short (|E_k - E| < delta), so fragments are read straight from HBM/L2.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_nearpole(const double *__restrict__ W, int ldw,
+                                                  const double *__restrict__ Ek, const double *__restrict__ E,
+                                                  const int *__restrict__ win, double inv2a, int n,
+                                                  double *__restrict__ R, long ldr, long strideR) {
+  const int e = blockIdx.y;
+  const int lo = win[2 * e], hi = win[2 * e + 1];
+  if (lo >= hi) return;
+  int bi, bj;
+  tri_tile(blockIdx.x, bi, bj);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int kk = lane >> 4, ii = lane & 15;
+  const int i0 = bi * TILE + wr * 32, j0 = bj * TILE + wc * 32;
+  const double Ev = E[e];
+  d4 acc[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) acc[m] = d4{0, 0, 0, 0};
+  for (int k = lo; k < hi; k += 4) {
+    const int kr = k + kk;
+    double d = 0.0, a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+    if (kr < hi) {
+      const double diff = Ek[kr] - Ev;
+      d = diff != 0.0 ? inv2a / diff : 0.0;
+      const double *row = W + (size_t)kr * ldw;
+      a0 = row[i0 + ii];
+      a1 = row[i0 + 16 + ii];
+      b0 = row[j0 + ii];
+      b1 = row[j0 + 16 + ii];
+    }
+    const double x0 = a0 * d, x1 = a1 * d;
+    acc[0] = mfma16(x0, b0, acc[0]);
+    acc[1] = mfma16(x0, b1, acc[1]);
+    acc[2] = mfma16(x1, b0, acc[2]);
+    acc[3] = mfma16(x1, b1, acc[3]);
+  }
+  double *Re = R + (size_t)e * strideR;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int j = j0 + (m & 1) * 16 + ii;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + (m >> 1) * 16 + 4 * v + kk;
+      if (i < n && j < n && i >= j) {
+        const double val = Re[(size_t)i * ldr + j] + acc[m][v];
+        Re[(size_t)i * ldr + j] = val;
+        Re[(size_t)j * ldr + i] = val;
+      }
+    }
+  }
+}
+
+void launch_nearpole(hipStream_t s, const DevPW &pw, const double *E, int ne, const int *win,
+                     double *R, long ldr, long strideR) {
+  const int nt = pw.npad / TILE;
+  dim3 grid(nt * (nt + 1) / 2, ne);
+  hipLaunchKernelGGL(k_nearpole, grid, dim3(256), 0, s, pw.W64, pw.npad, pw.Ek, E, win, 0.5 / pw.a,
+                     pw.n, R, ldr, strideR);
+}
+
+__global__ void k_nanfill_R(int n, const int *__restrict__ status, double *__restrict__ R, long ldr,
+                            long strideR) {
+  const int e = blockIdx.y;
+  if (!(status[e] & RM_PT_POLE)) return;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < (long)n * n; t += (long)gridDim.x * blockDim.x)
+    R[(size_t)e * strideR + (t / n) * ldr + t % n] = __builtin_nan("");
+}
+
+void launch_nanfill_R(hipStream_t s, int ne, int n, const int *status, double *R, long ldr, long strideR) {
+  hipLaunchKernelGGL(k_nanfill_R, dim3(64, ne), dim3(256), 0, s, n, status, R, ldr, strideR);
+}
+
+}  // namespace rm

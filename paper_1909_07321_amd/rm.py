@@ -1,0 +1,283 @@
+"""Python binding of librm (C ABI in include/rm.h): argument marshalling only.
+
+Every computation runs in the HIP library.  Host inputs/outputs are numpy
+arrays; device inputs/outputs may be torch CUDA tensors, in which case the call
+is ordered on the tensor's current torch stream (``device_ptrs = 1``).  There is
+no fallback: if ``librm.so`` is missing or fails to load, importing this module
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("RM_LIB", os.path.join(_HERE, "librm.so"))
+
+RM_OK, RM_PENDING = 0, 1
+RM_E_ARG, RM_E_NOMEM, RM_E_DEVICE, RM_E_NOTFOUND, RM_E_BUSY = -1, -2, -3, -4, -5
+PT_POLE, PT_THRESHOLD, PT_NOCONV, PT_SINGULAR, PT_NONFINITE = 1, 2, 4, 8, 16
+FP64, FP32_SPLIT = 0, 1
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"librm.so not built ({LIB_PATH}); run __graft_entry__.build()")
+try:
+    # torch carries its own HIP runtime with the same soname as ROCm's; loading
+    # it first makes librm bind to that one copy, so a process never holds two
+    # HIP runtimes (torch tensors and librm then share device memory and streams)
+    import torch  # noqa: F401
+except ImportError:  # pragma: no cover - torch is optional for host-array use
+    torch = None
+_lib = ctypes.CDLL(LIB_PATH)
+
+_vp, _i32, _u64, _d, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double, ctypes.c_size_t
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int), ("split_delta", _d), ("thr_guard", _d), ("stream", _vp),
+                ("device_ptrs", _i32)]
+
+
+class PWDesc(ctypes.Structure):
+    _fields_ = [("nchan", _i32), ("npole", _i32), ("ntarget", _i32), ("a", _d), ("b", _d), ("z", _d),
+                ("g", _d), ("e_thr", _vp), ("l", _vp), ("target", _vp), ("Ek", _vp), ("w", _vp)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("pw_id", _i32), ("E", _vp), ("ne", _i32), ("opts", Opts), ("omega", _vp), ("K", _vp),
+                ("status", _vp)]
+
+
+class ReqStats(ctypes.Structure):
+    _fields_ = [("t_arrive_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64), ("t_start_ns", ctypes.c_int64),
+                ("t_done_ns", ctypes.c_int64), ("nblocks", _i32)]
+
+
+_lib.rm_opts_default.argtypes = [ctypes.POINTER(Opts)]
+_lib.rm_create.argtypes = [ctypes.c_int, _sz, ctypes.POINTER(_vp)]
+_lib.rm_destroy.argtypes = [_vp]
+_lib.rm_last_error.argtypes = [_vp]
+_lib.rm_last_error.restype = ctypes.c_char_p
+_lib.rm_pw_upload.argtypes = [_vp, ctypes.POINTER(PWDesc), ctypes.POINTER(_i32)]
+_lib.rm_pw_release.argtypes = [_vp, _i32]
+_lib.rm_pw_footprint.argtypes = [_i32, _i32]
+_lib.rm_pw_footprint.restype = _sz
+_lib.rm_form_R.argtypes = [_vp, _i32, _vp, _i32, ctypes.POINTER(Opts), _vp, _vp]
+_lib.rm_asymptotic.argtypes = [_vp, _i32, _vp, _i32, ctypes.POINTER(Opts), _vp, _vp, _vp, _vp]
+_lib.rm_solve_K.argtypes = [_vp, _i32, _vp, _i32, _vp, _vp, ctypes.POINTER(Opts), _vp, _vp]
+_lib.rm_collision_strengths.argtypes = [_vp, _i32, _vp, _i32, _vp, ctypes.POINTER(Opts), _vp, _vp, _vp]
+_lib.rm_run.argtypes = [_vp, _i32, _vp, _i32, ctypes.POINTER(Opts), _vp, _vp, _vp]
+_lib.rm_submit.argtypes = [_vp, ctypes.POINTER(Request), ctypes.POINTER(_u64)]
+_lib.rm_poll.argtypes = [_vp, _u64, ctypes.POINTER(ReqStats)]
+_lib.rm_drain.argtypes = [_vp]
+_lib.rm_prof_enable.argtypes = [_vp, _i32]
+_lib.rm_prof_read.argtypes = [_vp, ctypes.c_char_p, ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_int64),
+                              ctypes.POINTER(ctypes.c_int64)]
+
+EXPORTS = ["rm_opts_default", "rm_create", "rm_destroy", "rm_last_error", "rm_pw_upload", "rm_pw_release",
+           "rm_pw_footprint", "rm_form_R", "rm_asymptotic", "rm_solve_K", "rm_collision_strengths", "rm_run",
+           "rm_submit", "rm_poll", "rm_drain", "rm_prof_enable", "rm_prof_read"]
+
+
+class RMError(RuntimeError):
+    pass
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if _is_torch(x):
+        return ctypes.c_void_p(x.data_ptr())
+    return x.ctypes.data_as(ctypes.c_void_p)
+
+
+def pw_footprint(nchan: int, npole: int) -> int:
+    return int(_lib.rm_pw_footprint(nchan, npole))
+
+
+class Context:
+    """One librm context on a HIP device (rm_create / rm_destroy)."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        h = _vp()
+        self._check(_lib.rm_create(device, hbm_budget_bytes, ctypes.byref(h)), None)
+        self.h = h
+        self.device = device
+        self._pw = {}
+
+    def _check(self, st: int, h=...):
+        if st < 0:
+            msg = _lib.rm_last_error(self.h if h is ... else h)
+            raise RMError(f"librm status {st}: {msg.decode() if msg else ''}")
+        return st
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.rm_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------
+    def pw_upload(self, pw) -> int:
+        """Upload a synth.PartialWave (or any object with the same fields)."""
+        keep = [np.ascontiguousarray(pw.e_thr, dtype=np.float64), np.ascontiguousarray(pw.l, dtype=np.int32),
+                np.ascontiguousarray(pw.target, dtype=np.int32), np.ascontiguousarray(pw.Ek, dtype=np.float64),
+                np.ascontiguousarray(pw.w, dtype=np.float64)]
+        d = PWDesc(pw.nchan, pw.npole, pw.ntarget, pw.a, pw.b, pw.z, pw.g, *[k.ctypes.data for k in keep])
+        pid = _i32()
+        self._check(_lib.rm_pw_upload(self.h, ctypes.byref(d), ctypes.byref(pid)))
+        self._pw[pid.value] = (pw.nchan, pw.ntarget)
+        return pid.value
+
+    def pw_release(self, pw_id: int):
+        self._check(_lib.rm_pw_release(self.h, pw_id))
+        self._pw.pop(pw_id, None)
+
+    def _opts(self, prec, split_delta, thr_guard, dev, stream=None):
+        o = Opts()
+        _lib.rm_opts_default(ctypes.byref(o))
+        o.prec = int(prec)
+        o.split_delta = float(split_delta)
+        o.thr_guard = float(thr_guard)
+        o.device_ptrs = 1 if dev else 0
+        if dev:
+            import torch
+            o.stream = ctypes.c_void_p(stream if stream is not None else torch.cuda.current_stream().cuda_stream)
+        return o
+
+    def _alloc(self, like, shape, dtype):
+        if _is_torch(like):
+            import torch
+            tdt = {np.float64: torch.float64, np.int32: torch.int32, np.int8: torch.int8}[dtype]
+            return torch.empty(shape, dtype=tdt, device=like.device)
+        return np.empty(shape, dtype=dtype)
+
+    def _E(self, E):
+        if _is_torch(E):
+            assert E.is_cuda and E.dtype.is_floating_point and E.is_contiguous()
+            return E, True
+        return np.ascontiguousarray(E, dtype=np.float64), False
+
+    def form_R(self, pw_id, E, prec=FP64, split_delta=0.05, thr_guard=1e-10):
+        E, dev = self._E(E)
+        n, _ = self._pw.get(pw_id, (1, 1))
+        ne = E.shape[0]
+        R = self._alloc(E, (ne, n, n), np.float64)
+        st = self._alloc(E, (ne,), np.int32)
+        o = self._opts(prec, split_delta, thr_guard, dev)
+        self._check(_lib.rm_form_R(self.h, pw_id, _ptr(E), ne, ctypes.byref(o), _ptr(R), _ptr(st)))
+        return R, st
+
+    def asymptotic(self, pw_id, E, thr_guard=1e-10):
+        E, dev = self._E(E)
+        n, _ = self._pw.get(pw_id, (1, 1))
+        ne = E.shape[0]
+        fg = self._alloc(E, (ne, n, 4), np.float64)
+        op = self._alloc(E, (ne, n), np.int8)
+        no = self._alloc(E, (ne,), np.int32)
+        st = self._alloc(E, (ne,), np.int32)
+        o = self._opts(FP64, 0.05, thr_guard, dev)
+        self._check(_lib.rm_asymptotic(self.h, pw_id, _ptr(E), ne, ctypes.byref(o), _ptr(fg), _ptr(op), _ptr(no),
+                                       _ptr(st)))
+        return fg, op, no, st
+
+    def solve_K(self, pw_id, E, R, fg, thr_guard=1e-10):
+        E, dev = self._E(E)
+        n, _ = self._pw.get(pw_id, (1, 1))
+        ne = E.shape[0]
+        if not dev:
+            R = np.ascontiguousarray(R, dtype=np.float64)
+            fg = np.ascontiguousarray(fg, dtype=np.float64)
+        K = self._alloc(E, (ne, n, n), np.float64)
+        st = self._alloc(E, (ne,), np.int32)
+        o = self._opts(FP64, 0.05, thr_guard, dev)
+        self._check(_lib.rm_solve_K(self.h, pw_id, _ptr(E), ne, _ptr(R), _ptr(fg), ctypes.byref(o), _ptr(K),
+                                    _ptr(st)))
+        return K, st
+
+    def collision_strengths(self, pw_id, E, K, thr_guard=1e-10, want_S=False):
+        E, dev = self._E(E)
+        n, nt = self._pw.get(pw_id, (1, 1))
+        ne = E.shape[0]
+        if not dev:
+            K = np.ascontiguousarray(K, dtype=np.float64)
+        om = self._alloc(E, (ne, nt, nt), np.float64)
+        S = self._alloc(E, (ne, n, n, 2), np.float64) if want_S else None
+        st = self._alloc(E, (ne,), np.int32)
+        o = self._opts(FP64, 0.05, thr_guard, dev)
+        self._check(_lib.rm_collision_strengths(self.h, pw_id, _ptr(E), ne, _ptr(K), ctypes.byref(o), _ptr(om),
+                                                _ptr(S), _ptr(st)))
+        if want_S and not dev:
+            S = S[..., 0] + 1j * S[..., 1]
+        return om, S, st
+
+    def run(self, pw_id, E, prec=FP64, split_delta=0.05, thr_guard=1e-10, want_K=True, out=None, stream=None):
+        """Fused R -> asymptotics -> K -> Omega for a block of energies."""
+        E, dev = self._E(E)
+        n, nt = self._pw.get(pw_id, (1, 1))
+        ne = E.shape[0]
+        if out is None:
+            om = self._alloc(E, (ne, nt, nt), np.float64)
+            K = self._alloc(E, (ne, n, n), np.float64) if want_K else None
+            st = self._alloc(E, (ne,), np.int32)
+        else:
+            om, K, st = out
+        o = self._opts(prec, split_delta, thr_guard, dev, stream)
+        self._check(_lib.rm_run(self.h, pw_id, _ptr(E), ne, ctypes.byref(o), _ptr(om), _ptr(K), _ptr(st)))
+        return om, K, st
+
+    # ------------------------------------------------------------ serving
+    def submit(self, pw_id, E, prec=FP64, split_delta=0.05, thr_guard=1e-10, want_K=False):
+        """Queue a request; returns (ticket, outputs dict).  The output arrays
+        belong to the request until poll() reports it done."""
+        n, nt = self._pw.get(pw_id, (1, 1))
+        E = np.ascontiguousarray(E, dtype=np.float64)
+        ne = E.shape[0]
+        outs = dict(omega=np.empty((ne, nt, nt)), K=np.empty((ne, n, n)) if want_K else None,
+                    status=np.zeros(ne, np.int32), E=E)
+        o = self._opts(prec, split_delta, thr_guard, False)
+        rq = Request(pw_id, E.ctypes.data, ne, o, outs["omega"].ctypes.data,
+                     outs["K"].ctypes.data if want_K else None, outs["status"].ctypes.data)
+        t = _u64()
+        self._check(_lib.rm_submit(self.h, ctypes.byref(rq), ctypes.byref(t)))
+        return t.value, outs
+
+    def poll(self, ticket):
+        """Returns None while pending, else the request's timing stats (ns)."""
+        s = ReqStats()
+        st = _lib.rm_poll(self.h, ticket, ctypes.byref(s))
+        if st == RM_PENDING:
+            return None
+        self._check(st)
+        return dict(t_arrive_ns=s.t_arrive_ns, t_admit_ns=s.t_admit_ns, t_start_ns=s.t_start_ns,
+                    t_done_ns=s.t_done_ns, nblocks=s.nblocks)
+
+    def drain(self):
+        self._check(_lib.rm_drain(self.h))
+
+    # ---------------------------------------------------------- profiling
+    def prof_enable(self, on: bool = True):
+        self._check(_lib.rm_prof_enable(self.h, 1 if on else 0))
+
+    def prof_read(self, stage: str):
+        """(total_ms, launches, energies) of a stage since the last read."""
+        ms, nl, ne = _d(), ctypes.c_int64(), ctypes.c_int64()
+        self._check(_lib.rm_prof_read(self.h, stage.encode(), ctypes.byref(ms), ctypes.byref(nl), ctypes.byref(ne)))
+        return ms.value, nl.value, ne.value

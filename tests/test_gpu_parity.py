@@ -1,0 +1,207 @@
+"""GPU parity: every stage of librm against the FP64 oracle on the same seeded
+inputs (PSTGF paper: eq. (rmatrix), the asymptotic forms of section "Overview",
+eq. (match), and the Glossary's T-matrix / collision strength).
+
+Metrics (normwise, per energy): ||X_gpu - X_ora||_max / max(1e-300, ||X_ora||_max)
+for R and K; per channel for the asymptotic functions; Omega elementwise
+relative above a floor of 1e-12 * max(Omega).  FP64 gate: 1e-10.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1909_07321_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+GATE = 1e-10
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1909_07321_amd import rm
+    c = rm.Context(0)
+    yield c
+    c.close()
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def normwise(a, b):
+    a = a.reshape(a.shape[0], -1)
+    b = b.reshape(b.shape[0], -1)
+    return np.abs(a - b).max(axis=1) / np.maximum(np.abs(b).max(axis=1), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return synth.config1()
+
+
+@pytest.fixture(scope="module")
+def c2():
+    pw, E = synth.config2()
+    return pw, E[::20]   # 100 energies spanning [0.01, 6] Ry
+
+
+@pytest.fixture(scope="module")
+def c2_oracle(c2):
+    pw, E = c2
+    o = oracle.Oracle(pw)
+    R, stR = o.form_R(E)
+    fg, op, no, stA = o.asymptotic(E)
+    K, cond, stK = o.solve_K(E, R, fg)
+    om, S, stO = o.collision_strengths(E, K, want_S=True)
+    return dict(R=R, fg=fg, open=op, nopen=no, K=K, cond=cond, omega=om, S=S)
+
+
+@pytest.mark.parametrize("cfg", ["c1", "c2"])
+def test_form_R_fp64(ctx, cfg, c1, c2, c2_oracle):
+    pw, E = c1 if cfg == "c1" else c2
+    _say("form_R fp64", cfg, pw.nchan, pw.npole, E.size)
+    pid = ctx.pw_upload(pw)
+    R, st = ctx.form_R(pid, E)
+    Ro = oracle.Oracle(pw).form_R(E)[0] if cfg == "c1" else c2_oracle["R"]
+    assert (st == 0).all()
+    err = normwise(R, Ro)
+    _say("R fp64 normwise max", err.max())
+    assert err.max() < GATE
+    assert np.array_equal(R, np.transpose(R, (0, 2, 1)))
+    ctx.pw_release(pid)
+
+
+def test_form_R_split_error_distribution(ctx, c2, c2_oracle):
+    pw, E = c2
+    pid = ctx.pw_upload(pw)
+    R, st = ctx.form_R(pid, E, prec=1)
+    err = normwise(R, c2_oracle["R"])
+    _say(f"R split normwise median {np.median(err):.2e} p99 {np.quantile(err, .99):.2e} max {err.max():.2e}")
+    assert err.max() < 1e-5
+    ctx.pw_release(pid)
+
+
+@pytest.mark.parametrize("cfg", ["c1", "c2"])
+def test_asymptotic(ctx, cfg, c1, c2, c2_oracle):
+    pw, E = c1 if cfg == "c1" else c2
+    pid = ctx.pw_upload(pw)
+    fg, op, no, st = ctx.asymptotic(pid, E)
+    if cfg == "c1":
+        fgo, opo, noo, sto = oracle.Oracle(pw).asymptotic(E)
+    else:
+        fgo, opo, noo = c2_oracle["fg"], c2_oracle["open"], c2_oracle["nopen"]
+    assert (st == 0).all()
+    assert np.array_equal(op, opo) and np.array_equal(no, noo)
+    scale = np.abs(fgo).max(axis=2)
+    err = np.abs(fg - fgo).max(axis=2) / scale
+    _say(f"asym per-channel max {err.max():.2e} median {np.median(err):.2e}")
+    assert err.max() < GATE
+    ctx.pw_release(pid)
+
+
+def test_solve_K_from_oracle_inputs(ctx, c2, c2_oracle):
+    pw, E = c2
+    pid = ctx.pw_upload(pw)
+    K, st = ctx.solve_K(pid, E, c2_oracle["R"], c2_oracle["fg"])
+    assert (st == 0).all()
+    no = c2_oracle["nopen"]
+    errs = []
+    for e in range(E.size):
+        n0 = no[e]
+        if n0 == 0:
+            continue
+        Ko = c2_oracle["K"][e, :n0, :n0]
+        errs.append(np.abs(K[e, :n0, :n0] - Ko).max() / max(1.0, np.abs(Ko).max()))
+        assert np.all(K[e, n0:, :] == 0) and np.all(K[e, :, n0:] == 0)
+    errs = np.array(errs)
+    _say(f"K (oracle R, fg) normwise max {errs.max():.2e} median {np.median(errs):.2e}")
+    assert errs.max() < GATE
+    ctx.pw_release(pid)
+
+
+def test_collision_strengths_from_oracle_K(ctx, c2, c2_oracle):
+    pw, E = c2
+    pid = ctx.pw_upload(pw)
+    om, S, st = ctx.collision_strengths(pid, E, c2_oracle["K"], want_S=True)
+    assert (st == 0).all()
+    omo = c2_oracle["omega"]
+    floor = 1e-12 * omo.max(axis=(1, 2), keepdims=True)
+    err = (np.abs(om - omo) / np.maximum(np.abs(omo), floor)).max(axis=(1, 2))
+    _say(f"Omega (oracle K) max rel {err.max():.2e}")
+    assert err.max() < GATE
+    no = c2_oracle["nopen"]
+    for e in range(E.size):
+        n0 = no[e]
+        d = np.abs(S[e, :n0, :n0] - c2_oracle["S"][e, :n0, :n0]).max()
+        assert d < GATE
+    ctx.pw_release(pid)
+
+
+@pytest.mark.parametrize("cfg", ["c1", "c2"])
+def test_run_end_to_end_fp64(ctx, cfg, c1, c2, c2_oracle):
+    pw, E = c1 if cfg == "c1" else c2
+    pid = ctx.pw_upload(pw)
+    om, K, st = ctx.run(pid, E)
+    if cfg == "c1":
+        res = oracle.Oracle(pw).run(E)
+        Ko, omo, no, cond = res["K"], res["omega"], oracle.open_count(pw, E), res["cond"]
+    else:
+        Ko, omo, no, cond = c2_oracle["K"], c2_oracle["omega"], c2_oracle["nopen"], c2_oracle["cond"]
+    assert (st == 0).all()
+    errK = np.array([np.abs(K[e, :no[e], :no[e]] - Ko[e, :no[e], :no[e]]).max() / max(1, np.abs(Ko[e]).max())
+                     for e in range(E.size) if no[e]])
+    floor = 1e-12 * omo.max(axis=(1, 2), keepdims=True)
+    errO = (np.abs(om - omo) / np.maximum(np.abs(omo), floor)).max(axis=(1, 2))
+    _say(f"{cfg} end-to-end K max {errK.max():.2e} median {np.median(errK):.2e}; Omega max {errO.max():.2e};"
+         f" cond max {np.nanmax(cond):.1e}")
+    assert errK.max() < GATE and errO.max() < GATE
+    ctx.pw_release(pid)
+
+
+def test_edge_cases(ctx, c1):
+    pw, E = c1
+    pid = ctx.pw_upload(pw)
+    # exact pole, threshold guard, below every open threshold, ragged count
+    Ee = np.array([pw.Ek[10], 0.5 + 1e-12, 0.2, 2.5, 1.0])
+    om, K, st = ctx.run(pid, Ee)
+    res = oracle.Oracle(pw).run(Ee)
+    assert st[0] & 1 and np.isnan(om[0]).all()
+    assert st[1] & 2 and np.isnan(om[1]).all()
+    assert st[2] == 0 and st[3] == 0 and st[4] == 0
+    np.testing.assert_allclose(om[2:], res["omega"][2:], rtol=1e-10, atol=1e-14)
+    R, stR = ctx.form_R(pid, Ee[:1])
+    assert stR[0] & 1 and np.isnan(R).all()
+    # empty request
+    om0, K0, st0 = ctx.run(pid, np.zeros(0))
+    assert om0.shape[0] == 0
+    ctx.pw_release(pid)
+
+
+def test_single_channel_and_neutral(ctx):
+    import math
+    rng = np.random.default_rng(4)
+    Ek = np.sort(rng.uniform(-1, 30, 12))
+    w = rng.normal(size=(12, 1)) / math.sqrt(8.0)
+    pw = synth.PartialWave(1, 12, 1, 8.0, 0.0, 0.0, 1.0, np.zeros(1), np.zeros(1, np.int32),
+                           np.zeros(1, np.int32), Ek, w)
+    pid = ctx.pw_upload(pw)
+    E = np.linspace(0.05, 3.0, 37)
+    om, K, st = ctx.run(pid, E)
+    R, _ = ctx.form_R(pid, E)
+    k = np.sqrt(E)
+    ka = k * 8.0
+    r = R[:, 0, 0]
+    tand = (ka * r * np.cos(ka) - np.sin(ka)) / (np.cos(ka) + ka * r * np.sin(ka))
+    np.testing.assert_allclose(K[:, 0, 0], tand, rtol=1e-11, atol=1e-12)
+    np.testing.assert_allclose(om[:, 0, 0], 2 * tand ** 2 / (1 + tand ** 2), rtol=1e-11, atol=1e-13)
+    ctx.pw_release(pid)
+
+
+def test_unknown_pw_and_bad_args(ctx):
+    from paper_1909_07321_amd import rm
+    with pytest.raises(rm.RMError):
+        ctx.run(12345, np.array([1.0]))

@@ -1,0 +1,128 @@
+"""GPU checks at the benchmark's full size (1500 channels, 60000 poles) and of
+the execution properties: device pointers, determinism, alone-vs-batch.
+
+Full-size parity uses what the oracle can compute one by one: individual R
+entries (a two-channel sub-problem has exactly the entries R_ii, R_ij, R_jj of
+eq. (rmatrix)), and the complete K and Omega of one mid-grid energy."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1909_07321_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1909_07321_amd import rm
+    c = rm.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def c4():
+    return synth.config4()
+
+
+@pytest.fixture(scope="module")
+def c4_pid(ctx, c4):
+    pid = ctx.pw_upload(c4[0])
+    yield pid
+    ctx.pw_release(pid)
+
+
+def _sub_pw(pw, i, j):
+    cols = [i, j] if i != j else [i]
+    return synth.PartialWave(len(cols), pw.npole, 1, pw.a, pw.b, pw.z, pw.g, np.zeros(1), pw.l[cols],
+                             np.zeros(len(cols), np.int32), pw.Ek, np.ascontiguousarray(pw.w[:, cols]))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_c4_R_sampled_entries(ctx, c4, c4_pid, prec):
+    pw, E = c4
+    sel = E[[0, 333, 501, 999]]
+    _say("c4 form_R", "fp64" if prec == 0 else "split", sel)
+    R, st = ctx.form_R(c4_pid, sel, prec=prec)
+    assert (st == 0).all()
+    rng = np.random.default_rng(7)
+    pairs = [(int(a), int(b)) for a, b in rng.integers(0, pw.nchan, size=(24, 2))] + [(1499, 0), (1499, 1499), (64, 63)]
+    worst = 0.0
+    for i, j in pairs:
+        Rs, _ = oracle.Oracle(_sub_pw(pw, i, j), nthreads=4).form_R(sel)
+        ref = Rs[:, 0, -1]
+        scale = np.abs(R).reshape(sel.size, -1).max(axis=1)   # normwise per energy
+        worst = max(worst, (np.abs(R[:, i, j] - ref) / scale).max())
+    _say(f"c4 R sampled entries worst normwise {worst:.2e}")
+    assert worst < (1e-10 if prec == 0 else 1e-5)
+
+
+def test_c4_full_energy_vs_oracle(ctx, c4, c4_pid):
+    pw, E = c4
+    sel = E[[500]]
+    om, K, st = ctx.run(c4_pid, sel)
+    res = oracle.Oracle(pw, nthreads=16).run(sel)
+    no = oracle.open_count(pw, sel)[0]
+    assert st[0] == 0 and res["status"][0] == 0
+    Ko = res["K"][0, :no, :no]
+    errK = np.abs(K[0, :no, :no] - Ko).max() / max(1, np.abs(Ko).max())
+    floor = 1e-12 * res["omega"].max()
+    errO = (np.abs(om - res["omega"]) / np.maximum(np.abs(res["omega"]), floor)).max()
+    _say(f"c4 E={sel[0]:.3f} no={no} cond={res['cond'][0]:.2e} K err {errK:.2e} Omega err {errO:.2e}")
+    assert errK < 1e-10 * max(1.0, res["cond"][0] / 1e4) and errO < 1e-10 * max(1.0, res["cond"][0] / 1e4)
+    # split mode on the same energy: stated tolerance
+    om2, K2, st2 = ctx.run(c4_pid, sel, prec=1)
+    errK2 = np.abs(K2[0, :no, :no] - Ko).max() / max(1, np.abs(Ko).max())
+    errO2 = (np.abs(om2 - res["omega"]) / np.maximum(np.abs(res["omega"]), 1e-6 * res["omega"].max())).max()
+    _say(f"c4 split K err {errK2:.2e} Omega err {errO2:.2e}")
+
+
+def test_c4_run_properties(ctx, c4, c4_pid):
+    pw, E = c4
+    sel = E[::16]
+    om, K, st = ctx.run(c4_pid, sel)
+    assert (st == 0).all(), st
+    assert np.isfinite(om).all() and om.min() >= 0
+    assert np.abs(om - np.transpose(om, (0, 2, 1))).max() <= 1e-9 * om.max()
+    no = oracle.open_count(pw, sel)
+    asym = max(np.abs(K[e, :no[e], :no[e]] - K[e, :no[e], :no[e]].T).max() / max(1, np.abs(K[e]).max())
+               for e in range(sel.size) if no[e])
+    _say(f"c4 K asymmetry max {asym:.2e}")
+    assert asym < 1e-8
+
+
+def test_device_pointers_match_host(ctx):
+    import torch
+    pw, E = synth.config2()
+    E = E[::50]
+    pid = ctx.pw_upload(pw)
+    om_h, K_h, st_h = ctx.run(pid, E)
+    Ed = torch.tensor(E, device="cuda")
+    om_d, K_d, st_d = ctx.run(pid, Ed)
+    torch.cuda.synchronize()
+    assert np.array_equal(om_h, om_d.cpu().numpy()) and np.array_equal(K_h, K_d.cpu().numpy())
+    R_h, _ = ctx.form_R(pid, E)
+    R_d, _ = ctx.form_R(pid, Ed)
+    torch.cuda.synchronize()
+    assert np.array_equal(R_h, R_d.cpu().numpy())
+    ctx.pw_release(pid)
+
+
+def test_deterministic_and_batch_independent(ctx):
+    pw, E = synth.config2()
+    pid = ctx.pw_upload(pw)
+    Eb = E[::37]
+    a = ctx.run(pid, Eb)
+    b = ctx.run(pid, Eb)
+    assert all(np.array_equal(x, y) for x, y in zip(a, b))
+    for prec in (0, 1):
+        full = ctx.run(pid, Eb, prec=prec)
+        for e in [0, 7, 31, Eb.size - 1]:
+            one = ctx.run(pid, Eb[e:e + 1], prec=prec)
+            assert np.array_equal(one[0][0], full[0][e]) and np.array_equal(one[1][0], full[1][e])
+    ctx.pw_release(pid)

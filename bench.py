@@ -28,6 +28,60 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def serve_measure(ctx, nreq: int) -> dict:
+    """Open-loop Poisson stream through rm_submit/rm_poll on a pool of resident
+    partial waves (channel counts log-uniform in 10..2000, 30-40 poles per
+    channel, energies in [0.01, 8] Ry), half FP64 and half FP32-split requests.
+    The arrival rate is 0.7 x the capacity measured by a closed-loop burst."""
+    import numpy as np
+
+    from paper_1909_07321_amd import rm, synth
+
+    pool = synth.config5_pool(16, 2000)
+    ids = [ctx.pw_upload(p) for p in pool]
+    block = (100, 4000)
+
+    def run_stream(reqs, rate_hz=None):
+        t0 = time.perf_counter()
+        tickets, pts = [], 0
+        for k, r in enumerate(reqs):
+            if rate_hz:
+                wait = t0 + r.arrival_s - time.perf_counter()
+                if wait > 0:
+                    time.sleep(wait)
+            t, _ = ctx.submit(ids[r.pw_index], r.energies, prec=rm.FP32_SPLIT if k % 2 else rm.FP64)
+            tickets.append(t)
+            pts += r.energies.size
+        stats, pending = [], set(tickets)
+        while pending:
+            for t in list(pending):
+                st = ctx.poll(t)
+                if st is not None:
+                    stats.append(st)
+                    pending.discard(t)
+            time.sleep(0.0005)
+        return pts, time.perf_counter() - t0, stats
+
+    burst = synth.config5_requests(pool, nreq=8, rate_hz=1.0, block_range=block)
+    pts, dt, _ = run_stream(burst)
+    capacity = pts / dt
+    mean_pts = float(np.mean([r.energies.size for r in burst]))
+    rate = 0.7 * capacity / mean_pts
+    reqs = synth.config5_requests(pool, nreq=nreq, rate_hz=rate, block_range=block)
+    pts, dt, stats = run_stream(reqs, rate_hz=rate)
+    lat = np.array([(s["t_done_ns"] - s["t_arrive_ns"]) * 1e-6 for s in stats])
+    for i in ids:
+        ctx.pw_release(i)
+    out = dict(requests=nreq, arrival_rate_hz=rate, capacity_points_per_s=capacity, points=pts,
+               points_per_s=pts / dt, p50_ms=float(np.median(lat)), p99_ms=float(np.quantile(lat, 0.99)),
+               max_ms=float(lat.max()), pool="16 partial waves, n log-uniform 10..2000, 30-40 poles/channel",
+               blocks=f"log-uniform {block[0]}..{block[1]} energies (reduced from 100..20000 to bound the run)",
+               modes="alternating FP64 / FP32-split requests")
+    log(f"serving: {nreq} requests at {rate:.2f}/s, {out['points_per_s']:.0f} points/s, "
+        f"p50 {out['p50_ms']:.0f} ms, p99 {out['p99_ms']:.0f} ms")
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -38,6 +92,10 @@ def main() -> int:
     ap.add_argument("--nenergy", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-threads", type=int, default=16)
+    ap.add_argument("--serving", type=int, default=32, metavar="NREQ",
+                    help="requests in the serving measurement (0 = skip)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first run a 1 GiB device copy (HBM counter calibration under rocprofv3 --pmc)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -50,6 +108,16 @@ def main() -> int:
     import torch
 
     from paper_1909_07321_amd import rm, synth
+
+    if args.copy_probe:
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: 1 GiB device-to-device copy done")
+        del src, dst
 
     t0 = time.time()
     pw, E = synth.config4(args.nenergy)
@@ -98,6 +166,10 @@ def main() -> int:
             + ", ".join(f"{s}={v[0] / args.steps:.1f}ms" for s, v in stages.items())
             + (f", R contraction {achieved:.1f} TFLOP/s" if achieved else ""))
 
+    serving = None
+    if args.serving > 0:
+        serving = serve_measure(ctx, args.serving)
+
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -126,6 +198,7 @@ def main() -> int:
         "roofline": head["roofline"],
         "cpu_baseline": cpu,
         "modes": results,
+        "serving": serving,
     }
     print(json.dumps(line), flush=True)
     ctx.close()

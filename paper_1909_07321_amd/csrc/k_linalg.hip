@@ -79,48 +79,55 @@ __device__ __forceinline__ long vcol(int v, int rows, int c0, long roff) {
 
 // Panel factorisation: columns [j0, j0 + jb) over rows [j0, rows), with row
 // interchanges applied to every column right of j0 (A and right-hand sides).
-__global__ __launch_bounds__(256) void k_lu_panel(int j0, const int *__restrict__ dims,
-                                                  double *__restrict__ aug, long ldaug, long strideA,
-                                                  long roff, int *__restrict__ status) {
+// One 1024-thread workgroup per energy: each thread owns rows t, t + 1024, ...;
+// the pivot search reduces within each wave by shuffles and across waves in
+// LDS (ties go to the smaller row, so the choice is deterministic), and the
+// pivot row's panel segment is staged in LDS for the rank-1 update.
+constexpr int PANEL_T = 256;
+__global__ __launch_bounds__(PANEL_T) void k_lu_panel(int j0, const int *__restrict__ dims,
+                                                      double *__restrict__ aug, long ldaug, long strideA,
+                                                      long roff, int *__restrict__ status) {
   const int e = blockIdx.x;
   const int rows = dims[2 * e], rhs = dims[2 * e + 1];
   if (j0 >= rows) return;
   const int jb = min(NB, rows - j0);
   double *A = aug + (size_t)e * strideA;
-  const int t = threadIdx.x;
-  __shared__ double sval[256];
-  __shared__ int sidx[256];
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  __shared__ double wv[PANEL_T / 64];
+  __shared__ int wi[PANEL_T / 64];
   __shared__ int spiv;
-  __shared__ double spv;
+  __shared__ double prow[NB];
   const int ncol_right = (rows - j0) + rhs;  // virtual columns from j0
   for (int c = j0; c < j0 + jb; ++c) {
-    // pivot search over rows c..rows-1 (ties -> smallest row)
     double best = -1.0;
-    int bidx = c;
-    for (int r = c + t; r < rows; r += 256) {
+    int bidx = rows;
+    for (int r = c + t; r < rows; r += PANEL_T) {
       const double v = fabs(A[(size_t)r * ldaug + c]);
       if (v > best) { best = v; bidx = r; }
     }
-    sval[t] = best;
-    sidx[t] = bidx;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-      if (t < off) {
-        const double vo = sval[t + off];
-        const int io = sidx[t + off];
-        if (vo > sval[t] || (vo == sval[t] && io < sidx[t])) { sval[t] = vo; sidx[t] = io; }
-      }
-      __syncthreads();
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(best, off);
+      const int oi = __shfl_xor(bidx, off);
+      if (ov > best || (ov == best && oi < bidx)) { best = ov; bidx = oi; }
     }
+    if (lane == 0) { wv[wid] = best; wi[wid] = bidx; }
+    __syncthreads();
     if (t == 0) {
-      spiv = sidx[0];
-      spv = sval[0];
-      if (!(sval[0] > 0.0)) atomicOr(status + e, RM_PT_SINGULAR);
+      double bv = wv[0];
+      int bi = wi[0];
+      for (int w = 1; w < PANEL_T / 64; ++w)
+        if (wv[w] > bv || (wv[w] == bv && wi[w] < bi)) { bv = wv[w]; bi = wi[w]; }
+      if (!(bv > 0.0) || bi >= rows) {
+        atomicOr(status + e, RM_PT_SINGULAR);
+        bi = c;
+      }
+      spiv = bi;
     }
     __syncthreads();
     const int p = spiv;
     if (p != c) {
-      for (int v = t; v < ncol_right; v += 256) {
+      for (int v = t; v < ncol_right; v += PANEL_T) {
         const long col = vcol(v, rows, j0, roff);
         const double x = A[(size_t)c * ldaug + col];
         A[(size_t)c * ldaug + col] = A[(size_t)p * ldaug + col];
@@ -128,13 +135,15 @@ __global__ __launch_bounds__(256) void k_lu_panel(int j0, const int *__restrict_
       }
     }
     __syncthreads();
-    const double piv = A[(size_t)c * ldaug + c];
+    if (t < jb) prow[t] = A[(size_t)c * ldaug + j0 + t];
+    __syncthreads();
+    const double piv = prow[c - j0];
     const double inv = piv != 0.0 ? 1.0 / piv : 0.0;
-    for (int r = c + 1 + t; r < rows; r += 256) {
+    for (int r = c + 1 + t; r < rows; r += PANEL_T) {
       double *row = A + (size_t)r * ldaug;
       const double m = row[c] * inv;
       row[c] = m;
-      for (int q = c + 1; q < j0 + jb; ++q) row[q] -= m * A[(size_t)c * ldaug + q];
+      for (int q = c + 1; q < j0 + jb; ++q) row[q] -= m * prow[q - j0];
     }
     __syncthreads();
   }
@@ -318,7 +327,7 @@ __global__ __launch_bounds__(256) void k_bs_update(int j0, const int *__restrict
 void launch_lu_solve(hipStream_t s, int ne, int maxrows, int maxrhs, const int *dims, double *aug,
                      long ldaug, long strideA, long roff, int *status) {
   for (int j0 = 0; j0 < maxrows; j0 += NB) {
-    hipLaunchKernelGGL(k_lu_panel, dim3(ne), dim3(256), 0, s, j0, dims, aug, ldaug, strideA, roff, status);
+    hipLaunchKernelGGL(k_lu_panel, dim3(ne), dim3(PANEL_T), 0, s, j0, dims, aug, ldaug, strideA, roff, status);
     const int c0 = min(maxrows, j0 + NB);
     const int ncols = (maxrows - c0) + maxrhs;
     if (ncols <= 0) continue;

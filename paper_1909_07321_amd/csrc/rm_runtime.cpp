@@ -83,6 +83,10 @@ struct rm_ctx {
   int max_queue = 4096;
   std::atomic<int> prof_on{0};
   std::vector<ProfRec> prof;  // guarded by mu
+  // rm_run alternates chunks over two streams so that one chunk's K solve
+  // overlaps the next chunk's R contraction
+  Slot pipe[2];
+  hipEvent_t ev_in = nullptr, ev_out[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -441,6 +445,16 @@ rm_status rm_destroy(rm_ctx *ctx) {
   }
   (void)hipStreamSynchronize(ctx->stream);
   free_work(ctx->work);
+  for (auto &pp : ctx->pipe) {
+    if (pp.stream) {
+      (void)hipStreamSynchronize(pp.stream);
+      (void)hipStreamDestroy(pp.stream);
+    }
+    free_work(pp.w);
+  }
+  if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
+  for (auto &ev : ctx->ev_out)
+    if (ev) (void)hipEventDestroy(ev);
   for (auto &kv : ctx->pws) {
     DevPW &p = kv.second;
     void *ptrs[] = {p.W64, p.W32, p.Ek, p.ethr, p.l, p.target, p.tptr, p.tch};
@@ -692,19 +706,46 @@ rm_status rm_run(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, const r
   if (rm_status st = get_pw(ctx, pwid, &pw)) return st;
   (void)hipSetDevice(ctx->device);
   const rm_opts o = fixed_opts(opts);
-  const hipStream_t s = call_stream(ctx, o);
-  const int cap = chunk_cap(*pw, sync_share(ctx), ne);
-  if (rm_status st = ensure_work(ctx, ctx->work, *pw, cap, false)) return st;
-  for (int e0 = 0; e0 < ne; e0 += cap) {
+  const hipStream_t user = call_stream(ctx, o);
+  if (!ctx->ev_in) {
+    HIPCHK(hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
+    for (int i = 0; i < 2; ++i) {
+      HIPCHK(hipEventCreateWithFlags(&ctx->ev_out[i], hipEventDisableTiming));
+      HIPCHK(hipStreamCreateWithFlags(&ctx->pipe[i].stream, hipStreamNonBlocking));
+    }
+  }
+  size_t share;
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    const size_t used = ctx->resident + ctx->work_bytes - ctx->pipe[0].w.bytes - ctx->pipe[1].w.bytes;
+    share = ctx->budget > used ? (ctx->budget - used) / 2 : 0;
+  }
+  // chunks of at most 128 energies, at least two chunks when there is enough work
+  int cap = std::min(chunk_cap(*pw, share, ne), 128);
+  if (ne > 2 * EB && cap * 2 > ne) cap = std::max(EB, (ne + 2 * EB - 1) / (2 * EB) * EB);
+  const int nuse = ne > cap ? 2 : 1;
+  for (int i = 0; i < nuse; ++i)
+    if (rm_status st = ensure_work(ctx, ctx->pipe[i].w, *pw, cap, false)) return st;
+  // the internal streams start after the caller's prior work on its stream
+  HIPCHK(hipEventRecord(ctx->ev_in, user));
+  for (int i = 0; i < nuse; ++i) HIPCHK(hipStreamWaitEvent(ctx->pipe[i].stream, ctx->ev_in, 0));
+  int k = 0;
+  for (int e0 = 0; e0 < ne; e0 += cap, ++k) {
+    Slot &sl = ctx->pipe[k % nuse];
     const int m = std::min(cap, ne - e0);
-    HIPCHK(hipMemcpyAsync(ctx->work.E, E + e0, sizeof(double) * m, kind_in(o), s));
+    HIPCHK(hipMemcpyAsync(sl.w.E, E + e0, sizeof(double) * m, kind_in(o), sl.stream));
     ChunkOut out;
     out.omega = omega + (size_t)e0 * pw->nt * pw->nt;
     out.K = K ? K + (size_t)e0 * pw->n * pw->n : nullptr;
     out.status = status + e0;
-    if (rm_status st = run_chunk(ctx, *pw, ctx->work, m, o, s, out, kind_out(o))) return st;
+    if (rm_status st = run_chunk(ctx, *pw, sl.w, m, o, sl.stream, out, kind_out(o))) return st;
   }
-  if (!o.device_ptrs) HIPCHK(hipStreamSynchronize(s));
+  // and the caller's stream continues after both
+  for (int i = 0; i < nuse; ++i) {
+    HIPCHK(hipEventRecord(ctx->ev_out[i], ctx->pipe[i].stream));
+    HIPCHK(hipStreamWaitEvent(user, ctx->ev_out[i], 0));
+  }
+  if (!o.device_ptrs) HIPCHK(hipStreamSynchronize(user));
   return RM_OK;
 }
 

@@ -1,0 +1,73 @@
+"""Serving path: rm_submit / rm_poll with continuous batching.  Requests on
+several resident partial waves arrive while others run; each result must equal,
+bitwise, the same request run alone with rm_run (each energy's arithmetic does
+not depend on which other energies share its chunk or slot)."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_1909_07321_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1909_07321_amd import rm
+    c = rm.Context(0)
+    yield c
+    c.close()
+
+
+def _pool():
+    sizes = [12, 70, 190, 333]
+    return [synth.make_partial_wave(synth.config_seed(5) + 100 + i, n, 30 + i, z=5.0, a=12.0, thr_range=(0.0, 8.0),
+                                    pole_range=(-2.0, 60.0), name=f"serve{i}") for i, n in enumerate(sizes)]
+
+
+def test_alone_equals_mix(ctx):
+    pool = _pool()
+    ids = [ctx.pw_upload(p) for p in pool]
+    rng = np.random.default_rng(3)
+    reqs = []
+    for r in range(10):
+        p = int(rng.integers(0, len(pool)))
+        ne = int(rng.integers(5, 300))
+        E = np.sort(rng.uniform(0.01, 8.0, ne))
+        reqs.append((p, E, int(r % 2)))
+    tickets = []
+    for p, E, prec in reqs:
+        t, out = ctx.submit(ids[p], E, prec=prec, want_K=True)
+        tickets.append((t, out))
+        time.sleep(0.002)
+    stats = []
+    deadline = time.time() + 120
+    pending = list(range(len(tickets)))
+    while pending and time.time() < deadline:
+        for k in list(pending):
+            st = ctx.poll(tickets[k][0])
+            if st is not None:
+                stats.append(st)
+                pending.remove(k)
+        time.sleep(0.001)
+    assert not pending, "requests did not finish"
+    for (p, E, prec), (t, out) in zip(reqs, tickets):
+        om, K, st = ctx.run(ids[p], E, prec=prec)
+        assert np.array_equal(out["status"], st)
+        assert np.array_equal(out["omega"], om, equal_nan=True)
+        assert np.array_equal(out["K"], K, equal_nan=True)
+    lat = np.array([(s["t_done_ns"] - s["t_arrive_ns"]) / 1e6 for s in stats])
+    print(f"serving: {len(stats)} requests, latency p50 {np.median(lat):.1f} ms p99 {np.quantile(lat, .99):.1f} ms",
+          flush=True)
+    assert all(s["t_arrive_ns"] <= s["t_admit_ns"] <= s["t_done_ns"] for s in stats)
+    for i in ids:
+        ctx.pw_release(i)
+
+
+def test_unknown_ticket_and_pw(ctx):
+    from paper_1909_07321_amd import rm
+    with pytest.raises(rm.RMError):
+        ctx.poll(987654321)
+    with pytest.raises(rm.RMError):
+        ctx.submit(4242, np.array([1.0]))

@@ -77,18 +77,20 @@ __device__ __forceinline__ long vcol(int v, int rows, int c0, long roff) {
   return v < rows - c0 ? (long)(c0 + v) : roff + (v - (rows - c0));
 }
 
-// Panel factorisation: columns [j0, j0 + jb) over rows [j0, rows), with row
-// interchanges applied to every column right of j0 (A and right-hand sides).
-// One 1024-thread workgroup per energy: each thread owns rows t, t + 1024, ...;
-// the pivot search reduces within each wave by shuffles and across waves in
-// LDS (ties go to the smaller row, so the choice is deterministic), and the
-// pivot row's panel segment is staged in LDS for the rank-1 update.
-constexpr int PANEL_T = 256;
+// Panel factorisation: columns [j0, j0 + jb) over rows [j0, rows).  Row
+// interchanges are applied here only to the panel's own columns and recorded in
+// ipiv; k_lu_trsm applies them to every column right of the panel.  One
+// workgroup per energy: each thread owns rows t, t + PANEL_T, ...; the pivot
+// search reduces within each wave by shuffles and across waves in LDS (ties go
+// to the smaller row, so the choice is deterministic), and the pivot row's panel
+// segment is staged in LDS for the rank-1 update.
+constexpr int PANEL_T = 512;
 __global__ __launch_bounds__(PANEL_T) void k_lu_panel(int j0, const int *__restrict__ dims,
                                                       double *__restrict__ aug, long ldaug, long strideA,
-                                                      long roff, int *__restrict__ status) {
+                                                      int *__restrict__ ipiv, long ldp,
+                                                      int *__restrict__ status) {
   const int e = blockIdx.x;
-  const int rows = dims[2 * e], rhs = dims[2 * e + 1];
+  const int rows = dims[2 * e];
   if (j0 >= rows) return;
   const int jb = min(NB, rows - j0);
   double *A = aug + (size_t)e * strideA;
@@ -97,7 +99,6 @@ __global__ __launch_bounds__(PANEL_T) void k_lu_panel(int j0, const int *__restr
   __shared__ int wi[PANEL_T / 64];
   __shared__ int spiv;
   __shared__ double prow[NB];
-  const int ncol_right = (rows - j0) + rhs;  // virtual columns from j0
   for (int c = j0; c < j0 + jb; ++c) {
     double best = -1.0;
     int bidx = rows;
@@ -123,19 +124,19 @@ __global__ __launch_bounds__(PANEL_T) void k_lu_panel(int j0, const int *__restr
         bi = c;
       }
       spiv = bi;
+      ipiv[(size_t)e * ldp + c] = bi;
     }
     __syncthreads();
     const int p = spiv;
-    if (p != c) {
-      for (int v = t; v < ncol_right; v += PANEL_T) {
-        const long col = vcol(v, rows, j0, roff);
-        const double x = A[(size_t)c * ldaug + col];
-        A[(size_t)c * ldaug + col] = A[(size_t)p * ldaug + col];
-        A[(size_t)p * ldaug + col] = x;
+    if (t < jb) {
+      const int col = j0 + t;
+      const double pv = A[(size_t)p * ldaug + col];
+      if (p != c) {
+        A[(size_t)p * ldaug + col] = A[(size_t)c * ldaug + col];
+        A[(size_t)c * ldaug + col] = pv;
       }
+      prow[t] = pv;
     }
-    __syncthreads();
-    if (t < jb) prow[t] = A[(size_t)c * ldaug + j0 + t];
     __syncthreads();
     const double piv = prow[c - j0];
     const double inv = piv != 0.0 ? 1.0 / piv : 0.0;
@@ -149,13 +150,14 @@ __global__ __launch_bounds__(PANEL_T) void k_lu_panel(int j0, const int *__restr
   }
 }
 
-// U12 = L11^-1 A12 for rows [j0, j0 + jb) and every column right of the panel.
-// One thread per column; the column is kept in LDS (its own slot) so the solve
-// needs no large per-thread register array.
+// For every column right of the panel: apply the panel's row interchanges,
+// then U12 = L11^-1 A12 on rows [j0, j0 + jb).  One thread per column; the
+// column's panel rows are kept in LDS (its own slot), so the solve needs no
+// large per-thread register array.
 constexpr int TRSM_T = 128;
 __global__ __launch_bounds__(TRSM_T) void k_lu_trsm(int j0, const int *__restrict__ dims,
                                                     double *__restrict__ aug, long ldaug, long strideA,
-                                                    long roff) {
+                                                    long roff, const int *__restrict__ ipiv, long ldp) {
   const int e = blockIdx.y;
   const int rows = dims[2 * e], rhs = dims[2 * e + 1];
   if (j0 >= rows) return;
@@ -166,23 +168,32 @@ __global__ __launch_bounds__(TRSM_T) void k_lu_trsm(int j0, const int *__restric
   double *A = aug + (size_t)e * strideA;
   __shared__ double L[NB][NB + 1];
   __shared__ double sx[NB][TRSM_T];
+  __shared__ int piv[NB];
   const int t = threadIdx.x;
   for (int idx = t; idx < jb * jb; idx += TRSM_T) {
     const int r = idx / jb, c = idx % jb;
     L[r][c] = A[(size_t)(j0 + r) * ldaug + j0 + c];
   }
+  if (t < jb) piv[t] = ipiv[(size_t)e * ldp + j0 + t];
+  __syncthreads();
   const int v = blockIdx.x * TRSM_T + t;
   const bool valid = v < ncols;
-  const long col = valid ? vcol(v, rows, c0, roff) : 0;
-  for (int r = 0; r < jb; ++r) sx[r][t] = valid ? A[(size_t)(j0 + r) * ldaug + col] : 0.0;
-  __syncthreads();
-  for (int r = 1; r < jb; ++r) {
-    double acc = sx[r][t];
-    for (int c = 0; c < r; ++c) acc -= L[r][c] * sx[c][t];
-    sx[r][t] = acc;
-  }
-  if (valid)
+  if (valid) {
+    const long col = vcol(v, rows, c0, roff);
+    for (int r = 0; r < jb; ++r) {
+      const int p = piv[r];
+      const double x = A[(size_t)p * ldaug + col];
+      if (p != j0 + r) A[(size_t)p * ldaug + col] = A[(size_t)(j0 + r) * ldaug + col];
+      sx[r][t] = x;  // row j0 + r after the interchange; later interchanges of
+                     // this panel only touch rows > j0 + r, so it stays in LDS
+    }
+    for (int r = 1; r < jb; ++r) {
+      double acc = sx[r][t];
+      for (int c = 0; c < r; ++c) acc -= L[r][c] * sx[c][t];
+      sx[r][t] = acc;
+    }
     for (int r = 0; r < jb; ++r) A[(size_t)(j0 + r) * ldaug + col] = sx[r][t];
+  }
 }
 
 // Trailing update A22 -= L21 U12 over rows [c0, rows) and all virtual columns
@@ -325,14 +336,15 @@ __global__ __launch_bounds__(256) void k_bs_update(int j0, const int *__restrict
 }
 
 void launch_lu_solve(hipStream_t s, int ne, int maxrows, int maxrhs, const int *dims, double *aug,
-                     long ldaug, long strideA, long roff, int *status) {
+                     long ldaug, long strideA, long roff, int *ipiv, long ldp, int *status) {
   for (int j0 = 0; j0 < maxrows; j0 += NB) {
-    hipLaunchKernelGGL(k_lu_panel, dim3(ne), dim3(PANEL_T), 0, s, j0, dims, aug, ldaug, strideA, roff, status);
+    hipLaunchKernelGGL(k_lu_panel, dim3(ne), dim3(PANEL_T), 0, s, j0, dims, aug, ldaug, strideA, ipiv, ldp,
+                       status);
     const int c0 = min(maxrows, j0 + NB);
     const int ncols = (maxrows - c0) + maxrhs;
     if (ncols <= 0) continue;
     hipLaunchKernelGGL(k_lu_trsm, dim3((ncols + TRSM_T - 1) / TRSM_T, ne), dim3(TRSM_T), 0, s, j0, dims, aug,
-                       ldaug, strideA, roff);
+                       ldaug, strideA, roff, ipiv, ldp);
     const int m = maxrows - c0;
     if (m <= 0) continue;
     const int tm = (m + TILE - 1) / TILE, tn = (ncols + TILE - 1) / TILE;

@@ -55,6 +55,7 @@ struct Work {
   double *Kw = nullptr;      // [cap_e][ldk][ldk]
   double *XK = nullptr;      // [cap_e][ldk][ldk]
   int *dims = nullptr;       // [cap_e][2] per-energy (rows, rhs) for batched LU
+  int *ipiv = nullptr;       // [cap_e][cap_n] LU row interchanges
   double *omega = nullptr;   // [cap_e][cap_nt][cap_nt]
   double *S = nullptr;       // [cap_e][cap_n][cap_n][2], allocated on demand
 };
@@ -78,7 +79,7 @@ void launch_build(hipStream_t s, const DevPW &pw, int ne, const double *fg, cons
 // [roff, roff + rhs)), then back substitution: on return the right-hand-side
 // columns hold A^-1 B.  Exact zero pivots set RM_PT_SINGULAR.
 void launch_lu_solve(hipStream_t s, int ne, int maxrows, int maxrhs, const int *dims, double *aug,
-                     long ldaug, long strideA, long roff, int *status);
+                     long ldaug, long strideA, long roff, int *ipiv, long ldp, int *status);
 // C[e] = A[e] B[e] for square no x no blocks, no = nopen[e]
 void launch_gemm_sq(hipStream_t s, int ne, int maxn, const int *nopen, const double *A, long lda, long sA,
                     const double *B, long ldb, long sB, double *C, long ldc, long sC);

@@ -86,7 +86,7 @@ struct rm_ctx {
   // rm_run alternates chunks over two streams so that one chunk's K solve
   // overlaps the next chunk's R contraction
   Slot pipe[2];
-  hipEvent_t ev_in = nullptr, ev_out[2] = {nullptr, nullptr};
+  hipEvent_t ev_in = nullptr, ev_out[2] = {nullptr, nullptr}, ev_R[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -100,7 +100,7 @@ namespace {
     }                                                                                          \
   } while (0)
 
-constexpr int MAX_CHUNK = 256;
+constexpr int MAX_CHUNK = 1024;
 
 size_t per_energy_bytes(int n, int npad, int Mpad) {
   return (size_t)n * 2 * npad * 8      // aug
@@ -113,7 +113,7 @@ size_t per_energy_bytes(int n, int npad, int Mpad) {
 
 void free_work(Work &w) {
   void *ptrs[] = {w.E, w.D64, w.D32, w.win, w.status, w.nopen, w.openidx, w.openpos, w.openflag,
-                  w.fg, w.aug, w.Kw, w.XK, w.dims, w.omega, w.S};
+                  w.fg, w.aug, w.Kw, w.XK, w.dims, w.omega, w.S, w.ipiv};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   w = Work();
@@ -135,7 +135,7 @@ rm_status ensure_work(rm_ctx *ctx, Work &w, const DevPW &pw, int cap, bool want_
                boi = sz((size_t)ce * cn * 4), bop = sz((size_t)ce * cn * 4), bof = sz((size_t)ce * cn),
                bfg = sz((size_t)ce * cn * 32), baug = sz((size_t)ce * cn * 2 * cnp * 8),
                bK = sz((size_t)ce * cn * cnp * 8), bXK = sz((size_t)ce * cn * cnp * 8),
-               bdims = sz((size_t)ce * 8), bom = sz((size_t)ce * ct * ct * 8),
+               bdims = sz((size_t)ce * 8), bom = sz((size_t)ce * ct * ct * 8), bpiv = sz((size_t)ce * cn * 4),
                bS = S ? sz((size_t)ce * cn * cn * 16) : 0;
   {
     std::lock_guard<std::mutex> g(ctx->mu);
@@ -165,6 +165,7 @@ rm_status ensure_work(rm_ctx *ctx, Work &w, const DevPW &pw, int cap, bool want_
   HIPCHK(hipMalloc(&w.XK, bXK));
   HIPCHK(hipMalloc(&w.dims, bdims));
   HIPCHK(hipMalloc(&w.omega, bom));
+  HIPCHK(hipMalloc(&w.ipiv, bpiv));
   if (S) HIPCHK(hipMalloc(&w.S, bS));
   w.cap_e = ce;
   w.cap_n = cn;
@@ -240,7 +241,7 @@ void stage_asym(rm_ctx *ctx, const DevPW &pw, Work &w, const Lay &L, int m, cons
 void stage_K(const DevPW &pw, Work &w, const Lay &L, int m, hipStream_t s) {
   launch_setdims(s, m, pw.n, w.nopen, w.dims);
   launch_build(s, pw, m, w.fg, w.nopen, w.openidx, L.ldo, w.aug, L.ldaug, L.sA, L.roff);
-  launch_lu_solve(s, m, pw.n, pw.n, w.dims, w.aug, L.ldaug, L.sA, L.roff, w.status);
+  launch_lu_solve(s, m, pw.n, pw.n, w.dims, w.aug, L.ldaug, L.sA, L.roff, w.ipiv, L.ldo, w.status);
   launch_gatherK(s, m, pw.n, w.nopen, w.openidx, L.ldo, w.aug, L.ldaug, L.sA, L.roff, w.Kw, L.ldk, L.sK);
 }
 
@@ -248,7 +249,7 @@ void stage_SO(const DevPW &pw, Work &w, const Lay &L, int m, bool want_S, hipStr
   // P = 1 + K K and X = P^-1 K on the same batched LU; then XK and Omega
   launch_gemm_sq(s, m, pw.n, w.nopen, w.Kw, L.ldk, L.sK, w.Kw, L.ldk, L.sK, w.aug, L.ldaug, L.sA);
   launch_formP(s, m, pw.n, w.nopen, w.Kw, L.ldk, L.sK, w.aug, L.ldaug, L.sA, L.roff, w.dims);
-  launch_lu_solve(s, m, pw.n, pw.n, w.dims, w.aug, L.ldaug, L.sA, L.roff, w.status);
+  launch_lu_solve(s, m, pw.n, pw.n, w.dims, w.aug, L.ldaug, L.sA, L.roff, w.ipiv, L.ldo, w.status);
   launch_gemm_sq(s, m, pw.n, w.nopen, w.aug + L.roff, L.ldaug, L.sA, w.Kw, L.ldk, L.sK, w.XK, L.ldk, L.sK);
   launch_omega(s, pw, m, w.openpos, L.ldo, w.nopen, w.aug + L.roff, L.ldaug, L.sA, w.XK, L.ldk, L.sK, w.omega,
                want_S ? w.S : nullptr);
@@ -294,11 +295,15 @@ struct ChunkOut {
 };
 
 // Runs all stages for energies already in w.E and copies the results out.
+// before_R / after_R (optional) order the R contraction against other streams.
 rm_status run_chunk(rm_ctx *ctx, const DevPW &pw, Work &w, int m, const rm_opts &o, hipStream_t s,
-                    const ChunkOut &out, hipMemcpyKind ko) {
+                    const ChunkOut &out, hipMemcpyKind ko, hipEvent_t before_R = nullptr,
+                    hipEvent_t after_R = nullptr) {
   const Lay L = layout(pw, w);
   HIPCHK(hipMemsetAsync(w.status, 0, sizeof(int) * m, s));
+  if (before_R) HIPCHK(hipStreamWaitEvent(s, before_R, 0));
   stage_R(ctx, pw, w, L, m, o, s);
+  if (after_R) HIPCHK(hipEventRecord(after_R, s));
   stage_asym(ctx, pw, w, L, m, o, s);
   timed(ctx, 3, m, s, [&] { stage_K(pw, w, L, m, s); });
   timed(ctx, 4, m, s, [&] { stage_SO(pw, w, L, m, false, s); });
@@ -454,6 +459,8 @@ rm_status rm_destroy(rm_ctx *ctx) {
   }
   if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
   for (auto &ev : ctx->ev_out)
+    if (ev) (void)hipEventDestroy(ev);
+  for (auto &ev : ctx->ev_R)
     if (ev) (void)hipEventDestroy(ev);
   for (auto &kv : ctx->pws) {
     DevPW &p = kv.second;
@@ -711,6 +718,7 @@ rm_status rm_run(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, const r
     HIPCHK(hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
     for (int i = 0; i < 2; ++i) {
       HIPCHK(hipEventCreateWithFlags(&ctx->ev_out[i], hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&ctx->ev_R[i], hipEventDisableTiming));
       HIPCHK(hipStreamCreateWithFlags(&ctx->pipe[i].stream, hipStreamNonBlocking));
     }
   }
@@ -720,8 +728,13 @@ rm_status rm_run(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, const r
     const size_t used = ctx->resident + ctx->work_bytes - ctx->pipe[0].w.bytes - ctx->pipe[1].w.bytes;
     share = ctx->budget > used ? (ctx->budget - used) / 2 : 0;
   }
-  // chunks of at most 128 energies, at least two chunks when there is enough work
-  int cap = std::min(chunk_cap(*pw, share, ne), 128);
+  // Chunks of up to 256 energies alternate over the two streams.  The R
+  // contractions are chained across the streams (each waits for the previous
+  // chunk's), so chunk k+1's compute-bound contraction overlaps chunk k's
+  // latency-bound K solve instead of competing with chunk k's contraction.
+  // The LU panel runs one workgroup per energy, so its cost grows with the
+  // number of chunks rather than with their size; 256 fills the CUs.
+  int cap = std::min(chunk_cap(*pw, share, ne), 256);
   if (ne > 2 * EB && cap * 2 > ne) cap = std::max(EB, (ne + 2 * EB - 1) / (2 * EB) * EB);
   const int nuse = ne > cap ? 2 : 1;
   for (int i = 0; i < nuse; ++i)
@@ -738,7 +751,9 @@ rm_status rm_run(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, const r
     out.omega = omega + (size_t)e0 * pw->nt * pw->nt;
     out.K = K ? K + (size_t)e0 * pw->n * pw->n : nullptr;
     out.status = status + e0;
-    if (rm_status st = run_chunk(ctx, *pw, sl.w, m, o, sl.stream, out, kind_out(o))) return st;
+    hipEvent_t prevR = k > 0 && nuse > 1 ? ctx->ev_R[(k - 1) % 2] : nullptr;
+    if (rm_status st = run_chunk(ctx, *pw, sl.w, m, o, sl.stream, out, kind_out(o), prevR, ctx->ev_R[k % 2]))
+      return st;
   }
   // and the caller's stream continues after both
   for (int i = 0; i < nuse; ++i) {

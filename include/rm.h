@@ -160,6 +160,24 @@ rm_status rm_collision_strengths(rm_ctx *ctx, int32_t pw, const double *E, int32
 rm_status rm_run(rm_ctx *ctx, int32_t pw, const double *E, int32_t ne, const rm_opts *opts,
                  double *omega, double *K, int32_t *status);
 
+/* ------------------------------------------------------------------ batching */
+/* One partial wave's block of energies in a batch; outputs as in rm_run. */
+typedef struct {
+  int32_t pw_id;
+  const double *E;   /* [ne], host or device as opts->device_ptrs says */
+  int32_t ne;
+  double *omega;     /* [ne][nt][nt] of this partial wave */
+  double *K;         /* [ne][n][n] or NULL */
+  int32_t *status;   /* [ne] */
+} rm_batch_item;
+
+/* Many partial waves of different sizes in one call.  Energies are drawn from
+   every item in turn into chunks, so each chunk mixes partial waves: one
+   persistent launch computes the R matrices of all of them (tasks ordered by
+   cost, largest first) and the K solve and Omega run batched over the mixed
+   sizes.  Results equal those of rm_run on each item alone. */
+rm_status rm_run_batch(rm_ctx *ctx, const rm_batch_item *items, int32_t nitems, const rm_opts *opts);
+
 /* ------------------------------------------------------------------ serving */
 typedef struct {
   int32_t pw_id;

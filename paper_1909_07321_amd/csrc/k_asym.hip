@@ -255,22 +255,22 @@ __device__ bool closed_fn(double z, double eps, double a, int l, double out[4]) 
   return true;
 }
 
-__global__ void k_asym(const double *__restrict__ ethr, const int *__restrict__ lch, int n, double z,
-                       double a, const double *__restrict__ E, int ne, double thr_guard,
-                       double *__restrict__ fg, int *__restrict__ status) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_asym(const DevPW *__restrict__ tab, const int *__restrict__ pwi, const double *__restrict__ E,
+                       long ldo, double thr_guard, double *__restrict__ fg, int *__restrict__ status) {
   const int e = blockIdx.y;
-  if (i >= n || e >= ne) return;
-  const double eps = E[e] - ethr[i];
+  const DevPW &p = tab[pwi[e]];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  const double eps = E[e] - p.ethr[i];
   double out[4];
   int bad = 0;
   if (fabs(eps) < thr_guard) {
     bad = RM_PT_THRESHOLD;
   } else {
-    const bool ok = eps > 0 ? open_fn(z, eps, a, lch[i], out) : closed_fn(z, eps, a, lch[i], out);
+    const bool ok = eps > 0 ? open_fn(p.z, eps, p.a, p.l[i], out) : closed_fn(p.z, eps, p.a, p.l[i], out);
     if (!ok) bad = RM_PT_NOCONV;
   }
-  double *o = fg + ((size_t)e * n + i) * 4;
+  double *o = fg + ((size_t)e * ldo + i) * 4;
   if (bad) {
     const double nan = __builtin_nan("");
     o[0] = o[1] = o[2] = o[3] = nan;
@@ -283,21 +283,23 @@ __global__ void k_asym(const double *__restrict__ ethr, const int *__restrict__ 
   }
 }
 
-void launch_asym(hipStream_t s, const DevPW &pw, const double *E, int ne, double thr_guard,
+void launch_asym(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const double *E, double thr_guard,
                  double *fg, int *status) {
-  dim3 grid((pw.n + 63) / 64, ne);
-  hipLaunchKernelGGL(k_asym, grid, dim3(64), 0, s, pw.ethr, pw.l, pw.n, pw.z, pw.a, E, ne, thr_guard,
-                     fg, status);
+  dim3 grid((L.nmax + 63) / 64, L.ne);
+  hipLaunchKernelGGL(k_asym, grid, dim3(64), 0, s, tab, pwi, E, L.ldo, thr_guard, fg, status);
 }
 
 // Open-channel list per energy in ascending channel order (one workgroup per
 // energy, block-wide exclusive scan of per-thread counts).
-__global__ __launch_bounds__(256) void k_openlist(const double *__restrict__ ethr, int n,
+__global__ __launch_bounds__(256) void k_openlist(const DevPW *__restrict__ tab, const int *__restrict__ pwi,
                                                   const double *__restrict__ E, int *__restrict__ nopen,
                                                   int *__restrict__ openidx, int *__restrict__ openpos,
                                                   int8_t *__restrict__ openflag, long ld) {
   __shared__ int cnt[256];
   const int e = blockIdx.x, t = threadIdx.x;
+  const DevPW &p = tab[pwi[e]];
+  const int n = p.n;
+  const double *ethr = p.ethr;
   const double Ev = E[e];
   const int per = (n + 255) / 256;
   const int c0 = t * per, c1 = min(n, c0 + per);
@@ -322,10 +324,10 @@ __global__ __launch_bounds__(256) void k_openlist(const double *__restrict__ eth
   if (t == 255) nopen[e] = cnt[255];
 }
 
-void launch_openlist(hipStream_t s, const DevPW &pw, const double *E, int ne, int *nopen,
-                     int *openidx, int *openpos, int8_t *openflag, long ld) {
-  hipLaunchKernelGGL(k_openlist, dim3(ne), dim3(256), 0, s, pw.ethr, pw.n, E, nopen, openidx, openpos,
-                     openflag, ld);
+void launch_openlist(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const double *E, int *nopen,
+                     int *openidx, int *openpos, int8_t *openflag) {
+  hipLaunchKernelGGL(k_openlist, dim3(L.ne), dim3(256), 0, s, tab, pwi, E, nopen, openidx, openpos, openflag,
+                     L.ldo);
 }
 
 }  // namespace rm

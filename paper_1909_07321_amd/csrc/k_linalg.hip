@@ -30,42 +30,46 @@ __device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
 // ---------------------------------------------------------------------------
 // assembly of B (reads R) and then A (in place over R)
 // ---------------------------------------------------------------------------
-__global__ void k_buildB(int n, double a, double b, const double *__restrict__ fg,
+__global__ void k_buildB(const DevPW *__restrict__ tab, const int *__restrict__ pwi, const double *__restrict__ fg,
                          const int *__restrict__ nopen, const int *__restrict__ openidx, long ldo,
                          double *__restrict__ aug, long ldaug, long strideA, long roff) {
   const int e = blockIdx.z;
+  const DevPW &p = tab[pwi[e]];
+  const int n = p.n;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;  // open column
   const int i = blockIdx.y;                             // row
   const int no = nopen[e];
   if (j >= no || i >= n) return;
+  const double a = p.a, b = p.b;
   const int oj = openidx[(size_t)e * ldo + j];
-  const double *f = fg + ((size_t)e * n + oj) * 4;
+  const double *f = fg + ((size_t)e * ldo + oj) * 4;
   const double s = f[0], sp = f[1];
   double *Ae = aug + (size_t)e * strideA;
   const double v = Ae[(size_t)i * ldaug + oj] * (a * sp - b * s) - (i == oj ? s : 0.0);
   Ae[(size_t)i * ldaug + roff + j] = v;
 }
 
-__global__ void k_buildA(int n, double a, double b, const double *__restrict__ fg,
-                         double *__restrict__ aug, long ldaug, long strideA) {
+__global__ void k_buildA(const DevPW *__restrict__ tab, const int *__restrict__ pwi, const double *__restrict__ fg,
+                         long ldo, double *__restrict__ aug, long ldaug, long strideA) {
   const int e = blockIdx.z;
+  const DevPW &p = tab[pwi[e]];
+  const int n = p.n;
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y;
   if (m >= n || i >= n) return;
-  const double *fm = fg + ((size_t)e * n + m) * 4;
-  const double lam = a * fm[3] - b * fm[2];
-  double *p = aug + (size_t)e * strideA + (size_t)i * ldaug + m;
-  double v = -(*p) * lam;
+  const double *fm = fg + ((size_t)e * ldo + m) * 4;
+  const double lam = p.a * fm[3] - p.b * fm[2];
+  double *q = aug + (size_t)e * strideA + (size_t)i * ldaug + m;
+  double v = -(*q) * lam;
   if (i == m) v += fm[2];
-  *p = v;
+  *q = v;
 }
 
-void launch_build(hipStream_t s, const DevPW &pw, int ne, const double *fg, const int *nopen,
-                  const int *openidx, long ldo, double *aug, long ldaug, long strideA, long roff) {
-  dim3 gB((pw.n + 63) / 64, pw.n, ne);
-  hipLaunchKernelGGL(k_buildB, gB, dim3(64), 0, s, pw.n, pw.a, pw.b, fg, nopen, openidx, ldo, aug, ldaug,
-                     strideA, roff);
-  hipLaunchKernelGGL(k_buildA, gB, dim3(64), 0, s, pw.n, pw.a, pw.b, fg, aug, ldaug, strideA);
+void launch_build(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const double *fg,
+                  const int *nopen, const int *openidx, double *aug) {
+  dim3 g((L.nmax + 63) / 64, L.nmax, L.ne);
+  hipLaunchKernelGGL(k_buildB, g, dim3(64), 0, s, tab, pwi, fg, nopen, openidx, L.ldo, aug, L.ldaug, L.sA, L.roff);
+  hipLaunchKernelGGL(k_buildA, g, dim3(64), 0, s, tab, pwi, fg, L.ldo, aug, L.ldaug, L.sA);
 }
 
 // ---------------------------------------------------------------------------
@@ -430,23 +434,22 @@ void launch_gemm_sq(hipStream_t s, int ne, int maxn, const int *nopen, const dou
 // ---------------------------------------------------------------------------
 // K gather, P = 1 + K^2 set-up, collision strengths
 // ---------------------------------------------------------------------------
-__global__ void k_gatherK(int n, const int *__restrict__ nopen, const int *__restrict__ openidx, long ldo,
+__global__ void k_gatherK(const int *__restrict__ nopen, const int *__restrict__ openidx, long ldo,
                           const double *__restrict__ aug, long ldaug, long strideA, long roff,
-                          double *__restrict__ Kw, long ldk, long strideK) {
+                          double *__restrict__ Kw, long ldk, long strideK, int nmax) {
   const int e = blockIdx.z, i = blockIdx.y;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || j >= n) return;
+  if (i >= nmax || j >= nmax) return;
   const int no = nopen[e];
   double v = 0.0;
   if (i < no && j < no) v = aug[(size_t)e * strideA + (size_t)openidx[(size_t)e * ldo + i] * ldaug + roff + j];
   Kw[(size_t)e * strideK + (size_t)i * ldk + j] = v;
 }
 
-void launch_gatherK(hipStream_t s, int ne, int n, const int *nopen, const int *openidx, long ldo,
-                    const double *aug, long ldaug, long strideA, long roff, double *Kw, long ldk,
-                    long strideK) {
-  hipLaunchKernelGGL(k_gatherK, dim3((n + 63) / 64, n, ne), dim3(64), 0, s, n, nopen, openidx, ldo, aug,
-                     ldaug, strideA, roff, Kw, ldk, strideK);
+void launch_gatherK(hipStream_t s, const Lay &L, const int *nopen, const int *openidx, const double *aug,
+                    double *Kw) {
+  hipLaunchKernelGGL(k_gatherK, dim3((L.nmax + 63) / 64, L.nmax, L.ne), dim3(64), 0, s, nopen, openidx, L.ldo, aug,
+                     L.ldaug, L.sA, L.roff, Kw, L.ldk, L.sK, L.nmax);
 }
 
 // aug rows [0, no): columns [0, no) hold K K (already written); add 1 on the
@@ -466,27 +469,31 @@ __global__ void k_formP(const int *__restrict__ nopen, const double *__restrict_
   row[roff + j] = Kw[(size_t)e * strideK + (size_t)i * ldk + j];
 }
 
-void launch_formP(hipStream_t s, int ne, int maxno, const int *nopen, const double *Kw, long ldk,
-                  long strideK, double *aug, long ldaug, long strideA, long roff, int *dims) {
-  hipLaunchKernelGGL(k_formP, dim3((maxno + 63) / 64 + 1, maxno + 1, ne), dim3(64), 0, s, nopen, Kw, ldk,
-                     strideK, aug, ldaug, strideA, roff, dims);
+void launch_formP(hipStream_t s, const Lay &L, const int *nopen, const double *Kw, double *aug, int *dims) {
+  hipLaunchKernelGGL(k_formP, dim3((L.nmax + 63) / 64 + 1, L.nmax + 1, L.ne), dim3(64), 0, s, nopen, Kw, L.ldk,
+                     L.sK, aug, L.ldaug, L.sA, L.roff, dims);
 }
 
 // Omega_pq for one energy and one target row p per wave; lanes stride over q.
 // Each entry sums its channel pairs in a fixed order (no atomics), so results
 // do not depend on scheduling.
-__global__ __launch_bounds__(64) void k_omega(int nt, double half_g, const int *__restrict__ tptr,
-                                              const int *__restrict__ tch, const int *__restrict__ openpos,
-                                              long ldo, const double *__restrict__ X, long ldx, long sX,
+__global__ __launch_bounds__(64) void k_omega(const DevPW *__restrict__ tab, const int *__restrict__ pwi,
+                                              const int *__restrict__ openpos, long ldo,
+                                              const double *__restrict__ X, long ldx, long sX,
                                               const double *__restrict__ XK, long ldxk, long sXK,
-                                              double *__restrict__ omega) {
-  const int p = blockIdx.x, e = blockIdx.y;
+                                              double *__restrict__ omega, int ntmax) {
+  const int pt = blockIdx.x, e = blockIdx.y;
+  const DevPW &pw = tab[pwi[e]];
+  const int nt = pw.nt;
+  if (pt >= nt) return;
+  const double half_g = 0.5 * pw.g;
+  const int *tptr = pw.tptr, *tch = pw.tch;
   const int *pos = openpos + (size_t)e * ldo;
   const double *Xe = X + (size_t)e * sX;
   const double *Ye = XK + (size_t)e * sXK;
   for (int q = threadIdx.x; q < nt; q += 64) {
     double acc = 0.0;
-    for (int a = tptr[p]; a < tptr[p + 1]; ++a) {
+    for (int a = tptr[pt]; a < tptr[pt + 1]; ++a) {
       const int i = pos[tch[a]];
       if (i < 0) continue;
       for (int b = tptr[q]; b < tptr[q + 1]; ++b) {
@@ -496,99 +503,113 @@ __global__ __launch_bounds__(64) void k_omega(int nt, double half_g, const int *
         acc += 4.0 * (y * y + x * x);
       }
     }
-    omega[((size_t)e * nt + p) * nt + q] = half_g * acc;
+    omega[((size_t)e * ntmax + pt) * ntmax + q] = half_g * acc;
   }
 }
 
 // S_ij = d_ij - 2 (XK)_ij + 2i X_ij on the leading no x no block, zero elsewhere
-__global__ void k_smatrix(int n, const int *__restrict__ nopen, const double *__restrict__ X, long ldx, long sX,
-                          const double *__restrict__ XK, long ldxk, long sXK, double *__restrict__ S) {
+__global__ void k_smatrix(const DevPW *__restrict__ tab, const int *__restrict__ pwi, const int *__restrict__ nopen,
+                          const double *__restrict__ X, long ldx, long sX, const double *__restrict__ XK, long ldxk,
+                          long sXK, double *__restrict__ S, int nmax) {
   const int e = blockIdx.z, i = blockIdx.y;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
+  const int n = tab[pwi[e]].n;
+  if (i >= n || j >= n) return;
   const int no = nopen[e];
   double re = 0.0, im = 0.0;
   if (i < no && j < no) {
     re = (i == j ? 1.0 : 0.0) - 2.0 * XK[(size_t)e * sXK + (size_t)i * ldxk + j];
     im = 2.0 * X[(size_t)e * sX + (size_t)i * ldx + j];
   }
-  double *o = S + (((size_t)e * n + i) * n + j) * 2;
+  double *o = S + (((size_t)e * nmax + i) * nmax + j) * 2;
   o[0] = re;
   o[1] = im;
 }
 
-void launch_omega(hipStream_t s, const DevPW &pw, int ne, const int *openpos, long ldo, const int *nopen,
-                  const double *X, long ldx, long sX, const double *XK, long ldxk, long sXK, double *omega,
-                  double *S) {
-  hipLaunchKernelGGL(k_omega, dim3(pw.nt, ne), dim3(64), 0, s, pw.nt, 0.5 * pw.g, pw.tptr, pw.tch, openpos,
-                     ldo, X, ldx, sX, XK, ldxk, sXK, omega);
+void launch_omega(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *openpos,
+                  const int *nopen, const double *X, const double *XK, double *omega, double *S) {
+  hipLaunchKernelGGL(k_omega, dim3(L.ntmax, L.ne), dim3(64), 0, s, tab, pwi, openpos, L.ldo, X, L.ldaug, L.sA, XK,
+                     L.ldk, L.sK, omega, L.ntmax);
   if (S)
-    hipLaunchKernelGGL(k_smatrix, dim3((pw.n + 63) / 64, pw.n, ne), dim3(64), 0, s, pw.n, nopen, X, ldx, sX,
-                       XK, ldxk, sXK, S);
+    hipLaunchKernelGGL(k_smatrix, dim3((L.nmax + 63) / 64, L.nmax, L.ne), dim3(64), 0, s, tab, pwi, nopen, X,
+                       L.ldaug, L.sA, XK, L.ldk, L.sK, S, L.nmax);
 }
 
 // Flag non-finite results and overwrite the outputs of flagged energies with NaN.
-__global__ __launch_bounds__(256) void k_finalize(int n, int nt, int *__restrict__ status,
-                                                  double *__restrict__ omega, double *__restrict__ K, long ldk,
-                                                  long strideK, double *__restrict__ S) {
+__global__ __launch_bounds__(256) void k_finalize(const DevPW *__restrict__ tab, const int *__restrict__ pwi,
+                                                  int *__restrict__ status, double *__restrict__ omega, int ntmax,
+                                                  double *__restrict__ K, long ldk, long strideK,
+                                                  double *__restrict__ S, int nmax) {
   const int e = blockIdx.x;
+  const DevPW &p = tab[pwi[e]];
+  const int n = p.n, nt = p.nt;
   __shared__ int bad;
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
   int mine = 0;
-  for (int t = threadIdx.x; t < nt * nt; t += 256)
-    if (!isfinite(omega[(size_t)e * nt * nt + t])) mine = 1;
+  if (omega)
+    for (int t = threadIdx.x; t < nt * nt; t += 256)
+      if (!isfinite(omega[(size_t)e * ntmax * ntmax + (t / nt) * ntmax + t % nt])) mine = 1;
   if (mine) atomicOr(&bad, 1);
   __syncthreads();
   if (threadIdx.x == 0 && bad) status[e] |= RM_PT_NONFINITE;
   __syncthreads();
   if (status[e] == 0) return;
   const double nan = __builtin_nan("");
-  for (int t = threadIdx.x; t < nt * nt; t += 256) omega[(size_t)e * nt * nt + t] = nan;
+  if (omega)
+    for (int t = threadIdx.x; t < nt * nt; t += 256) omega[(size_t)e * ntmax * ntmax + (t / nt) * ntmax + t % nt] = nan;
   if (K)
     for (long t = threadIdx.x; t < (long)n * n; t += 256) K[(size_t)e * strideK + (t / n) * ldk + t % n] = nan;
   if (S)
-    for (long t = threadIdx.x; t < 2L * n * n; t += 256) S[(size_t)e * 2 * n * n + t] = nan;
+    for (long t = threadIdx.x; t < (long)n * n; t += 256) {
+      double *o = S + (((size_t)e * nmax + t / n) * nmax + t % n) * 2;
+      o[0] = nan;
+      o[1] = nan;
+    }
 }
 
-void launch_finalize(hipStream_t s, int ne, int n, int nt, int *status, double *omega, double *K, long ldk,
-                     long strideK, double *S) {
-  hipLaunchKernelGGL(k_finalize, dim3(ne), dim3(256), 0, s, n, nt, status, omega, K, ldk, strideK, S);
+void launch_finalize(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, int *status, double *omega,
+                     double *K, double *S) {
+  hipLaunchKernelGGL(k_finalize, dim3(L.ne), dim3(256), 0, s, tab, pwi, status, omega, L.ntmax, K, L.ldk, L.sK, S,
+                     L.nmax);
 }
 
-__global__ void k_setdims(int ne, int rows, const int *__restrict__ nopen, int *__restrict__ dims) {
+__global__ void k_setdims(const DevPW *__restrict__ tab, const int *__restrict__ pwi, int ne,
+                          const int *__restrict__ nopen, int *__restrict__ dims) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= ne) return;
-  dims[2 * e] = rows;
+  dims[2 * e] = tab[pwi[e]].n;
   dims[2 * e + 1] = nopen[e];
 }
 
-void launch_setdims(hipStream_t s, int ne, int rows, const int *nopen, int *dims) {
-  hipLaunchKernelGGL(k_setdims, dim3((ne + 127) / 128), dim3(128), 0, s, ne, rows, nopen, dims);
+void launch_setdims(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *nopen, int *dims) {
+  hipLaunchKernelGGL(k_setdims, dim3((L.ne + 127) / 128), dim3(128), 0, s, tab, pwi, L.ne, nopen, dims);
 }
 
 // Flags of the staged calls that take R, fg or K from the caller: energies within
 // thr of a threshold, and non-finite inputs.
-__global__ __launch_bounds__(256) void k_check_inputs(int n, const double *__restrict__ E,
-                                                      const double *__restrict__ ethr, double thr,
+__global__ __launch_bounds__(256) void k_check_inputs(const DevPW *__restrict__ tab, const int *__restrict__ pwi,
+                                                      const double *__restrict__ E, double thr,
                                                       const double *__restrict__ R, long ldr, long strideR,
-                                                      const double *__restrict__ fg, const double *__restrict__ K,
-                                                      long ldk, long strideK, const int *__restrict__ nopen,
-                                                      int *__restrict__ status) {
+                                                      const double *__restrict__ fg, long ldo,
+                                                      const double *__restrict__ K, long ldk, long strideK,
+                                                      const int *__restrict__ nopen, int *__restrict__ status) {
   const int e = blockIdx.x;
+  const DevPW &p = tab[pwi[e]];
+  const int n = p.n;
   __shared__ int flags;
   if (threadIdx.x == 0) flags = 0;
   __syncthreads();
   int f = 0;
   const double Ev = E[e];
   for (int i = threadIdx.x; i < n; i += 256)
-    if (fabs(Ev - ethr[i]) < thr) f |= RM_PT_THRESHOLD;
+    if (fabs(Ev - p.ethr[i]) < thr) f |= RM_PT_THRESHOLD;
   if (R)
     for (long t = threadIdx.x; t < (long)n * n; t += 256)
       if (!isfinite(R[(size_t)e * strideR + (t / n) * ldr + t % n])) f |= RM_PT_NONFINITE;
   if (fg)
     for (long t = threadIdx.x; t < 4L * n; t += 256)
-      if (!isfinite(fg[(size_t)e * n * 4 + t])) f |= RM_PT_NONFINITE;
+      if (!isfinite(fg[(size_t)e * ldo * 4 + t])) f |= RM_PT_NONFINITE;
   if (K) {
     const int no = nopen[e];
     for (long t = threadIdx.x; t < (long)no * no; t += 256)
@@ -599,11 +620,29 @@ __global__ __launch_bounds__(256) void k_check_inputs(int n, const double *__res
   if (threadIdx.x == 0 && flags) atomicOr(status + e, flags);
 }
 
-void launch_check_inputs(hipStream_t s, int ne, int n, const double *E, const double *ethr, double thr,
-                         const double *R, long ldr, long strideR, const double *fg, const double *K, long ldk,
-                         long strideK, const int *nopen, int *status) {
-  hipLaunchKernelGGL(k_check_inputs, dim3(ne), dim3(256), 0, s, n, E, ethr, thr, R, ldr, strideR, fg, K, ldk,
-                     strideK, nopen, status);
+void launch_check_inputs(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const double *E,
+                         double thr, const double *R, const double *fg, const double *K, const int *nopen,
+                         int *status) {
+  hipLaunchKernelGGL(k_check_inputs, dim3(L.ne), dim3(256), 0, s, tab, pwi, E, thr, R, L.ldaug, L.sA, fg, L.ldo, K,
+                     L.ldk, L.sK, nopen, status);
+}
+
+// Output packing: energy e's leading block goes to pack + off[e], row-major.
+__global__ void k_pack(const DevPW *__restrict__ tab, const int *__restrict__ pwi, int what,
+                       const double *__restrict__ src, long ld, long stride, const long *__restrict__ off,
+                       double *__restrict__ pack) {
+  const int e = blockIdx.y;
+  const DevPW &p = tab[pwi[e]];
+  const int w = what == 0 ? p.nt : p.n;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < (long)w * w; t += (long)gridDim.x * blockDim.x)
+    pack[off[e] + t] = src[(size_t)e * stride + (t / w) * ld + t % w];
+}
+
+void launch_pack(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, int what, const double *src,
+                 const long *off, double *pack) {
+  const long ld = what == 0 ? L.ntmax : L.ldk;
+  const long stride = what == 0 ? L.sOm : L.sK;
+  hipLaunchKernelGGL(k_pack, dim3(32, L.ne), dim3(256), 0, s, tab, pwi, what, src, ld, stride, off, pack);
 }
 
 }  // namespace rm

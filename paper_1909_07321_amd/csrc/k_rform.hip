@@ -2,8 +2,10 @@
 //   R_ij(E) = 1/(2a) sum_k w_ik w_jk / (E_k - E)
 // for a batch of energies, as the symmetric contraction W diag(d(E)) W^T on
 // MFMA, plus the FP64 near-pole correction of the split-precision mode.
-#include "rm_internal.h"
+#include <algorithm>
+
 #include "rm.h"
+#include "rm_internal.h"
 
 namespace rm {
 
@@ -17,30 +19,33 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 // difference fl(E_k - E), which is monotone in E_k, so the masked poles form
 // one contiguous window [lo, hi) of the ascending pole list.
 // ---------------------------------------------------------------------------
-__global__ void k_dvec(const double *__restrict__ Ek, int M, int Mpad, const double *__restrict__ E,
-                       double inv2a, int split, double delta, double *__restrict__ D64,
-                       float *__restrict__ D32) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_dvec(const DevPW *__restrict__ tab, const int *__restrict__ pwi, const double *__restrict__ E,
+                       long ldD, int split, double delta, double *__restrict__ D64, float *__restrict__ D32) {
   const int e = blockIdx.y;
-  if (k >= Mpad) return;
+  const DevPW &p = tab[pwi[e]];
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= p.Mpad) return;
   const double Ev = E[e];
   double d = 0.0;
-  if (k < M) {
-    const double diff = Ek[k] - Ev;
-    d = diff != 0.0 ? inv2a / diff : 0.0;  // exact pole: flagged, value unused
+  if (k < p.M) {
+    const double diff = p.Ek[k] - Ev;
+    d = diff != 0.0 ? (0.5 / p.a) / diff : 0.0;  // exact pole: flagged, value unused
     if (split && fabs(diff) < delta) d = 0.0;
   }
   if (split)
-    D32[(size_t)e * Mpad + k] = (float)d;
+    D32[(size_t)e * ldD + k] = (float)d;
   else
-    D64[(size_t)e * Mpad + k] = d;
+    D64[(size_t)e * ldD + k] = d;
 }
 
 // Window [lo, hi) of poles with |fl(E_k - E)| < delta, and the pole flag.
-__global__ void k_window(const double *__restrict__ Ek, int M, const double *__restrict__ E, int ne,
-                         double delta, int *__restrict__ win, int *__restrict__ status) {
+__global__ void k_window(const DevPW *__restrict__ tab, const int *__restrict__ pwi, const double *__restrict__ E,
+                         int ne, double delta, int *__restrict__ win, int *__restrict__ status) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= ne) return;
+  const DevPW &p = tab[pwi[e]];
+  const double *Ek = p.Ek;
+  const int M = p.M;
   const double Ev = E[e];
   // first k with fl(E_k - E) > -delta
   int lo = 0, hi = M;
@@ -66,12 +71,11 @@ __global__ void k_window(const double *__restrict__ Ek, int M, const double *__r
   if (lo < M && Ek[lo] == Ev) atomicOr(status + e, RM_PT_POLE);
 }
 
-void launch_dvec(hipStream_t s, const DevPW &pw, const double *E, int ne, int split, double delta,
-                 double *D64, float *D32, int *win, int *status) {
-  dim3 grid((pw.Mpad + 255) / 256, ne);
-  hipLaunchKernelGGL(k_dvec, grid, dim3(256), 0, s, pw.Ek, pw.M, pw.Mpad, E, 0.5 / pw.a, split, delta,
-                     D64, D32);
-  hipLaunchKernelGGL(k_window, dim3((ne + 127) / 128), dim3(128), 0, s, pw.Ek, pw.M, E, ne,
+void launch_dvec(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const double *E, int split,
+                 double delta, double *D64, float *D32, int *win, int *status) {
+  dim3 grid((L.Mpadmax + 255) / 256, L.ne);
+  hipLaunchKernelGGL(k_dvec, grid, dim3(256), 0, s, tab, pwi, E, L.ldD, split, delta, D64, D32);
+  hipLaunchKernelGGL(k_window, dim3((L.ne + 127) / 128), dim3(128), 0, s, tab, pwi, E, L.ne,
                      split ? delta : 0.0, win, status);
 }
 
@@ -113,125 +117,179 @@ __device__ __forceinline__ void tri_tile(int t, int &bi, int &bj) {
   bj = t - r * (r + 1) / 2;
 }
 
-template <typename T, int KC>
-__global__ __launch_bounds__(256) void k_rform(const T *__restrict__ W, int ldw, int Mpad,
-                                               const T *__restrict__ D, int ne, int n,
-                                               double *__restrict__ R, long ldr, long strideR) {
-  typedef typename Vec4<T>::type V4;
-  __shared__ T sA[2][KC][TILE];
-  __shared__ T sB[2][KC][TILE];
-  __shared__ T sD[2][EB][KC];
+template <typename T> __device__ __forceinline__ const T *amplitudes(const DevPW &p);
+template <> __device__ __forceinline__ const double *amplitudes<double>(const DevPW &p) { return p.W64; }
+template <> __device__ __forceinline__ const float *amplitudes<float>(const DevPW &p) { return p.W32; }
 
-  int bi, bj;
-  tri_tile(blockIdx.x, bi, bj);
-  const bool diag = bi == bj;
-  const int e0 = blockIdx.y * EB;
+// Persistent: every workgroup takes tasks from a queue (ordered by cost, largest
+// first) until it is empty; a task is one tile of one partial wave for up to EB
+// energies of that wave.  Each energy's sums run over k in ascending order
+// whatever workgroup takes the task, so results do not depend on scheduling.
+template <typename T, int KC>
+__device__ __forceinline__ void rform_body(const DevPW *__restrict__ tab, const RTask *__restrict__ tasks, int ntasks,
+                                           int *__restrict__ counter, const T *__restrict__ D, long ldD,
+                                           double *__restrict__ R, long ldr, long strideR, T (*sA)[KC][TILE],
+                                           T (*sB)[KC][TILE], T (*sD)[EB][KC], int &stask) {
+  typedef typename Vec4<T>::type V4;
+
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int kk = lane >> 4, ii = lane & 15;
-  const int i0 = bi * TILE, j0 = bj * TILE;
-
-  V4 acc[EB][4];
-#pragma unroll
-  for (int e = 0; e < EB; ++e)
-#pragma unroll
-    for (int m = 0; m < 4; ++m) acc[e][m] = V4{0, 0, 0, 0};
-
-  // global -> LDS copy of one stage: KC rows x 64 columns in 16-byte vectors
   constexpr int VEC = 16 / sizeof(T);            // elements per 16-byte load
   constexpr int PER_ROW = TILE / VEC;            // vectors per row
   constexpr int NVEC = KC * PER_ROW / 256;       // vectors per thread per panel
   typedef T TV __attribute__((ext_vector_type(VEC)));
 
-  // register-staged double buffering: the next stage's global loads are in
-  // flight while the current stage is multiplied out of LDS
-  TV ra[NVEC], rb[NVEC];
-  T rd = T(0);
-  auto gload = [&](int k0) {
-#pragma unroll
-    for (int r = 0; r < NVEC; ++r) {
-      const int idx = tid + 256 * r;
-      const int row = idx / PER_ROW, col = (idx % PER_ROW) * VEC;
-      ra[r] = *reinterpret_cast<const TV *>(W + (size_t)(k0 + row) * ldw + i0 + col);
-      if (!diag) rb[r] = *reinterpret_cast<const TV *>(W + (size_t)(k0 + row) * ldw + j0 + col);
-    }
-    if (tid < EB * KC) {
-      const int e = tid / KC, k = tid % KC;
-      rd = (e0 + e < ne) ? D[(size_t)(e0 + e) * Mpad + k0 + k] : T(0);
-    }
-  };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int r = 0; r < NVEC; ++r) {
-      const int idx = tid + 256 * r;
-      const int row = idx / PER_ROW, col = (idx % PER_ROW) * VEC;
-      *reinterpret_cast<TV *>(&sA[buf][row][col]) = ra[r];
-      if (!diag) *reinterpret_cast<TV *>(&sB[buf][row][col]) = rb[r];
-    }
-    if (tid < EB * KC) sD[buf][tid / KC][tid % KC] = rd;
-  };
-
-  const int nstage = Mpad / KC;
-  gload(0);
-  sstore(0);
-  __syncthreads();
-  for (int st = 0; st < nstage; ++st) {
-    const int buf = st & 1;
-    if (st + 1 < nstage) gload((st + 1) * KC);
-    const T(*pA)[TILE] = sA[buf];
-    const T(*pB)[TILE] = diag ? sA[buf] : sB[buf];
-#pragma unroll 4
-    for (int ks = 0; ks < KC; ks += 4) {
-      const T a0 = pA[ks + kk][wr * 32 + ii];
-      const T a1 = pA[ks + kk][wr * 32 + 16 + ii];
-      const T b0 = pB[ks + kk][wc * 32 + ii];
-      const T b1 = pB[ks + kk][wc * 32 + 16 + ii];
-#pragma unroll
-      for (int e = 0; e < EB; ++e) {
-        const T d = sD[buf][e][ks + kk];
-        const T x0 = a0 * d, x1 = a1 * d;
-        acc[e][0] = mfma16(x0, b0, acc[e][0]);
-        acc[e][1] = mfma16(x0, b1, acc[e][1]);
-        acc[e][2] = mfma16(x1, b0, acc[e][2]);
-        acc[e][3] = mfma16(x1, b1, acc[e][3]);
-      }
-    }
-    if (st + 1 < nstage) sstore(buf ^ 1);
+  for (;;) {
+    if (tid == 0) stask = atomicAdd(counter, 1);
     __syncthreads();
-  }
+    const int task = stask;
+    __syncthreads();
+    if (task >= ntasks) return;
+    const RTask tk = tasks[task];
+    const DevPW &p = tab[tk.slot];
+    const T *__restrict__ W = amplitudes<T>(p);
+    const int ldw = p.npad, Mpad = p.Mpad, n = p.n;
+    const int e0 = tk.e0, me = tk.m;
+    int bi, bj;
+    tri_tile(tk.tile, bi, bj);
+    const bool diag = bi == bj;
+    const int i0 = bi * TILE, j0 = bj * TILE;
 
-  // epilogue: lower-triangle elements are written to (i, j) and mirrored to (j, i)
+    V4 acc[EB][4];
 #pragma unroll
-  for (int e = 0; e < EB; ++e) {
-    if (e0 + e >= ne) break;
-    double *Re = R + (size_t)(e0 + e) * strideR;
+    for (int e = 0; e < EB; ++e)
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int j = j0 + wc * 32 + (m & 1) * 16 + ii;
+      for (int m = 0; m < 4; ++m) acc[e][m] = V4{0, 0, 0, 0};
+
+    // register-staged double buffering: the next stage's global loads are in
+    // flight while the current stage is multiplied out of LDS
+    TV ra[NVEC], rb[NVEC];
+    T rd = T(0);
+    auto gload = [&](int k0) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = i0 + wr * 32 + (m >> 1) * 16 + MfmaRow<T>::row(kk, v);
-        if (i < n && j < n && i >= j) {
-          const double val = (double)acc[e][m][v];
-          Re[(size_t)i * ldr + j] = val;
-          Re[(size_t)j * ldr + i] = val;
+      for (int r = 0; r < NVEC; ++r) {
+        const int idx = tid + 256 * r;
+        const int row = idx / PER_ROW, col = (idx % PER_ROW) * VEC;
+        ra[r] = *reinterpret_cast<const TV *>(W + (size_t)(k0 + row) * ldw + i0 + col);
+        if (!diag) rb[r] = *reinterpret_cast<const TV *>(W + (size_t)(k0 + row) * ldw + j0 + col);
+      }
+      if (tid < EB * KC) {
+        const int e = tid / KC, k = tid % KC;
+        rd = e < me ? D[(size_t)(e0 + e) * ldD + k0 + k] : T(0);
+      }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+      for (int r = 0; r < NVEC; ++r) {
+        const int idx = tid + 256 * r;
+        const int row = idx / PER_ROW, col = (idx % PER_ROW) * VEC;
+        *reinterpret_cast<TV *>(&sA[buf][row][col]) = ra[r];
+        if (!diag) *reinterpret_cast<TV *>(&sB[buf][row][col]) = rb[r];
+      }
+      if (tid < EB * KC) sD[buf][tid / KC][tid % KC] = rd;
+    };
+
+    const int nstage = Mpad / KC;
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int st = 0; st < nstage; ++st) {
+      const int buf = st & 1;
+      if (st + 1 < nstage) gload((st + 1) * KC);
+      const T(*pA)[TILE] = sA[buf];
+      const T(*pB)[TILE] = diag ? sA[buf] : sB[buf];
+#pragma unroll 4
+      for (int ks = 0; ks < KC; ks += 4) {
+        const T a0 = pA[ks + kk][wr * 32 + ii];
+        const T a1 = pA[ks + kk][wr * 32 + 16 + ii];
+        const T b0 = pB[ks + kk][wc * 32 + ii];
+        const T b1 = pB[ks + kk][wc * 32 + 16 + ii];
+#pragma unroll
+        for (int e = 0; e < EB; ++e) {
+          const T d = sD[buf][e][ks + kk];
+          const T x0 = a0 * d, x1 = a1 * d;
+          acc[e][0] = mfma16(x0, b0, acc[e][0]);
+          acc[e][1] = mfma16(x0, b1, acc[e][1]);
+          acc[e][2] = mfma16(x1, b0, acc[e][2]);
+          acc[e][3] = mfma16(x1, b1, acc[e][3]);
+        }
+      }
+      if (st + 1 < nstage) sstore(buf ^ 1);
+      __syncthreads();
+    }
+
+    // epilogue: lower-triangle elements are written to (i, j) and mirrored to (j, i)
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      if (e >= me) break;
+      double *Re = R + (size_t)(e0 + e) * strideR;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int j = j0 + wc * 32 + (m & 1) * 16 + ii;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = i0 + wr * 32 + (m >> 1) * 16 + MfmaRow<T>::row(kk, v);
+          if (i < n && j < n && i >= j) {
+            const double val = (double)acc[e][m][v];
+            Re[(size_t)i * ldr + j] = val;
+            Re[(size_t)j * ldr + i] = val;
+          }
         }
       }
     }
   }
 }
 
-void launch_rform(hipStream_t s, const DevPW &pw, int ne, int split, const double *D64,
-                  const float *D32, double *R, long ldr, long strideR) {
-  const int nt = pw.npad / TILE;
-  dim3 grid(nt * (nt + 1) / 2, (ne + EB - 1) / EB);
+// The FP32 variant is held to two waves per SIMD (its accumulators are half the
+// size); the FP64 one keeps its 128 accumulator registers at one wave per SIMD.
+__global__ __launch_bounds__(256, 2) void k_rform_f32(const DevPW *__restrict__ tab, const RTask *__restrict__ tasks,
+                                                      int ntasks, int *__restrict__ counter,
+                                                      const float *__restrict__ D, long ldD, double *__restrict__ R,
+                                                      long ldr, long strideR) {
+  __shared__ float sA[2][KC32][TILE];
+  __shared__ float sB[2][KC32][TILE];
+  __shared__ float sD[2][EB][KC32];
+  __shared__ int stask;
+  rform_body<float, KC32>(tab, tasks, ntasks, counter, D, ldD, R, ldr, strideR, sA, sB, sD, stask);
+}
+
+__global__ __launch_bounds__(256) void k_rform_f64(const DevPW *__restrict__ tab, const RTask *__restrict__ tasks,
+                                                   int ntasks, int *__restrict__ counter,
+                                                   const double *__restrict__ D, long ldD, double *__restrict__ R,
+                                                   long ldr, long strideR) {
+  __shared__ double sA[2][KC64][TILE];
+  __shared__ double sB[2][KC64][TILE];
+  __shared__ double sD[2][EB][KC64];
+  __shared__ int stask;
+  rform_body<double, KC64>(tab, tasks, ntasks, counter, D, ldD, R, ldr, strideR, sA, sB, sD, stask);
+}
+
+__global__ void k_reset(int *__restrict__ counter) { *counter = 0; }
+
+void launch_rform(hipStream_t s, const Lay &L, int split, const DevPW *tab, const RTask *tasks, int ntasks,
+                  int *counter, int nworkgroups, const double *D64, const float *D32, double *R) {
+  if (ntasks <= 0) return;
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, s, counter);
+  // persistent grid: as many workgroups as can be resident at once
+  static int occ[2] = {0, 0};
+  int &oc = occ[split ? 1 : 0];
+  if (!oc) {
+    int b = 0;
+    if (split)
+      (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_rform_f32, 256, 0);
+    else
+      (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_rform_f64, 256, 0);
+    oc = std::max(1, b);
+  }
+  const dim3 grid(std::max(1, std::min(ntasks, oc * nworkgroups)));
   if (split)
-    hipLaunchKernelGGL((k_rform<float, KC32>), grid, dim3(256), 0, s, pw.W32, pw.npad, pw.Mpad, D32,
-                       ne, pw.n, R, ldr, strideR);
+    hipLaunchKernelGGL(k_rform_f32, grid, dim3(256), 0, s, tab, tasks, ntasks, counter, D32, L.ldD, R, L.ldaug,
+                       L.sA);
   else
-    hipLaunchKernelGGL((k_rform<double, KC64>), grid, dim3(256), 0, s, pw.W64, pw.npad, pw.Mpad, D64,
-                       ne, pw.n, R, ldr, strideR);
+    hipLaunchKernelGGL(k_rform_f64, grid, dim3(256), 0, s, tab, tasks, ntasks, counter, D64, L.ldD, R, L.ldaug,
+                       L.sA);
 }
 
 // ---------------------------------------------------------------------------
@@ -239,13 +297,18 @@ void launch_rform(hipStream_t s, const DevPW &pw, int ne, int split, const doubl
 // W[:, lo:hi]^T in FP64, one workgroup per (lower tile, energy).  The window is
 // short (|E_k - E| < delta), so fragments are read straight from HBM/L2.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_nearpole(const double *__restrict__ W, int ldw,
-                                                  const double *__restrict__ Ek, const double *__restrict__ E,
-                                                  const int *__restrict__ win, double inv2a, int n,
+__global__ __launch_bounds__(256) void k_nearpole(const DevPW *__restrict__ tab, const int *__restrict__ pwi,
+                                                  const double *__restrict__ E, const int *__restrict__ win,
                                                   double *__restrict__ R, long ldr, long strideR) {
   const int e = blockIdx.y;
   const int lo = win[2 * e], hi = win[2 * e + 1];
   if (lo >= hi) return;
+  const DevPW &p = tab[pwi[e]];
+  const int ntl = p.npad / TILE;
+  if ((int)blockIdx.x >= ntl * (ntl + 1) / 2) return;
+  const double *__restrict__ W = p.W64;
+  const int ldw = p.npad, n = p.n;
+  const double inv2a = 0.5 / p.a;
   int bi, bj;
   tri_tile(blockIdx.x, bi, bj);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -253,6 +316,7 @@ __global__ __launch_bounds__(256) void k_nearpole(const double *__restrict__ W, 
   const int kk = lane >> 4, ii = lane & 15;
   const int i0 = bi * TILE + wr * 32, j0 = bj * TILE + wc * 32;
   const double Ev = E[e];
+  const double *Ek = p.Ek;
   d4 acc[4];
 #pragma unroll
   for (int m = 0; m < 4; ++m) acc[m] = d4{0, 0, 0, 0};
@@ -290,24 +354,23 @@ __global__ __launch_bounds__(256) void k_nearpole(const double *__restrict__ W, 
   }
 }
 
-void launch_nearpole(hipStream_t s, const DevPW &pw, const double *E, int ne, const int *win,
-                     double *R, long ldr, long strideR) {
-  const int nt = pw.npad / TILE;
-  dim3 grid(nt * (nt + 1) / 2, ne);
-  hipLaunchKernelGGL(k_nearpole, grid, dim3(256), 0, s, pw.W64, pw.npad, pw.Ek, E, win, 0.5 / pw.a,
-                     pw.n, R, ldr, strideR);
+void launch_nearpole(hipStream_t s, const Lay &L, int maxtiles, const DevPW *tab, const int *pwi, const double *E,
+                     const int *win, double *R) {
+  dim3 grid(maxtiles, L.ne);
+  hipLaunchKernelGGL(k_nearpole, grid, dim3(256), 0, s, tab, pwi, E, win, R, L.ldaug, L.sA);
 }
 
-__global__ void k_nanfill_R(int n, const int *__restrict__ status, double *__restrict__ R, long ldr,
-                            long strideR) {
+__global__ void k_nanfill_R(const DevPW *__restrict__ tab, const int *__restrict__ pwi,
+                            const int *__restrict__ status, double *__restrict__ R, long ldr, long strideR) {
   const int e = blockIdx.y;
   if (!(status[e] & RM_PT_POLE)) return;
+  const int n = tab[pwi[e]].n;
   for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < (long)n * n; t += (long)gridDim.x * blockDim.x)
     R[(size_t)e * strideR + (t / n) * ldr + t % n] = __builtin_nan("");
 }
 
-void launch_nanfill_R(hipStream_t s, int ne, int n, const int *status, double *R, long ldr, long strideR) {
-  hipLaunchKernelGGL(k_nanfill_R, dim3(64, ne), dim3(256), 0, s, n, status, R, ldr, strideR);
+void launch_nanfill_R(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *status, double *R) {
+  hipLaunchKernelGGL(k_nanfill_R, dim3(64, L.ne), dim3(256), 0, s, tab, pwi, status, R, L.ldaug, L.sA);
 }
 
 }  // namespace rm

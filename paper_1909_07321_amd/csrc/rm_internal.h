@@ -22,6 +22,9 @@ inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 // A partial wave resident in HBM.  Amplitudes are stored pole-major with the
 // channel dimension padded to TILE and the pole dimension padded to KC32, the
 // padding filled with zeros so every tile load is in bounds and contributes 0.
+// The struct is plain data: a chunk's partial waves are copied to the device as
+// a table, and every kernel reads its energy's entry through a per-energy slot
+// index, so one launch can serve energies of several partial waves.
 struct DevPW {
   int n = 0, M = 0, nt = 0;
   int npad = 0, Mpad = 0;
@@ -37,43 +40,70 @@ struct DevPW {
   size_t bytes = 0;
 };
 
-// Per-chunk device workspace (E_c energies of one partial wave).
+// Strides of one chunk of energies.  Every per-energy block is laid out for the
+// largest partial wave in the chunk.
+struct Lay {
+  int ne = 0;
+  int nmax = 0, npadmax = 0, Mpadmax = 0, ntmax = 0;
+  long ldD = 0;                 // d(E) rows: Mpadmax
+  long ldaug = 0, roff = 0, sA = 0;  // [A | B]: ldaug = 2 npadmax, B at column roff = npadmax
+  long ldk = 0, sK = 0;         // K and XK: ldk = npadmax, sK = nmax * ldk
+  long ldo = 0;                 // per-channel arrays (fg has 4 per channel): nmax
+  long sOm = 0;                 // Omega: ntmax * ntmax per energy
+};
+
+// One task of the R contraction: energies [e0, e0 + m) (m <= EB, one partial
+// wave, table slot `slot`) times one lower-triangle tile.
+struct RTask {
+  int slot, e0, m, tile;
+};
+
+// Per-chunk device workspace.
 struct Work {
-  int cap_e = 0, cap_n = 0, cap_npad = 0, cap_M = 0, cap_nt = 0;
+  int cap_e = 0, cap_n = 0, cap_npad = 0, cap_M = 0, cap_nt = 0, cap_tab = 0, cap_tasks = 0;
   size_t bytes = 0;
   double *E = nullptr;       // [cap_e]
-  double *D64 = nullptr;     // [cap_e][Mpad]
-  float *D32 = nullptr;      // [cap_e][Mpad]
+  int *pwi = nullptr;        // [cap_e] table slot of each energy
+  DevPW *tab = nullptr;      // [cap_tab]
+  RTask *tasks = nullptr;    // [cap_tasks]
+  int *counter = nullptr;    // task queue head of the persistent R contraction
+  double *D64 = nullptr;     // [cap_e][ldD]
+  float *D32 = nullptr;      // [cap_e][ldD]
   int *win = nullptr;        // [cap_e][2] near-pole window [lo, hi)
   int *status = nullptr;     // [cap_e]
   int *nopen = nullptr;      // [cap_e]
-  int *openidx = nullptr;    // [cap_e][cap_n]
-  int *openpos = nullptr;    // [cap_e][cap_n] position in the open list or -1
-  int8_t *openflag = nullptr;// [cap_e][cap_n]
-  double *fg = nullptr;      // [cap_e][cap_n][4]
-  double *aug = nullptr;     // [cap_e][cap_n][ldaug]
-  double *Kw = nullptr;      // [cap_e][ldk][ldk]
-  double *XK = nullptr;      // [cap_e][ldk][ldk]
+  int *openidx = nullptr;    // [cap_e][ldo]
+  int *openpos = nullptr;    // [cap_e][ldo] position in the open list or -1
+  int8_t *openflag = nullptr;// [cap_e][ldo]
+  double *fg = nullptr;      // [cap_e][ldo][4]
+  double *aug = nullptr;     // [cap_e][nmax][ldaug]
+  double *Kw = nullptr;      // [cap_e][nmax][ldk]
+  double *XK = nullptr;      // [cap_e][nmax][ldk]
   int *dims = nullptr;       // [cap_e][2] per-energy (rows, rhs) for batched LU
-  int *ipiv = nullptr;       // [cap_e][cap_n] LU row interchanges
-  double *omega = nullptr;   // [cap_e][cap_nt][cap_nt]
-  double *S = nullptr;       // [cap_e][cap_n][cap_n][2], allocated on demand
+  int *ipiv = nullptr;       // [cap_e][ldo] LU row interchanges
+  double *omega = nullptr;   // [cap_e][ntmax][ntmax]
+  double *pack = nullptr;    // packed outputs, [cap_e][nmax][nmax] doubles
+  long *pack_off = nullptr;  // [cap_e + 1] offsets of each energy's packed block
+  double *S = nullptr;       // [cap_e][nmax][nmax][2], allocated on demand
 };
 
-// ---- kernel launchers (all asynchronous on `s`) ----
-void launch_dvec(hipStream_t s, const DevPW &pw, const double *E, int ne, int split, double delta,
-                 double *D64, float *D32, int *win, int *status);
-void launch_rform(hipStream_t s, const DevPW &pw, int ne, int split, const double *D64,
-                  const float *D32, double *R, long ldr, long strideR);
-void launch_nearpole(hipStream_t s, const DevPW &pw, const double *E, int ne, const int *win,
-                     double *R, long ldr, long strideR);
-void launch_nanfill_R(hipStream_t s, int ne, int n, const int *status, double *R, long ldr, long strideR);
-void launch_openlist(hipStream_t s, const DevPW &pw, const double *E, int ne, int *nopen,
-                     int *openidx, int *openpos, int8_t *openflag, long ld);
-void launch_asym(hipStream_t s, const DevPW &pw, const double *E, int ne, double thr_guard,
+// ---- kernel launchers (all asynchronous on `s`).  tab/pwi are device pointers.
+void launch_dvec(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const double *E, int split,
+                 double delta, double *D64, float *D32, int *win, int *status);
+// Persistent R contraction over `tasks`; ncu = compute units of the device (the
+// grid is the number of workgroups that fit at once).
+void launch_rform(hipStream_t s, const Lay &L, int split, const DevPW *tab, const RTask *tasks, int ntasks,
+                  int *counter, int ncu, const double *D64, const float *D32, double *R);
+void launch_nearpole(hipStream_t s, const Lay &L, int maxtiles, const DevPW *tab, const int *pwi, const double *E,
+                     const int *win, double *R);
+void launch_nanfill_R(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *status, double *R);
+void launch_openlist(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const double *E, int *nopen,
+                     int *openidx, int *openpos, int8_t *openflag);
+void launch_asym(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const double *E, double thr_guard,
                  double *fg, int *status);
-void launch_build(hipStream_t s, const DevPW &pw, int ne, const double *fg, const int *nopen,
-                  const int *openidx, long ldo, double *aug, long ldaug, long strideA, long roff);
+void launch_setdims(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *nopen, int *dims);
+void launch_build(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const double *fg,
+                  const int *nopen, const int *openidx, double *aug);
 // Batched LU with partial pivoting of [A | B] per energy (dims[2e] = rows of the
 // square A in columns [0, rows), dims[2e+1] = right-hand sides in columns
 // [roff, roff + rhs)), then back substitution: on return the right-hand-side
@@ -83,15 +113,19 @@ void launch_lu_solve(hipStream_t s, int ne, int maxrows, int maxrhs, const int *
 // C[e] = A[e] B[e] for square no x no blocks, no = nopen[e]
 void launch_gemm_sq(hipStream_t s, int ne, int maxn, const int *nopen, const double *A, long lda, long sA,
                     const double *B, long ldb, long sB, double *C, long ldc, long sC);
-void launch_gatherK(hipStream_t s, int ne, int n, const int *nopen, const int *openidx, long ldo,
-                    const double *aug, long ldaug, long strideA, long roff, double *Kw, long ldk,
-                    long strideK);
-void launch_formP(hipStream_t s, int ne, int maxno, const int *nopen, const double *Kw, long ldk,
-                  long strideK, double *aug, long ldaug, long strideA, long roff, int *dims);
-void launch_omega(hipStream_t s, const DevPW &pw, int ne, const int *openpos, long ldo, const int *nopen,
-                  const double *X, long ldx, long sX, const double *XK, long ldxk, long sXK, double *omega,
-                  double *S);
-void launch_finalize(hipStream_t s, int ne, int n, int nt, int *status, double *omega, double *K, long ldk,
-                     long strideK, double *S);
+void launch_gatherK(hipStream_t s, const Lay &L, const int *nopen, const int *openidx, const double *aug,
+                    double *Kw);
+void launch_formP(hipStream_t s, const Lay &L, const int *nopen, const double *Kw, double *aug, int *dims);
+void launch_omega(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *openpos,
+                  const int *nopen, const double *X, const double *XK, double *omega, double *S);
+void launch_finalize(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, int *status, double *omega,
+                     double *K, double *S);
+void launch_check_inputs(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const double *E,
+                         double thr, const double *R, const double *fg, const double *K, const int *nopen,
+                         int *status);
+// Packs each energy's leading nt x nt Omega block (what = 0) or n x n K block
+// (what = 1) contiguously at pack + off[e].
+void launch_pack(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, int what, const double *src,
+                 const long *off, double *pack);
 
 }  // namespace rm

@@ -1,6 +1,14 @@
 // rm_runtime.cpp -- host runtime behind include/rm.h: context, resident partial
-// waves, workspaces sized against the HBM budget, the staged and fused calls,
-// and the serving scheduler (continuous batching over worker streams).
+// waves, workspaces sized against the HBM budget, chunk planning, the staged,
+// fused and batched calls, and the serving scheduler.
+//
+// Every call is reduced to a list of segments (one partial wave, a block of
+// energies, where its outputs go).  Segments are cut into chunks; a chunk may
+// hold energies of several partial waves.  Per chunk the device gets a table
+// of the partial waves involved, each energy's table slot, and a task list for
+// the persistent R contraction (tasks ordered by cost, largest first); every
+// later stage reads its energy's partial wave through the slot, so the whole
+// chunk runs as one launch sequence whatever its mix of channel counts.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,13 +31,6 @@
 
 using namespace rm;
 
-namespace rm {
-void launch_setdims(hipStream_t s, int ne, int rows, const int *nopen, int *dims);
-void launch_check_inputs(hipStream_t s, int ne, int n, const double *E, const double *ethr, double thr,
-                         const double *R, long ldr, long strideR, const double *fg, const double *K, long ldk,
-                         long strideK, const int *nopen, int *status);
-}  // namespace rm
-
 namespace {
 
 int64_t now_ns() {
@@ -37,9 +38,23 @@ int64_t now_ns() {
       .count();
 }
 
+// Pinned host staging of one workspace: chunk plans are written here and copied
+// to the device on the workspace's stream; `ready` marks when the copies of the
+// previous chunk that used this staging have run.
+struct Staging {
+  double *E = nullptr;
+  int *pwi = nullptr;
+  DevPW *tab = nullptr;
+  RTask *tasks = nullptr;
+  long *off = nullptr;  // [2][cap_e + 1]: Omega and K pack offsets
+  int cap_e = 0, cap_tab = 0, cap_tasks = 0;
+  hipEvent_t ready = nullptr;
+};
+
 struct Slot {
   hipStream_t stream = nullptr;
   Work w;
+  Staging h;
 };
 
 struct ProfRec {
@@ -60,31 +75,55 @@ struct Req {
   bool admitted = false;
 };
 
+// One partial wave's block of energies and where its results go.
+struct Seg {
+  const DevPW *pw = nullptr;
+  const double *E = nullptr;  // host or device, see the call's opts
+  int ne = 0;
+  double *omega = nullptr;    // [ne][nt][nt]
+  double *K = nullptr;        // [ne][n][n] or null
+  int32_t *status = nullptr;  // [ne]
+};
+
+// The part [e_begin, e_begin + m) of segment `seg`, placed at chunk energy e0.
+struct Part {
+  int seg, e_begin, m, e0, slot;
+};
+
+struct Plan {
+  std::vector<Part> parts;
+  std::vector<const DevPW *> slots;
+  Lay L;
+  int ntasks = 0, maxtiles = 0;
+};
+
 }  // namespace
 
 struct rm_ctx {
   int device = 0;
+  int ncu = 256;
   size_t budget = 0;
-  size_t resident = 0;   // bytes of resident partial waves
-  size_t work_bytes = 0; // bytes of all workspaces
+  size_t resident = 0;    // bytes of resident partial waves
+  size_t work_bytes = 0;  // bytes of all workspaces
   hipStream_t stream = nullptr;
-  Work work;  // workspace of the synchronous calls
+  Slot sync;  // workspace of the staged calls
   std::map<int32_t, DevPW> pws;
   int32_t next_id = 1;
   std::string err;
-  std::mutex mu;  // guards everything below and the budget counters
+  std::mutex mu;  // guards the maps, queues and budget counters
   std::condition_variable cv;
   std::deque<Req *> active;  // arrival order
   std::map<uint64_t, std::unique_ptr<Req>> reqs;
-  std::vector<std::unique_ptr<Slot>> slots;
+  std::vector<std::unique_ptr<Slot>> slots;  // serving workers
   std::vector<std::thread> workers;
   bool stop = false;
   uint64_t next_ticket = 1;
   int max_queue = 4096;
   std::atomic<int> prof_on{0};
   std::vector<ProfRec> prof;  // guarded by mu
-  // rm_run alternates chunks over two streams so that one chunk's K solve
-  // overlaps the next chunk's R contraction
+  // rm_run / rm_run_batch alternate chunks over two streams; the R
+  // contractions are chained across them so that one chunk's K solve overlaps
+  // the next chunk's contraction
   Slot pipe[2];
   hipEvent_t ev_in = nullptr, ev_out[2] = {nullptr, nullptr}, ev_R[2] = {nullptr, nullptr};
 };
@@ -102,105 +141,217 @@ namespace {
 
 constexpr int MAX_CHUNK = 1024;
 
-size_t per_energy_bytes(int n, int npad, int Mpad) {
-  return (size_t)n * 2 * npad * 8      // aug
-         + (size_t)n * npad * 8 * 2    // Kw, XK
-         + (size_t)Mpad * 12           // D64 + D32
-         + (size_t)n * (32 + 9)        // fg, openidx, openpos, openflag
-         + (size_t)n * n * 8 / 8       // headroom
-         + 64;
+size_t per_energy_bytes(int n, int npad, int Mpad, int nt) {
+  return (size_t)n * 2 * npad * 8    // aug
+         + (size_t)n * npad * 8 * 2  // Kw, XK
+         + (size_t)n * n * 8         // packed outputs
+         + (size_t)Mpad * 12         // D64 + D32
+         + (size_t)n * (32 + 13)     // fg, openidx, openpos, openflag, ipiv
+         + (size_t)nt * nt * 8       // Omega
+         + 128;
 }
 
 void free_work(Work &w) {
-  void *ptrs[] = {w.E, w.D64, w.D32, w.win, w.status, w.nopen, w.openidx, w.openpos, w.openflag,
-                  w.fg, w.aug, w.Kw, w.XK, w.dims, w.omega, w.S, w.ipiv};
+  void *ptrs[] = {w.E, w.pwi, w.tab, w.tasks, w.counter, w.D64, w.D32, w.win, w.status, w.nopen, w.openidx,
+                  w.openpos, w.openflag, w.fg, w.aug, w.Kw, w.XK, w.dims, w.ipiv, w.omega, w.pack, w.pack_off,
+                  w.S};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   w = Work();
 }
 
-// (Re)allocates w for chunks of up to cap energies of partial wave pw.
-rm_status ensure_work(rm_ctx *ctx, Work &w, const DevPW &pw, int cap, bool want_S) {
-  const int n = pw.n, npad = pw.npad, Mpad = pw.Mpad;
-  if (w.cap_e >= cap && w.cap_n >= n && w.cap_npad >= npad && w.cap_M >= Mpad && w.cap_nt >= pw.nt &&
-      (!want_S || w.S))
-    return RM_OK;
-  const int ce = std::max(cap, w.cap_e), cn = std::max(n, w.cap_n), cnp = std::max(npad, w.cap_npad),
-            cm = std::max(Mpad, w.cap_M), ct = std::max(pw.nt, w.cap_nt);
-  const bool S = want_S || w.S != nullptr;
-  size_t need = 0;
-  auto sz = [&](size_t b) { need += (b + 255) / 256 * 256; return b; };
-  const size_t bE = sz((size_t)ce * 8), bD64 = sz((size_t)ce * cm * 8), bD32 = sz((size_t)ce * cm * 4),
-               bwin = sz((size_t)ce * 8), bst = sz((size_t)ce * 4), bno = sz((size_t)ce * 4),
-               boi = sz((size_t)ce * cn * 4), bop = sz((size_t)ce * cn * 4), bof = sz((size_t)ce * cn),
-               bfg = sz((size_t)ce * cn * 32), baug = sz((size_t)ce * cn * 2 * cnp * 8),
-               bK = sz((size_t)ce * cn * cnp * 8), bXK = sz((size_t)ce * cn * cnp * 8),
-               bdims = sz((size_t)ce * 8), bom = sz((size_t)ce * ct * ct * 8), bpiv = sz((size_t)ce * cn * 4),
-               bS = S ? sz((size_t)ce * cn * cn * 16) : 0;
-  {
-    std::lock_guard<std::mutex> g(ctx->mu);
-    if (ctx->resident + ctx->work_bytes - w.bytes + need > ctx->budget) {
-      ctx->err = "workspace exceeds the HBM budget";
-      return RM_E_NOMEM;
+void free_staging(Staging &h) {
+  void *ptrs[] = {h.E, h.pwi, h.tab, h.tasks, h.off};
+  for (void *p : ptrs)
+    if (p) (void)hipHostFree(p);
+  if (h.ready) (void)hipEventDestroy(h.ready);
+  h = Staging();
+}
+
+// (Re)allocates a slot for chunks with layout L, ntab partial waves and ntasks
+// R tasks.  Grows only.
+rm_status ensure_slot(rm_ctx *ctx, Slot &sl, const Lay &L, int ntab, int ntasks, bool want_S) {
+  Work &w = sl.w;
+  Staging &h = sl.h;
+  if (!h.ready) HIPCHK(hipEventCreateWithFlags(&h.ready, hipEventDisableTiming));
+  const bool fits = w.cap_e >= L.ne && w.cap_n >= L.nmax && w.cap_npad >= L.npadmax && w.cap_M >= L.Mpadmax &&
+                    w.cap_nt >= L.ntmax && w.cap_tab >= ntab && w.cap_tasks >= ntasks && (!want_S || w.S);
+  if (!fits) {
+    const int ce = std::max(L.ne, w.cap_e), cn = std::max(L.nmax, w.cap_n),
+              cnp = std::max(L.npadmax, w.cap_npad), cm = std::max(L.Mpadmax, w.cap_M),
+              ct = std::max(L.ntmax, w.cap_nt), ctab = std::max(ntab, w.cap_tab),
+              ctask = std::max(ntasks, w.cap_tasks);
+    const bool S = want_S || w.S != nullptr;
+    size_t need = 0;
+    auto sz = [&](size_t b) {
+      need += (b + 255) / 256 * 256;
+      return std::max<size_t>(b, 8);
+    };
+    const size_t bE = sz((size_t)ce * 8), bpwi = sz((size_t)ce * 4), btab = sz((size_t)ctab * sizeof(DevPW)),
+                 btask = sz((size_t)ctask * sizeof(RTask)), bcnt = sz(64), bD64 = sz((size_t)ce * cm * 8),
+                 bD32 = sz((size_t)ce * cm * 4), bwin = sz((size_t)ce * 8), bst = sz((size_t)ce * 4),
+                 bno = sz((size_t)ce * 4), bidx = sz((size_t)ce * cn * 4), bflag = sz((size_t)ce * cn),
+                 bfg = sz((size_t)ce * cn * 32), baug = sz((size_t)ce * cn * 2 * cnp * 8),
+                 bK = sz((size_t)ce * cn * cnp * 8), bdims = sz((size_t)ce * 8),
+                 bom = sz((size_t)ce * ct * ct * 8),
+                 bpack = sz((size_t)ce * std::max((size_t)cn * cn, (size_t)ct * ct) * 8),
+                 boff = sz((size_t)(ce + 1) * 8), bS = S ? sz((size_t)ce * cn * cn * 16) : 0;
+    // openpos and ipiv share bidx's size, XK shares bK's, the pack offsets are two blocks
+    need += 2 * ((bidx + 255) / 256 * 256) + (bK + 255) / 256 * 256 + (boff + 255) / 256 * 256;
+    {
+      std::lock_guard<std::mutex> g(ctx->mu);
+      if (ctx->resident + ctx->work_bytes - w.bytes + need > ctx->budget) {
+        ctx->err = "workspace exceeds the HBM budget";
+        return RM_E_NOMEM;
+      }
     }
-  }
-  const size_t old = w.bytes;
-  free_work(w);
-  {
+    HIPCHK(hipStreamSynchronize(sl.stream));
+    const size_t old = w.bytes;
+    free_work(w);
+    {
+      std::lock_guard<std::mutex> g(ctx->mu);
+      ctx->work_bytes -= old;
+    }
+    HIPCHK(hipMalloc(&w.E, bE));
+    HIPCHK(hipMalloc(&w.pwi, bpwi));
+    HIPCHK(hipMalloc(&w.tab, btab));
+    HIPCHK(hipMalloc(&w.tasks, btask));
+    HIPCHK(hipMalloc(&w.counter, bcnt));
+    HIPCHK(hipMalloc(&w.D64, bD64));
+    HIPCHK(hipMalloc(&w.D32, bD32));
+    HIPCHK(hipMalloc(&w.win, bwin));
+    HIPCHK(hipMalloc(&w.status, bst));
+    HIPCHK(hipMalloc(&w.nopen, bno));
+    HIPCHK(hipMalloc(&w.openidx, bidx));
+    HIPCHK(hipMalloc(&w.openpos, bidx));
+    HIPCHK(hipMalloc(&w.ipiv, bidx));
+    HIPCHK(hipMalloc(&w.openflag, bflag));
+    HIPCHK(hipMalloc(&w.fg, bfg));
+    HIPCHK(hipMalloc(&w.aug, baug));
+    HIPCHK(hipMalloc(&w.Kw, bK));
+    HIPCHK(hipMalloc(&w.XK, bK));
+    HIPCHK(hipMalloc(&w.dims, bdims));
+    HIPCHK(hipMalloc(&w.omega, bom));
+    HIPCHK(hipMalloc(&w.pack, bpack));
+    HIPCHK(hipMalloc(&w.pack_off, 2 * boff));
+    if (S) HIPCHK(hipMalloc(&w.S, bS));
+    w.cap_e = ce;
+    w.cap_n = cn;
+    w.cap_npad = cnp;
+    w.cap_M = cm;
+    w.cap_nt = ct;
+    w.cap_tab = ctab;
+    w.cap_tasks = ctask;
+    w.bytes = need;
     std::lock_guard<std::mutex> g(ctx->mu);
-    ctx->work_bytes -= old;
+    ctx->work_bytes += need;
   }
-  HIPCHK(hipMalloc(&w.E, bE));
-  HIPCHK(hipMalloc(&w.D64, bD64));
-  HIPCHK(hipMalloc(&w.D32, bD32));
-  HIPCHK(hipMalloc(&w.win, bwin));
-  HIPCHK(hipMalloc(&w.status, bst));
-  HIPCHK(hipMalloc(&w.nopen, bno));
-  HIPCHK(hipMalloc(&w.openidx, boi));
-  HIPCHK(hipMalloc(&w.openpos, bop));
-  HIPCHK(hipMalloc(&w.openflag, bof));
-  HIPCHK(hipMalloc(&w.fg, bfg));
-  HIPCHK(hipMalloc(&w.aug, baug));
-  HIPCHK(hipMalloc(&w.Kw, bK));
-  HIPCHK(hipMalloc(&w.XK, bXK));
-  HIPCHK(hipMalloc(&w.dims, bdims));
-  HIPCHK(hipMalloc(&w.omega, bom));
-  HIPCHK(hipMalloc(&w.ipiv, bpiv));
-  if (S) HIPCHK(hipMalloc(&w.S, bS));
-  w.cap_e = ce;
-  w.cap_n = cn;
-  w.cap_npad = cnp;
-  w.cap_M = cm;
-  w.cap_nt = ct;
-  w.bytes = need;
-  std::lock_guard<std::mutex> g(ctx->mu);
-  ctx->work_bytes += need;
+  if (h.cap_e < L.ne || h.cap_tab < ntab || h.cap_tasks < ntasks) {
+    HIPCHK(hipStreamSynchronize(sl.stream));
+    const int ce = std::max(L.ne, h.cap_e), ctab = std::max(ntab, h.cap_tab), ctask = std::max(ntasks, h.cap_tasks);
+    hipEvent_t ev = h.ready;
+    h.ready = nullptr;
+    free_staging(h);
+    h.ready = ev;
+    HIPCHK(hipHostMalloc((void **)&h.E, sizeof(double) * ce, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&h.pwi, sizeof(int) * ce, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&h.tab, sizeof(DevPW) * ctab, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&h.tasks, sizeof(RTask) * std::max(ctask, 1), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&h.off, sizeof(long) * 2 * (ce + 1), hipHostMallocDefault));
+    h.cap_e = ce;
+    h.cap_tab = ctab;
+    h.cap_tasks = ctask;
+  }
   return RM_OK;
 }
 
-// Energies per chunk for partial wave pw given `share` bytes of budget.
-int chunk_cap(const DevPW &pw, size_t share, int ne) {
-  const size_t per = per_energy_bytes(pw.n, pw.npad, pw.Mpad);
+// Strides of a chunk holding the given partial waves.
+Lay make_layout(const std::vector<const DevPW *> &slots, int ne) {
+  Lay L;
+  L.ne = ne;
+  for (const DevPW *p : slots) {
+    L.nmax = std::max(L.nmax, p->n);
+    L.npadmax = std::max(L.npadmax, p->npad);
+    L.Mpadmax = std::max(L.Mpadmax, p->Mpad);
+    L.ntmax = std::max(L.ntmax, p->nt);
+  }
+  L.ldD = L.Mpadmax;
+  L.ldaug = 2L * L.npadmax;
+  L.roff = L.npadmax;
+  L.sA = (long)L.nmax * L.ldaug;
+  L.ldk = L.npadmax;
+  L.sK = (long)L.nmax * L.ldk;
+  L.ldo = L.nmax;
+  L.sOm = (long)L.ntmax * L.ntmax;
+  return L;
+}
+
+// Energies per chunk for a chunk whose largest members are (n, npad, Mpad, nt),
+// given `share` bytes of budget.
+int chunk_cap(int n, int npad, int Mpad, int nt, size_t share, int limit) {
+  const size_t per = per_energy_bytes(n, npad, Mpad, nt);
   long cap = (long)(share / std::max<size_t>(per, 1));
-  cap = std::min<long>(cap, MAX_CHUNK);
-  cap = std::min<long>(cap, ((long)ne + EB - 1) / EB * EB);
+  cap = std::min<long>(cap, limit);
   if (cap >= EB) cap = cap / EB * EB;
   return (int)std::max<long>(cap, 1);
 }
 
-// Layout helpers: all per-energy blocks have rows of the partial wave's n
-struct Lay {
-  long ldaug, roff, sA, ldk, sK, ldo;
-};
-Lay layout(const DevPW &pw, const Work &w) {
-  Lay L;
-  L.ldaug = 2L * w.cap_npad;
-  L.roff = w.cap_npad;
-  L.sA = (long)pw.n * L.ldaug;
-  L.ldk = w.cap_npad;
-  L.sK = (long)pw.n * L.ldk;
-  L.ldo = pw.n;
-  return L;
+// Fills the slot's staging for the chunk (energies, slots, tasks, pack offsets)
+// and queues its copies to the device.
+rm_status upload_plan(rm_ctx *ctx, Slot &sl, Plan &P, const std::vector<Seg> &segs, const rm_opts &o, bool want_K) {
+  Staging &h = sl.h;
+  Work &w = sl.w;
+  const Lay &L = P.L;
+  // the previous chunk on this slot must have consumed the staging
+  HIPCHK(hipEventSynchronize(h.ready));
+  for (const Part &pt : P.parts)
+    for (int i = 0; i < pt.m; ++i) h.pwi[pt.e0 + i] = pt.slot;
+  for (size_t i = 0; i < P.slots.size(); ++i) h.tab[i] = *P.slots[i];
+  // R tasks: energy batches of <= EB energies of one partial wave times its tiles,
+  // largest pole count first (longest tasks start first)
+  std::vector<int> order(P.parts.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return P.slots[P.parts[a].slot]->Mpad > P.slots[P.parts[b].slot]->Mpad; });
+  int nt = 0;
+  for (int pi : order) {
+    const Part &pt = P.parts[pi];
+    const int tl = P.slots[pt.slot]->npad / TILE;
+    const int ntile = tl * (tl + 1) / 2;
+    for (int b = 0; b < pt.m; b += EB)
+      for (int t = 0; t < ntile; ++t) h.tasks[nt++] = RTask{pt.slot, pt.e0 + b, std::min(EB, pt.m - b), t};
+  }
+  P.ntasks = nt;
+  long om = 0, kk = 0;
+  for (const Part &pt : P.parts) {
+    const DevPW *p = P.slots[pt.slot];
+    for (int i = 0; i < pt.m; ++i) {
+      h.off[pt.e0 + i] = om;
+      h.off[L.ne + 1 + pt.e0 + i] = kk;
+      om += (long)p->nt * p->nt;
+      kk += (long)p->n * p->n;
+    }
+  }
+  h.off[L.ne] = om;
+  h.off[2 * L.ne + 1] = kk;
+  const hipStream_t s = sl.stream;
+  HIPCHK(hipMemcpyAsync(w.pwi, h.pwi, sizeof(int) * L.ne, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(w.tab, h.tab, sizeof(DevPW) * P.slots.size(), hipMemcpyHostToDevice, s));
+  if (nt) HIPCHK(hipMemcpyAsync(w.tasks, h.tasks, sizeof(RTask) * nt, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(w.pack_off, h.off, sizeof(long) * 2 * (L.ne + 1), hipMemcpyHostToDevice, s));
+  // energies: contiguous per part
+  if (o.device_ptrs) {
+    for (const Part &pt : P.parts)
+      HIPCHK(hipMemcpyAsync(w.E + pt.e0, segs[pt.seg].E + pt.e_begin, sizeof(double) * pt.m,
+                            hipMemcpyDeviceToDevice, s));
+  } else {
+    for (const Part &pt : P.parts)
+      std::memcpy(h.E + pt.e0, segs[pt.seg].E + pt.e_begin, sizeof(double) * pt.m);
+    HIPCHK(hipMemcpyAsync(w.E, h.E, sizeof(double) * L.ne, hipMemcpyHostToDevice, s));
+  }
+  HIPCHK(hipEventRecord(h.ready, s));
+  (void)want_K;
+  return RM_OK;
 }
 
 // Brackets the launches issued by `body` with events when profiling is on.
@@ -224,41 +375,48 @@ void timed(rm_ctx *ctx, int stage, long energies, hipStream_t s, F &&body) {
   ctx->prof.push_back(r);
 }
 
-void stage_R(rm_ctx *ctx, const DevPW &pw, Work &w, const Lay &L, int m, const rm_opts &o, hipStream_t s) {
+void stage_R(rm_ctx *ctx, const Plan &P, Work &w, const rm_opts &o, hipStream_t s) {
+  const Lay &L = P.L;
   const int split = o.prec == RM_FP32_SPLIT;
-  launch_dvec(s, pw, w.E, m, split, o.split_delta, w.D64, w.D32, w.win, w.status);
-  timed(ctx, 0, m, s, [&] { launch_rform(s, pw, m, split, w.D64, w.D32, w.aug, L.ldaug, L.sA); });
-  if (split) timed(ctx, 1, m, s, [&] { launch_nearpole(s, pw, w.E, m, w.win, w.aug, L.ldaug, L.sA); });
+  launch_dvec(s, L, w.tab, w.pwi, w.E, split, o.split_delta, w.D64, w.D32, w.win, w.status);
+  timed(ctx, 0, L.ne, s, [&] {
+    launch_rform(s, L, split, w.tab, w.tasks, P.ntasks, w.counter, ctx->ncu, w.D64, w.D32, w.aug);
+  });
+  if (split)
+    timed(ctx, 1, L.ne, s, [&] { launch_nearpole(s, L, P.maxtiles, w.tab, w.pwi, w.E, w.win, w.aug); });
 }
 
-void stage_asym(rm_ctx *ctx, const DevPW &pw, Work &w, const Lay &L, int m, const rm_opts &o, hipStream_t s) {
-  timed(ctx, 2, m, s, [&] {
-    launch_openlist(s, pw, w.E, m, w.nopen, w.openidx, w.openpos, w.openflag, L.ldo);
-    launch_asym(s, pw, w.E, m, o.thr_guard, w.fg, w.status);
+void stage_asym(rm_ctx *ctx, const Plan &P, Work &w, const rm_opts &o, hipStream_t s) {
+  const Lay &L = P.L;
+  timed(ctx, 2, L.ne, s, [&] {
+    launch_openlist(s, L, w.tab, w.pwi, w.E, w.nopen, w.openidx, w.openpos, w.openflag);
+    launch_asym(s, L, w.tab, w.pwi, w.E, o.thr_guard, w.fg, w.status);
   });
 }
 
-void stage_K(const DevPW &pw, Work &w, const Lay &L, int m, hipStream_t s) {
-  launch_setdims(s, m, pw.n, w.nopen, w.dims);
-  launch_build(s, pw, m, w.fg, w.nopen, w.openidx, L.ldo, w.aug, L.ldaug, L.sA, L.roff);
-  launch_lu_solve(s, m, pw.n, pw.n, w.dims, w.aug, L.ldaug, L.sA, L.roff, w.ipiv, L.ldo, w.status);
-  launch_gatherK(s, m, pw.n, w.nopen, w.openidx, L.ldo, w.aug, L.ldaug, L.sA, L.roff, w.Kw, L.ldk, L.sK);
+void stage_K(const Plan &P, Work &w, hipStream_t s) {
+  const Lay &L = P.L;
+  launch_setdims(s, L, w.tab, w.pwi, w.nopen, w.dims);
+  launch_build(s, L, w.tab, w.pwi, w.fg, w.nopen, w.openidx, w.aug);
+  launch_lu_solve(s, L.ne, L.nmax, L.nmax, w.dims, w.aug, L.ldaug, L.sA, L.roff, w.ipiv, L.ldo, w.status);
+  launch_gatherK(s, L, w.nopen, w.openidx, w.aug, w.Kw);
 }
 
-void stage_SO(const DevPW &pw, Work &w, const Lay &L, int m, bool want_S, hipStream_t s) {
+void stage_SO(const Plan &P, Work &w, bool want_S, hipStream_t s) {
   // P = 1 + K K and X = P^-1 K on the same batched LU; then XK and Omega
-  launch_gemm_sq(s, m, pw.n, w.nopen, w.Kw, L.ldk, L.sK, w.Kw, L.ldk, L.sK, w.aug, L.ldaug, L.sA);
-  launch_formP(s, m, pw.n, w.nopen, w.Kw, L.ldk, L.sK, w.aug, L.ldaug, L.sA, L.roff, w.dims);
-  launch_lu_solve(s, m, pw.n, pw.n, w.dims, w.aug, L.ldaug, L.sA, L.roff, w.ipiv, L.ldo, w.status);
-  launch_gemm_sq(s, m, pw.n, w.nopen, w.aug + L.roff, L.ldaug, L.sA, w.Kw, L.ldk, L.sK, w.XK, L.ldk, L.sK);
-  launch_omega(s, pw, m, w.openpos, L.ldo, w.nopen, w.aug + L.roff, L.ldaug, L.sA, w.XK, L.ldk, L.sK, w.omega,
-               want_S ? w.S : nullptr);
+  const Lay &L = P.L;
+  launch_gemm_sq(s, L.ne, L.nmax, w.nopen, w.Kw, L.ldk, L.sK, w.Kw, L.ldk, L.sK, w.aug, L.ldaug, L.sA);
+  launch_formP(s, L, w.nopen, w.Kw, w.aug, w.dims);
+  launch_lu_solve(s, L.ne, L.nmax, L.nmax, w.dims, w.aug, L.ldaug, L.sA, L.roff, w.ipiv, L.ldo, w.status);
+  launch_gemm_sq(s, L.ne, L.nmax, w.nopen, w.aug + L.roff, L.ldaug, L.sA, w.Kw, L.ldk, L.sK, w.XK, L.ldk, L.sK);
+  launch_omega(s, L, w.tab, w.pwi, w.openpos, w.nopen, w.aug + L.roff, w.XK, w.omega, want_S ? w.S : nullptr);
 }
 
 hipMemcpyKind kind_out(const rm_opts &o) { return o.device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost; }
 hipMemcpyKind kind_in(const rm_opts &o) { return o.device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice; }
 
-rm_status get_pw(rm_ctx *ctx, int32_t id, DevPW **out) {
+rm_status get_pw(rm_ctx *ctx, int32_t id, const DevPW **out) {
+  std::lock_guard<std::mutex> g(ctx->mu);
   auto it = ctx->pws.find(id);
   if (it == ctx->pws.end()) {
     ctx->err = "unknown partial wave id";
@@ -281,49 +439,248 @@ hipStream_t call_stream(rm_ctx *ctx, const rm_opts &o) {
   return (o.device_ptrs && o.stream) ? (hipStream_t)o.stream : ctx->stream;
 }
 
-size_t sync_share(rm_ctx *ctx) {
+// Budget available to `sl` (its own workspace counts as available).
+size_t free_share(rm_ctx *ctx, const Slot &sl) {
   std::lock_guard<std::mutex> g(ctx->mu);
-  const size_t used = ctx->resident + ctx->work_bytes - ctx->work.bytes;
+  const size_t used = ctx->resident + ctx->work_bytes - sl.w.bytes;
   return ctx->budget > used ? ctx->budget - used : 0;
 }
 
-// Which stages a fused chunk runs and where its results go.
-struct ChunkOut {
-  double *omega = nullptr;   // [m][nt][nt]
-  double *K = nullptr;       // [m][n][n]
-  int32_t *status = nullptr; // [m]
-};
+// Builds the plan for parts already chosen (slots assigned here).
+void finish_plan(Plan &P, const std::vector<Seg> &segs, int ne) {
+  std::vector<const DevPW *> slots;
+  for (Part &pt : P.parts) {
+    const DevPW *p = segs[pt.seg].pw;
+    int s = -1;
+    for (size_t i = 0; i < slots.size(); ++i)
+      if (slots[i] == p) s = (int)i;
+    if (s < 0) {
+      s = (int)slots.size();
+      slots.push_back(p);
+    }
+    pt.slot = s;
+  }
+  P.slots = slots;
+  P.L = make_layout(slots, ne);
+  P.maxtiles = 0;
+  for (const DevPW *p : slots) {
+    const int tl = p->npad / TILE;
+    P.maxtiles = std::max(P.maxtiles, tl * (tl + 1) / 2);
+  }
+}
 
-// Runs all stages for energies already in w.E and copies the results out.
-// before_R / after_R (optional) order the R contraction against other streams.
-rm_status run_chunk(rm_ctx *ctx, const DevPW &pw, Work &w, int m, const rm_opts &o, hipStream_t s,
-                    const ChunkOut &out, hipMemcpyKind ko, hipEvent_t before_R = nullptr,
-                    hipEvent_t after_R = nullptr) {
-  const Lay L = layout(pw, w);
-  HIPCHK(hipMemsetAsync(w.status, 0, sizeof(int) * m, s));
+int plan_tasks(const Plan &P) {
+  int nt = 0;
+  for (const Part &pt : P.parts) {
+    const int tl = P.slots[pt.slot]->npad / TILE;
+    nt += (pt.m + EB - 1) / EB * (tl * (tl + 1) / 2);
+  }
+  return nt;
+}
+
+// Runs every stage of a planned chunk (inputs already uploaded) and copies
+// each part's results to its segment.  before_R / after_R (optional) order the
+// R contraction against other streams.
+rm_status run_chunk(rm_ctx *ctx, const Plan &P, Slot &sl, const std::vector<Seg> &segs, const rm_opts &o,
+                    hipMemcpyKind ko, hipEvent_t before_R = nullptr, hipEvent_t after_R = nullptr) {
+  const Lay &L = P.L;
+  Work &w = sl.w;
+  const hipStream_t s = sl.stream;
+  HIPCHK(hipMemsetAsync(w.status, 0, sizeof(int) * L.ne, s));
+  stage_asym(ctx, P, w, o, s);
   if (before_R) HIPCHK(hipStreamWaitEvent(s, before_R, 0));
-  stage_R(ctx, pw, w, L, m, o, s);
+  stage_R(ctx, P, w, o, s);
   if (after_R) HIPCHK(hipEventRecord(after_R, s));
-  stage_asym(ctx, pw, w, L, m, o, s);
-  timed(ctx, 3, m, s, [&] { stage_K(pw, w, L, m, s); });
-  timed(ctx, 4, m, s, [&] { stage_SO(pw, w, L, m, false, s); });
-  launch_finalize(s, m, pw.n, pw.nt, w.status, w.omega, w.Kw, L.ldk, L.sK, nullptr);
-  HIPCHK(hipMemcpyAsync(out.omega, w.omega, sizeof(double) * m * pw.nt * pw.nt, ko, s));
-  if (out.K)
-    HIPCHK(hipMemcpy2DAsync(out.K, sizeof(double) * pw.n, w.Kw, sizeof(double) * L.ldk, sizeof(double) * pw.n,
-                            (size_t)m * pw.n, ko, s));
-  HIPCHK(hipMemcpyAsync(out.status, w.status, sizeof(int) * m, ko, s));
+  timed(ctx, 3, L.ne, s, [&] { stage_K(P, w, s); });
+  timed(ctx, 4, L.ne, s, [&] { stage_SO(P, w, false, s); });
+  launch_finalize(s, L, w.tab, w.pwi, w.status, w.omega, w.Kw, nullptr);
+  bool want_K = false;
+  for (const Part &pt : P.parts) want_K |= segs[pt.seg].K != nullptr;
+  launch_pack(s, L, w.tab, w.pwi, 0, w.omega, w.pack_off, w.pack);
+  for (const Part &pt : P.parts) {
+    const Seg &g = segs[pt.seg];
+    const long o0 = sl.h.off[pt.e0], o1 = sl.h.off[pt.e0 + pt.m - 1] + (long)g.pw->nt * g.pw->nt;
+    HIPCHK(hipMemcpyAsync(g.omega + (size_t)pt.e_begin * g.pw->nt * g.pw->nt, w.pack + o0, sizeof(double) * (o1 - o0),
+                          ko, s));
+    HIPCHK(hipMemcpyAsync(g.status + pt.e_begin, w.status + pt.e0, sizeof(int) * pt.m, ko, s));
+  }
+  if (want_K) {
+    launch_pack(s, L, w.tab, w.pwi, 1, w.Kw, w.pack_off + L.ne + 1, w.pack);
+    for (const Part &pt : P.parts) {
+      const Seg &g = segs[pt.seg];
+      if (!g.K) continue;
+      const long o0 = sl.h.off[L.ne + 1 + pt.e0], o1 = o0 + (long)pt.m * g.pw->n * g.pw->n;
+      HIPCHK(hipMemcpyAsync(g.K + (size_t)pt.e_begin * g.pw->n * g.pw->n, w.pack + o0, sizeof(double) * (o1 - o0), ko,
+                            s));
+    }
+  }
   HIPCHK(hipGetLastError());
   return RM_OK;
 }
 
+// Cuts the segments into chunks of at most `cap` energies.  With `interleave`
+// every chunk takes up to EB energies from each segment in turn, so a chunk
+// holds many partial waves (one persistent R launch serves them all);
+// otherwise segments are cut in order.
+std::vector<Plan> cut_chunks(const std::vector<Seg> &segs, int cap, bool interleave) {
+  std::vector<Plan> plans;
+  std::vector<int> pos(segs.size(), 0);
+  size_t left = 0;
+  for (const Seg &g : segs) left += g.ne;
+  size_t cur = 0;
+  while (left > 0) {
+    Plan P;
+    int ne = 0;
+    if (interleave) {
+      bool progress = true;
+      while (ne < cap && progress) {
+        progress = false;
+        for (size_t g = 0; g < segs.size() && ne < cap; ++g) {
+          const int take = std::min({EB, segs[g].ne - pos[g], cap - ne});
+          if (take <= 0) continue;
+          if (!P.parts.empty() && P.parts.back().seg == (int)g && P.parts.back().e_begin + P.parts.back().m == pos[g])
+            P.parts.back().m += take;
+          else
+            P.parts.push_back(Part{(int)g, pos[g], take, ne, 0});
+          pos[g] += take;
+          ne += take;
+          progress = true;
+        }
+      }
+      // keep each segment's energies of this chunk contiguous: merge its parts
+      std::vector<Part> merged;
+      for (size_t g = 0; g < segs.size(); ++g) {
+        int first = -1, total = 0;
+        for (const Part &pt : P.parts)
+          if (pt.seg == (int)g) {
+            if (first < 0) first = pt.e_begin;
+            total += pt.m;
+          }
+        if (total) merged.push_back(Part{(int)g, first, total, 0, 0});
+      }
+      int e0 = 0;
+      for (Part &pt : merged) {
+        pt.e0 = e0;
+        e0 += pt.m;
+      }
+      P.parts = merged;
+    } else {
+      while (ne < cap && cur < segs.size()) {
+        const int take = std::min(segs[cur].ne - pos[cur], cap - ne);
+        if (take > 0) {
+          P.parts.push_back(Part{(int)cur, pos[cur], take, ne, 0});
+          pos[cur] += take;
+          ne += take;
+        }
+        if (pos[cur] >= segs[cur].ne) ++cur;
+      }
+    }
+    left -= ne;
+    finish_plan(P, segs, ne);
+    plans.push_back(std::move(P));
+  }
+  return plans;
+}
+
+// The pipelined executor behind rm_run and rm_run_batch.
+rm_status run_segments(rm_ctx *ctx, const std::vector<Seg> &segs, const rm_opts &o, bool interleave) {
+  const hipStream_t user = call_stream(ctx, o);
+  if (!ctx->ev_in) {
+    HIPCHK(hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
+    for (int i = 0; i < 2; ++i) {
+      HIPCHK(hipEventCreateWithFlags(&ctx->ev_out[i], hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&ctx->ev_R[i], hipEventDisableTiming));
+      HIPCHK(hipStreamCreateWithFlags(&ctx->pipe[i].stream, hipStreamNonBlocking));
+    }
+  }
+  size_t total = 0;
+  int n = 0, npad = 0, Mpad = 0, nt = 0;
+  for (const Seg &g : segs) {
+    total += g.ne;
+    n = std::max(n, g.pw->n);
+    npad = std::max(npad, g.pw->npad);
+    Mpad = std::max(Mpad, g.pw->Mpad);
+    nt = std::max(nt, g.pw->nt);
+  }
+  if (!total) return RM_OK;
+  size_t share;
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    const size_t used = ctx->resident + ctx->work_bytes - ctx->pipe[0].w.bytes - ctx->pipe[1].w.bytes;
+    share = ctx->budget > used ? (ctx->budget - used) / 2 : 0;
+  }
+  // Chunks of up to 256 energies (1024 for interleaved batches) alternate over the
+  // two streams.  The LU panel runs one workgroup per energy, so its cost grows
+  // with the number of chunks rather than with their size.
+  int cap = chunk_cap(n, npad, Mpad, nt, share, interleave ? MAX_CHUNK : 256);
+  if (!interleave && total > (size_t)2 * EB && (size_t)cap * 2 > total)
+    cap = std::max(EB, (int)((total + 2 * EB - 1) / (2 * EB) * EB));
+  std::vector<Plan> plans = cut_chunks(segs, cap, interleave);
+  const int nuse = plans.size() > 1 ? 2 : 1;
+  HIPCHK(hipEventRecord(ctx->ev_in, user));
+  for (int i = 0; i < nuse; ++i) HIPCHK(hipStreamWaitEvent(ctx->pipe[i].stream, ctx->ev_in, 0));
+  for (size_t k = 0; k < plans.size(); ++k) {
+    Slot &sl = ctx->pipe[k % nuse];
+    Plan &P = plans[k];
+    if (rm_status st = ensure_slot(ctx, sl, P.L, (int)P.slots.size(), plan_tasks(P), false)) return st;
+    if (rm_status st = upload_plan(ctx, sl, P, segs, o, false)) return st;
+    hipEvent_t prevR = k > 0 && nuse > 1 ? ctx->ev_R[(k - 1) % 2] : nullptr;
+    if (rm_status st = run_chunk(ctx, P, sl, segs, o, kind_out(o), prevR, ctx->ev_R[k % 2])) return st;
+  }
+  for (int i = 0; i < nuse; ++i) {
+    HIPCHK(hipEventRecord(ctx->ev_out[i], ctx->pipe[i].stream));
+    HIPCHK(hipStreamWaitEvent(user, ctx->ev_out[i], 0));
+  }
+  if (!o.device_ptrs) HIPCHK(hipStreamSynchronize(user));
+  return RM_OK;
+}
+
+// Plans one chunk of one partial wave for the staged calls (on ctx->sync).
+rm_status staged_chunk(rm_ctx *ctx, const DevPW *pw, const double *E, int e0, int m, const rm_opts &o, bool want_S,
+                       Plan &P, std::vector<Seg> &segs) {
+  segs.assign(1, Seg{pw, E, e0 + m, nullptr, nullptr, nullptr});
+  P = Plan();
+  P.parts.push_back(Part{0, e0, m, 0, 0});
+  finish_plan(P, segs, m);
+  if (rm_status st = ensure_slot(ctx, ctx->sync, P.L, 1, plan_tasks(P), want_S)) return st;
+  return upload_plan(ctx, ctx->sync, P, segs, o, false);
+}
+
+int staged_cap(rm_ctx *ctx, const DevPW *pw, int ne) {
+  return chunk_cap(pw->n, pw->npad, pw->Mpad, pw->nt, free_share(ctx, ctx->sync), std::min(ne, 256));
+}
+
+// The staged calls run on ctx->sync.stream; with device pointers it is ordered
+// after the caller's stream on entry and the caller's stream after it on exit.
+rm_status staged_enter(rm_ctx *ctx, const rm_opts &o, hipEvent_t &ev) {
+  if (!ctx->sync.stream) HIPCHK(hipStreamCreateWithFlags(&ctx->sync.stream, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(ev, call_stream(ctx, o)));
+  HIPCHK(hipStreamWaitEvent(ctx->sync.stream, ev, 0));
+  return RM_OK;
+}
+
+rm_status staged_leave(rm_ctx *ctx, const rm_opts &o, hipEvent_t ev) {
+  HIPCHK(hipEventRecord(ev, ctx->sync.stream));
+  HIPCHK(hipStreamWaitEvent(call_stream(ctx, o), ev, 0));
+  if (!o.device_ptrs) HIPCHK(hipStreamSynchronize(ctx->sync.stream));
+  HIPCHK(hipEventDestroy(ev));
+  return RM_OK;
+}
+
 // ------------------------------------------------------------------ serving
+// A worker forms a chunk from the queued requests (continuous batching): it
+// takes energies from every active request with work left, earliest arrival
+// first, up to the chunk capacity, runs the chunk on its own stream, and hands
+// the results back per request.  Requests that arrive while chunks run join
+// the next chunk a worker forms.
 void worker_main(rm_ctx *ctx, Slot *slot) {
   (void)hipSetDevice(ctx->device);
   for (;;) {
-    Req *r = nullptr;
-    int e0 = 0, m = 0;
-    DevPW pw;
+    std::vector<Seg> segs;
+    std::vector<Req *> owners;
+    Plan P;
+    rm_opts o;
     {
       std::unique_lock<std::mutex> lk(ctx->mu);
       ctx->cv.wait(lk, [&] {
@@ -333,61 +690,102 @@ void worker_main(rm_ctx *ctx, Slot *slot) {
         return false;
       });
       if (ctx->stop) return;
-      // continuous batching: the earliest request with work left that has the
-      // fewest chunks in flight gets the free slot, so a newly arrived request
-      // starts on the next free slot while longer ones keep progressing
-      Req *best = nullptr;
+      // the precision of the earliest request with work decides the chunk's
+      const Req *first = nullptr;
       for (Req *q : ctx->active)
-        if (q->next_e < q->rq.ne && (!best || q->inflight < best->inflight)) best = q;
-      r = best;
-      auto it = ctx->pws.find(r->rq.pw_id);
-      if (it == ctx->pws.end()) {
-        r->err = RM_E_NOTFOUND;
-        r->next_e = r->done_e = r->rq.ne;
-        r->st.t_done_ns = now_ns();
-        ctx->cv.notify_all();
-        continue;
-      }
-      pw = it->second;
-      const size_t used = ctx->resident + ctx->work_bytes - slot->w.bytes;
-      const size_t share = ctx->budget > used ? (ctx->budget - used) / 1 : 0;
-      const int nslots = (int)ctx->slots.size();
-      const int cap = chunk_cap(pw, share / std::max(1, nslots - 0), r->rq.ne - r->next_e);
-      e0 = r->next_e;
-      m = std::min(cap, r->rq.ne - e0);
-      r->next_e += m;
-      r->inflight++;
-      if (!r->admitted) {
-        r->admitted = true;
-        r->st.t_admit_ns = now_ns();
-      }
-      if (!r->st.t_start_ns) r->st.t_start_ns = now_ns();
-      r->st.nblocks++;
-    }
-    rm_ctx *c = ctx;
-    rm_status st = ensure_work(c, slot->w, pw, m, false);
-    if (st == RM_OK) {
-      const hipStream_t s = slot->stream;
-      rm_opts o = fixed_opts(&r->rq.opts);
+        if (q->next_e < q->rq.ne) {
+          first = q;
+          break;
+        }
+      o = fixed_opts(&first->rq.opts);
       o.device_ptrs = 0;
-      ChunkOut out;
-      out.omega = r->rq.omega + (size_t)e0 * pw.nt * pw.nt;
-      out.K = r->rq.K ? r->rq.K + (size_t)e0 * pw.n * pw.n : nullptr;
-      out.status = r->rq.status + e0;
-      if (hipMemcpyAsync(slot->w.E, r->E.data() + e0, sizeof(double) * m, hipMemcpyHostToDevice, s) != hipSuccess)
-        st = RM_E_DEVICE;
-      if (st == RM_OK) st = run_chunk(c, pw, slot->w, m, o, s, out, hipMemcpyDeviceToHost);
-      if (st == RM_OK && hipStreamSynchronize(s) != hipSuccess) st = RM_E_DEVICE;
+      o.stream = nullptr;
+      // largest member shapes decide the per-energy footprint
+      const size_t used = ctx->resident + ctx->work_bytes - slot->w.bytes;
+      const size_t share = (ctx->budget > used ? ctx->budget - used : 0) / std::max<size_t>(ctx->slots.size(), 1);
+      int n = 0, npad = 0, Mpad = 0, nt = 0;
+      for (Req *q : ctx->active) {
+        if (q->next_e >= q->rq.ne || fixed_opts(&q->rq.opts).prec != o.prec) continue;
+        auto it = ctx->pws.find(q->rq.pw_id);
+        if (it == ctx->pws.end()) continue;
+        n = std::max(n, it->second.n);
+        npad = std::max(npad, it->second.npad);
+        Mpad = std::max(Mpad, it->second.Mpad);
+        nt = std::max(nt, it->second.nt);
+      }
+      int room = n ? chunk_cap(n, npad, Mpad, nt, share, 256) : 0;
+      for (Req *q : ctx->active) {
+        if (room <= 0) break;
+        if (q->next_e >= q->rq.ne || fixed_opts(&q->rq.opts).prec != o.prec) continue;
+        auto it = ctx->pws.find(q->rq.pw_id);
+        if (it == ctx->pws.end()) {
+          q->err = RM_E_NOTFOUND;
+          q->done_e = q->next_e = q->rq.ne;
+          q->st.t_done_ns = now_ns();
+          continue;
+        }
+        const int take = std::min(room, q->rq.ne - q->next_e);
+        Seg g;
+        g.pw = &it->second;
+        g.E = q->E.data();
+        g.ne = q->rq.ne;
+        g.omega = q->rq.omega;
+        g.K = q->rq.K;
+        g.status = q->rq.status;
+        P.parts.push_back(Part{(int)segs.size(), q->next_e, take, 0, 0});
+        segs.push_back(g);
+        owners.push_back(q);
+        q->next_e += take;
+        q->inflight++;
+        room -= take;
+        const int64_t t = now_ns();
+        if (!q->admitted) {
+          q->admitted = true;
+          q->st.t_admit_ns = t;
+        }
+        if (!q->st.t_start_ns) q->st.t_start_ns = t;
+        q->st.nblocks++;
+      }
+      ctx->cv.notify_all();
     }
+    if (P.parts.empty()) continue;
+    int ne = 0;
+    for (Part &pt : P.parts) {
+      pt.e0 = ne;
+      ne += pt.m;
+    }
+    finish_plan(P, segs, ne);
+    rm_status st = ensure_slot(ctx, *slot, P.L, (int)P.slots.size(), plan_tasks(P), false);
+    if (st == RM_OK) st = upload_plan(ctx, *slot, P, segs, o, false);
+    if (st == RM_OK) st = run_chunk(ctx, P, *slot, segs, o, hipMemcpyDeviceToHost);
+    if (st == RM_OK && hipStreamSynchronize(slot->stream) != hipSuccess) st = RM_E_DEVICE;
     {
       std::lock_guard<std::mutex> lk(ctx->mu);
-      r->inflight--;
-      r->done_e += m;
-      if (st != RM_OK) r->err = st;
-      if (r->done_e >= r->rq.ne) r->st.t_done_ns = now_ns();
+      for (size_t i = 0; i < owners.size(); ++i) {
+        Req *r = owners[i];
+        r->inflight--;
+        r->done_e += P.parts[i].m;
+        if (st != RM_OK) r->err = st;
+        if (r->done_e >= r->rq.ne) r->st.t_done_ns = now_ns();
+      }
       ctx->cv.notify_all();
     }
   }
+}
+
+void free_pw(DevPW &p) {
+  void *ptrs[] = {p.W64, p.W32, p.Ek, p.ethr, p.l, p.target, p.tptr, p.tch};
+  for (void *q : ptrs)
+    if (q) (void)hipFree(q);
+}
+
+void destroy_slot(Slot &sl) {
+  if (sl.stream) {
+    (void)hipStreamSynchronize(sl.stream);
+    (void)hipStreamDestroy(sl.stream);
+  }
+  free_work(sl.w);
+  free_staging(sl.h);
 }
 
 }  // namespace
@@ -410,10 +808,14 @@ rm_status rm_create(int device, size_t hbm_budget_bytes, rm_ctx **out) {
   rm_ctx *ctx = new (std::nothrow) rm_ctx();
   if (!ctx) return RM_E_NOMEM;
   ctx->device = device;
-  if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+  if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&ctx->sync.stream, hipStreamNonBlocking) != hipSuccess) {
     delete ctx;
     return RM_E_DEVICE;
   }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+    ctx->ncu = prop.multiProcessorCount;
   size_t fr = 0, tot = 0;
   if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
     delete ctx;
@@ -443,31 +845,16 @@ rm_status rm_destroy(rm_ctx *ctx) {
   }
   for (auto &t : ctx->workers) t.join();
   (void)hipSetDevice(ctx->device);
-  for (auto &sl : ctx->slots) {
-    (void)hipStreamSynchronize(sl->stream);
-    free_work(sl->w);
-    (void)hipStreamDestroy(sl->stream);
-  }
-  (void)hipStreamSynchronize(ctx->stream);
-  free_work(ctx->work);
-  for (auto &pp : ctx->pipe) {
-    if (pp.stream) {
-      (void)hipStreamSynchronize(pp.stream);
-      (void)hipStreamDestroy(pp.stream);
-    }
-    free_work(pp.w);
-  }
+  for (auto &sl : ctx->slots) destroy_slot(*sl);
+  destroy_slot(ctx->sync);
+  for (auto &pp : ctx->pipe) destroy_slot(pp);
   if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
   for (auto &ev : ctx->ev_out)
     if (ev) (void)hipEventDestroy(ev);
   for (auto &ev : ctx->ev_R)
     if (ev) (void)hipEventDestroy(ev);
-  for (auto &kv : ctx->pws) {
-    DevPW &p = kv.second;
-    void *ptrs[] = {p.W64, p.W32, p.Ek, p.ethr, p.l, p.target, p.tptr, p.tch};
-    for (void *q : ptrs)
-      if (q) (void)hipFree(q);
-  }
+  for (auto &kv : ctx->pws) free_pw(kv.second);
+  (void)hipStreamSynchronize(ctx->stream);
   (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return RM_OK;
@@ -565,16 +952,14 @@ rm_status rm_pw_release(rm_ctx *ctx, int32_t pw_id) {
   auto it = ctx->pws.find(pw_id);
   if (it == ctx->pws.end()) return RM_E_NOTFOUND;
   for (Req *q : ctx->active)
-    if (q->rq.pw_id == pw_id && q->done_e < q->rq.ne) return RM_E_BUSY;
+    if (q->rq.pw_id == pw_id && (q->done_e < q->rq.ne || q->inflight > 0)) return RM_E_BUSY;
   DevPW p = it->second;
   ctx->pws.erase(it);
   ctx->resident -= p.bytes;
   lk.unlock();
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
-  void *ptrs[] = {p.W64, p.W32, p.Ek, p.ethr, p.l, p.target, p.tptr, p.tch};
-  for (void *q : ptrs)
-    if (q) (void)hipFree(q);
+  free_pw(p);
   return RM_OK;
 }
 
@@ -582,186 +967,159 @@ rm_status rm_form_R(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, cons
                     int32_t *status) {
   if (!ctx || (ne > 0 && (!E || !R || !status)) || ne < 0) return RM_E_ARG;
   if (ne == 0) return RM_OK;
-  DevPW *pw;
+  const DevPW *pw;
   if (rm_status st = get_pw(ctx, pwid, &pw)) return st;
   (void)hipSetDevice(ctx->device);
   const rm_opts o = fixed_opts(opts);
-  const hipStream_t s = call_stream(ctx, o);
-  const int cap = chunk_cap(*pw, sync_share(ctx), ne);
-  if (rm_status st = ensure_work(ctx, ctx->work, *pw, cap, false)) return st;
-  Work &w = ctx->work;
-  const Lay L = layout(*pw, w);
+  hipEvent_t ev;
+  if (rm_status st = staged_enter(ctx, o, ev)) return st;
+  const hipStream_t s = ctx->sync.stream;
+  const int cap = staged_cap(ctx, pw, ne);
   for (int e0 = 0; e0 < ne; e0 += cap) {
     const int m = std::min(cap, ne - e0);
-    HIPCHK(hipMemcpyAsync(w.E, E + e0, sizeof(double) * m, kind_in(o), s));
+    Plan P;
+    std::vector<Seg> segs;
+    if (rm_status st = staged_chunk(ctx, pw, E, e0, m, o, false, P, segs)) return st;
+    Work &w = ctx->sync.w;
     HIPCHK(hipMemsetAsync(w.status, 0, sizeof(int) * m, s));
-    stage_R(ctx, *pw, w, L, m, o, s);
-    launch_nanfill_R(s, m, pw->n, w.status, w.aug, L.ldaug, L.sA);
+    stage_R(ctx, P, w, o, s);
+    launch_nanfill_R(s, P.L, w.tab, w.pwi, w.status, w.aug);
     HIPCHK(hipMemcpy2DAsync(R + (size_t)e0 * pw->n * pw->n, sizeof(double) * pw->n, w.aug,
-                            sizeof(double) * L.ldaug, sizeof(double) * pw->n, (size_t)m * pw->n, kind_out(o), s));
+                            sizeof(double) * P.L.ldaug, sizeof(double) * pw->n, (size_t)m * pw->n, kind_out(o), s));
     HIPCHK(hipMemcpyAsync(status + e0, w.status, sizeof(int) * m, kind_out(o), s));
     HIPCHK(hipGetLastError());
   }
-  if (!o.device_ptrs) HIPCHK(hipStreamSynchronize(s));
-  return RM_OK;
+  return staged_leave(ctx, o, ev);
 }
 
 rm_status rm_asymptotic(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, const rm_opts *opts, double *fg,
                         int8_t *open, int32_t *nopen, int32_t *status) {
   if (!ctx || ne < 0 || (ne > 0 && (!E || !fg || !open || !nopen || !status))) return RM_E_ARG;
   if (ne == 0) return RM_OK;
-  DevPW *pw;
+  const DevPW *pw;
   if (rm_status st = get_pw(ctx, pwid, &pw)) return st;
   (void)hipSetDevice(ctx->device);
   const rm_opts o = fixed_opts(opts);
-  const hipStream_t s = call_stream(ctx, o);
-  const int cap = chunk_cap(*pw, sync_share(ctx), ne);
-  if (rm_status st = ensure_work(ctx, ctx->work, *pw, cap, false)) return st;
-  Work &w = ctx->work;
-  const Lay L = layout(*pw, w);
+  hipEvent_t ev;
+  if (rm_status st = staged_enter(ctx, o, ev)) return st;
+  const hipStream_t s = ctx->sync.stream;
+  const int cap = staged_cap(ctx, pw, ne);
   const int n = pw->n;
   for (int e0 = 0; e0 < ne; e0 += cap) {
     const int m = std::min(cap, ne - e0);
-    HIPCHK(hipMemcpyAsync(w.E, E + e0, sizeof(double) * m, kind_in(o), s));
+    Plan P;
+    std::vector<Seg> segs;
+    if (rm_status st = staged_chunk(ctx, pw, E, e0, m, o, false, P, segs)) return st;
+    Work &w = ctx->sync.w;
     HIPCHK(hipMemsetAsync(w.status, 0, sizeof(int) * m, s));
-    stage_asym(ctx, *pw, w, L, m, o, s);
+    stage_asym(ctx, P, w, o, s);
     HIPCHK(hipMemcpyAsync(fg + (size_t)e0 * n * 4, w.fg, sizeof(double) * m * n * 4, kind_out(o), s));
     HIPCHK(hipMemcpyAsync(open + (size_t)e0 * n, w.openflag, (size_t)m * n, kind_out(o), s));
     HIPCHK(hipMemcpyAsync(nopen + e0, w.nopen, sizeof(int) * m, kind_out(o), s));
     HIPCHK(hipMemcpyAsync(status + e0, w.status, sizeof(int) * m, kind_out(o), s));
     HIPCHK(hipGetLastError());
   }
-  if (!o.device_ptrs) HIPCHK(hipStreamSynchronize(s));
-  return RM_OK;
+  return staged_leave(ctx, o, ev);
 }
 
 rm_status rm_solve_K(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, const double *R, const double *fg,
                      const rm_opts *opts, double *K, int32_t *status) {
   if (!ctx || ne < 0 || (ne > 0 && (!E || !R || !fg || !K || !status))) return RM_E_ARG;
   if (ne == 0) return RM_OK;
-  DevPW *pw;
+  const DevPW *pw;
   if (rm_status st = get_pw(ctx, pwid, &pw)) return st;
   (void)hipSetDevice(ctx->device);
   const rm_opts o = fixed_opts(opts);
-  const hipStream_t s = call_stream(ctx, o);
-  const int cap = chunk_cap(*pw, sync_share(ctx), ne);
-  if (rm_status st = ensure_work(ctx, ctx->work, *pw, cap, false)) return st;
-  Work &w = ctx->work;
-  const Lay L = layout(*pw, w);
+  hipEvent_t ev;
+  if (rm_status st = staged_enter(ctx, o, ev)) return st;
+  const hipStream_t s = ctx->sync.stream;
+  const int cap = staged_cap(ctx, pw, ne);
   const int n = pw->n;
   for (int e0 = 0; e0 < ne; e0 += cap) {
     const int m = std::min(cap, ne - e0);
-    HIPCHK(hipMemcpyAsync(w.E, E + e0, sizeof(double) * m, kind_in(o), s));
+    Plan P;
+    std::vector<Seg> segs;
+    if (rm_status st = staged_chunk(ctx, pw, E, e0, m, o, false, P, segs)) return st;
+    Work &w = ctx->sync.w;
+    const Lay &L = P.L;
     HIPCHK(hipMemsetAsync(w.status, 0, sizeof(int) * m, s));
     HIPCHK(hipMemcpy2DAsync(w.aug, sizeof(double) * L.ldaug, R + (size_t)e0 * n * n, sizeof(double) * n,
                             sizeof(double) * n, (size_t)m * n, kind_in(o), s));
     HIPCHK(hipMemcpyAsync(w.fg, fg + (size_t)e0 * n * 4, sizeof(double) * m * n * 4, kind_in(o), s));
-    launch_dvec(s, *pw, w.E, m, 0, 0.0, w.D64, w.D32, w.win, w.status);  // pole flags
-    launch_openlist(s, *pw, w.E, m, w.nopen, w.openidx, w.openpos, w.openflag, L.ldo);
-    launch_check_inputs(s, m, n, w.E, pw->ethr, o.thr_guard, w.aug, L.ldaug, L.sA, w.fg, nullptr, 0, 0, w.nopen,
-                        w.status);
-    stage_K(*pw, w, L, m, s);
-    launch_finalize(s, m, n, 0, w.status, nullptr, w.Kw, L.ldk, L.sK, nullptr);
+    launch_dvec(s, L, w.tab, w.pwi, w.E, 0, 0.0, w.D64, w.D32, w.win, w.status);  // pole flags
+    launch_openlist(s, L, w.tab, w.pwi, w.E, w.nopen, w.openidx, w.openpos, w.openflag);
+    launch_check_inputs(s, L, w.tab, w.pwi, w.E, o.thr_guard, w.aug, w.fg, nullptr, w.nopen, w.status);
+    stage_K(P, w, s);
+    launch_finalize(s, L, w.tab, w.pwi, w.status, nullptr, w.Kw, nullptr);
     HIPCHK(hipMemcpy2DAsync(K + (size_t)e0 * n * n, sizeof(double) * n, w.Kw, sizeof(double) * L.ldk,
                             sizeof(double) * n, (size_t)m * n, kind_out(o), s));
     HIPCHK(hipMemcpyAsync(status + e0, w.status, sizeof(int) * m, kind_out(o), s));
     HIPCHK(hipGetLastError());
   }
-  if (!o.device_ptrs) HIPCHK(hipStreamSynchronize(s));
-  return RM_OK;
+  return staged_leave(ctx, o, ev);
 }
 
 rm_status rm_collision_strengths(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, const double *K,
                                  const rm_opts *opts, double *omega, double *S, int32_t *status) {
   if (!ctx || ne < 0 || (ne > 0 && (!E || !K || !omega || !status))) return RM_E_ARG;
   if (ne == 0) return RM_OK;
-  DevPW *pw;
+  const DevPW *pw;
   if (rm_status st = get_pw(ctx, pwid, &pw)) return st;
   (void)hipSetDevice(ctx->device);
   const rm_opts o = fixed_opts(opts);
-  const hipStream_t s = call_stream(ctx, o);
-  const int cap = chunk_cap(*pw, sync_share(ctx), ne);
-  if (rm_status st = ensure_work(ctx, ctx->work, *pw, cap, S != nullptr)) return st;
-  Work &w = ctx->work;
-  const Lay L = layout(*pw, w);
+  hipEvent_t ev;
+  if (rm_status st = staged_enter(ctx, o, ev)) return st;
+  const hipStream_t s = ctx->sync.stream;
+  const int cap = staged_cap(ctx, pw, ne);
   const int n = pw->n, nt = pw->nt;
   for (int e0 = 0; e0 < ne; e0 += cap) {
     const int m = std::min(cap, ne - e0);
-    HIPCHK(hipMemcpyAsync(w.E, E + e0, sizeof(double) * m, kind_in(o), s));
+    Plan P;
+    std::vector<Seg> segs;
+    if (rm_status st = staged_chunk(ctx, pw, E, e0, m, o, S != nullptr, P, segs)) return st;
+    Work &w = ctx->sync.w;
+    const Lay &L = P.L;
     HIPCHK(hipMemsetAsync(w.status, 0, sizeof(int) * m, s));
     HIPCHK(hipMemcpy2DAsync(w.Kw, sizeof(double) * L.ldk, K + (size_t)e0 * n * n, sizeof(double) * n,
                             sizeof(double) * n, (size_t)m * n, kind_in(o), s));
-    launch_openlist(s, *pw, w.E, m, w.nopen, w.openidx, w.openpos, w.openflag, L.ldo);
-    launch_check_inputs(s, m, n, w.E, pw->ethr, o.thr_guard, nullptr, 0, 0, nullptr, w.Kw, L.ldk, L.sK, w.nopen,
-                        w.status);
-    stage_SO(*pw, w, L, m, S != nullptr, s);
-    launch_finalize(s, m, n, nt, w.status, w.omega, nullptr, 0, 0, S ? w.S : nullptr);
+    launch_openlist(s, L, w.tab, w.pwi, w.E, w.nopen, w.openidx, w.openpos, w.openflag);
+    launch_check_inputs(s, L, w.tab, w.pwi, w.E, o.thr_guard, nullptr, nullptr, w.Kw, w.nopen, w.status);
+    stage_SO(P, w, S != nullptr, s);
+    launch_finalize(s, L, w.tab, w.pwi, w.status, w.omega, nullptr, S ? w.S : nullptr);
     HIPCHK(hipMemcpyAsync(omega + (size_t)e0 * nt * nt, w.omega, sizeof(double) * m * nt * nt, kind_out(o), s));
     if (S) HIPCHK(hipMemcpyAsync(S + (size_t)e0 * n * n * 2, w.S, sizeof(double) * m * n * n * 2, kind_out(o), s));
     HIPCHK(hipMemcpyAsync(status + e0, w.status, sizeof(int) * m, kind_out(o), s));
     HIPCHK(hipGetLastError());
   }
-  if (!o.device_ptrs) HIPCHK(hipStreamSynchronize(s));
-  return RM_OK;
+  return staged_leave(ctx, o, ev);
 }
 
 rm_status rm_run(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, const rm_opts *opts, double *omega,
                  double *K, int32_t *status) {
   if (!ctx || ne < 0 || (ne > 0 && (!E || !omega || !status))) return RM_E_ARG;
   if (ne == 0) return RM_OK;
-  DevPW *pw;
+  const DevPW *pw;
   if (rm_status st = get_pw(ctx, pwid, &pw)) return st;
   (void)hipSetDevice(ctx->device);
   const rm_opts o = fixed_opts(opts);
-  const hipStream_t user = call_stream(ctx, o);
-  if (!ctx->ev_in) {
-    HIPCHK(hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
-    for (int i = 0; i < 2; ++i) {
-      HIPCHK(hipEventCreateWithFlags(&ctx->ev_out[i], hipEventDisableTiming));
-      HIPCHK(hipEventCreateWithFlags(&ctx->ev_R[i], hipEventDisableTiming));
-      HIPCHK(hipStreamCreateWithFlags(&ctx->pipe[i].stream, hipStreamNonBlocking));
-    }
+  std::vector<Seg> segs(1, Seg{pw, E, ne, omega, K, status});
+  return run_segments(ctx, segs, o, false);
+}
+
+rm_status rm_run_batch(rm_ctx *ctx, const rm_batch_item *items, int32_t nitems, const rm_opts *opts) {
+  if (!ctx || nitems < 0 || (nitems > 0 && !items)) return RM_E_ARG;
+  (void)hipSetDevice(ctx->device);
+  const rm_opts o = fixed_opts(opts);
+  std::vector<Seg> segs;
+  for (int i = 0; i < nitems; ++i) {
+    const rm_batch_item &it = items[i];
+    if (it.ne < 0 || (it.ne > 0 && (!it.E || !it.omega || !it.status))) return RM_E_ARG;
+    const DevPW *pw;
+    if (rm_status st = get_pw(ctx, it.pw_id, &pw)) return st;
+    if (it.ne) segs.push_back(Seg{pw, it.E, it.ne, it.omega, it.K, it.status});
   }
-  size_t share;
-  {
-    std::lock_guard<std::mutex> g(ctx->mu);
-    const size_t used = ctx->resident + ctx->work_bytes - ctx->pipe[0].w.bytes - ctx->pipe[1].w.bytes;
-    share = ctx->budget > used ? (ctx->budget - used) / 2 : 0;
-  }
-  // Chunks of up to 256 energies alternate over the two streams.  The R
-  // contractions are chained across the streams (each waits for the previous
-  // chunk's), so chunk k+1's compute-bound contraction overlaps chunk k's
-  // latency-bound K solve instead of competing with chunk k's contraction.
-  // The LU panel runs one workgroup per energy, so its cost grows with the
-  // number of chunks rather than with their size; 256 fills the CUs.
-  int cap = std::min(chunk_cap(*pw, share, ne), 256);
-  if (ne > 2 * EB && cap * 2 > ne) cap = std::max(EB, (ne + 2 * EB - 1) / (2 * EB) * EB);
-  const int nuse = ne > cap ? 2 : 1;
-  for (int i = 0; i < nuse; ++i)
-    if (rm_status st = ensure_work(ctx, ctx->pipe[i].w, *pw, cap, false)) return st;
-  // the internal streams start after the caller's prior work on its stream
-  HIPCHK(hipEventRecord(ctx->ev_in, user));
-  for (int i = 0; i < nuse; ++i) HIPCHK(hipStreamWaitEvent(ctx->pipe[i].stream, ctx->ev_in, 0));
-  int k = 0;
-  for (int e0 = 0; e0 < ne; e0 += cap, ++k) {
-    Slot &sl = ctx->pipe[k % nuse];
-    const int m = std::min(cap, ne - e0);
-    HIPCHK(hipMemcpyAsync(sl.w.E, E + e0, sizeof(double) * m, kind_in(o), sl.stream));
-    ChunkOut out;
-    out.omega = omega + (size_t)e0 * pw->nt * pw->nt;
-    out.K = K ? K + (size_t)e0 * pw->n * pw->n : nullptr;
-    out.status = status + e0;
-    hipEvent_t prevR = k > 0 && nuse > 1 ? ctx->ev_R[(k - 1) % 2] : nullptr;
-    if (rm_status st = run_chunk(ctx, *pw, sl.w, m, o, sl.stream, out, kind_out(o), prevR, ctx->ev_R[k % 2]))
-      return st;
-  }
-  // and the caller's stream continues after both
-  for (int i = 0; i < nuse; ++i) {
-    HIPCHK(hipEventRecord(ctx->ev_out[i], ctx->pipe[i].stream));
-    HIPCHK(hipStreamWaitEvent(user, ctx->ev_out[i], 0));
-  }
-  if (!o.device_ptrs) HIPCHK(hipStreamSynchronize(user));
-  return RM_OK;
+  if (segs.empty()) return RM_OK;
+  return run_segments(ctx, segs, o, true);
 }
 
 rm_status rm_submit(rm_ctx *ctx, const rm_request *req, uint64_t *ticket) {
@@ -780,7 +1138,7 @@ rm_status rm_submit(rm_ctx *ctx, const rm_request *req, uint64_t *ticket) {
   }
   r->ticket = ctx->next_ticket++;
   *ticket = r->ticket;
-  if (req->ne == 0) r->st.t_done_ns = r->st.t_arrive_ns;
+  if (req->ne == 0) r->st.t_admit_ns = r->st.t_start_ns = r->st.t_done_ns = r->st.t_arrive_ns;
   ctx->active.push_back(r.get());
   ctx->reqs[r->ticket] = std::move(r);
   ctx->cv.notify_all();

@@ -45,6 +45,10 @@ class PWDesc(ctypes.Structure):
                 ("g", _d), ("e_thr", _vp), ("l", _vp), ("target", _vp), ("Ek", _vp), ("w", _vp)]
 
 
+class BatchItem(ctypes.Structure):
+    _fields_ = [("pw_id", _i32), ("E", _vp), ("ne", _i32), ("omega", _vp), ("K", _vp), ("status", _vp)]
+
+
 class Request(ctypes.Structure):
     _fields_ = [("pw_id", _i32), ("E", _vp), ("ne", _i32), ("opts", Opts), ("omega", _vp), ("K", _vp),
                 ("status", _vp)]
@@ -69,6 +73,7 @@ _lib.rm_asymptotic.argtypes = [_vp, _i32, _vp, _i32, ctypes.POINTER(Opts), _vp, 
 _lib.rm_solve_K.argtypes = [_vp, _i32, _vp, _i32, _vp, _vp, ctypes.POINTER(Opts), _vp, _vp]
 _lib.rm_collision_strengths.argtypes = [_vp, _i32, _vp, _i32, _vp, ctypes.POINTER(Opts), _vp, _vp, _vp]
 _lib.rm_run.argtypes = [_vp, _i32, _vp, _i32, ctypes.POINTER(Opts), _vp, _vp, _vp]
+_lib.rm_run_batch.argtypes = [_vp, ctypes.POINTER(BatchItem), _i32, ctypes.POINTER(Opts)]
 _lib.rm_submit.argtypes = [_vp, ctypes.POINTER(Request), ctypes.POINTER(_u64)]
 _lib.rm_poll.argtypes = [_vp, _u64, ctypes.POINTER(ReqStats)]
 _lib.rm_drain.argtypes = [_vp]
@@ -78,6 +83,7 @@ _lib.rm_prof_read.argtypes = [_vp, ctypes.c_char_p, ctypes.POINTER(_d), ctypes.P
 
 EXPORTS = ["rm_opts_default", "rm_create", "rm_destroy", "rm_last_error", "rm_pw_upload", "rm_pw_release",
            "rm_pw_footprint", "rm_form_R", "rm_asymptotic", "rm_solve_K", "rm_collision_strengths", "rm_run",
+           "rm_run_batch",
            "rm_submit", "rm_poll", "rm_drain", "rm_prof_enable", "rm_prof_read"]
 
 
@@ -110,6 +116,7 @@ class Context:
         self.h = h
         self.device = device
         self._pw = {}
+        self._inflight = {}  # ticket -> the request's host buffers, held until poll() retires it
 
     def _check(self, st: int, h=...):
         if st < 0:
@@ -121,6 +128,7 @@ class Context:
         if getattr(self, "h", None):
             _lib.rm_destroy(self.h)
             self.h = None
+            self._inflight.clear()
 
     def __enter__(self):
         return self
@@ -243,6 +251,26 @@ class Context:
         self._check(_lib.rm_run(self.h, pw_id, _ptr(E), ne, ctypes.byref(o), _ptr(om), _ptr(K), _ptr(st)))
         return om, K, st
 
+    def run_batch(self, items, prec=FP64, split_delta=0.05, thr_guard=1e-10, want_K=False):
+        """items: list of (pw_id, E).  All partial waves in one rm_run_batch call;
+        returns a list of (omega, K or None, status) per item."""
+        keep, outs = [], []
+        arr = (BatchItem * max(1, len(items)))()
+        dev = False
+        for k, (pid, E) in enumerate(items):
+            E, dev = self._E(E)
+            n, nt = self._pw.get(pid, (1, 1))
+            ne = E.shape[0]
+            om = self._alloc(E, (ne, nt, nt), np.float64)
+            K = self._alloc(E, (ne, n, n), np.float64) if want_K else None
+            st = self._alloc(E, (ne,), np.int32)
+            keep.append(E)
+            outs.append((om, K, st))
+            arr[k] = BatchItem(pid, _ptr(E), ne, _ptr(om), _ptr(K), _ptr(st))
+        o = self._opts(prec, split_delta, thr_guard, dev)
+        self._check(_lib.rm_run_batch(self.h, arr, len(items), ctypes.byref(o)))
+        return outs
+
     # ------------------------------------------------------------ serving
     def submit(self, pw_id, E, prec=FP64, split_delta=0.05, thr_guard=1e-10, want_K=False):
         """Queue a request; returns (ticket, outputs dict).  The output arrays
@@ -257,6 +285,7 @@ class Context:
                      outs["K"].ctypes.data if want_K else None, outs["status"].ctypes.data)
         t = _u64()
         self._check(_lib.rm_submit(self.h, ctypes.byref(rq), ctypes.byref(t)))
+        self._inflight[t.value] = outs
         return t.value, outs
 
     def poll(self, ticket):
@@ -265,6 +294,7 @@ class Context:
         st = _lib.rm_poll(self.h, ticket, ctypes.byref(s))
         if st == RM_PENDING:
             return None
+        self._inflight.pop(ticket, None)
         self._check(st)
         return dict(t_arrive_ns=s.t_arrive_ns, t_admit_ns=s.t_admit_ns, t_start_ns=s.t_start_ns,
                     t_done_ns=s.t_done_ns, nblocks=s.nblocks)

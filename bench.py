@@ -95,7 +95,7 @@ def main() -> int:
     ap.add_argument("--serving", type=int, default=32, metavar="NREQ",
                     help="requests in the serving measurement (0 = skip)")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="first run a 1 GiB device copy (HBM counter calibration under rocprofv3 --pmc)")
+                    help="first run a 1 GiB read + 1 GiB write kernel (HBM counter calibration under rocprofv3 --pmc)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -114,9 +114,9 @@ def main() -> int:
         dst = torch.empty_like(src)
         src.fill_(1.0)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        torch.neg(src, out=dst)  # one elementwise kernel: reads 1 GiB, writes 1 GiB
         torch.cuda.synchronize()
-        log("copy probe: 1 GiB device-to-device copy done")
+        log("copy probe: 1 GiB read + 1 GiB write elementwise kernel done")
         del src, dst
 
     t0 = time.time()

@@ -16,10 +16,21 @@
 //
 // Augmented layout per energy: rows [0, rows), A in columns [0, rows), the
 // right-hand sides in columns [roff, roff + rhs), row stride ldaug.
+#include <type_traits>
+#include <utility>
+
 #include "rm.h"
 #include "rm_internal.h"
 
 namespace rm {
+
+// Calls f(std::integral_constant<int, I>) for I = 0, 1, ...: a loop whose index
+// is a compile-time constant in every iteration, so register arrays indexed by
+// it stay in registers.
+template <typename F, int... I>
+__device__ __forceinline__ void static_for(F &&f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
@@ -151,6 +162,133 @@ __global__ __launch_bounds__(PANEL_T) void k_lu_panel(int j0, const int *__restr
       for (int q = c + 1; q < j0 + jb; ++q) row[q] -= m * prow[q - j0];
     }
     __syncthreads();
+  }
+}
+
+// Register-resident panel factorisation, the same algorithm as k_lu_panel for
+// panels of at most RPT * PREG_T rows: the panel is read from memory once, each
+// thread keeps rows t, t + PREG_T, ... (all NB columns) in registers, the pivot
+// row and the row it replaces are exchanged through LDS, and the factored panel
+// is written back once.
+constexpr int PREG_T = 512;
+template <int RPT>
+__global__ __launch_bounds__(PREG_T) void k_lu_panel_reg(int j0, const int *__restrict__ dims,
+                                                         double *__restrict__ aug, long ldaug, long strideA,
+                                                         int *__restrict__ ipiv, long ldp,
+                                                         int *__restrict__ status) {
+  const int e = blockIdx.x;
+  const int rows = dims[2 * e];
+  if (j0 >= rows) return;
+  const int jb = min(NB, rows - j0);
+  const int m = rows - j0;  // panel height; rows below are relative to j0
+  double *P = aug + (size_t)e * strideA + (size_t)j0 * ldaug + j0;
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  __shared__ double wv[PREG_T / 64];
+  __shared__ int wi[PREG_T / 64];
+  __shared__ int spiv;
+  __shared__ double prow[NB], crow[NB];
+  double v[RPT][NB];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = t + PREG_T * q;
+    if (r < m) {
+      const double2 *src = reinterpret_cast<const double2 *>(P + (size_t)r * ldaug);
+#pragma unroll
+      for (int c = 0; c < NB / 2; ++c) {
+        const double2 x = src[c];
+        v[q][2 * c] = x.x;
+        v[q][2 * c + 1] = x.y;
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < NB; ++c) v[q][c] = 0.0;
+    }
+  }
+  static_for([&](auto cI) {
+    constexpr int c = decltype(cI)::value;
+    if (c >= jb) return;  // uniform over the workgroup
+    double best = -1.0;
+    int bidx = m;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = t + PREG_T * q;
+      if (r >= c && r < m) {
+        const double a = fabs(v[q][c]);
+        if (a > best) { best = a; bidx = r; }
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(best, off);
+      const int oi = __shfl_xor(bidx, off);
+      if (ov > best || (ov == best && oi < bidx)) { best = ov; bidx = oi; }
+    }
+    if (lane == 0) { wv[wid] = best; wi[wid] = bidx; }
+    __syncthreads();
+    if (t == 0) {
+      double bv = wv[0];
+      int bi = wi[0];
+      for (int w = 1; w < PREG_T / 64; ++w)
+        if (wv[w] > bv || (wv[w] == bv && wi[w] < bi)) { bv = wv[w]; bi = wi[w]; }
+      if (!(bv > 0.0) || bi >= m) {
+        atomicOr(status + e, RM_PT_SINGULAR);
+        bi = c;
+      }
+      spiv = bi;
+      ipiv[(size_t)e * ldp + j0 + c] = j0 + bi;
+    }
+    __syncthreads();
+    const int p = spiv;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = t + PREG_T * q;
+      if (r == p) {
+#pragma unroll
+        for (int cc = 0; cc < NB; ++cc) prow[cc] = v[q][cc];
+      }
+      if (r == c) {
+#pragma unroll
+        for (int cc = 0; cc < NB; ++cc) crow[cc] = v[q][cc];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = t + PREG_T * q;
+      if (r == c) {
+#pragma unroll
+        for (int cc = 0; cc < NB; ++cc) v[q][cc] = prow[cc];
+      } else if (r == p) {
+#pragma unroll
+        for (int cc = 0; cc < NB; ++cc) v[q][cc] = crow[cc];
+      }
+    }
+    const double piv = prow[c];
+    const double inv = piv != 0.0 ? 1.0 / piv : 0.0;
+    double l[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = t + PREG_T * q;
+      const bool below = r > c && r < m;
+      l[q] = below ? v[q][c] * inv : 0.0;
+      if (below) v[q][c] = l[q];
+    }
+#pragma unroll
+    for (int cc = c + 1; cc < NB; ++cc) {
+      const double pr = cc < jb ? prow[cc] : 0.0;
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) v[q][cc] -= l[q] * pr;
+    }
+    __syncthreads();
+  }, std::make_integer_sequence<int, NB>{});
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = t + PREG_T * q;
+    if (r < m) {
+      double2 *dst = reinterpret_cast<double2 *>(P + (size_t)r * ldaug);
+#pragma unroll
+      for (int c = 0; c < NB / 2; ++c) dst[c] = double2{v[q][2 * c], v[q][2 * c + 1]};
+    }
   }
 }
 
@@ -342,8 +480,19 @@ __global__ __launch_bounds__(256) void k_bs_update(int j0, const int *__restrict
 void launch_lu_solve(hipStream_t s, int ne, int maxrows, int maxrhs, const int *dims, double *aug,
                      long ldaug, long strideA, long roff, int *ipiv, long ldp, int *status) {
   for (int j0 = 0; j0 < maxrows; j0 += NB) {
-    hipLaunchKernelGGL(k_lu_panel, dim3(ne), dim3(PANEL_T), 0, s, j0, dims, aug, ldaug, strideA, ipiv, ldp,
-                       status);
+    const int h = maxrows - j0;
+    if (h <= PREG_T)
+      hipLaunchKernelGGL(k_lu_panel_reg<1>, dim3(ne), dim3(PREG_T), 0, s, j0, dims, aug, ldaug, strideA, ipiv, ldp,
+                         status);
+    else if (h <= 2 * PREG_T)
+      hipLaunchKernelGGL(k_lu_panel_reg<2>, dim3(ne), dim3(PREG_T), 0, s, j0, dims, aug, ldaug, strideA, ipiv, ldp,
+                         status);
+    else if (h <= 3 * PREG_T)
+      hipLaunchKernelGGL(k_lu_panel_reg<3>, dim3(ne), dim3(PREG_T), 0, s, j0, dims, aug, ldaug, strideA, ipiv, ldp,
+                         status);
+    else
+      hipLaunchKernelGGL(k_lu_panel, dim3(ne), dim3(PANEL_T), 0, s, j0, dims, aug, ldaug, strideA, ipiv, ldp,
+                         status);
     const int c0 = min(maxrows, j0 + NB);
     const int ncols = (maxrows - c0) + maxrhs;
     if (ncols <= 0) continue;

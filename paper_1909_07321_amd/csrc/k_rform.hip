@@ -86,7 +86,10 @@ void launch_dvec(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, 
 // when bi == bj), then every wave computes its 32 x 32 quarter with 2 x 2
 // MFMA 16x16x4 tiles per energy, scaling the A fragment by d_k(E) in
 // registers.  MFMA operand layout (16x16x4): lane l holds A[l%16][l/16] and
-// B[l/16][l%16]; the result rows are given by MfmaRow.
+// B[l/16][l%16]; the result rows are given by MfmaRow.  Row r of a staged panel
+// is stored rotated by 16 (r % 4) elements: a fragment read touches four
+// consecutive rows at the same columns, which the rotation spreads over
+// distinct LDS banks.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -121,15 +124,16 @@ template <typename T> __device__ __forceinline__ const T *amplitudes(const DevPW
 template <> __device__ __forceinline__ const double *amplitudes<double>(const DevPW &p) { return p.W64; }
 template <> __device__ __forceinline__ const float *amplitudes<float>(const DevPW &p) { return p.W32; }
 
-// Persistent: every workgroup takes tasks from a queue (ordered by cost, largest
-// first) until it is empty; a task is one tile of one partial wave for up to EB
-// energies of that wave.  Each energy's sums run over k in ascending order
-// whatever workgroup takes the task, so results do not depend on scheduling.
+// Persistent: every workgroup takes tasks from the queue of its XCD until it is
+// empty, then from the other queues in turn; a task is one tile of one partial
+// wave for up to EB energies of that wave.  Each energy's sums run over k in
+// ascending order whatever workgroup takes the task, so results do not depend
+// on scheduling.
 template <typename T, int KC>
-__device__ __forceinline__ void rform_body(const DevPW *__restrict__ tab, const RTask *__restrict__ tasks, int ntasks,
-                                           int *__restrict__ counter, const T *__restrict__ D, long ldD,
-                                           double *__restrict__ R, long ldr, long strideR, T (*sA)[KC][TILE],
-                                           T (*sB)[KC][TILE], T (*sD)[EB][KC], int &stask) {
+__device__ __forceinline__ void rform_body(const DevPW *__restrict__ tab, const RTask *__restrict__ tasks,
+                                           const RQueues &qs, int *__restrict__ counter, const T *__restrict__ D,
+                                           long ldD, double *__restrict__ R, long ldr, long strideR,
+                                           T (*sA)[KC][TILE], T (*sB)[KC][TILE], T (*sD)[EB][KC], int &stask) {
   typedef typename Vec4<T>::type V4;
 
   const int tid = threadIdx.x;
@@ -141,12 +145,30 @@ __device__ __forceinline__ void rform_body(const DevPW *__restrict__ tab, const 
   constexpr int NVEC = KC * PER_ROW / 256;       // vectors per thread per panel
   typedef T TV __attribute__((ext_vector_type(VEC)));
 
+  // fragment columns in the rotated panel rows (ks is a multiple of 4, so row
+  // ks + kk is rotated by 16 kk)
+  const int ca0 = (wr * 32 + ii + 16 * kk) & (TILE - 1), ca1 = (wr * 32 + 16 + ii + 16 * kk) & (TILE - 1);
+  const int cb0 = (wc * 32 + ii + 16 * kk) & (TILE - 1), cb1 = (wc * 32 + 16 + ii + 16 * kk) & (TILE - 1);
+  int q = blockIdx.x % NQ, tried = 0;
   for (;;) {
-    if (tid == 0) stask = atomicAdd(counter, 1);
+    if (tid == 0) {
+      int task = -1;
+      while (tried < NQ) {
+        const int len = qs.start[q + 1] - qs.start[q];
+        const int idx = len > 0 ? atomicAdd(counter + q, 1) : len;
+        if (idx < len) {
+          task = qs.start[q] + idx;
+          break;
+        }
+        q = (q + 1) % NQ;
+        ++tried;
+      }
+      stask = task;
+    }
     __syncthreads();
     const int task = stask;
     __syncthreads();
-    if (task >= ntasks) return;
+    if (task < 0) return;
     const RTask tk = tasks[task];
     const DevPW &p = tab[tk.slot];
     const T *__restrict__ W = amplitudes<T>(p);
@@ -185,8 +207,9 @@ __device__ __forceinline__ void rform_body(const DevPW *__restrict__ tab, const 
       for (int r = 0; r < NVEC; ++r) {
         const int idx = tid + 256 * r;
         const int row = idx / PER_ROW, col = (idx % PER_ROW) * VEC;
-        *reinterpret_cast<TV *>(&sA[buf][row][col]) = ra[r];
-        if (!diag) *reinterpret_cast<TV *>(&sB[buf][row][col]) = rb[r];
+        const int scol = (col + 16 * (row & 3)) & (TILE - 1);
+        *reinterpret_cast<TV *>(&sA[buf][row][scol]) = ra[r];
+        if (!diag) *reinterpret_cast<TV *>(&sB[buf][row][scol]) = rb[r];
       }
       if (tid < EB * KC) sD[buf][tid / KC][tid % KC] = rd;
     };
@@ -202,10 +225,10 @@ __device__ __forceinline__ void rform_body(const DevPW *__restrict__ tab, const 
       const T(*pB)[TILE] = diag ? sA[buf] : sB[buf];
 #pragma unroll 4
       for (int ks = 0; ks < KC; ks += 4) {
-        const T a0 = pA[ks + kk][wr * 32 + ii];
-        const T a1 = pA[ks + kk][wr * 32 + 16 + ii];
-        const T b0 = pB[ks + kk][wc * 32 + ii];
-        const T b1 = pB[ks + kk][wc * 32 + 16 + ii];
+        const T a0 = pA[ks + kk][ca0];
+        const T a1 = pA[ks + kk][ca1];
+        const T b0 = pB[ks + kk][cb0];
+        const T b1 = pB[ks + kk][cb1];
 #pragma unroll
         for (int e = 0; e < EB; ++e) {
           const T d = sD[buf][e][ks + kk];
@@ -245,33 +268,36 @@ __device__ __forceinline__ void rform_body(const DevPW *__restrict__ tab, const 
 // The FP32 variant is held to two waves per SIMD (its accumulators are half the
 // size); the FP64 one keeps its 128 accumulator registers at one wave per SIMD.
 __global__ __launch_bounds__(256, 2) void k_rform_f32(const DevPW *__restrict__ tab, const RTask *__restrict__ tasks,
-                                                      int ntasks, int *__restrict__ counter,
+                                                      const RQueues qs, int *__restrict__ counter,
                                                       const float *__restrict__ D, long ldD, double *__restrict__ R,
                                                       long ldr, long strideR) {
   __shared__ float sA[2][KC32][TILE];
   __shared__ float sB[2][KC32][TILE];
   __shared__ float sD[2][EB][KC32];
   __shared__ int stask;
-  rform_body<float, KC32>(tab, tasks, ntasks, counter, D, ldD, R, ldr, strideR, sA, sB, sD, stask);
+  rform_body<float, KC32>(tab, tasks, qs, counter, D, ldD, R, ldr, strideR, sA, sB, sD, stask);
 }
 
 __global__ __launch_bounds__(256) void k_rform_f64(const DevPW *__restrict__ tab, const RTask *__restrict__ tasks,
-                                                   int ntasks, int *__restrict__ counter,
+                                                   const RQueues qs, int *__restrict__ counter,
                                                    const double *__restrict__ D, long ldD, double *__restrict__ R,
                                                    long ldr, long strideR) {
   __shared__ double sA[2][KC64][TILE];
   __shared__ double sB[2][KC64][TILE];
   __shared__ double sD[2][EB][KC64];
   __shared__ int stask;
-  rform_body<double, KC64>(tab, tasks, ntasks, counter, D, ldD, R, ldr, strideR, sA, sB, sD, stask);
+  rform_body<double, KC64>(tab, tasks, qs, counter, D, ldD, R, ldr, strideR, sA, sB, sD, stask);
 }
 
-__global__ void k_reset(int *__restrict__ counter) { *counter = 0; }
+__global__ void k_reset(int *__restrict__ counter) {
+  if (threadIdx.x < NQ) counter[threadIdx.x] = 0;
+}
 
-void launch_rform(hipStream_t s, const Lay &L, int split, const DevPW *tab, const RTask *tasks, int ntasks,
+void launch_rform(hipStream_t s, const Lay &L, int split, const DevPW *tab, const RTask *tasks, const RQueues &qs,
                   int *counter, int nworkgroups, const double *D64, const float *D32, double *R) {
+  const int ntasks = qs.start[NQ];
   if (ntasks <= 0) return;
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, s, counter);
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, counter);
   // persistent grid: as many workgroups as can be resident at once
   static int occ[2] = {0, 0};
   int &oc = occ[split ? 1 : 0];
@@ -285,11 +311,9 @@ void launch_rform(hipStream_t s, const Lay &L, int split, const DevPW *tab, cons
   }
   const dim3 grid(std::max(1, std::min(ntasks, oc * nworkgroups)));
   if (split)
-    hipLaunchKernelGGL(k_rform_f32, grid, dim3(256), 0, s, tab, tasks, ntasks, counter, D32, L.ldD, R, L.ldaug,
-                       L.sA);
+    hipLaunchKernelGGL(k_rform_f32, grid, dim3(256), 0, s, tab, tasks, qs, counter, D32, L.ldD, R, L.ldaug, L.sA);
   else
-    hipLaunchKernelGGL(k_rform_f64, grid, dim3(256), 0, s, tab, tasks, ntasks, counter, D64, L.ldD, R, L.ldaug,
-                       L.sA);
+    hipLaunchKernelGGL(k_rform_f64, grid, dim3(256), 0, s, tab, tasks, qs, counter, D64, L.ldD, R, L.ldaug, L.sA);
 }
 
 // ---------------------------------------------------------------------------

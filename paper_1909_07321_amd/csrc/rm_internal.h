@@ -58,6 +58,15 @@ struct RTask {
   int slot, e0, m, tile;
 };
 
+// The R contraction's task list is split into NQ queues, one per XCD (workgroup
+// b of a launch is placed on XCD b % NQ).  Queue q holds tasks [start[q],
+// start[q + 1]); a queue keeps all energy batches of a tile together, so the
+// workgroups of one XCD stream the same amplitude rows through its L2.
+constexpr int NQ = 8;
+struct RQueues {
+  int start[NQ + 1];
+};
+
 // Per-chunk device workspace.
 struct Work {
   int cap_e = 0, cap_n = 0, cap_npad = 0, cap_M = 0, cap_nt = 0, cap_tab = 0, cap_tasks = 0;
@@ -66,7 +75,7 @@ struct Work {
   int *pwi = nullptr;        // [cap_e] table slot of each energy
   DevPW *tab = nullptr;      // [cap_tab]
   RTask *tasks = nullptr;    // [cap_tasks]
-  int *counter = nullptr;    // task queue head of the persistent R contraction
+  int *counter = nullptr;    // [NQ] queue heads of the persistent R contraction
   double *D64 = nullptr;     // [cap_e][ldD]
   float *D32 = nullptr;      // [cap_e][ldD]
   int *win = nullptr;        // [cap_e][2] near-pole window [lo, hi)
@@ -92,7 +101,7 @@ void launch_dvec(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, 
                  double delta, double *D64, float *D32, int *win, int *status);
 // Persistent R contraction over `tasks`; ncu = compute units of the device (the
 // grid is the number of workgroups that fit at once).
-void launch_rform(hipStream_t s, const Lay &L, int split, const DevPW *tab, const RTask *tasks, int ntasks,
+void launch_rform(hipStream_t s, const Lay &L, int split, const DevPW *tab, const RTask *tasks, const RQueues &q,
                   int *counter, int ncu, const double *D64, const float *D32, double *R);
 void launch_nearpole(hipStream_t s, const Lay &L, int maxtiles, const DevPW *tab, const int *pwi, const double *E,
                      const int *win, double *R);

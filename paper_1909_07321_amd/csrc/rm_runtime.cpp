@@ -95,6 +95,7 @@ struct Plan {
   std::vector<const DevPW *> slots;
   Lay L;
   int ntasks = 0, maxtiles = 0;
+  RQueues q{};
 };
 
 }  // namespace
@@ -307,20 +308,39 @@ rm_status upload_plan(rm_ctx *ctx, Slot &sl, Plan &P, const std::vector<Seg> &se
   for (const Part &pt : P.parts)
     for (int i = 0; i < pt.m; ++i) h.pwi[pt.e0 + i] = pt.slot;
   for (size_t i = 0; i < P.slots.size(); ++i) h.tab[i] = *P.slots[i];
-  // R tasks: energy batches of <= EB energies of one partial wave times its tiles,
-  // largest pole count first (longest tasks start first)
-  std::vector<int> order(P.parts.size());
-  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int b) { return P.slots[P.parts[a].slot]->Mpad > P.slots[P.parts[b].slot]->Mpad; });
-  int nt = 0;
-  for (int pi : order) {
+  // R tasks: energy batches of <= EB energies of one partial wave times its
+  // tiles.  All batches of one (part, tile) form a unit; units go, longest
+  // first, to the XCD queue with the least work so far, and each queue lists
+  // its units in that order.
+  struct Unit {
+    int part, tile;
+    double cost;
+  };
+  std::vector<Unit> units;
+  for (size_t pi = 0; pi < P.parts.size(); ++pi) {
     const Part &pt = P.parts[pi];
-    const int tl = P.slots[pt.slot]->npad / TILE;
-    const int ntile = tl * (tl + 1) / 2;
-    for (int b = 0; b < pt.m; b += EB)
-      for (int t = 0; t < ntile; ++t) h.tasks[nt++] = RTask{pt.slot, pt.e0 + b, std::min(EB, pt.m - b), t};
+    const DevPW *p = P.slots[pt.slot];
+    const int tl = p->npad / TILE;
+    const double c = (double)p->Mpad * ((pt.m + EB - 1) / EB);
+    for (int t = 0; t < tl * (tl + 1) / 2; ++t) units.push_back(Unit{(int)pi, t, c});
   }
+  std::stable_sort(units.begin(), units.end(), [](const Unit &a, const Unit &b) { return a.cost > b.cost; });
+  std::vector<std::vector<int>> qu(NQ);
+  double load[NQ] = {0};
+  for (size_t u = 0; u < units.size(); ++u) {
+    const int q = (int)(std::min_element(load, load + NQ) - load);
+    qu[q].push_back((int)u);
+    load[q] += units[u].cost;
+  }
+  int nt = 0;
+  for (int q = 0; q < NQ; ++q) {
+    P.q.start[q] = nt;
+    for (int u : qu[q]) {
+      const Part &pt = P.parts[units[u].part];
+      for (int b = 0; b < pt.m; b += EB) h.tasks[nt++] = RTask{pt.slot, pt.e0 + b, std::min(EB, pt.m - b), units[u].tile};
+    }
+  }
+  P.q.start[NQ] = nt;
   P.ntasks = nt;
   long om = 0, kk = 0;
   for (const Part &pt : P.parts) {
@@ -380,7 +400,7 @@ void stage_R(rm_ctx *ctx, const Plan &P, Work &w, const rm_opts &o, hipStream_t 
   const int split = o.prec == RM_FP32_SPLIT;
   launch_dvec(s, L, w.tab, w.pwi, w.E, split, o.split_delta, w.D64, w.D32, w.win, w.status);
   timed(ctx, 0, L.ne, s, [&] {
-    launch_rform(s, L, split, w.tab, w.tasks, P.ntasks, w.counter, ctx->ncu, w.D64, w.D32, w.aug);
+    launch_rform(s, L, split, w.tab, w.tasks, P.q, w.counter, ctx->ncu, w.D64, w.D32, w.aug);
   });
   if (split)
     timed(ctx, 1, L.ne, s, [&] { launch_nearpole(s, L, P.maxtiles, w.tab, w.pwi, w.E, w.win, w.aug); });
@@ -609,12 +629,10 @@ rm_status run_segments(rm_ctx *ctx, const std::vector<Seg> &segs, const rm_opts 
     const size_t used = ctx->resident + ctx->work_bytes - ctx->pipe[0].w.bytes - ctx->pipe[1].w.bytes;
     share = ctx->budget > used ? (ctx->budget - used) / 2 : 0;
   }
-  // Chunks of up to 256 energies (1024 for interleaved batches) alternate over the
-  // two streams.  The LU panel runs one workgroup per energy, so its cost grows
-  // with the number of chunks rather than with their size.
-  int cap = chunk_cap(n, npad, Mpad, nt, share, interleave ? MAX_CHUNK : 256);
-  if (!interleave && total > (size_t)2 * EB && (size_t)cap * 2 > total)
-    cap = std::max(EB, (int)((total + 2 * EB - 1) / (2 * EB) * EB));
+  // Chunks of up to MAX_CHUNK energies (fewer if the HBM budget says so)
+  // alternate over the two streams.  Large chunks keep every launch of the LU
+  // chain wide enough to fill the device.
+  const int cap = chunk_cap(n, npad, Mpad, nt, share, MAX_CHUNK);
   std::vector<Plan> plans = cut_chunks(segs, cap, interleave);
   const int nuse = plans.size() > 1 ? 2 : 1;
   HIPCHK(hipEventRecord(ctx->ev_in, user));

@@ -24,6 +24,12 @@
 
 namespace rm {
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 // Calls f(std::integral_constant<int, I>) for I = 0, 1, ...: a loop whose index
 // is a compile-time constant in every iteration, so register arrays indexed by
 // it stay in registers.
@@ -32,11 +38,29 @@ __device__ __forceinline__ void static_for(F &&f, std::integer_sequence<int, I..
   (f(std::integral_constant<int, I>{}), ...);
 }
 
-typedef double d4 __attribute__((ext_vector_type(4)));
+// LDS slabs of the 64 x 64 FP64 MFMA tiles.  The A operand is staged as it lies
+// in memory, [row][k] with pitch K + 2, the B operand as [k][col] with pitch
+// TILE + 16: with these pitches the fragment reads of one MFMA step (lanes
+// 0..31 and 32..63 each covering two k and sixteen rows or columns) fall on
+// distinct LDS banks, and the staging stores are row-contiguous.
+constexpr int PB = TILE + 16;
+template <int K> struct Pitch { static constexpr int A = K + 2; };
 
-__device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+// acc += A_slab (64 x K) * B_slab (K x 64): every wave owns a 32 x 32 quarter.
+template <int K>
+__device__ __forceinline__ void mfma_slab(const double (*sA)[Pitch<K>::A], const double (*sB)[PB], d4 (&acc)[4],
+                                          int wr, int wc, int kk, int ii) {
+#pragma unroll
+  for (int ks = 0; ks < K; ks += 4) {
+    const double a0 = sA[wr * 32 + ii][ks + kk], a1 = sA[wr * 32 + 16 + ii][ks + kk];
+    const double b0 = sB[ks + kk][wc * 32 + ii], b1 = sB[ks + kk][wc * 32 + 16 + ii];
+    acc[0] = mfma64(a0, b0, acc[0]);
+    acc[1] = mfma64(a0, b1, acc[1]);
+    acc[2] = mfma64(a1, b0, acc[2]);
+    acc[3] = mfma64(a1, b1, acc[3]);
+  }
 }
+
 
 // ---------------------------------------------------------------------------
 // assembly of B (reads R) and then A (in place over R)
@@ -292,179 +316,370 @@ __global__ __launch_bounds__(PREG_T) void k_lu_panel_reg(int j0, const int *__re
   }
 }
 
-// For every column right of the panel: apply the panel's row interchanges,
-// then U12 = L11^-1 A12 on rows [j0, j0 + jb).  One thread per column; the
-// column's panel rows are kept in LDS (its own slot), so the solve needs no
-// large per-thread register array.
-constexpr int TRSM_T = 128;
-__global__ __launch_bounds__(TRSM_T) void k_lu_trsm(int j0, const int *__restrict__ dims,
-                                                    double *__restrict__ aug, long ldaug, long strideA,
-                                                    long roff, const int *__restrict__ ipiv, long ldp) {
+// Number of trailing "virtual" columns right of a block that ends at column c0:
+// the remaining columns of A, then (if with_rhs) the right-hand sides, at most
+// vlimit in all.
+__device__ __forceinline__ int trailing_cols(int rows, int rhs, int c0, int with_rhs, int vlimit) {
+  return min(vlimit, (rows - c0) + (with_rhs ? rhs : 0));
+}
+
+// After the panels of an outer block [p0, p0 + jb) are factored: the second
+// panel's interchanges (rows >= p0 + NB) are applied to the first panel's
+// columns, so that the block's L21 rows line up with the trailing rows, and the
+// net permutation of all jb interchanges is written to bperm: the source row of
+// each block row, and every row outside the block that receives another row,
+// with its source.  One wave per energy: lane 0 applies the transpositions in
+// order; the outside rows are found by a wave-wide compare.
+__global__ __launch_bounds__(64) void k_lu_blockperm(int p0, const int *__restrict__ dims, double *__restrict__ aug,
+                                                     long ldaug, long strideA, const int *__restrict__ ipiv, long ldp,
+                                                     int *__restrict__ bperm, double *__restrict__ linv) {
+  const int e = blockIdx.x;
+  const int rows = dims[2 * e];
+  if (p0 >= rows) return;
+  const int jb = min(NBU, rows - p0);
+  const int lane = threadIdx.x;
+  double *A = aug + (size_t)e * strideA;
+  const int *pv = ipiv + (size_t)e * ldp + p0;
+  if (jb > NB && lane < NB) {
+    const long col = p0 + lane;
+    for (int r = NB; r < jb; ++r) {
+      const int p = pv[r];
+      if (p != p0 + r) {
+        const double x = A[(size_t)p * ldaug + col];
+        A[(size_t)p * ldaug + col] = A[(size_t)(p0 + r) * ldaug + col];
+        A[(size_t)(p0 + r) * ldaug + col] = x;
+      }
+    }
+  }
+  __shared__ int src[2 * NBU], pos[NBU];
+  for (int r = lane; r < jb; r += 64) src[r] = p0 + r;
+  __syncthreads();
+  int nout = 0;
+  for (int r = 0; r < jb; ++r) {
+    const int p = pv[r];
+    int sp;
+    if (p < p0 + jb) {
+      sp = p - p0;
+    } else {
+      const bool hit = lane < nout && pos[lane] == p;
+      const unsigned long long m = __ballot(hit);
+      if (m) {
+        sp = NBU + __ffsll((long long)m) - 1;
+      } else {
+        sp = NBU + nout;
+        if (lane == 0) {
+          pos[nout] = p;
+          src[sp] = p;
+        }
+        ++nout;
+      }
+    }
+    __syncthreads();
+    if (lane == 0 && sp != r) {
+      const int a = src[r];
+      src[r] = src[sp];
+      src[sp] = a;
+    }
+    __syncthreads();
+  }
+  int *out = bperm + (size_t)e * BPERM;
+  if (lane == 0) out[0] = nout;
+  for (int r = lane; r < NBU; r += 64) {
+    out[1 + r] = r < jb ? src[r] : 0;
+    out[1 + NBU + r] = r < nout ? src[NBU + r] : 0;
+    out[1 + 2 * NBU + r] = r < nout ? pos[r] : 0;
+  }
+  // Inverse of the unit lower L11 (identity beyond jb): lane j computes column j
+  // by forward substitution, X[i][j] = -sum_{j <= k < i} L[i][k] X[k][j].
+  __shared__ double sl[NBU][NBU + 1];
+  __syncthreads();
+  for (int idx = lane; idx < NBU * NBU; idx += 64) {
+    const int r = idx / NBU, c = idx % NBU;
+    sl[r][c] = (r < jb && c < r) ? A[(size_t)(p0 + r) * ldaug + p0 + c] : 0.0;
+  }
+  __syncthreads();
+  double *Li = linv + (size_t)e * NBU * NBU;
+  const int j = lane;
+  double xc[NBU];
+  static_for([&](auto iI) {
+    constexpr int i = decltype(iI)::value;
+    double acc = i == j ? 1.0 : 0.0;
+    static_for([&](auto kI) {
+      constexpr int k = decltype(kI)::value;
+      if constexpr (k < i) acc -= sl[i][k] * xc[k];
+    }, std::make_integer_sequence<int, NBU>{});
+    xc[i] = i < j ? 0.0 : acc;
+  }, std::make_integer_sequence<int, NBU>{});
+  static_for([&](auto iI) {
+    constexpr int i = decltype(iI)::value;
+    Li[(size_t)i * NBU + j] = xc[i];
+  }, std::make_integer_sequence<int, NBU>{});
+}
+
+// Triangular solve for the trailing columns of an outer block, U12 = L11^-1 P A12,
+// as a product with the block's explicit inverse (k_lu_blockinv) on FP64 MFMA.
+// Each workgroup owns 64 trailing columns: it gathers their block rows from the
+// source rows of the net permutation into LDS and loads the rows that move out
+// of the block into registers (every load before any store), writes the moved
+// rows, then forms the 64 x 64 product.
+__global__ __launch_bounds__(256) void k_lu_trsm_inv(int p0, const int *__restrict__ dims, double *__restrict__ aug,
+                                                     long ldaug, long strideA, long roff,
+                                                     const int *__restrict__ bperm, const double *__restrict__ linv) {
+  constexpr int KB = NBU;
   const int e = blockIdx.y;
   const int rows = dims[2 * e], rhs = dims[2 * e + 1];
-  if (j0 >= rows) return;
-  const int jb = min(NB, rows - j0);
-  const int c0 = j0 + jb;
+  if (p0 >= rows) return;
+  const int jb = min(KB, rows - p0);
+  const int c0 = p0 + jb;
   const int ncols = (rows - c0) + rhs;
-  if ((int)(blockIdx.x * TRSM_T) >= ncols) return;
+  const int v0 = blockIdx.x * TILE;
+  if (v0 >= ncols) return;
   double *A = aug + (size_t)e * strideA;
-  __shared__ double L[NB][NB + 1];
-  __shared__ double sx[NB][TRSM_T];
-  __shared__ int piv[NB];
+  const int *pm = bperm + (size_t)e * BPERM;
+  const double *Li = linv + (size_t)e * KB * KB;
+  __shared__ double sL[KB][Pitch<KB>::A];  // sL[i][k] = Linv[i][k]
+  __shared__ double sX[KB][PB];            // sX[k][j] = (P A12)[k][v0 + j]
+  __shared__ int sp[1 + 3 * KB];
+  __shared__ long scol[TILE];
   const int t = threadIdx.x;
-  for (int idx = t; idx < jb * jb; idx += TRSM_T) {
-    const int r = idx / jb, c = idx % jb;
-    L[r][c] = A[(size_t)(j0 + r) * ldaug + j0 + c];
-  }
-  if (t < jb) piv[t] = ipiv[(size_t)e * ldp + j0 + t];
+  for (int idx = t; idx < 1 + 3 * KB; idx += 256) sp[idx] = pm[idx];
+  if (t < TILE) scol[t] = v0 + t < ncols ? vcol(v0 + t, rows, c0, roff) : -1;
+  for (int idx = t; idx < KB * KB; idx += 256) sL[idx / KB][idx % KB] = Li[idx];
   __syncthreads();
-  const int v = blockIdx.x * TRSM_T + t;
-  const bool valid = v < ncols;
-  if (valid) {
+  const int nout = sp[0];
+  for (int idx = t; idx < KB * TILE; idx += 256) {
+    const int k = idx / TILE, j = idx % TILE;
+    const long col = scol[j];
+    sX[k][j] = (k < jb && col >= 0) ? A[(size_t)sp[1 + k] * ldaug + col] : 0.0;
+  }
+  constexpr int NY = KB * TILE / 256;
+  double yv[NY];
+#pragma unroll
+  for (int q = 0; q < NY; ++q) {
+    const int idx = t + 256 * q, k = idx / TILE, j = idx % TILE;
+    const long col = scol[j];
+    yv[q] = (k < nout && col >= 0) ? A[(size_t)sp[1 + KB + k] * ldaug + col] : 0.0;
+  }
+  __syncthreads();  // every load of the workgroup has completed
+#pragma unroll
+  for (int q = 0; q < NY; ++q) {
+    const int idx = t + 256 * q, k = idx / TILE, j = idx % TILE;
+    const long col = scol[j];
+    if (k < nout && col >= 0) A[(size_t)sp[1 + 2 * KB + k] * ldaug + col] = yv[q];
+  }
+  const int lane = t & 63, wave = t >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int kk = lane >> 4, ii = lane & 15;
+  d4 acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = d4{0, 0, 0, 0};
+  mfma_slab<KB>(sL, sX, acc, wr, wc, kk, ii);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const long col = scol[wc * 32 + (q & 1) * 16 + ii];
+    if (col < 0) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = wr * 32 + (q >> 1) * 16 + 4 * v + kk;
+      if (i < jb) A[(size_t)(p0 + i) * ldaug + col] = acc[q][v];
+    }
+  }
+}
+
+// For trailing columns of the block of kb rows starting at p0 (columns [p0 +
+// jb, ...) as in trailing_cols): apply the block's row interchanges in order,
+// then U12 = L11^-1 A12 on rows [p0, p0 + jb).  One thread per column; the
+// column's block rows are kept in LDS (its own slot).
+template <int KB, int T>
+__global__ __launch_bounds__(T) void k_lu_trsm(int p0, const int *__restrict__ dims, double *__restrict__ aug,
+                                               long ldaug, long strideA, long roff, const int *__restrict__ ipiv,
+                                               long ldp, int with_rhs, int vlimit) {
+  const int e = blockIdx.y;
+  const int rows = dims[2 * e], rhs = dims[2 * e + 1];
+  if (p0 >= rows) return;
+  const int jb = min(KB, rows - p0);
+  const int c0 = p0 + jb;
+  const int ncols = trailing_cols(rows, rhs, c0, with_rhs, vlimit);
+  if ((int)(blockIdx.x * T) >= ncols) return;
+  double *A = aug + (size_t)e * strideA;
+  __shared__ double L[KB][KB + 1];
+  __shared__ double sx[KB][T];
+  __shared__ int piv[KB];
+  const int t = threadIdx.x;
+  for (int idx = t; idx < jb * jb; idx += T) {
+    const int r = idx / jb, c = idx % jb;
+    L[r][c] = A[(size_t)(p0 + r) * ldaug + p0 + c];
+  }
+  if (t < jb) piv[t] = ipiv[(size_t)e * ldp + p0 + t];
+  __syncthreads();
+  const int v = blockIdx.x * T + t;
+  if (v < ncols) {
     const long col = vcol(v, rows, c0, roff);
     for (int r = 0; r < jb; ++r) {
       const int p = piv[r];
       const double x = A[(size_t)p * ldaug + col];
-      if (p != j0 + r) A[(size_t)p * ldaug + col] = A[(size_t)(j0 + r) * ldaug + col];
-      sx[r][t] = x;  // row j0 + r after the interchange; later interchanges of
-                     // this panel only touch rows > j0 + r, so it stays in LDS
+      if (p != p0 + r) A[(size_t)p * ldaug + col] = A[(size_t)(p0 + r) * ldaug + col];
+      sx[r][t] = x;  // row p0 + r after the interchange; later interchanges of
+                     // this block only touch rows > p0 + r, so it stays in LDS
     }
     for (int r = 1; r < jb; ++r) {
       double acc = sx[r][t];
       for (int c = 0; c < r; ++c) acc -= L[r][c] * sx[c][t];
       sx[r][t] = acc;
     }
-    for (int r = 0; r < jb; ++r) A[(size_t)(j0 + r) * ldaug + col] = sx[r][t];
+    for (int r = 0; r < jb; ++r) A[(size_t)(p0 + r) * ldaug + col] = sx[r][t];
   }
 }
 
-// Trailing update A22 -= L21 U12 over rows [c0, rows) and all virtual columns
-// right of the panel; 64 x 64 output tiles, K = jb, FP64 MFMA.
-__global__ __launch_bounds__(256) void k_lu_update(int j0, const int *__restrict__ dims,
-                                                   double *__restrict__ aug, long ldaug, long strideA,
-                                                   long roff, int tiles_n) {
+// Trailing update A22 -= L21 U12 for the block of kb columns starting at p0:
+// rows [c0, rows) with c0 = p0 + jb, trailing columns as in trailing_cols.
+// 64 x 64 output tiles, K = jb, FP64 MFMA; the C tile is loaded into registers
+// before the operands are staged, so its latency overlaps the staging.
+template <int KB>
+__global__ __launch_bounds__(256) void k_lu_update(int p0, const int *__restrict__ dims, double *__restrict__ aug,
+                                                   long ldaug, long strideA, long roff, int tiles_n, int with_rhs,
+                                                   int vlimit) {
   const int e = blockIdx.y;
   const int rows = dims[2 * e], rhs = dims[2 * e + 1];
-  if (j0 >= rows) return;
-  const int jb = min(NB, rows - j0);
-  const int c0 = j0 + jb;
+  if (p0 >= rows) return;
+  const int jb = min(KB, rows - p0);
+  const int c0 = p0 + jb;
   const int m = rows - c0;
-  const int ncols = (rows - c0) + rhs;
+  const int ncols = trailing_cols(rows, rhs, c0, with_rhs, vlimit);
   const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
   const int r0 = tm * TILE, v0 = tn * TILE;
   if (r0 >= m || v0 >= ncols) return;
   double *A = aug + (size_t)e * strideA;
-  __shared__ double sL[NB][TILE];  // sL[k][i] = L21[r0 + i][k]
-  __shared__ double sU[NB][TILE];  // sU[k][j] = U12[k][v0 + j]
   const int t = threadIdx.x;
-  for (int idx = t; idx < NB * TILE; idx += 256) {
-    const int i = idx / NB, k = idx % NB;
-    sL[k][i] = (r0 + i < m && k < jb) ? A[(size_t)(c0 + r0 + i) * ldaug + j0 + k] : 0.0;
-  }
-  for (int idx = t; idx < NB * TILE; idx += 256) {
-    const int k = idx / TILE, j = idx % TILE;
-    sU[k][j] = (v0 + j < ncols && k < jb) ? A[(size_t)(j0 + k) * ldaug + vcol(v0 + j, rows, c0, roff)] : 0.0;
-  }
-  __syncthreads();
   const int lane = t & 63, wave = t >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int kk = lane >> 4, ii = lane & 15;
-  d4 acc[4];
+  // this thread's 16 C elements: (q, v) -> row r0 + wr*32 + (q>>1)*16 + 4v + kk, virtual column v0 + wc*32 + (q&1)*16 + ii
+  double cv[4][4];
+  long ccol[2];
+  bool cok[2];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) acc[q] = d4{0, 0, 0, 0};
-#pragma unroll
-  for (int ks = 0; ks < NB; ks += 4) {
-    const double a0 = sL[ks + kk][wr * 32 + ii], a1 = sL[ks + kk][wr * 32 + 16 + ii];
-    const double b0 = sU[ks + kk][wc * 32 + ii], b1 = sU[ks + kk][wc * 32 + 16 + ii];
-    acc[0] = mfma64(a0, b0, acc[0]);
-    acc[1] = mfma64(a0, b1, acc[1]);
-    acc[2] = mfma64(a1, b0, acc[2]);
-    acc[3] = mfma64(a1, b1, acc[3]);
+  for (int h = 0; h < 2; ++h) {
+    const int jv = v0 + wc * 32 + h * 16 + ii;
+    cok[h] = jv < ncols;
+    ccol[h] = cok[h] ? vcol(jv, rows, c0, roff) : 0;
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int jv = v0 + wc * 32 + (q & 1) * 16 + ii;
-    if (jv >= ncols) continue;
-    const long col = vcol(jv, rows, c0, roff);
+  for (int q = 0; q < 4; ++q)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int i = r0 + wr * 32 + (q >> 1) * 16 + 4 * v + kk;
-      if (i < m) A[(size_t)(c0 + i) * ldaug + col] -= acc[q][v];
+      cv[q][v] = (cok[q & 1] && i < m) ? A[(size_t)(c0 + i) * ldaug + ccol[q & 1]] : 0.0;
+    }
+  __shared__ double sL[TILE][Pitch<KB>::A];  // sL[i][k] = L21[r0 + i][k]
+  __shared__ double sU[KB][PB];              // sU[k][j] = U12[k][v0 + j]
+  for (int idx = t; idx < KB * TILE; idx += 256) {
+    const int i = idx / KB, k = idx % KB;
+    sL[i][k] = (r0 + i < m && k < jb) ? A[(size_t)(c0 + r0 + i) * ldaug + p0 + k] : 0.0;
+  }
+  for (int idx = t; idx < KB * TILE; idx += 256) {
+    const int k = idx / TILE, j = idx % TILE;
+    sU[k][j] = (v0 + j < ncols && k < jb) ? A[(size_t)(p0 + k) * ldaug + vcol(v0 + j, rows, c0, roff)] : 0.0;
+  }
+  __syncthreads();
+  d4 acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = d4{0, 0, 0, 0};
+  mfma_slab<KB>(sL, sU, acc, wr, wc, kk, ii);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (!cok[q & 1]) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = r0 + wr * 32 + (q >> 1) * 16 + 4 * v + kk;
+      if (i < m) A[(size_t)(c0 + i) * ldaug + ccol[q & 1]] = cv[q][v] - acc[q][v];
     }
   }
 }
 
-// Back substitution, diagonal block: Y_b = U_bb^-1 B_b for the right-hand sides
-// (one thread per right-hand side, its column kept in LDS).
-__global__ __launch_bounds__(TRSM_T) void k_bs_block(int j0, const int *__restrict__ dims,
-                                                     double *__restrict__ aug, long ldaug, long strideA,
-                                                     long roff) {
+// Back substitution, diagonal block: Y_b = U_bb^-1 B_b for the right-hand sides,
+// one thread per right-hand side with its column in registers and U_bb in LDS
+// (column-oriented: each solved entry is eliminated from the rows above it).
+template <int KB, int T>
+__global__ __launch_bounds__(T) void k_bs_block(int j0, const int *__restrict__ dims, double *__restrict__ aug,
+                                                long ldaug, long strideA, long roff) {
   const int e = blockIdx.y;
   const int rows = dims[2 * e], rhs = dims[2 * e + 1];
   if (j0 >= rows) return;
-  if ((int)(blockIdx.x * TRSM_T) >= rhs) return;
-  const int jb = min(NB, rows - j0);
+  if ((int)(blockIdx.x * T) >= rhs) return;
+  const int jb = min(KB, rows - j0);
   double *A = aug + (size_t)e * strideA;
-  __shared__ double U[NB][NB + 1];
-  __shared__ double sx[NB][TRSM_T];
+  __shared__ double U[KB][KB];
   const int t = threadIdx.x;
-  for (int idx = t; idx < jb * jb; idx += TRSM_T) {
-    const int r = idx / jb, c = idx % jb;
-    U[r][c] = A[(size_t)(j0 + r) * ldaug + j0 + c];
+  for (int idx = t; idx < KB * KB; idx += T) {
+    const int r = idx / KB, c = idx % KB;
+    U[r][c] = (r < jb && c < jb) ? A[(size_t)(j0 + r) * ldaug + j0 + c] : (r == c ? 1.0 : 0.0);
   }
-  const int q = blockIdx.x * TRSM_T + t;
-  const bool valid = q < rhs;
-  const long col = roff + (valid ? q : 0);
-  for (int r = 0; r < jb; ++r) sx[r][t] = valid ? A[(size_t)(j0 + r) * ldaug + col] : 0.0;
   __syncthreads();
-  for (int r = jb - 1; r >= 0; --r) {
-    double acc = sx[r][t];
-    for (int c = r + 1; c < jb; ++c) acc -= U[r][c] * sx[c][t];
-    sx[r][t] = U[r][r] != 0.0 ? acc / U[r][r] : 0.0;
-  }
-  if (valid)
-    for (int r = 0; r < jb; ++r) A[(size_t)(j0 + r) * ldaug + col] = sx[r][t];
+  const int q = blockIdx.x * T + t;
+  if (q >= rhs) return;
+  const long col = roff + q;
+  double x[KB];
+  static_for([&](auto rI) {
+    constexpr int r = decltype(rI)::value;
+    x[r] = r < jb ? A[(size_t)(j0 + r) * ldaug + col] : 0.0;
+  }, std::make_integer_sequence<int, KB>{});
+  static_for([&](auto rI) {
+    constexpr int r = KB - 1 - decltype(rI)::value;
+    const double d = U[r][r];
+    x[r] = d != 0.0 ? x[r] / d : 0.0;
+    static_for([&](auto iI) {
+      constexpr int i = decltype(iI)::value;
+      if constexpr (i < r) x[i] -= U[i][r] * x[r];
+    }, std::make_integer_sequence<int, KB>{});
+  }, std::make_integer_sequence<int, KB>{});
+  static_for([&](auto rI) {
+    constexpr int r = decltype(rI)::value;
+    if (r < jb) A[(size_t)(j0 + r) * ldaug + col] = x[r];
+  }, std::make_integer_sequence<int, KB>{});
 }
 
-// Back substitution, update above the block: B[0:j0] -= U[0:j0, j0:j0+jb] Y_b.
-__global__ __launch_bounds__(256) void k_bs_update(int j0, const int *__restrict__ dims,
-                                                   double *__restrict__ aug, long ldaug, long strideA,
-                                                   long roff, int tiles_n) {
+// Back substitution, update above the block: B[0:j0] -= U[0:j0, j0:j0+jb] Y_b,
+// with the C tile loaded before the operands are staged.
+template <int KB>
+__global__ __launch_bounds__(256) void k_bs_update(int j0, const int *__restrict__ dims, double *__restrict__ aug,
+                                                   long ldaug, long strideA, long roff, int tiles_n) {
   const int e = blockIdx.y;
   const int rows = dims[2 * e], rhs = dims[2 * e + 1];
   if (j0 >= rows || j0 == 0) return;
-  const int jb = min(NB, rows - j0);
+  const int jb = min(KB, rows - j0);
   const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
   const int r0 = tm * TILE, q0 = tn * TILE;
   if (r0 >= j0 || q0 >= rhs) return;
   double *A = aug + (size_t)e * strideA;
-  __shared__ double sU[NB][TILE];  // sU[k][i] = U[r0 + i][j0 + k]
-  __shared__ double sY[NB][TILE];  // sY[k][j] = Y[j0 + k][q0 + j]
   const int t = threadIdx.x;
-  for (int idx = t; idx < NB * TILE; idx += 256) {
-    const int i = idx / NB, k = idx % NB;
-    sU[k][i] = (r0 + i < j0 && k < jb) ? A[(size_t)(r0 + i) * ldaug + j0 + k] : 0.0;
+  const int lane = t & 63, wave = t >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int kk = lane >> 4, ii = lane & 15;
+  double cv[4][4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = r0 + wr * 32 + (q >> 1) * 16 + 4 * v + kk;
+      const int j = q0 + wc * 32 + (q & 1) * 16 + ii;
+      cv[q][v] = (i < j0 && j < rhs) ? A[(size_t)i * ldaug + roff + j] : 0.0;
+    }
+  __shared__ double sU[TILE][Pitch<KB>::A];  // sU[i][k] = U[r0 + i][j0 + k]
+  __shared__ double sY[KB][PB];              // sY[k][j] = Y[j0 + k][q0 + j]
+  for (int idx = t; idx < KB * TILE; idx += 256) {
+    const int i = idx / KB, k = idx % KB;
+    sU[i][k] = (r0 + i < j0 && k < jb) ? A[(size_t)(r0 + i) * ldaug + j0 + k] : 0.0;
   }
-  for (int idx = t; idx < NB * TILE; idx += 256) {
+  for (int idx = t; idx < KB * TILE; idx += 256) {
     const int k = idx / TILE, j = idx % TILE;
     sY[k][j] = (q0 + j < rhs && k < jb) ? A[(size_t)(j0 + k) * ldaug + roff + q0 + j] : 0.0;
   }
   __syncthreads();
-  const int lane = t & 63, wave = t >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
-  const int kk = lane >> 4, ii = lane & 15;
   d4 acc[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) acc[q] = d4{0, 0, 0, 0};
-#pragma unroll
-  for (int ks = 0; ks < NB; ks += 4) {
-    const double a0 = sU[ks + kk][wr * 32 + ii], a1 = sU[ks + kk][wr * 32 + 16 + ii];
-    const double b0 = sY[ks + kk][wc * 32 + ii], b1 = sY[ks + kk][wc * 32 + 16 + ii];
-    acc[0] = mfma64(a0, b0, acc[0]);
-    acc[1] = mfma64(a0, b1, acc[1]);
-    acc[2] = mfma64(a1, b0, acc[2]);
-    acc[3] = mfma64(a1, b1, acc[3]);
-  }
+  mfma_slab<KB>(sU, sY, acc, wr, wc, kk, ii);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int j = q0 + wc * 32 + (q & 1) * 16 + ii;
@@ -472,46 +687,70 @@ __global__ __launch_bounds__(256) void k_bs_update(int j0, const int *__restrict
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int i = r0 + wr * 32 + (q >> 1) * 16 + 4 * v + kk;
-      if (i < j0) A[(size_t)i * ldaug + roff + j] -= acc[q][v];
+      if (i < j0) A[(size_t)i * ldaug + roff + j] = cv[q][v] - acc[q][v];
     }
   }
 }
 
+namespace {
+void launch_panel(hipStream_t s, int ne, int j0, int h, const int *dims, double *aug, long ldaug, long strideA,
+                  int *ipiv, long ldp, int *status) {
+  if (h <= PREG_T)
+    hipLaunchKernelGGL(k_lu_panel_reg<1>, dim3(ne), dim3(PREG_T), 0, s, j0, dims, aug, ldaug, strideA, ipiv, ldp,
+                       status);
+  else if (h <= 2 * PREG_T)
+    hipLaunchKernelGGL(k_lu_panel_reg<2>, dim3(ne), dim3(PREG_T), 0, s, j0, dims, aug, ldaug, strideA, ipiv, ldp,
+                       status);
+  else if (h <= 3 * PREG_T)
+    hipLaunchKernelGGL(k_lu_panel_reg<3>, dim3(ne), dim3(PREG_T), 0, s, j0, dims, aug, ldaug, strideA, ipiv, ldp,
+                       status);
+  else
+    hipLaunchKernelGGL(k_lu_panel, dim3(ne), dim3(PANEL_T), 0, s, j0, dims, aug, ldaug, strideA, ipiv, ldp,
+                       status);
+}
+}  // namespace
+
+// Outer blocks of NBU = 2 NB columns: factor the first panel, bring the second
+// panel up to date (interchanges, triangular solve, rank-NB update), factor it,
+// align the first panel's rows with its interchanges, then one triangular solve
+// and one rank-NBU update for everything right of the block.
 void launch_lu_solve(hipStream_t s, int ne, int maxrows, int maxrhs, const int *dims, double *aug,
-                     long ldaug, long strideA, long roff, int *ipiv, long ldp, int *status) {
-  for (int j0 = 0; j0 < maxrows; j0 += NB) {
-    const int h = maxrows - j0;
-    if (h <= PREG_T)
-      hipLaunchKernelGGL(k_lu_panel_reg<1>, dim3(ne), dim3(PREG_T), 0, s, j0, dims, aug, ldaug, strideA, ipiv, ldp,
-                         status);
-    else if (h <= 2 * PREG_T)
-      hipLaunchKernelGGL(k_lu_panel_reg<2>, dim3(ne), dim3(PREG_T), 0, s, j0, dims, aug, ldaug, strideA, ipiv, ldp,
-                         status);
-    else if (h <= 3 * PREG_T)
-      hipLaunchKernelGGL(k_lu_panel_reg<3>, dim3(ne), dim3(PREG_T), 0, s, j0, dims, aug, ldaug, strideA, ipiv, ldp,
-                         status);
-    else
-      hipLaunchKernelGGL(k_lu_panel, dim3(ne), dim3(PANEL_T), 0, s, j0, dims, aug, ldaug, strideA, ipiv, ldp,
-                         status);
-    const int c0 = min(maxrows, j0 + NB);
+                     long ldaug, long strideA, long roff, int *ipiv, long ldp, int *bperm, double *linv,
+                     int *status) {
+  constexpr int T32 = 128, T64 = 64;
+  for (int j0 = 0; j0 < maxrows; j0 += NBU) {
+    launch_panel(s, ne, j0, maxrows - j0, dims, aug, ldaug, strideA, ipiv, ldp, status);
+    const int p1 = j0 + NB;
+    if (p1 < maxrows) {
+      // second panel's columns [p1, p1 + NB): no right-hand sides
+      hipLaunchKernelGGL((k_lu_trsm<NB, T32>), dim3((NB + T32 - 1) / T32, ne), dim3(T32), 0, s, j0, dims, aug,
+                         ldaug, strideA, roff, ipiv, ldp, 0, NB);
+      const int tm = (maxrows - p1 + TILE - 1) / TILE;
+      hipLaunchKernelGGL(k_lu_update<NB>, dim3(tm, ne), dim3(256), 0, s, j0, dims, aug, ldaug, strideA, roff, 1, 0,
+                         NB);
+      launch_panel(s, ne, p1, maxrows - p1, dims, aug, ldaug, strideA, ipiv, ldp, status);
+    }
+    hipLaunchKernelGGL(k_lu_blockperm, dim3(ne), dim3(64), 0, s, j0, dims, aug, ldaug, strideA, ipiv, ldp, bperm,
+                       linv);
+    const int c0 = std::min(maxrows, j0 + NBU);
     const int ncols = (maxrows - c0) + maxrhs;
     if (ncols <= 0) continue;
-    hipLaunchKernelGGL(k_lu_trsm, dim3((ncols + TRSM_T - 1) / TRSM_T, ne), dim3(TRSM_T), 0, s, j0, dims, aug,
-                       ldaug, strideA, roff, ipiv, ldp);
+    hipLaunchKernelGGL(k_lu_trsm_inv, dim3((ncols + TILE - 1) / TILE, ne), dim3(256), 0, s, j0, dims, aug, ldaug,
+                       strideA, roff, bperm, linv);
     const int m = maxrows - c0;
     if (m <= 0) continue;
     const int tm = (m + TILE - 1) / TILE, tn = (ncols + TILE - 1) / TILE;
-    hipLaunchKernelGGL(k_lu_update, dim3(tm * tn, ne), dim3(256), 0, s, j0, dims, aug, ldaug, strideA,
-                       roff, tn);
+    hipLaunchKernelGGL(k_lu_update<NBU>, dim3(tm * tn, ne), dim3(256), 0, s, j0, dims, aug, ldaug, strideA, roff,
+                       tn, 1, 1 << 30);
   }
   if (maxrhs <= 0) return;
-  for (int j0 = (maxrows - 1) / NB * NB; j0 >= 0; j0 -= NB) {
-    hipLaunchKernelGGL(k_bs_block, dim3((maxrhs + TRSM_T - 1) / TRSM_T, ne), dim3(TRSM_T), 0, s, j0, dims, aug,
+  for (int j0 = (maxrows - 1) / NBU * NBU; j0 >= 0; j0 -= NBU) {
+    hipLaunchKernelGGL((k_bs_block<NBU, T64>), dim3((maxrhs + T64 - 1) / T64, ne), dim3(T64), 0, s, j0, dims, aug,
                        ldaug, strideA, roff);
     if (j0 == 0) break;
     const int tm = (j0 + TILE - 1) / TILE, tn = (maxrhs + TILE - 1) / TILE;
-    hipLaunchKernelGGL(k_bs_update, dim3(tm * tn, ne), dim3(256), 0, s, j0, dims, aug, ldaug, strideA,
-                       roff, tn);
+    hipLaunchKernelGGL(k_bs_update<NBU>, dim3(tm * tn, ne), dim3(256), 0, s, j0, dims, aug, ldaug, strideA, roff,
+                       tn);
   }
 }
 
@@ -522,6 +761,8 @@ __global__ __launch_bounds__(256) void k_gemm_sq(const int *__restrict__ nopen, 
                                                  long lda, long sA, const double *__restrict__ B, long ldb,
                                                  long sB, double *__restrict__ C, long ldc, long sC,
                                                  int tiles_n) {
+  constexpr int GK = 32;
+  constexpr int NL = TILE * GK / 256;  // slab elements per thread (A and B each)
   const int e = blockIdx.y;
   const int n = nopen[e];
   const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
@@ -530,34 +771,38 @@ __global__ __launch_bounds__(256) void k_gemm_sq(const int *__restrict__ nopen, 
   const double *Ae = A + (size_t)e * sA;
   const double *Be = B + (size_t)e * sB;
   double *Ce = C + (size_t)e * sC;
-  __shared__ double sa[16][TILE];  // sa[k][i] = A[r0 + i][k0 + k]
-  __shared__ double sb[16][TILE];  // sb[k][j] = B[k0 + k][q0 + j]
+  __shared__ double sa[TILE][Pitch<GK>::A];  // sa[i][k] = A[r0 + i][k0 + k]
+  __shared__ double sb[GK][PB];              // sb[k][j] = B[k0 + k][q0 + j]
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int kk = lane >> 4, ii = lane & 15;
+  // the next slab is loaded into registers while the current one is multiplied
+  double ra[NL], rb[NL];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int idx = t + 256 * q;
+      const int i = idx / GK, k = idx % GK;
+      ra[q] = (r0 + i < n && k0 + k < n) ? Ae[(size_t)(r0 + i) * lda + k0 + k] : 0.0;
+      const int kb = idx / TILE, j = idx % TILE;
+      rb[q] = (q0 + j < n && k0 + kb < n) ? Be[(size_t)(k0 + kb) * ldb + q0 + j] : 0.0;
+    }
+  };
   d4 acc[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) acc[q] = d4{0, 0, 0, 0};
-  for (int k0 = 0; k0 < n; k0 += 16) {
-    for (int idx = t; idx < 16 * TILE; idx += 256) {
-      const int i = idx / 16, k = idx % 16;
-      sa[k][i] = (r0 + i < n && k0 + k < n) ? Ae[(size_t)(r0 + i) * lda + k0 + k] : 0.0;
-    }
-    for (int idx = t; idx < 16 * TILE; idx += 256) {
-      const int k = idx / TILE, j = idx % TILE;
-      sb[k][j] = (q0 + j < n && k0 + k < n) ? Be[(size_t)(k0 + k) * ldb + q0 + j] : 0.0;
+  gload(0);
+  for (int k0 = 0; k0 < n; k0 += GK) {
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int idx = t + 256 * q;
+      sa[idx / GK][idx % GK] = ra[q];
+      sb[idx / TILE][idx % TILE] = rb[q];
     }
     __syncthreads();
-#pragma unroll
-    for (int ks = 0; ks < 16; ks += 4) {
-      const double a0 = sa[ks + kk][wr * 32 + ii], a1 = sa[ks + kk][wr * 32 + 16 + ii];
-      const double b0 = sb[ks + kk][wc * 32 + ii], b1 = sb[ks + kk][wc * 32 + 16 + ii];
-      acc[0] = mfma64(a0, b0, acc[0]);
-      acc[1] = mfma64(a0, b1, acc[1]);
-      acc[2] = mfma64(a1, b0, acc[2]);
-      acc[3] = mfma64(a1, b1, acc[3]);
-    }
+    if (k0 + GK < n) gload(k0 + GK);
+    mfma_slab<GK>(sa, sb, acc, wr, wc, kk, ii);
     __syncthreads();
   }
 #pragma unroll

@@ -14,8 +14,15 @@ constexpr int KC64 = 32;
 constexpr int KC32 = 64;
 // Energies that share one staged amplitude panel in the R contraction.
 constexpr int EB = 4;
-// Panel width of the blocked LU.
+// Panel width of the blocked LU (one register-resident panel) and the outer
+// block: two panels are factored, then the trailing matrix is updated once
+// with a rank-NBU product.
 constexpr int NB = 32;
+constexpr int NBU = 2 * NB;
+// Net row permutation of one outer block's interchanges, per energy: [0] the
+// number of rows outside the block that receive a row, then NBU source rows of
+// the block's rows, NBU source rows of those outside rows and their NBU indices.
+constexpr int BPERM = 1 + 3 * NBU;
 
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
@@ -90,6 +97,8 @@ struct Work {
   double *XK = nullptr;      // [cap_e][nmax][ldk]
   int *dims = nullptr;       // [cap_e][2] per-energy (rows, rhs) for batched LU
   int *ipiv = nullptr;       // [cap_e][ldo] LU row interchanges
+  int *bperm = nullptr;      // [cap_e][BPERM] net permutation of the current LU block
+  double *linv = nullptr;    // [cap_e][NBU][NBU] inverse of the current block's unit lower L11
   double *omega = nullptr;   // [cap_e][ntmax][ntmax]
   double *pack = nullptr;    // packed outputs, [cap_e][nmax][nmax] doubles
   long *pack_off = nullptr;  // [cap_e + 1] offsets of each energy's packed block
@@ -116,9 +125,11 @@ void launch_build(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi,
 // Batched LU with partial pivoting of [A | B] per energy (dims[2e] = rows of the
 // square A in columns [0, rows), dims[2e+1] = right-hand sides in columns
 // [roff, roff + rhs)), then back substitution: on return the right-hand-side
-// columns hold A^-1 B.  Exact zero pivots set RM_PT_SINGULAR.
+// columns hold A^-1 B.  Exact zero pivots set RM_PT_SINGULAR.  bperm (ne * BPERM
+// ints) and linv (ne * NBU * NBU doubles) are scratch.
 void launch_lu_solve(hipStream_t s, int ne, int maxrows, int maxrhs, const int *dims, double *aug,
-                     long ldaug, long strideA, long roff, int *ipiv, long ldp, int *status);
+                     long ldaug, long strideA, long roff, int *ipiv, long ldp, int *bperm, double *linv,
+                     int *status);
 // C[e] = A[e] B[e] for square no x no blocks, no = nopen[e]
 void launch_gemm_sq(hipStream_t s, int ne, int maxn, const int *nopen, const double *A, long lda, long sA,
                     const double *B, long ldb, long sB, double *C, long ldc, long sC);

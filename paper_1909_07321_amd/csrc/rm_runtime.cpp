@@ -149,12 +149,12 @@ size_t per_energy_bytes(int n, int npad, int Mpad, int nt) {
          + (size_t)Mpad * 12         // D64 + D32
          + (size_t)n * (32 + 13)     // fg, openidx, openpos, openflag, ipiv
          + (size_t)nt * nt * 8       // Omega
-         + 128;
+         + BPERM * 4 + NBU * NBU * 8 + 128;
 }
 
 void free_work(Work &w) {
   void *ptrs[] = {w.E, w.pwi, w.tab, w.tasks, w.counter, w.D64, w.D32, w.win, w.status, w.nopen, w.openidx,
-                  w.openpos, w.openflag, w.fg, w.aug, w.Kw, w.XK, w.dims, w.ipiv, w.omega, w.pack, w.pack_off,
+                  w.openpos, w.openflag, w.fg, w.aug, w.Kw, w.XK, w.dims, w.ipiv, w.bperm, w.linv, w.omega, w.pack, w.pack_off,
                   w.S};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -196,7 +196,8 @@ rm_status ensure_slot(rm_ctx *ctx, Slot &sl, const Lay &L, int ntab, int ntasks,
                  bK = sz((size_t)ce * cn * cnp * 8), bdims = sz((size_t)ce * 8),
                  bom = sz((size_t)ce * ct * ct * 8),
                  bpack = sz((size_t)ce * std::max((size_t)cn * cn, (size_t)ct * ct) * 8),
-                 boff = sz((size_t)(ce + 1) * 8), bS = S ? sz((size_t)ce * cn * cn * 16) : 0;
+                 boff = sz((size_t)(ce + 1) * 8), bS = S ? sz((size_t)ce * cn * cn * 16) : 0,
+                 bperm = sz((size_t)ce * BPERM * 4), blinv = sz((size_t)ce * NBU * NBU * 8);
     // openpos and ipiv share bidx's size, XK shares bK's, the pack offsets are two blocks
     need += 2 * ((bidx + 255) / 256 * 256) + (bK + 255) / 256 * 256 + (boff + 255) / 256 * 256;
     {
@@ -226,6 +227,8 @@ rm_status ensure_slot(rm_ctx *ctx, Slot &sl, const Lay &L, int ntab, int ntasks,
     HIPCHK(hipMalloc(&w.openidx, bidx));
     HIPCHK(hipMalloc(&w.openpos, bidx));
     HIPCHK(hipMalloc(&w.ipiv, bidx));
+    HIPCHK(hipMalloc(&w.bperm, bperm));
+    HIPCHK(hipMalloc(&w.linv, blinv));
     HIPCHK(hipMalloc(&w.openflag, bflag));
     HIPCHK(hipMalloc(&w.fg, bfg));
     HIPCHK(hipMalloc(&w.aug, baug));
@@ -418,7 +421,7 @@ void stage_K(const Plan &P, Work &w, hipStream_t s) {
   const Lay &L = P.L;
   launch_setdims(s, L, w.tab, w.pwi, w.nopen, w.dims);
   launch_build(s, L, w.tab, w.pwi, w.fg, w.nopen, w.openidx, w.aug);
-  launch_lu_solve(s, L.ne, L.nmax, L.nmax, w.dims, w.aug, L.ldaug, L.sA, L.roff, w.ipiv, L.ldo, w.status);
+  launch_lu_solve(s, L.ne, L.nmax, L.nmax, w.dims, w.aug, L.ldaug, L.sA, L.roff, w.ipiv, L.ldo, w.bperm, w.linv, w.status);
   launch_gatherK(s, L, w.nopen, w.openidx, w.aug, w.Kw);
 }
 
@@ -427,7 +430,7 @@ void stage_SO(const Plan &P, Work &w, bool want_S, hipStream_t s) {
   const Lay &L = P.L;
   launch_gemm_sq(s, L.ne, L.nmax, w.nopen, w.Kw, L.ldk, L.sK, w.Kw, L.ldk, L.sK, w.aug, L.ldaug, L.sA);
   launch_formP(s, L, w.nopen, w.Kw, w.aug, w.dims);
-  launch_lu_solve(s, L.ne, L.nmax, L.nmax, w.dims, w.aug, L.ldaug, L.sA, L.roff, w.ipiv, L.ldo, w.status);
+  launch_lu_solve(s, L.ne, L.nmax, L.nmax, w.dims, w.aug, L.ldaug, L.sA, L.roff, w.ipiv, L.ldo, w.bperm, w.linv, w.status);
   launch_gemm_sq(s, L.ne, L.nmax, w.nopen, w.aug + L.roff, L.ldaug, L.sA, w.Kw, L.ldk, L.sK, w.XK, L.ldk, L.sK);
   launch_omega(s, L, w.tab, w.pwi, w.openpos, w.nopen, w.aug + L.roff, w.XK, w.omega, want_S ? w.S : nullptr);
 }

@@ -16,6 +16,9 @@
 //
 // Augmented layout per energy: rows [0, rows), A in columns [0, rows), the
 // right-hand sides in columns [roff, roff + rhs), row stride ldaug.
+#include <algorithm>
+#include <map>
+#include <mutex>
 #include <type_traits>
 #include <utility>
 
@@ -45,6 +48,19 @@ __device__ __forceinline__ void static_for(F &&f, std::integer_sequence<int, I..
 // distinct LDS banks, and the staging stores are row-contiguous.
 constexpr int PB = TILE + 16;
 template <int K> struct Pitch { static constexpr int A = K + 2; };
+
+// Persistent distribution of per-energy work items: energy e belongs to XCD
+// e % NQ (workgroup b runs on XCD b % NQ), and the items of an XCD's energies go
+// round-robin to its workgroups, so the items of one energy share one L2 and no
+// workgroup is launched for an item that turns out to be empty.  f(e, r) runs
+// item r of energy e; its early returns must be uniform over the workgroup.
+template <typename F>
+__device__ __forceinline__ void for_items(int ne, int ipe, F &&f) {
+  const int x = blockIdx.x % NQ, l = blockIdx.x / NQ, nl = gridDim.x / NQ;
+  const int nex = ne > x ? (ne - x + NQ - 1) / NQ : 0;
+  const long total = (long)nex * ipe;
+  for (long u = l; u < total; u += nl) f(x + NQ * (int)(u / ipe), (int)(u % ipe));
+}
 
 // acc += A_slab (64 x K) * B_slab (K x 64): every wave owns a 32 x 32 quarter.
 template <int K>
@@ -424,66 +440,69 @@ __global__ __launch_bounds__(64) void k_lu_blockperm(int p0, const int *__restri
 // rows, then forms the 64 x 64 product.
 __global__ __launch_bounds__(256) void k_lu_trsm_inv(int p0, const int *__restrict__ dims, double *__restrict__ aug,
                                                      long ldaug, long strideA, long roff,
-                                                     const int *__restrict__ bperm, const double *__restrict__ linv) {
+                                                     const int *__restrict__ bperm, const double *__restrict__ linv,
+                                                     int tiles_n, int ne) {
   constexpr int KB = NBU;
-  const int e = blockIdx.y;
-  const int rows = dims[2 * e], rhs = dims[2 * e + 1];
-  if (p0 >= rows) return;
-  const int jb = min(KB, rows - p0);
-  const int c0 = p0 + jb;
-  const int ncols = (rows - c0) + rhs;
-  const int v0 = blockIdx.x * TILE;
-  if (v0 >= ncols) return;
-  double *A = aug + (size_t)e * strideA;
-  const int *pm = bperm + (size_t)e * BPERM;
-  const double *Li = linv + (size_t)e * KB * KB;
   __shared__ double sL[KB][Pitch<KB>::A];  // sL[i][k] = Linv[i][k]
   __shared__ double sX[KB][PB];            // sX[k][j] = (P A12)[k][v0 + j]
   __shared__ int sp[1 + 3 * KB];
   __shared__ long scol[TILE];
   const int t = threadIdx.x;
-  for (int idx = t; idx < 1 + 3 * KB; idx += 256) sp[idx] = pm[idx];
-  if (t < TILE) scol[t] = v0 + t < ncols ? vcol(v0 + t, rows, c0, roff) : -1;
-  for (int idx = t; idx < KB * KB; idx += 256) sL[idx / KB][idx % KB] = Li[idx];
-  __syncthreads();
-  const int nout = sp[0];
-  for (int idx = t; idx < KB * TILE; idx += 256) {
-    const int k = idx / TILE, j = idx % TILE;
-    const long col = scol[j];
-    sX[k][j] = (k < jb && col >= 0) ? A[(size_t)sp[1 + k] * ldaug + col] : 0.0;
-  }
-  constexpr int NY = KB * TILE / 256;
-  double yv[NY];
-#pragma unroll
-  for (int q = 0; q < NY; ++q) {
-    const int idx = t + 256 * q, k = idx / TILE, j = idx % TILE;
-    const long col = scol[j];
-    yv[q] = (k < nout && col >= 0) ? A[(size_t)sp[1 + KB + k] * ldaug + col] : 0.0;
-  }
-  __syncthreads();  // every load of the workgroup has completed
-#pragma unroll
-  for (int q = 0; q < NY; ++q) {
-    const int idx = t + 256 * q, k = idx / TILE, j = idx % TILE;
-    const long col = scol[j];
-    if (k < nout && col >= 0) A[(size_t)sp[1 + 2 * KB + k] * ldaug + col] = yv[q];
-  }
   const int lane = t & 63, wave = t >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int kk = lane >> 4, ii = lane & 15;
-  d4 acc[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) acc[q] = d4{0, 0, 0, 0};
-  mfma_slab<KB>(sL, sX, acc, wr, wc, kk, ii);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const long col = scol[wc * 32 + (q & 1) * 16 + ii];
-    if (col < 0) continue;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = wr * 32 + (q >> 1) * 16 + 4 * v + kk;
-      if (i < jb) A[(size_t)(p0 + i) * ldaug + col] = acc[q][v];
+  for_items(ne, tiles_n, [&](int e, int tile) {
+    const int rows = dims[2 * e], rhs = dims[2 * e + 1];
+    if (p0 >= rows) return;
+    const int jb = min(KB, rows - p0);
+    const int c0 = p0 + jb;
+    const int ncols = (rows - c0) + rhs;
+    const int v0 = tile * TILE;
+    if (v0 >= ncols) return;
+    double *A = aug + (size_t)e * strideA;
+    const int *pm = bperm + (size_t)e * BPERM;
+    const double *Li = linv + (size_t)e * KB * KB;
+    for (int idx = t; idx < 1 + 3 * KB; idx += 256) sp[idx] = pm[idx];
+    if (t < TILE) scol[t] = v0 + t < ncols ? vcol(v0 + t, rows, c0, roff) : -1;
+    for (int idx = t; idx < KB * KB; idx += 256) sL[idx / KB][idx % KB] = Li[idx];
+    __syncthreads();
+    const int nout = sp[0];
+    for (int idx = t; idx < KB * TILE; idx += 256) {
+      const int k = idx / TILE, j = idx % TILE;
+      const long col = scol[j];
+      sX[k][j] = (k < jb && col >= 0) ? A[(size_t)sp[1 + k] * ldaug + col] : 0.0;
     }
-  }
+    constexpr int NY = KB * TILE / 256;
+    double yv[NY];
+#pragma unroll
+    for (int q = 0; q < NY; ++q) {
+      const int idx = t + 256 * q, k = idx / TILE, j = idx % TILE;
+      const long col = scol[j];
+      yv[q] = (k < nout && col >= 0) ? A[(size_t)sp[1 + KB + k] * ldaug + col] : 0.0;
+    }
+    __syncthreads();  // every load of the workgroup has completed
+#pragma unroll
+    for (int q = 0; q < NY; ++q) {
+      const int idx = t + 256 * q, k = idx / TILE, j = idx % TILE;
+      const long col = scol[j];
+      if (k < nout && col >= 0) A[(size_t)sp[1 + 2 * KB + k] * ldaug + col] = yv[q];
+    }
+    d4 acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = d4{0, 0, 0, 0};
+    mfma_slab<KB>(sL, sX, acc, wr, wc, kk, ii);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const long col = scol[wc * 32 + (q & 1) * 16 + ii];
+      if (col < 0) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = wr * 32 + (q >> 1) * 16 + 4 * v + kk;
+        if (i < jb) A[(size_t)(p0 + i) * ldaug + col] = acc[q][v];
+      }
+    }
+    __syncthreads();  // LDS is reused by the next item
+  });
 }
 
 // For trailing columns of the block of kb rows starting at p0 (columns [p0 +
@@ -531,70 +550,96 @@ __global__ __launch_bounds__(T) void k_lu_trsm(int p0, const int *__restrict__ d
   }
 }
 
-// Trailing update A22 -= L21 U12 for the block of kb columns starting at p0:
-// rows [c0, rows) with c0 = p0 + jb, trailing columns as in trailing_cols.
-// 64 x 64 output tiles, K = jb, FP64 MFMA; the C tile is loaded into registers
-// before the operands are staged, so its latency overlaps the staging.
-template <int KB>
-__global__ __launch_bounds__(256) void k_lu_update(int p0, const int *__restrict__ dims, double *__restrict__ aug,
-                                                   long ldaug, long strideA, long roff, int tiles_n, int with_rhs,
-                                                   int vlimit) {
-  const int e = blockIdx.y;
-  const int rows = dims[2 * e], rhs = dims[2 * e + 1];
-  if (p0 >= rows) return;
-  const int jb = min(KB, rows - p0);
-  const int c0 = p0 + jb;
-  const int m = rows - c0;
-  const int ncols = trailing_cols(rows, rhs, c0, with_rhs, vlimit);
-  const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
-  const int r0 = tm * TILE, v0 = tn * TILE;
-  if (r0 >= m || v0 >= ncols) return;
-  double *A = aug + (size_t)e * strideA;
+// C (64 rows x G column tiles) -= Lb (64 x KB, staged in sL) * U (KB x columns),
+// one column tile at a time: a tile's C values are loaded while its product is
+// formed, and the next tile's U slab is loaded into registers meanwhile.
+// cptr(i, v) addresses C's element (i, v); uval(k, v) returns U's element
+// (k, v) (0 past the block).
+template <int KB, int G, typename CPtr, typename UVal>
+__device__ __forceinline__ void rowblock_update(const double (*sL)[Pitch<KB>::A], double (*sU)[PB], int mrem,
+                                                int vbeg, int ncols, CPtr cptr, UVal uval) {
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int kk = lane >> 4, ii = lane & 15;
-  // this thread's 16 C elements: (q, v) -> row r0 + wr*32 + (q>>1)*16 + 4v + kk, virtual column v0 + wc*32 + (q&1)*16 + ii
-  double cv[4][4];
-  long ccol[2];
-  bool cok[2];
+  constexpr int NU = KB * TILE / 256;
+  double nu[NU];
+  auto loadU = [&](int v0) {
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int jv = v0 + wc * 32 + h * 16 + ii;
-    cok[h] = jv < ncols;
-    ccol[h] = cok[h] ? vcol(jv, rows, c0, roff) : 0;
-  }
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = r0 + wr * 32 + (q >> 1) * 16 + 4 * v + kk;
-      cv[q][v] = (cok[q & 1] && i < m) ? A[(size_t)(c0 + i) * ldaug + ccol[q & 1]] : 0.0;
+    for (int q = 0; q < NU; ++q) {
+      const int idx = t + 256 * q, k = idx / TILE, j = idx % TILE;
+      nu[q] = v0 + j < ncols ? uval(k, v0 + j) : 0.0;
     }
+  };
+  loadU(vbeg);
+  for (int g = 0; g < G; ++g) {
+    const int v0 = vbeg + g * TILE;
+    if (v0 >= ncols) break;
+#pragma unroll
+    for (int q = 0; q < NU; ++q) {
+      const int idx = t + 256 * q;
+      sU[idx / TILE][idx % TILE] = nu[q];
+    }
+    __syncthreads();
+    double cv[16];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = wr * 32 + (q >> 1) * 16 + 4 * v + kk;
+        const int jv = v0 + wc * 32 + (q & 1) * 16 + ii;
+        cv[q * 4 + v] = (i < mrem && jv < ncols) ? *cptr(i, jv) : 0.0;
+      }
+    if (g + 1 < G && v0 + TILE < ncols) loadU(v0 + TILE);
+    d4 acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = d4{0, 0, 0, 0};
+    mfma_slab<KB>(sL, sU, acc, wr, wc, kk, ii);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = wr * 32 + (q >> 1) * 16 + 4 * v + kk;
+        const int jv = v0 + wc * 32 + (q & 1) * 16 + ii;
+        if (i < mrem && jv < ncols) *cptr(i, jv) = cv[q * 4 + v] - acc[q][v];
+      }
+    __syncthreads();
+  }
+}
+
+// Column tiles per workgroup of the streaming updates.
+constexpr int UPD_G = 4;
+
+// Trailing update A22 -= L21 U12 for the block of kb columns starting at p0:
+// rows [c0, rows) with c0 = p0 + jb, trailing columns as in trailing_cols.
+// Items: (energy, column group of UPD_G tiles, 64-row block), FP64 MFMA.
+template <int KB>
+__global__ __launch_bounds__(256, 2) void k_lu_update(int p0, const int *__restrict__ dims, double *__restrict__ aug,
+                                                   long ldaug, long strideA, long roff, int tiles_m, int groups,
+                                                   int ne, int with_rhs, int vlimit) {
   __shared__ double sL[TILE][Pitch<KB>::A];  // sL[i][k] = L21[r0 + i][k]
   __shared__ double sU[KB][PB];              // sU[k][j] = U12[k][v0 + j]
-  for (int idx = t; idx < KB * TILE; idx += 256) {
-    const int i = idx / KB, k = idx % KB;
-    sL[i][k] = (r0 + i < m && k < jb) ? A[(size_t)(c0 + r0 + i) * ldaug + p0 + k] : 0.0;
-  }
-  for (int idx = t; idx < KB * TILE; idx += 256) {
-    const int k = idx / TILE, j = idx % TILE;
-    sU[k][j] = (v0 + j < ncols && k < jb) ? A[(size_t)(p0 + k) * ldaug + vcol(v0 + j, rows, c0, roff)] : 0.0;
-  }
-  __syncthreads();
-  d4 acc[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) acc[q] = d4{0, 0, 0, 0};
-  mfma_slab<KB>(sL, sU, acc, wr, wc, kk, ii);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    if (!cok[q & 1]) continue;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = r0 + wr * 32 + (q >> 1) * 16 + 4 * v + kk;
-      if (i < m) A[(size_t)(c0 + i) * ldaug + ccol[q & 1]] = cv[q][v] - acc[q][v];
+  for_items(ne, tiles_m * groups, [&](int e, int it) {
+    const int tmi = it % tiles_m, g = it / tiles_m;
+    const int rows = dims[2 * e], rhs = dims[2 * e + 1];
+    if (p0 >= rows) return;
+    const int jb = min(KB, rows - p0);
+    const int c0 = p0 + jb;
+    const int m = rows - c0;
+    const int ncols = trailing_cols(rows, rhs, c0, with_rhs, vlimit);
+    const int r0 = tmi * TILE, vbeg = g * UPD_G * TILE;
+    if (r0 >= m || vbeg >= ncols) return;
+    double *A = aug + (size_t)e * strideA;
+    for (int idx = threadIdx.x; idx < KB * TILE; idx += 256) {
+      const int i = idx / KB, k = idx % KB;
+      sL[i][k] = (r0 + i < m && k < jb) ? A[(size_t)(c0 + r0 + i) * ldaug + p0 + k] : 0.0;
     }
-  }
+    double *Cb = A + (size_t)(c0 + r0) * ldaug;
+    rowblock_update<KB, UPD_G>(
+        sL, sU, m - r0, vbeg, ncols,
+        [&](int i, int v) { return Cb + (size_t)i * ldaug + vcol(v, rows, c0, roff); },
+        [&](int k, int v) { return k < jb ? A[(size_t)(p0 + k) * ldaug + vcol(v, rows, c0, roff)] : 0.0; });
+  });
 }
 
 // Back substitution, diagonal block: Y_b = U_bb^-1 B_b for the right-hand sides,
@@ -602,97 +647,101 @@ __global__ __launch_bounds__(256) void k_lu_update(int p0, const int *__restrict
 // (column-oriented: each solved entry is eliminated from the rows above it).
 template <int KB, int T>
 __global__ __launch_bounds__(T) void k_bs_block(int j0, const int *__restrict__ dims, double *__restrict__ aug,
-                                                long ldaug, long strideA, long roff) {
-  const int e = blockIdx.y;
-  const int rows = dims[2 * e], rhs = dims[2 * e + 1];
-  if (j0 >= rows) return;
-  if ((int)(blockIdx.x * T) >= rhs) return;
-  const int jb = min(KB, rows - j0);
-  double *A = aug + (size_t)e * strideA;
+                                                long ldaug, long strideA, long roff, int tiles, int ne) {
   __shared__ double U[KB][KB];
   const int t = threadIdx.x;
-  for (int idx = t; idx < KB * KB; idx += T) {
-    const int r = idx / KB, c = idx % KB;
-    U[r][c] = (r < jb && c < jb) ? A[(size_t)(j0 + r) * ldaug + j0 + c] : (r == c ? 1.0 : 0.0);
-  }
-  __syncthreads();
-  const int q = blockIdx.x * T + t;
-  if (q >= rhs) return;
-  const long col = roff + q;
-  double x[KB];
-  static_for([&](auto rI) {
-    constexpr int r = decltype(rI)::value;
-    x[r] = r < jb ? A[(size_t)(j0 + r) * ldaug + col] : 0.0;
-  }, std::make_integer_sequence<int, KB>{});
-  static_for([&](auto rI) {
-    constexpr int r = KB - 1 - decltype(rI)::value;
-    const double d = U[r][r];
-    x[r] = d != 0.0 ? x[r] / d : 0.0;
-    static_for([&](auto iI) {
-      constexpr int i = decltype(iI)::value;
-      if constexpr (i < r) x[i] -= U[i][r] * x[r];
-    }, std::make_integer_sequence<int, KB>{});
-  }, std::make_integer_sequence<int, KB>{});
-  static_for([&](auto rI) {
-    constexpr int r = decltype(rI)::value;
-    if (r < jb) A[(size_t)(j0 + r) * ldaug + col] = x[r];
-  }, std::make_integer_sequence<int, KB>{});
+  for_items(ne, tiles, [&](int e, int tile) {
+    const int rows = dims[2 * e], rhs = dims[2 * e + 1];
+    if (j0 >= rows || tile * T >= rhs) return;
+    const int jb = min(KB, rows - j0);
+    double *A = aug + (size_t)e * strideA;
+    for (int idx = t; idx < KB * KB; idx += T) {
+      const int r = idx / KB, c = idx % KB;
+      U[r][c] = (r < jb && c < jb) ? A[(size_t)(j0 + r) * ldaug + j0 + c] : (r == c ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    const int q = tile * T + t;
+    if (q < rhs) {
+      const long col = roff + q;
+      double x[KB];
+      static_for([&](auto rI) {
+        constexpr int r = decltype(rI)::value;
+        x[r] = r < jb ? A[(size_t)(j0 + r) * ldaug + col] : 0.0;
+      }, std::make_integer_sequence<int, KB>{});
+      static_for([&](auto rI) {
+        constexpr int r = KB - 1 - decltype(rI)::value;
+        const double d = U[r][r];
+        x[r] = d != 0.0 ? x[r] / d : 0.0;
+        static_for([&](auto iI) {
+          constexpr int i = decltype(iI)::value;
+          if constexpr (i < r) x[i] -= U[i][r] * x[r];
+        }, std::make_integer_sequence<int, KB>{});
+      }, std::make_integer_sequence<int, KB>{});
+      static_for([&](auto rI) {
+        constexpr int r = decltype(rI)::value;
+        if (r < jb) A[(size_t)(j0 + r) * ldaug + col] = x[r];
+      }, std::make_integer_sequence<int, KB>{});
+    }
+    __syncthreads();  // U is reused by the next item
+  });
 }
 
-// Back substitution, update above the block: B[0:j0] -= U[0:j0, j0:j0+jb] Y_b,
-// with the C tile loaded before the operands are staged.
+// Back substitution, update above the block: B[0:j0] -= U[0:j0, j0:j0+jb] Y_b.
+// Items: (energy, group of UPD_G right-hand-side tiles, 64-row block).
 template <int KB>
-__global__ __launch_bounds__(256) void k_bs_update(int j0, const int *__restrict__ dims, double *__restrict__ aug,
-                                                   long ldaug, long strideA, long roff, int tiles_n) {
-  const int e = blockIdx.y;
-  const int rows = dims[2 * e], rhs = dims[2 * e + 1];
-  if (j0 >= rows || j0 == 0) return;
-  const int jb = min(KB, rows - j0);
-  const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
-  const int r0 = tm * TILE, q0 = tn * TILE;
-  if (r0 >= j0 || q0 >= rhs) return;
-  double *A = aug + (size_t)e * strideA;
-  const int t = threadIdx.x;
-  const int lane = t & 63, wave = t >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
-  const int kk = lane >> 4, ii = lane & 15;
-  double cv[4][4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = r0 + wr * 32 + (q >> 1) * 16 + 4 * v + kk;
-      const int j = q0 + wc * 32 + (q & 1) * 16 + ii;
-      cv[q][v] = (i < j0 && j < rhs) ? A[(size_t)i * ldaug + roff + j] : 0.0;
-    }
+__global__ __launch_bounds__(256, 2) void k_bs_update(int j0, const int *__restrict__ dims, double *__restrict__ aug,
+                                                   long ldaug, long strideA, long roff, int tiles_m, int groups,
+                                                   int ne) {
   __shared__ double sU[TILE][Pitch<KB>::A];  // sU[i][k] = U[r0 + i][j0 + k]
   __shared__ double sY[KB][PB];              // sY[k][j] = Y[j0 + k][q0 + j]
-  for (int idx = t; idx < KB * TILE; idx += 256) {
-    const int i = idx / KB, k = idx % KB;
-    sU[i][k] = (r0 + i < j0 && k < jb) ? A[(size_t)(r0 + i) * ldaug + j0 + k] : 0.0;
-  }
-  for (int idx = t; idx < KB * TILE; idx += 256) {
-    const int k = idx / TILE, j = idx % TILE;
-    sY[k][j] = (q0 + j < rhs && k < jb) ? A[(size_t)(j0 + k) * ldaug + roff + q0 + j] : 0.0;
-  }
-  __syncthreads();
-  d4 acc[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) acc[q] = d4{0, 0, 0, 0};
-  mfma_slab<KB>(sU, sY, acc, wr, wc, kk, ii);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int j = q0 + wc * 32 + (q & 1) * 16 + ii;
-    if (j >= rhs) continue;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = r0 + wr * 32 + (q >> 1) * 16 + 4 * v + kk;
-      if (i < j0) A[(size_t)i * ldaug + roff + j] = cv[q][v] - acc[q][v];
+  for_items(ne, tiles_m * groups, [&](int e, int it) {
+    const int tmi = it % tiles_m, g = it / tiles_m;
+    const int rows = dims[2 * e], rhs = dims[2 * e + 1];
+    if (j0 >= rows || j0 == 0) return;
+    const int jb = min(KB, rows - j0);
+    const int r0 = tmi * TILE, qbeg = g * UPD_G * TILE;
+    if (r0 >= j0 || qbeg >= rhs) return;
+    double *A = aug + (size_t)e * strideA;
+    for (int idx = threadIdx.x; idx < KB * TILE; idx += 256) {
+      const int i = idx / KB, k = idx % KB;
+      sU[i][k] = (r0 + i < j0 && k < jb) ? A[(size_t)(r0 + i) * ldaug + j0 + k] : 0.0;
     }
-  }
+    double *Cb = A + (size_t)r0 * ldaug + roff;
+    rowblock_update<KB, UPD_G>(
+        sU, sY, j0 - r0, qbeg, rhs, [&](int i, int q) { return Cb + (size_t)i * ldaug + q; },
+        [&](int k, int q) { return k < jb ? A[(size_t)(j0 + k) * ldaug + roff + q] : 0.0; });
+  });
 }
 
 namespace {
+// Grid of a persistent for_items launch: enough workgroups to fill every CU at
+// the kernel's occupancy, and no more than there are items per XCD.
+template <typename K>
+int persist_grid(K kernel, int threads, int ne, long ipe) {
+  static std::mutex mu;
+  static std::map<const void *, int> occ;
+  static int ncu = 0;
+  int oc;
+  {
+    std::lock_guard<std::mutex> g(mu);
+    if (!ncu) {
+      int dev = 0;
+      (void)hipGetDevice(&dev);
+      if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0) ncu = 256;
+    }
+    auto it = occ.find((const void *)kernel);
+    if (it == occ.end()) {
+      int b = 0;
+      (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kernel, threads, 0);
+      it = occ.emplace((const void *)kernel, std::max(1, b)).first;
+    }
+    oc = it->second;
+  }
+  const long per_xcd = (long)((ne + NQ - 1) / NQ) * ipe;
+  const long lim = (long)oc * std::max(1, ncu / NQ);
+  return NQ * (int)std::max(1L, std::min(per_xcd, lim));
+}
+
 void launch_panel(hipStream_t s, int ne, int j0, int h, const int *dims, double *aug, long ldaug, long strideA,
                   int *ipiv, long ldp, int *status) {
   if (h <= PREG_T)
@@ -726,8 +775,8 @@ void launch_lu_solve(hipStream_t s, int ne, int maxrows, int maxrhs, const int *
       hipLaunchKernelGGL((k_lu_trsm<NB, T32>), dim3((NB + T32 - 1) / T32, ne), dim3(T32), 0, s, j0, dims, aug,
                          ldaug, strideA, roff, ipiv, ldp, 0, NB);
       const int tm = (maxrows - p1 + TILE - 1) / TILE;
-      hipLaunchKernelGGL(k_lu_update<NB>, dim3(tm, ne), dim3(256), 0, s, j0, dims, aug, ldaug, strideA, roff, 1, 0,
-                         NB);
+      hipLaunchKernelGGL(k_lu_update<NB>, dim3(persist_grid(k_lu_update<NB>, 256, ne, tm)), dim3(256), 0, s, j0,
+                         dims, aug, ldaug, strideA, roff, tm, 1, ne, 0, NB);
       launch_panel(s, ne, p1, maxrows - p1, dims, aug, ldaug, strideA, ipiv, ldp, status);
     }
     hipLaunchKernelGGL(k_lu_blockperm, dim3(ne), dim3(64), 0, s, j0, dims, aug, ldaug, strideA, ipiv, ldp, bperm,
@@ -735,22 +784,24 @@ void launch_lu_solve(hipStream_t s, int ne, int maxrows, int maxrhs, const int *
     const int c0 = std::min(maxrows, j0 + NBU);
     const int ncols = (maxrows - c0) + maxrhs;
     if (ncols <= 0) continue;
-    hipLaunchKernelGGL(k_lu_trsm_inv, dim3((ncols + TILE - 1) / TILE, ne), dim3(256), 0, s, j0, dims, aug, ldaug,
-                       strideA, roff, bperm, linv);
+    const int tn = (ncols + TILE - 1) / TILE;
+    hipLaunchKernelGGL(k_lu_trsm_inv, dim3(persist_grid(k_lu_trsm_inv, 256, ne, tn)), dim3(256), 0, s, j0, dims, aug,
+                       ldaug, strideA, roff, bperm, linv, tn, ne);
     const int m = maxrows - c0;
     if (m <= 0) continue;
-    const int tm = (m + TILE - 1) / TILE, tn = (ncols + TILE - 1) / TILE;
-    hipLaunchKernelGGL(k_lu_update<NBU>, dim3(tm * tn, ne), dim3(256), 0, s, j0, dims, aug, ldaug, strideA, roff,
-                       tn, 1, 1 << 30);
+    const int tm = (m + TILE - 1) / TILE, gr = (ncols + UPD_G * TILE - 1) / (UPD_G * TILE);
+    hipLaunchKernelGGL(k_lu_update<NBU>, dim3(persist_grid(k_lu_update<NBU>, 256, ne, (long)tm * gr)), dim3(256), 0,
+                       s, j0, dims, aug, ldaug, strideA, roff, tm, gr, ne, 1, 1 << 30);
   }
   if (maxrhs <= 0) return;
   for (int j0 = (maxrows - 1) / NBU * NBU; j0 >= 0; j0 -= NBU) {
-    hipLaunchKernelGGL((k_bs_block<NBU, T64>), dim3((maxrhs + T64 - 1) / T64, ne), dim3(T64), 0, s, j0, dims, aug,
-                       ldaug, strideA, roff);
+    const int tb = (maxrhs + T64 - 1) / T64;
+    hipLaunchKernelGGL((k_bs_block<NBU, T64>), dim3(persist_grid(k_bs_block<NBU, T64>, T64, ne, tb)), dim3(T64), 0, s,
+                       j0, dims, aug, ldaug, strideA, roff, tb, ne);
     if (j0 == 0) break;
-    const int tm = (j0 + TILE - 1) / TILE, tn = (maxrhs + TILE - 1) / TILE;
-    hipLaunchKernelGGL(k_bs_update<NBU>, dim3(tm * tn, ne), dim3(256), 0, s, j0, dims, aug, ldaug, strideA, roff,
-                       tn);
+    const int tm = (j0 + TILE - 1) / TILE, gr = (maxrhs + UPD_G * TILE - 1) / (UPD_G * TILE);
+    hipLaunchKernelGGL(k_bs_update<NBU>, dim3(persist_grid(k_bs_update<NBU>, 256, ne, (long)tm * gr)), dim3(256), 0,
+                       s, j0, dims, aug, ldaug, strideA, roff, tm, gr, ne);
   }
 }
 
@@ -760,23 +811,23 @@ void launch_lu_solve(hipStream_t s, int ne, int maxrows, int maxrhs, const int *
 __global__ __launch_bounds__(256) void k_gemm_sq(const int *__restrict__ nopen, const double *__restrict__ A,
                                                  long lda, long sA, const double *__restrict__ B, long ldb,
                                                  long sB, double *__restrict__ C, long ldc, long sC,
-                                                 int tiles_n) {
+                                                 int tiles_n, int ne) {
   constexpr int GK = 32;
   constexpr int NL = TILE * GK / 256;  // slab elements per thread (A and B each)
-  const int e = blockIdx.y;
-  const int n = nopen[e];
-  const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
-  const int r0 = tm * TILE, q0 = tn * TILE;
-  if (r0 >= n || q0 >= n) return;
-  const double *Ae = A + (size_t)e * sA;
-  const double *Be = B + (size_t)e * sB;
-  double *Ce = C + (size_t)e * sC;
   __shared__ double sa[TILE][Pitch<GK>::A];  // sa[i][k] = A[r0 + i][k0 + k]
   __shared__ double sb[GK][PB];              // sb[k][j] = B[k0 + k][q0 + j]
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int kk = lane >> 4, ii = lane & 15;
+  for_items(ne, tiles_n * tiles_n, [&](int e, int it) {
+  const int n = nopen[e];
+  const int tm = it / tiles_n, tn = it % tiles_n;
+  const int r0 = tm * TILE, q0 = tn * TILE;
+  if (r0 >= n || q0 >= n) return;
+  const double *Ae = A + (size_t)e * sA;
+  const double *Be = B + (size_t)e * sB;
+  double *Ce = C + (size_t)e * sC;
   // the next slab is loaded into registers while the current one is multiplied
   double ra[NL], rb[NL];
   auto gload = [&](int k0) {
@@ -815,14 +866,15 @@ __global__ __launch_bounds__(256) void k_gemm_sq(const int *__restrict__ nopen, 
       if (i < n) Ce[(size_t)i * ldc + j] = acc[q][v];
     }
   }
+  });
 }
 
 void launch_gemm_sq(hipStream_t s, int ne, int maxn, const int *nopen, const double *A, long lda, long sA,
                     const double *B, long ldb, long sB, double *C, long ldc, long sC) {
   if (maxn <= 0) return;
   const int tn = (maxn + TILE - 1) / TILE;
-  hipLaunchKernelGGL(k_gemm_sq, dim3(tn * tn, ne), dim3(256), 0, s, nopen, A, lda, sA, B, ldb, sB, C, ldc,
-                     sC, tn);
+  hipLaunchKernelGGL(k_gemm_sq, dim3(persist_grid(k_gemm_sq, 256, ne, (long)tn * tn)), dim3(256), 0, s, nopen, A, lda,
+                     sA, B, ldb, sB, C, ldc, sC, tn, ne);
 }
 
 // ---------------------------------------------------------------------------

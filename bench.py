@@ -22,10 +22,37 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"f32": 157.3, "f64": 78.6}  # MI355X dense MFMA TFLOP/s
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_rform_c4_traffic.md")
+RFORM_SOURCES = [os.path.join(ROOT, "paper_1909_07321_amd", "csrc", f) for f in ("k_rform.hip", "rm_internal.h")]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def rform_source_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in RFORM_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary (already scaled by the copy-kernel calibration), or None
+    if there is none or the kernel's sources changed since it was taken."""
+    import re
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    m = re.search(r"^traffic: %s fetch_bytes=(\S+) write_bytes=(\S+) source_sha256=(\S+)" % re.escape(kernel),
+                  text, re.M)
+    if not m or m.group(3) != rform_source_sha():
+        return None
+    return float(m.group(1)) + float(m.group(2))
 
 
 def serve_measure(ctx, nreq: int) -> dict:
@@ -153,13 +180,14 @@ def main() -> int:
         rf_ms, rf_n, rf_e = stages["rform"]
         achieved = flops_R * rf_e / (rf_ms * 1e-3) / 1e12 if rf_ms > 0 else None
         dt = "f32" if prec == rm.FP32_SPLIT else "f64"
+        kname = "k_rform_f32" if dt == "f32" else "k_rform_f64"
         results[name] = dict(
             value=E.size * args.steps / (t2 - t1), ms_per_step=ms_step,
             flagged_energies=int((stat != 0).sum()),
             stage_ms_per_step={s: v[0] / args.steps for s, v in stages.items()},
             roofline=dict(bound="mfma", achieved=achieved, peak=PEAK[dt], unit="TFLOP/s",
-                          frac=(achieved / PEAK[dt]) if achieved else None, traffic=None,
-                          kernel=f"k_rform<{'float' if dt == 'f32' else 'double'}>",
+                          frac=(achieved / PEAK[dt]) if achieved else None, traffic=measured_traffic(kname),
+                          kernel=kname,
                           launches=rf_n, avg_launch_ms=rf_ms / max(rf_n, 1),
                           flops_per_launch=flops_R * rf_e / max(rf_n, 1)))
         log(f"{name}: {results[name]['value']:.1f} points/s, {ms_step:.1f} ms/step, stages "

@@ -143,13 +143,16 @@ __device__ __forceinline__ void rform_body(const DevPW *__restrict__ tab, const 
   constexpr int VEC = 16 / sizeof(T);            // elements per 16-byte load
   constexpr int PER_ROW = TILE / VEC;            // vectors per row
   constexpr int NVEC = KC * PER_ROW / 256;       // vectors per thread per panel
+  constexpr int ND = (EB * KC + 255) / 256;      // d values per thread per stage
   typedef T TV __attribute__((ext_vector_type(VEC)));
 
   // fragment columns in the rotated panel rows (ks is a multiple of 4, so row
   // ks + kk is rotated by 16 kk)
   const int ca0 = (wr * 32 + ii + 16 * kk) & (TILE - 1), ca1 = (wr * 32 + 16 + ii + 16 * kk) & (TILE - 1);
   const int cb0 = (wc * 32 + ii + 16 * kk) & (TILE - 1), cb1 = (wc * 32 + 16 + ii + 16 * kk) & (TILE - 1);
-  int q = blockIdx.x % NQ, tried = 0;
+  // start with the queue of the XCD this workgroup runs on (hardware register
+  // XCC_ID, bits [3:0])
+  int q = __builtin_amdgcn_s_getreg((3 << 11) | 20) & (NQ - 1), tried = 0;
   for (;;) {
     if (tid == 0) {
       int task = -1;
@@ -188,7 +191,7 @@ __device__ __forceinline__ void rform_body(const DevPW *__restrict__ tab, const 
     // register-staged double buffering: the next stage's global loads are in
     // flight while the current stage is multiplied out of LDS
     TV ra[NVEC], rb[NVEC];
-    T rd = T(0);
+    T rd[ND];
     auto gload = [&](int k0) {
 #pragma unroll
       for (int r = 0; r < NVEC; ++r) {
@@ -197,9 +200,11 @@ __device__ __forceinline__ void rform_body(const DevPW *__restrict__ tab, const 
         ra[r] = *reinterpret_cast<const TV *>(W + (size_t)(k0 + row) * ldw + i0 + col);
         if (!diag) rb[r] = *reinterpret_cast<const TV *>(W + (size_t)(k0 + row) * ldw + j0 + col);
       }
-      if (tid < EB * KC) {
-        const int e = tid / KC, k = tid % KC;
-        rd = e < me ? D[(size_t)(e0 + e) * ldD + k0 + k] : T(0);
+#pragma unroll
+      for (int r = 0; r < ND; ++r) {
+        const int idx = tid + 256 * r;
+        const int e = idx / KC, k = idx % KC;
+        if (idx < EB * KC) rd[r] = e < me ? D[(size_t)(e0 + e) * ldD + k0 + k] : T(0);
       }
     };
     auto sstore = [&](int buf) {
@@ -211,7 +216,11 @@ __device__ __forceinline__ void rform_body(const DevPW *__restrict__ tab, const 
         *reinterpret_cast<TV *>(&sA[buf][row][scol]) = ra[r];
         if (!diag) *reinterpret_cast<TV *>(&sB[buf][row][scol]) = rb[r];
       }
-      if (tid < EB * KC) sD[buf][tid / KC][tid % KC] = rd;
+#pragma unroll
+      for (int r = 0; r < ND; ++r) {
+        const int idx = tid + 256 * r;
+        if (idx < EB * KC) sD[buf][idx / KC][idx % KC] = rd[r];
+      }
     };
 
     const int nstage = Mpad / KC;

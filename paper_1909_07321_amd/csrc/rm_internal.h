@@ -13,7 +13,7 @@ constexpr int TILE = 64;
 constexpr int KC64 = 32;
 constexpr int KC32 = 64;
 // Energies that share one staged amplitude panel in the R contraction.
-constexpr int EB = 4;
+constexpr int EB = 8;
 // Panel width of the blocked LU (one register-resident panel) and the outer
 // block: two panels are factored, then the trailing matrix is updated once
 // with a rank-NBU product.
@@ -65,8 +65,8 @@ struct RTask {
   int slot, e0, m, tile;
 };
 
-// The R contraction's task list is split into NQ queues, one per XCD (workgroup
-// b of a launch is placed on XCD b % NQ).  Queue q holds tasks [start[q],
+// The R contraction's task list is split into NQ queues, one per XCD (a
+// workgroup starts with the queue of the XCD it runs on).  Queue q holds tasks [start[q],
 // start[q + 1]); a queue keeps all energy batches of a tile together, so the
 // workgroups of one XCD stream the same amplitude rows through its L2.
 constexpr int NQ = 8;

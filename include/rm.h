@@ -65,6 +65,10 @@ typedef int32_t rm_status;
 #define RM_E_NOTFOUND (-4) /* unknown partial-wave id or ticket */
 #define RM_E_BUSY (-5)     /* serving admission queue full */
 
+/* Largest channel count of a partial wave (one matching-matrix row is staged
+   on chip during assembly). */
+#define RM_MAX_CHANNELS 16384
+
 /* per-energy status bits; a flagged energy never fails its call, its outputs
    are NaN (R is NaN only for RM_PT_POLE) */
 #define RM_PT_POLE 1        /* E equals a pole E_k exactly */
@@ -105,7 +109,7 @@ const char *rm_last_error(const rm_ctx *ctx);
    section "Input files", H.DAT table: VALUE = Ek, WMAT = w written pole by pole,
    L2P = l, NCONAT expanded to a channel -> target map). */
 typedef struct {
-  int32_t nchan;        /* n >= 1 channels */
+  int32_t nchan;        /* 1 <= n <= RM_MAX_CHANNELS channels */
   int32_t npole;        /* M >= 1 poles */
   int32_t ntarget;      /* targets; target[i] in [0, ntarget) */
   double a;             /* R-matrix box radius (bohr) */

@@ -294,7 +294,7 @@ void launch_asym(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, 
 __global__ __launch_bounds__(256) void k_openlist(const DevPW *__restrict__ tab, const int *__restrict__ pwi,
                                                   const double *__restrict__ E, int *__restrict__ nopen,
                                                   int *__restrict__ openidx, int *__restrict__ openpos,
-                                                  int8_t *__restrict__ openflag, long ld) {
+                                                  int *__restrict__ colpos, int8_t *__restrict__ openflag, long ld) {
   __shared__ int cnt[256];
   const int e = blockIdx.x, t = threadIdx.x;
   const DevPW &p = tab[pwi[e]];
@@ -315,18 +315,20 @@ __global__ __launch_bounds__(256) void k_openlist(const DevPW *__restrict__ tab,
     __syncthreads();
   }
   int pos = cnt[t] - c;
+  const int nc = n - cnt[255];  // closed channels take the first columns of A
   for (int i = c0; i < c1; ++i) {
     const bool op = Ev - ethr[i] > 0.0;
     openflag[(size_t)e * ld + i] = op ? 1 : 0;
     openpos[(size_t)e * ld + i] = op ? pos : -1;
+    colpos[(size_t)e * ld + i] = op ? nc + pos : i - pos;
     if (op) openidx[(size_t)e * ld + pos++] = i;
   }
   if (t == 255) nopen[e] = cnt[255];
 }
 
 void launch_openlist(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const double *E, int *nopen,
-                     int *openidx, int *openpos, int8_t *openflag) {
-  hipLaunchKernelGGL(k_openlist, dim3(L.ne), dim3(256), 0, s, tab, pwi, E, nopen, openidx, openpos, openflag,
+                     int *openidx, int *openpos, int *colpos, int8_t *openflag) {
+  hipLaunchKernelGGL(k_openlist, dim3(L.ne), dim3(256), 0, s, tab, pwi, E, nopen, openidx, openpos, colpos, openflag,
                      L.ldo);
 }
 

@@ -5,9 +5,11 @@
 // becomes A Y = B with C_i = c_i (open) or e_i (closed) and
 //   A_im = d_im C_i - R_im (a C'_m - b C_m)
 //   B_ij = R_{i,o_j} (a s'_{o_j} - b s_{o_j}) - d_{i,o_j} s_{o_j}
-// and K = Y restricted to the open rows.  A Y = B is solved by a batched,
-// blocked, right-looking LU with partial pivoting applied to [A | B] followed by
-// a blocked back substitution.
+// and K = Y restricted to the open rows.  The unknowns (columns of A, rows of
+// Y) are ordered closed channels first, then open ones, so K is the last nopen
+// rows of Y and the back substitution can stop there.  A Y = B is solved by a
+// batched, blocked, right-looking LU with partial pivoting applied to [A | B]
+// followed by a blocked back substitution.
 //
 // S and Omega (Glossary): S = (1 + iK)(1 - iK)^-1 = (2Y - 1) + 2iKY with
 // Y = (1 + K^2)^-1, so with X = (1 + K^2)^-1 K (same LU, on [1 + K^2 | K]):
@@ -79,48 +81,45 @@ __device__ __forceinline__ void mfma_slab(const double (*sA)[Pitch<K>::A], const
 
 
 // ---------------------------------------------------------------------------
-// assembly of B (reads R) and then A (in place over R)
+// Assembly of [A | B] in place over R, one workgroup per (row, energy): the row
+// of R is staged in LDS, then B's row (open columns of R) and A's row (every
+// column, moved to the channel's column in A) are written.
 // ---------------------------------------------------------------------------
-__global__ void k_buildB(const DevPW *__restrict__ tab, const int *__restrict__ pwi, const double *__restrict__ fg,
-                         const int *__restrict__ nopen, const int *__restrict__ openidx, long ldo,
-                         double *__restrict__ aug, long ldaug, long strideA, long roff) {
-  const int e = blockIdx.z;
+__global__ __launch_bounds__(256) void k_build(const DevPW *__restrict__ tab, const int *__restrict__ pwi,
+                                               const double *__restrict__ fg, const int *__restrict__ nopen,
+                                               const int *__restrict__ openidx, const int *__restrict__ colpos,
+                                               long ldo, double *__restrict__ aug, long ldaug, long strideA,
+                                               long roff) {
+  extern __shared__ double rrow[];
+  const int i = blockIdx.x, e = blockIdx.y;
   const DevPW &p = tab[pwi[e]];
   const int n = p.n;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;  // open column
-  const int i = blockIdx.y;                             // row
-  const int no = nopen[e];
-  if (j >= no || i >= n) return;
+  if (i >= n) return;
   const double a = p.a, b = p.b;
-  const int oj = openidx[(size_t)e * ldo + j];
-  const double *f = fg + ((size_t)e * ldo + oj) * 4;
-  const double s = f[0], sp = f[1];
-  double *Ae = aug + (size_t)e * strideA;
-  const double v = Ae[(size_t)i * ldaug + oj] * (a * sp - b * s) - (i == oj ? s : 0.0);
-  Ae[(size_t)i * ldaug + roff + j] = v;
-}
-
-__global__ void k_buildA(const DevPW *__restrict__ tab, const int *__restrict__ pwi, const double *__restrict__ fg,
-                         long ldo, double *__restrict__ aug, long ldaug, long strideA) {
-  const int e = blockIdx.z;
-  const DevPW &p = tab[pwi[e]];
-  const int n = p.n;
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = blockIdx.y;
-  if (m >= n || i >= n) return;
-  const double *fm = fg + ((size_t)e * ldo + m) * 4;
-  const double lam = p.a * fm[3] - p.b * fm[2];
-  double *q = aug + (size_t)e * strideA + (size_t)i * ldaug + m;
-  double v = -(*q) * lam;
-  if (i == m) v += fm[2];
-  *q = v;
+  double *row = aug + (size_t)e * strideA + (size_t)i * ldaug;
+  const double *f = fg + (size_t)e * ldo * 4;
+  for (int m = threadIdx.x; m < n; m += 256) rrow[m] = row[m];
+  __syncthreads();
+  const int no = nopen[e];
+  const int *oi = openidx + (size_t)e * ldo;
+  for (int j = threadIdx.x; j < no; j += 256) {
+    const int oj = oi[j];
+    const double s = f[4 * oj], sp = f[4 * oj + 1];
+    row[roff + j] = rrow[oj] * (a * sp - b * s) - (i == oj ? s : 0.0);
+  }
+  const int *cp = colpos + (size_t)e * ldo;
+  for (int m = threadIdx.x; m < n; m += 256) {
+    const double lam = a * f[4 * m + 3] - b * f[4 * m + 2];
+    double v = -rrow[m] * lam;
+    if (i == m) v += f[4 * m + 2];
+    row[cp[m]] = v;
+  }
 }
 
 void launch_build(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const double *fg,
-                  const int *nopen, const int *openidx, double *aug) {
-  dim3 g((L.nmax + 63) / 64, L.nmax, L.ne);
-  hipLaunchKernelGGL(k_buildB, g, dim3(64), 0, s, tab, pwi, fg, nopen, openidx, L.ldo, aug, L.ldaug, L.sA, L.roff);
-  hipLaunchKernelGGL(k_buildA, g, dim3(64), 0, s, tab, pwi, fg, L.ldo, aug, L.ldaug, L.sA);
+                  const int *nopen, const int *openidx, const int *colpos, double *aug) {
+  hipLaunchKernelGGL(k_build, dim3(L.nmax, L.ne), dim3(256), sizeof(double) * L.nmax, s, tab, pwi, fg, nopen, openidx,
+                     colpos, L.ldo, aug, L.ldaug, L.sA, L.roff);
 }
 
 // ---------------------------------------------------------------------------
@@ -647,12 +646,13 @@ __global__ __launch_bounds__(256, 2) void k_lu_update(int p0, const int *__restr
 // (column-oriented: each solved entry is eliminated from the rows above it).
 template <int KB, int T>
 __global__ __launch_bounds__(T) void k_bs_block(int j0, const int *__restrict__ dims, double *__restrict__ aug,
-                                                long ldaug, long strideA, long roff, int tiles, int ne) {
+                                                long ldaug, long strideA, long roff, int tiles, int ne, int tail) {
   __shared__ double U[KB][KB];
   const int t = threadIdx.x;
   for_items(ne, tiles, [&](int e, int tile) {
     const int rows = dims[2 * e], rhs = dims[2 * e + 1];
     if (j0 >= rows || tile * T >= rhs) return;
+    if (tail && j0 + KB <= rows - rhs) return;  // block above the rows that are needed
     const int jb = min(KB, rows - j0);
     double *A = aug + (size_t)e * strideA;
     for (int idx = t; idx < KB * KB; idx += T) {
@@ -691,7 +691,7 @@ __global__ __launch_bounds__(T) void k_bs_block(int j0, const int *__restrict__ 
 template <int KB>
 __global__ __launch_bounds__(256, 2) void k_bs_update(int j0, const int *__restrict__ dims, double *__restrict__ aug,
                                                    long ldaug, long strideA, long roff, int tiles_m, int groups,
-                                                   int ne) {
+                                                   int ne, int tail) {
   __shared__ double sU[TILE][Pitch<KB>::A];  // sU[i][k] = U[r0 + i][j0 + k]
   __shared__ double sY[KB][PB];              // sY[k][j] = Y[j0 + k][q0 + j]
   for_items(ne, tiles_m * groups, [&](int e, int it) {
@@ -701,6 +701,7 @@ __global__ __launch_bounds__(256, 2) void k_bs_update(int j0, const int *__restr
     const int jb = min(KB, rows - j0);
     const int r0 = tmi * TILE, qbeg = g * UPD_G * TILE;
     if (r0 >= j0 || qbeg >= rhs) return;
+    if (tail && r0 + TILE <= rows - rhs) return;  // rows above the ones that are needed
     double *A = aug + (size_t)e * strideA;
     for (int idx = threadIdx.x; idx < KB * TILE; idx += 256) {
       const int i = idx / KB, k = idx % KB;
@@ -764,7 +765,7 @@ void launch_panel(hipStream_t s, int ne, int j0, int h, const int *dims, double 
 // align the first panel's rows with its interchanges, then one triangular solve
 // and one rank-NBU update for everything right of the block.
 void launch_lu_solve(hipStream_t s, int ne, int maxrows, int maxrhs, const int *dims, double *aug,
-                     long ldaug, long strideA, long roff, int *ipiv, long ldp, int *bperm, double *linv,
+                     long ldaug, long strideA, long roff, int *ipiv, long ldp, int *bperm, double *linv, int tail,
                      int *status) {
   constexpr int T32 = 128, T64 = 64;
   for (int j0 = 0; j0 < maxrows; j0 += NBU) {
@@ -797,11 +798,11 @@ void launch_lu_solve(hipStream_t s, int ne, int maxrows, int maxrhs, const int *
   for (int j0 = (maxrows - 1) / NBU * NBU; j0 >= 0; j0 -= NBU) {
     const int tb = (maxrhs + T64 - 1) / T64;
     hipLaunchKernelGGL((k_bs_block<NBU, T64>), dim3(persist_grid(k_bs_block<NBU, T64>, T64, ne, tb)), dim3(T64), 0, s,
-                       j0, dims, aug, ldaug, strideA, roff, tb, ne);
+                       j0, dims, aug, ldaug, strideA, roff, tb, ne, tail);
     if (j0 == 0) break;
     const int tm = (j0 + TILE - 1) / TILE, gr = (maxrhs + UPD_G * TILE - 1) / (UPD_G * TILE);
     hipLaunchKernelGGL(k_bs_update<NBU>, dim3(persist_grid(k_bs_update<NBU>, 256, ne, (long)tm * gr)), dim3(256), 0,
-                       s, j0, dims, aug, ldaug, strideA, roff, tm, gr, ne);
+                       s, j0, dims, aug, ldaug, strideA, roff, tm, gr, ne, tail);
   }
 }
 
@@ -880,21 +881,21 @@ void launch_gemm_sq(hipStream_t s, int ne, int maxn, const int *nopen, const dou
 // ---------------------------------------------------------------------------
 // K gather, P = 1 + K^2 set-up, collision strengths
 // ---------------------------------------------------------------------------
-__global__ void k_gatherK(const int *__restrict__ nopen, const int *__restrict__ openidx, long ldo,
+__global__ void k_gatherK(const DevPW *__restrict__ tab, const int *__restrict__ pwi, const int *__restrict__ nopen,
                           const double *__restrict__ aug, long ldaug, long strideA, long roff,
                           double *__restrict__ Kw, long ldk, long strideK, int nmax) {
   const int e = blockIdx.z, i = blockIdx.y;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nmax || j >= nmax) return;
-  const int no = nopen[e];
+  const int no = nopen[e], n = tab[pwi[e]].n;
   double v = 0.0;
-  if (i < no && j < no) v = aug[(size_t)e * strideA + (size_t)openidx[(size_t)e * ldo + i] * ldaug + roff + j];
+  if (i < no && j < no) v = aug[(size_t)e * strideA + (size_t)(n - no + i) * ldaug + roff + j];
   Kw[(size_t)e * strideK + (size_t)i * ldk + j] = v;
 }
 
-void launch_gatherK(hipStream_t s, const Lay &L, const int *nopen, const int *openidx, const double *aug,
-                    double *Kw) {
-  hipLaunchKernelGGL(k_gatherK, dim3((L.nmax + 63) / 64, L.nmax, L.ne), dim3(64), 0, s, nopen, openidx, L.ldo, aug,
+void launch_gatherK(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *nopen,
+                    const double *aug, double *Kw) {
+  hipLaunchKernelGGL(k_gatherK, dim3((L.nmax + 63) / 64, L.nmax, L.ne), dim3(64), 0, s, tab, pwi, nopen, aug,
                      L.ldaug, L.sA, L.roff, Kw, L.ldk, L.sK, L.nmax);
 }
 

@@ -90,6 +90,7 @@ struct Work {
   int *nopen = nullptr;      // [cap_e]
   int *openidx = nullptr;    // [cap_e][ldo]
   int *openpos = nullptr;    // [cap_e][ldo] position in the open list or -1
+  int *colpos = nullptr;     // [cap_e][ldo] column of each channel in the matching matrix (closed first)
   int8_t *openflag = nullptr;// [cap_e][ldo]
   double *fg = nullptr;      // [cap_e][ldo][4]
   double *aug = nullptr;     // [cap_e][nmax][ldaug]
@@ -116,25 +117,29 @@ void launch_nearpole(hipStream_t s, const Lay &L, int maxtiles, const DevPW *tab
                      const int *win, double *R);
 void launch_nanfill_R(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *status, double *R);
 void launch_openlist(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const double *E, int *nopen,
-                     int *openidx, int *openpos, int8_t *openflag);
+                     int *openidx, int *openpos, int *colpos, int8_t *openflag);
 void launch_asym(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const double *E, double thr_guard,
                  double *fg, int *status);
 void launch_setdims(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *nopen, int *dims);
+// Assembles [A | B] in place over R; A's columns are ordered closed channels
+// first, then open channels (both ascending), as colpos says.
 void launch_build(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const double *fg,
-                  const int *nopen, const int *openidx, double *aug);
+                  const int *nopen, const int *openidx, const int *colpos, double *aug);
 // Batched LU with partial pivoting of [A | B] per energy (dims[2e] = rows of the
 // square A in columns [0, rows), dims[2e+1] = right-hand sides in columns
 // [roff, roff + rhs)), then back substitution: on return the right-hand-side
 // columns hold A^-1 B.  Exact zero pivots set RM_PT_SINGULAR.  bperm (ne * BPERM
-// ints) and linv (ne * NBU * NBU doubles) are scratch.
+// ints) and linv (ne * NBU * NBU doubles) are scratch.  With tail = 1 only the
+// last rhs rows of the solution are formed (the back substitution stops there).
 void launch_lu_solve(hipStream_t s, int ne, int maxrows, int maxrhs, const int *dims, double *aug,
-                     long ldaug, long strideA, long roff, int *ipiv, long ldp, int *bperm, double *linv,
+                     long ldaug, long strideA, long roff, int *ipiv, long ldp, int *bperm, double *linv, int tail,
                      int *status);
 // C[e] = A[e] B[e] for square no x no blocks, no = nopen[e]
 void launch_gemm_sq(hipStream_t s, int ne, int maxn, const int *nopen, const double *A, long lda, long sA,
                     const double *B, long ldb, long sB, double *C, long ldc, long sC);
-void launch_gatherK(hipStream_t s, const Lay &L, const int *nopen, const int *openidx, const double *aug,
-                    double *Kw);
+// K = the last nopen rows of the solution (the open channels, ascending).
+void launch_gatherK(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *nopen,
+                    const double *aug, double *Kw);
 void launch_formP(hipStream_t s, const Lay &L, const int *nopen, const double *Kw, double *aug, int *dims);
 void launch_omega(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *openpos,
                   const int *nopen, const double *X, const double *XK, double *omega, double *S);

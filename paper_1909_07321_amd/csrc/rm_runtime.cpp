@@ -147,14 +147,14 @@ size_t per_energy_bytes(int n, int npad, int Mpad, int nt) {
          + (size_t)n * npad * 8 * 2  // Kw, XK
          + (size_t)n * n * 8         // packed outputs
          + (size_t)Mpad * 12         // D64 + D32
-         + (size_t)n * (32 + 13)     // fg, openidx, openpos, openflag, ipiv
+         + (size_t)n * (32 + 17)     // fg, openidx, openpos, colpos, openflag, ipiv
          + (size_t)nt * nt * 8       // Omega
          + BPERM * 4 + NBU * NBU * 8 + 128;
 }
 
 void free_work(Work &w) {
   void *ptrs[] = {w.E, w.pwi, w.tab, w.tasks, w.counter, w.D64, w.D32, w.win, w.status, w.nopen, w.openidx,
-                  w.openpos, w.openflag, w.fg, w.aug, w.Kw, w.XK, w.dims, w.ipiv, w.bperm, w.linv, w.omega, w.pack, w.pack_off,
+                  w.openpos, w.colpos, w.openflag, w.fg, w.aug, w.Kw, w.XK, w.dims, w.ipiv, w.bperm, w.linv, w.omega, w.pack, w.pack_off,
                   w.S};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -198,8 +198,8 @@ rm_status ensure_slot(rm_ctx *ctx, Slot &sl, const Lay &L, int ntab, int ntasks,
                  bpack = sz((size_t)ce * std::max((size_t)cn * cn, (size_t)ct * ct) * 8),
                  boff = sz((size_t)(ce + 1) * 8), bS = S ? sz((size_t)ce * cn * cn * 16) : 0,
                  bperm = sz((size_t)ce * BPERM * 4), blinv = sz((size_t)ce * NBU * NBU * 8);
-    // openpos and ipiv share bidx's size, XK shares bK's, the pack offsets are two blocks
-    need += 2 * ((bidx + 255) / 256 * 256) + (bK + 255) / 256 * 256 + (boff + 255) / 256 * 256;
+    // openpos, colpos and ipiv share bidx's size, XK shares bK's, the pack offsets are two blocks
+    need += 3 * ((bidx + 255) / 256 * 256) + (bK + 255) / 256 * 256 + (boff + 255) / 256 * 256;
     {
       std::lock_guard<std::mutex> g(ctx->mu);
       if (ctx->resident + ctx->work_bytes - w.bytes + need > ctx->budget) {
@@ -226,6 +226,7 @@ rm_status ensure_slot(rm_ctx *ctx, Slot &sl, const Lay &L, int ntab, int ntasks,
     HIPCHK(hipMalloc(&w.nopen, bno));
     HIPCHK(hipMalloc(&w.openidx, bidx));
     HIPCHK(hipMalloc(&w.openpos, bidx));
+    HIPCHK(hipMalloc(&w.colpos, bidx));
     HIPCHK(hipMalloc(&w.ipiv, bidx));
     HIPCHK(hipMalloc(&w.bperm, bperm));
     HIPCHK(hipMalloc(&w.linv, blinv));
@@ -412,7 +413,7 @@ void stage_R(rm_ctx *ctx, const Plan &P, Work &w, const rm_opts &o, hipStream_t 
 void stage_asym(rm_ctx *ctx, const Plan &P, Work &w, const rm_opts &o, hipStream_t s) {
   const Lay &L = P.L;
   timed(ctx, 2, L.ne, s, [&] {
-    launch_openlist(s, L, w.tab, w.pwi, w.E, w.nopen, w.openidx, w.openpos, w.openflag);
+    launch_openlist(s, L, w.tab, w.pwi, w.E, w.nopen, w.openidx, w.openpos, w.colpos, w.openflag);
     launch_asym(s, L, w.tab, w.pwi, w.E, o.thr_guard, w.fg, w.status);
   });
 }
@@ -420,9 +421,10 @@ void stage_asym(rm_ctx *ctx, const Plan &P, Work &w, const rm_opts &o, hipStream
 void stage_K(const Plan &P, Work &w, hipStream_t s) {
   const Lay &L = P.L;
   launch_setdims(s, L, w.tab, w.pwi, w.nopen, w.dims);
-  launch_build(s, L, w.tab, w.pwi, w.fg, w.nopen, w.openidx, w.aug);
-  launch_lu_solve(s, L.ne, L.nmax, L.nmax, w.dims, w.aug, L.ldaug, L.sA, L.roff, w.ipiv, L.ldo, w.bperm, w.linv, w.status);
-  launch_gatherK(s, L, w.nopen, w.openidx, w.aug, w.Kw);
+  launch_build(s, L, w.tab, w.pwi, w.fg, w.nopen, w.openidx, w.colpos, w.aug);
+  launch_lu_solve(s, L.ne, L.nmax, L.nmax, w.dims, w.aug, L.ldaug, L.sA, L.roff, w.ipiv, L.ldo, w.bperm, w.linv, 1,
+                  w.status);
+  launch_gatherK(s, L, w.tab, w.pwi, w.nopen, w.aug, w.Kw);
 }
 
 void stage_SO(const Plan &P, Work &w, bool want_S, hipStream_t s) {
@@ -430,7 +432,8 @@ void stage_SO(const Plan &P, Work &w, bool want_S, hipStream_t s) {
   const Lay &L = P.L;
   launch_gemm_sq(s, L.ne, L.nmax, w.nopen, w.Kw, L.ldk, L.sK, w.Kw, L.ldk, L.sK, w.aug, L.ldaug, L.sA);
   launch_formP(s, L, w.nopen, w.Kw, w.aug, w.dims);
-  launch_lu_solve(s, L.ne, L.nmax, L.nmax, w.dims, w.aug, L.ldaug, L.sA, L.roff, w.ipiv, L.ldo, w.bperm, w.linv, w.status);
+  launch_lu_solve(s, L.ne, L.nmax, L.nmax, w.dims, w.aug, L.ldaug, L.sA, L.roff, w.ipiv, L.ldo, w.bperm, w.linv, 0,
+                  w.status);
   launch_gemm_sq(s, L.ne, L.nmax, w.nopen, w.aug + L.roff, L.ldaug, L.sA, w.Kw, L.ldk, L.sK, w.XK, L.ldk, L.sK);
   launch_omega(s, L, w.tab, w.pwi, w.openpos, w.nopen, w.aug + L.roff, w.XK, w.omega, want_S ? w.S : nullptr);
 }
@@ -891,7 +894,7 @@ size_t rm_pw_footprint(int32_t nchan, int32_t npole) {
 
 rm_status rm_pw_upload(rm_ctx *ctx, const rm_pw_desc *d, int32_t *pw_id) {
   if (!ctx || !d || !pw_id) return RM_E_ARG;
-  if (d->nchan < 1 || d->npole < 1 || d->ntarget < 1 || !d->e_thr || !d->l || !d->target || !d->Ek || !d->w ||
+  if (d->nchan < 1 || d->nchan > RM_MAX_CHANNELS || d->npole < 1 || d->ntarget < 1 || !d->e_thr || !d->l || !d->target || !d->Ek || !d->w ||
       !(d->a > 0) || !(d->z >= 0)) {
     ctx->err = "invalid partial-wave descriptor";
     return RM_E_ARG;
@@ -1068,7 +1071,7 @@ rm_status rm_solve_K(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, con
                             sizeof(double) * n, (size_t)m * n, kind_in(o), s));
     HIPCHK(hipMemcpyAsync(w.fg, fg + (size_t)e0 * n * 4, sizeof(double) * m * n * 4, kind_in(o), s));
     launch_dvec(s, L, w.tab, w.pwi, w.E, 0, 0.0, w.D64, w.D32, w.win, w.status);  // pole flags
-    launch_openlist(s, L, w.tab, w.pwi, w.E, w.nopen, w.openidx, w.openpos, w.openflag);
+    launch_openlist(s, L, w.tab, w.pwi, w.E, w.nopen, w.openidx, w.openpos, w.colpos, w.openflag);
     launch_check_inputs(s, L, w.tab, w.pwi, w.E, o.thr_guard, w.aug, w.fg, nullptr, w.nopen, w.status);
     stage_K(P, w, s);
     launch_finalize(s, L, w.tab, w.pwi, w.status, nullptr, w.Kw, nullptr);
@@ -1103,7 +1106,7 @@ rm_status rm_collision_strengths(rm_ctx *ctx, int32_t pwid, const double *E, int
     HIPCHK(hipMemsetAsync(w.status, 0, sizeof(int) * m, s));
     HIPCHK(hipMemcpy2DAsync(w.Kw, sizeof(double) * L.ldk, K + (size_t)e0 * n * n, sizeof(double) * n,
                             sizeof(double) * n, (size_t)m * n, kind_in(o), s));
-    launch_openlist(s, L, w.tab, w.pwi, w.E, w.nopen, w.openidx, w.openpos, w.openflag);
+    launch_openlist(s, L, w.tab, w.pwi, w.E, w.nopen, w.openidx, w.openpos, w.colpos, w.openflag);
     launch_check_inputs(s, L, w.tab, w.pwi, w.E, o.thr_guard, nullptr, nullptr, w.Kw, w.nopen, w.status);
     stage_SO(P, w, S != nullptr, s);
     launch_finalize(s, L, w.tab, w.pwi, w.status, w.omega, nullptr, S ? w.S : nullptr);

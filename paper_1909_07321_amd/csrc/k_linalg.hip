@@ -334,6 +334,11 @@ __global__ __launch_bounds__(PREG_T) void k_lu_panel_reg(int j0, const int *__re
 // Number of trailing "virtual" columns right of a block that ends at column c0:
 // the remaining columns of A, then (if with_rhs) the right-hand sides, at most
 // vlimit in all.
+// Virtual column v of a trailing block whose A part is acols wide.
+__device__ __forceinline__ long vcol2(int v, int acols, int c0, long roff) {
+  return v < acols ? (long)(c0 + v) : roff + (v - acols);
+}
+
 __device__ __forceinline__ int trailing_cols(int rows, int rhs, int c0, int with_rhs, int vlimit) {
   return min(vlimit, (rows - c0) + (with_rhs ? rhs : 0));
 }
@@ -615,7 +620,7 @@ constexpr int UPD_G = 4;
 template <int KB>
 __global__ __launch_bounds__(256, 2) void k_lu_update(int p0, const int *__restrict__ dims, double *__restrict__ aug,
                                                    long ldaug, long strideA, long roff, int tiles_m, int groups,
-                                                   int ne, int with_rhs, int vlimit) {
+                                                   int ne, int with_rhs, int vlimit, int lower) {
   __shared__ double sL[TILE][Pitch<KB>::A];  // sL[i][k] = L21[r0 + i][k]
   __shared__ double sU[KB][PB];              // sU[k][j] = U12[k][v0 + j]
   for_items(ne, tiles_m * groups, [&](int e, int it) {
@@ -625,8 +630,11 @@ __global__ __launch_bounds__(256, 2) void k_lu_update(int p0, const int *__restr
     const int jb = min(KB, rows - p0);
     const int c0 = p0 + jb;
     const int m = rows - c0;
-    const int ncols = trailing_cols(rows, rhs, c0, with_rhs, vlimit);
     const int r0 = tmi * TILE, vbeg = g * UPD_G * TILE;
+    // with lower set only the columns up to this row block's diagonal tile
+    // (the update is symmetric and its upper part is never read)
+    const int acols = lower ? min(m, r0 + TILE) : m;
+    const int ncols = min(vlimit, acols + (with_rhs ? rhs : 0));
     if (r0 >= m || vbeg >= ncols) return;
     double *A = aug + (size_t)e * strideA;
     for (int idx = threadIdx.x; idx < KB * TILE; idx += 256) {
@@ -636,8 +644,8 @@ __global__ __launch_bounds__(256, 2) void k_lu_update(int p0, const int *__restr
     double *Cb = A + (size_t)(c0 + r0) * ldaug;
     rowblock_update<KB, UPD_G>(
         sL, sU, m - r0, vbeg, ncols,
-        [&](int i, int v) { return Cb + (size_t)i * ldaug + vcol(v, rows, c0, roff); },
-        [&](int k, int v) { return k < jb ? A[(size_t)(p0 + k) * ldaug + vcol(v, rows, c0, roff)] : 0.0; });
+        [&](int i, int v) { return Cb + (size_t)i * ldaug + vcol2(v, acols, c0, roff); },
+        [&](int k, int v) { return k < jb ? A[(size_t)(p0 + k) * ldaug + vcol2(v, acols, c0, roff)] : 0.0; });
   });
 }
 
@@ -760,6 +768,9 @@ void launch_panel(hipStream_t s, int ne, int j0, int h, const int *dims, double 
 }
 }  // namespace
 
+void launch_backsub(hipStream_t s, int ne, int maxrows, int maxrhs, const int *dims, double *aug, long ldaug,
+                    long strideA, long roff, int tail);
+
 // Outer blocks of NBU = 2 NB columns: factor the first panel, bring the second
 // panel up to date (interchanges, triangular solve, rank-NB update), factor it,
 // align the first panel's rows with its interchanges, then one triangular solve
@@ -777,7 +788,7 @@ void launch_lu_solve(hipStream_t s, int ne, int maxrows, int maxrhs, const int *
                          ldaug, strideA, roff, ipiv, ldp, 0, NB);
       const int tm = (maxrows - p1 + TILE - 1) / TILE;
       hipLaunchKernelGGL(k_lu_update<NB>, dim3(persist_grid(k_lu_update<NB>, 256, ne, tm)), dim3(256), 0, s, j0,
-                         dims, aug, ldaug, strideA, roff, tm, 1, ne, 0, NB);
+                         dims, aug, ldaug, strideA, roff, tm, 1, ne, 0, NB, 0);
       launch_panel(s, ne, p1, maxrows - p1, dims, aug, ldaug, strideA, ipiv, ldp, status);
     }
     hipLaunchKernelGGL(k_lu_blockperm, dim3(ne), dim3(64), 0, s, j0, dims, aug, ldaug, strideA, ipiv, ldp, bperm,
@@ -792,8 +803,16 @@ void launch_lu_solve(hipStream_t s, int ne, int maxrows, int maxrhs, const int *
     if (m <= 0) continue;
     const int tm = (m + TILE - 1) / TILE, gr = (ncols + UPD_G * TILE - 1) / (UPD_G * TILE);
     hipLaunchKernelGGL(k_lu_update<NBU>, dim3(persist_grid(k_lu_update<NBU>, 256, ne, (long)tm * gr)), dim3(256), 0,
-                       s, j0, dims, aug, ldaug, strideA, roff, tm, gr, ne, 1, 1 << 30);
+                       s, j0, dims, aug, ldaug, strideA, roff, tm, gr, ne, 1, 1 << 30, 0);
   }
+  launch_backsub(s, ne, maxrows, maxrhs, dims, aug, ldaug, strideA, roff, tail);
+}
+
+// Blocked back substitution with the upper triangle of [A | B] (blocks of NBU
+// rows from the bottom).
+void launch_backsub(hipStream_t s, int ne, int maxrows, int maxrhs, const int *dims, double *aug, long ldaug,
+                    long strideA, long roff, int tail) {
+  constexpr int T64 = 64;
   if (maxrhs <= 0) return;
   for (int j0 = (maxrows - 1) / NBU * NBU; j0 >= 0; j0 -= NBU) {
     const int tb = (maxrhs + T64 - 1) / T64;
@@ -807,8 +826,200 @@ void launch_lu_solve(hipStream_t s, int ne, int maxrows, int maxrhs, const int *
 }
 
 // ---------------------------------------------------------------------------
+// Cholesky forward phase for the symmetric positive definite P = 1 + K^2 (rows =
+// right-hand sides = nopen): P = L L^T in blocks of NBU, L kept in the lower
+// triangle and L^T in the upper one (so the back substitution above can use
+// it as U), with the right-hand sides carried along: on return they hold
+// Z = L^-1 K.
+// ---------------------------------------------------------------------------
+
+// Diagonal block: unblocked Cholesky of P11 in LDS, L11 written to the lower
+// and L11^T to the upper part, and the explicit inverse of L11 (lower,
+// identity past jb) to linv.  A pivot that is not positive (only possible for
+// non-finite input) sets RM_PT_SINGULAR and is replaced by 1.
+__global__ __launch_bounds__(256) void k_chol_diag(int j0, const int *__restrict__ dims, double *__restrict__ aug,
+                                                   long ldaug, long strideA, double *__restrict__ linv,
+                                                   int *__restrict__ status) {
+  constexpr int KB = NBU;
+  const int e = blockIdx.x;
+  const int rows = dims[2 * e];
+  if (j0 >= rows) return;
+  const int jb = min(KB, rows - j0);
+  double *A = aug + (size_t)e * strideA + (size_t)j0 * ldaug + j0;
+  __shared__ double a[KB][KB + 1];
+  const int t = threadIdx.x;
+  for (int idx = t; idx < KB * KB; idx += 256) {
+    const int i = idx / KB, k = idx % KB;
+    a[i][k] = (i < jb && k < jb) ? (k <= i ? A[(size_t)i * ldaug + k] : 0.0) : (i == k ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  for (int j = 0; j < jb; ++j) {
+    if (t == 0) {
+      double d = a[j][j];
+      if (!(d > 0.0)) {
+        atomicOr(status + e, RM_PT_SINGULAR);
+        d = 1.0;
+      }
+      a[j][j] = sqrt(d);
+    }
+    __syncthreads();
+    const double r = a[j][j];
+    for (int i = j + 1 + t; i < jb; i += 256) a[i][j] /= r;
+    __syncthreads();
+    const int c = jb - 1 - j;
+    for (int idx = t; idx < c * c; idx += 256) {
+      const int i = j + 1 + idx / c, k = j + 1 + idx % c;
+      if (k <= i) a[i][k] -= a[i][j] * a[k][j];
+    }
+    __syncthreads();
+  }
+  for (int idx = t; idx < jb * jb; idx += 256) {
+    const int i = idx / jb, k = idx % jb;
+    if (k <= i) {
+      A[(size_t)i * ldaug + k] = a[i][k];
+      A[(size_t)k * ldaug + i] = a[i][k];
+    }
+  }
+  // lane j of wave 0: column j of L11^-1 by forward substitution
+  if (t < KB) {
+    const int j = t;
+    double x[KB];
+    static_for([&](auto iI) {
+      constexpr int i = decltype(iI)::value;
+      double acc = i == j ? 1.0 : 0.0;
+      static_for([&](auto kI) {
+        constexpr int k = decltype(kI)::value;
+        if constexpr (k < i) acc -= a[i][k] * x[k];
+      }, std::make_integer_sequence<int, KB>{});
+      x[i] = i < j ? 0.0 : acc / a[i][i];
+    }, std::make_integer_sequence<int, KB>{});
+    double *Li = linv + (size_t)e * KB * KB;
+    static_for([&](auto iI) {
+      constexpr int i = decltype(iI)::value;
+      Li[(size_t)i * KB + j] = x[i];
+    }, std::make_integer_sequence<int, KB>{});
+  }
+}
+
+// Panel below the diagonal block: L21 = P21 L11^-T on FP64 MFMA, one 64-row
+// tile per item, written in place and transposed into the upper part.
+__global__ __launch_bounds__(256) void k_chol_panel(int j0, const int *__restrict__ dims, double *__restrict__ aug,
+                                                    long ldaug, long strideA, const double *__restrict__ linv,
+                                                    int tiles_m, int ne) {
+  constexpr int KB = NBU;
+  __shared__ double sA[TILE][Pitch<KB>::A];  // sA[i][k] = P21[r0 + i][k]
+  __shared__ double sB[KB][PB];              // sB[k][j] = Linv[j][k]
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int kk = lane >> 4, ii = lane & 15;
+  for_items(ne, tiles_m, [&](int e, int tile) {
+    const int rows = dims[2 * e];
+    if (j0 >= rows) return;
+    const int jb = min(KB, rows - j0);
+    const int c0 = j0 + jb, m = rows - c0, r0 = tile * TILE;
+    if (r0 >= m) return;
+    double *A = aug + (size_t)e * strideA;
+    const double *Li = linv + (size_t)e * KB * KB;
+    for (int idx = t; idx < KB * TILE; idx += 256) {
+      const int i = idx / KB, k = idx % KB;
+      sA[i][k] = (r0 + i < m && k < jb) ? A[(size_t)(c0 + r0 + i) * ldaug + j0 + k] : 0.0;
+    }
+    for (int idx = t; idx < KB * KB; idx += 256) sB[idx % KB][idx / KB] = Li[idx];
+    __syncthreads();
+    d4 acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = d4{0, 0, 0, 0};
+    mfma_slab<KB>(sA, sB, acc, wr, wc, kk, ii);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = wc * 32 + (q & 1) * 16 + ii;
+      if (j >= jb) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = wr * 32 + (q >> 1) * 16 + 4 * v + kk;
+        if (r0 + i < m) {
+          A[(size_t)(c0 + r0 + i) * ldaug + j0 + j] = acc[q][v];
+          A[(size_t)(j0 + j) * ldaug + c0 + r0 + i] = acc[q][v];
+        }
+      }
+    }
+    __syncthreads();
+  });
+}
+
+// Right-hand sides of the diagonal block: Z1 = L11^-1 K1 (rows [j0, j0 + jb)),
+// one 64-column tile per item, in place.
+__global__ __launch_bounds__(256) void k_chol_rhs(int j0, const int *__restrict__ dims, double *__restrict__ aug,
+                                                  long ldaug, long strideA, long roff,
+                                                  const double *__restrict__ linv, int tiles_n, int ne) {
+  constexpr int KB = NBU;
+  __shared__ double sL[KB][Pitch<KB>::A];  // sL[i][k] = Linv[i][k]
+  __shared__ double sX[KB][PB];            // sX[k][j] = K1[k][q0 + j]
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int kk = lane >> 4, ii = lane & 15;
+  for_items(ne, tiles_n, [&](int e, int tile) {
+    const int rows = dims[2 * e], rhs = dims[2 * e + 1];
+    if (j0 >= rows) return;
+    const int jb = min(KB, rows - j0);
+    const int q0 = tile * TILE;
+    if (q0 >= rhs) return;
+    double *A = aug + (size_t)e * strideA + (size_t)j0 * ldaug + roff;
+    const double *Li = linv + (size_t)e * KB * KB;
+    for (int idx = t; idx < KB * KB; idx += 256) sL[idx / KB][idx % KB] = Li[idx];
+    for (int idx = t; idx < KB * TILE; idx += 256) {
+      const int k = idx / TILE, j = idx % TILE;
+      sX[k][j] = (k < jb && q0 + j < rhs) ? A[(size_t)k * ldaug + q0 + j] : 0.0;
+    }
+    __syncthreads();
+    d4 acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = d4{0, 0, 0, 0};
+    mfma_slab<KB>(sL, sX, acc, wr, wc, kk, ii);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = q0 + wc * 32 + (q & 1) * 16 + ii;
+      if (j >= rhs) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = wr * 32 + (q >> 1) * 16 + 4 * v + kk;
+        if (i < jb) A[(size_t)i * ldaug + j] = acc[q][v];
+      }
+    }
+    __syncthreads();
+  });
+}
+
+void launch_chol_forward(hipStream_t s, int ne, int maxrows, int maxrhs, const int *dims, double *aug, long ldaug,
+                         long strideA, long roff, double *linv, int *status) {
+  for (int j0 = 0; j0 < maxrows; j0 += NBU) {
+    hipLaunchKernelGGL(k_chol_diag, dim3(ne), dim3(256), 0, s, j0, dims, aug, ldaug, strideA, linv, status);
+    const int c0 = std::min(maxrows, j0 + NBU), m = maxrows - c0;
+    if (m > 0) {
+      const int tm = (m + TILE - 1) / TILE;
+      hipLaunchKernelGGL(k_chol_panel, dim3(persist_grid(k_chol_panel, 256, ne, tm)), dim3(256), 0, s, j0, dims, aug,
+                         ldaug, strideA, linv, tm, ne);
+    }
+    if (maxrhs > 0) {
+      const int tn = (maxrhs + TILE - 1) / TILE;
+      hipLaunchKernelGGL(k_chol_rhs, dim3(persist_grid(k_chol_rhs, 256, ne, tn)), dim3(256), 0, s, j0, dims, aug,
+                         ldaug, strideA, roff, linv, tn, ne);
+    }
+    if (m > 0) {
+      const int ncols = m + maxrhs;
+      const int tm = (m + TILE - 1) / TILE, gr = (ncols + UPD_G * TILE - 1) / (UPD_G * TILE);
+      hipLaunchKernelGGL(k_lu_update<NBU>, dim3(persist_grid(k_lu_update<NBU>, 256, ne, (long)tm * gr)), dim3(256),
+                         0, s, j0, dims, aug, ldaug, strideA, roff, tm, gr, ne, 1, 1 << 30, 1);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Small batched GEMM, C = A B (square no x no per energy), FP64 MFMA.
 // ---------------------------------------------------------------------------
+template <bool TA, bool LOWER, bool MIRROR>
 __global__ __launch_bounds__(256) void k_gemm_sq(const int *__restrict__ nopen, const double *__restrict__ A,
                                                  long lda, long sA, const double *__restrict__ B, long ldb,
                                                  long sB, double *__restrict__ C, long ldc, long sC,
@@ -825,7 +1036,7 @@ __global__ __launch_bounds__(256) void k_gemm_sq(const int *__restrict__ nopen, 
   const int n = nopen[e];
   const int tm = it / tiles_n, tn = it % tiles_n;
   const int r0 = tm * TILE, q0 = tn * TILE;
-  if (r0 >= n || q0 >= n) return;
+  if (r0 >= n || q0 >= n || (LOWER && tn > tm)) return;
   const double *Ae = A + (size_t)e * sA;
   const double *Be = B + (size_t)e * sB;
   double *Ce = C + (size_t)e * sC;
@@ -836,7 +1047,13 @@ __global__ __launch_bounds__(256) void k_gemm_sq(const int *__restrict__ nopen, 
     for (int q = 0; q < NL; ++q) {
       const int idx = t + 256 * q;
       const int i = idx / GK, k = idx % GK;
-      ra[q] = (r0 + i < n && k0 + k < n) ? Ae[(size_t)(r0 + i) * lda + k0 + k] : 0.0;
+      if (TA) {
+        // A^T: element (i, k) is A[k][i]; lanes run along i so the load is contiguous
+        const int ia = idx % TILE, ka = idx / TILE;
+        ra[q] = (r0 + ia < n && k0 + ka < n) ? Ae[(size_t)(k0 + ka) * lda + r0 + ia] : 0.0;
+      } else {
+        ra[q] = (r0 + i < n && k0 + k < n) ? Ae[(size_t)(r0 + i) * lda + k0 + k] : 0.0;
+      }
       const int kb = idx / TILE, j = idx % TILE;
       rb[q] = (q0 + j < n && k0 + kb < n) ? Be[(size_t)(k0 + kb) * ldb + q0 + j] : 0.0;
     }
@@ -849,7 +1066,10 @@ __global__ __launch_bounds__(256) void k_gemm_sq(const int *__restrict__ nopen, 
 #pragma unroll
     for (int q = 0; q < NL; ++q) {
       const int idx = t + 256 * q;
-      sa[idx / GK][idx % GK] = ra[q];
+      if (TA)
+        sa[idx % TILE][idx / TILE] = ra[q];
+      else
+        sa[idx / GK][idx % GK] = ra[q];
       sb[idx / TILE][idx % TILE] = rb[q];
     }
     __syncthreads();
@@ -864,7 +1084,10 @@ __global__ __launch_bounds__(256) void k_gemm_sq(const int *__restrict__ nopen, 
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int i = r0 + wr * 32 + (q >> 1) * 16 + 4 * v + kk;
-      if (i < n) Ce[(size_t)i * ldc + j] = acc[q][v];
+      if (i < n) {
+        Ce[(size_t)i * ldc + j] = acc[q][v];
+        if (MIRROR && tm != tn) Ce[(size_t)j * ldc + i] = acc[q][v];
+      }
     }
   }
   });
@@ -874,8 +1097,42 @@ void launch_gemm_sq(hipStream_t s, int ne, int maxn, const int *nopen, const dou
                     const double *B, long ldb, long sB, double *C, long ldc, long sC) {
   if (maxn <= 0) return;
   const int tn = (maxn + TILE - 1) / TILE;
-  hipLaunchKernelGGL(k_gemm_sq, dim3(persist_grid(k_gemm_sq, 256, ne, (long)tn * tn)), dim3(256), 0, s, nopen, A, lda,
-                     sA, B, ldb, sB, C, ldc, sC, tn, ne);
+  hipLaunchKernelGGL((k_gemm_sq<false, false, false>), dim3(persist_grid(k_gemm_sq<false, false, false>, 256, ne,
+                     (long)tn * tn)), dim3(256), 0, s, nopen, A, lda, sA, B, ldb, sB, C, ldc, sC, tn, ne);
+}
+
+// Lower triangle (block tiles) of C = A B for symmetric products.
+void launch_gemm_lower(hipStream_t s, int ne, int maxn, const int *nopen, const double *A, long lda, long sA,
+                       const double *B, long ldb, long sB, double *C, long ldc, long sC) {
+  if (maxn <= 0) return;
+  const int tn = (maxn + TILE - 1) / TILE;
+  hipLaunchKernelGGL((k_gemm_sq<false, true, false>), dim3(persist_grid(k_gemm_sq<false, true, false>, 256, ne,
+                     (long)tn * tn)), dim3(256), 0, s, nopen, A, lda, sA, B, ldb, sB, C, ldc, sC, tn, ne);
+}
+
+// C = A^T A, formed on the lower block tiles and mirrored.
+void launch_gemm_ata(hipStream_t s, int ne, int maxn, const int *nopen, const double *A, long lda, long sA,
+                     double *C, long ldc, long sC) {
+  if (maxn <= 0) return;
+  const int tn = (maxn + TILE - 1) / TILE;
+  hipLaunchKernelGGL((k_gemm_sq<true, true, true>), dim3(persist_grid(k_gemm_sq<true, true, true>, 256, ne,
+                     (long)tn * tn)), dim3(256), 0, s, nopen, A, lda, sA, A, lda, sA, C, ldc, sC, tn, ne);
+}
+
+// K <- (K + K^T) / 2 on the leading nopen x nopen block.
+__global__ void k_symK(const int *__restrict__ nopen, double *__restrict__ Kw, long ldk, long strideK) {
+  const int e = blockIdx.z, i = blockIdx.y;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int no = nopen[e];
+  if (i >= no || j >= i) return;
+  double *K = Kw + (size_t)e * strideK;
+  const double v = 0.5 * (K[(size_t)i * ldk + j] + K[(size_t)j * ldk + i]);
+  K[(size_t)i * ldk + j] = v;
+  K[(size_t)j * ldk + i] = v;
+}
+
+void launch_symK(hipStream_t s, const Lay &L, const int *nopen, double *Kw) {
+  hipLaunchKernelGGL(k_symK, dim3((L.nmax + 63) / 64, L.nmax, L.ne), dim3(64), 0, s, nopen, Kw, L.ldk, L.sK);
 }
 
 // ---------------------------------------------------------------------------

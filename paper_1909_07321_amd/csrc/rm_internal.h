@@ -134,6 +134,23 @@ void launch_build(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi,
 void launch_lu_solve(hipStream_t s, int ne, int maxrows, int maxrhs, const int *dims, double *aug,
                      long ldaug, long strideA, long roff, int *ipiv, long ldp, int *bperm, double *linv, int tail,
                      int *status);
+// Back substitution alone: the right-hand sides of [U | Y] become U^-1 Y (U in
+// the upper triangle of each block of rows).
+void launch_backsub(hipStream_t s, int ne, int maxrows, int maxrhs, const int *dims, double *aug, long ldaug,
+                    long strideA, long roff, int tail);
+// Cholesky forward phase of [P | K] for symmetric positive definite P (lower
+// triangle read): L in the lower and L^T in the upper triangle, Z = L^-1 K in
+// the right-hand sides.  linv is scratch of ne * NBU * NBU doubles.
+void launch_chol_forward(hipStream_t s, int ne, int maxrows, int maxrhs, const int *dims, double *aug, long ldaug,
+                         long strideA, long roff, double *linv, int *status);
+// K <- (K + K^T) / 2 on each energy's leading nopen x nopen block.
+void launch_symK(hipStream_t s, const Lay &L, const int *nopen, double *Kw);
+// Lower block tiles of C = A B (no x no) for products known to be symmetric.
+void launch_gemm_lower(hipStream_t s, int ne, int maxn, const int *nopen, const double *A, long lda, long sA,
+                       const double *B, long ldb, long sB, double *C, long ldc, long sC);
+// C = A^T A (no x no), both triangles.
+void launch_gemm_ata(hipStream_t s, int ne, int maxn, const int *nopen, const double *A, long lda, long sA, double *C,
+                     long ldc, long sC);
 // C[e] = A[e] B[e] for square no x no blocks, no = nopen[e]
 void launch_gemm_sq(hipStream_t s, int ne, int maxn, const int *nopen, const double *A, long lda, long sA,
                     const double *B, long ldb, long sB, double *C, long ldc, long sC);

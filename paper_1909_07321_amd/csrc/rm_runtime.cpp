@@ -428,13 +428,15 @@ void stage_K(const Plan &P, Work &w, hipStream_t s) {
 }
 
 void stage_SO(const Plan &P, Work &w, bool want_S, hipStream_t s) {
-  // P = 1 + K K and X = P^-1 K on the same batched LU; then XK and Omega
+  // K symmetrised; P = 1 + K K = L L^T (Cholesky) with Z = L^-1 K carried
+  // along; XK = K P^-1 K = Z^T Z; X = P^-1 K = L^-T Z; then Omega
   const Lay &L = P.L;
-  launch_gemm_sq(s, L.ne, L.nmax, w.nopen, w.Kw, L.ldk, L.sK, w.Kw, L.ldk, L.sK, w.aug, L.ldaug, L.sA);
+  launch_symK(s, L, w.nopen, w.Kw);
+  launch_gemm_lower(s, L.ne, L.nmax, w.nopen, w.Kw, L.ldk, L.sK, w.Kw, L.ldk, L.sK, w.aug, L.ldaug, L.sA);
   launch_formP(s, L, w.nopen, w.Kw, w.aug, w.dims);
-  launch_lu_solve(s, L.ne, L.nmax, L.nmax, w.dims, w.aug, L.ldaug, L.sA, L.roff, w.ipiv, L.ldo, w.bperm, w.linv, 0,
-                  w.status);
-  launch_gemm_sq(s, L.ne, L.nmax, w.nopen, w.aug + L.roff, L.ldaug, L.sA, w.Kw, L.ldk, L.sK, w.XK, L.ldk, L.sK);
+  launch_chol_forward(s, L.ne, L.nmax, L.nmax, w.dims, w.aug, L.ldaug, L.sA, L.roff, w.linv, w.status);
+  launch_gemm_ata(s, L.ne, L.nmax, w.nopen, w.aug + L.roff, L.ldaug, L.sA, w.XK, L.ldk, L.sK);
+  launch_backsub(s, L.ne, L.nmax, L.nmax, w.dims, w.aug, L.ldaug, L.sA, L.roff, 0);
   launch_omega(s, L, w.tab, w.pwi, w.openpos, w.nopen, w.aug + L.roff, w.XK, w.omega, want_S ? w.S : nullptr);
 }
 

@@ -43,13 +43,15 @@ __device__ __forceinline__ void static_for(F &&f, std::integer_sequence<int, I..
   (f(std::integral_constant<int, I>{}), ...);
 }
 
-// LDS slabs of the 64 x 64 FP64 MFMA tiles.  The A operand is staged as it lies
-// in memory, [row][k] with pitch K + 2, the B operand as [k][col] with pitch
-// TILE + 16: with these pitches the fragment reads of one MFMA step (lanes
-// 0..31 and 32..63 each covering two k and sixteen rows or columns) fall on
-// distinct LDS banks, and the staging stores are row-contiguous.
-constexpr int PB = TILE + 16;
-template <int K> struct Pitch { static constexpr int A = K + 2; };
+// LDS slabs of the 64 x 64 FP64 MFMA tiles.  LDS serves 64-bit reads sixteen
+// lanes at a time from 32 four-byte banks.  The A operand is staged as it lies
+// in memory, [row][k], with an odd pitch K + 1: the sixteen lanes of a fragment
+// read take sixteen rows at one k, which an odd pitch spreads over all banks
+// (a pitch of 64 would put them on one bank pair).  The B operand is staged
+// [k][col]: sixteen lanes read sixteen consecutive columns, conflict-free at
+// pitch TILE.  Staging stores are row-contiguous.
+constexpr int PB = TILE;
+template <int K> struct Pitch { static constexpr int A = K + 1; };
 
 // Persistent distribution of per-energy work items: energy e belongs to XCD
 // e % NQ (workgroup b runs on XCD b % NQ), and the items of an XCD's energies go
@@ -925,7 +927,7 @@ __global__ __launch_bounds__(256) void k_chol_panel(int j0, const int *__restric
       const int i = idx / KB, k = idx % KB;
       sA[i][k] = (r0 + i < m && k < jb) ? A[(size_t)(c0 + r0 + i) * ldaug + j0 + k] : 0.0;
     }
-    for (int idx = t; idx < KB * KB; idx += 256) sB[idx % KB][idx / KB] = Li[idx];
+    for (int idx = t; idx < KB * KB; idx += 256) sB[idx / KB][idx % KB] = Li[(idx % KB) * KB + idx / KB];
     __syncthreads();
     d4 acc[4];
 #pragma unroll

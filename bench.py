@@ -56,10 +56,11 @@ def measured_traffic(kernel: str):
 
 
 def serve_measure(ctx, nreq: int) -> dict:
-    """Open-loop Poisson stream through rm_submit/rm_poll on a pool of resident
+    """Open-loop Poisson streams through rm_submit/rm_poll on a pool of resident
     partial waves (channel counts log-uniform in 10..2000, 30-40 poles per
-    channel, energies in [0.01, 8] Ry), half FP64 and half FP32-split requests.
-    The arrival rate is 0.7 x the capacity measured by a closed-loop burst."""
+    channel, energies in [0.01, 8] Ry), once all-FP64 and once all-FP32-split.
+    Each stream's arrival rate is 0.7 x the capacity measured by a closed-loop
+    burst of the same mode."""
     import numpy as np
 
     from paper_1909_07321_amd import rm, synth
@@ -68,15 +69,15 @@ def serve_measure(ctx, nreq: int) -> dict:
     ids = [ctx.pw_upload(p) for p in pool]
     block = (100, 4000)
 
-    def run_stream(reqs, rate_hz=None):
+    def run_stream(reqs, prec, rate_hz=None):
         t0 = time.perf_counter()
         tickets, pts = [], 0
-        for k, r in enumerate(reqs):
+        for r in reqs:
             if rate_hz:
                 wait = t0 + r.arrival_s - time.perf_counter()
                 if wait > 0:
                     time.sleep(wait)
-            t, _ = ctx.submit(ids[r.pw_index], r.energies, prec=rm.FP32_SPLIT if k % 2 else rm.FP64)
+            t, _ = ctx.submit(ids[r.pw_index], r.energies, prec=prec)
             tickets.append(t)
             pts += r.energies.size
         stats, pending = [], set(tickets)
@@ -89,23 +90,94 @@ def serve_measure(ctx, nreq: int) -> dict:
             time.sleep(0.0005)
         return pts, time.perf_counter() - t0, stats
 
-    burst = synth.config5_requests(pool, nreq=8, rate_hz=1.0, block_range=block)
-    pts, dt, _ = run_stream(burst)
-    capacity = pts / dt
-    mean_pts = float(np.mean([r.energies.size for r in burst]))
-    rate = 0.7 * capacity / mean_pts
-    reqs = synth.config5_requests(pool, nreq=nreq, rate_hz=rate, block_range=block)
-    pts, dt, stats = run_stream(reqs, rate_hz=rate)
-    lat = np.array([(s["t_done_ns"] - s["t_arrive_ns"]) * 1e-6 for s in stats])
+    out = {}
+    for name, prec in (("fp64", rm.FP64), ("split", rm.FP32_SPLIT)):
+        burst = synth.config5_requests(pool, nreq=8, rate_hz=1.0, block_range=block)
+        pts, dt, _ = run_stream(burst, prec)
+        capacity = pts / dt
+        mean_pts = float(np.mean([r.energies.size for r in burst]))
+        rate = 0.7 * capacity / mean_pts
+        reqs = synth.config5_requests(pool, nreq=nreq, rate_hz=rate, block_range=block)
+        pts, dt, stats = run_stream(reqs, prec, rate_hz=rate)
+        lat = np.array([(st["t_done_ns"] - st["t_arrive_ns"]) * 1e-6 for st in stats])
+        out[name] = dict(requests=nreq, arrival_rate_hz=rate, capacity_points_per_s=capacity, points=pts,
+                         points_per_s=pts / dt, p50_ms=float(np.median(lat)), p99_ms=float(np.quantile(lat, 0.99)),
+                         max_ms=float(lat.max()))
+        log(f"serving {name}: {nreq} requests at {rate:.2f}/s, {out[name]['points_per_s']:.0f} points/s, "
+            f"p50 {out[name]['p50_ms']:.0f} ms, p99 {out[name]['p99_ms']:.0f} ms")
     for i in ids:
         ctx.pw_release(i)
-    out = dict(requests=nreq, arrival_rate_hz=rate, capacity_points_per_s=capacity, points=pts,
-               points_per_s=pts / dt, p50_ms=float(np.median(lat)), p99_ms=float(np.quantile(lat, 0.99)),
-               max_ms=float(lat.max()), pool="16 partial waves, n log-uniform 10..2000, 30-40 poles/channel",
-               blocks=f"log-uniform {block[0]}..{block[1]} energies (reduced from 100..20000 to bound the run)",
-               modes="alternating FP64 / FP32-split requests")
-    log(f"serving: {nreq} requests at {rate:.2f}/s, {out['points_per_s']:.0f} points/s, "
-        f"p50 {out['p50_ms']:.0f} ms, p99 {out['p99_ms']:.0f} ms")
+    out["pool"] = "16 partial waves, n log-uniform 10..2000, 30-40 poles/channel"
+    out["blocks"] = f"log-uniform {block[0]}..{block[1]} energies (reduced from 100..20000 to bound the run)"
+    return out
+
+
+STAGES = ("rform", "nearpole", "asym", "ksolve", "somega")
+
+
+def drain_prof(ctx):
+    return {s_: ctx.prof_read(s_) for s_ in STAGES}
+
+
+def config_measure(ctx) -> dict:
+    """Throughput on the other workloads: the 200-channel wave (2000 energies,
+    both modes, one rm_run each) and the batch of 64 waves of 20..600 channels
+    (5000 energies each, FP64, one rm_run_batch).  R-stage points/s come from
+    the same run's R-contraction launch times."""
+    import torch
+
+    from paper_1909_07321_amd import rm, synth
+
+    dev = torch.device("cuda", 0)
+    out = {}
+    pw, E = synth.config2()
+    pid = ctx.pw_upload(pw)
+    Ed = torch.tensor(E, dtype=torch.float64, device=dev)
+    om = torch.empty((E.size, pw.ntarget, pw.ntarget), dtype=torch.float64, device=dev)
+    st = torch.empty(E.size, dtype=torch.int32, device=dev)
+    for name, prec in (("fp64", rm.FP64), ("split", rm.FP32_SPLIT)):
+        ctx.run(pid, Ed, prec=prec, want_K=False, out=(om, None, st))
+        torch.cuda.synchronize()
+        drain_prof(ctx)
+        ctx.prof_enable(True)
+        t1 = time.perf_counter()
+        ctx.run(pid, Ed, prec=prec, want_K=False, out=(om, None, st))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        ctx.prof_enable(False)
+        rf_ms, _, rf_e = drain_prof(ctx)["rform"]
+        out[f"c2_{name}"] = dict(points_per_s=E.size / dt, r_stage_points_per_s=rf_e / (rf_ms * 1e-3),
+                                 workload="one wave, 200 channels, 6000 poles, 2000 energies in [0.01, 6] Ry")
+        log(f"c2 {name}: {E.size / dt:.0f} points/s (R stage {rf_e / (rf_ms * 1e-3):.0f} points/s)")
+    ctx.pw_release(pid)
+
+    t0 = time.time()
+    pws, E = synth.config3()
+    ids = [ctx.pw_upload(p) for p in pws]
+    log(f"c3 workload generated in {time.time() - t0:.1f}s: {len(pws)} waves, {E.size} energies each")
+    Ed = torch.tensor(E, dtype=torch.float64, device=dev)
+    ctx.run_batch([(i, Ed[:64]) for i in ids], prec=rm.FP64)  # warm-up: workspaces and code
+    torch.cuda.synchronize()
+    drain_prof(ctx)
+    ctx.prof_enable(True)
+    t1 = time.perf_counter()
+    res = ctx.run_batch([(i, Ed) for i in ids], prec=rm.FP64)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    ctx.prof_enable(False)
+    rf_ms, _, rf_e = drain_prof(ctx)["rform"]
+    flagged = int(sum(int((r[2] != 0).sum().item()) for r in res))
+    del res
+    pts = len(ids) * E.size
+    flops = sum(float(p.nchan) * (p.nchan + 1) * p.npole for p in pws) * E.size
+    out["c3_fp64"] = dict(points_per_s=pts / dt, r_stage_points_per_s=rf_e / (rf_ms * 1e-3),
+                          r_tflops=flops / (rf_ms * 1e-3) / 1e12, seconds=dt, flagged_energies=flagged,
+                          workload="64 waves, 20..600 channels, 30 poles per channel, 5000 energies each, "
+                                   "one rm_run_batch call")
+    log(f"c3 fp64: {pts / dt:.0f} points/s over {dt:.1f}s (R stage {rf_e / (rf_ms * 1e-3):.0f} points/s, "
+        f"{flops / (rf_ms * 1e-3) / 1e12:.1f} TFLOP/s)")
+    for i in ids:
+        ctx.pw_release(i)
     return out
 
 
@@ -119,8 +191,10 @@ def main() -> int:
     ap.add_argument("--nenergy", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-threads", type=int, default=16)
-    ap.add_argument("--serving", type=int, default=32, metavar="NREQ",
-                    help="requests in the serving measurement (0 = skip)")
+    ap.add_argument("--serving", type=int, default=24, metavar="NREQ",
+                    help="requests per mode in the serving measurement (0 = skip)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the 200-channel and 64-wave batch throughput measurements")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a 1 GiB read + 1 GiB write kernel (HBM counter calibration under rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -197,6 +271,7 @@ def main() -> int:
     serving = None
     if args.serving > 0:
         serving = serve_measure(ctx, args.serving)
+    configs = None if args.no_configs else config_measure(ctx)
 
     cpu = None
     if not args.no_cpu:
@@ -227,6 +302,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "modes": results,
         "serving": serving,
+        "configs": configs,
     }
     print(json.dumps(line), flush=True)
     ctx.close()

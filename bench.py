@@ -178,6 +178,26 @@ def config_measure(ctx) -> dict:
         f"{flops / (rf_ms * 1e-3) / 1e12:.1f} TFLOP/s)")
     for i in ids:
         ctx.pw_release(i)
+
+    # sum over partial waves: 12 waves sharing 60 targets, both chunk orders
+    pws, E = synth.config_sum()
+    ids = [ctx.pw_upload(p) for p in pws]
+    Ed = torch.tensor(E, dtype=torch.float64, device=dev)
+    ctx.run_sum(ids, Ed[:64])
+    torch.cuda.synchronize()
+    for name, order in (("wave", rm.ORDER_WAVE), ("permuted", rm.ORDER_PERMUTED)):
+        t1 = time.perf_counter()
+        ctx.run_sum(ids, Ed, prec=rm.FP64, order=order)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        pts = len(ids) * E.size
+        out[f"sum_fp64_{name}_order"] = dict(
+            points_per_s=pts / dt, seconds=dt,
+            workload=f"{len(ids)} waves sharing 60 targets, {min(p.nchan for p in pws)}..{max(p.nchan for p in pws)} "
+                     f"channels, 30 poles per channel, {E.size} energies, Omega summed over the waves")
+        log(f"sum over {len(ids)} waves ({name} order): {pts / dt:.0f} points/s over {dt:.2f}s")
+    for i in ids:
+        ctx.pw_release(i)
     return out
 
 

@@ -182,6 +182,25 @@ typedef struct {
    sizes.  Results equal those of rm_run on each item alone. */
 rm_status rm_run_batch(rm_ctx *ctx, const rm_batch_item *items, int32_t nitems, const rm_opts *opts);
 
+/* Sum over partial waves of one collision problem (PSTGF paper, Glossary,
+   "Collision strength", and section "Overview", the outer loop over partial
+   waves: the collision strength is the sum of the partial ones):
+     omega[e][p][q] = sum over w = 0 .. npw-1 of Omega^(pw_ids[w])_pq(E[e]),
+   added in the order of pw_ids, so the result does not depend on scheduling.
+   status[e] is the OR of the waves' status bits (a flagged wave makes the sum
+   NaN).  All waves must have the same ntarget (RM_E_ARG otherwise).  order
+   chooses how (wave, energy) points fill the chunks: RM_ORDER_WAVE runs the
+   waves one after the other; RM_ORDER_PERMUTED gives every chunk a slice of
+   consecutive energies of every wave (the permuted (J pi, E) assignment of
+   section "Computational details", which spreads the slow energies).  Results
+   do not depend on it.
+   omega [ne][nt][nt] and status [ne] are host or device memory as
+   opts->device_ptrs says; the call returns when the sum is complete. */
+#define RM_ORDER_WAVE 0
+#define RM_ORDER_PERMUTED 1
+rm_status rm_run_sum(rm_ctx *ctx, const int32_t *pw_ids, int32_t npw, const double *E, int32_t ne, int32_t order,
+                     const rm_opts *opts, double *omega, int32_t *status);
+
 /* ------------------------------------------------------------------ serving */
 typedef struct {
   int32_t pw_id;

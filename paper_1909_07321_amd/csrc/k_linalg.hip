@@ -1333,6 +1333,30 @@ void launch_check_inputs(hipStream_t s, const Lay &L, const DevPW *tab, const in
                      L.ldk, L.sK, nopen, status);
 }
 
+// Sum over partial waves: one thread per (energy, p, q) element, waves added in
+// ascending order.
+__global__ void k_sum_waves(int npw, long per, int ne, const double *__restrict__ om, const int32_t *__restrict__ st,
+                            double *__restrict__ sum, int32_t *__restrict__ sst) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < per) {
+    double acc = 0.0;
+    for (int w = 0; w < npw; ++w) acc += om[(size_t)w * per + idx];
+    sum[idx] = acc;
+  }
+  if (idx < ne) {
+    int32_t f = 0;
+    for (int w = 0; w < npw; ++w) f |= st[(size_t)w * ne + idx];
+    sst[idx] = f;
+  }
+}
+
+void launch_sum_waves(hipStream_t s, int npw, int ne, int nt, const double *om, const int32_t *st, double *sum,
+                      int32_t *sst) {
+  const long per = (long)ne * nt * nt;
+  const long n = std::max<long>(per, ne);
+  hipLaunchKernelGGL(k_sum_waves, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, npw, per, ne, om, st, sum, sst);
+}
+
 // Output packing: energy e's leading block goes to pack + off[e], row-major.
 __global__ void k_pack(const DevPW *__restrict__ tab, const int *__restrict__ pwi, int what,
                        const double *__restrict__ src, long ld, long stride, const long *__restrict__ off,

@@ -165,6 +165,9 @@ void launch_finalize(hipStream_t s, const Lay &L, const DevPW *tab, const int *p
 void launch_check_inputs(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const double *E,
                          double thr, const double *R, const double *fg, const double *K, const int *nopen,
                          int *status);
+// sum[e][p][q] = sum over w (ascending) of om[w][e][p][q]; sst[e] = OR of st[w][e].
+void launch_sum_waves(hipStream_t s, int npw, int ne, int nt, const double *om, const int32_t *st, double *sum,
+                      int32_t *sst);
 // Packs each energy's leading nt x nt Omega block (what = 0) or n x n K block
 // (what = 1) contiguously at pack + off[e].
 void launch_pack(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, int what, const double *src,

@@ -1148,6 +1148,71 @@ rm_status rm_run_batch(rm_ctx *ctx, const rm_batch_item *items, int32_t nitems, 
   return run_segments(ctx, segs, o, true);
 }
 
+rm_status rm_run_sum(rm_ctx *ctx, const int32_t *pw_ids, int32_t npw, const double *E, int32_t ne, int32_t order,
+                     const rm_opts *opts, double *omega, int32_t *status) {
+  if (!ctx || npw < 1 || !pw_ids || ne < 0 || (ne > 0 && (!E || !omega || !status)) ||
+      (order != RM_ORDER_WAVE && order != RM_ORDER_PERMUTED))
+    return RM_E_ARG;
+  (void)hipSetDevice(ctx->device);
+  const rm_opts o = fixed_opts(opts);
+  std::vector<const DevPW *> pws(npw);
+  for (int w = 0; w < npw; ++w) {
+    if (rm_status st = get_pw(ctx, pw_ids[w], &pws[w])) return st;
+    if (pws[w]->nt != pws[0]->nt) {
+      ctx->err = "partial waves of a sum must share their targets (same ntarget)";
+      return RM_E_ARG;
+    }
+  }
+  if (ne == 0) return RM_OK;
+  const int nt = pws[0]->nt;
+  const size_t per = (size_t)ne * nt * nt;
+  const hipStream_t user = call_stream(ctx, o);
+  // device temporaries: every wave's Omega and status, the energies, the sum
+  struct Tmp {
+    hipStream_t s = nullptr;
+    void *p[3] = {nullptr, nullptr, nullptr};
+    ~Tmp() {
+      if (s) (void)hipStreamSynchronize(s);  // no buffer is freed under running work
+      for (void *q : p)
+        if (q) (void)hipFree(q);
+    }
+  } tmp;
+  tmp.s = user;
+  double *tom, *dE, *sum;
+  int32_t *tst, *sst;
+  HIPCHK(hipMalloc(&tmp.p[0], sizeof(double) * per * npw + sizeof(int32_t) * (size_t)ne * npw));
+  tom = static_cast<double *>(tmp.p[0]);
+  tst = reinterpret_cast<int32_t *>(tom + per * npw);
+  if (o.device_ptrs) {
+    dE = const_cast<double *>(E);
+    sum = omega;
+    sst = status;
+  } else {
+    HIPCHK(hipMalloc(&tmp.p[1], sizeof(double) * ne));
+    HIPCHK(hipMalloc(&tmp.p[2], sizeof(double) * per + sizeof(int32_t) * ne));
+    dE = static_cast<double *>(tmp.p[1]);
+    sum = static_cast<double *>(tmp.p[2]);
+    sst = reinterpret_cast<int32_t *>(sum + per);
+    HIPCHK(hipMemcpyAsync(dE, E, sizeof(double) * ne, hipMemcpyHostToDevice, user));
+  }
+  std::vector<Seg> segs;
+  for (int w = 0; w < npw; ++w) segs.push_back(Seg{pws[w], dE, ne, tom + per * w, nullptr, tst + (size_t)ne * w});
+  rm_opts od = o;
+  od.device_ptrs = 1;
+  od.stream = user;
+  if (rm_status st = run_segments(ctx, segs, od, order == RM_ORDER_PERMUTED)) {
+    (void)hipStreamSynchronize(user);
+    return st;
+  }
+  launch_sum_waves(user, npw, ne, nt, tom, tst, sum, sst);
+  if (!o.device_ptrs) {
+    HIPCHK(hipMemcpyAsync(omega, sum, sizeof(double) * per, hipMemcpyDeviceToHost, user));
+    HIPCHK(hipMemcpyAsync(status, sst, sizeof(int32_t) * ne, hipMemcpyDeviceToHost, user));
+  }
+  HIPCHK(hipStreamSynchronize(user));
+  return RM_OK;
+}
+
 rm_status rm_submit(rm_ctx *ctx, const rm_request *req, uint64_t *ticket) {
   if (!ctx || !req || !ticket || req->ne < 0 || (req->ne > 0 && (!req->E || !req->omega || !req->status)) ||
       req->opts.device_ptrs)

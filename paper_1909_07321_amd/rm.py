@@ -20,6 +20,7 @@ RM_OK, RM_PENDING = 0, 1
 RM_E_ARG, RM_E_NOMEM, RM_E_DEVICE, RM_E_NOTFOUND, RM_E_BUSY = -1, -2, -3, -4, -5
 PT_POLE, PT_THRESHOLD, PT_NOCONV, PT_SINGULAR, PT_NONFINITE = 1, 2, 4, 8, 16
 FP64, FP32_SPLIT = 0, 1
+ORDER_WAVE, ORDER_PERMUTED = 0, 1
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"librm.so not built ({LIB_PATH}); run __graft_entry__.build()")
@@ -74,6 +75,7 @@ _lib.rm_solve_K.argtypes = [_vp, _i32, _vp, _i32, _vp, _vp, ctypes.POINTER(Opts)
 _lib.rm_collision_strengths.argtypes = [_vp, _i32, _vp, _i32, _vp, ctypes.POINTER(Opts), _vp, _vp, _vp]
 _lib.rm_run.argtypes = [_vp, _i32, _vp, _i32, ctypes.POINTER(Opts), _vp, _vp, _vp]
 _lib.rm_run_batch.argtypes = [_vp, ctypes.POINTER(BatchItem), _i32, ctypes.POINTER(Opts)]
+_lib.rm_run_sum.argtypes = [_vp, ctypes.POINTER(_i32), _i32, _vp, _i32, _i32, ctypes.POINTER(Opts), _vp, _vp]
 _lib.rm_submit.argtypes = [_vp, ctypes.POINTER(Request), ctypes.POINTER(_u64)]
 _lib.rm_poll.argtypes = [_vp, _u64, ctypes.POINTER(ReqStats)]
 _lib.rm_drain.argtypes = [_vp]
@@ -83,7 +85,7 @@ _lib.rm_prof_read.argtypes = [_vp, ctypes.c_char_p, ctypes.POINTER(_d), ctypes.P
 
 EXPORTS = ["rm_opts_default", "rm_create", "rm_destroy", "rm_last_error", "rm_pw_upload", "rm_pw_release",
            "rm_pw_footprint", "rm_form_R", "rm_asymptotic", "rm_solve_K", "rm_collision_strengths", "rm_run",
-           "rm_run_batch",
+           "rm_run_batch", "rm_run_sum",
            "rm_submit", "rm_poll", "rm_drain", "rm_prof_enable", "rm_prof_read"]
 
 
@@ -270,6 +272,20 @@ class Context:
         o = self._opts(prec, split_delta, thr_guard, dev)
         self._check(_lib.rm_run_batch(self.h, arr, len(items), ctypes.byref(o)))
         return outs
+
+    def run_sum(self, pw_ids, E, prec=FP64, order=ORDER_PERMUTED, split_delta=0.05, thr_guard=1e-10):
+        """Omega summed over the partial waves pw_ids (same targets), added in
+        that order; returns (omega [ne][nt][nt], status [ne])."""
+        E, dev = self._E(E)
+        ne = E.shape[0]
+        nt = self._pw.get(pw_ids[0], (1, 1))[1]
+        om = self._alloc(E, (ne, nt, nt), np.float64)
+        st = self._alloc(E, (ne,), np.int32)
+        ids = (_i32 * len(pw_ids))(*pw_ids)
+        o = self._opts(prec, split_delta, thr_guard, dev)
+        self._check(_lib.rm_run_sum(self.h, ids, len(pw_ids), _ptr(E), ne, order, ctypes.byref(o), _ptr(om),
+                                    _ptr(st)))
+        return om, st
 
     # ------------------------------------------------------------ serving
     def submit(self, pw_id, E, prec=FP64, split_delta=0.05, thr_guard=1e-10, want_K=False):

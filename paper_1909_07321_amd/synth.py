@@ -145,6 +145,45 @@ def make_partial_wave(seed: int, nchan: int, poles_per_chan: float, *, z: float,
                        e_target, l, target, Ek, np.ascontiguousarray(w))
 
 
+def partial_wave_family(seed: int, npw: int, ntarget: int, chan_per_target: tuple[int, int],
+                        poles_per_chan: float, *, z: float, a: float, thr_range: tuple[float, float],
+                        pole_range: tuple[float, float], lmax: int = 12,
+                        avoid_energies: np.ndarray | None = None, name: str = "fam") -> list[PartialWave]:
+    """Partial waves of one collision problem: they share the targets (target 0
+    at 0 Ry, the others sorted uniform in ``thr_range``), and wave w couples each
+    target to a uniform number of channels in ``chan_per_target`` (channels
+    ordered by target), with its own l values, poles and amplitudes.  Wave w has
+    statistical weight g = 2w + 1 (a stand-in for 2J + 1)."""
+    for attempt in range(1000):
+        e_target = np.concatenate([[0.0], np.sort(Stream(seed, f"{name}/targets/{attempt}").uniform(ntarget - 1,
+                                                                                                   *thr_range))])
+        if avoid_energies is None or _thresholds_clear(e_target, avoid_energies):
+            break
+    else:  # pragma: no cover
+        raise RuntimeError("could not place thresholds away from the energy grid")
+    out = []
+    for w in range(npw):
+        counts = Stream(seed, f"{name}/w{w}/counts").integers(ntarget, *chan_per_target)
+        target = np.repeat(np.arange(ntarget), counts).astype(np.int32)
+        n = int(target.size)
+        M = int(round(poles_per_chan * n))
+        l = Stream(seed, f"{name}/w{w}/l").integers(n, 0, lmax).astype(np.int32)
+        Ek = np.sort(Stream(seed, f"{name}/w{w}/poles").uniform(M, *pole_range))
+        amp = (Stream(seed, f"{name}/w{w}/amp").normal(M * n) / math.sqrt(a)).reshape(M, n)
+        out.append(PartialWave(n, M, ntarget, float(a), 0.0, float(z), float(2 * w + 1), e_target.copy(), l, target,
+                               Ek, np.ascontiguousarray(amp)))
+    return out
+
+
+def config_sum(npw: int = 12, nenergy: int = 2000) -> tuple[list[PartialWave], np.ndarray]:
+    """Sum over partial waves: 12 waves sharing 60 targets (thresholds in
+    [0, 4] Ry), 1..4 channels per target, 30 poles per channel in [-2, 60] Ry,
+    z=5, a=12, 2000 energies uniform in [0.01, 6] Ry."""
+    E = np.linspace(0.01, 6.0, nenergy)
+    return partial_wave_family(config_seed(6), npw, 60, (1, 4), 30, z=5.0, a=12.0, thr_range=(0.0, 4.0),
+                               pole_range=(-2.0, 60.0), avoid_energies=E, name="sum"), E
+
+
 def config_seed(index: int) -> int:
     return 1909 * 1000 + index
 

@@ -444,6 +444,7 @@ __global__ __launch_bounds__(64) void k_lu_blockperm(int p0, const int *__restri
 // source rows of the net permutation into LDS and loads the rows that move out
 // of the block into registers (every load before any store), writes the moved
 // rows, then forms the 64 x 64 product.
+constexpr int TRSM_G = 8;
 __global__ __launch_bounds__(256) void k_lu_trsm_inv(int p0, const int *__restrict__ dims, double *__restrict__ aug,
                                                      long ldaug, long strideA, long roff,
                                                      const int *__restrict__ bperm, const double *__restrict__ linv,
@@ -457,57 +458,62 @@ __global__ __launch_bounds__(256) void k_lu_trsm_inv(int p0, const int *__restri
   const int lane = t & 63, wave = t >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int kk = lane >> 4, ii = lane & 15;
-  for_items(ne, tiles_n, [&](int e, int tile) {
+  // an item is a group of TRSM_G column tiles of one energy: L11^-1 and the
+  // permutation are staged once for the group
+  for_items(ne, (tiles_n + TRSM_G - 1) / TRSM_G, [&](int e, int grp) {
     const int rows = dims[2 * e], rhs = dims[2 * e + 1];
     if (p0 >= rows) return;
     const int jb = min(KB, rows - p0);
     const int c0 = p0 + jb;
     const int ncols = (rows - c0) + rhs;
-    const int v0 = tile * TILE;
-    if (v0 >= ncols) return;
+    if (grp * TRSM_G * TILE >= ncols) return;
     double *A = aug + (size_t)e * strideA;
     const int *pm = bperm + (size_t)e * BPERM;
     const double *Li = linv + (size_t)e * KB * KB;
     for (int idx = t; idx < 1 + 3 * KB; idx += 256) sp[idx] = pm[idx];
-    if (t < TILE) scol[t] = v0 + t < ncols ? vcol(v0 + t, rows, c0, roff) : -1;
     for (int idx = t; idx < KB * KB; idx += 256) sL[idx / KB][idx % KB] = Li[idx];
-    __syncthreads();
-    const int nout = sp[0];
-    for (int idx = t; idx < KB * TILE; idx += 256) {
-      const int k = idx / TILE, j = idx % TILE;
-      const long col = scol[j];
-      sX[k][j] = (k < jb && col >= 0) ? A[(size_t)sp[1 + k] * ldaug + col] : 0.0;
-    }
-    constexpr int NY = KB * TILE / 256;
-    double yv[NY];
-#pragma unroll
-    for (int q = 0; q < NY; ++q) {
-      const int idx = t + 256 * q, k = idx / TILE, j = idx % TILE;
-      const long col = scol[j];
-      yv[q] = (k < nout && col >= 0) ? A[(size_t)sp[1 + KB + k] * ldaug + col] : 0.0;
-    }
-    __syncthreads();  // every load of the workgroup has completed
-#pragma unroll
-    for (int q = 0; q < NY; ++q) {
-      const int idx = t + 256 * q, k = idx / TILE, j = idx % TILE;
-      const long col = scol[j];
-      if (k < nout && col >= 0) A[(size_t)sp[1 + 2 * KB + k] * ldaug + col] = yv[q];
-    }
-    d4 acc[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = d4{0, 0, 0, 0};
-    mfma_slab<KB>(sL, sX, acc, wr, wc, kk, ii);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const long col = scol[wc * 32 + (q & 1) * 16 + ii];
-      if (col < 0) continue;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = wr * 32 + (q >> 1) * 16 + 4 * v + kk;
-        if (i < jb) A[(size_t)(p0 + i) * ldaug + col] = acc[q][v];
+    for (int g = 0; g < TRSM_G; ++g) {
+      const int v0 = (grp * TRSM_G + g) * TILE;
+      if (v0 >= ncols) break;
+      if (t < TILE) scol[t] = v0 + t < ncols ? vcol(v0 + t, rows, c0, roff) : -1;
+      __syncthreads();
+      const int nout = sp[0];
+      for (int idx = t; idx < KB * TILE; idx += 256) {
+        const int k = idx / TILE, j = idx % TILE;
+        const long col = scol[j];
+        sX[k][j] = (k < jb && col >= 0) ? A[(size_t)sp[1 + k] * ldaug + col] : 0.0;
       }
+      constexpr int NY = KB * TILE / 256;
+      double yv[NY];
+#pragma unroll
+      for (int q = 0; q < NY; ++q) {
+        const int idx = t + 256 * q, k = idx / TILE, j = idx % TILE;
+        const long col = scol[j];
+        yv[q] = (k < nout && col >= 0) ? A[(size_t)sp[1 + KB + k] * ldaug + col] : 0.0;
+      }
+      __syncthreads();  // every load of the workgroup has completed
+#pragma unroll
+      for (int q = 0; q < NY; ++q) {
+        const int idx = t + 256 * q, k = idx / TILE, j = idx % TILE;
+        const long col = scol[j];
+        if (k < nout && col >= 0) A[(size_t)sp[1 + 2 * KB + k] * ldaug + col] = yv[q];
+      }
+      d4 acc[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = d4{0, 0, 0, 0};
+      mfma_slab<KB>(sL, sX, acc, wr, wc, kk, ii);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const long col = scol[wc * 32 + (q & 1) * 16 + ii];
+        if (col < 0) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = wr * 32 + (q >> 1) * 16 + 4 * v + kk;
+          if (i < jb) A[(size_t)(p0 + i) * ldaug + col] = acc[q][v];
+        }
+      }
+      __syncthreads();  // LDS is reused by the next tile
     }
-    __syncthreads();  // LDS is reused by the next item
   });
 }
 
@@ -614,7 +620,7 @@ __device__ __forceinline__ void rowblock_update(const double (*sL)[Pitch<KB>::A]
 }
 
 // Column tiles per workgroup of the streaming updates.
-constexpr int UPD_G = 4;
+constexpr int UPD_G = 64;
 
 // Trailing update A22 -= L21 U12 for the block of kb columns starting at p0:
 // rows [c0, rows) with c0 = p0 + jb, trailing columns as in trailing_cols.
@@ -654,14 +660,16 @@ __global__ __launch_bounds__(256, 2) void k_lu_update(int p0, const int *__restr
 // Back substitution, diagonal block: Y_b = U_bb^-1 B_b for the right-hand sides,
 // one thread per right-hand side with its column in registers and U_bb in LDS
 // (column-oriented: each solved entry is eliminated from the rows above it).
+constexpr int BS_G = 4;
 template <int KB, int T>
 __global__ __launch_bounds__(T) void k_bs_block(int j0, const int *__restrict__ dims, double *__restrict__ aug,
                                                 long ldaug, long strideA, long roff, int tiles, int ne, int tail) {
   __shared__ double U[KB][KB];
   const int t = threadIdx.x;
-  for_items(ne, tiles, [&](int e, int tile) {
+  // an item is a group of BS_G column tiles of one energy: U_bb is staged once
+  for_items(ne, (tiles + BS_G - 1) / BS_G, [&](int e, int grp) {
     const int rows = dims[2 * e], rhs = dims[2 * e + 1];
-    if (j0 >= rows || tile * T >= rhs) return;
+    if (j0 >= rows || grp * BS_G * T >= rhs) return;
     if (tail && j0 + KB <= rows - rhs) return;  // block above the rows that are needed
     const int jb = min(KB, rows - j0);
     double *A = aug + (size_t)e * strideA;
@@ -670,27 +678,29 @@ __global__ __launch_bounds__(T) void k_bs_block(int j0, const int *__restrict__ 
       U[r][c] = (r < jb && c < jb) ? A[(size_t)(j0 + r) * ldaug + j0 + c] : (r == c ? 1.0 : 0.0);
     }
     __syncthreads();
-    const int q = tile * T + t;
-    if (q < rhs) {
-      const long col = roff + q;
-      double x[KB];
-      static_for([&](auto rI) {
-        constexpr int r = decltype(rI)::value;
-        x[r] = r < jb ? A[(size_t)(j0 + r) * ldaug + col] : 0.0;
-      }, std::make_integer_sequence<int, KB>{});
-      static_for([&](auto rI) {
-        constexpr int r = KB - 1 - decltype(rI)::value;
-        const double d = U[r][r];
-        x[r] = d != 0.0 ? x[r] / d : 0.0;
-        static_for([&](auto iI) {
-          constexpr int i = decltype(iI)::value;
-          if constexpr (i < r) x[i] -= U[i][r] * x[r];
+    for (int g = 0; g < BS_G; ++g) {
+      const int q = (grp * BS_G + g) * T + t;
+      if (q < rhs) {
+        const long col = roff + q;
+        double x[KB];
+        static_for([&](auto rI) {
+          constexpr int r = decltype(rI)::value;
+          x[r] = r < jb ? A[(size_t)(j0 + r) * ldaug + col] : 0.0;
         }, std::make_integer_sequence<int, KB>{});
-      }, std::make_integer_sequence<int, KB>{});
-      static_for([&](auto rI) {
-        constexpr int r = decltype(rI)::value;
-        if (r < jb) A[(size_t)(j0 + r) * ldaug + col] = x[r];
-      }, std::make_integer_sequence<int, KB>{});
+        static_for([&](auto rI) {
+          constexpr int r = KB - 1 - decltype(rI)::value;
+          const double d = U[r][r];
+          x[r] = d != 0.0 ? x[r] / d : 0.0;
+          static_for([&](auto iI) {
+            constexpr int i = decltype(iI)::value;
+            if constexpr (i < r) x[i] -= U[i][r] * x[r];
+          }, std::make_integer_sequence<int, KB>{});
+        }, std::make_integer_sequence<int, KB>{});
+        static_for([&](auto rI) {
+          constexpr int r = decltype(rI)::value;
+          if (r < jb) A[(size_t)(j0 + r) * ldaug + col] = x[r];
+        }, std::make_integer_sequence<int, KB>{});
+      }
     }
     __syncthreads();  // U is reused by the next item
   });
@@ -799,8 +809,8 @@ void launch_lu_solve(hipStream_t s, int ne, int maxrows, int maxrhs, const int *
     const int ncols = (maxrows - c0) + maxrhs;
     if (ncols <= 0) continue;
     const int tn = (ncols + TILE - 1) / TILE;
-    hipLaunchKernelGGL(k_lu_trsm_inv, dim3(persist_grid(k_lu_trsm_inv, 256, ne, tn)), dim3(256), 0, s, j0, dims, aug,
-                       ldaug, strideA, roff, bperm, linv, tn, ne);
+    hipLaunchKernelGGL(k_lu_trsm_inv, dim3(persist_grid(k_lu_trsm_inv, 256, ne, (tn + TRSM_G - 1) / TRSM_G)),
+                       dim3(256), 0, s, j0, dims, aug, ldaug, strideA, roff, bperm, linv, tn, ne);
     const int m = maxrows - c0;
     if (m <= 0) continue;
     const int tm = (m + TILE - 1) / TILE, gr = (ncols + UPD_G * TILE - 1) / (UPD_G * TILE);
@@ -818,7 +828,8 @@ void launch_backsub(hipStream_t s, int ne, int maxrows, int maxrhs, const int *d
   if (maxrhs <= 0) return;
   for (int j0 = (maxrows - 1) / NBU * NBU; j0 >= 0; j0 -= NBU) {
     const int tb = (maxrhs + T64 - 1) / T64;
-    hipLaunchKernelGGL((k_bs_block<NBU, T64>), dim3(persist_grid(k_bs_block<NBU, T64>, T64, ne, tb)), dim3(T64), 0, s,
+    hipLaunchKernelGGL((k_bs_block<NBU, T64>), dim3(persist_grid(k_bs_block<NBU, T64>, T64, ne, (tb + BS_G - 1) / BS_G)),
+                       dim3(T64), 0, s,
                        j0, dims, aug, ldaug, strideA, roff, tb, ne, tail);
     if (j0 == 0) break;
     const int tm = (j0 + TILE - 1) / TILE, gr = (maxrhs + UPD_G * TILE - 1) / (UPD_G * TILE);

@@ -1032,11 +1032,12 @@ void launch_chol_forward(hipStream_t s, int ne, int maxrows, int maxrhs, const i
 // ---------------------------------------------------------------------------
 // Small batched GEMM, C = A B (square no x no per energy), FP64 MFMA.
 // ---------------------------------------------------------------------------
-template <bool TA, bool LOWER, bool MIRROR>
+// FORMP: C = 1 + A B, and A (= K) copied to C's right-hand-side columns at roff.
+template <bool TA, bool LOWER, bool MIRROR, bool FORMP = false>
 __global__ __launch_bounds__(256) void k_gemm_sq(const int *__restrict__ nopen, const double *__restrict__ A,
                                                  long lda, long sA, const double *__restrict__ B, long ldb,
                                                  long sB, double *__restrict__ C, long ldc, long sC,
-                                                 int tiles_n, int ne) {
+                                                 int tiles_n, int ne, long roff = 0) {
   constexpr int GK = 32;
   constexpr int NL = TILE * GK / 256;  // slab elements per thread (A and B each)
   __shared__ double sa[TILE][Pitch<GK>::A];  // sa[i][k] = A[r0 + i][k0 + k]
@@ -1098,8 +1099,12 @@ __global__ __launch_bounds__(256) void k_gemm_sq(const int *__restrict__ nopen, 
     for (int v = 0; v < 4; ++v) {
       const int i = r0 + wr * 32 + (q >> 1) * 16 + 4 * v + kk;
       if (i < n) {
-        Ce[(size_t)i * ldc + j] = acc[q][v];
+        Ce[(size_t)i * ldc + j] = FORMP && i == j ? 1.0 + acc[q][v] : acc[q][v];
         if (MIRROR && tm != tn) Ce[(size_t)j * ldc + i] = acc[q][v];
+        if (FORMP) {
+          Ce[(size_t)i * ldc + roff + j] = Ae[(size_t)i * lda + j];
+          if (tm != tn) Ce[(size_t)j * ldc + roff + i] = Ae[(size_t)j * lda + i];
+        }
       }
     }
   }
@@ -1112,6 +1117,16 @@ void launch_gemm_sq(hipStream_t s, int ne, int maxn, const int *nopen, const dou
   const int tn = (maxn + TILE - 1) / TILE;
   hipLaunchKernelGGL((k_gemm_sq<false, false, false>), dim3(persist_grid(k_gemm_sq<false, false, false>, 256, ne,
                      (long)tn * tn)), dim3(256), 0, s, nopen, A, lda, sA, B, ldb, sB, C, ldc, sC, tn, ne);
+}
+
+// [1 + K K | K] for the S/Omega stage: the lower block tiles of 1 + K K and all
+// of K in the right-hand-side columns.
+void launch_formP(hipStream_t s, int ne, int maxn, const int *nopen, const double *K, long ldk, long sK, double *aug,
+                  long ldaug, long sA, long roff) {
+  if (maxn <= 0) return;
+  const int tn = (maxn + TILE - 1) / TILE;
+  hipLaunchKernelGGL((k_gemm_sq<false, true, false, true>), dim3(persist_grid(k_gemm_sq<false, true, false, true>, 256,
+                     ne, (long)tn * tn)), dim3(256), 0, s, nopen, K, ldk, sK, K, ldk, sK, aug, ldaug, sA, tn, ne, roff);
 }
 
 // Lower triangle (block tiles) of C = A B for symmetric products.
@@ -1132,64 +1147,87 @@ void launch_gemm_ata(hipStream_t s, int ne, int maxn, const int *nopen, const do
                      (long)tn * tn)), dim3(256), 0, s, nopen, A, lda, sA, A, lda, sA, C, ldc, sC, tn, ne);
 }
 
-// K <- (K + K^T) / 2 on the leading nopen x nopen block.
-__global__ void k_symK(const int *__restrict__ nopen, double *__restrict__ Kw, long ldk, long strideK) {
-  const int e = blockIdx.z, i = blockIdx.y;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int no = nopen[e];
-  if (i >= no || j >= i) return;
-  double *K = Kw + (size_t)e * strideK;
-  const double v = 0.5 * (K[(size_t)i * ldk + j] + K[(size_t)j * ldk + i]);
-  K[(size_t)i * ldk + j] = v;
-  K[(size_t)j * ldk + i] = v;
-}
-
-void launch_symK(hipStream_t s, const Lay &L, const int *nopen, double *Kw) {
-  hipLaunchKernelGGL(k_symK, dim3((L.nmax + 63) / 64, L.nmax, L.ne), dim3(64), 0, s, nopen, Kw, L.ldk, L.sK);
-}
 
 // ---------------------------------------------------------------------------
 // K gather, P = 1 + K^2 set-up, collision strengths
 // ---------------------------------------------------------------------------
-__global__ void k_gatherK(const DevPW *__restrict__ tab, const int *__restrict__ pwi, const int *__restrict__ nopen,
-                          const double *__restrict__ aug, long ldaug, long strideA, long roff,
-                          double *__restrict__ Kw, long ldk, long strideK, int nmax) {
-  const int e = blockIdx.z, i = blockIdx.y;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nmax || j >= nmax) return;
-  const int no = nopen[e], n = tab[pwi[e]].n;
-  double v = 0.0;
-  if (i < no && j < no) v = aug[(size_t)e * strideA + (size_t)(n - no + i) * ldaug + roff + j];
-  Kw[(size_t)e * strideK + (size_t)i * ldk + j] = v;
-}
-
-void launch_gatherK(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *nopen,
-                    const double *aug, double *Kw) {
-  hipLaunchKernelGGL(k_gatherK, dim3((L.nmax + 63) / 64, L.nmax, L.ne), dim3(64), 0, s, tab, pwi, nopen, aug,
-                     L.ldaug, L.sA, L.roff, Kw, L.ldk, L.sK, L.nmax);
-}
-
-// aug rows [0, no): columns [0, no) hold K K (already written); add 1 on the
-// diagonal and copy K into the right-hand-side columns; dims = {no, no}.
-__global__ void k_formP(const int *__restrict__ nopen, const double *__restrict__ Kw, long ldk, long strideK,
-                        double *__restrict__ aug, long ldaug, long strideA, long roff, int *__restrict__ dims) {
-  const int e = blockIdx.z, i = blockIdx.y;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int no = nopen[e];
-  if (i == 0 && j == 0) {
+// K from the solution: the last nopen rows of Y (the open unknowns), written
+// symmetrised, K_ij = (Y_ij + Y_ji) / 2, with zeros for i or j in [nopen, n);
+// also dims = {nopen, nopen} for the S/Omega stage.  32 x 32 tiles, the
+// transposed tile staged in LDS so that every access is row-contiguous.
+__global__ __launch_bounds__(256) void k_gatherK(const DevPW *__restrict__ tab, const int *__restrict__ pwi,
+                                                 const int *__restrict__ nopen, const double *__restrict__ aug,
+                                                 long ldaug, long strideA, long roff, double *__restrict__ Kw, long ldk,
+                                                 long strideK, int *__restrict__ dims, int nt32) {
+  const int e = blockIdx.y;
+  const int ti = blockIdx.x / nt32, tj = blockIdx.x % nt32;
+  const int n = tab[pwi[e]].n, no = nopen[e];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     dims[2 * e] = no;
     dims[2 * e + 1] = no;
   }
-  if (i >= no || j >= no) return;
-  double *row = aug + (size_t)e * strideA + (size_t)i * ldaug;
-  if (i == j) row[j] += 1.0;
-  row[roff + j] = Kw[(size_t)e * strideK + (size_t)i * ldk + j];
+  const int i0 = ti * 32, j0 = tj * 32;
+  if (i0 >= n || j0 >= n) return;
+  __shared__ double t1[32][33], t2[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const double *Y = aug + (size_t)e * strideA + (size_t)(n - no) * ldaug + roff;
+  for (int r = ty; r < 32; r += 8) {
+    const int i = i0 + r, j = j0 + tx, i2 = j0 + r, j2 = i0 + tx;
+    t1[r][tx] = (i < no && j < no) ? Y[(size_t)i * ldaug + j] : 0.0;
+    t2[r][tx] = (i2 < no && j2 < no) ? Y[(size_t)i2 * ldaug + j2] : 0.0;
+  }
+  __syncthreads();
+  double *K = Kw + (size_t)e * strideK;
+  for (int r = ty; r < 32; r += 8) {
+    const int i = i0 + r, j = j0 + tx;
+    if (i < n && j < n) K[(size_t)i * ldk + j] = (i < no && j < no) ? 0.5 * (t1[r][tx] + t2[tx][r]) : 0.0;
+  }
 }
 
-void launch_formP(hipStream_t s, const Lay &L, const int *nopen, const double *Kw, double *aug, int *dims) {
-  hipLaunchKernelGGL(k_formP, dim3((L.nmax + 63) / 64 + 1, L.nmax + 1, L.ne), dim3(64), 0, s, nopen, Kw, L.ldk,
-                     L.sK, aug, L.ldaug, L.sA, L.roff, dims);
+void launch_gatherK(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *nopen,
+                    const double *aug, double *Kw, int *dims) {
+  const int nt32 = (L.nmax + 31) / 32;
+  hipLaunchKernelGGL(k_gatherK, dim3(nt32 * nt32, L.ne), dim3(256), 0, s, tab, pwi, nopen, aug, L.ldaug, L.sA,
+                     L.roff, Kw, L.ldk, L.sK, dims, nt32);
 }
+
+// K given by the caller (the staged S/Omega call): symmetrised in place on the
+// leading nopen x nopen block, one pair of mirrored 32 x 32 tiles per block;
+// dims = {nopen, nopen}.
+__global__ __launch_bounds__(256) void k_symK(const int *__restrict__ nopen, double *__restrict__ Kw, long ldk,
+                                              long strideK, int *__restrict__ dims, int nt32) {
+  const int e = blockIdx.y;
+  const int no = nopen[e];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    dims[2 * e] = no;
+    dims[2 * e + 1] = no;
+  }
+  int ti = 0;
+  while ((ti + 1) * (ti + 2) / 2 <= (int)blockIdx.x) ++ti;
+  const int tj = blockIdx.x - ti * (ti + 1) / 2;  // tile pair (ti, tj), ti >= tj
+  const int i0 = ti * 32, j0 = tj * 32;
+  if (i0 >= no) return;
+  __shared__ double t1[32][33], t2[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  double *K = Kw + (size_t)e * strideK;
+  for (int r = ty; r < 32; r += 8) {
+    const int i = i0 + r, j = j0 + tx, i2 = j0 + r, j2 = i0 + tx;
+    t1[r][tx] = (i < no && j < no) ? K[(size_t)i * ldk + j] : 0.0;
+    t2[r][tx] = (i2 < no && j2 < no) ? K[(size_t)i2 * ldk + j2] : 0.0;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int i = i0 + r, j = j0 + tx, i2 = j0 + r, j2 = i0 + tx;
+    if (i < no && j < no) K[(size_t)i * ldk + j] = 0.5 * (t1[r][tx] + t2[tx][r]);
+    if (i2 < no && j2 < no) K[(size_t)i2 * ldk + j2] = 0.5 * (t2[r][tx] + t1[tx][r]);
+  }
+}
+
+void launch_symK(hipStream_t s, const Lay &L, const int *nopen, double *Kw, int *dims) {
+  const int nt32 = (L.nmax + 31) / 32;
+  hipLaunchKernelGGL(k_symK, dim3(nt32 * (nt32 + 1) / 2, L.ne), dim3(256), 0, s, nopen, Kw, L.ldk, L.sK, dims, nt32);
+}
+
 
 // Omega_pq for one energy and one target row p per wave; lanes stride over q.
 // Each entry sums its channel pairs in a fixed order (no atomics), so results

@@ -143,8 +143,11 @@ void launch_backsub(hipStream_t s, int ne, int maxrows, int maxrhs, const int *d
 // the right-hand sides.  linv is scratch of ne * NBU * NBU doubles.
 void launch_chol_forward(hipStream_t s, int ne, int maxrows, int maxrhs, const int *dims, double *aug, long ldaug,
                          long strideA, long roff, double *linv, int *status);
-// K <- (K + K^T) / 2 on each energy's leading nopen x nopen block.
-void launch_symK(hipStream_t s, const Lay &L, const int *nopen, double *Kw);
+// K <- (K + K^T) / 2 on each energy's leading nopen x nopen block; dims = {nopen, nopen}.
+void launch_symK(hipStream_t s, const Lay &L, const int *nopen, double *Kw, int *dims);
+// [1 + K K | K] in aug (lower block tiles of 1 + K K; K in the right-hand sides at roff).
+void launch_formP(hipStream_t s, int ne, int maxn, const int *nopen, const double *K, long ldk, long sK, double *aug,
+                  long ldaug, long sA, long roff);
 // Lower block tiles of C = A B (no x no) for products known to be symmetric.
 void launch_gemm_lower(hipStream_t s, int ne, int maxn, const int *nopen, const double *A, long lda, long sA,
                        const double *B, long ldb, long sB, double *C, long ldc, long sC);
@@ -154,10 +157,10 @@ void launch_gemm_ata(hipStream_t s, int ne, int maxn, const int *nopen, const do
 // C[e] = A[e] B[e] for square no x no blocks, no = nopen[e]
 void launch_gemm_sq(hipStream_t s, int ne, int maxn, const int *nopen, const double *A, long lda, long sA,
                     const double *B, long ldb, long sB, double *C, long ldc, long sC);
-// K = the last nopen rows of the solution (the open channels, ascending).
+// K = the last nopen rows of the solution (the open channels, ascending),
+// symmetrised, zero past nopen; dims = {nopen, nopen}.
 void launch_gatherK(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *nopen,
-                    const double *aug, double *Kw);
-void launch_formP(hipStream_t s, const Lay &L, const int *nopen, const double *Kw, double *aug, int *dims);
+                    const double *aug, double *Kw, int *dims);
 void launch_omega(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *openpos,
                   const int *nopen, const double *X, const double *XK, double *omega, double *S);
 void launch_finalize(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, int *status, double *omega,

@@ -424,16 +424,14 @@ void stage_K(const Plan &P, Work &w, hipStream_t s) {
   launch_build(s, L, w.tab, w.pwi, w.fg, w.nopen, w.openidx, w.colpos, w.aug);
   launch_lu_solve(s, L.ne, L.nmax, L.nmax, w.dims, w.aug, L.ldaug, L.sA, L.roff, w.ipiv, L.ldo, w.bperm, w.linv, 1,
                   w.status);
-  launch_gatherK(s, L, w.tab, w.pwi, w.nopen, w.aug, w.Kw);
+  launch_gatherK(s, L, w.tab, w.pwi, w.nopen, w.aug, w.Kw, w.dims);
 }
 
 void stage_SO(const Plan &P, Work &w, bool want_S, hipStream_t s) {
-  // K symmetrised; P = 1 + K K = L L^T (Cholesky) with Z = L^-1 K carried
+  // K (symmetric, in Kw); P = 1 + K K = L L^T (Cholesky) with Z = L^-1 K carried
   // along; XK = K P^-1 K = Z^T Z; X = P^-1 K = L^-T Z; then Omega
   const Lay &L = P.L;
-  launch_symK(s, L, w.nopen, w.Kw);
-  launch_gemm_lower(s, L.ne, L.nmax, w.nopen, w.Kw, L.ldk, L.sK, w.Kw, L.ldk, L.sK, w.aug, L.ldaug, L.sA);
-  launch_formP(s, L, w.nopen, w.Kw, w.aug, w.dims);
+  launch_formP(s, L.ne, L.nmax, w.nopen, w.Kw, L.ldk, L.sK, w.aug, L.ldaug, L.sA, L.roff);
   launch_chol_forward(s, L.ne, L.nmax, L.nmax, w.dims, w.aug, L.ldaug, L.sA, L.roff, w.linv, w.status);
   launch_gemm_ata(s, L.ne, L.nmax, w.nopen, w.aug + L.roff, L.ldaug, L.sA, w.XK, L.ldk, L.sK);
   launch_backsub(s, L.ne, L.nmax, L.nmax, w.dims, w.aug, L.ldaug, L.sA, L.roff, 0);
@@ -1110,6 +1108,7 @@ rm_status rm_collision_strengths(rm_ctx *ctx, int32_t pwid, const double *E, int
                             sizeof(double) * n, (size_t)m * n, kind_in(o), s));
     launch_openlist(s, L, w.tab, w.pwi, w.E, w.nopen, w.openidx, w.openpos, w.colpos, w.openflag);
     launch_check_inputs(s, L, w.tab, w.pwi, w.E, o.thr_guard, nullptr, nullptr, w.Kw, w.nopen, w.status);
+    launch_symK(s, L, w.nopen, w.Kw, w.dims);
     stage_SO(P, w, S != nullptr, s);
     launch_finalize(s, L, w.tab, w.pwi, w.status, w.omega, nullptr, S ? w.S : nullptr);
     HIPCHK(hipMemcpyAsync(omega + (size_t)e0 * nt * nt, w.omega, sizeof(double) * m * nt * nt, kind_out(o), s));

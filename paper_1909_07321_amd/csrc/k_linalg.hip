@@ -562,59 +562,102 @@ __global__ __launch_bounds__(T) void k_lu_trsm(int p0, const int *__restrict__ d
   }
 }
 
+// Memory column of virtual column v of a trailing block: the A part (acols
+// wide, from column c0), then the right-hand sides from column roff.
+struct ColMap {
+  int acols, c0;
+  long roff;
+  __device__ __forceinline__ long operator()(int v) const { return v < acols ? (long)(c0 + v) : roff + (v - acols); }
+};
+
 // C (64 rows x G column tiles) -= Lb (64 x KB, staged in sL) * U (KB x columns),
-// one column tile at a time: a tile's C values are loaded while its product is
-// formed, and the next tile's U slab is loaded into registers meanwhile.
-// cptr(i, v) addresses C's element (i, v); uval(k, v) returns U's element
-// (k, v) (0 past the block).
-template <int KB, int G, typename CPtr, typename UVal>
+// one column tile at a time.  The next tile's C values and U slab are loaded
+// into registers while the current tile is multiplied, so two tiles of C are
+// in flight per workgroup.  Cb and Ub point at row 0 of the C block and of U;
+// both are addressed through the column map cm; U rows past jb read as 0.
+template <int KB, int G>
 __device__ __forceinline__ void rowblock_update(const double (*sL)[Pitch<KB>::A], double (*sU)[PB], int mrem,
-                                                int vbeg, int ncols, CPtr cptr, UVal uval) {
+                                                int vbeg, int ncols, ColMap cm, double *Cb, const double *Ub, int jb,
+                                                long ld) {
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int kk = lane >> 4, ii = lane & 15;
   constexpr int NU = KB * TILE / 256;
-  double nu[NU];
-  auto loadU = [&](int v0) {
+  // U slab: this thread stages column ju, rows ku0 + 4q
+  const int ju = t % TILE, ku0 = t / TILE;
+  // C: rows wr*32 + h*16 + 4v + kk (h, v) and columns wc*32 + c*16 + ii (c)
+  long rowoff[8];
+  bool rok[8];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = wr * 32 + h * 16 + 4 * v + kk;
+      rok[h * 4 + v] = i < mrem;
+      rowoff[h * 4 + v] = (long)i * ld;
+    }
+  auto loadU = [&](int v0, double (&dst)[NU]) {
+    const int v = v0 + ju;
+    const bool ok = v < ncols;
+    const long col = ok ? cm(v) : 0;
 #pragma unroll
     for (int q = 0; q < NU; ++q) {
-      const int idx = t + 256 * q, k = idx / TILE, j = idx % TILE;
-      nu[q] = v0 + j < ncols ? uval(k, v0 + j) : 0.0;
+      const int k = ku0 + 4 * q;
+      dst[q] = (ok && k < jb) ? Ub[(long)k * ld + col] : 0.0;
     }
   };
-  loadU(vbeg);
+  auto cols = [&](int v0, long (&col)[2], bool (&cok)[2]) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int v = v0 + wc * 32 + c * 16 + ii;
+      cok[c] = v < ncols;
+      col[c] = cok[c] ? cm(v) : 0;
+    }
+  };
+  auto loadC = [&](int v0, double (&dst)[16]) {
+    long col[2];
+    bool cok[2];
+    cols(v0, col, cok);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          dst[(h * 2 + c) * 4 + v] = (rok[h * 4 + v] && cok[c]) ? Cb[rowoff[h * 4 + v] + col[c]] : 0.0;
+  };
+  double nu[NU], cv[16], cn[16];
+  loadU(vbeg, nu);
+  loadC(vbeg, cv);
   for (int g = 0; g < G; ++g) {
     const int v0 = vbeg + g * TILE;
     if (v0 >= ncols) break;
 #pragma unroll
-    for (int q = 0; q < NU; ++q) {
-      const int idx = t + 256 * q;
-      sU[idx / TILE][idx % TILE] = nu[q];
-    }
+    for (int q = 0; q < NU; ++q) sU[ku0 + 4 * q][ju] = nu[q];
     __syncthreads();
-    double cv[16];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = wr * 32 + (q >> 1) * 16 + 4 * v + kk;
-        const int jv = v0 + wc * 32 + (q & 1) * 16 + ii;
-        cv[q * 4 + v] = (i < mrem && jv < ncols) ? *cptr(i, jv) : 0.0;
-      }
-    if (g + 1 < G && v0 + TILE < ncols) loadU(v0 + TILE);
+    const bool more = g + 1 < G && v0 + TILE < ncols;
+    if (more) {
+      loadU(v0 + TILE, nu);
+      loadC(v0 + TILE, cn);
+    }
     d4 acc[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[q] = d4{0, 0, 0, 0};
     mfma_slab<KB>(sL, sU, acc, wr, wc, kk, ii);
+    long col[2];
+    bool cok[2];
+    cols(v0, col, cok);
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = wr * 32 + (q >> 1) * 16 + 4 * v + kk;
-        const int jv = v0 + wc * 32 + (q & 1) * 16 + ii;
-        if (i < mrem && jv < ncols) *cptr(i, jv) = cv[q * 4 + v] - acc[q][v];
-      }
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (rok[h * 4 + v] && cok[c]) Cb[rowoff[h * 4 + v] + col[c]] = cv[(h * 2 + c) * 4 + v] - acc[h * 2 + c][v];
+    if (more)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) cv[q] = cn[q];
     __syncthreads();
   }
 }
@@ -649,11 +692,8 @@ __global__ __launch_bounds__(256, 2) void k_lu_update(int p0, const int *__restr
       const int i = idx / KB, k = idx % KB;
       sL[i][k] = (r0 + i < m && k < jb) ? A[(size_t)(c0 + r0 + i) * ldaug + p0 + k] : 0.0;
     }
-    double *Cb = A + (size_t)(c0 + r0) * ldaug;
-    rowblock_update<KB, UPD_G>(
-        sL, sU, m - r0, vbeg, ncols,
-        [&](int i, int v) { return Cb + (size_t)i * ldaug + vcol2(v, acols, c0, roff); },
-        [&](int k, int v) { return k < jb ? A[(size_t)(p0 + k) * ldaug + vcol2(v, acols, c0, roff)] : 0.0; });
+    rowblock_update<KB, UPD_G>(sL, sU, m - r0, vbeg, ncols, ColMap{acols, c0, roff}, A + (size_t)(c0 + r0) * ldaug,
+                               A + (size_t)p0 * ldaug, jb, ldaug);
   });
 }
 
@@ -727,10 +767,8 @@ __global__ __launch_bounds__(256, 2) void k_bs_update(int j0, const int *__restr
       const int i = idx / KB, k = idx % KB;
       sU[i][k] = (r0 + i < j0 && k < jb) ? A[(size_t)(r0 + i) * ldaug + j0 + k] : 0.0;
     }
-    double *Cb = A + (size_t)r0 * ldaug + roff;
-    rowblock_update<KB, UPD_G>(
-        sU, sY, j0 - r0, qbeg, rhs, [&](int i, int q) { return Cb + (size_t)i * ldaug + q; },
-        [&](int k, int q) { return k < jb ? A[(size_t)(j0 + k) * ldaug + roff + q] : 0.0; });
+    rowblock_update<KB, UPD_G>(sU, sY, j0 - r0, qbeg, rhs, ColMap{0, 0, roff}, A + (size_t)r0 * ldaug,
+                               A + (size_t)j0 * ldaug, jb, ldaug);
   });
 }
 

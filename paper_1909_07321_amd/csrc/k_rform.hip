@@ -232,20 +232,37 @@ __device__ __forceinline__ void rform_body(const DevPW *__restrict__ tab, const 
       if (st + 1 < nstage) gload((st + 1) * KC);
       const T(*pA)[TILE] = sA[buf];
       const T(*pB)[TILE] = diag ? sA[buf] : sB[buf];
-#pragma unroll 4
+      // fragments of step ks + 4 are read from LDS while step ks is multiplied
+      T a0 = pA[kk][ca0], a1 = pA[kk][ca1], b0 = pB[kk][cb0], b1 = pB[kk][cb1];
+      T d[EB];
+#pragma unroll
+      for (int e = 0; e < EB; ++e) d[e] = sD[buf][e][kk];
+#pragma unroll
       for (int ks = 0; ks < KC; ks += 4) {
-        const T a0 = pA[ks + kk][ca0];
-        const T a1 = pA[ks + kk][ca1];
-        const T b0 = pB[ks + kk][cb0];
-        const T b1 = pB[ks + kk][cb1];
+        T na0 = a0, na1 = a1, nb0 = b0, nb1 = b1, nd[EB];
+        if (ks + 4 < KC) {
+          na0 = pA[ks + 4 + kk][ca0];
+          na1 = pA[ks + 4 + kk][ca1];
+          nb0 = pB[ks + 4 + kk][cb0];
+          nb1 = pB[ks + 4 + kk][cb1];
+#pragma unroll
+          for (int e = 0; e < EB; ++e) nd[e] = sD[buf][e][ks + 4 + kk];
+        }
 #pragma unroll
         for (int e = 0; e < EB; ++e) {
-          const T d = sD[buf][e][ks + kk];
-          const T x0 = a0 * d, x1 = a1 * d;
+          const T x0 = a0 * d[e], x1 = a1 * d[e];
           acc[e][0] = mfma16(x0, b0, acc[e][0]);
           acc[e][1] = mfma16(x0, b1, acc[e][1]);
           acc[e][2] = mfma16(x1, b0, acc[e][2]);
           acc[e][3] = mfma16(x1, b1, acc[e][3]);
+        }
+        if (ks + 4 < KC) {
+          a0 = na0;
+          a1 = na1;
+          b0 = nb0;
+          b1 = nb1;
+#pragma unroll
+          for (int e = 0; e < EB; ++e) d[e] = nd[e];
         }
       }
       if (st + 1 < nstage) sstore(buf ^ 1);

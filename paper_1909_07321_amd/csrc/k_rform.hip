@@ -80,16 +80,18 @@ void launch_dvec(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, 
 }
 
 // ---------------------------------------------------------------------------
-// Contraction kernel.  One workgroup (4 waves) owns a 64 x 64 tile (bi, bj),
-// bi >= bj, of the lower triangle for EB energies.  Per stage it copies a
-// KC x 64 panel of W rows for the tile's channels i and j into LDS (one panel
-// when bi == bj), then every wave computes its 32 x 32 quarter with 2 x 2
-// MFMA 16x16x4 tiles per energy, scaling the A fragment by d_k(E) in
-// registers.  MFMA operand layout (16x16x4): lane l holds A[l%16][l/16] and
-// B[l/16][l%16]; the result rows are given by MfmaRow.  Row r of a staged panel
-// is stored rotated by 16 (r % 4) elements: a fragment read touches four
-// consecutive rows at the same columns, which the rotation spreads over
-// distinct LDS banks.
+// Contraction kernel.  Every wave works on its own: a task is one lower-
+// triangle 32 x 32 tile (bi, bj), bi >= bj, of one partial wave for up to EB
+// energies of that wave.  Per stage of KW poles the wave copies the KW x 32
+// slices of W for the tile's rows i and columns j (one slice on a diagonal
+// tile) into its own LDS region, then forms its 2 x 2 MFMA 16x16x4 blocks per
+// energy, scaling the A fragment by d_k(E) in registers.  No workgroup barrier
+// is involved: the next stage's slices are loaded into registers while the
+// current one is multiplied, and a wave's own LDS accesses are ordered.  MFMA
+// operand layout (16x16x4): lane l holds A[l%16][l/16] and B[l/16][l%16]; the
+// result rows are given by MfmaRow.  The FP32 slices rotate odd rows by 16
+// elements so that the two k-rows read by one 32-lane half fall on distinct
+// banks.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -124,38 +126,41 @@ template <typename T> __device__ __forceinline__ const T *amplitudes(const DevPW
 template <> __device__ __forceinline__ const double *amplitudes<double>(const DevPW &p) { return p.W64; }
 template <> __device__ __forceinline__ const float *amplitudes<float>(const DevPW &p) { return p.W32; }
 
-// Persistent: every workgroup takes tasks from the queue of its XCD until it is
-// empty, then from the other queues in turn; a task is one tile of one partial
-// wave for up to EB energies of that wave.  Each energy's sums run over k in
-// ascending order whatever workgroup takes the task, so results do not depend
-// on scheduling.
-template <typename T, int KC>
-__device__ __forceinline__ void rform_body(const DevPW *__restrict__ tab, const RTask *__restrict__ tasks,
+// One wave's LDS region.
+template <typename T, int KW> struct WaveLds {
+  T a[KW][RT];
+  T b[KW][RT];
+  T d[EB][KW];
+};
+
+// Persistent: every wave takes tasks from the queue of its XCD until it is
+// empty, then from the other queues in turn.  Each energy's sums run over k in
+// ascending order whatever wave takes the task, so results do not depend on
+// scheduling.
+template <typename T, int KW>
+__device__ __forceinline__ void rform_wave(const DevPW *__restrict__ tab, const RTask *__restrict__ tasks,
                                            const RQueues &qs, int *__restrict__ counter, const T *__restrict__ D,
                                            long ldD, double *__restrict__ R, long ldr, long strideR,
-                                           T (*sA)[KC][TILE], T (*sB)[KC][TILE], T (*sD)[EB][KC], int &stask) {
+                                           WaveLds<T, KW> &sm) {
   typedef typename Vec4<T>::type V4;
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
+  const int lane = threadIdx.x & 63;
   const int kk = lane >> 4, ii = lane & 15;
   constexpr int VEC = 16 / sizeof(T);            // elements per 16-byte load
-  constexpr int PER_ROW = TILE / VEC;            // vectors per row
-  constexpr int NVEC = KC * PER_ROW / 256;       // vectors per thread per panel
-  constexpr int ND = (EB * KC + 255) / 256;      // d values per thread per stage
+  constexpr int PER_ROW = RT / VEC;              // vectors per slice row
+  constexpr int NVEC = KW * PER_ROW / 64;        // vectors per lane per slice
+  constexpr int ND = EB * KW / 64;               // scale factors per lane per stage
+  constexpr int ROT = sizeof(T) == 4 ? 16 : 0;   // odd-row rotation of the FP32 slices
+  static_assert(NVEC * 64 == KW * PER_ROW && ND * 64 == EB * KW, "stage shape");
   typedef T TV __attribute__((ext_vector_type(VEC)));
 
-  // fragment columns in the rotated panel rows (ks is a multiple of 4, so row
-  // ks + kk is rotated by 16 kk)
-  const int ca0 = (wr * 32 + ii + 16 * kk) & (TILE - 1), ca1 = (wr * 32 + 16 + ii + 16 * kk) & (TILE - 1);
-  const int cb0 = (wc * 32 + ii + 16 * kk) & (TILE - 1), cb1 = (wc * 32 + 16 + ii + 16 * kk) & (TILE - 1);
-  // start with the queue of the XCD this workgroup runs on (hardware register
+  // fragment columns in the slice rows (row ks + kk is rotated when kk is odd)
+  const int c0 = (ii + ROT * (kk & 1)) & (RT - 1), c1 = (16 + ii + ROT * (kk & 1)) & (RT - 1);
+  // start with the queue of the XCD this wave runs on (hardware register
   // XCC_ID, bits [3:0])
   int q = __builtin_amdgcn_s_getreg((3 << 11) | 20) & (NQ - 1), tried = 0;
   for (;;) {
-    if (tid == 0) {
-      int task = -1;
+    int task = -1;
+    if (lane == 0) {
       while (tried < NQ) {
         const int len = qs.start[q + 1] - qs.start[q];
         const int idx = len > 0 ? atomicAdd(counter + q, 1) : len;
@@ -166,11 +171,8 @@ __device__ __forceinline__ void rform_body(const DevPW *__restrict__ tab, const 
         q = (q + 1) % NQ;
         ++tried;
       }
-      stask = task;
     }
-    __syncthreads();
-    const int task = stask;
-    __syncthreads();
+    task = __shfl(task, 0);
     if (task < 0) return;
     const RTask tk = tasks[task];
     const DevPW &p = tab[tk.slot];
@@ -180,7 +182,7 @@ __device__ __forceinline__ void rform_body(const DevPW *__restrict__ tab, const 
     int bi, bj;
     tri_tile(tk.tile, bi, bj);
     const bool diag = bi == bj;
-    const int i0 = bi * TILE, j0 = bj * TILE;
+    const int i0 = bi * RT, j0 = bj * RT;
 
     V4 acc[EB][4];
 #pragma unroll
@@ -188,85 +190,59 @@ __device__ __forceinline__ void rform_body(const DevPW *__restrict__ tab, const 
 #pragma unroll
       for (int m = 0; m < 4; ++m) acc[e][m] = V4{0, 0, 0, 0};
 
-    // register-staged double buffering: the next stage's global loads are in
-    // flight while the current stage is multiplied out of LDS
     TV ra[NVEC], rb[NVEC];
     T rd[ND];
     auto gload = [&](int k0) {
 #pragma unroll
       for (int r = 0; r < NVEC; ++r) {
-        const int idx = tid + 256 * r;
+        const int idx = lane + 64 * r;
         const int row = idx / PER_ROW, col = (idx % PER_ROW) * VEC;
         ra[r] = *reinterpret_cast<const TV *>(W + (size_t)(k0 + row) * ldw + i0 + col);
         if (!diag) rb[r] = *reinterpret_cast<const TV *>(W + (size_t)(k0 + row) * ldw + j0 + col);
       }
 #pragma unroll
       for (int r = 0; r < ND; ++r) {
-        const int idx = tid + 256 * r;
-        const int e = idx / KC, k = idx % KC;
-        if (idx < EB * KC) rd[r] = e < me ? D[(size_t)(e0 + e) * ldD + k0 + k] : T(0);
+        const int idx = lane + 64 * r;
+        const int e = idx / KW, k = idx % KW;
+        rd[r] = e < me ? D[(size_t)(e0 + e) * ldD + k0 + k] : T(0);
       }
     };
-    auto sstore = [&](int buf) {
+    auto sstore = [&]() {
 #pragma unroll
       for (int r = 0; r < NVEC; ++r) {
-        const int idx = tid + 256 * r;
+        const int idx = lane + 64 * r;
         const int row = idx / PER_ROW, col = (idx % PER_ROW) * VEC;
-        const int scol = (col + 16 * (row & 3)) & (TILE - 1);
-        *reinterpret_cast<TV *>(&sA[buf][row][scol]) = ra[r];
-        if (!diag) *reinterpret_cast<TV *>(&sB[buf][row][scol]) = rb[r];
+        const int scol = (col + ROT * (row & 1)) & (RT - 1);
+        *reinterpret_cast<TV *>(&sm.a[row][scol]) = ra[r];
+        if (!diag) *reinterpret_cast<TV *>(&sm.b[row][scol]) = rb[r];
       }
 #pragma unroll
       for (int r = 0; r < ND; ++r) {
-        const int idx = tid + 256 * r;
-        if (idx < EB * KC) sD[buf][idx / KC][idx % KC] = rd[r];
+        const int idx = lane + 64 * r;
+        sm.d[idx / KW][idx % KW] = rd[r];
       }
     };
 
-    const int nstage = Mpad / KC;
+    const int nstage = Mpad / KW;
+    const T(*pB)[RT] = diag ? sm.a : sm.b;
     gload(0);
-    sstore(0);
-    __syncthreads();
     for (int st = 0; st < nstage; ++st) {
-      const int buf = st & 1;
-      if (st + 1 < nstage) gload((st + 1) * KC);
-      const T(*pA)[TILE] = sA[buf];
-      const T(*pB)[TILE] = diag ? sA[buf] : sB[buf];
-      // fragments of step ks + 4 are read from LDS while step ks is multiplied
-      T a0 = pA[kk][ca0], a1 = pA[kk][ca1], b0 = pB[kk][cb0], b1 = pB[kk][cb1];
-      T d[EB];
+      sstore();
+      if (st + 1 < nstage) gload((st + 1) * KW);
 #pragma unroll
-      for (int e = 0; e < EB; ++e) d[e] = sD[buf][e][kk];
-#pragma unroll
-      for (int ks = 0; ks < KC; ks += 4) {
-        T na0 = a0, na1 = a1, nb0 = b0, nb1 = b1, nd[EB];
-        if (ks + 4 < KC) {
-          na0 = pA[ks + 4 + kk][ca0];
-          na1 = pA[ks + 4 + kk][ca1];
-          nb0 = pB[ks + 4 + kk][cb0];
-          nb1 = pB[ks + 4 + kk][cb1];
-#pragma unroll
-          for (int e = 0; e < EB; ++e) nd[e] = sD[buf][e][ks + 4 + kk];
-        }
+      for (int ks = 0; ks < KW; ks += 4) {
+        const T a0 = sm.a[ks + kk][c0], a1 = sm.a[ks + kk][c1];
+        const T b0 = pB[ks + kk][c0], b1 = pB[ks + kk][c1];
 #pragma unroll
         for (int e = 0; e < EB; ++e) {
-          const T x0 = a0 * d[e], x1 = a1 * d[e];
+          const T d = sm.d[e][ks + kk];
+          const T x0 = a0 * d, x1 = a1 * d;
           acc[e][0] = mfma16(x0, b0, acc[e][0]);
           acc[e][1] = mfma16(x0, b1, acc[e][1]);
           acc[e][2] = mfma16(x1, b0, acc[e][2]);
           acc[e][3] = mfma16(x1, b1, acc[e][3]);
         }
-        if (ks + 4 < KC) {
-          a0 = na0;
-          a1 = na1;
-          b0 = nb0;
-          b1 = nb1;
-#pragma unroll
-          for (int e = 0; e < EB; ++e) d[e] = nd[e];
-        }
       }
-      if (st + 1 < nstage) sstore(buf ^ 1);
-      __syncthreads();
     }
 
     // epilogue: lower-triangle elements are written to (i, j) and mirrored to (j, i)
@@ -276,10 +252,10 @@ __device__ __forceinline__ void rform_body(const DevPW *__restrict__ tab, const 
       double *Re = R + (size_t)(e0 + e) * strideR;
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        const int j = j0 + wc * 32 + (m & 1) * 16 + ii;
+        const int j = j0 + (m & 1) * 16 + ii;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int i = i0 + wr * 32 + (m >> 1) * 16 + MfmaRow<T>::row(kk, v);
+          const int i = i0 + (m >> 1) * 16 + MfmaRow<T>::row(kk, v);
           if (i < n && j < n && i >= j) {
             const double val = (double)acc[e][m][v];
             Re[(size_t)i * ldr + j] = val;
@@ -291,28 +267,23 @@ __device__ __forceinline__ void rform_body(const DevPW *__restrict__ tab, const 
   }
 }
 
-// The FP32 variant is held to two waves per SIMD (its accumulators are half the
-// size); the FP64 one keeps its 128 accumulator registers at one wave per SIMD.
+// Four independent waves per workgroup.  The FP32 variant is held to two waves
+// per SIMD (its accumulators are half the size); the FP64 one keeps its 256
+// accumulator registers at one wave per SIMD.
 __global__ __launch_bounds__(256, 2) void k_rform_f32(const DevPW *__restrict__ tab, const RTask *__restrict__ tasks,
                                                       const RQueues qs, int *__restrict__ counter,
                                                       const float *__restrict__ D, long ldD, double *__restrict__ R,
                                                       long ldr, long strideR) {
-  __shared__ float sA[2][KC32][TILE];
-  __shared__ float sB[2][KC32][TILE];
-  __shared__ float sD[2][EB][KC32];
-  __shared__ int stask;
-  rform_body<float, KC32>(tab, tasks, qs, counter, D, ldD, R, ldr, strideR, sA, sB, sD, stask);
+  __shared__ WaveLds<float, KW32> sm[4];
+  rform_wave<float, KW32>(tab, tasks, qs, counter, D, ldD, R, ldr, strideR, sm[threadIdx.x >> 6]);
 }
 
 __global__ __launch_bounds__(256) void k_rform_f64(const DevPW *__restrict__ tab, const RTask *__restrict__ tasks,
                                                    const RQueues qs, int *__restrict__ counter,
                                                    const double *__restrict__ D, long ldD, double *__restrict__ R,
                                                    long ldr, long strideR) {
-  __shared__ double sA[2][KC64][TILE];
-  __shared__ double sB[2][KC64][TILE];
-  __shared__ double sD[2][EB][KC64];
-  __shared__ int stask;
-  rform_body<double, KC64>(tab, tasks, qs, counter, D, ldD, R, ldr, strideR, sA, sB, sD, stask);
+  __shared__ WaveLds<double, KW64> sm[4];
+  rform_wave<double, KW64>(tab, tasks, qs, counter, D, ldD, R, ldr, strideR, sm[threadIdx.x >> 6]);
 }
 
 __global__ void k_reset(int *__restrict__ counter) {

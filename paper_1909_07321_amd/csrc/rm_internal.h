@@ -9,9 +9,13 @@ namespace rm {
 
 // Output tile of the R contraction and of the batched GEMMs (rows x cols).
 constexpr int TILE = 64;
-// Poles staged per LDS buffer in the R contraction (FP64 path; FP32 stages twice as many).
-constexpr int KC64 = 32;
-constexpr int KC32 = 64;
+// Output tile of one wave in the R contraction, and the poles one wave stages per
+// step (FP64 and FP32): the same 4 KB of amplitudes per slice.
+constexpr int RT = 32;
+constexpr int KW64 = 16;
+constexpr int KW32 = 32;
+// Pole-dimension padding of resident amplitudes (a multiple of both).
+constexpr int MALIGN = 64;
 // Energies that share one staged amplitude panel in the R contraction.
 constexpr int EB = 8;
 // Panel width of the blocked LU (one register-resident panel) and the outer
@@ -27,7 +31,7 @@ constexpr int BPERM = 1 + 3 * NBU;
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
 // A partial wave resident in HBM.  Amplitudes are stored pole-major with the
-// channel dimension padded to TILE and the pole dimension padded to KC32, the
+// channel dimension padded to TILE and the pole dimension padded to MALIGN, the
 // padding filled with zeros so every tile load is in bounds and contributes 0.
 // The struct is plain data: a chunk's partial waves are copied to the device as
 // a table, and every kernel reads its energy's entry through a per-energy slot
@@ -60,7 +64,7 @@ struct Lay {
 };
 
 // One task of the R contraction: energies [e0, e0 + m) (m <= EB, one partial
-// wave, table slot `slot`) times one lower-triangle tile.
+// wave, table slot `slot`) times one lower-triangle RT x RT tile.
 struct RTask {
   int slot, e0, m, tile;
 };

@@ -324,7 +324,7 @@ rm_status upload_plan(rm_ctx *ctx, Slot &sl, Plan &P, const std::vector<Seg> &se
   for (size_t pi = 0; pi < P.parts.size(); ++pi) {
     const Part &pt = P.parts[pi];
     const DevPW *p = P.slots[pt.slot];
-    const int tl = p->npad / TILE;
+    const int tl = (p->n + RT - 1) / RT;
     const double c = (double)p->Mpad * ((pt.m + EB - 1) / EB);
     for (int t = 0; t < tl * (tl + 1) / 2; ++t) units.push_back(Unit{(int)pi, t, c});
   }
@@ -498,7 +498,7 @@ void finish_plan(Plan &P, const std::vector<Seg> &segs, int ne) {
 int plan_tasks(const Plan &P) {
   int nt = 0;
   for (const Part &pt : P.parts) {
-    const int tl = P.slots[pt.slot]->npad / TILE;
+    const int tl = (P.slots[pt.slot]->n + RT - 1) / RT;
     nt += (pt.m + EB - 1) / EB * (tl * (tl + 1) / 2);
   }
   return nt;
@@ -888,7 +888,7 @@ const char *rm_last_error(const rm_ctx *ctx) { return ctx ? ctx->err.c_str() : "
 
 size_t rm_pw_footprint(int32_t nchan, int32_t npole) {
   const size_t npad = (size_t)round_up(std::max(nchan, 1), TILE);
-  const size_t Mpad = (size_t)round_up(std::max(npole, 1), KC32);
+  const size_t Mpad = (size_t)round_up(std::max(npole, 1), MALIGN);
   return Mpad * npad * 12 + Mpad * 8 + (size_t)nchan * 24 + 4096;
 }
 
@@ -923,7 +923,7 @@ rm_status rm_pw_upload(rm_ctx *ctx, const rm_pw_desc *d, int32_t *pw_id) {
   p.M = d->npole;
   p.nt = d->ntarget;
   p.npad = round_up(p.n, TILE);
-  p.Mpad = round_up(p.M, KC32);
+  p.Mpad = round_up(p.M, MALIGN);
   p.a = d->a;
   p.b = d->b;
   p.z = d->z;

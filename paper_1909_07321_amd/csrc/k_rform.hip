@@ -127,7 +127,7 @@ template <> __device__ __forceinline__ const double *amplitudes<double>(const De
 template <> __device__ __forceinline__ const float *amplitudes<float>(const DevPW &p) { return p.W32; }
 
 // One wave's LDS region.
-template <typename T, int KW> struct WaveLds {
+template <typename T, int KW, int EB> struct WaveLds {
   T a[KW][RT];
   T b[KW][RT];
   T d[EB][KW];
@@ -137,20 +137,20 @@ template <typename T, int KW> struct WaveLds {
 // empty, then from the other queues in turn.  Each energy's sums run over k in
 // ascending order whatever wave takes the task, so results do not depend on
 // scheduling.
-template <typename T, int KW>
+template <typename T, int KW, int EB>
 __device__ __forceinline__ void rform_wave(const DevPW *__restrict__ tab, const RTask *__restrict__ tasks,
                                            const RQueues &qs, int *__restrict__ counter, const T *__restrict__ D,
                                            long ldD, double *__restrict__ R, long ldr, long strideR,
-                                           WaveLds<T, KW> &sm) {
+                                           WaveLds<T, KW, EB> &sm) {
   typedef typename Vec4<T>::type V4;
   const int lane = threadIdx.x & 63;
   const int kk = lane >> 4, ii = lane & 15;
   constexpr int VEC = 16 / sizeof(T);            // elements per 16-byte load
   constexpr int PER_ROW = RT / VEC;              // vectors per slice row
   constexpr int NVEC = KW * PER_ROW / 64;        // vectors per lane per slice
-  constexpr int ND = EB * KW / 64;               // scale factors per lane per stage
+  constexpr int ND = (EB * KW + 63) / 64;        // scale factors per lane per stage
   constexpr int ROT = sizeof(T) == 4 ? 16 : 0;   // odd-row rotation of the FP32 slices
-  static_assert(NVEC * 64 == KW * PER_ROW && ND * 64 == EB * KW, "stage shape");
+  static_assert(NVEC * 64 == KW * PER_ROW, "stage shape");
   typedef T TV __attribute__((ext_vector_type(VEC)));
 
   // fragment columns in the slice rows (row ks + kk is rotated when kk is odd)
@@ -204,7 +204,7 @@ __device__ __forceinline__ void rform_wave(const DevPW *__restrict__ tab, const 
       for (int r = 0; r < ND; ++r) {
         const int idx = lane + 64 * r;
         const int e = idx / KW, k = idx % KW;
-        rd[r] = e < me ? D[(size_t)(e0 + e) * ldD + k0 + k] : T(0);
+        rd[r] = (idx < EB * KW && e < me) ? D[(size_t)(e0 + e) * ldD + k0 + k] : T(0);
       }
     };
     auto sstore = [&]() {
@@ -219,7 +219,7 @@ __device__ __forceinline__ void rform_wave(const DevPW *__restrict__ tab, const 
 #pragma unroll
       for (int r = 0; r < ND; ++r) {
         const int idx = lane + 64 * r;
-        sm.d[idx / KW][idx % KW] = rd[r];
+        if (idx < EB * KW) sm.d[idx / KW][idx % KW] = rd[r];
       }
     };
 
@@ -267,23 +267,23 @@ __device__ __forceinline__ void rform_wave(const DevPW *__restrict__ tab, const 
   }
 }
 
-// Four independent waves per workgroup.  The FP32 variant is held to two waves
-// per SIMD (its accumulators are half the size); the FP64 one keeps its 256
-// accumulator registers at one wave per SIMD.
-__global__ __launch_bounds__(256, 2) void k_rform_f32(const DevPW *__restrict__ tab, const RTask *__restrict__ tasks,
+// Four independent waves per workgroup; a task carries 4 energies.  The FP32
+// variant runs three waves per SIMD, the FP64 one (twice the accumulator
+// registers) two.
+__global__ __launch_bounds__(256, 3) void k_rform_f32(const DevPW *__restrict__ tab, const RTask *__restrict__ tasks,
                                                       const RQueues qs, int *__restrict__ counter,
                                                       const float *__restrict__ D, long ldD, double *__restrict__ R,
                                                       long ldr, long strideR) {
-  __shared__ WaveLds<float, KW32> sm[4];
-  rform_wave<float, KW32>(tab, tasks, qs, counter, D, ldD, R, ldr, strideR, sm[threadIdx.x >> 6]);
+  __shared__ WaveLds<float, KW32, EB32> sm[4];
+  rform_wave<float, KW32, EB32>(tab, tasks, qs, counter, D, ldD, R, ldr, strideR, sm[threadIdx.x >> 6]);
 }
 
-__global__ __launch_bounds__(256) void k_rform_f64(const DevPW *__restrict__ tab, const RTask *__restrict__ tasks,
+__global__ __launch_bounds__(256, 2) void k_rform_f64(const DevPW *__restrict__ tab, const RTask *__restrict__ tasks,
                                                    const RQueues qs, int *__restrict__ counter,
                                                    const double *__restrict__ D, long ldD, double *__restrict__ R,
                                                    long ldr, long strideR) {
-  __shared__ WaveLds<double, KW64> sm[4];
-  rform_wave<double, KW64>(tab, tasks, qs, counter, D, ldD, R, ldr, strideR, sm[threadIdx.x >> 6]);
+  __shared__ WaveLds<double, KW64, EB64> sm[4];
+  rform_wave<double, KW64, EB64>(tab, tasks, qs, counter, D, ldD, R, ldr, strideR, sm[threadIdx.x >> 6]);
 }
 
 __global__ void k_reset(int *__restrict__ counter) {

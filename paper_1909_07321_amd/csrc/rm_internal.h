@@ -16,8 +16,13 @@ constexpr int KW64 = 16;
 constexpr int KW32 = 32;
 // Pole-dimension padding of resident amplitudes (a multiple of both).
 constexpr int MALIGN = 64;
-// Energies that share one staged amplitude panel in the R contraction.
-constexpr int EB = 8;
+// Energies per batch: chunks take energies from their partial waves in batches
+// of EB; one R-contraction task covers EB32 (split mode) or EB64 (FP64) energies
+// of one wave with one staged amplitude slice.
+constexpr int EB = 4;
+constexpr int EB32 = 4;
+constexpr int EB64 = 4;
+constexpr int EBMIN = EB64 < EB32 ? EB64 : EB32;
 // Panel width of the blocked LU (one register-resident panel) and the outer
 // block: two panels are factored, then the trailing matrix is updated once
 // with a rank-NBU product.
@@ -63,7 +68,7 @@ struct Lay {
   long sOm = 0;                 // Omega: ntmax * ntmax per energy
 };
 
-// One task of the R contraction: energies [e0, e0 + m) (m <= EB, one partial
+// One task of the R contraction: energies [e0, e0 + m) (m <= EB32 or EB64, one partial
 // wave, table slot `slot`) times one lower-triangle RT x RT tile.
 struct RTask {
   int slot, e0, m, tile;

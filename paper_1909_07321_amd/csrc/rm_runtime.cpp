@@ -312,7 +312,8 @@ rm_status upload_plan(rm_ctx *ctx, Slot &sl, Plan &P, const std::vector<Seg> &se
   for (const Part &pt : P.parts)
     for (int i = 0; i < pt.m; ++i) h.pwi[pt.e0 + i] = pt.slot;
   for (size_t i = 0; i < P.slots.size(); ++i) h.tab[i] = *P.slots[i];
-  // R tasks: energy batches of <= EB energies of one partial wave times its
+  const int eb = o.prec == RM_FP32_SPLIT ? EB32 : EB64;
+  // R tasks: energy batches of <= eb energies of one partial wave times its
   // tiles.  All batches of one (part, tile) form a unit; units go, longest
   // first, to the XCD queue with the least work so far, and each queue lists
   // its units in that order.
@@ -325,7 +326,7 @@ rm_status upload_plan(rm_ctx *ctx, Slot &sl, Plan &P, const std::vector<Seg> &se
     const Part &pt = P.parts[pi];
     const DevPW *p = P.slots[pt.slot];
     const int tl = (p->n + RT - 1) / RT;
-    const double c = (double)p->Mpad * ((pt.m + EB - 1) / EB);
+    const double c = (double)p->Mpad * ((pt.m + eb - 1) / eb);
     for (int t = 0; t < tl * (tl + 1) / 2; ++t) units.push_back(Unit{(int)pi, t, c});
   }
   std::stable_sort(units.begin(), units.end(), [](const Unit &a, const Unit &b) { return a.cost > b.cost; });
@@ -341,7 +342,7 @@ rm_status upload_plan(rm_ctx *ctx, Slot &sl, Plan &P, const std::vector<Seg> &se
     P.q.start[q] = nt;
     for (int u : qu[q]) {
       const Part &pt = P.parts[units[u].part];
-      for (int b = 0; b < pt.m; b += EB) h.tasks[nt++] = RTask{pt.slot, pt.e0 + b, std::min(EB, pt.m - b), units[u].tile};
+      for (int b = 0; b < pt.m; b += eb) h.tasks[nt++] = RTask{pt.slot, pt.e0 + b, std::min(eb, pt.m - b), units[u].tile};
     }
   }
   P.q.start[NQ] = nt;
@@ -499,7 +500,7 @@ int plan_tasks(const Plan &P) {
   int nt = 0;
   for (const Part &pt : P.parts) {
     const int tl = (P.slots[pt.slot]->n + RT - 1) / RT;
-    nt += (pt.m + EB - 1) / EB * (tl * (tl + 1) / 2);
+    nt += (pt.m + EBMIN - 1) / EBMIN * (tl * (tl + 1) / 2);
   }
   return nt;
 }

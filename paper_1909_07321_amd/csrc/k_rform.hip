@@ -229,18 +229,36 @@ __device__ __forceinline__ void rform_wave(const DevPW *__restrict__ tab, const 
     for (int st = 0; st < nstage; ++st) {
       sstore();
       if (st + 1 < nstage) gload((st + 1) * KW);
+      // fragments of step ks + 4 are read from LDS while step ks is multiplied
+      T a0 = sm.a[kk][c0], a1 = sm.a[kk][c1], b0 = pB[kk][c0], b1 = pB[kk][c1], d[EB];
+#pragma unroll
+      for (int e = 0; e < EB; ++e) d[e] = sm.d[e][kk];
 #pragma unroll
       for (int ks = 0; ks < KW; ks += 4) {
-        const T a0 = sm.a[ks + kk][c0], a1 = sm.a[ks + kk][c1];
-        const T b0 = pB[ks + kk][c0], b1 = pB[ks + kk][c1];
+        T na0 = a0, na1 = a1, nb0 = b0, nb1 = b1, nd[EB];
+        if (ks + 4 < KW) {
+          na0 = sm.a[ks + 4 + kk][c0];
+          na1 = sm.a[ks + 4 + kk][c1];
+          nb0 = pB[ks + 4 + kk][c0];
+          nb1 = pB[ks + 4 + kk][c1];
+#pragma unroll
+          for (int e = 0; e < EB; ++e) nd[e] = sm.d[e][ks + 4 + kk];
+        }
 #pragma unroll
         for (int e = 0; e < EB; ++e) {
-          const T d = sm.d[e][ks + kk];
-          const T x0 = a0 * d, x1 = a1 * d;
+          const T x0 = a0 * d[e], x1 = a1 * d[e];
           acc[e][0] = mfma16(x0, b0, acc[e][0]);
           acc[e][1] = mfma16(x0, b1, acc[e][1]);
           acc[e][2] = mfma16(x1, b0, acc[e][2]);
           acc[e][3] = mfma16(x1, b1, acc[e][3]);
+        }
+        if (ks + 4 < KW) {
+          a0 = na0;
+          a1 = na1;
+          b0 = nb0;
+          b1 = nb1;
+#pragma unroll
+          for (int e = 0; e < EB; ++e) d[e] = nd[e];
         }
       }
     }

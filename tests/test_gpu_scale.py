@@ -133,3 +133,32 @@ def test_deterministic_and_batch_independent(ctx):
             one = ctx.run(pid, Eb[e:e + 1], prec=prec)
             assert np.array_equal(one[0][0], full[0][e]) and np.array_equal(one[1][0], full[1][e])
     ctx.pw_release(pid)
+
+
+def test_widest_panels_vs_oracle(ctx):
+    """1700 channels: the first LU panels are taller than the register-resident
+    panel holds (3 x 512 rows), so they take the global-memory panel; checked
+    against the oracle at two energies (one with most channels closed, one with
+    most open), alone and batched with a small wave."""
+    from paper_1909_07321_amd import rm
+    E = np.array([1.37, 6.81])
+    pw = synth.make_partial_wave(synth.config_seed(4) + 7, 1700, 10, z=5.0, a=12.0, thr_range=(0.0, 8.0),
+                                 pole_range=(-2.0, 60.0), avoid_energies=E, name="wide")
+    small = synth.make_partial_wave(synth.config_seed(4) + 8, 90, 30, z=5.0, a=12.0, thr_range=(0.0, 8.0),
+                                    pole_range=(-2.0, 60.0), avoid_energies=E, name="wide-small")
+    pid, sid = ctx.pw_upload(pw), ctx.pw_upload(small)
+    om, K, st = ctx.run(pid, E)
+    res = oracle.Oracle(pw, nthreads=16).run(E)
+    assert (st == 0).all() and (res["status"] == 0).all()
+    no = oracle.open_count(pw, E)
+    for e in range(E.size):
+        Ko = res["K"][e, :no[e], :no[e]]
+        errK = np.abs(K[e, :no[e], :no[e]] - Ko).max() / max(1, np.abs(Ko).max())
+        errO = np.abs(om[e] - res["omega"][e]).max() / np.abs(res["omega"][e]).max()
+        g = 1e-10 if res["cond"][e] <= 1e4 else max(1e-10, 1e-15 * res["cond"][e])
+        _say(f"n=1700 E={E[e]} no={no[e]} cond={res['cond'][e]:.1e} K err {errK:.2e} Omega err {errO:.2e}")
+        assert errK <= g and errO <= g
+    outs = ctx.run_batch([(sid, E), (pid, E)], prec=rm.FP64, want_K=True)
+    assert np.array_equal(outs[1][0], om) and np.array_equal(outs[1][1], K)
+    ctx.pw_release(pid)
+    ctx.pw_release(sid)

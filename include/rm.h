@@ -201,6 +201,46 @@ rm_status rm_run_batch(rm_ctx *ctx, const rm_batch_item *items, int32_t nitems, 
 rm_status rm_run_sum(rm_ctx *ctx, const int32_t *pw_ids, int32_t npw, const double *E, int32_t ne, int32_t order,
                      const rm_opts *opts, double *omega, int32_t *status);
 
+/* ------------------------------------------------------------ tile autotuner */
+/* Tile shapes of the R contraction, eq. (rmatrix) (section "Overview"), formed
+   in output tiles padded to multiples of 16 as in section "CUDA optimisations
+   for PSTGF" (matrices padded with zeros to 32/64 boundaries).  A shape is a
+   square output tile of `tile` channels per side computed for up to `energies`
+   energies at once; each precision has rm_tile_count(prec) shapes (shape 0 is
+   the default).  Channel counts fall into RM_NBUCKET size buckets
+   (rm_tile_bucket), and a context uses one shape per (precision, bucket).
+   Every shape sums each R element over the poles in the same order, so the
+   choice changes the speed and never the results. */
+#define RM_NBUCKET 4
+/* Bucket of a channel count (0 .. RM_NBUCKET-1). */
+int32_t rm_tile_bucket(int32_t nchan);
+/* Number of shapes of precision prec (RM_FP64 or RM_FP32_SPLIT); 0 if prec is invalid. */
+int32_t rm_tile_count(int32_t prec);
+/* Tile side (channels) and energies per task of a shape.  RM_E_ARG for an
+   invalid prec or shape. */
+rm_status rm_tile_shape(int32_t prec, int32_t shape, int32_t *tile, int32_t *energies);
+/* The shape the context uses for (prec, bucket), and setting it (takes effect
+   for calls planned afterwards). */
+rm_status rm_get_tile(rm_ctx *ctx, int32_t prec, int32_t bucket, int32_t *shape);
+rm_status rm_set_tile(rm_ctx *ctx, int32_t prec, int32_t bucket, int32_t shape);
+/* Autotuner: times the R contraction (the d(E) vector and the persistent
+   contraction launch) of every shape of prec on each resident partial wave
+   pw_ids[0 .. npw) for the ne host energies E (reps timed runs after one
+   warmup; the minimum counts), sums the times of the waves of each bucket, and
+   makes the fastest shape the context's choice for every bucket that holds one
+   of the waves.  ms (NULL or [npw][rm_tile_count(prec)]) receives the times.
+   If cache_path is not NULL the choices are also written there (JSON, one
+   entry per tuned bucket, with the device architecture and compute-unit count)
+   for rm_tune_load.  Synchronous; RM_E_NOTFOUND for an unknown wave, RM_E_ARG
+   for bad sizes, RM_E_DEVICE if the file cannot be written. */
+rm_status rm_tune(rm_ctx *ctx, int32_t prec, const int32_t *pw_ids, int32_t npw, const double *E, int32_t ne,
+                  int32_t reps, const char *cache_path, double *ms);
+/* Loads the choices of a cache written by rm_tune.  RM_E_NOTFOUND if the file
+   cannot be read; RM_E_ARG (nothing changed) if it is malformed, names a shape
+   or bucket out of range, or was made on a device of another architecture or
+   compute-unit count. */
+rm_status rm_tune_load(rm_ctx *ctx, const char *cache_path);
+
 /* ------------------------------------------------------------------ serving */
 typedef struct {
   int32_t pw_id;

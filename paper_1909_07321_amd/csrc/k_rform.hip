@@ -81,17 +81,20 @@ void launch_dvec(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, 
 
 // ---------------------------------------------------------------------------
 // Contraction kernel.  Every wave works on its own: a task is one lower-
-// triangle 32 x 32 tile (bi, bj), bi >= bj, of one partial wave for up to EB
-// energies of that wave.  Per stage of KW poles the wave copies the KW x 32
-// slices of W for the tile's rows i and columns j (one slice on a diagonal
-// tile) into its own LDS region, then forms its 2 x 2 MFMA 16x16x4 blocks per
-// energy, scaling the A fragment by d_k(E) in registers.  No workgroup barrier
-// is involved: the next stage's slices are loaded into registers while the
-// current one is multiplied, and a wave's own LDS accesses are ordered.  MFMA
-// operand layout (16x16x4): lane l holds A[l%16][l/16] and B[l/16][l%16]; the
-// result rows are given by MfmaRow.  The FP32 slices rotate odd rows by 16
+// triangle RTW x RTW tile (bi, bj), bi >= bj, RTW = 16 TM, of one partial wave
+// for up to EB energies of that wave.  Per stage of KW poles the wave copies
+// the KW x RTW slices of W for the tile's rows i and columns j (one slice on a
+// diagonal tile) into its own LDS region, then forms its TM x TM MFMA 16x16x4
+// blocks per energy, scaling the A fragment by d_k(E) in registers; on a
+// diagonal tile the blocks above the diagonal are skipped.  No workgroup
+// barrier is involved: the next stage's slices are loaded into registers while
+// the current one is multiplied, and a wave's own LDS accesses are ordered.
+// MFMA operand layout (16x16x4): lane l holds A[l%16][l/16] and B[l/16][l%16];
+// the result rows are given by MfmaRow.  The FP32 slices rotate odd rows by 16
 // elements so that the two k-rows read by one 32-lane half fall on distinct
-// banks.
+// banks.  The tile shapes (TM, EB) are the choices of the tile autotuner; every
+// shape sums each R element over k in the same order, so they give identical
+// results.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -127,34 +130,156 @@ template <> __device__ __forceinline__ const double *amplitudes<double>(const De
 template <> __device__ __forceinline__ const float *amplitudes<float>(const DevPW &p) { return p.W32; }
 
 // One wave's LDS region.
-template <typename T, int KW, int EB> struct WaveLds {
-  T a[KW][RT];
-  T b[KW][RT];
+template <typename T, int KW, int EB, int RTW> struct WaveLds {
+  T a[KW][RTW];
+  T b[KW][RTW];
   T d[EB][KW];
 };
 
-// Persistent: every wave takes tasks from the queue of its XCD until it is
-// empty, then from the other queues in turn.  Each energy's sums run over k in
-// ascending order whatever wave takes the task, so results do not depend on
-// scheduling.
-template <typename T, int KW, int EB>
-__device__ __forceinline__ void rform_wave(const DevPW *__restrict__ tab, const RTask *__restrict__ tasks,
-                                           const RQueues &qs, int *__restrict__ counter, const T *__restrict__ D,
-                                           long ldD, double *__restrict__ R, long ldr, long strideR,
-                                           WaveLds<T, KW, EB> &sm) {
+// One task: the tile with rows [i0, i0 + RTW) and columns [j0, j0 + RTW) for
+// energies [e0, e0 + me).  DIAG: i0 == j0.
+template <typename T, int KW, int EB, int TM, bool DIAG>
+__device__ __forceinline__ void rform_task(const T *__restrict__ W, int ldw, int Mpad, int n, int i0, int j0,
+                                           const T *__restrict__ D, long ldD, int e0, int me,
+                                           double *__restrict__ R, long ldr, long strideR,
+                                           WaveLds<T, KW, EB, 16 * TM> &sm) {
   typedef typename Vec4<T>::type V4;
+  constexpr int RTW = 16 * TM;
   const int lane = threadIdx.x & 63;
   const int kk = lane >> 4, ii = lane & 15;
   constexpr int VEC = 16 / sizeof(T);            // elements per 16-byte load
-  constexpr int PER_ROW = RT / VEC;              // vectors per slice row
+  constexpr int PER_ROW = RTW / VEC;             // vectors per slice row
   constexpr int NVEC = KW * PER_ROW / 64;        // vectors per lane per slice
   constexpr int ND = (EB * KW + 63) / 64;        // scale factors per lane per stage
   constexpr int ROT = sizeof(T) == 4 ? 16 : 0;   // odd-row rotation of the FP32 slices
   static_assert(NVEC * 64 == KW * PER_ROW, "stage shape");
   typedef T TV __attribute__((ext_vector_type(VEC)));
 
-  // fragment columns in the slice rows (row ks + kk is rotated when kk is odd)
-  const int c0 = (ii + ROT * (kk & 1)) & (RT - 1), c1 = (16 + ii + ROT * (kk & 1)) & (RT - 1);
+  // fragment column of 16-block m in the slice rows (row ks + kk is rotated when kk is odd)
+  int col[TM];
+#pragma unroll
+  for (int m = 0; m < TM; ++m) col[m] = (16 * m + ii + ROT * (kk & 1)) & (RTW - 1);
+
+  V4 acc[EB][TM * TM];
+#pragma unroll
+  for (int e = 0; e < EB; ++e)
+#pragma unroll
+    for (int m = 0; m < TM * TM; ++m) acc[e][m] = V4{0, 0, 0, 0};
+
+  TV ra[NVEC], rb[NVEC];
+  T rd[ND];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < NVEC; ++r) {
+      const int idx = lane + 64 * r;
+      const int row = idx / PER_ROW, c = (idx % PER_ROW) * VEC;
+      ra[r] = *reinterpret_cast<const TV *>(W + (size_t)(k0 + row) * ldw + i0 + c);
+      if (!DIAG) rb[r] = *reinterpret_cast<const TV *>(W + (size_t)(k0 + row) * ldw + j0 + c);
+    }
+#pragma unroll
+    for (int r = 0; r < ND; ++r) {
+      const int idx = lane + 64 * r;
+      const int e = idx / KW, k = idx % KW;
+      rd[r] = (idx < EB * KW && e < me) ? D[(size_t)(e0 + e) * ldD + k0 + k] : T(0);
+    }
+  };
+  auto sstore = [&]() {
+#pragma unroll
+    for (int r = 0; r < NVEC; ++r) {
+      const int idx = lane + 64 * r;
+      const int row = idx / PER_ROW, c = (idx % PER_ROW) * VEC;
+      const int scol = (c + ROT * (row & 1)) & (RTW - 1);
+      *reinterpret_cast<TV *>(&sm.a[row][scol]) = ra[r];
+      if (!DIAG) *reinterpret_cast<TV *>(&sm.b[row][scol]) = rb[r];
+    }
+#pragma unroll
+    for (int r = 0; r < ND; ++r) {
+      const int idx = lane + 64 * r;
+      if (idx < EB * KW) sm.d[idx / KW][idx % KW] = rd[r];
+    }
+  };
+
+  const int nstage = Mpad / KW;
+  gload(0);
+  for (int st = 0; st < nstage; ++st) {
+    sstore();
+    if (st + 1 < nstage) gload((st + 1) * KW);
+    // fragments of step ks + 4 are read from LDS while step ks is multiplied
+    T a[TM], b[TM], d[EB];
+#pragma unroll
+    for (int m = 0; m < TM; ++m) {
+      a[m] = sm.a[kk][col[m]];
+      b[m] = DIAG ? a[m] : sm.b[kk][col[m]];
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) d[e] = sm.d[e][kk];
+#pragma unroll
+    for (int ks = 0; ks < KW; ks += 4) {
+      T na[TM], nb[TM], nd[EB];
+      if (ks + 4 < KW) {
+#pragma unroll
+        for (int m = 0; m < TM; ++m) {
+          na[m] = sm.a[ks + 4 + kk][col[m]];
+          nb[m] = DIAG ? na[m] : sm.b[ks + 4 + kk][col[m]];
+        }
+#pragma unroll
+        for (int e = 0; e < EB; ++e) nd[e] = sm.d[e][ks + 4 + kk];
+      }
+#pragma unroll
+      for (int e = 0; e < EB; ++e)
+#pragma unroll
+        for (int mr = 0; mr < TM; ++mr) {
+          const T x = a[mr] * d[e];
+#pragma unroll
+          for (int mc = 0; mc < TM; ++mc)
+            if (!DIAG || mc <= mr) acc[e][mr * TM + mc] = mfma16(x, b[mc], acc[e][mr * TM + mc]);
+        }
+      if (ks + 4 < KW) {
+#pragma unroll
+        for (int m = 0; m < TM; ++m) {
+          a[m] = na[m];
+          b[m] = nb[m];
+        }
+#pragma unroll
+        for (int e = 0; e < EB; ++e) d[e] = nd[e];
+      }
+    }
+  }
+
+  // epilogue: lower-triangle elements are written to (i, j) and mirrored to (j, i)
+#pragma unroll
+  for (int e = 0; e < EB; ++e) {
+    if (e >= me) break;
+    double *Re = R + (size_t)(e0 + e) * strideR;
+#pragma unroll
+    for (int mr = 0; mr < TM; ++mr)
+#pragma unroll
+      for (int mc = 0; mc < TM; ++mc) {
+        if (DIAG && mc > mr) continue;
+        const int j = j0 + 16 * mc + ii;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = i0 + 16 * mr + MfmaRow<T>::row(kk, v);
+          if (i < n && j < n && i >= j) {
+            const double val = (double)acc[e][mr * TM + mc][v];
+            Re[(size_t)i * ldr + j] = val;
+            Re[(size_t)j * ldr + i] = val;
+          }
+        }
+      }
+  }
+}
+
+// Persistent: every wave takes tasks from the queue of its XCD until it is
+// empty, then from the other queues in turn.  Each energy's sums run over k in
+// ascending order whatever wave takes the task, so results do not depend on
+// scheduling.
+template <typename T, int KW, int EB, int TM>
+__device__ __forceinline__ void rform_wave(const DevPW *__restrict__ tab, const RTask *__restrict__ tasks,
+                                           const RQueues &qs, int *__restrict__ counter, const T *__restrict__ D,
+                                           long ldD, double *__restrict__ R, long ldr, long strideR,
+                                           WaveLds<T, KW, EB, 16 * TM> &sm) {
+  const int lane = threadIdx.x & 63;
   // start with the queue of the XCD this wave runs on (hardware register
   // XCC_ID, bits [3:0])
   int q = __builtin_amdgcn_s_getreg((3 << 11) | 20) & (NQ - 1), tried = 0;
@@ -177,158 +302,72 @@ __device__ __forceinline__ void rform_wave(const DevPW *__restrict__ tab, const 
     const RTask tk = tasks[task];
     const DevPW &p = tab[tk.slot];
     const T *__restrict__ W = amplitudes<T>(p);
-    const int ldw = p.npad, Mpad = p.Mpad, n = p.n;
-    const int e0 = tk.e0, me = tk.m;
     int bi, bj;
     tri_tile(tk.tile, bi, bj);
-    const bool diag = bi == bj;
-    const int i0 = bi * RT, j0 = bj * RT;
-
-    V4 acc[EB][4];
-#pragma unroll
-    for (int e = 0; e < EB; ++e)
-#pragma unroll
-      for (int m = 0; m < 4; ++m) acc[e][m] = V4{0, 0, 0, 0};
-
-    TV ra[NVEC], rb[NVEC];
-    T rd[ND];
-    auto gload = [&](int k0) {
-#pragma unroll
-      for (int r = 0; r < NVEC; ++r) {
-        const int idx = lane + 64 * r;
-        const int row = idx / PER_ROW, col = (idx % PER_ROW) * VEC;
-        ra[r] = *reinterpret_cast<const TV *>(W + (size_t)(k0 + row) * ldw + i0 + col);
-        if (!diag) rb[r] = *reinterpret_cast<const TV *>(W + (size_t)(k0 + row) * ldw + j0 + col);
-      }
-#pragma unroll
-      for (int r = 0; r < ND; ++r) {
-        const int idx = lane + 64 * r;
-        const int e = idx / KW, k = idx % KW;
-        rd[r] = (idx < EB * KW && e < me) ? D[(size_t)(e0 + e) * ldD + k0 + k] : T(0);
-      }
-    };
-    auto sstore = [&]() {
-#pragma unroll
-      for (int r = 0; r < NVEC; ++r) {
-        const int idx = lane + 64 * r;
-        const int row = idx / PER_ROW, col = (idx % PER_ROW) * VEC;
-        const int scol = (col + ROT * (row & 1)) & (RT - 1);
-        *reinterpret_cast<TV *>(&sm.a[row][scol]) = ra[r];
-        if (!diag) *reinterpret_cast<TV *>(&sm.b[row][scol]) = rb[r];
-      }
-#pragma unroll
-      for (int r = 0; r < ND; ++r) {
-        const int idx = lane + 64 * r;
-        if (idx < EB * KW) sm.d[idx / KW][idx % KW] = rd[r];
-      }
-    };
-
-    const int nstage = Mpad / KW;
-    const T(*pB)[RT] = diag ? sm.a : sm.b;
-    gload(0);
-    for (int st = 0; st < nstage; ++st) {
-      sstore();
-      if (st + 1 < nstage) gload((st + 1) * KW);
-      // fragments of step ks + 4 are read from LDS while step ks is multiplied
-      T a0 = sm.a[kk][c0], a1 = sm.a[kk][c1], b0 = pB[kk][c0], b1 = pB[kk][c1], d[EB];
-#pragma unroll
-      for (int e = 0; e < EB; ++e) d[e] = sm.d[e][kk];
-#pragma unroll
-      for (int ks = 0; ks < KW; ks += 4) {
-        T na0 = a0, na1 = a1, nb0 = b0, nb1 = b1, nd[EB];
-        if (ks + 4 < KW) {
-          na0 = sm.a[ks + 4 + kk][c0];
-          na1 = sm.a[ks + 4 + kk][c1];
-          nb0 = pB[ks + 4 + kk][c0];
-          nb1 = pB[ks + 4 + kk][c1];
-#pragma unroll
-          for (int e = 0; e < EB; ++e) nd[e] = sm.d[e][ks + 4 + kk];
-        }
-#pragma unroll
-        for (int e = 0; e < EB; ++e) {
-          const T x0 = a0 * d[e], x1 = a1 * d[e];
-          acc[e][0] = mfma16(x0, b0, acc[e][0]);
-          acc[e][1] = mfma16(x0, b1, acc[e][1]);
-          acc[e][2] = mfma16(x1, b0, acc[e][2]);
-          acc[e][3] = mfma16(x1, b1, acc[e][3]);
-        }
-        if (ks + 4 < KW) {
-          a0 = na0;
-          a1 = na1;
-          b0 = nb0;
-          b1 = nb1;
-#pragma unroll
-          for (int e = 0; e < EB; ++e) d[e] = nd[e];
-        }
-      }
-    }
-
-    // epilogue: lower-triangle elements are written to (i, j) and mirrored to (j, i)
-#pragma unroll
-    for (int e = 0; e < EB; ++e) {
-      if (e >= me) break;
-      double *Re = R + (size_t)(e0 + e) * strideR;
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const int j = j0 + (m & 1) * 16 + ii;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = i0 + (m >> 1) * 16 + MfmaRow<T>::row(kk, v);
-          if (i < n && j < n && i >= j) {
-            const double val = (double)acc[e][m][v];
-            Re[(size_t)i * ldr + j] = val;
-            Re[(size_t)j * ldr + i] = val;
-          }
-        }
-      }
-    }
+    if (bi == bj)
+      rform_task<T, KW, EB, TM, true>(W, p.npad, p.Mpad, p.n, bi * 16 * TM, bj * 16 * TM, D, ldD, tk.e0, tk.m, R,
+                                      ldr, strideR, sm);
+    else
+      rform_task<T, KW, EB, TM, false>(W, p.npad, p.Mpad, p.n, bi * 16 * TM, bj * 16 * TM, D, ldD, tk.e0, tk.m, R,
+                                       ldr, strideR, sm);
   }
 }
 
-// Four independent waves per workgroup; a task carries 4 energies.  The FP32
-// variant runs three waves per SIMD, the FP64 one (twice the accumulator
-// registers) two.
-__global__ __launch_bounds__(256, 3) void k_rform_f32(const DevPW *__restrict__ tab, const RTask *__restrict__ tasks,
-                                                      const RQueues qs, int *__restrict__ counter,
-                                                      const float *__restrict__ D, long ldD, double *__restrict__ R,
-                                                      long ldr, long strideR) {
-  __shared__ WaveLds<float, KW32, EB32> sm[4];
-  rform_wave<float, KW32, EB32>(tab, tasks, qs, counter, D, ldD, R, ldr, strideR, sm[threadIdx.x >> 6]);
+// Four independent waves per workgroup; OCC workgroups per CU (launch bound).
+template <int TM, int EB, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_rform_f32(const DevPW *__restrict__ tab, const RTask *__restrict__ tasks,
+                                                        const RQueues qs, int *__restrict__ counter,
+                                                        const float *__restrict__ D, long ldD,
+                                                        double *__restrict__ R, long ldr, long strideR) {
+  __shared__ WaveLds<float, KW32, EB, 16 * TM> sm[4];
+  rform_wave<float, KW32, EB, TM>(tab, tasks, qs, counter, D, ldD, R, ldr, strideR, sm[threadIdx.x >> 6]);
 }
 
-__global__ __launch_bounds__(256, 2) void k_rform_f64(const DevPW *__restrict__ tab, const RTask *__restrict__ tasks,
-                                                   const RQueues qs, int *__restrict__ counter,
-                                                   const double *__restrict__ D, long ldD, double *__restrict__ R,
-                                                   long ldr, long strideR) {
-  __shared__ WaveLds<double, KW64, EB64> sm[4];
-  rform_wave<double, KW64, EB64>(tab, tasks, qs, counter, D, ldD, R, ldr, strideR, sm[threadIdx.x >> 6]);
+template <int TM, int EB, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_rform_f64(const DevPW *__restrict__ tab, const RTask *__restrict__ tasks,
+                                                        const RQueues qs, int *__restrict__ counter,
+                                                        const double *__restrict__ D, long ldD,
+                                                        double *__restrict__ R, long ldr, long strideR) {
+  __shared__ WaveLds<double, KW64, EB, 16 * TM> sm[4];
+  rform_wave<double, KW64, EB, TM>(tab, tasks, qs, counter, D, ldD, R, ldr, strideR, sm[threadIdx.x >> 6]);
 }
 
 __global__ void k_reset(int *__restrict__ counter) {
   if (threadIdx.x < NQ) counter[threadIdx.x] = 0;
 }
 
-void launch_rform(hipStream_t s, const Lay &L, int split, const DevPW *tab, const RTask *tasks, const RQueues &qs,
-                  int *counter, int nworkgroups, const double *D64, const float *D32, double *R) {
-  const int ntasks = qs.start[NQ];
+namespace {
+typedef void (*RformF32)(const DevPW *, const RTask *, const RQueues, int *, const float *, long, double *, long,
+                         long);
+typedef void (*RformF64)(const DevPW *, const RTask *, const RQueues, int *, const double *, long, double *, long,
+                         long);
+// Kernel of each tile shape; the order is that of kRTile32 / kRTile64.
+const RformF32 kF32[NRT32] = {k_rform_f32<2, 4, 3>, k_rform_f32<4, 2, 2>, k_rform_f32<1, 8, 3>};
+const RformF64 kF64[NRT64] = {k_rform_f64<2, 4, 2>, k_rform_f64<1, 8, 2>};
+}  // namespace
+
+void launch_rform(hipStream_t s, const Lay &L, int split, int shape, const DevPW *tab, const RTask *tasks,
+                  const RQueues &qs, int *counter, int nworkgroups, const double *D64, const float *D32,
+                  double *R) {
+  const int ntasks = qs.start[NQ] - qs.start[0];
   if (ntasks <= 0) return;
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, counter);
   // persistent grid: as many workgroups as can be resident at once
-  static int occ[2] = {0, 0};
-  int &oc = occ[split ? 1 : 0];
+  static int occ[2][NRT32 > NRT64 ? NRT32 : NRT64] = {};
+  int &oc = occ[split ? 1 : 0][shape];
   if (!oc) {
     int b = 0;
     if (split)
-      (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_rform_f32, 256, 0);
+      (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kF32[shape], 256, 0);
     else
-      (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_rform_f64, 256, 0);
+      (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kF64[shape], 256, 0);
     oc = std::max(1, b);
   }
   const dim3 grid(std::max(1, std::min(ntasks, oc * nworkgroups)));
   if (split)
-    hipLaunchKernelGGL(k_rform_f32, grid, dim3(256), 0, s, tab, tasks, qs, counter, D32, L.ldD, R, L.ldaug, L.sA);
+    hipLaunchKernelGGL(kF32[shape], grid, dim3(256), 0, s, tab, tasks, qs, counter, D32, L.ldD, R, L.ldaug, L.sA);
   else
-    hipLaunchKernelGGL(k_rform_f64, grid, dim3(256), 0, s, tab, tasks, qs, counter, D64, L.ldD, R, L.ldaug, L.sA);
+    hipLaunchKernelGGL(kF64[shape], grid, dim3(256), 0, s, tab, tasks, qs, counter, D64, L.ldD, R, L.ldaug, L.sA);
 }
 
 // ---------------------------------------------------------------------------

@@ -9,20 +9,34 @@ namespace rm {
 
 // Output tile of the R contraction and of the batched GEMMs (rows x cols).
 constexpr int TILE = 64;
-// Output tile of one wave in the R contraction, and the poles one wave stages per
-// step (FP64 and FP32): the same 4 KB of amplitudes per slice.
-constexpr int RT = 32;
+// Poles one wave stages per step of the R contraction (FP64 and FP32): the same
+// bytes per slice row.
 constexpr int KW64 = 16;
 constexpr int KW32 = 32;
 // Pole-dimension padding of resident amplitudes (a multiple of both).
 constexpr int MALIGN = 64;
 // Energies per batch: chunks take energies from their partial waves in batches
-// of EB; one R-contraction task covers EB32 (split mode) or EB64 (FP64) energies
-// of one wave with one staged amplitude slice.
+// of EB.
 constexpr int EB = 4;
-constexpr int EB32 = 4;
-constexpr int EB64 = 4;
-constexpr int EBMIN = EB64 < EB32 ? EB64 : EB32;
+// Tile shapes of the R contraction: one wave computes a 16 tm x 16 tm lower-
+// triangle tile for up to eb energies of one partial wave per task.  Entry 0 is
+// the default; the tile autotuner picks one entry per (precision, size bucket).
+struct RTile {
+  int tm, eb;
+};
+constexpr int NRT32 = 3, NRT64 = 2, NRTMAX = 3;
+constexpr RTile kRTile32[NRT32] = {{2, 4}, {4, 2}, {1, 8}};
+constexpr RTile kRTile64[NRT64] = {{2, 4}, {1, 8}};
+inline RTile rtile(int split, int shape) { return split ? kRTile32[shape] : kRTile64[shape]; }
+inline int nrtile(int split) { return split ? NRT32 : NRT64; }
+// Size buckets of the autotuner: bucket b holds channel counts up to kBucketMaxN[b].
+constexpr int NBUCKET = 4;
+constexpr int kBucketMaxN[NBUCKET] = {64, 192, 512, 1 << 30};
+inline int size_bucket(int n) {
+  int b = 0;
+  while (b + 1 < NBUCKET && n > kBucketMaxN[b]) ++b;
+  return b;
+}
 // Panel width of the blocked LU (one register-resident panel) and the outer
 // block: two panels are factored, then the trailing matrix is updated once
 // with a rank-NBU product.
@@ -68,8 +82,8 @@ struct Lay {
   long sOm = 0;                 // Omega: ntmax * ntmax per energy
 };
 
-// One task of the R contraction: energies [e0, e0 + m) (m <= EB32 or EB64, one partial
-// wave, table slot `slot`) times one lower-triangle RT x RT tile.
+// One task of the R contraction: energies [e0, e0 + m) (m <= the tile shape's eb,
+// one partial wave, table slot `slot`) times one lower-triangle tile of the shape.
 struct RTask {
   int slot, e0, m, tile;
 };
@@ -91,7 +105,7 @@ struct Work {
   int *pwi = nullptr;        // [cap_e] table slot of each energy
   DevPW *tab = nullptr;      // [cap_tab]
   RTask *tasks = nullptr;    // [cap_tasks]
-  int *counter = nullptr;    // [NQ] queue heads of the persistent R contraction
+  int *counter = nullptr;    // [NRTMAX][NQ] queue heads of the persistent R contraction, per tile shape
   double *D64 = nullptr;     // [cap_e][ldD]
   float *D32 = nullptr;      // [cap_e][ldD]
   int *win = nullptr;        // [cap_e][2] near-pole window [lo, hi)
@@ -118,10 +132,11 @@ struct Work {
 // ---- kernel launchers (all asynchronous on `s`).  tab/pwi are device pointers.
 void launch_dvec(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const double *E, int split,
                  double delta, double *D64, float *D32, int *win, int *status);
-// Persistent R contraction over `tasks`; ncu = compute units of the device (the
-// grid is the number of workgroups that fit at once).
-void launch_rform(hipStream_t s, const Lay &L, int split, const DevPW *tab, const RTask *tasks, const RQueues &q,
-                  int *counter, int ncu, const double *D64, const float *D32, double *R);
+// Persistent R contraction over the tasks of q (tile shape `shape` of the
+// precision); ncu = compute units of the device (the grid is the number of
+// workgroups that fit at once); counter: NQ ints of this shape.
+void launch_rform(hipStream_t s, const Lay &L, int split, int shape, const DevPW *tab, const RTask *tasks,
+                  const RQueues &q, int *counter, int ncu, const double *D64, const float *D32, double *R);
 void launch_nearpole(hipStream_t s, const Lay &L, int maxtiles, const DevPW *tab, const int *pwi, const double *E,
                      const int *win, double *R);
 void launch_nanfill_R(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *status, double *R);

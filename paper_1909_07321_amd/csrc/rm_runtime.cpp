@@ -12,10 +12,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -95,7 +97,9 @@ struct Plan {
   std::vector<const DevPW *> slots;
   Lay L;
   int ntasks = 0, maxtiles = 0;
-  RQueues q{};
+  int split = 0;
+  std::vector<int> pshape;  // R tile shape of each part
+  RQueues q[NRTMAX]{};      // R task queues of each tile shape
 };
 
 }  // namespace
@@ -103,6 +107,7 @@ struct Plan {
 struct rm_ctx {
   int device = 0;
   int ncu = 256;
+  std::string arch;  // device architecture name, for the tile cache
   size_t budget = 0;
   size_t resident = 0;    // bytes of resident partial waves
   size_t work_bytes = 0;  // bytes of all workspaces
@@ -122,6 +127,7 @@ struct rm_ctx {
   int max_queue = 4096;
   std::atomic<int> prof_on{0};
   std::vector<ProfRec> prof;  // guarded by mu
+  int tile[2][NBUCKET] = {};  // R tile shape per (split, size bucket); guarded by mu
   // rm_run / rm_run_batch alternate chunks over two streams; the R
   // contractions are chained across them so that one chunk's K solve overlaps
   // the next chunk's contraction
@@ -189,7 +195,7 @@ rm_status ensure_slot(rm_ctx *ctx, Slot &sl, const Lay &L, int ntab, int ntasks,
       return std::max<size_t>(b, 8);
     };
     const size_t bE = sz((size_t)ce * 8), bpwi = sz((size_t)ce * 4), btab = sz((size_t)ctab * sizeof(DevPW)),
-                 btask = sz((size_t)ctask * sizeof(RTask)), bcnt = sz(64), bD64 = sz((size_t)ce * cm * 8),
+                 btask = sz((size_t)ctask * sizeof(RTask)), bcnt = sz(256), bD64 = sz((size_t)ce * cm * 8),
                  bD32 = sz((size_t)ce * cm * 4), bwin = sz((size_t)ce * 8), bst = sz((size_t)ce * 4),
                  bno = sz((size_t)ce * 4), bidx = sz((size_t)ce * cn * 4), bflag = sz((size_t)ce * cn),
                  bfg = sz((size_t)ce * cn * 32), baug = sz((size_t)ce * cn * 2 * cnp * 8),
@@ -312,40 +318,45 @@ rm_status upload_plan(rm_ctx *ctx, Slot &sl, Plan &P, const std::vector<Seg> &se
   for (const Part &pt : P.parts)
     for (int i = 0; i < pt.m; ++i) h.pwi[pt.e0 + i] = pt.slot;
   for (size_t i = 0; i < P.slots.size(); ++i) h.tab[i] = *P.slots[i];
-  const int eb = o.prec == RM_FP32_SPLIT ? EB32 : EB64;
   // R tasks: energy batches of <= eb energies of one partial wave times its
-  // tiles.  All batches of one (part, tile) form a unit; units go, longest
-  // first, to the XCD queue with the least work so far, and each queue lists
-  // its units in that order.
+  // tiles, per tile shape.  All batches of one (part, tile) form a unit; units
+  // go, longest first, to the XCD queue with the least work so far, and each
+  // queue lists its units in that order.  The shapes' task lists follow each
+  // other in `tasks`.
   struct Unit {
     int part, tile;
     double cost;
   };
-  std::vector<Unit> units;
-  for (size_t pi = 0; pi < P.parts.size(); ++pi) {
-    const Part &pt = P.parts[pi];
-    const DevPW *p = P.slots[pt.slot];
-    const int tl = (p->n + RT - 1) / RT;
-    const double c = (double)p->Mpad * ((pt.m + eb - 1) / eb);
-    for (int t = 0; t < tl * (tl + 1) / 2; ++t) units.push_back(Unit{(int)pi, t, c});
-  }
-  std::stable_sort(units.begin(), units.end(), [](const Unit &a, const Unit &b) { return a.cost > b.cost; });
-  std::vector<std::vector<int>> qu(NQ);
-  double load[NQ] = {0};
-  for (size_t u = 0; u < units.size(); ++u) {
-    const int q = (int)(std::min_element(load, load + NQ) - load);
-    qu[q].push_back((int)u);
-    load[q] += units[u].cost;
-  }
   int nt = 0;
-  for (int q = 0; q < NQ; ++q) {
-    P.q.start[q] = nt;
-    for (int u : qu[q]) {
-      const Part &pt = P.parts[units[u].part];
-      for (int b = 0; b < pt.m; b += eb) h.tasks[nt++] = RTask{pt.slot, pt.e0 + b, std::min(eb, pt.m - b), units[u].tile};
+  for (int sh = 0; sh < NRTMAX; ++sh) {
+    std::vector<Unit> units;
+    const RTile rt = rtile(P.split, std::min(sh, nrtile(P.split) - 1));
+    for (size_t pi = 0; pi < P.parts.size(); ++pi) {
+      if (sh >= nrtile(P.split) || P.pshape[pi] != sh) continue;
+      const Part &pt = P.parts[pi];
+      const DevPW *p = P.slots[pt.slot];
+      const int tl = (p->n + 16 * rt.tm - 1) / (16 * rt.tm);
+      const double c = (double)p->Mpad * ((pt.m + rt.eb - 1) / rt.eb) * rt.tm * rt.tm;
+      for (int t = 0; t < tl * (tl + 1) / 2; ++t) units.push_back(Unit{(int)pi, t, c});
     }
+    std::stable_sort(units.begin(), units.end(), [](const Unit &a, const Unit &b) { return a.cost > b.cost; });
+    std::vector<std::vector<int>> qu(NQ);
+    double load[NQ] = {0};
+    for (size_t u = 0; u < units.size(); ++u) {
+      const int q = (int)(std::min_element(load, load + NQ) - load);
+      qu[q].push_back((int)u);
+      load[q] += units[u].cost;
+    }
+    for (int q = 0; q < NQ; ++q) {
+      P.q[sh].start[q] = nt;
+      for (int u : qu[q]) {
+        const Part &pt = P.parts[units[u].part];
+        for (int b = 0; b < pt.m; b += rt.eb)
+          h.tasks[nt++] = RTask{pt.slot, pt.e0 + b, std::min(rt.eb, pt.m - b), units[u].tile};
+      }
+    }
+    P.q[sh].start[NQ] = nt;
   }
-  P.q.start[NQ] = nt;
   P.ntasks = nt;
   long om = 0, kk = 0;
   for (const Part &pt : P.parts) {
@@ -405,7 +416,8 @@ void stage_R(rm_ctx *ctx, const Plan &P, Work &w, const rm_opts &o, hipStream_t 
   const int split = o.prec == RM_FP32_SPLIT;
   launch_dvec(s, L, w.tab, w.pwi, w.E, split, o.split_delta, w.D64, w.D32, w.win, w.status);
   timed(ctx, 0, L.ne, s, [&] {
-    launch_rform(s, L, split, w.tab, w.tasks, P.q, w.counter, ctx->ncu, w.D64, w.D32, w.aug);
+    for (int sh = 0; sh < nrtile(split); ++sh)
+      launch_rform(s, L, split, sh, w.tab, w.tasks, P.q[sh], w.counter + NQ * sh, ctx->ncu, w.D64, w.D32, w.aug);
   });
   if (split)
     timed(ctx, 1, L.ne, s, [&] { launch_nearpole(s, L, P.maxtiles, w.tab, w.pwi, w.E, w.win, w.aug); });
@@ -496,11 +508,25 @@ void finish_plan(Plan &P, const std::vector<Seg> &segs, int ne) {
   }
 }
 
-int plan_tasks(const Plan &P) {
+// Picks each part's R tile shape (the context's choice for its precision and
+// size bucket, or `force` if it is >= 0) and returns the number of R tasks of
+// the chunk.
+int plan_tasks(rm_ctx *ctx, Plan &P, const rm_opts &o, int force = -1) {
+  P.split = o.prec == RM_FP32_SPLIT;
+  int tile[NBUCKET];
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    std::copy(ctx->tile[P.split], ctx->tile[P.split] + NBUCKET, tile);
+  }
+  P.pshape.assign(P.parts.size(), 0);
   int nt = 0;
-  for (const Part &pt : P.parts) {
-    const int tl = (P.slots[pt.slot]->n + RT - 1) / RT;
-    nt += (pt.m + EBMIN - 1) / EBMIN * (tl * (tl + 1) / 2);
+  for (size_t i = 0; i < P.parts.size(); ++i) {
+    const Part &pt = P.parts[i];
+    const int n = P.slots[pt.slot]->n;
+    P.pshape[i] = force >= 0 ? force : tile[size_bucket(n)];
+    const RTile rt = rtile(P.split, P.pshape[i]);
+    const int tl = (n + 16 * rt.tm - 1) / (16 * rt.tm);
+    nt += (pt.m + rt.eb - 1) / rt.eb * (tl * (tl + 1) / 2);
   }
   return nt;
 }
@@ -647,7 +673,7 @@ rm_status run_segments(rm_ctx *ctx, const std::vector<Seg> &segs, const rm_opts 
   for (size_t k = 0; k < plans.size(); ++k) {
     Slot &sl = ctx->pipe[k % nuse];
     Plan &P = plans[k];
-    if (rm_status st = ensure_slot(ctx, sl, P.L, (int)P.slots.size(), plan_tasks(P), false)) return st;
+    if (rm_status st = ensure_slot(ctx, sl, P.L, (int)P.slots.size(), plan_tasks(ctx, P, o), false)) return st;
     if (rm_status st = upload_plan(ctx, sl, P, segs, o, false)) return st;
     hipEvent_t prevR = k > 0 && nuse > 1 ? ctx->ev_R[(k - 1) % 2] : nullptr;
     if (rm_status st = run_chunk(ctx, P, sl, segs, o, kind_out(o), prevR, ctx->ev_R[k % 2])) return st;
@@ -667,7 +693,7 @@ rm_status staged_chunk(rm_ctx *ctx, const DevPW *pw, const double *E, int e0, in
   P = Plan();
   P.parts.push_back(Part{0, e0, m, 0, 0});
   finish_plan(P, segs, m);
-  if (rm_status st = ensure_slot(ctx, ctx->sync, P.L, 1, plan_tasks(P), want_S)) return st;
+  if (rm_status st = ensure_slot(ctx, ctx->sync, P.L, 1, plan_tasks(ctx, P, o), want_S)) return st;
   return upload_plan(ctx, ctx->sync, P, segs, o, false);
 }
 
@@ -780,7 +806,7 @@ void worker_main(rm_ctx *ctx, Slot *slot) {
       ne += pt.m;
     }
     finish_plan(P, segs, ne);
-    rm_status st = ensure_slot(ctx, *slot, P.L, (int)P.slots.size(), plan_tasks(P), false);
+    rm_status st = ensure_slot(ctx, *slot, P.L, (int)P.slots.size(), plan_tasks(ctx, P, o), false);
     if (st == RM_OK) st = upload_plan(ctx, *slot, P, segs, o, false);
     if (st == RM_OK) st = run_chunk(ctx, P, *slot, segs, o, hipMemcpyDeviceToHost);
     if (st == RM_OK && hipStreamSynchronize(slot->stream) != hipSuccess) st = RM_E_DEVICE;
@@ -839,8 +865,10 @@ rm_status rm_create(int device, size_t hbm_budget_bytes, rm_ctx **out) {
     return RM_E_DEVICE;
   }
   hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0) {
     ctx->ncu = prop.multiProcessorCount;
+    ctx->arch = prop.gcnArchName;
+  }
   size_t fr = 0, tot = 0;
   if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
     delete ctx;
@@ -1210,6 +1238,181 @@ rm_status rm_run_sum(rm_ctx *ctx, const int32_t *pw_ids, int32_t npw, const doub
     HIPCHK(hipMemcpyAsync(status, sst, sizeof(int32_t) * ne, hipMemcpyDeviceToHost, user));
   }
   HIPCHK(hipStreamSynchronize(user));
+  return RM_OK;
+}
+
+// ------------------------------------------------------------ tile autotuner
+int32_t rm_tile_bucket(int32_t nchan) { return size_bucket(nchan); }
+
+int32_t rm_tile_count(int32_t prec) {
+  if (prec != RM_FP64 && prec != RM_FP32_SPLIT) return 0;
+  return nrtile(prec == RM_FP32_SPLIT);
+}
+
+rm_status rm_tile_shape(int32_t prec, int32_t shape, int32_t *tile, int32_t *energies) {
+  if (shape < 0 || shape >= rm_tile_count(prec) || !tile || !energies) return RM_E_ARG;
+  const RTile t = rtile(prec == RM_FP32_SPLIT, shape);
+  *tile = 16 * t.tm;
+  *energies = t.eb;
+  return RM_OK;
+}
+
+rm_status rm_get_tile(rm_ctx *ctx, int32_t prec, int32_t bucket, int32_t *shape) {
+  if (!ctx || !shape || rm_tile_count(prec) == 0 || bucket < 0 || bucket >= NBUCKET) return RM_E_ARG;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  *shape = ctx->tile[prec == RM_FP32_SPLIT][bucket];
+  return RM_OK;
+}
+
+rm_status rm_set_tile(rm_ctx *ctx, int32_t prec, int32_t bucket, int32_t shape) {
+  if (!ctx || shape < 0 || shape >= rm_tile_count(prec) || bucket < 0 || bucket >= NBUCKET) return RM_E_ARG;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  ctx->tile[prec == RM_FP32_SPLIT][bucket] = shape;
+  return RM_OK;
+}
+
+rm_status rm_tune(rm_ctx *ctx, int32_t prec, const int32_t *pw_ids, int32_t npw, const double *E, int32_t ne,
+                  int32_t reps, const char *cache_path, double *ms) {
+  if (!ctx || rm_tile_count(prec) == 0 || !pw_ids || npw < 1 || !E || ne < 1 || reps < 1) return RM_E_ARG;
+  (void)hipSetDevice(ctx->device);
+  const int split = prec == RM_FP32_SPLIT, ns = nrtile(split);
+  rm_opts o;
+  rm_opts_default(&o);
+  o.prec = (rm_precision)prec;
+  std::vector<double> tot((size_t)NBUCKET * ns, 0.0), best_ms((size_t)npw * ns, 0.0);
+  bool seen[NBUCKET] = {false};
+  hipEvent_t ea = nullptr, eb = nullptr;
+  HIPCHK(hipEventCreate(&ea));
+  HIPCHK(hipEventCreate(&eb));
+  rm_status st = RM_OK;
+  for (int w = 0; w < npw && st == RM_OK; ++w) {
+    const DevPW *pw;
+    if ((st = get_pw(ctx, pw_ids[w], &pw))) break;
+    const int m = std::min(ne, staged_cap(ctx, pw, ne));
+    const int bk = size_bucket(pw->n);
+    seen[bk] = true;
+    for (int sh = 0; sh < ns && st == RM_OK; ++sh) {
+      std::vector<Seg> segs(1, Seg{pw, E, m, nullptr, nullptr, nullptr});
+      Plan P;
+      P.parts.push_back(Part{0, 0, m, 0, 0});
+      finish_plan(P, segs, m);
+      const int ntask = plan_tasks(ctx, P, o, sh);
+      if ((st = ensure_slot(ctx, ctx->sync, P.L, 1, ntask, false))) break;
+      if ((st = upload_plan(ctx, ctx->sync, P, segs, o, false))) break;
+      Work &wk = ctx->sync.w;
+      const hipStream_t s = ctx->sync.stream;
+      double best = 1e300;
+      for (int r = 0; r <= reps; ++r) {
+        if (hipEventRecord(ea, s) != hipSuccess) { st = RM_E_DEVICE; break; }
+        launch_dvec(s, P.L, wk.tab, wk.pwi, wk.E, split, o.split_delta, wk.D64, wk.D32, wk.win, wk.status);
+        launch_rform(s, P.L, split, sh, wk.tab, wk.tasks, P.q[sh], wk.counter + NQ * sh, ctx->ncu, wk.D64, wk.D32,
+                     wk.aug);
+        float t = 0;
+        if (hipEventRecord(eb, s) != hipSuccess || hipEventSynchronize(eb) != hipSuccess ||
+            hipEventElapsedTime(&t, ea, eb) != hipSuccess) {
+          st = RM_E_DEVICE;
+          break;
+        }
+        if (r > 0) best = std::min(best, (double)t);
+      }
+      best_ms[(size_t)w * ns + sh] = best;
+      tot[(size_t)bk * ns + sh] += best;
+    }
+  }
+  (void)hipEventDestroy(ea);
+  (void)hipEventDestroy(eb);
+  if (st != RM_OK) {
+    if (st == RM_E_DEVICE) ctx->err = "device error while tuning";
+    return st;
+  }
+  if (ms) std::copy(best_ms.begin(), best_ms.end(), ms);
+  int choice[NBUCKET];
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    for (int b = 0; b < NBUCKET; ++b) {
+      if (seen[b])
+        ctx->tile[split][b] = (int)(std::min_element(tot.begin() + (size_t)b * ns, tot.begin() + (size_t)(b + 1) * ns) -
+                                    (tot.begin() + (size_t)b * ns));
+      choice[b] = ctx->tile[split][b];
+    }
+  }
+  if (cache_path) {
+    FILE *f = std::fopen(cache_path, "w");
+    if (!f) {
+      ctx->err = "cannot write the tile cache";
+      return RM_E_DEVICE;
+    }
+    std::fprintf(f, "{\"rm_tile_cache\": 1, \"arch\": \"%s\", \"cus\": %d, \"entries\": [\n", ctx->arch.c_str(),
+                 ctx->ncu);
+    bool first = true;
+    for (int b = 0; b < NBUCKET; ++b) {
+      if (!seen[b]) continue;
+      const RTile t = rtile(split, choice[b]);
+      std::fprintf(f, "%s {\"prec\": %d, \"bucket\": %d, \"shape\": %d, \"tile\": %d, \"energies\": %d, \"ms\": [",
+                   first ? "" : ",\n", prec, b, choice[b], 16 * t.tm, t.eb);
+      for (int sh = 0; sh < ns; ++sh) std::fprintf(f, "%s%.4f", sh ? ", " : "", tot[(size_t)b * ns + sh]);
+      std::fprintf(f, "]}");
+      first = false;
+    }
+    std::fprintf(f, "\n]}\n");
+    if (std::fclose(f) != 0) {
+      ctx->err = "cannot write the tile cache";
+      return RM_E_DEVICE;
+    }
+  }
+  return RM_OK;
+}
+
+rm_status rm_tune_load(rm_ctx *ctx, const char *cache_path) {
+  if (!ctx || !cache_path) return RM_E_ARG;
+  FILE *f = std::fopen(cache_path, "r");
+  if (!f) {
+    ctx->err = "cannot read the tile cache";
+    return RM_E_NOTFOUND;
+  }
+  std::string text;
+  char buf[4096];
+  size_t got;
+  while ((got = std::fread(buf, 1, sizeof buf, f)) > 0 && text.size() < (1u << 20)) text.append(buf, got);
+  std::fclose(f);
+  auto bad = [&](const char *why) {
+    ctx->err = std::string("tile cache: ") + why;
+    return RM_E_ARG;
+  };
+  // integer value of "key": at or after position `from`; false if absent
+  auto intval = [&](const char *key, size_t from, size_t to, long &out) {
+    const std::string k = std::string("\"") + key + "\":";
+    const size_t at = text.find(k, from);
+    if (at == std::string::npos || at >= to) return false;
+    const char *p = text.c_str() + at + k.size();
+    char *end = nullptr;
+    out = std::strtol(p, &end, 10);
+    return end != p;
+  };
+  long v = 0;
+  if (!intval("rm_tile_cache", 0, text.size(), v) || v != 1) return bad("not a tile cache of this version");
+  const std::string ak = "\"arch\": \"";
+  const size_t a0 = text.find(ak);
+  if (a0 == std::string::npos) return bad("no architecture");
+  const size_t a1 = text.find('"', a0 + ak.size());
+  if (a1 == std::string::npos || text.substr(a0 + ak.size(), a1 - a0 - ak.size()) != ctx->arch)
+    return bad("made on a device of another architecture");
+  if (!intval("cus", 0, text.size(), v) || v != ctx->ncu) return bad("made on a device with another compute-unit count");
+  std::vector<std::array<int, 3>> set;
+  for (size_t pos = text.find("{\"prec\":"); pos != std::string::npos; pos = text.find("{\"prec\":", pos + 1)) {
+    const size_t end = text.find('}', pos);
+    if (end == std::string::npos) return bad("unterminated entry");
+    long prec, bucket, shape;
+    if (!intval("prec", pos, end, prec) || !intval("bucket", pos, end, bucket) || !intval("shape", pos, end, shape))
+      return bad("entry without prec, bucket or shape");
+    if (rm_tile_count((int32_t)prec) == 0 || bucket < 0 || bucket >= NBUCKET || shape < 0 ||
+        shape >= rm_tile_count((int32_t)prec))
+      return bad("entry out of range");
+    set.push_back({(int)prec, (int)bucket, (int)shape});
+  }
+  if (set.empty()) return bad("no entries");
+  std::lock_guard<std::mutex> g(ctx->mu);
+  for (const auto &e : set) ctx->tile[e[0] == RM_FP32_SPLIT][e[1]] = e[2];
   return RM_OK;
 }
 

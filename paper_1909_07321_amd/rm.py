@@ -82,10 +82,20 @@ _lib.rm_drain.argtypes = [_vp]
 _lib.rm_prof_enable.argtypes = [_vp, _i32]
 _lib.rm_prof_read.argtypes = [_vp, ctypes.c_char_p, ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_int64),
                               ctypes.POINTER(ctypes.c_int64)]
+_lib.rm_tile_bucket.argtypes = [_i32]
+_lib.rm_tile_bucket.restype = _i32
+_lib.rm_tile_count.argtypes = [_i32]
+_lib.rm_tile_count.restype = _i32
+_lib.rm_tile_shape.argtypes = [_i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]
+_lib.rm_get_tile.argtypes = [_vp, _i32, _i32, ctypes.POINTER(_i32)]
+_lib.rm_set_tile.argtypes = [_vp, _i32, _i32, _i32]
+_lib.rm_tune.argtypes = [_vp, _i32, ctypes.POINTER(_i32), _i32, _vp, _i32, _i32, ctypes.c_char_p, _vp]
+_lib.rm_tune_load.argtypes = [_vp, ctypes.c_char_p]
 
 EXPORTS = ["rm_opts_default", "rm_create", "rm_destroy", "rm_last_error", "rm_pw_upload", "rm_pw_release",
            "rm_pw_footprint", "rm_form_R", "rm_asymptotic", "rm_solve_K", "rm_collision_strengths", "rm_run",
-           "rm_run_batch", "rm_run_sum",
+           "rm_run_batch", "rm_run_sum", "rm_tile_bucket", "rm_tile_count", "rm_tile_shape", "rm_get_tile",
+           "rm_set_tile", "rm_tune", "rm_tune_load",
            "rm_submit", "rm_poll", "rm_drain", "rm_prof_enable", "rm_prof_read"]
 
 
@@ -107,6 +117,25 @@ def _ptr(x):
 
 def pw_footprint(nchan: int, npole: int) -> int:
     return int(_lib.rm_pw_footprint(nchan, npole))
+
+
+NBUCKET = 4
+
+
+def tile_bucket(nchan: int) -> int:
+    """Size bucket of a channel count (rm_tile_bucket)."""
+    return int(_lib.rm_tile_bucket(nchan))
+
+
+def tile_shapes(prec: int):
+    """[(tile side, energies per task)] of the R-contraction shapes of a precision."""
+    out = []
+    for sh in range(int(_lib.rm_tile_count(prec))):
+        t, e = _i32(), _i32()
+        if _lib.rm_tile_shape(prec, sh, ctypes.byref(t), ctypes.byref(e)) != 0:
+            raise RMError("rm_tile_shape failed")
+        out.append((t.value, e.value))
+    return out
 
 
 class Context:
@@ -317,6 +346,28 @@ class Context:
 
     def drain(self):
         self._check(_lib.rm_drain(self.h))
+
+    # ------------------------------------------------------ tile autotuner
+    def get_tile(self, prec, bucket):
+        sh = _i32()
+        self._check(_lib.rm_get_tile(self.h, prec, bucket, ctypes.byref(sh)))
+        return sh.value
+
+    def set_tile(self, prec, bucket, shape):
+        self._check(_lib.rm_set_tile(self.h, prec, bucket, shape))
+
+    def tune(self, prec, pw_ids, E, reps=2, cache_path=None):
+        """Times every R tile shape of prec on the waves pw_ids for the energies
+        E, keeps the fastest per size bucket; returns the times [npw][nshapes] (ms)."""
+        E = np.ascontiguousarray(E, dtype=np.float64)
+        ids = (_i32 * len(pw_ids))(*pw_ids)
+        ms = np.zeros((len(pw_ids), len(tile_shapes(prec))))
+        path = cache_path.encode() if cache_path else None
+        self._check(_lib.rm_tune(self.h, prec, ids, len(pw_ids), _ptr(E), E.shape[0], reps, path, _ptr(ms)))
+        return ms
+
+    def tune_load(self, cache_path):
+        self._check(_lib.rm_tune_load(self.h, cache_path.encode()))
 
     # ---------------------------------------------------------- profiling
     def prof_enable(self, on: bool = True):

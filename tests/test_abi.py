@@ -42,3 +42,17 @@ def test_oracle_not_linked_into_library():
         pytest.skip("librm.so not built")
     data = open(LIB, "rb").read()
     assert b"rmo_" not in data and b"librmo" not in data
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="librm.so not built")
+def test_tile_shape_table():
+    # host-only queries of the R tile shapes (no device call)
+    from paper_1909_07321_amd import rm
+    assert [rm.tile_bucket(n) for n in (1, 64, 65, 192, 193, 512, 513, 16384)] == [0, 0, 1, 1, 2, 2, 3, 3]
+    for prec in (0, 1):
+        shapes = rm.tile_shapes(prec)
+        assert shapes[0] == (32, 4)  # the default shape
+        assert len(set(shapes)) == len(shapes) >= 2
+        for tile, eb in shapes:
+            assert tile in (16, 32, 64) and 1 <= eb <= 8
+    assert rm.tile_shapes(7) == []

@@ -1,0 +1,123 @@
+"""Tile shapes of the R contraction and the tile autotuner.
+
+Every shape sums each R element over the poles in the same order, so R, K and
+Omega must be bitwise equal whichever shape a size bucket uses (and match the
+oracle, which the other parity tests check for the default shape).  The tuner
+must time every shape, keep a valid choice per bucket, write a cache that a
+fresh context loads back to the same choices, and refuse malformed caches
+without changing anything."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1909_07321_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rm():
+    from paper_1909_07321_amd import rm as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(rm):
+    c = rm.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def waves():
+    # one wave per size bucket, ragged against every tile side (16, 32, 64)
+    sizes = [23, 150, 333, 700]
+    E = np.linspace(0.01, 6.0, 13)
+    pws = [synth.make_partial_wave(synth.config_seed(3) + 80 + i, n, 12, z=5.0, a=12.0, thr_range=(0.0, 4.0),
+                                   pole_range=(-2.0, 60.0), avoid_energies=E, name=f"tile{i}")
+           for i, n in enumerate(sizes)]
+    return pws, E
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_shapes_bitwise_equal(rm, ctx, waves, prec):
+    pws, E = waves
+    shapes = rm.tile_shapes(prec)
+    assert len(shapes) >= 2
+    for pw in pws:
+        pid = ctx.pw_upload(pw)
+        b = rm.tile_bucket(pw.nchan)
+        keep = ctx.get_tile(prec, b)
+        try:
+            ref = None
+            for sh, (tile, eb) in enumerate(shapes):
+                ctx.set_tile(prec, b, sh)
+                R, stR = ctx.form_R(pid, E, prec=prec)
+                om, K, st = ctx.run(pid, E, prec=prec)
+                print(f"prec={prec} n={pw.nchan} shape {sh} ({tile}x{tile}, {eb} energies)", flush=True)
+                if ref is None:
+                    ref = (R, om, K, st, stR)
+                    continue
+                assert np.array_equal(R, ref[0], equal_nan=True), (pw.nchan, sh)
+                assert np.array_equal(om, ref[1], equal_nan=True), (pw.nchan, sh)
+                assert np.array_equal(K, ref[2], equal_nan=True), (pw.nchan, sh)
+                assert np.array_equal(st, ref[3]) and np.array_equal(stR, ref[4])
+        finally:
+            ctx.set_tile(prec, b, keep)
+            ctx.pw_release(pid)
+        # the shared result is the oracle's R (FP64 gate / split tolerance)
+        Ro = oracle.Oracle(pw).form_R(E)[0]
+        err = np.abs(ref[0] - Ro).max() / np.abs(Ro).max()
+        assert err < (1e-10 if prec == 0 else 1e-5), (pw.nchan, err)
+
+
+def test_tune_and_cache(rm, ctx, waves, tmp_path):
+    pws, E = waves
+    ids = [ctx.pw_upload(p) for p in pws[:3]]
+    try:
+        path = str(tmp_path / "tiles.json")
+        for prec in (0, 1):
+            ms = ctx.tune(prec, ids, E[:8], reps=1, cache_path=path)
+            print(f"prec={prec} tuning ms per wave and shape:\n{ms}", flush=True)
+            assert ms.shape == (3, len(rm.tile_shapes(prec))) and (ms > 0).all()
+            chosen = [ctx.get_tile(prec, rm.tile_bucket(p.nchan)) for p in pws[:3]]
+            for p, row, c in zip(pws[:3], ms, chosen):
+                assert 0 <= c < len(rm.tile_shapes(prec))
+                assert row[c] == row.min(), (p.nchan, row, c)  # one wave per bucket: its own fastest
+            doc = json.load(open(path))
+            assert doc["rm_tile_cache"] == 1 and doc["cus"] > 0 and doc["arch"]
+            ent = {(e["prec"], e["bucket"]): e["shape"] for e in doc["entries"]}
+            assert ent == {(prec, rm.tile_bucket(p.nchan)): c for p, c in zip(pws[:3], chosen)}
+            # a fresh context loads the same choices
+            with rm.Context(0) as c2:
+                for b in range(rm.NBUCKET):
+                    c2.set_tile(prec, b, len(rm.tile_shapes(prec)) - 1 - c2.get_tile(prec, b))
+                before = [c2.get_tile(prec, b) for b in range(rm.NBUCKET)]
+                c2.tune_load(path)
+                for (pr, b), sh in ent.items():
+                    assert c2.get_tile(pr, b) == sh
+                untouched = [b for b in range(rm.NBUCKET) if (prec, b) not in ent]
+                assert all(c2.get_tile(prec, b) == before[b] for b in untouched)
+                # malformed caches are refused and change nothing
+                state = [c2.get_tile(prec, b) for b in range(rm.NBUCKET)]
+                bad = dict(doc)
+                bad["arch"] = "gfx000"
+                for i, text in enumerate([json.dumps(bad), json.dumps({**doc, "cus": doc["cus"] + 1}),
+                                          json.dumps({**doc, "entries": [{"prec": prec, "bucket": 9, "shape": 0}]}),
+                                          json.dumps({**doc, "entries": [{"prec": prec, "bucket": 0,
+                                                                          "shape": 7}]}),
+                                          "not json"]):
+                    p = str(tmp_path / f"bad{i}.json")
+                    with open(p, "w") as f:
+                        f.write(text)
+                    with pytest.raises(rm.RMError):
+                        c2.tune_load(p)
+                    assert [c2.get_tile(prec, b) for b in range(rm.NBUCKET)] == state
+                with pytest.raises(rm.RMError):
+                    c2.tune_load(str(tmp_path / "missing.json"))
+    finally:
+        for i in ids:
+            ctx.pw_release(i)

@@ -156,6 +156,15 @@ def config_measure(ctx) -> dict:
     ids = [ctx.pw_upload(p) for p in pws]
     log(f"c3 workload generated in {time.time() - t0:.1f}s: {len(pws)} waves, {E.size} energies each")
     Ed = torch.tensor(E, dtype=torch.float64, device=dev)
+    # tile autotuner: up to 4 waves of each size bucket, every R tile shape, one choice per bucket
+    byb = {}
+    for p, i in zip(pws, ids):
+        byb.setdefault(rm.tile_bucket(p.nchan), []).append(i)
+    t0 = time.time()
+    for b, lst in sorted(byb.items()):
+        ctx.tune(rm.FP64, lst[:4], E[::20][:256], reps=1)
+    tiles = {b: rm.tile_shapes(rm.FP64)[ctx.get_tile(rm.FP64, b)] for b in sorted(byb)}
+    log(f"c3 tuned in {time.time() - t0:.1f}s: tile shape per size bucket {tiles}")
     ctx.run_batch([(i, Ed[:64]) for i in ids], prec=rm.FP64)  # warm-up: workspaces and code
     torch.cuda.synchronize()
     drain_prof(ctx)
@@ -172,6 +181,7 @@ def config_measure(ctx) -> dict:
     flops = sum(float(p.nchan) * (p.nchan + 1) * p.npole for p in pws) * E.size
     out["c3_fp64"] = dict(points_per_s=pts / dt, r_stage_points_per_s=rf_e / (rf_ms * 1e-3),
                           r_tflops=flops / (rf_ms * 1e-3) / 1e12, seconds=dt, flagged_energies=flagged,
+                          tiles={str(b): dict(side=t[0], energies_per_task=t[1]) for b, t in tiles.items()},
                           workload="64 waves, 20..600 channels, 30 poles per channel, 5000 energies each, "
                                    "one rm_run_batch call")
     log(f"c3 fp64: {pts / dt:.0f} points/s over {dt:.1f}s (R stage {rf_e / (rf_ms * 1e-3):.0f} points/s, "
@@ -255,6 +265,11 @@ def main() -> int:
              "both": [("split", rm.FP32_SPLIT), ("fp64", rm.FP64)]}[args.prec]
     results = {}
     for name, prec in modes:
+        # tile autotuner: time every R tile shape on a slice of the grid, keep the fastest
+        tune_ms = ctx.tune(prec, [pid], E[::4][:256], reps=1)[0]
+        shape = ctx.get_tile(prec, rm.tile_bucket(pw.nchan))
+        tile = rm.tile_shapes(prec)[shape]
+        log(f"{name}: tile shapes {rm.tile_shapes(prec)} tuned at {np.round(tune_ms, 1).tolist()} ms -> {tile}")
         for _ in range(args.warmup):
             ctx.run(pid, Ed, prec=prec, want_K=False, out=(om, None, st))
         torch.cuda.synchronize()
@@ -278,6 +293,7 @@ def main() -> int:
         results[name] = dict(
             value=E.size * args.steps / (t2 - t1), ms_per_step=ms_step,
             flagged_energies=int((stat != 0).sum()),
+            tile=dict(side=tile[0], energies_per_task=tile[1], tuned_ms=tune_ms.tolist()),
             stage_ms_per_step={s: v[0] / args.steps for s, v in stages.items()},
             roofline=dict(bound="mfma", achieved=achieved, peak=PEAK[dt], unit="TFLOP/s",
                           frac=(achieved / PEAK[dt]) if achieved else None, traffic=measured_traffic(kname),
@@ -323,6 +339,7 @@ def main() -> int:
         "modes": results,
         "serving": serving,
         "configs": configs,
+        "graphs": dict(zip(("captured", "replayed"), ctx.graph_stats())),
     }
     print(json.dumps(line), flush=True)
     ctx.close()

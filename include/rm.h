@@ -182,6 +182,19 @@ typedef struct {
    sizes.  Results equal those of rm_run on each item alone. */
 rm_status rm_run_batch(rm_ctx *ctx, const rm_batch_item *items, int32_t nitems, const rm_opts *opts);
 
+/* Graph mode (on by default): rm_run, rm_run_batch, rm_run_sum and the
+   serving workers launch each chunk's kernels as HIP graphs, one per stage
+   group (asymptotics, d(E), R contraction, near-pole correction, K solve,
+   S/Omega, packing of Omega, packing of K).  A group is captured from the
+   stream the first time a chunk of its shape (sizes, workspace, task queues,
+   options) runs on a stream and replayed while the shape repeats, so a run of
+   equal chunks issues at most eight graph launches per chunk instead of
+   hundreds of kernel launches.  The graphs hold kernel nodes only.  Results
+   are the same in both modes.  rm_graph_stats returns how many group graphs
+   were captured and replayed since the context was created. */
+rm_status rm_set_graph(rm_ctx *ctx, int32_t on);
+rm_status rm_graph_stats(rm_ctx *ctx, int64_t *captures, int64_t *replays);
+
 /* Sum over partial waves of one collision problem (PSTGF paper, Glossary,
    "Collision strength", and section "Overview", the outer loop over partial
    waves: the collision strength is the sum of the partial ones):
@@ -228,7 +241,8 @@ rm_status rm_set_tile(rm_ctx *ctx, int32_t prec, int32_t bucket, int32_t shape);
    pw_ids[0 .. npw) for the ne host energies E (reps timed runs after one
    warmup; the minimum counts), sums the times of the waves of each bucket, and
    makes the fastest shape the context's choice for every bucket that holds one
-   of the waves.  ms (NULL or [npw][rm_tile_count(prec)]) receives the times.
+   of the waves (a shape other than shape 0 must be at least 3% faster than
+   shape 0: a chunk launches the contraction once per shape it uses).  ms (NULL or [npw][rm_tile_count(prec)]) receives the times.
    If cache_path is not NULL the choices are also written there (JSON, one
    entry per tuned bucket, with the device architecture and compute-unit count)
    for rm_tune_load.  Synchronous; RM_E_NOTFOUND for an unknown wave, RM_E_ARG

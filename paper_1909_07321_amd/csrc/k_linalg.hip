@@ -1367,6 +1367,16 @@ void launch_finalize(hipStream_t s, const Lay &L, const DevPW *tab, const int *p
                      L.nmax);
 }
 
+// p[0 .. n) = v (a fill kernel: stream-captured graphs keep no memset nodes).
+__global__ void k_fill_int(int *__restrict__ p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+void launch_fill_int(hipStream_t s, int *p, int n, int v) {
+  if (n > 0) hipLaunchKernelGGL(k_fill_int, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+}
+
 __global__ void k_setdims(const DevPW *__restrict__ tab, const int *__restrict__ pwi, int ne,
                           const int *__restrict__ nopen, int *__restrict__ dims) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;

@@ -144,6 +144,8 @@ void launch_openlist(hipStream_t s, const Lay &L, const DevPW *tab, const int *p
                      int *openidx, int *openpos, int *colpos, int8_t *openflag);
 void launch_asym(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const double *E, double thr_guard,
                  double *fg, int *status);
+// p[0 .. n) = v.
+void launch_fill_int(hipStream_t s, int *p, int n, int v);
 void launch_setdims(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *nopen, int *dims);
 // Assembles [A | B] in place over R; A's columns are ordered closed channels
 // first, then open channels (both ascending), as colpos says.

@@ -53,10 +53,23 @@ struct Staging {
   hipEvent_t ready = nullptr;
 };
 
+// HIP graphs of one slot's chunk pipeline, one per stage group: the captured
+// launch sequence of the group for the last chunk shape (key), replayed while
+// the shape repeats.  Replaced executables wait in `retired` until an event
+// recorded after their last launch has completed.
+constexpr int NGROUP = 8;
+struct GraphCache {
+  std::string key[NGROUP];
+  hipGraphExec_t exec[NGROUP] = {};
+  std::vector<std::pair<hipGraphExec_t, hipEvent_t>> retired;
+  std::atomic<long> captures{0}, replays{0};
+};
+
 struct Slot {
   hipStream_t stream = nullptr;
   Work w;
   Staging h;
+  GraphCache g;
 };
 
 struct ProfRec {
@@ -128,6 +141,7 @@ struct rm_ctx {
   std::atomic<int> prof_on{0};
   std::vector<ProfRec> prof;  // guarded by mu
   int tile[2][NBUCKET] = {};  // R tile shape per (split, size bucket); guarded by mu
+  std::atomic<int> graphs{1};  // chunk pipelines run as captured HIP graphs
   // rm_run / rm_run_batch alternate chunks over two streams; the R
   // contractions are chained across them so that one chunk's K solve overlaps
   // the next chunk's contraction
@@ -147,6 +161,7 @@ namespace {
   } while (0)
 
 constexpr int MAX_CHUNK = 1024;
+constexpr double TUNE_MARGIN = 0.03;
 
 size_t per_energy_bytes(int n, int npad, int Mpad, int nt) {
   return (size_t)n * 2 * npad * 8    // aug
@@ -531,6 +546,90 @@ int plan_tasks(rm_ctx *ctx, Plan &P, const rm_opts &o, int force = -1) {
   return nt;
 }
 
+// Everything the captured launch sequence of a chunk depends on: sizes and
+// strides, workspace addresses, task queues and options (the kernels read the
+// chunk's tables, tasks and energies from the workspace, so chunks with equal
+// keys replay the same graphs).
+std::string chunk_key(rm_ctx *ctx, const Plan &P, const Work &w, const rm_opts &o, bool want_K) {
+  std::string k;
+  auto add = [&](const auto &v) { k.append(reinterpret_cast<const char *>(&v), sizeof v); };
+  const Lay &L = P.L;
+  for (long v : {(long)L.ne, (long)L.nmax, (long)L.npadmax, (long)L.Mpadmax, (long)L.ntmax, L.ldD, L.ldaug, L.roff,
+                 L.sA, L.ldk, L.sK, L.ldo, L.sOm})
+    add(v);
+  for (const void *p : {(const void *)w.E, (const void *)w.pwi, (const void *)w.tab, (const void *)w.tasks,
+                        (const void *)w.counter, (const void *)w.D64, (const void *)w.D32, (const void *)w.win,
+                        (const void *)w.status, (const void *)w.nopen, (const void *)w.openidx,
+                        (const void *)w.openpos, (const void *)w.colpos, (const void *)w.openflag,
+                        (const void *)w.fg, (const void *)w.aug, (const void *)w.Kw, (const void *)w.XK,
+                        (const void *)w.dims, (const void *)w.ipiv, (const void *)w.bperm, (const void *)w.linv,
+                        (const void *)w.omega, (const void *)w.pack, (const void *)w.pack_off})
+    add(p);
+  for (int sh = 0; sh < NRTMAX; ++sh) add(P.q[sh]);
+  add(P.maxtiles);
+  add(P.split);
+  add(o.split_delta);
+  add(o.thr_guard);
+  add(want_K);
+  add(ctx->ncu);
+  return k;
+}
+
+// Runs the launches of `body` on the slot's stream: directly, or (graph mode)
+// as the executable graph of stage group `grp`, captured from body when the
+// slot has none for this key and replayed otherwise.
+template <typename F>
+rm_status launch_group(rm_ctx *ctx, Slot &sl, int grp, const std::string &key, F &&body) {
+  const hipStream_t s = sl.stream;
+  if (!ctx->graphs.load()) {
+    body();
+    HIPCHK(hipGetLastError());
+    return RM_OK;
+  }
+  GraphCache &gc = sl.g;
+  for (size_t i = 0; i < gc.retired.size();) {
+    if (hipEventQuery(gc.retired[i].second) == hipSuccess) {
+      (void)hipGraphExecDestroy(gc.retired[i].first);
+      (void)hipEventDestroy(gc.retired[i].second);
+      gc.retired[i] = gc.retired.back();
+      gc.retired.pop_back();
+    } else {
+      ++i;
+    }
+  }
+  (void)hipGetLastError();  // a query of a pending event is not an error
+  if (!gc.exec[grp] || gc.key[grp] != key) {
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+    body();
+    const hipError_t ec = hipStreamEndCapture(s, &g);
+    if (ec != hipSuccess || !g) {
+      ctx->err = std::string("graph capture: ") + hipGetErrorString(ec);
+      return RM_E_DEVICE;
+    }
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+      ctx->err = std::string("graph instantiation: ") + hipGetErrorString(ei);
+      return RM_E_DEVICE;
+    }
+    if (gc.exec[grp]) {
+      hipEvent_t ev = nullptr;
+      HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      HIPCHK(hipEventRecord(ev, s));
+      gc.retired.emplace_back(gc.exec[grp], ev);
+    }
+    gc.exec[grp] = ex;
+    gc.key[grp] = key;
+    ++gc.captures;
+  } else {
+    ++gc.replays;
+  }
+  HIPCHK(hipGraphLaunch(gc.exec[grp], s));
+  return RM_OK;
+}
+
 // Runs every stage of a planned chunk (inputs already uploaded) and copies
 // each part's results to its segment.  before_R / after_R (optional) order the
 // R contraction against other streams.
@@ -539,17 +638,40 @@ rm_status run_chunk(rm_ctx *ctx, const Plan &P, Slot &sl, const std::vector<Seg>
   const Lay &L = P.L;
   Work &w = sl.w;
   const hipStream_t s = sl.stream;
-  HIPCHK(hipMemsetAsync(w.status, 0, sizeof(int) * L.ne, s));
-  stage_asym(ctx, P, w, o, s);
-  if (before_R) HIPCHK(hipStreamWaitEvent(s, before_R, 0));
-  stage_R(ctx, P, w, o, s);
-  if (after_R) HIPCHK(hipEventRecord(after_R, s));
-  timed(ctx, 3, L.ne, s, [&] { stage_K(P, w, s); });
-  timed(ctx, 4, L.ne, s, [&] { stage_SO(P, w, false, s); });
-  launch_finalize(s, L, w.tab, w.pwi, w.status, w.omega, w.Kw, nullptr);
+  const int split = o.prec == RM_FP32_SPLIT;
   bool want_K = false;
   for (const Part &pt : P.parts) want_K |= segs[pt.seg].K != nullptr;
-  launch_pack(s, L, w.tab, w.pwi, 0, w.omega, w.pack_off, w.pack);
+  const std::string key = chunk_key(ctx, P, w, o, want_K);
+  rm_status st = RM_OK;
+  auto group = [&](int g, auto &&body) {
+    if (st == RM_OK) st = launch_group(ctx, sl, g, key, body);
+  };
+  timed(ctx, 2, L.ne, s, [&] {
+    group(0, [&] {
+      launch_fill_int(s, w.status, L.ne, 0);
+      launch_openlist(s, L, w.tab, w.pwi, w.E, w.nopen, w.openidx, w.openpos, w.colpos, w.openflag);
+      launch_asym(s, L, w.tab, w.pwi, w.E, o.thr_guard, w.fg, w.status);
+    });
+  });
+  if (before_R) HIPCHK(hipStreamWaitEvent(s, before_R, 0));
+  group(1, [&] { launch_dvec(s, L, w.tab, w.pwi, w.E, split, o.split_delta, w.D64, w.D32, w.win, w.status); });
+  timed(ctx, 0, L.ne, s, [&] {
+    group(2, [&] {
+      for (int sh = 0; sh < nrtile(split); ++sh)
+        launch_rform(s, L, split, sh, w.tab, w.tasks, P.q[sh], w.counter + NQ * sh, ctx->ncu, w.D64, w.D32, w.aug);
+    });
+  });
+  if (split) timed(ctx, 1, L.ne, s, [&] {
+      group(3, [&] { launch_nearpole(s, L, P.maxtiles, w.tab, w.pwi, w.E, w.win, w.aug); });
+    });
+  if (after_R) HIPCHK(hipEventRecord(after_R, s));
+  timed(ctx, 3, L.ne, s, [&] { group(4, [&] { stage_K(P, w, s); }); });
+  timed(ctx, 4, L.ne, s, [&] { group(5, [&] { stage_SO(P, w, false, s); }); });
+  group(6, [&] {
+    launch_finalize(s, L, w.tab, w.pwi, w.status, w.omega, w.Kw, nullptr);
+    launch_pack(s, L, w.tab, w.pwi, 0, w.omega, w.pack_off, w.pack);
+  });
+  if (st != RM_OK) return st;
   for (const Part &pt : P.parts) {
     const Seg &g = segs[pt.seg];
     const long o0 = sl.h.off[pt.e0], o1 = sl.h.off[pt.e0 + pt.m - 1] + (long)g.pw->nt * g.pw->nt;
@@ -558,7 +680,9 @@ rm_status run_chunk(rm_ctx *ctx, const Plan &P, Slot &sl, const std::vector<Seg>
     HIPCHK(hipMemcpyAsync(g.status + pt.e_begin, w.status + pt.e0, sizeof(int) * pt.m, ko, s));
   }
   if (want_K) {
-    launch_pack(s, L, w.tab, w.pwi, 1, w.Kw, w.pack_off + L.ne + 1, w.pack);
+    // K is packed into the same buffer once Omega's copies are queued
+    group(7, [&] { launch_pack(s, L, w.tab, w.pwi, 1, w.Kw, w.pack_off + L.ne + 1, w.pack); });
+    if (st != RM_OK) return st;
     for (const Part &pt : P.parts) {
       const Seg &g = segs[pt.seg];
       if (!g.K) continue;
@@ -835,6 +959,17 @@ void destroy_slot(Slot &sl) {
     (void)hipStreamSynchronize(sl.stream);
     (void)hipStreamDestroy(sl.stream);
   }
+  for (hipGraphExec_t &ex : sl.g.exec)
+    if (ex) (void)hipGraphExecDestroy(ex);
+  for (auto &r : sl.g.retired) {
+    (void)hipGraphExecDestroy(r.first);
+    (void)hipEventDestroy(r.second);
+  }
+  for (int g = 0; g < NGROUP; ++g) {
+    sl.g.exec[g] = nullptr;
+    sl.g.key[g].clear();
+  }
+  sl.g.retired.clear();
   free_work(sl.w);
   free_staging(sl.h);
 }
@@ -1241,6 +1376,25 @@ rm_status rm_run_sum(rm_ctx *ctx, const int32_t *pw_ids, int32_t npw, const doub
   return RM_OK;
 }
 
+rm_status rm_set_graph(rm_ctx *ctx, int32_t on) {
+  if (!ctx) return RM_E_ARG;
+  ctx->graphs.store(on ? 1 : 0);
+  return RM_OK;
+}
+
+rm_status rm_graph_stats(rm_ctx *ctx, int64_t *captures, int64_t *replays) {
+  if (!ctx || !captures || !replays) return RM_E_ARG;
+  int64_t c = ctx->sync.g.captures + ctx->pipe[0].g.captures + ctx->pipe[1].g.captures;
+  int64_t r = ctx->sync.g.replays + ctx->pipe[0].g.replays + ctx->pipe[1].g.replays;
+  for (auto &sl : ctx->slots) {
+    c += sl->g.captures;
+    r += sl->g.replays;
+  }
+  *captures = c;
+  *replays = r;
+  return RM_OK;
+}
+
 // ------------------------------------------------------------ tile autotuner
 int32_t rm_tile_bucket(int32_t nchan) { return size_bucket(nchan); }
 
@@ -1329,10 +1483,16 @@ rm_status rm_tune(rm_ctx *ctx, int32_t prec, const int32_t *pw_ids, int32_t npw,
   int choice[NBUCKET];
   {
     std::lock_guard<std::mutex> g(ctx->mu);
+    // another shape must beat the default by TUNE_MARGIN: a chunk launches the
+    // contraction once per shape it uses, so a near tie is not worth a launch
     for (int b = 0; b < NBUCKET; ++b) {
-      if (seen[b])
-        ctx->tile[split][b] = (int)(std::min_element(tot.begin() + (size_t)b * ns, tot.begin() + (size_t)(b + 1) * ns) -
-                                    (tot.begin() + (size_t)b * ns));
+      if (seen[b]) {
+        const double *t = tot.data() + (size_t)b * ns;
+        int best = 0;
+        for (int sh = 1; sh < ns; ++sh)
+          if (t[sh] < t[best] && t[sh] < (1.0 - TUNE_MARGIN) * t[0]) best = sh;
+        ctx->tile[split][b] = best;
+      }
       choice[b] = ctx->tile[split][b];
     }
   }

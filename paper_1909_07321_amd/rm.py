@@ -91,11 +91,13 @@ _lib.rm_get_tile.argtypes = [_vp, _i32, _i32, ctypes.POINTER(_i32)]
 _lib.rm_set_tile.argtypes = [_vp, _i32, _i32, _i32]
 _lib.rm_tune.argtypes = [_vp, _i32, ctypes.POINTER(_i32), _i32, _vp, _i32, _i32, ctypes.c_char_p, _vp]
 _lib.rm_tune_load.argtypes = [_vp, ctypes.c_char_p]
+_lib.rm_set_graph.argtypes = [_vp, _i32]
+_lib.rm_graph_stats.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
 
 EXPORTS = ["rm_opts_default", "rm_create", "rm_destroy", "rm_last_error", "rm_pw_upload", "rm_pw_release",
            "rm_pw_footprint", "rm_form_R", "rm_asymptotic", "rm_solve_K", "rm_collision_strengths", "rm_run",
            "rm_run_batch", "rm_run_sum", "rm_tile_bucket", "rm_tile_count", "rm_tile_shape", "rm_get_tile",
-           "rm_set_tile", "rm_tune", "rm_tune_load",
+           "rm_set_tile", "rm_tune", "rm_tune_load", "rm_set_graph", "rm_graph_stats",
            "rm_submit", "rm_poll", "rm_drain", "rm_prof_enable", "rm_prof_read"]
 
 
@@ -346,6 +348,16 @@ class Context:
 
     def drain(self):
         self._check(_lib.rm_drain(self.h))
+
+    # ------------------------------------------------------- graph mode
+    def set_graph(self, on: bool):
+        self._check(_lib.rm_set_graph(self.h, 1 if on else 0))
+
+    def graph_stats(self):
+        """(captured, replayed) stage-group graphs since the context was made."""
+        c, r = ctypes.c_int64(), ctypes.c_int64()
+        self._check(_lib.rm_graph_stats(self.h, ctypes.byref(c), ctypes.byref(r)))
+        return c.value, r.value
 
     # ------------------------------------------------------ tile autotuner
     def get_tile(self, prec, bucket):

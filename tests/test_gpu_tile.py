@@ -86,7 +86,9 @@ def test_tune_and_cache(rm, ctx, waves, tmp_path):
             chosen = [ctx.get_tile(prec, rm.tile_bucket(p.nchan)) for p in pws[:3]]
             for p, row, c in zip(pws[:3], ms, chosen):
                 assert 0 <= c < len(rm.tile_shapes(prec))
-                assert row[c] == row.min(), (p.nchan, row, c)  # one wave per bucket: its own fastest
+                # one wave per bucket: its own fastest, the default unless another is 3% faster
+                assert row[c] == row.min() or (c == 0 and row.min() >= 0.97 * row[0]), (p.nchan, row, c)
+                assert c == 0 or row[c] < 0.97 * row[0], (p.nchan, row, c)
             doc = json.load(open(path))
             assert doc["rm_tile_cache"] == 1 and doc["cus"] > 0 and doc["arch"]
             ent = {(e["prec"], e["bucket"]): e["shape"] for e in doc["entries"]}

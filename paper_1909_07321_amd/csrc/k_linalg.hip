@@ -67,10 +67,11 @@ __device__ __forceinline__ void for_items(int ne, int ipe, F &&f) {
 }
 
 // acc += A_slab (64 x K) * B_slab (K x 64): every wave owns a 32 x 32 quarter.
-template <int K>
+// UNROLL bounds how many k-steps' fragments are read ahead (registers).
+template <int K, int UNROLL = K / 4>
 __device__ __forceinline__ void mfma_slab(const double (*sA)[Pitch<K>::A], const double (*sB)[PB], d4 (&acc)[4],
                                           int wr, int wc, int kk, int ii) {
-#pragma unroll
+#pragma unroll UNROLL
   for (int ks = 0; ks < K; ks += 4) {
     const double a0 = sA[wr * 32 + ii][ks + kk], a1 = sA[wr * 32 + 16 + ii][ks + kk];
     const double b0 = sB[ks + kk][wc * 32 + ii], b1 = sB[ks + kk][wc * 32 + 16 + ii];
@@ -570,12 +571,18 @@ struct ColMap {
   __device__ __forceinline__ long operator()(int v) const { return v < acols ? (long)(c0 + v) : roff + (v - acols); }
 };
 
-// C (64 rows x G column tiles) -= Lb (64 x KB, staged in sL) * U (KB x columns),
-// one column tile at a time.  The next tile's C values and U slab are loaded
-// into registers while the current tile is multiplied, so two tiles of C are
-// in flight per workgroup.  Cb and Ub point at row 0 of the C block and of U;
-// both are addressed through the column map cm; U rows past jb read as 0.
-template <int KB, int G>
+// Tiles of C loaded ahead by the streaming updates.
+#ifndef UPD_DEPTH
+#define UPD_DEPTH 1
+#endif
+// C (64 rows x G column tiles) -= Lb (64 x KB) * U (KB x columns), one column
+// tile at a time, with sL holding -Lb: the MFMAs accumulate onto the loaded C
+// values.  The C values of the next two tiles and the U slab of the next tile
+// are loaded into registers while the current tile is multiplied, so three
+// tiles of C are in flight per workgroup.  Cb and Ub point at row 0 of the C
+// block and of U; both are addressed through the column map cm; U rows past jb
+// read as 0.
+template <int KB, int G, int DEPTH = UPD_DEPTH>
 __device__ __forceinline__ void rowblock_update(const double (*sL)[Pitch<KB>::A], double (*sU)[PB], int mrem,
                                                 int vbeg, int ncols, ColMap cm, double *Cb, const double *Ub, int jb,
                                                 long ld) {
@@ -627,24 +634,25 @@ __device__ __forceinline__ void rowblock_update(const double (*sL)[Pitch<KB>::A]
         for (int v = 0; v < 4; ++v)
           dst[(h * 2 + c) * 4 + v] = (rok[h * 4 + v] && cok[c]) ? Cb[rowoff[h * 4 + v] + col[c]] : 0.0;
   };
-  double nu[NU], cv[16], cn[16];
-  loadU(vbeg, nu);
-  loadC(vbeg, cv);
-  for (int g = 0; g < G; ++g) {
+  const int ntile = min(G, (ncols - vbeg + TILE - 1) / TILE);
+  double nu[NU], ca[16], cb[16];
+  if (ntile > 0) {
+    loadU(vbeg, nu);
+    loadC(vbeg, ca);
+  }
+  if (DEPTH > 1 && ntile > 1) loadC(vbeg + TILE, cb);
+  // tile g: its C values are in cur, which then receives tile g + DEPTH
+  auto step = [&](int g, double (&cur)[16]) {
     const int v0 = vbeg + g * TILE;
-    if (v0 >= ncols) break;
 #pragma unroll
     for (int q = 0; q < NU; ++q) sU[ku0 + 4 * q][ju] = nu[q];
     __syncthreads();
-    const bool more = g + 1 < G && v0 + TILE < ncols;
-    if (more) {
-      loadU(v0 + TILE, nu);
-      loadC(v0 + TILE, cn);
-    }
     d4 acc[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = d4{0, 0, 0, 0};
-    mfma_slab<KB>(sL, sU, acc, wr, wc, kk, ii);
+    for (int q = 0; q < 4; ++q) acc[q] = d4{cur[4 * q], cur[4 * q + 1], cur[4 * q + 2], cur[4 * q + 3]};
+    if (g + 1 < ntile) loadU(v0 + TILE, nu);
+    if (g + DEPTH < ntile) loadC(v0 + DEPTH * TILE, cur);
+    mfma_slab<KB, 4>(sL, sU, acc, wr, wc, kk, ii);
     long col[2];
     bool cok[2];
     cols(v0, col, cok);
@@ -654,11 +662,12 @@ __device__ __forceinline__ void rowblock_update(const double (*sL)[Pitch<KB>::A]
       for (int c = 0; c < 2; ++c)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          if (rok[h * 4 + v] && cok[c]) Cb[rowoff[h * 4 + v] + col[c]] = cv[(h * 2 + c) * 4 + v] - acc[h * 2 + c][v];
-    if (more)
-#pragma unroll
-      for (int q = 0; q < 16; ++q) cv[q] = cn[q];
+          if (rok[h * 4 + v] && cok[c]) Cb[rowoff[h * 4 + v] + col[c]] = acc[h * 2 + c][v];
     __syncthreads();
+  };
+  for (int g = 0; g < ntile; g += DEPTH) {
+    step(g, ca);
+    if (DEPTH > 1 && g + 1 < ntile) step(g + 1, cb);
   }
 }
 
@@ -672,7 +681,7 @@ template <int KB>
 __global__ __launch_bounds__(256, 2) void k_lu_update(int p0, const int *__restrict__ dims, double *__restrict__ aug,
                                                    long ldaug, long strideA, long roff, int tiles_m, int groups,
                                                    int ne, int with_rhs, int vlimit, int lower) {
-  __shared__ double sL[TILE][Pitch<KB>::A];  // sL[i][k] = L21[r0 + i][k]
+  __shared__ double sL[TILE][Pitch<KB>::A];  // sL[i][k] = -L21[r0 + i][k]
   __shared__ double sU[KB][PB];              // sU[k][j] = U12[k][v0 + j]
   for_items(ne, tiles_m * groups, [&](int e, int it) {
     const int tmi = it % tiles_m, g = it / tiles_m;
@@ -690,7 +699,7 @@ __global__ __launch_bounds__(256, 2) void k_lu_update(int p0, const int *__restr
     double *A = aug + (size_t)e * strideA;
     for (int idx = threadIdx.x; idx < KB * TILE; idx += 256) {
       const int i = idx / KB, k = idx % KB;
-      sL[i][k] = (r0 + i < m && k < jb) ? A[(size_t)(c0 + r0 + i) * ldaug + p0 + k] : 0.0;
+      sL[i][k] = (r0 + i < m && k < jb) ? -A[(size_t)(c0 + r0 + i) * ldaug + p0 + k] : 0.0;
     }
     rowblock_update<KB, UPD_G>(sL, sU, m - r0, vbeg, ncols, ColMap{acols, c0, roff}, A + (size_t)(c0 + r0) * ldaug,
                                A + (size_t)p0 * ldaug, jb, ldaug);
@@ -752,7 +761,7 @@ template <int KB>
 __global__ __launch_bounds__(256, 2) void k_bs_update(int j0, const int *__restrict__ dims, double *__restrict__ aug,
                                                    long ldaug, long strideA, long roff, int tiles_m, int groups,
                                                    int ne, int tail) {
-  __shared__ double sU[TILE][Pitch<KB>::A];  // sU[i][k] = U[r0 + i][j0 + k]
+  __shared__ double sU[TILE][Pitch<KB>::A];  // sU[i][k] = -U[r0 + i][j0 + k]
   __shared__ double sY[KB][PB];              // sY[k][j] = Y[j0 + k][q0 + j]
   for_items(ne, tiles_m * groups, [&](int e, int it) {
     const int tmi = it % tiles_m, g = it / tiles_m;
@@ -765,7 +774,7 @@ __global__ __launch_bounds__(256, 2) void k_bs_update(int j0, const int *__restr
     double *A = aug + (size_t)e * strideA;
     for (int idx = threadIdx.x; idx < KB * TILE; idx += 256) {
       const int i = idx / KB, k = idx % KB;
-      sU[i][k] = (r0 + i < j0 && k < jb) ? A[(size_t)(r0 + i) * ldaug + j0 + k] : 0.0;
+      sU[i][k] = (r0 + i < j0 && k < jb) ? -A[(size_t)(r0 + i) * ldaug + j0 + k] : 0.0;
     }
     rowblock_update<KB, UPD_G>(sU, sY, j0 - r0, qbeg, rhs, ColMap{0, 0, roff}, A + (size_t)r0 * ldaug,
                                A + (size_t)j0 * ldaug, jb, ldaug);

@@ -40,9 +40,10 @@ def rform_source_sha() -> str:
 
 
 def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE summary (already scaled by the copy-kernel calibration), or None
-    if there is none or the kernel's sources changed since it was taken."""
+    """HBM bytes per launch of `kernel` (name and tile shape, e.g. "k_rform_f32
+    tile=32x4") from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary
+    (already scaled by the copy-kernel calibration), or None if there is none or
+    the kernel's sources changed since it was taken."""
     import re
     try:
         text = open(TRAFFIC_FILE).read()
@@ -225,6 +226,8 @@ def main() -> int:
                     help="requests per mode in the serving measurement (0 = skip)")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the 200-channel and 64-wave batch throughput measurements")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default R tile shapes instead of running the tile autotuner first")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a 1 GiB read + 1 GiB write kernel (HBM counter calibration under rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -266,10 +269,13 @@ def main() -> int:
     results = {}
     for name, prec in modes:
         # tile autotuner: time every R tile shape on a slice of the grid, keep the fastest
-        tune_ms = ctx.tune(prec, [pid], E[::4][:256], reps=1)[0]
+        tune_ms = None
+        if not args.no_tune:
+            tune_ms = ctx.tune(prec, [pid], E[::4][:256], reps=1)[0].tolist()
         shape = ctx.get_tile(prec, rm.tile_bucket(pw.nchan))
         tile = rm.tile_shapes(prec)[shape]
-        log(f"{name}: tile shapes {rm.tile_shapes(prec)} tuned at {np.round(tune_ms, 1).tolist()} ms -> {tile}")
+        log(f"{name}: tile shapes {rm.tile_shapes(prec)} tuned at "
+            f"{[round(x, 1) for x in tune_ms] if tune_ms else 'default'} ms -> {tile}")
         for _ in range(args.warmup):
             ctx.run(pid, Ed, prec=prec, want_K=False, out=(om, None, st))
         torch.cuda.synchronize()
@@ -289,11 +295,11 @@ def main() -> int:
         rf_ms, rf_n, rf_e = stages["rform"]
         achieved = flops_R * rf_e / (rf_ms * 1e-3) / 1e12 if rf_ms > 0 else None
         dt = "f32" if prec == rm.FP32_SPLIT else "f64"
-        kname = "k_rform_f32" if dt == "f32" else "k_rform_f64"
+        kname = ("k_rform_f32" if dt == "f32" else "k_rform_f64") + f" tile={tile[0]}x{tile[1]}"
         results[name] = dict(
             value=E.size * args.steps / (t2 - t1), ms_per_step=ms_step,
             flagged_energies=int((stat != 0).sum()),
-            tile=dict(side=tile[0], energies_per_task=tile[1], tuned_ms=tune_ms.tolist()),
+            tile=dict(side=tile[0], energies_per_task=tile[1], tuned_ms=tune_ms),
             stage_ms_per_step={s: v[0] / args.steps for s, v in stages.items()},
             roofline=dict(bound="mfma", achieved=achieved, peak=PEAK[dt], unit="TFLOP/s",
                           frac=(achieved / PEAK[dt]) if achieved else None, traffic=measured_traffic(kname),

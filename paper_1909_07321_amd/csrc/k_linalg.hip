@@ -441,24 +441,28 @@ __global__ __launch_bounds__(64) void k_lu_blockperm(int p0, const int *__restri
 
 // Triangular solve for the trailing columns of an outer block, U12 = L11^-1 P A12,
 // as a product with the block's explicit inverse (k_lu_blockinv) on FP64 MFMA.
-// Each workgroup owns 64 trailing columns: it gathers their block rows from the
-// source rows of the net permutation into LDS and loads the rows that move out
-// of the block into registers (every load before any store), writes the moved
-// rows, then forms the 64 x 64 product.
+// Each workgroup owns 64 trailing columns at a time: it gathers their block
+// rows from the source rows of the net permutation and loads the rows that
+// move out of the block (every load of a tile before any of its stores),
+// writes the moved rows, then forms the 64 x 64 product.  The loads of the
+// next tile (other columns, untouched by this tile's stores) are issued before
+// this tile is multiplied and have completed, in every thread, before the
+// next tile's first store.
 constexpr int TRSM_G = 8;
 __global__ __launch_bounds__(256) void k_lu_trsm_inv(int p0, const int *__restrict__ dims, double *__restrict__ aug,
                                                      long ldaug, long strideA, long roff,
                                                      const int *__restrict__ bperm, const double *__restrict__ linv,
                                                      int tiles_n, int ne) {
   constexpr int KB = NBU;
+  constexpr int NY = KB * TILE / 256;      // gathered and moved elements per thread
   __shared__ double sL[KB][Pitch<KB>::A];  // sL[i][k] = Linv[i][k]
   __shared__ double sX[KB][PB];            // sX[k][j] = (P A12)[k][v0 + j]
   __shared__ int sp[1 + 3 * KB];
-  __shared__ long scol[TILE];
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int kk = lane >> 4, ii = lane & 15;
+  const int jt = t % TILE, kt = t / TILE;  // this thread's column and first row of a tile (rows kt + 4q)
   // an item is a group of TRSM_G column tiles of one energy: L11^-1 and the
   // permutation are staged once for the group
   for_items(ne, (tiles_n + TRSM_G - 1) / TRSM_G, [&](int e, int grp) {
@@ -467,53 +471,63 @@ __global__ __launch_bounds__(256) void k_lu_trsm_inv(int p0, const int *__restri
     const int jb = min(KB, rows - p0);
     const int c0 = p0 + jb;
     const int ncols = (rows - c0) + rhs;
-    if (grp * TRSM_G * TILE >= ncols) return;
+    const int vfirst = grp * TRSM_G * TILE;
+    if (vfirst >= ncols) return;
+    const int ntile = min(TRSM_G, (ncols - vfirst + TILE - 1) / TILE);
     double *A = aug + (size_t)e * strideA;
     const int *pm = bperm + (size_t)e * BPERM;
     const double *Li = linv + (size_t)e * KB * KB;
     for (int idx = t; idx < 1 + 3 * KB; idx += 256) sp[idx] = pm[idx];
     for (int idx = t; idx < KB * KB; idx += 256) sL[idx / KB][idx % KB] = Li[idx];
-    for (int g = 0; g < TRSM_G; ++g) {
-      const int v0 = (grp * TRSM_G + g) * TILE;
-      if (v0 >= ncols) break;
-      if (t < TILE) scol[t] = v0 + t < ncols ? vcol(v0 + t, rows, c0, roff) : -1;
+    __syncthreads();
+    const int nout = sp[0];
+    double xv[NY], yv[NY];
+    auto load = [&](int v0) {
+      const bool ok = v0 + jt < ncols;
+      const long col = ok ? vcol(v0 + jt, rows, c0, roff) : 0;
+#pragma unroll
+      for (int q = 0; q < NY; ++q) {
+        const int k = kt + 4 * q;
+        xv[q] = (ok && k < jb) ? A[(size_t)sp[1 + k] * ldaug + col] : 0.0;
+        yv[q] = (ok && k < nout) ? A[(size_t)sp[1 + KB + k] * ldaug + col] : 0.0;
+      }
+    };
+    load(vfirst);
+    // every load of a tile completes before any store of that tile: the moved
+    // rows' destinations are gather sources of the same columns
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int g = 0; g < ntile; ++g) {
+      const int v0 = vfirst + g * TILE;
+      {
+        const bool ok = v0 + jt < ncols;
+        const long col = ok ? vcol(v0 + jt, rows, c0, roff) : 0;
+#pragma unroll
+        for (int q = 0; q < NY; ++q) {
+          const int k = kt + 4 * q;
+          sX[k][jt] = xv[q];
+          if (ok && k < nout) A[(size_t)sp[1 + 2 * KB + k] * ldaug + col] = yv[q];
+        }
+      }
       __syncthreads();
-      const int nout = sp[0];
-      for (int idx = t; idx < KB * TILE; idx += 256) {
-        const int k = idx / TILE, j = idx % TILE;
-        const long col = scol[j];
-        sX[k][j] = (k < jb && col >= 0) ? A[(size_t)sp[1 + k] * ldaug + col] : 0.0;
-      }
-      constexpr int NY = KB * TILE / 256;
-      double yv[NY];
-#pragma unroll
-      for (int q = 0; q < NY; ++q) {
-        const int idx = t + 256 * q, k = idx / TILE, j = idx % TILE;
-        const long col = scol[j];
-        yv[q] = (k < nout && col >= 0) ? A[(size_t)sp[1 + KB + k] * ldaug + col] : 0.0;
-      }
-      __syncthreads();  // every load of the workgroup has completed
-#pragma unroll
-      for (int q = 0; q < NY; ++q) {
-        const int idx = t + 256 * q, k = idx / TILE, j = idx % TILE;
-        const long col = scol[j];
-        if (k < nout && col >= 0) A[(size_t)sp[1 + 2 * KB + k] * ldaug + col] = yv[q];
-      }
+      if (g + 1 < ntile) load(v0 + TILE);
       d4 acc[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) acc[q] = d4{0, 0, 0, 0};
       mfma_slab<KB>(sL, sX, acc, wr, wc, kk, ii);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const long col = scol[wc * 32 + (q & 1) * 16 + ii];
-        if (col < 0) continue;
+        const int v = v0 + wc * 32 + (q & 1) * 16 + ii;
+        if (v >= ncols) continue;
+        const long col = vcol(v, rows, c0, roff);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = wr * 32 + (q >> 1) * 16 + 4 * v + kk;
-          if (i < jb) A[(size_t)(p0 + i) * ldaug + col] = acc[q][v];
+        for (int r = 0; r < 4; ++r) {
+          const int i = wr * 32 + (q >> 1) * 16 + 4 * r + kk;
+          if (i < jb) A[(size_t)(p0 + i) * ldaug + col] = acc[q][r];
         }
       }
-      __syncthreads();  // LDS is reused by the next tile
+      __builtin_amdgcn_s_waitcnt(0);  // this thread's loads of the next tile have completed
+      __syncthreads();                // and LDS is reused by the next tile
     }
   });
 }
@@ -709,7 +723,9 @@ __global__ __launch_bounds__(256, 2) void k_lu_update(int p0, const int *__restr
 // Back substitution, diagonal block: Y_b = U_bb^-1 B_b for the right-hand sides,
 // one thread per right-hand side with its column in registers and U_bb in LDS
 // (column-oriented: each solved entry is eliminated from the rows above it).
-constexpr int BS_G = 4;
+// A workgroup of BS_T threads (several waves share one staged U_bb) takes BS_G
+// groups of BS_T right-hand sides per item.
+constexpr int BS_T = 256, BS_G = 1;
 template <int KB, int T>
 __global__ __launch_bounds__(T) void k_bs_block(int j0, const int *__restrict__ dims, double *__restrict__ aug,
                                                 long ldaug, long strideA, long roff, int tiles, int ne, int tail) {
@@ -871,12 +887,11 @@ void launch_lu_solve(hipStream_t s, int ne, int maxrows, int maxrhs, const int *
 // rows from the bottom).
 void launch_backsub(hipStream_t s, int ne, int maxrows, int maxrhs, const int *dims, double *aug, long ldaug,
                     long strideA, long roff, int tail) {
-  constexpr int T64 = 64;
   if (maxrhs <= 0) return;
   for (int j0 = (maxrows - 1) / NBU * NBU; j0 >= 0; j0 -= NBU) {
-    const int tb = (maxrhs + T64 - 1) / T64;
-    hipLaunchKernelGGL((k_bs_block<NBU, T64>), dim3(persist_grid(k_bs_block<NBU, T64>, T64, ne, (tb + BS_G - 1) / BS_G)),
-                       dim3(T64), 0, s,
+    const int tb = (maxrhs + BS_T - 1) / BS_T;
+    hipLaunchKernelGGL((k_bs_block<NBU, BS_T>),
+                       dim3(persist_grid(k_bs_block<NBU, BS_T>, BS_T, ne, (tb + BS_G - 1) / BS_G)), dim3(BS_T), 0, s,
                        j0, dims, aug, ldaug, strideA, roff, tb, ne, tail);
     if (j0 == 0) break;
     const int tm = (j0 + TILE - 1) / TILE, gr = (maxrhs + UPD_G * TILE - 1) / (UPD_G * TILE);

@@ -686,7 +686,10 @@ __device__ __forceinline__ void rowblock_update(const double (*sL)[Pitch<KB>::A]
 }
 
 // Column tiles per workgroup of the streaming updates.
-constexpr int UPD_G = 64;
+#ifndef RM_UPD_G
+#define RM_UPD_G 64
+#endif
+constexpr int UPD_G = RM_UPD_G;
 
 // Trailing update A22 -= L21 U12 for the block of kb columns starting at p0:
 // rows [c0, rows) with c0 = p0 + jb, trailing columns as in trailing_cols.
@@ -1095,12 +1098,16 @@ void launch_chol_forward(hipStream_t s, int ne, int maxrows, int maxrhs, const i
 // Small batched GEMM, C = A B (square no x no per energy), FP64 MFMA.
 // ---------------------------------------------------------------------------
 // FORMP: C = 1 + A B, and A (= K) copied to C's right-hand-side columns at roff.
+// K slab of the batched products.
+#ifndef RM_GEMM_GK
+#define RM_GEMM_GK 32
+#endif
 template <bool TA, bool LOWER, bool MIRROR, bool FORMP = false>
 __global__ __launch_bounds__(256) void k_gemm_sq(const int *__restrict__ nopen, const double *__restrict__ A,
                                                  long lda, long sA, const double *__restrict__ B, long ldb,
                                                  long sB, double *__restrict__ C, long ldc, long sC,
                                                  int tiles_n, int ne, long roff = 0) {
-  constexpr int GK = 32;
+  constexpr int GK = RM_GEMM_GK;
   constexpr int NL = TILE * GK / 256;  // slab elements per thread (A and B each)
   __shared__ double sa[TILE][Pitch<GK>::A];  // sa[i][k] = A[r0 + i][k0 + k]
   __shared__ double sb[GK][PB];              // sb[k][j] = B[k0 + k][q0 + j]

@@ -129,6 +129,12 @@ template <typename T> __device__ __forceinline__ const T *amplitudes(const DevPW
 template <> __device__ __forceinline__ const double *amplitudes<double>(const DevPW &p) { return p.W64; }
 template <> __device__ __forceinline__ const float *amplitudes<float>(const DevPW &p) { return p.W32; }
 
+// Global-memory view of a pointer read from a table: loads through it are
+// global loads, which count only against vmcnt (a generic pointer gives flat
+// loads, which also count against lgkmcnt, so every wait for an LDS read would
+// wait for the next stage's amplitudes as well).
+template <typename T> using GlobalPtr = const T __attribute__((address_space(1))) *;
+
 // One wave's LDS region.
 template <typename T, int KW, int EB, int RTW> struct WaveLds {
   T a[KW][RTW];
@@ -168,13 +174,14 @@ __device__ __forceinline__ void rform_task(const T *__restrict__ W, int ldw, int
 
   TV ra[NVEC], rb[NVEC];
   T rd[ND];
+  const GlobalPtr<TV> Wg = (GlobalPtr<TV>)W;  // ldw and the tile offsets are multiples of VEC
   auto gload = [&](int k0) {
 #pragma unroll
     for (int r = 0; r < NVEC; ++r) {
       const int idx = lane + 64 * r;
       const int row = idx / PER_ROW, c = (idx % PER_ROW) * VEC;
-      ra[r] = *reinterpret_cast<const TV *>(W + (size_t)(k0 + row) * ldw + i0 + c);
-      if (!DIAG) rb[r] = *reinterpret_cast<const TV *>(W + (size_t)(k0 + row) * ldw + j0 + c);
+      ra[r] = Wg[((size_t)(k0 + row) * ldw + i0 + c) / VEC];
+      if (!DIAG) rb[r] = Wg[((size_t)(k0 + row) * ldw + j0 + c) / VEC];
     }
 #pragma unroll
     for (int r = 0; r < ND; ++r) {

@@ -1192,9 +1192,117 @@ void launch_gemm_sq(hipStream_t s, int ne, int maxn, const int *nopen, const dou
 
 // [1 + K K | K] for the S/Omega stage: the lower block tiles of 1 + K K and all
 // of K in the right-hand-side columns.
+// Products of the S/Omega stage in 128 x 128 tiles (k_gemm128) or 64 x 64 tiles (k_gemm_sq).
+#ifndef RM_GEMM128
+#define RM_GEMM128 1
+#endif
+// The same products in 128 x 128 output tiles with eight waves per workgroup,
+// each owning a 64 x 32 block (4 x 2 MFMA blocks): half the operand traffic of
+// k_gemm_sq per output element at two waves per SIMD.  K slabs of 16 are
+// staged through LDS with the next slab loaded into registers while the
+// current one is multiplied.  Each element sums over k in the same order as
+// k_gemm_sq (one MFMA step per 4 k, ascending).
+template <bool TA, bool LOWER, bool MIRROR, bool FORMP = false>
+__global__ __launch_bounds__(512, 1) void k_gemm128(const int *__restrict__ nopen, const double *__restrict__ A,
+                                                    long lda, long sA, const double *__restrict__ B, long ldb,
+                                                    long sB, double *__restrict__ C, long ldc, long sC, int tiles_n,
+                                                    int ne, long roff = 0) {
+  constexpr int BT = 2 * TILE, GK = 16, NT = 512;
+  constexpr int NL = BT * GK / NT;         // slab elements per thread (A and B each)
+  __shared__ double sa[BT][Pitch<GK>::A];  // sa[i][k] = op(A)[r0 + i][k0 + k]
+  __shared__ double sb[GK][BT];            // sb[k][j] = B[k0 + k][q0 + j]
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wr = wave >> 2, wc = wave & 3;  // 2 x 4 waves: rows wr*64, columns wc*32
+  const int kk = lane >> 4, ii = lane & 15;
+  for_items(ne, tiles_n * tiles_n, [&](int e, int it) {
+    const int n = nopen[e];
+    const int tm = it / tiles_n, tn = it % tiles_n;
+    const int r0 = tm * BT, q0 = tn * BT;
+    if (r0 >= n || q0 >= n || (LOWER && tn > tm)) return;
+    const double *Ae = A + (size_t)e * sA;
+    const double *Be = B + (size_t)e * sB;
+    double *Ce = C + (size_t)e * sC;
+    double ra[NL], rb[NL];
+    auto gload = [&](int k0) {
+#pragma unroll
+      for (int q = 0; q < NL; ++q) {
+        const int idx = t + NT * q;
+        if (TA) {
+          // op(A)(i, k) = A[k][i]; lanes run along i so the load is contiguous
+          const int ia = idx % BT, ka = idx / BT;
+          ra[q] = (r0 + ia < n && k0 + ka < n) ? Ae[(size_t)(k0 + ka) * lda + r0 + ia] : 0.0;
+        } else {
+          const int i = idx / GK, k = idx % GK;
+          ra[q] = (r0 + i < n && k0 + k < n) ? Ae[(size_t)(r0 + i) * lda + k0 + k] : 0.0;
+        }
+        const int kb = idx / BT, j = idx % BT;
+        rb[q] = (q0 + j < n && k0 + kb < n) ? Be[(size_t)(k0 + kb) * ldb + q0 + j] : 0.0;
+      }
+    };
+    d4 acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = d4{0, 0, 0, 0};
+    gload(0);
+    for (int k0 = 0; k0 < n; k0 += GK) {
+#pragma unroll
+      for (int q = 0; q < NL; ++q) {
+        const int idx = t + NT * q;
+        if (TA)
+          sa[idx % BT][idx / BT] = ra[q];
+        else
+          sa[idx / GK][idx % GK] = ra[q];
+        sb[idx / BT][idx % BT] = rb[q];
+      }
+      __syncthreads();
+      if (k0 + GK < n) gload(k0 + GK);
+#pragma unroll
+      for (int ks = 0; ks < GK; ks += 4) {
+        double a[4], b[2];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) a[m] = sa[wr * 64 + m * 16 + ii][ks + kk];
+#pragma unroll
+        for (int m = 0; m < 2; ++m) b[m] = sb[ks + kk][wc * 32 + m * 16 + ii];
+#pragma unroll
+        for (int mr = 0; mr < 4; ++mr)
+#pragma unroll
+          for (int mc = 0; mc < 2; ++mc) acc[mr * 2 + mc] = mfma64(a[mr], b[mc], acc[mr * 2 + mc]);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int mr = 0; mr < 4; ++mr)
+#pragma unroll
+      for (int mc = 0; mc < 2; ++mc) {
+        const int j = q0 + wc * 32 + mc * 16 + ii;
+        if (j >= n) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = r0 + wr * 64 + mr * 16 + 4 * v + kk;
+          if (i < n) {
+            const double x = acc[mr * 2 + mc][v];
+            Ce[(size_t)i * ldc + j] = FORMP && i == j ? 1.0 + x : x;
+            if (MIRROR && tm != tn) Ce[(size_t)j * ldc + i] = x;
+            if (FORMP) {
+              Ce[(size_t)i * ldc + roff + j] = Ae[(size_t)i * lda + j];
+              if (tm != tn) Ce[(size_t)j * ldc + roff + i] = Ae[(size_t)j * lda + i];
+            }
+          }
+        }
+      }
+  });
+}
+
 void launch_formP(hipStream_t s, int ne, int maxn, const int *nopen, const double *K, long ldk, long sK, double *aug,
                   long ldaug, long sA, long roff) {
   if (maxn <= 0) return;
+  if (RM_GEMM128) {
+    const int tn = (maxn + 2 * TILE - 1) / (2 * TILE);
+    hipLaunchKernelGGL((k_gemm128<false, true, false, true>),
+                       dim3(persist_grid(k_gemm128<false, true, false, true>, 512, ne, (long)tn * tn)), dim3(512), 0, s,
+                       nopen, K, ldk, sK, K, ldk, sK, aug, ldaug, sA, tn, ne, roff);
+    return;
+  }
   const int tn = (maxn + TILE - 1) / TILE;
   hipLaunchKernelGGL((k_gemm_sq<false, true, false, true>), dim3(persist_grid(k_gemm_sq<false, true, false, true>, 256,
                      ne, (long)tn * tn)), dim3(256), 0, s, nopen, K, ldk, sK, K, ldk, sK, aug, ldaug, sA, tn, ne, roff);
@@ -1213,6 +1321,12 @@ void launch_gemm_lower(hipStream_t s, int ne, int maxn, const int *nopen, const 
 void launch_gemm_ata(hipStream_t s, int ne, int maxn, const int *nopen, const double *A, long lda, long sA,
                      double *C, long ldc, long sC) {
   if (maxn <= 0) return;
+  if (RM_GEMM128) {
+    const int tn = (maxn + 2 * TILE - 1) / (2 * TILE);
+    hipLaunchKernelGGL((k_gemm128<true, true, true>), dim3(persist_grid(k_gemm128<true, true, true>, 512, ne,
+                       (long)tn * tn)), dim3(512), 0, s, nopen, A, lda, sA, A, lda, sA, C, ldc, sC, tn, ne);
+    return;
+  }
   const int tn = (maxn + TILE - 1) / TILE;
   hipLaunchKernelGGL((k_gemm_sq<true, true, true>), dim3(persist_grid(k_gemm_sq<true, true, true>, 256, ne,
                      (long)tn * tn)), dim3(256), 0, s, nopen, A, lda, sA, A, lda, sA, C, ldc, sC, tn, ne);

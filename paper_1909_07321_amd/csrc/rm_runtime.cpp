@@ -17,6 +17,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <cstdio>
+#include <cctype>
 #include <cstdlib>
 #include <cstring>
 #include <deque>
@@ -1539,31 +1540,48 @@ rm_status rm_tune_load(rm_ctx *ctx, const char *cache_path) {
     ctx->err = std::string("tile cache: ") + why;
     return RM_E_ARG;
   };
-  // integer value of "key": at or after position `from`; false if absent
+  // integer value of "key" (JSON: optional blanks around the colon) within
+  // [from, to); false if absent
   auto intval = [&](const char *key, size_t from, size_t to, long &out) {
-    const std::string k = std::string("\"") + key + "\":";
+    const std::string k = std::string("\"") + key + "\"";
     const size_t at = text.find(k, from);
     if (at == std::string::npos || at >= to) return false;
-    const char *p = text.c_str() + at + k.size();
+    size_t p = at + k.size();
+    while (p < to && std::isspace((unsigned char)text[p])) ++p;
+    if (p >= to || text[p] != ':') return false;
+    const char *c = text.c_str() + p + 1;
     char *end = nullptr;
-    out = std::strtol(p, &end, 10);
-    return end != p;
+    out = std::strtol(c, &end, 10);
+    return end != c && (size_t)(end - text.c_str()) <= to;
+  };
+  // string value of "key"
+  auto strval = [&](const char *key, std::string &out) {
+    const std::string k = std::string("\"") + key + "\"";
+    const size_t at = text.find(k);
+    if (at == std::string::npos) return false;
+    size_t p = at + k.size();
+    while (p < text.size() && std::isspace((unsigned char)text[p])) ++p;
+    if (p >= text.size() || text[p] != ':') return false;
+    p = text.find('"', p + 1);
+    if (p == std::string::npos) return false;
+    const size_t q = text.find('"', p + 1);
+    if (q == std::string::npos) return false;
+    out = text.substr(p + 1, q - p - 1);
+    return true;
   };
   long v = 0;
   if (!intval("rm_tile_cache", 0, text.size(), v) || v != 1) return bad("not a tile cache of this version");
-  const std::string ak = "\"arch\": \"";
-  const size_t a0 = text.find(ak);
-  if (a0 == std::string::npos) return bad("no architecture");
-  const size_t a1 = text.find('"', a0 + ak.size());
-  if (a1 == std::string::npos || text.substr(a0 + ak.size(), a1 - a0 - ak.size()) != ctx->arch)
-    return bad("made on a device of another architecture");
+  std::string arch;
+  if (!strval("arch", arch)) return bad("no architecture");
+  if (arch != ctx->arch) return bad("made on a device of another architecture");
   if (!intval("cus", 0, text.size(), v) || v != ctx->ncu) return bad("made on a device with another compute-unit count");
+  // entries: every object that holds a "prec" key
   std::vector<std::array<int, 3>> set;
-  for (size_t pos = text.find("{\"prec\":"); pos != std::string::npos; pos = text.find("{\"prec\":", pos + 1)) {
-    const size_t end = text.find('}', pos);
-    if (end == std::string::npos) return bad("unterminated entry");
+  for (size_t pos = text.find("\"prec\""); pos != std::string::npos; pos = text.find("\"prec\"", pos + 1)) {
+    const size_t b = text.rfind('{', pos), end = text.find('}', pos);
+    if (b == std::string::npos || end == std::string::npos) return bad("entry outside an object");
     long prec, bucket, shape;
-    if (!intval("prec", pos, end, prec) || !intval("bucket", pos, end, bucket) || !intval("shape", pos, end, shape))
+    if (!intval("prec", b, end, prec) || !intval("bucket", b, end, bucket) || !intval("shape", b, end, shape))
       return bad("entry without prec, bucket or shape");
     if (rm_tile_count((int32_t)prec) == 0 || bucket < 0 || bucket >= NBUCKET || shape < 0 ||
         shape >= rm_tile_count((int32_t)prec))

@@ -62,3 +62,38 @@ def test_graph_replays_equal_direct(rm, waves, prec):
         om_noK, K_none, st_noK = ctx.run(ids[2], E, prec=prec, want_K=False)
         assert K_none is None
         assert np.array_equal(om_noK, direct[0], equal_nan=True) and np.array_equal(st_noK, direct[2])
+
+
+def test_graph_recapture_on_shape_change(rm, waves):
+    """Chunks of new shapes (more energies, so the workspace grows and moves)
+    recapture their graphs; going back to an old shape is correct too."""
+    pws, E = waves
+    with rm.Context(0) as ctx:
+        pid = ctx.pw_upload(pws[1])
+        blocks = [E[:7], np.linspace(0.02, 5.9, 300), E[:7], E[::2]]
+        ctx.set_graph(False)
+        ref = [ctx.run(pid, b, prec=1) for b in blocks]
+        ctx.set_graph(True)
+        for rep in range(2):
+            for b, (om0, K0, st0) in zip(blocks, ref):
+                om, K, st = ctx.run(pid, b, prec=1)
+                print(f"rep {rep} ne={b.size}: captures/replays {ctx.graph_stats()}", flush=True)
+                assert np.array_equal(om, om0, equal_nan=True) and np.array_equal(K, K0, equal_nan=True)
+                assert np.array_equal(st, st0)
+
+
+def test_tile_and_graph_argument_errors(rm, waves):
+    pws, E = waves
+    with rm.Context(0) as ctx:
+        with pytest.raises(rm.RMError):
+            ctx.set_tile(0, rm.NBUCKET, 0)
+        with pytest.raises(rm.RMError):
+            ctx.set_tile(1, 0, len(rm.tile_shapes(1)))
+        with pytest.raises(rm.RMError):
+            ctx.get_tile(5, 0)
+        with pytest.raises(rm.RMError):
+            ctx.tune(0, [12345], E[:4])  # unknown partial wave
+        pid = ctx.pw_upload(pws[0])
+        with pytest.raises(rm.RMError):
+            ctx.tune(0, [pid], E[:4], reps=0)
+        assert ctx.get_tile(0, rm.tile_bucket(pws[0].nchan)) == 0  # nothing changed

@@ -120,6 +120,13 @@ def test_tune_and_cache(rm, ctx, waves, tmp_path):
                     assert [c2.get_tile(prec, b) for b in range(rm.NBUCKET)] == state
                 with pytest.raises(rm.RMError):
                     c2.tune_load(str(tmp_path / "missing.json"))
+                # any JSON layout of the same content loads the same choices
+                pretty = str(tmp_path / "pretty.json")
+                with open(pretty, "w") as f:
+                    f.write(json.dumps(doc, indent=2, separators=(" ,", " : ")))
+                c2.tune_load(pretty)
+                for (pr, b), sh in ent.items():
+                    assert c2.get_tile(pr, b) == sh
     finally:
         for i in ids:
             ctx.pw_release(i)

@@ -233,8 +233,8 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(each partial wave and energy is independent; see DESIGN.md for how it would shard)",
+        print("bench.py measures one GPU; there is no multi-GPU path "
+              "(each partial wave and energy is independent, so points would be dealt out over GPUs; that is not built)",
               file=sys.stderr)
         return 2
 

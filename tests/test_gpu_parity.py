@@ -238,3 +238,33 @@ def test_unknown_pw_and_bad_args(ctx):
     from paper_1909_07321_amd import rm
     with pytest.raises(rm.RMError):
         ctx.run(12345, np.array([1.0]))
+
+
+def test_upload_rejects_bad_waves(ctx):
+    """Descriptors the library must refuse before allocating anything: too many
+    channels, no poles, descending poles, a channel target out of range, and a
+    wave larger than the context's HBM budget."""
+    import math
+    from paper_1909_07321_amd import rm
+
+    def wave(n, M, Ek=None, target=None, ntarget=1):
+        # e_target has a spare entry so that an out-of-range target still forms e_thr on the host
+        return synth.PartialWave(n, M, ntarget, 8.0, 0.0, 1.0, 1.0, np.zeros(ntarget + 1),
+                                 np.zeros(n, np.int32),
+                                 np.zeros(n, np.int32) if target is None else target,
+                                 np.linspace(0.0, 1.0, M) if Ek is None else Ek,
+                                 np.ones((max(M, 1), n)) / math.sqrt(8.0))
+
+    bad = [wave(16385, 1),                                   # above RM_MAX_CHANNELS
+           wave(4, 0),                                       # no poles
+           wave(4, 3, Ek=np.array([1.0, 0.5, 2.0])),         # descending poles
+           wave(4, 3, target=np.array([0, 0, 1, 0], np.int32))]  # target 1 of 1 target
+    for pw in bad:
+        with pytest.raises(rm.RMError):
+            ctx.pw_upload(pw)
+    ok = wave(4, 3)
+    pid = ctx.pw_upload(ok)
+    ctx.pw_release(pid)
+    with rm.Context(0, hbm_budget_bytes=1 << 20) as small:  # 1 MiB
+        with pytest.raises(rm.RMError):
+            small.pw_upload(wave(512, 2048))

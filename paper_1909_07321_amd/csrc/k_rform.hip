@@ -135,11 +135,15 @@ template <> __device__ __forceinline__ const float *amplitudes<float>(const DevP
 // wait for the next stage's amplitudes as well).
 template <typename T> using GlobalPtr = const T __attribute__((address_space(1))) *;
 
-// One wave's LDS region.
+// One wave's LDS region.  The FP32 kernels keep one pole's scale factors of all
+// energies together (one wide LDS read per step serves every energy); the FP64
+// kernels keep each energy's factors together, which measured faster there.
 template <typename T, int KW, int EB, int RTW> struct WaveLds {
+  static constexpr bool DT = sizeof(T) == 4;
   T a[KW][RTW];
   T b[KW][RTW];
-  T d[EB][KW];
+  T d[DT ? KW : EB][DT ? EB : KW];
+  __device__ __forceinline__ T &dk(int e, int k) { return DT ? d[k][e] : d[e][k]; }
 };
 
 // One task: the tile with rows [i0, i0 + RTW) and columns [j0, j0 + RTW) for
@@ -202,7 +206,7 @@ __device__ __forceinline__ void rform_task(const T *__restrict__ W, int ldw, int
 #pragma unroll
     for (int r = 0; r < ND; ++r) {
       const int idx = lane + 64 * r;
-      if (idx < EB * KW) sm.d[idx / KW][idx % KW] = rd[r];
+      if (idx < EB * KW) sm.dk(idx / KW, idx % KW) = rd[r];
     }
   };
 
@@ -219,7 +223,7 @@ __device__ __forceinline__ void rform_task(const T *__restrict__ W, int ldw, int
       b[m] = DIAG ? a[m] : sm.b[kk][col[m]];
     }
 #pragma unroll
-    for (int e = 0; e < EB; ++e) d[e] = sm.d[e][kk];
+    for (int e = 0; e < EB; ++e) d[e] = sm.dk(e, kk);
 #pragma unroll
     for (int ks = 0; ks < KW; ks += 4) {
       T na[TM], nb[TM], nd[EB];
@@ -230,7 +234,7 @@ __device__ __forceinline__ void rform_task(const T *__restrict__ W, int ldw, int
           nb[m] = DIAG ? na[m] : sm.b[ks + 4 + kk][col[m]];
         }
 #pragma unroll
-        for (int e = 0; e < EB; ++e) nd[e] = sm.d[e][ks + 4 + kk];
+        for (int e = 0; e < EB; ++e) nd[e] = sm.dk(e, ks + 4 + kk);
       }
 #pragma unroll
       for (int e = 0; e < EB; ++e)

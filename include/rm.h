@@ -238,11 +238,13 @@ rm_status rm_get_tile(rm_ctx *ctx, int32_t prec, int32_t bucket, int32_t *shape)
 rm_status rm_set_tile(rm_ctx *ctx, int32_t prec, int32_t bucket, int32_t shape);
 /* Autotuner: times the R contraction (the d(E) vector and the persistent
    contraction launch) of every shape of prec on each resident partial wave
-   pw_ids[0 .. npw) for the ne host energies E (reps timed runs after one
-   warmup; the minimum counts), sums the times of the waves of each bucket, and
-   makes the fastest shape the context's choice for every bucket that holds one
-   of the waves (a shape other than shape 0 must be at least 3% faster than
-   shape 0: a chunk launches the contraction once per shape it uses).  ms (NULL or [npw][rm_tile_count(prec)]) receives the times.
+   pw_ids[0 .. npw) for the host energies E (the first ne, at most 256 and at
+   most what the HBM budget allows; reps timed runs after one warmup, the
+   minimum counts), sums the times of the waves of each bucket, and makes the
+   fastest shape the context's choice for every bucket that holds one of the
+   waves (a shape other than shape 0 must be at least 3% faster than shape 0:
+   a chunk launches the contraction once per shape it uses).  ms (NULL or
+   [npw][rm_tile_count(prec)]) receives the times.
    If cache_path is not NULL the choices are also written there (JSON, one
    entry per tuned bucket, with the device architecture and compute-unit count)
    for rm_tune_load.  Synchronous; RM_E_NOTFOUND for an unknown wave, RM_E_ARG

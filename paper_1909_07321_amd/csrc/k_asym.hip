@@ -104,15 +104,28 @@ __device__ bool cf2_value(double eta, double rho, int l, double &p, double &q) {
   return true;
 }
 
+// 1/m for the CF1 recursion (no division for its coefficients while m < INV_INT_N).
+constexpr int INV_INT_N = 1024;
+struct InvInts {
+  double v[INV_INT_N];
+  constexpr InvInts() : v() {
+    for (int m = 1; m < INV_INT_N; ++m) v[m] = 1.0 / (double)m;
+  }
+};
+__constant__ constexpr InvInts kInvInts{};
+
 __device__ double cf1_eval(double eta, double rho, int l, int Lmax, int &sign) {
-  double f = (double)(Lmax + 1) / rho;
+  const double irho = 1.0 / rho;
+  double f = (double)(Lmax + 1) * irho;
   int sg = 1;
   for (int L = Lmax - 1; L >= l; --L) {
     const double Lp = (double)(L + 1);
-    const double S = Lp / rho + eta / Lp;
+    const double iLp = L + 1 < INV_INT_N ? kInvInts.v[L + 1] : 1.0 / Lp;
+    const double S = Lp * irho + eta * iLp;
     const double den = S + f;
     if (den < 0) sg = -sg;
-    f = S - (1.0 + eta * eta / (Lp * Lp)) / den;
+    const double ei = eta * iLp;
+    f = S - (1.0 + ei * ei) / den;
   }
   sign = sg;
   return f;
@@ -125,6 +138,16 @@ __device__ bool cf1_value(double eta, double rho, int l, double &f, int &sign) {
   const double f2 = cf1_eval(eta, rho, l, l + extra + 64, s2);
   return fabs(f - f2) <= 1e-14 * fabs(f) + 1e-300 && s2 == sign;
 }
+
+// 1/((n + 1)(n + 2)) for the Taylor recurrence below (no division per term).
+constexpr int TAYLOR_MAX = 240;
+struct InvPairs {
+  double v[TAYLOR_MAX];
+  constexpr InvPairs() : v() {
+    for (int n = 0; n < TAYLOR_MAX; ++n) v[n] = 1.0 / ((double)(n + 1) * (double)(n + 2));
+  }
+};
+__constant__ constexpr InvPairs kInvPairs{};
 
 // Taylor steps of u'' = (L2/r^2 - 2 zz/r - ee) u from r0 inward to r1.  Terms are
 // carried as d_n = c_n h^n through the four-term recurrence obtained from
@@ -140,14 +163,14 @@ __device__ bool taylor_in(double zz, double ee, double L2, double r0, double r1,
     const double A = L2 - 2.0 * zz * r - ee * r * r;
     const double B = -(2.0 * zz + 2.0 * ee * r);
     const double C = -ee;
-    const double h2 = h * h, h3 = h2 * h, h4 = h2 * h2, rr = r * r;
+    const double h2 = h * h, h3 = h2 * h, h4 = h2 * h2, irr = 1.0 / (r * r);
     double dm2 = 0.0, dm1 = 0.0, d0 = u, d1 = up * h;
     double su = d0 + d1, sd = d1;
     int small = 0, nn;
-    for (nn = 0; nn < 240; ++nn) {
+    for (nn = 0; nn < TAYLOR_MAX; ++nn) {
       const double dn = ((A - (double)nn * (nn - 1)) * d0 * h2 - 2.0 * r * (double)nn * (nn + 1) * d1 * h +
-                         B * dm1 * h3 + C * dm2 * h4) /
-                        (rr * (double)(nn + 1) * (nn + 2));
+                         B * dm1 * h3 + C * dm2 * h4) *
+                        irr * kInvPairs.v[nn];
       su += dn;
       sd += (double)(nn + 2) * dn;
       dm2 = dm1;
@@ -160,7 +183,7 @@ __device__ bool taylor_in(double zz, double ee, double L2, double r0, double r1,
         small = 0;
       }
     }
-    if (nn >= 240) return false;
+    if (nn >= TAYLOR_MAX) return false;
     u = su;
     up = sd / h;
     if (renorm) {

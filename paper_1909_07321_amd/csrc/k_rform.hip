@@ -383,61 +383,68 @@ void launch_rform(hipStream_t s, const Lay &L, int split, int shape, const DevPW
 
 // ---------------------------------------------------------------------------
 // Near-pole correction of the split mode: R += 1/(2a) W[:, lo:hi] diag(1/(E_k - E))
-// W[:, lo:hi]^T in FP64, one workgroup per (lower tile, energy).  The window is
-// short (|E_k - E| < delta), so fragments are read straight from HBM/L2.
+// W[:, lo:hi]^T in FP64, one workgroup per (lower tile, NP_E consecutive
+// energies).  The window is short (|E_k - E| < delta), so fragments are read
+// straight from HBM/L2; the k loop is unrolled so that several steps' loads are
+// in flight together.
 // ---------------------------------------------------------------------------
+constexpr int NP_E = 4;
 __global__ __launch_bounds__(256) void k_nearpole(const DevPW *__restrict__ tab, const int *__restrict__ pwi,
-                                                  const double *__restrict__ E, const int *__restrict__ win,
+                                                  const double *__restrict__ E, const int *__restrict__ win, int ne,
                                                   double *__restrict__ R, long ldr, long strideR) {
-  const int e = blockIdx.y;
-  const int lo = win[2 * e], hi = win[2 * e + 1];
-  if (lo >= hi) return;
-  const DevPW &p = tab[pwi[e]];
-  const int ntl = p.npad / TILE;
-  if ((int)blockIdx.x >= ntl * (ntl + 1) / 2) return;
-  const double *__restrict__ W = p.W64;
-  const int ldw = p.npad, n = p.n;
-  const double inv2a = 0.5 / p.a;
-  int bi, bj;
-  tri_tile(blockIdx.x, bi, bj);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int kk = lane >> 4, ii = lane & 15;
-  const int i0 = bi * TILE + wr * 32, j0 = bj * TILE + wc * 32;
-  const double Ev = E[e];
-  const double *Ek = p.Ek;
-  d4 acc[4];
+  for (int q = 0; q < NP_E; ++q) {
+    const int e = blockIdx.y * NP_E + q;
+    if (e >= ne) return;
+    const int lo = win[2 * e], hi = win[2 * e + 1];
+    if (lo >= hi) continue;
+    const DevPW &p = tab[pwi[e]];
+    const int ntl = p.npad / TILE;
+    if ((int)blockIdx.x >= ntl * (ntl + 1) / 2) continue;
+    const GlobalPtr<double> W = (GlobalPtr<double>)p.W64;
+    const GlobalPtr<double> Ek = (GlobalPtr<double>)p.Ek;
+    const int ldw = p.npad, n = p.n;
+    const double inv2a = 0.5 / p.a;
+    int bi, bj;
+    tri_tile(blockIdx.x, bi, bj);
+    const int i0 = bi * TILE + wr * 32, j0 = bj * TILE + wc * 32;
+    const double Ev = E[e];
+    d4 acc[4];
 #pragma unroll
-  for (int m = 0; m < 4; ++m) acc[m] = d4{0, 0, 0, 0};
-  for (int k = lo; k < hi; k += 4) {
-    const int kr = k + kk;
-    double d = 0.0, a0 = 0, a1 = 0, b0 = 0, b1 = 0;
-    if (kr < hi) {
-      const double diff = Ek[kr] - Ev;
-      d = diff != 0.0 ? inv2a / diff : 0.0;
-      const double *row = W + (size_t)kr * ldw;
-      a0 = row[i0 + ii];
-      a1 = row[i0 + 16 + ii];
-      b0 = row[j0 + ii];
-      b1 = row[j0 + 16 + ii];
+    for (int m = 0; m < 4; ++m) acc[m] = d4{0, 0, 0, 0};
+#pragma unroll 4
+    for (int k = lo; k < hi; k += 4) {
+      const int kr = k + kk;
+      double d = 0.0, a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+      if (kr < hi) {
+        const double diff = Ek[kr] - Ev;
+        d = diff != 0.0 ? inv2a / diff : 0.0;
+        const size_t row = (size_t)kr * ldw;
+        a0 = W[row + i0 + ii];
+        a1 = W[row + i0 + 16 + ii];
+        b0 = W[row + j0 + ii];
+        b1 = W[row + j0 + 16 + ii];
+      }
+      const double x0 = a0 * d, x1 = a1 * d;
+      acc[0] = mfma16(x0, b0, acc[0]);
+      acc[1] = mfma16(x0, b1, acc[1]);
+      acc[2] = mfma16(x1, b0, acc[2]);
+      acc[3] = mfma16(x1, b1, acc[3]);
     }
-    const double x0 = a0 * d, x1 = a1 * d;
-    acc[0] = mfma16(x0, b0, acc[0]);
-    acc[1] = mfma16(x0, b1, acc[1]);
-    acc[2] = mfma16(x1, b0, acc[2]);
-    acc[3] = mfma16(x1, b1, acc[3]);
-  }
-  double *Re = R + (size_t)e * strideR;
+    double *Re = R + (size_t)e * strideR;
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const int j = j0 + (m & 1) * 16 + ii;
+    for (int m = 0; m < 4; ++m) {
+      const int j = j0 + (m & 1) * 16 + ii;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = i0 + (m >> 1) * 16 + 4 * v + kk;
-      if (i < n && j < n && i >= j) {
-        const double val = Re[(size_t)i * ldr + j] + acc[m][v];
-        Re[(size_t)i * ldr + j] = val;
-        Re[(size_t)j * ldr + i] = val;
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + (m >> 1) * 16 + 4 * v + kk;
+        if (i < n && j < n && i >= j) {
+          const double val = Re[(size_t)i * ldr + j] + acc[m][v];
+          Re[(size_t)i * ldr + j] = val;
+          Re[(size_t)j * ldr + i] = val;
+        }
       }
     }
   }
@@ -445,8 +452,8 @@ __global__ __launch_bounds__(256) void k_nearpole(const DevPW *__restrict__ tab,
 
 void launch_nearpole(hipStream_t s, const Lay &L, int maxtiles, const DevPW *tab, const int *pwi, const double *E,
                      const int *win, double *R) {
-  dim3 grid(maxtiles, L.ne);
-  hipLaunchKernelGGL(k_nearpole, grid, dim3(256), 0, s, tab, pwi, E, win, R, L.ldaug, L.sA);
+  dim3 grid(maxtiles, (L.ne + NP_E - 1) / NP_E);
+  hipLaunchKernelGGL(k_nearpole, grid, dim3(256), 0, s, tab, pwi, E, win, L.ne, R, L.ldaug, L.sA);
 }
 
 __global__ void k_nanfill_R(const DevPW *__restrict__ tab, const int *__restrict__ pwi,

@@ -24,7 +24,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc into oracle/librmo.so."""
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
         tmp = _SO + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-std=c11", "-Wall", "-fPIC", "-shared",
+        subprocess.check_call(["gcc", "-O3", "-fopenmp", "-std=c11", "-Wall", "-fPIC", "-shared",
                                _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _SO)
     return _SO

@@ -866,7 +866,7 @@ void worker_main(rm_ctx *ctx, Slot *slot) {
         return false;
       });
       if (ctx->stop) return;
-      // the precision of the earliest request with work decides the chunk's
+      // the options of the earliest request with work decide the chunk's
       const Req *first = nullptr;
       for (Req *q : ctx->active)
         if (q->next_e < q->rq.ne) {
@@ -876,12 +876,18 @@ void worker_main(rm_ctx *ctx, Slot *slot) {
       o = fixed_opts(&first->rq.opts);
       o.device_ptrs = 0;
       o.stream = nullptr;
+      // requests join the chunk only if every option the chunk's kernels read
+      // (precision, near-pole window, threshold guard) equals the first one's
+      auto compatible = [&](const Req *q) {
+        const rm_opts f = fixed_opts(&q->rq.opts);
+        return f.prec == o.prec && f.split_delta == o.split_delta && f.thr_guard == o.thr_guard;
+      };
       // largest member shapes decide the per-energy footprint
       const size_t used = ctx->resident + ctx->work_bytes - slot->w.bytes;
       const size_t share = (ctx->budget > used ? ctx->budget - used : 0) / std::max<size_t>(ctx->slots.size(), 1);
       int n = 0, npad = 0, Mpad = 0, nt = 0;
       for (Req *q : ctx->active) {
-        if (q->next_e >= q->rq.ne || fixed_opts(&q->rq.opts).prec != o.prec) continue;
+        if (q->next_e >= q->rq.ne || !compatible(q)) continue;
         auto it = ctx->pws.find(q->rq.pw_id);
         if (it == ctx->pws.end()) continue;
         n = std::max(n, it->second.n);
@@ -892,7 +898,7 @@ void worker_main(rm_ctx *ctx, Slot *slot) {
       int room = n ? chunk_cap(n, npad, Mpad, nt, share, 256) : 0;
       for (Req *q : ctx->active) {
         if (room <= 0) break;
-        if (q->next_e >= q->rq.ne || fixed_opts(&q->rq.opts).prec != o.prec) continue;
+        if (q->next_e >= q->rq.ne || !compatible(q)) continue;
         auto it = ctx->pws.find(q->rq.pw_id);
         if (it == ctx->pws.end()) {
           q->err = RM_E_NOTFOUND;

@@ -65,6 +65,25 @@ def test_alone_equals_mix(ctx):
         ctx.pw_release(i)
 
 
+def test_mixed_options_run_with_their_own(ctx):
+    """Split-mode requests with different near-pole windows are queued
+    together; each must run with its own window (equal, bitwise, to rm_run with
+    that window), not with the window of a request it shares a chunk with."""
+    pool = _pool()[:2]
+    ids = [ctx.pw_upload(p) for p in pool]
+    rng = np.random.default_rng(11)
+    reqs = [(i % 2, np.sort(rng.uniform(0.01, 8.0, 40 + 7 * i)), 0.02 if i % 3 == 0 else 0.08) for i in range(6)]
+    tickets = [ctx.submit(ids[p], E, prec=1, split_delta=d) for p, E, d in reqs]
+    ctx.drain()
+    for (p, E, d), (t, out) in zip(reqs, tickets):
+        assert ctx.poll(t) is not None
+        om, _, st = ctx.run(ids[p], E, prec=1, split_delta=d)
+        assert np.array_equal(out["status"], st)
+        assert np.array_equal(out["omega"], om, equal_nan=True)
+    for i in ids:
+        ctx.pw_release(i)
+
+
 def test_unknown_ticket_and_pw(ctx):
     from paper_1909_07321_amd import rm
     with pytest.raises(rm.RMError):

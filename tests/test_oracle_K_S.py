@@ -275,3 +275,32 @@ def test_channel_permutation_covariance():
         scale = max(1, np.abs(K0).max())
         assert np.abs(K1 - K0[np.ix_(q, q)]).max() < 1e-9 * scale
         np.testing.assert_allclose(r1["omega"][e], r0["omega"][e], atol=1e-9)
+
+
+@pytest.mark.parametrize("cfg", ["c1", "c2"])
+def test_cond1_estimate_bounds_true_condition_number(cfg):
+    """The oracle's condition estimate of the matching matrix (Hager's method
+    for ||A^-1||_1 times ||A||_1) against the exact 1-norm condition number of
+    A_im = d_im C_i - R_im (a C'_m - b C_m) (eq. (match)), rebuilt here from
+    the oracle's own R and asymptotic values and evaluated by numpy.  Hager's
+    estimate is a lower bound of ||A^-1||_1 that is in practice within a small
+    factor of it, so the estimate must lie in [0.3, 1] x cond_1(A)."""
+    if cfg == "c1":
+        pw, E = synth.config1()
+        E = E[::17]
+    else:
+        pw, E = synth.config2()
+        E = E[::167]   # 12 energies across [0.01, 6] Ry
+    o = oracle.Oracle(pw)
+    R, _ = o.form_R(E)
+    fg, _, no, _ = o.asymptotic(E)
+    _, cond, st = o.solve_K(E, R, fg)
+    assert (st == 0).all()
+    for e in range(E.size):
+        if no[e] == 0:
+            assert cond[e] == 0
+            continue
+        C, Cp = fg[e, :, 2], fg[e, :, 3]
+        A = np.diag(C) - R[e] * (pw.a * Cp - pw.b * C)[None, :]
+        exact = np.linalg.cond(A, 1)
+        assert 0.3 * exact <= cond[e] <= exact * (1 + 1e-12), (E[e], cond[e], exact)

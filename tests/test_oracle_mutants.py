@@ -41,6 +41,11 @@ MUTANTS = {
                   "test_oracle_K_S.py::test_S_unitary_symmetric_and_T_identity"),
     "omega_target_index": ("pw->target[open_idx[j]]] += half_g * t2;", "pw->target[open_idx[i]]] += half_g * t2;",
                            "test_oracle_K_S.py::test_omega_from_T_identity_by_target"),
+    "cond1_row_norm": ("for (int i = 0; i < n; ++i) s += fabsl(A[(size_t)i * n + j]);",
+                       "for (int i = 0; i < n; ++i) s += fabsl(A[(size_t)j * n + i]);",
+                       "test_oracle_K_S.py::test_cond1_estimate_bounds_true_condition_number"),
+    "cond1_transposed_solve": ("lu_solve(LU, n, piv, y, 1);", "lu_solve(LU, n, piv, y, 0);",
+                               "test_oracle_K_S.py::test_cond1_estimate_bounds_true_condition_number"),
     "omega_half_g": ("const ld half_g = 0.5L * (ld)pw->g;", "const ld half_g = (ld)pw->g;",
                      "test_oracle_K_S.py::test_single_channel_ion_closed_form"),
 }

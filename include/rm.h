@@ -148,13 +148,17 @@ rm_status rm_asymptotic(rm_ctx *ctx, int32_t pw, const double *E, int32_t ne, co
 
 /* Stage 3, eq. (match): from R [ne][n][n] and fg [ne][n][4] (as produced by the
    two calls above, or by any other source), the K-matrix K: [ne][n][n] with the
-   leading nopen x nopen block filled (row stride n) and the rest zero. */
+   leading nopen x nopen block filled (row stride n) and the rest zero.  K is
+   returned as solved: it is symmetric up to the rounding of the solve. */
 rm_status rm_solve_K(rm_ctx *ctx, int32_t pw, const double *E, int32_t ne, const double *R,
                      const double *fg, const rm_opts *opts, double *K, int32_t *status);
 
-/* Stage 4: from K [ne][n][n] (leading nopen x nopen block), the collision
-   strengths omega: [ne][ntarget][ntarget] and, if S != NULL, S: [ne][n][n][2]
-   (re, im; leading nopen x nopen block). */
+/* Stage 4, Glossary ("Transitions matrix", "Collision strength"): from K
+   [ne][n][n] (leading nopen x nopen block, symmetrised as (K + K^T)/2), the
+   collision strengths omega: [ne][ntarget][ntarget] and, if S != NULL,
+   S = (1 + iK)(1 - iK)^-1: [ne][n][n][2] (re, im; leading nopen x nopen block).
+   (1 - iK)^-1 comes from a complex symmetric factorisation of 1 - iK itself,
+   so the result keeps the conditioning of 1 - iK. */
 rm_status rm_collision_strengths(rm_ctx *ctx, int32_t pw, const double *E, int32_t ne,
                                  const double *K, const rm_opts *opts, double *omega, double *S,
                                  int32_t *status);

@@ -11,9 +11,10 @@
 // batched, blocked, right-looking LU with partial pivoting applied to [A | B]
 // followed by a blocked back substitution.
 //
-// S and Omega (Glossary): S = (1 + iK)(1 - iK)^-1 = (2Y - 1) + 2iKY with
-// Y = (1 + K^2)^-1, so with X = (1 + K^2)^-1 K (same LU, on [1 + K^2 | K]):
-//   T = S - 1,  T_ij = -2 (XK)_ij + 2i X_ij,  |T_ij|^2 = 4 [(XK)_ij^2 + X_ij^2]
+// S and Omega (Glossary): S = (1 + iK)(1 - iK)^-1 = 2 M^-1 - 1 with M = 1 - iK,
+// formed from a complex symmetric Cholesky factorisation of M (section "S and
+// Omega from K" below):
+//   T = S - 1 = 2 (M^-1 - 1),  |T_ij|^2 = 4 |(M^-1)_ij - d_ij|^2
 //   Omega_pq = (g/2) sum_{i in p, j in q, both open} |T_ij|^2
 //
 // Augmented layout per energy: rows [0, rows), A in columns [0, rows), the
@@ -589,17 +590,25 @@ struct ColMap {
 #ifndef UPD_DEPTH
 #define UPD_DEPTH 1
 #endif
+// Rows of U for the streaming updates: row k of a block of jb rows that starts
+// at Ub (rows past jb read as 0).
+struct RowsU {
+  const double *Ub;
+  long ld;
+  int jb;
+  __device__ __forceinline__ double operator()(int k, long col) const { return k < jb ? Ub[(long)k * ld + col] : 0.0; }
+};
+
 // C (64 rows x G column tiles) -= Lb (64 x KB) * U (KB x columns), one column
 // tile at a time, with sL holding -Lb: the MFMAs accumulate onto the loaded C
 // values.  The C values of the next two tiles and the U slab of the next tile
 // are loaded into registers while the current tile is multiplied, so three
-// tiles of C are in flight per workgroup.  Cb and Ub point at row 0 of the C
-// block and of U; both are addressed through the column map cm; U rows past jb
-// read as 0.
-template <int KB, int G, int DEPTH = UPD_DEPTH>
+// tiles of C are in flight per workgroup.  Cb points at row 0 of the C block
+// (row stride ld); C and U are addressed through the column map cm, and
+// u(k, col) reads row k of U at memory column col.
+template <int KB, int G, int DEPTH = UPD_DEPTH, typename UL>
 __device__ __forceinline__ void rowblock_update(const double (*sL)[Pitch<KB>::A], double (*sU)[PB], int mrem,
-                                                int vbeg, int ncols, ColMap cm, double *Cb, const double *Ub, int jb,
-                                                long ld) {
+                                                int vbeg, int ncols, ColMap cm, double *Cb, UL u, long ld) {
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int wr = wave >> 1, wc = wave & 1;
@@ -625,7 +634,7 @@ __device__ __forceinline__ void rowblock_update(const double (*sL)[Pitch<KB>::A]
 #pragma unroll
     for (int q = 0; q < NU; ++q) {
       const int k = ku0 + 4 * q;
-      dst[q] = (ok && k < jb) ? Ub[(long)k * ld + col] : 0.0;
+      dst[q] = ok ? u(k, col) : 0.0;
     }
   };
   auto cols = [&](int v0, long (&col)[2], bool (&cok)[2]) {
@@ -720,7 +729,7 @@ __global__ __launch_bounds__(256, 2) void k_lu_update(int p0, const int *__restr
       sL[i][k] = (r0 + i < m && k < jb) ? -A[(size_t)(c0 + r0 + i) * ldaug + p0 + k] : 0.0;
     }
     rowblock_update<KB, UPD_G>(sL, sU, m - r0, vbeg, ncols, ColMap{acols, c0, roff}, A + (size_t)(c0 + r0) * ldaug,
-                               A + (size_t)p0 * ldaug, jb, ldaug);
+                               RowsU{A + (size_t)p0 * ldaug, ldaug, jb}, ldaug);
   });
 }
 
@@ -797,7 +806,7 @@ __global__ __launch_bounds__(256, 2) void k_bs_update(int j0, const int *__restr
       sU[i][k] = (r0 + i < j0 && k < jb) ? -A[(size_t)(r0 + i) * ldaug + j0 + k] : 0.0;
     }
     rowblock_update<KB, UPD_G>(sU, sY, j0 - r0, qbeg, rhs, ColMap{0, 0, roff}, A + (size_t)r0 * ldaug,
-                               A + (size_t)j0 * ldaug, jb, ldaug);
+                               RowsU{A + (size_t)j0 * ldaug, ldaug, jb}, ldaug);
   });
 }
 
@@ -905,482 +914,39 @@ void launch_backsub(hipStream_t s, int ne, int maxrows, int maxrhs, const int *d
 }
 
 // ---------------------------------------------------------------------------
-// Cholesky forward phase for the symmetric positive definite P = 1 + K^2 (rows =
-// right-hand sides = nopen): P = L L^T in blocks of NBU, L kept in the lower
-// triangle and L^T in the upper one (so the back substitution above can use
-// it as U), with the right-hand sides carried along: on return they hold
-// Z = L^-1 K.
+// S and Omega from K (Glossary, "Transitions matrix" and "Collision
+// strength").  With M = 1 - iK,
+//   S = (1 + iK) M^-1 = 2 M^-1 - 1,   T = S - 1 = 2 (M^-1 - 1),
+//   |T_ij|^2 = 4 |(M^-1)_ij - d_ij|^2.
+// K is real symmetric, so M is complex symmetric with Hermitian part 1: every
+// leading block of M and of its Schur complements has Hermitian part >= 1, so
+// M = C C^T (complex symmetric Cholesky, no pivoting) exists and every pivot
+// has real part >= 1.  G = C^-1 is formed by forward substitution carried
+// along the factorisation (identity right-hand sides), and M^-1 = G^T G.  No
+// product K K is formed, so the result keeps the conditioning of M itself,
+// max_lambda |1 - i lambda| over the eigenvalues lambda of K.
+//
+// Complex matrices are held as two real planes.  Per energy: M, then C, then
+// M^-1 in aug (real part in columns [0, no), imaginary part in columns [roff,
+// roff + no)); G in the planes gre and gim (row stride ldg).  The factorisation
+// runs in complex blocks of ZB = 32 columns.  A complex product with a 32-wide
+// inner dimension is a real product with a 64-wide one,
+//   [Pr | Pi] [[Qr, Qi], [-Qi, Qr]] = [Re PQ | Im PQ],
+//   [[Pr, -Pi], [Pi, Pr]] [Qr; Qi]  = [Re PQ; Im PQ],
+// so the block solves are the 64 x 64 x 64 MFMA slabs of the LU, and the
+// trailing update of each plane is a real rank-64 streaming update.
 // ---------------------------------------------------------------------------
+constexpr int ZB = NB;
+constexpr int ZK = 2 * ZB;  // real inner dimension of a complex block product
 
-// Diagonal block: unblocked Cholesky of P11 in LDS, L11 written to the lower
-// and L11^T to the upper part, and the explicit inverse of L11 (lower,
-// identity past jb) to linv.  A pivot that is not positive (only possible for
-// non-finite input) sets RM_PT_SINGULAR and is replaced by 1.
-__global__ __launch_bounds__(256) void k_chol_diag(int j0, const int *__restrict__ dims, double *__restrict__ aug,
-                                                   long ldaug, long strideA, double *__restrict__ linv,
-                                                   int *__restrict__ status) {
-  constexpr int KB = NBU;
-  const int e = blockIdx.x;
-  const int rows = dims[2 * e];
-  if (j0 >= rows) return;
-  const int jb = min(KB, rows - j0);
-  double *A = aug + (size_t)e * strideA + (size_t)j0 * ldaug + j0;
-  __shared__ double a[KB][KB + 1];
-  const int t = threadIdx.x;
-  for (int idx = t; idx < KB * KB; idx += 256) {
-    const int i = idx / KB, k = idx % KB;
-    a[i][k] = (i < jb && k < jb) ? (k <= i ? A[(size_t)i * ldaug + k] : 0.0) : (i == k ? 1.0 : 0.0);
-  }
-  __syncthreads();
-  for (int j = 0; j < jb; ++j) {
-    if (t == 0) {
-      double d = a[j][j];
-      if (!(d > 0.0)) {
-        atomicOr(status + e, RM_PT_SINGULAR);
-        d = 1.0;
-      }
-      a[j][j] = sqrt(d);
-    }
-    __syncthreads();
-    const double r = a[j][j];
-    for (int i = j + 1 + t; i < jb; i += 256) a[i][j] /= r;
-    __syncthreads();
-    const int c = jb - 1 - j;
-    for (int idx = t; idx < c * c; idx += 256) {
-      const int i = j + 1 + idx / c, k = j + 1 + idx % c;
-      if (k <= i) a[i][k] -= a[i][j] * a[k][j];
-    }
-    __syncthreads();
-  }
-  for (int idx = t; idx < jb * jb; idx += 256) {
-    const int i = idx / jb, k = idx % jb;
-    if (k <= i) {
-      A[(size_t)i * ldaug + k] = a[i][k];
-      A[(size_t)k * ldaug + i] = a[i][k];
-    }
-  }
-  // lane j of wave 0: column j of L11^-1 by forward substitution
-  if (t < KB) {
-    const int j = t;
-    double x[KB];
-    static_for([&](auto iI) {
-      constexpr int i = decltype(iI)::value;
-      double acc = i == j ? 1.0 : 0.0;
-      static_for([&](auto kI) {
-        constexpr int k = decltype(kI)::value;
-        if constexpr (k < i) acc -= a[i][k] * x[k];
-      }, std::make_integer_sequence<int, KB>{});
-      x[i] = i < j ? 0.0 : acc / a[i][i];
-    }, std::make_integer_sequence<int, KB>{});
-    double *Li = linv + (size_t)e * KB * KB;
-    static_for([&](auto iI) {
-      constexpr int i = decltype(iI)::value;
-      Li[(size_t)i * KB + j] = x[i];
-    }, std::make_integer_sequence<int, KB>{});
-  }
-}
-
-// Panel below the diagonal block: L21 = P21 L11^-T on FP64 MFMA, one 64-row
-// tile per item, written in place and transposed into the upper part.
-__global__ __launch_bounds__(256) void k_chol_panel(int j0, const int *__restrict__ dims, double *__restrict__ aug,
-                                                    long ldaug, long strideA, const double *__restrict__ linv,
-                                                    int tiles_m, int ne) {
-  constexpr int KB = NBU;
-  __shared__ double sA[TILE][Pitch<KB>::A];  // sA[i][k] = P21[r0 + i][k]
-  __shared__ double sB[KB][PB];              // sB[k][j] = Linv[j][k]
-  const int t = threadIdx.x;
-  const int lane = t & 63, wave = t >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
-  const int kk = lane >> 4, ii = lane & 15;
-  for_items(ne, tiles_m, [&](int e, int tile) {
-    const int rows = dims[2 * e];
-    if (j0 >= rows) return;
-    const int jb = min(KB, rows - j0);
-    const int c0 = j0 + jb, m = rows - c0, r0 = tile * TILE;
-    if (r0 >= m) return;
-    double *A = aug + (size_t)e * strideA;
-    const double *Li = linv + (size_t)e * KB * KB;
-    for (int idx = t; idx < KB * TILE; idx += 256) {
-      const int i = idx / KB, k = idx % KB;
-      sA[i][k] = (r0 + i < m && k < jb) ? A[(size_t)(c0 + r0 + i) * ldaug + j0 + k] : 0.0;
-    }
-    for (int idx = t; idx < KB * KB; idx += 256) sB[idx / KB][idx % KB] = Li[(idx % KB) * KB + idx / KB];
-    __syncthreads();
-    d4 acc[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = d4{0, 0, 0, 0};
-    mfma_slab<KB>(sA, sB, acc, wr, wc, kk, ii);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int j = wc * 32 + (q & 1) * 16 + ii;
-      if (j >= jb) continue;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = wr * 32 + (q >> 1) * 16 + 4 * v + kk;
-        if (r0 + i < m) {
-          A[(size_t)(c0 + r0 + i) * ldaug + j0 + j] = acc[q][v];
-          A[(size_t)(j0 + j) * ldaug + c0 + r0 + i] = acc[q][v];
-        }
-      }
-    }
-    __syncthreads();
-  });
-}
-
-// Right-hand sides of the diagonal block: Z1 = L11^-1 K1 (rows [j0, j0 + jb)),
-// one 64-column tile per item, in place.
-__global__ __launch_bounds__(256) void k_chol_rhs(int j0, const int *__restrict__ dims, double *__restrict__ aug,
-                                                  long ldaug, long strideA, long roff,
-                                                  const double *__restrict__ linv, int tiles_n, int ne) {
-  constexpr int KB = NBU;
-  __shared__ double sL[KB][Pitch<KB>::A];  // sL[i][k] = Linv[i][k]
-  __shared__ double sX[KB][PB];            // sX[k][j] = K1[k][q0 + j]
-  const int t = threadIdx.x;
-  const int lane = t & 63, wave = t >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
-  const int kk = lane >> 4, ii = lane & 15;
-  for_items(ne, tiles_n, [&](int e, int tile) {
-    const int rows = dims[2 * e], rhs = dims[2 * e + 1];
-    if (j0 >= rows) return;
-    const int jb = min(KB, rows - j0);
-    const int q0 = tile * TILE;
-    if (q0 >= rhs) return;
-    double *A = aug + (size_t)e * strideA + (size_t)j0 * ldaug + roff;
-    const double *Li = linv + (size_t)e * KB * KB;
-    for (int idx = t; idx < KB * KB; idx += 256) sL[idx / KB][idx % KB] = Li[idx];
-    for (int idx = t; idx < KB * TILE; idx += 256) {
-      const int k = idx / TILE, j = idx % TILE;
-      sX[k][j] = (k < jb && q0 + j < rhs) ? A[(size_t)k * ldaug + q0 + j] : 0.0;
-    }
-    __syncthreads();
-    d4 acc[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = d4{0, 0, 0, 0};
-    mfma_slab<KB>(sL, sX, acc, wr, wc, kk, ii);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int j = q0 + wc * 32 + (q & 1) * 16 + ii;
-      if (j >= rhs) continue;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = wr * 32 + (q >> 1) * 16 + 4 * v + kk;
-        if (i < jb) A[(size_t)i * ldaug + j] = acc[q][v];
-      }
-    }
-    __syncthreads();
-  });
-}
-
-void launch_chol_forward(hipStream_t s, int ne, int maxrows, int maxrhs, const int *dims, double *aug, long ldaug,
-                         long strideA, long roff, double *linv, int *status) {
-  for (int j0 = 0; j0 < maxrows; j0 += NBU) {
-    hipLaunchKernelGGL(k_chol_diag, dim3(ne), dim3(256), 0, s, j0, dims, aug, ldaug, strideA, linv, status);
-    const int c0 = std::min(maxrows, j0 + NBU), m = maxrows - c0;
-    if (m > 0) {
-      const int tm = (m + TILE - 1) / TILE;
-      hipLaunchKernelGGL(k_chol_panel, dim3(persist_grid(k_chol_panel, 256, ne, tm)), dim3(256), 0, s, j0, dims, aug,
-                         ldaug, strideA, linv, tm, ne);
-    }
-    if (maxrhs > 0) {
-      const int tn = (maxrhs + TILE - 1) / TILE;
-      hipLaunchKernelGGL(k_chol_rhs, dim3(persist_grid(k_chol_rhs, 256, ne, tn)), dim3(256), 0, s, j0, dims, aug,
-                         ldaug, strideA, roff, linv, tn, ne);
-    }
-    if (m > 0) {
-      const int ncols = m + maxrhs;
-      const int tm = (m + TILE - 1) / TILE, gr = (ncols + UPD_G * TILE - 1) / (UPD_G * TILE);
-      hipLaunchKernelGGL(k_lu_update<NBU>, dim3(persist_grid(k_lu_update<NBU>, 256, ne, (long)tm * gr)), dim3(256),
-                         0, s, j0, dims, aug, ldaug, strideA, roff, tm, gr, ne, 1, 1 << 30, 1);
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Small batched GEMM, C = A B (square no x no per energy), FP64 MFMA.
-// ---------------------------------------------------------------------------
-// FORMP: C = 1 + A B, and A (= K) copied to C's right-hand-side columns at roff.
-// K slab of the batched products (a compile-time knob; 16 and 64 measured
-// slower than 32 at 1500 channels).
-#ifndef RM_GEMM_GK
-#define RM_GEMM_GK 32
-#endif
-template <bool TA, bool LOWER, bool MIRROR, bool FORMP = false>
-__global__ __launch_bounds__(256) void k_gemm_sq(const int *__restrict__ nopen, const double *__restrict__ A,
-                                                 long lda, long sA, const double *__restrict__ B, long ldb,
-                                                 long sB, double *__restrict__ C, long ldc, long sC,
-                                                 int tiles_n, int ne, long roff = 0) {
-  constexpr int GK = RM_GEMM_GK;
-  constexpr int NL = TILE * GK / 256;  // slab elements per thread (A and B each)
-  __shared__ double sa[TILE][Pitch<GK>::A];  // sa[i][k] = A[r0 + i][k0 + k]
-  __shared__ double sb[GK][PB];              // sb[k][j] = B[k0 + k][q0 + j]
-  const int t = threadIdx.x;
-  const int lane = t & 63, wave = t >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
-  const int kk = lane >> 4, ii = lane & 15;
-  for_items(ne, tiles_n * tiles_n, [&](int e, int it) {
-  const int n = nopen[e];
-  const int tm = it / tiles_n, tn = it % tiles_n;
-  const int r0 = tm * TILE, q0 = tn * TILE;
-  if (r0 >= n || q0 >= n || (LOWER && tn > tm)) return;
-  const double *Ae = A + (size_t)e * sA;
-  const double *Be = B + (size_t)e * sB;
-  double *Ce = C + (size_t)e * sC;
-  // the next slab is loaded into registers while the current one is multiplied
-  double ra[NL], rb[NL];
-  auto gload = [&](int k0) {
-#pragma unroll
-    for (int q = 0; q < NL; ++q) {
-      const int idx = t + 256 * q;
-      const int i = idx / GK, k = idx % GK;
-      if (TA) {
-        // A^T: element (i, k) is A[k][i]; lanes run along i so the load is contiguous
-        const int ia = idx % TILE, ka = idx / TILE;
-        ra[q] = (r0 + ia < n && k0 + ka < n) ? Ae[(size_t)(k0 + ka) * lda + r0 + ia] : 0.0;
-      } else {
-        ra[q] = (r0 + i < n && k0 + k < n) ? Ae[(size_t)(r0 + i) * lda + k0 + k] : 0.0;
-      }
-      const int kb = idx / TILE, j = idx % TILE;
-      rb[q] = (q0 + j < n && k0 + kb < n) ? Be[(size_t)(k0 + kb) * ldb + q0 + j] : 0.0;
-    }
-  };
-  d4 acc[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) acc[q] = d4{0, 0, 0, 0};
-  gload(0);
-  for (int k0 = 0; k0 < n; k0 += GK) {
-#pragma unroll
-    for (int q = 0; q < NL; ++q) {
-      const int idx = t + 256 * q;
-      if (TA)
-        sa[idx % TILE][idx / TILE] = ra[q];
-      else
-        sa[idx / GK][idx % GK] = ra[q];
-      sb[idx / TILE][idx % TILE] = rb[q];
-    }
-    __syncthreads();
-    if (k0 + GK < n) gload(k0 + GK);
-    mfma_slab<GK>(sa, sb, acc, wr, wc, kk, ii);
-    __syncthreads();
-  }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int j = q0 + wc * 32 + (q & 1) * 16 + ii;
-    if (j >= n) continue;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = r0 + wr * 32 + (q >> 1) * 16 + 4 * v + kk;
-      if (i < n) {
-        Ce[(size_t)i * ldc + j] = FORMP && i == j ? 1.0 + acc[q][v] : acc[q][v];
-        if (MIRROR && tm != tn) Ce[(size_t)j * ldc + i] = acc[q][v];
-        if (FORMP) {
-          Ce[(size_t)i * ldc + roff + j] = Ae[(size_t)i * lda + j];
-          if (tm != tn) Ce[(size_t)j * ldc + roff + i] = Ae[(size_t)j * lda + i];
-        }
-      }
-    }
-  }
-  });
-}
-
-void launch_gemm_sq(hipStream_t s, int ne, int maxn, const int *nopen, const double *A, long lda, long sA,
-                    const double *B, long ldb, long sB, double *C, long ldc, long sC) {
-  if (maxn <= 0) return;
-  const int tn = (maxn + TILE - 1) / TILE;
-  hipLaunchKernelGGL((k_gemm_sq<false, false, false>), dim3(persist_grid(k_gemm_sq<false, false, false>, 256, ne,
-                     (long)tn * tn)), dim3(256), 0, s, nopen, A, lda, sA, B, ldb, sB, C, ldc, sC, tn, ne);
-}
-
-// [1 + K K | K] for the S/Omega stage: the lower block tiles of 1 + K K and all
-// of K in the right-hand-side columns.
-// Products of the S/Omega stage in 128 x 128 tiles (k_gemm128) or 64 x 64 tiles (k_gemm_sq).
-#ifndef RM_GEMM128
-#define RM_GEMM128 1
-#endif
-// The same products in 128 x 128 output tiles with eight waves per workgroup,
-// each owning a 64 x 32 block (4 x 2 MFMA blocks): half the operand traffic of
-// k_gemm_sq per output element at two waves per SIMD.  K slabs of 16 are
-// staged through LDS with the next slab loaded into registers while the
-// current one is multiplied.  Each element sums over k in the same order as
-// k_gemm_sq (one MFMA step per 4 k, ascending).
-template <bool TA, bool LOWER, bool MIRROR, bool FORMP = false>
-__global__ __launch_bounds__(512, 1) void k_gemm128(const int *__restrict__ nopen, const double *__restrict__ A,
-                                                    long lda, long sA, const double *__restrict__ B, long ldb,
-                                                    long sB, double *__restrict__ C, long ldc, long sC, int tiles_n,
-                                                    int ne, long roff = 0) {
-  constexpr int BT = 2 * TILE, GK = 16, NT = 512;
-  constexpr int NL = BT * GK / NT;         // slab elements per thread (A and B each)
-  __shared__ double sa[BT][Pitch<GK>::A];  // sa[i][k] = op(A)[r0 + i][k0 + k]
-  __shared__ double sb[GK][BT];            // sb[k][j] = B[k0 + k][q0 + j]
-  const int t = threadIdx.x;
-  const int lane = t & 63, wave = t >> 6;
-  const int wr = wave >> 2, wc = wave & 3;  // 2 x 4 waves: rows wr*64, columns wc*32
-  const int kk = lane >> 4, ii = lane & 15;
-  for_items(ne, tiles_n * tiles_n, [&](int e, int it) {
-    const int n = nopen[e];
-    const int tm = it / tiles_n, tn = it % tiles_n;
-    const int r0 = tm * BT, q0 = tn * BT;
-    if (r0 >= n || q0 >= n || (LOWER && tn > tm)) return;
-    const double *Ae = A + (size_t)e * sA;
-    const double *Be = B + (size_t)e * sB;
-    double *Ce = C + (size_t)e * sC;
-    double ra[NL], rb[NL];
-    auto gload = [&](int k0) {
-#pragma unroll
-      for (int q = 0; q < NL; ++q) {
-        const int idx = t + NT * q;
-        if (TA) {
-          // op(A)(i, k) = A[k][i]; lanes run along i so the load is contiguous
-          const int ia = idx % BT, ka = idx / BT;
-          ra[q] = (r0 + ia < n && k0 + ka < n) ? Ae[(size_t)(k0 + ka) * lda + r0 + ia] : 0.0;
-        } else {
-          const int i = idx / GK, k = idx % GK;
-          ra[q] = (r0 + i < n && k0 + k < n) ? Ae[(size_t)(r0 + i) * lda + k0 + k] : 0.0;
-        }
-        const int kb = idx / BT, j = idx % BT;
-        rb[q] = (q0 + j < n && k0 + kb < n) ? Be[(size_t)(k0 + kb) * ldb + q0 + j] : 0.0;
-      }
-    };
-    d4 acc[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) acc[q] = d4{0, 0, 0, 0};
-    gload(0);
-    for (int k0 = 0; k0 < n; k0 += GK) {
-#pragma unroll
-      for (int q = 0; q < NL; ++q) {
-        const int idx = t + NT * q;
-        if (TA)
-          sa[idx % BT][idx / BT] = ra[q];
-        else
-          sa[idx / GK][idx % GK] = ra[q];
-        sb[idx / BT][idx % BT] = rb[q];
-      }
-      __syncthreads();
-      if (k0 + GK < n) gload(k0 + GK);
-#pragma unroll
-      for (int ks = 0; ks < GK; ks += 4) {
-        double a[4], b[2];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) a[m] = sa[wr * 64 + m * 16 + ii][ks + kk];
-#pragma unroll
-        for (int m = 0; m < 2; ++m) b[m] = sb[ks + kk][wc * 32 + m * 16 + ii];
-#pragma unroll
-        for (int mr = 0; mr < 4; ++mr)
-#pragma unroll
-          for (int mc = 0; mc < 2; ++mc) acc[mr * 2 + mc] = mfma64(a[mr], b[mc], acc[mr * 2 + mc]);
-      }
-      __syncthreads();
-    }
-#pragma unroll
-    for (int mr = 0; mr < 4; ++mr)
-#pragma unroll
-      for (int mc = 0; mc < 2; ++mc) {
-        const int j = q0 + wc * 32 + mc * 16 + ii;
-        if (j >= n) continue;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = r0 + wr * 64 + mr * 16 + 4 * v + kk;
-          if (i < n) {
-            const double x = acc[mr * 2 + mc][v];
-            Ce[(size_t)i * ldc + j] = FORMP && i == j ? 1.0 + x : x;
-            if (MIRROR && tm != tn) Ce[(size_t)j * ldc + i] = x;
-            if (FORMP) {
-              Ce[(size_t)i * ldc + roff + j] = Ae[(size_t)i * lda + j];
-              if (tm != tn) Ce[(size_t)j * ldc + roff + i] = Ae[(size_t)j * lda + i];
-            }
-          }
-        }
-      }
-  });
-}
-
-void launch_formP(hipStream_t s, int ne, int maxn, const int *nopen, const double *K, long ldk, long sK, double *aug,
-                  long ldaug, long sA, long roff) {
-  if (maxn <= 0) return;
-  if (RM_GEMM128) {
-    const int tn = (maxn + 2 * TILE - 1) / (2 * TILE);
-    hipLaunchKernelGGL((k_gemm128<false, true, false, true>),
-                       dim3(persist_grid(k_gemm128<false, true, false, true>, 512, ne, (long)tn * tn)), dim3(512), 0, s,
-                       nopen, K, ldk, sK, K, ldk, sK, aug, ldaug, sA, tn, ne, roff);
-    return;
-  }
-  const int tn = (maxn + TILE - 1) / TILE;
-  hipLaunchKernelGGL((k_gemm_sq<false, true, false, true>), dim3(persist_grid(k_gemm_sq<false, true, false, true>, 256,
-                     ne, (long)tn * tn)), dim3(256), 0, s, nopen, K, ldk, sK, K, ldk, sK, aug, ldaug, sA, tn, ne, roff);
-}
-
-// Lower triangle (block tiles) of C = A B for symmetric products.
-void launch_gemm_lower(hipStream_t s, int ne, int maxn, const int *nopen, const double *A, long lda, long sA,
-                       const double *B, long ldb, long sB, double *C, long ldc, long sC) {
-  if (maxn <= 0) return;
-  const int tn = (maxn + TILE - 1) / TILE;
-  hipLaunchKernelGGL((k_gemm_sq<false, true, false>), dim3(persist_grid(k_gemm_sq<false, true, false>, 256, ne,
-                     (long)tn * tn)), dim3(256), 0, s, nopen, A, lda, sA, B, ldb, sB, C, ldc, sC, tn, ne);
-}
-
-// C = A^T A, formed on the lower block tiles and mirrored.
-void launch_gemm_ata(hipStream_t s, int ne, int maxn, const int *nopen, const double *A, long lda, long sA,
-                     double *C, long ldc, long sC) {
-  if (maxn <= 0) return;
-  if (RM_GEMM128) {
-    const int tn = (maxn + 2 * TILE - 1) / (2 * TILE);
-    hipLaunchKernelGGL((k_gemm128<true, true, true>), dim3(persist_grid(k_gemm128<true, true, true>, 512, ne,
-                       (long)tn * tn)), dim3(512), 0, s, nopen, A, lda, sA, A, lda, sA, C, ldc, sC, tn, ne);
-    return;
-  }
-  const int tn = (maxn + TILE - 1) / TILE;
-  hipLaunchKernelGGL((k_gemm_sq<true, true, true>), dim3(persist_grid(k_gemm_sq<true, true, true>, 256, ne,
-                     (long)tn * tn)), dim3(256), 0, s, nopen, A, lda, sA, A, lda, sA, C, ldc, sC, tn, ne);
-}
-
-
-// ---------------------------------------------------------------------------
-// K gather, P = 1 + K^2 set-up, collision strengths
-// ---------------------------------------------------------------------------
-// K from the solution: the last nopen rows of Y (the open unknowns), written
-// symmetrised, K_ij = (Y_ij + Y_ji) / 2, with zeros for i or j in [nopen, n);
-// also dims = {nopen, nopen} for the S/Omega stage.  32 x 32 tiles, the
+// M = 1 - i (K + K^T)/2 on the leading no x no block (both triangles) and G = 0
+// there; dims = {no, no}.  One pair of mirrored 32 x 32 tiles per workgroup, the
 // transposed tile staged in LDS so that every access is row-contiguous.
-__global__ __launch_bounds__(256) void k_gatherK(const DevPW *__restrict__ tab, const int *__restrict__ pwi,
-                                                 const int *__restrict__ nopen, const double *__restrict__ aug,
-                                                 long ldaug, long strideA, long roff, double *__restrict__ Kw, long ldk,
-                                                 long strideK, int *__restrict__ dims, int nt32) {
-  const int e = blockIdx.y;
-  const int ti = blockIdx.x / nt32, tj = blockIdx.x % nt32;
-  const int n = tab[pwi[e]].n, no = nopen[e];
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    dims[2 * e] = no;
-    dims[2 * e + 1] = no;
-  }
-  const int i0 = ti * 32, j0 = tj * 32;
-  if (i0 >= n || j0 >= n) return;
-  __shared__ double t1[32][33], t2[32][33];
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  const double *Y = aug + (size_t)e * strideA + (size_t)(n - no) * ldaug + roff;
-  for (int r = ty; r < 32; r += 8) {
-    const int i = i0 + r, j = j0 + tx, i2 = j0 + r, j2 = i0 + tx;
-    t1[r][tx] = (i < no && j < no) ? Y[(size_t)i * ldaug + j] : 0.0;
-    t2[r][tx] = (i2 < no && j2 < no) ? Y[(size_t)i2 * ldaug + j2] : 0.0;
-  }
-  __syncthreads();
-  double *K = Kw + (size_t)e * strideK;
-  for (int r = ty; r < 32; r += 8) {
-    const int i = i0 + r, j = j0 + tx;
-    if (i < n && j < n) K[(size_t)i * ldk + j] = (i < no && j < no) ? 0.5 * (t1[r][tx] + t2[tx][r]) : 0.0;
-  }
-}
-
-void launch_gatherK(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *nopen,
-                    const double *aug, double *Kw, int *dims) {
-  const int nt32 = (L.nmax + 31) / 32;
-  hipLaunchKernelGGL(k_gatherK, dim3(nt32 * nt32, L.ne), dim3(256), 0, s, tab, pwi, nopen, aug, L.ldaug, L.sA,
-                     L.roff, Kw, L.ldk, L.sK, dims, nt32);
-}
-
-// K given by the caller (the staged S/Omega call): symmetrised in place on the
-// leading nopen x nopen block, one pair of mirrored 32 x 32 tiles per block;
-// dims = {nopen, nopen}.
-__global__ __launch_bounds__(256) void k_symK(const int *__restrict__ nopen, double *__restrict__ Kw, long ldk,
-                                              long strideK, int *__restrict__ dims, int nt32) {
+__global__ __launch_bounds__(256) void k_zs_setup(const int *__restrict__ nopen, const double *__restrict__ Kw,
+                                                  long ldk, long strideK, double *__restrict__ aug, long ldaug,
+                                                  long strideA, long roff, double *__restrict__ gre,
+                                                  double *__restrict__ gim, long ldg, long strideG,
+                                                  int *__restrict__ dims) {
   const int e = blockIdx.y;
   const int no = nopen[e];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1394,34 +960,487 @@ __global__ __launch_bounds__(256) void k_symK(const int *__restrict__ nopen, dou
   if (i0 >= no) return;
   __shared__ double t1[32][33], t2[32][33];
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  double *K = Kw + (size_t)e * strideK;
+  const double *K = Kw + (size_t)e * strideK;
   for (int r = ty; r < 32; r += 8) {
     const int i = i0 + r, j = j0 + tx, i2 = j0 + r, j2 = i0 + tx;
     t1[r][tx] = (i < no && j < no) ? K[(size_t)i * ldk + j] : 0.0;
     t2[r][tx] = (i2 < no && j2 < no) ? K[(size_t)i2 * ldk + j2] : 0.0;
   }
   __syncthreads();
+  double *A = aug + (size_t)e * strideA;
+  double *Gr = gre + (size_t)e * strideG, *Gi = gim + (size_t)e * strideG;
   for (int r = ty; r < 32; r += 8) {
     const int i = i0 + r, j = j0 + tx, i2 = j0 + r, j2 = i0 + tx;
-    if (i < no && j < no) K[(size_t)i * ldk + j] = 0.5 * (t1[r][tx] + t2[tx][r]);
-    if (i2 < no && j2 < no) K[(size_t)i2 * ldk + j2] = 0.5 * (t2[r][tx] + t1[tx][r]);
+    if (i < no && j < no) {
+      A[(size_t)i * ldaug + j] = i == j ? 1.0 : 0.0;
+      A[(size_t)i * ldaug + roff + j] = -0.5 * (t1[r][tx] + t2[tx][r]);
+      Gr[(size_t)i * ldg + j] = 0.0;
+      Gi[(size_t)i * ldg + j] = 0.0;
+    }
+    if (ti != tj && i2 < no && j2 < no) {
+      A[(size_t)i2 * ldaug + j2] = 0.0;
+      A[(size_t)i2 * ldaug + roff + j2] = -0.5 * (t2[r][tx] + t1[tx][r]);
+      Gr[(size_t)i2 * ldg + j2] = 0.0;
+      Gi[(size_t)i2 * ldg + j2] = 0.0;
+    }
   }
 }
 
-void launch_symK(hipStream_t s, const Lay &L, const int *nopen, double *Kw, int *dims) {
+// Diagonal block [j0, j0 + jb): unblocked complex symmetric Cholesky of M11 in
+// LDS, C11 written back to the lower part of the planes, and L = C11^-1 (lower)
+// both to G's diagonal block and, as the real 64 x 64 matrix
+// Z = [[Lr, -Li], [Li, Lr]] (zero outside jb), to zinv for the block solves.
+// A pivot of zero modulus (possible only for non-finite input) sets
+// RM_PT_SINGULAR and is replaced by 1.
+__global__ __launch_bounds__(256) void k_zs_diag(int j0, const int *__restrict__ dims, double *__restrict__ aug,
+                                                 long ldaug, long strideA, long roff, double *__restrict__ gre,
+                                                 double *__restrict__ gim, long ldg, long strideG,
+                                                 double *__restrict__ zinv, int *__restrict__ status) {
+  const int e = blockIdx.x;
+  const int rows = dims[2 * e];
+  if (j0 >= rows) return;
+  const int jb = min(ZB, rows - j0);
+  double *Ar = aug + (size_t)e * strideA + (size_t)j0 * ldaug + j0;
+  double *Ai = Ar + roff;
+  __shared__ double cr[ZB][ZB + 1], ci[ZB][ZB + 1], xr[ZB][ZB + 1], xi[ZB][ZB + 1];
+  const int t = threadIdx.x;
+  for (int idx = t; idx < ZB * ZB; idx += 256) {
+    const int i = idx / ZB, k = idx % ZB;
+    const bool in = i < jb && k <= i;
+    cr[i][k] = in ? Ar[(size_t)i * ldaug + k] : (i == k ? 1.0 : 0.0);
+    ci[i][k] = in ? Ai[(size_t)i * ldaug + k] : 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < jb; ++j) {
+    if (t == 0) {
+      // principal square root of the pivot x + iy (x >= 1 in exact arithmetic)
+      double x = cr[j][j], y = ci[j][j];
+      const double r = hypot(x, y);
+      if (!(r > 0.0) || !isfinite(r)) {
+        atomicOr(status + e, RM_PT_SINGULAR);
+        x = 1.0;
+        y = 0.0;
+      }
+      double u, v;
+      if (x >= 0.0) {
+        u = sqrt(0.5 * (hypot(x, y) + x));
+        v = y / (2.0 * u);
+      } else {
+        v = copysign(sqrt(0.5 * (hypot(x, y) - x)), y);
+        u = y / (2.0 * v);
+      }
+      cr[j][j] = u;
+      ci[j][j] = v;
+    }
+    __syncthreads();
+    // column below the pivot: c_ij = m_ij / c_jj
+    const double dr = cr[j][j], di = ci[j][j], den = 1.0 / (dr * dr + di * di);
+    for (int i = j + 1 + t; i < jb; i += 256) {
+      const double ar = cr[i][j], ai = ci[i][j];
+      cr[i][j] = (ar * dr + ai * di) * den;
+      ci[i][j] = (ai * dr - ar * di) * den;
+    }
+    __syncthreads();
+    // m_ik -= c_ij c_kj (lower part of the trailing block)
+    const int c = jb - 1 - j;
+    for (int idx = t; idx < c * c; idx += 256) {
+      const int i = j + 1 + idx / c, k = j + 1 + idx % c;
+      if (k <= i) {
+        const double pr = cr[i][j] * cr[k][j] - ci[i][j] * ci[k][j];
+        const double pi = cr[i][j] * ci[k][j] + ci[i][j] * cr[k][j];
+        cr[i][k] -= pr;
+        ci[i][k] -= pi;
+      }
+    }
+    __syncthreads();
+  }
+  for (int idx = t; idx < jb * jb; idx += 256) {
+    const int i = idx / jb, k = idx % jb;
+    if (k <= i) {
+      Ar[(size_t)i * ldaug + k] = cr[i][k];
+      Ai[(size_t)i * ldaug + k] = ci[i][k];
+    }
+  }
+  // lane j of wave 0: column j of C11^-1 by forward substitution, into LDS
+  if (t < ZB) {
+    const int j = t;
+    for (int i = 0; i < ZB; ++i) {
+      double sr = i == j ? 1.0 : 0.0, si = 0.0;
+      for (int k = j; k < i; ++k) {
+        const double pr = cr[i][k], pi = ci[i][k], qr = xr[k][j], qi = xi[k][j];
+        sr -= pr * qr - pi * qi;
+        si -= pr * qi + pi * qr;
+      }
+      const double dr = cr[i][i], di = ci[i][i], den = 1.0 / (dr * dr + di * di);
+      xr[i][j] = i < j ? 0.0 : (sr * dr + si * di) * den;
+      xi[i][j] = i < j ? 0.0 : (si * dr - sr * di) * den;
+    }
+  }
+  __syncthreads();
+  double *Gr = gre + (size_t)e * strideG + (size_t)j0 * ldg + j0;
+  double *Gi = gim + (size_t)e * strideG + (size_t)j0 * ldg + j0;
+  double *Z = zinv + (size_t)e * ZK * ZK;
+  for (int idx = t; idx < ZB * ZB; idx += 256) {
+    const int i = idx / ZB, j = idx % ZB;
+    const bool in = i < jb && j < jb;
+    const double lr = in ? xr[i][j] : 0.0, li = in ? xi[i][j] : 0.0;
+    if (in) {
+      Gr[(size_t)i * ldg + j] = lr;
+      Gi[(size_t)i * ldg + j] = li;
+    }
+    Z[(size_t)i * ZK + j] = lr;
+    Z[(size_t)i * ZK + ZB + j] = -li;
+    Z[(size_t)(ZB + i) * ZK + j] = li;
+    Z[(size_t)(ZB + i) * ZK + ZB + j] = lr;
+  }
+}
+
+// Panel below the diagonal block: C21 = M21 C11^-T, one 64-row tile per item,
+// as the real product [M21r | M21i] Z^T = [C21r | C21i].  C21 is written to the
+// lower part of the planes and transposed into the upper part (rows [j0, j0 +
+// jb)), where the trailing update reads it as U.
+__global__ __launch_bounds__(256) void k_zs_panel(int j0, const int *__restrict__ dims, double *__restrict__ aug,
+                                                  long ldaug, long strideA, long roff,
+                                                  const double *__restrict__ zinv, int tiles_m, int ne) {
+  __shared__ double sA[TILE][Pitch<ZK>::A];  // sA[i][k] = [M21r | M21i][r0 + i][k]
+  __shared__ double sB[ZK][PB];              // sB[k][j] = Z[j][k]
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int kk = lane >> 4, ii = lane & 15;
+  for_items(ne, tiles_m, [&](int e, int tile) {
+    const int rows = dims[2 * e];
+    if (j0 >= rows) return;
+    const int jb = min(ZB, rows - j0);
+    const int c0 = j0 + jb, m = rows - c0, r0 = tile * TILE;
+    if (r0 >= m) return;
+    double *A = aug + (size_t)e * strideA;
+    const double *Z = zinv + (size_t)e * ZK * ZK;
+    for (int idx = t; idx < ZK * TILE; idx += 256) {
+      const int i = idx / ZK, k = idx % ZK, kc = k & (ZB - 1);
+      sA[i][k] = (r0 + i < m && kc < jb) ? A[(size_t)(c0 + r0 + i) * ldaug + (k < ZB ? 0 : roff) + j0 + kc] : 0.0;
+    }
+    for (int idx = t; idx < ZK * ZK; idx += 256) sB[idx / ZK][idx % ZK] = Z[(idx % ZK) * ZK + idx / ZK];
+    __syncthreads();
+    d4 acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = d4{0, 0, 0, 0};
+    mfma_slab<ZK>(sA, sB, acc, wr, wc, kk, ii);
+    // output column j: real part (j < ZB) or imaginary part (j >= ZB) of column j0 + (j mod ZB)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = wc * 32 + (q & 1) * 16 + ii, jc = j & (ZB - 1);
+      if (jc >= jb) continue;
+      const long off = j < ZB ? 0 : roff;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = wr * 32 + (q >> 1) * 16 + 4 * v + kk;
+        if (r0 + i < m) {
+          A[(size_t)(c0 + r0 + i) * ldaug + off + j0 + jc] = acc[q][v];
+          A[(size_t)(j0 + jc) * ldaug + off + c0 + r0 + i] = acc[q][v];
+        }
+      }
+    }
+    __syncthreads();
+  });
+}
+
+// Right-hand sides of the diagonal block left of it: G1 = C11^-1 B1 on G's rows
+// [j0, j0 + jb), columns [0, j0) (the diagonal block itself was written by
+// k_zs_diag), as the real product Z [B1r; B1i] = [G1r; G1i], one 64-column
+// tile per item, in place.
+__global__ __launch_bounds__(256) void k_zs_rhs(int j0, const int *__restrict__ dims, double *__restrict__ gre,
+                                                double *__restrict__ gim, long ldg, long strideG,
+                                                const double *__restrict__ zinv, int tiles_n, int ne) {
+  __shared__ double sL[ZK][Pitch<ZK>::A];  // sL[i][k] = Z[i][k]
+  __shared__ double sX[ZK][PB];            // sX[k][j] = [B1r; B1i][k][q0 + j]
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int kk = lane >> 4, ii = lane & 15;
+  for_items(ne, tiles_n, [&](int e, int tile) {
+    const int rows = dims[2 * e];
+    if (j0 >= rows) return;
+    const int jb = min(ZB, rows - j0);
+    const int q0 = tile * TILE;
+    if (q0 >= j0) return;
+    double *Gr = gre + (size_t)e * strideG + (size_t)j0 * ldg;
+    double *Gi = gim + (size_t)e * strideG + (size_t)j0 * ldg;
+    const double *Z = zinv + (size_t)e * ZK * ZK;
+    for (int idx = t; idx < ZK * ZK; idx += 256) sL[idx / ZK][idx % ZK] = Z[idx];
+    for (int idx = t; idx < ZK * TILE; idx += 256) {
+      const int k = idx / TILE, j = idx % TILE, kc = k & (ZB - 1);
+      sX[k][j] = (kc < jb && q0 + j < j0) ? (k < ZB ? Gr : Gi)[(size_t)kc * ldg + q0 + j] : 0.0;
+    }
+    __syncthreads();
+    d4 acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = d4{0, 0, 0, 0};
+    mfma_slab<ZK>(sL, sX, acc, wr, wc, kk, ii);
+    // output row i: real part (i < ZB) or imaginary part (i >= ZB) of row j0 + (i mod ZB)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = q0 + wc * 32 + (q & 1) * 16 + ii;
+      if (j >= j0) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = wr * 32 + (q >> 1) * 16 + 4 * v + kk, ic = i & (ZB - 1);
+        if (ic < jb) (i < ZB ? Gr : Gi)[(size_t)ic * ldg + j] = acc[q][v];
+      }
+    }
+    __syncthreads();
+  });
+}
+
+// U of the complex trailing update, stacked [Ur; Ui]: rows k < ZB from the
+// real plane, rows ZB + k from the imaginary one (rows past jb read as 0).
+struct ZRowsU {
+  const double *re, *im;
+  long ld;
+  int jb;
+  __device__ __forceinline__ double operator()(int k, long col) const {
+    const int kc = k & (ZB - 1);
+    return kc < jb ? (k < ZB ? re : im)[(long)kc * ld + col] : 0.0;
+  }
+};
+
+// Trailing update after the complex block [j0, j0 + jb), with c0 = j0 + jb:
+//   region 0: M22 -= C21 C21^T on rows [c0, rows), columns up to each row
+//             block's diagonal tile (the lower part; U = C21^T from the upper
+//             part of the planes);
+//   region 1: B2 -= C21 G1 on G's rows [c0, rows), columns [0, c0).
+// Each plane is a real rank-64 update with the stacked U [Ur; Ui] and sL holding
+// [-C21r | C21i] (real plane) or [-C21i | -C21r] (imaginary plane).
+// Items: (energy, region x plane x column group, 64-row block).
+__global__ __launch_bounds__(256, 2) void k_zs_update(int j0, const int *__restrict__ dims, double *__restrict__ aug,
+                                                   long ldaug, long strideA, long roff, double *__restrict__ gre,
+                                                   double *__restrict__ gim, long ldg, long strideG, int tiles_m,
+                                                   int groups, int ne) {
+  __shared__ double sL[TILE][Pitch<ZK>::A];
+  __shared__ double sU[ZK][PB];
+  for_items(ne, tiles_m * groups * 4, [&](int e, int it) {
+    const int tmi = it % tiles_m, rest = it / tiles_m;
+    const int g = rest % groups, kind = rest / groups;
+    const int plane = kind & 1, region = kind >> 1;
+    const int rows = dims[2 * e];
+    if (j0 >= rows) return;
+    const int jb = min(ZB, rows - j0);
+    const int c0 = j0 + jb, m = rows - c0, r0 = tmi * TILE, vbeg = g * UPD_G * TILE;
+    if (r0 >= m) return;
+    const int ncols = region == 0 ? min(m, r0 + TILE) : c0;
+    if (vbeg >= ncols) return;
+    double *A = aug + (size_t)e * strideA;
+    for (int idx = threadIdx.x; idx < ZK * TILE; idx += 256) {
+      const int i = idx / ZK, k = idx % ZK, kc = k & (ZB - 1);
+      double x = 0.0;
+      if (r0 + i < m && kc < jb) {
+        const double *c = A + (size_t)(c0 + r0 + i) * ldaug + j0 + kc;
+        if (plane == 0)
+          x = k < ZB ? -c[0] : c[roff];
+        else
+          x = k < ZB ? -c[roff] : -c[0];
+      }
+      sL[i][k] = x;
+    }
+    if (region == 0) {
+      const double *U = A + (size_t)j0 * ldaug;
+      rowblock_update<ZK, UPD_G>(sL, sU, m - r0, vbeg, ncols, ColMap{ncols, c0, 0},
+                                 A + (size_t)(c0 + r0) * ldaug + (plane ? roff : 0), ZRowsU{U, U + roff, ldaug, jb},
+                                 ldaug);
+    } else {
+      double *Gr = gre + (size_t)e * strideG, *Gi = gim + (size_t)e * strideG;
+      rowblock_update<ZK, UPD_G>(sL, sU, m - r0, vbeg, ncols, ColMap{ncols, 0, 0},
+                                 (plane ? Gi : Gr) + (size_t)(c0 + r0) * ldg,
+                                 ZRowsU{Gr + (size_t)j0 * ldg, Gi + (size_t)j0 * ldg, ldg, jb}, ldg);
+    }
+  });
+}
+
+void launch_zs_factor(hipStream_t s, int ne, int maxrows, const int *dims, double *aug, long ldaug, long strideA,
+                      long roff, double *gre, double *gim, long ldg, long strideG, double *zinv, int *status) {
+  for (int j0 = 0; j0 < maxrows; j0 += ZB) {
+    hipLaunchKernelGGL(k_zs_diag, dim3(ne), dim3(256), 0, s, j0, dims, aug, ldaug, strideA, roff, gre, gim, ldg,
+                       strideG, zinv, status);
+    const int c0 = std::min(maxrows, j0 + ZB), m = maxrows - c0;
+    if (m > 0) {
+      const int tm = (m + TILE - 1) / TILE;
+      hipLaunchKernelGGL(k_zs_panel, dim3(persist_grid(k_zs_panel, 256, ne, tm)), dim3(256), 0, s, j0, dims, aug,
+                         ldaug, strideA, roff, zinv, tm, ne);
+    }
+    if (j0 > 0) {
+      const int tn = (j0 + TILE - 1) / TILE;
+      hipLaunchKernelGGL(k_zs_rhs, dim3(persist_grid(k_zs_rhs, 256, ne, tn)), dim3(256), 0, s, j0, dims, gre, gim,
+                         ldg, strideG, zinv, tn, ne);
+    }
+    if (m > 0) {
+      const int tm = (m + TILE - 1) / TILE, gr = (std::max(m, c0) + UPD_G * TILE - 1) / (UPD_G * TILE);
+      hipLaunchKernelGGL(k_zs_update, dim3(persist_grid(k_zs_update, 256, ne, (long)tm * gr * 4)), dim3(256), 0, s,
+                         j0, dims, aug, ldaug, strideA, roff, gre, gim, ldg, strideG, tm, gr, ne);
+    }
+  }
+}
+
+// M^-1 = G^T G (complex, G lower triangular) in 128 x 128 output tiles of the
+// lower triangle, mirrored, written over the planes of aug:
+//   Re = Gr^T Gr - Gi^T Gi,   Im = Gr^T Gi + Gi^T Gr.
+// Eight waves per workgroup, each owning a 64 x 32 block of both parts; K slabs
+// of 16 are staged through LDS with the next slab loaded into registers while
+// the current one is multiplied.  Because G_ki = 0 for k < i, a tile of rows
+// [r0, r0 + 128) sums over k >= r0 only.
+__global__ __launch_bounds__(512, 1) void k_zs_gtg(const int *__restrict__ dims, const double *__restrict__ gre,
+                                                   const double *__restrict__ gim, long ldg, long strideG,
+                                                   double *__restrict__ aug, long ldaug, long strideA, long roff,
+                                                   int tiles_n, int ne) {
+  constexpr int BT = 2 * TILE, GK = 16, NT = 512;
+  constexpr int NL = BT * GK / NT;  // slab elements per thread and operand
+  __shared__ double sar[BT][Pitch<GK>::A], sai[BT][Pitch<GK>::A];  // [i][k] = G[k0 + k][r0 + i]
+  __shared__ double sbr[GK][BT], sbi[GK][BT];                      // [k][j] = G[k0 + k][q0 + j]
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wr = wave >> 2, wc = wave & 3;  // 2 x 4 waves: rows wr*64, columns wc*32
+  const int kk = lane >> 4, ii = lane & 15;
+  for_items(ne, tiles_n * tiles_n, [&](int e, int it) {
+    const int n = dims[2 * e];
+    const int tm = it / tiles_n, tn = it % tiles_n;
+    const int r0 = tm * BT, q0 = tn * BT;
+    if (r0 >= n || q0 >= n || tn > tm) return;
+    const double *Gr = gre + (size_t)e * strideG, *Gi = gim + (size_t)e * strideG;
+    double ar[NL], ai[NL], br[NL], bi[NL];
+    auto gload = [&](int k0) {
+#pragma unroll
+      for (int q = 0; q < NL; ++q) {
+        const int idx = t + NT * q;
+        const int c = idx % BT, k = k0 + idx / BT;
+        const bool kin = k < n;
+        const size_t ra = (size_t)k * ldg + r0 + c, rb = (size_t)k * ldg + q0 + c;
+        const bool aok = kin && r0 + c < n, bok = kin && q0 + c < n;
+        ar[q] = aok ? Gr[ra] : 0.0;
+        ai[q] = aok ? Gi[ra] : 0.0;
+        br[q] = bok ? Gr[rb] : 0.0;
+        bi[q] = bok ? Gi[rb] : 0.0;
+      }
+    };
+    d4 accr[8], acci[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      accr[q] = d4{0, 0, 0, 0};
+      acci[q] = d4{0, 0, 0, 0};
+    }
+    gload(r0);
+    for (int k0 = r0; k0 < n; k0 += GK) {
+#pragma unroll
+      for (int q = 0; q < NL; ++q) {
+        const int idx = t + NT * q;
+        sar[idx % BT][idx / BT] = ar[q];
+        sai[idx % BT][idx / BT] = ai[q];
+        sbr[idx / BT][idx % BT] = br[q];
+        sbi[idx / BT][idx % BT] = bi[q];
+      }
+      __syncthreads();
+      if (k0 + GK < n) gload(k0 + GK);
+#pragma unroll
+      for (int ks = 0; ks < GK; ks += 4) {
+        double xr[4], xi[4], yr[2], yi[2];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          xr[m] = sar[wr * 64 + m * 16 + ii][ks + kk];
+          xi[m] = sai[wr * 64 + m * 16 + ii][ks + kk];
+        }
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+          yr[m] = sbr[ks + kk][wc * 32 + m * 16 + ii];
+          yi[m] = sbi[ks + kk][wc * 32 + m * 16 + ii];
+        }
+#pragma unroll
+        for (int mr = 0; mr < 4; ++mr)
+#pragma unroll
+          for (int mc = 0; mc < 2; ++mc) {
+            d4 &cr = accr[mr * 2 + mc], &ci = acci[mr * 2 + mc];
+            cr = mfma64(xr[mr], yr[mc], cr);
+            cr = mfma64(-xi[mr], yi[mc], cr);
+            ci = mfma64(xr[mr], yi[mc], ci);
+            ci = mfma64(xi[mr], yr[mc], ci);
+          }
+      }
+      __syncthreads();
+    }
+    double *A = aug + (size_t)e * strideA;
+#pragma unroll
+    for (int mr = 0; mr < 4; ++mr)
+#pragma unroll
+      for (int mc = 0; mc < 2; ++mc) {
+        const int j = q0 + wc * 32 + mc * 16 + ii;
+        if (j >= n) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = r0 + wr * 64 + mr * 16 + 4 * v + kk;
+          if (i < n) {
+            const double xr = accr[mr * 2 + mc][v], xi = acci[mr * 2 + mc][v];
+            A[(size_t)i * ldaug + j] = xr;
+            A[(size_t)i * ldaug + roff + j] = xi;
+            if (tm != tn) {
+              A[(size_t)j * ldaug + i] = xr;
+              A[(size_t)j * ldaug + roff + i] = xi;
+            }
+          }
+        }
+      }
+  });
+}
+
+void launch_zs_setup(hipStream_t s, const Lay &L, const int *nopen, const double *Kw, double *aug, double *gre,
+                     double *gim, int *dims) {
   const int nt32 = (L.nmax + 31) / 32;
-  hipLaunchKernelGGL(k_symK, dim3(nt32 * (nt32 + 1) / 2, L.ne), dim3(256), 0, s, nopen, Kw, L.ldk, L.sK, dims, nt32);
+  hipLaunchKernelGGL(k_zs_setup, dim3(nt32 * (nt32 + 1) / 2, L.ne), dim3(256), 0, s, nopen, Kw, L.ldk, L.sK, aug,
+                     L.ldaug, L.sA, L.roff, gre, gim, L.ldk, L.sK, dims);
+}
+
+void launch_zs_inverse(hipStream_t s, const Lay &L, const int *dims, double *aug, double *gre, double *gim,
+                       double *zinv, int *status) {
+  if (L.nmax <= 0) return;
+  launch_zs_factor(s, L.ne, L.nmax, dims, aug, L.ldaug, L.sA, L.roff, gre, gim, L.ldk, L.sK, zinv, status);
+  const int tn = (L.nmax + 2 * TILE - 1) / (2 * TILE);
+  hipLaunchKernelGGL(k_zs_gtg, dim3(persist_grid(k_zs_gtg, 512, L.ne, (long)tn * tn)), dim3(512), 0, s, dims, gre,
+                     gim, L.ldk, L.sK, aug, L.ldaug, L.sA, L.roff, tn, L.ne);
+}
+
+// ---------------------------------------------------------------------------
+// K gather, collision strengths
+// ---------------------------------------------------------------------------
+// K from the solution: the last nopen rows of Y (the open unknowns) as solved
+// (not symmetrised; the S/Omega stage symmetrises its own copy), with zeros for
+// i or j in [nopen, n); also dims = {nopen, nopen} for the S/Omega stage.
+__global__ __launch_bounds__(256) void k_gatherK(const DevPW *__restrict__ tab, const int *__restrict__ pwi,
+                                                 const int *__restrict__ nopen, const double *__restrict__ aug,
+                                                 long ldaug, long strideA, long roff, double *__restrict__ Kw, long ldk,
+                                                 long strideK, int *__restrict__ dims) {
+  const int e = blockIdx.y, i = blockIdx.x;
+  const int n = tab[pwi[e]].n, no = nopen[e];
+  if (i == 0 && threadIdx.x == 0) {
+    dims[2 * e] = no;
+    dims[2 * e + 1] = no;
+  }
+  if (i >= n) return;
+  const double *Y = aug + (size_t)e * strideA + (size_t)(n - no + i) * ldaug + roff;
+  double *K = Kw + (size_t)e * strideK + (size_t)i * ldk;
+  for (int j = threadIdx.x; j < n; j += 256) K[j] = (i < no && j < no) ? Y[j] : 0.0;
+}
+
+void launch_gatherK(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *nopen,
+                    const double *aug, double *Kw, int *dims) {
+  hipLaunchKernelGGL(k_gatherK, dim3(L.nmax, L.ne), dim3(256), 0, s, tab, pwi, nopen, aug, L.ldaug, L.sA, L.roff, Kw,
+                     L.ldk, L.sK, dims);
 }
 
 
 // Omega_pq for one energy and one target row p per wave; lanes stride over q.
-// Each entry sums its channel pairs in a fixed order (no atomics), so results
-// do not depend on scheduling.
+// |T_ij|^2 = 4 |(M^-1)_ij - d_ij|^2 with the real and imaginary parts of M^-1 in
+// X and Y.  Each entry sums its channel pairs in a fixed order (no atomics), so
+// results do not depend on scheduling.
 __global__ __launch_bounds__(64) void k_omega(const DevPW *__restrict__ tab, const int *__restrict__ pwi,
                                               const int *__restrict__ openpos, long ldo,
-                                              const double *__restrict__ X, long ldx, long sX,
-                                              const double *__restrict__ XK, long ldxk, long sXK,
-                                              double *__restrict__ omega, int ntmax) {
+                                              const double *__restrict__ X, const double *__restrict__ Y, long ldx,
+                                              long sX, double *__restrict__ omega, int ntmax) {
   const int pt = blockIdx.x, e = blockIdx.y;
   const DevPW &pw = tab[pwi[e]];
   const int nt = pw.nt;
@@ -1430,7 +1449,7 @@ __global__ __launch_bounds__(64) void k_omega(const DevPW *__restrict__ tab, con
   const int *tptr = pw.tptr, *tch = pw.tch;
   const int *pos = openpos + (size_t)e * ldo;
   const double *Xe = X + (size_t)e * sX;
-  const double *Ye = XK + (size_t)e * sXK;
+  const double *Ye = Y + (size_t)e * sX;
   for (int q = threadIdx.x; q < nt; q += 64) {
     double acc = 0.0;
     for (int a = tptr[pt]; a < tptr[pt + 1]; ++a) {
@@ -1439,18 +1458,18 @@ __global__ __launch_bounds__(64) void k_omega(const DevPW *__restrict__ tab, con
       for (int b = tptr[q]; b < tptr[q + 1]; ++b) {
         const int j = pos[tch[b]];
         if (j < 0) continue;
-        const double x = Xe[(size_t)i * ldx + j], y = Ye[(size_t)i * ldxk + j];
-        acc += 4.0 * (y * y + x * x);
+        const double x = Xe[(size_t)i * ldx + j] - (i == j ? 1.0 : 0.0), y = Ye[(size_t)i * ldx + j];
+        acc += 4.0 * (x * x + y * y);
       }
     }
     omega[((size_t)e * ntmax + pt) * ntmax + q] = half_g * acc;
   }
 }
 
-// S_ij = d_ij - 2 (XK)_ij + 2i X_ij on the leading no x no block, zero elsewhere
+// S = 2 M^-1 - 1 on the leading no x no block, zero elsewhere
 __global__ void k_smatrix(const DevPW *__restrict__ tab, const int *__restrict__ pwi, const int *__restrict__ nopen,
-                          const double *__restrict__ X, long ldx, long sX, const double *__restrict__ XK, long ldxk,
-                          long sXK, double *__restrict__ S, int nmax) {
+                          const double *__restrict__ X, const double *__restrict__ Y, long ldx, long sX,
+                          double *__restrict__ S, int nmax) {
   const int e = blockIdx.z, i = blockIdx.y;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int n = tab[pwi[e]].n;
@@ -1458,8 +1477,8 @@ __global__ void k_smatrix(const DevPW *__restrict__ tab, const int *__restrict__
   const int no = nopen[e];
   double re = 0.0, im = 0.0;
   if (i < no && j < no) {
-    re = (i == j ? 1.0 : 0.0) - 2.0 * XK[(size_t)e * sXK + (size_t)i * ldxk + j];
-    im = 2.0 * X[(size_t)e * sX + (size_t)i * ldx + j];
+    re = 2.0 * X[(size_t)e * sX + (size_t)i * ldx + j] - (i == j ? 1.0 : 0.0);
+    im = 2.0 * Y[(size_t)e * sX + (size_t)i * ldx + j];
   }
   double *o = S + (((size_t)e * nmax + i) * nmax + j) * 2;
   o[0] = re;
@@ -1467,12 +1486,12 @@ __global__ void k_smatrix(const DevPW *__restrict__ tab, const int *__restrict__
 }
 
 void launch_omega(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *openpos,
-                  const int *nopen, const double *X, const double *XK, double *omega, double *S) {
-  hipLaunchKernelGGL(k_omega, dim3(L.ntmax, L.ne), dim3(64), 0, s, tab, pwi, openpos, L.ldo, X, L.ldaug, L.sA, XK,
-                     L.ldk, L.sK, omega, L.ntmax);
+                  const int *nopen, const double *X, const double *Y, double *omega, double *S) {
+  hipLaunchKernelGGL(k_omega, dim3(L.ntmax, L.ne), dim3(64), 0, s, tab, pwi, openpos, L.ldo, X, Y, L.ldaug, L.sA,
+                     omega, L.ntmax);
   if (S)
-    hipLaunchKernelGGL(k_smatrix, dim3((L.nmax + 63) / 64, L.nmax, L.ne), dim3(64), 0, s, tab, pwi, nopen, X,
-                       L.ldaug, L.sA, XK, L.ldk, L.sK, S, L.nmax);
+    hipLaunchKernelGGL(k_smatrix, dim3((L.nmax + 63) / 64, L.nmax, L.ne), dim3(64), 0, s, tab, pwi, nopen, X, Y,
+                       L.ldaug, L.sA, S, L.nmax);
 }
 
 // Flag non-finite results and overwrite the outputs of flagged energies with NaN.

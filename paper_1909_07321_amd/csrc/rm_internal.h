@@ -77,7 +77,7 @@ struct Lay {
   int nmax = 0, npadmax = 0, Mpadmax = 0, ntmax = 0;
   long ldD = 0;                 // d(E) rows: Mpadmax
   long ldaug = 0, roff = 0, sA = 0;  // [A | B]: ldaug = 2 npadmax, B at column roff = npadmax
-  long ldk = 0, sK = 0;         // K and XK: ldk = npadmax, sK = nmax * ldk
+  long ldk = 0, sK = 0;         // K, gre and gim: ldk = npadmax, sK = nmax * ldk
   long ldo = 0;                 // per-channel arrays (fg has 4 per channel): nmax
   long sOm = 0;                 // Omega: ntmax * ntmax per energy
 };
@@ -118,11 +118,12 @@ struct Work {
   double *fg = nullptr;      // [cap_e][ldo][4]
   double *aug = nullptr;     // [cap_e][nmax][ldaug]
   double *Kw = nullptr;      // [cap_e][nmax][ldk]
-  double *XK = nullptr;      // [cap_e][nmax][ldk]
+  double *gre = nullptr;     // [cap_e][nmax][ldk] real part of G = C^-1 (S/Omega stage)
+  double *gim = nullptr;     // [cap_e][nmax][ldk] imaginary part of G
   int *dims = nullptr;       // [cap_e][2] per-energy (rows, rhs) for batched LU
   int *ipiv = nullptr;       // [cap_e][ldo] LU row interchanges
   int *bperm = nullptr;      // [cap_e][BPERM] net permutation of the current LU block
-  double *linv = nullptr;    // [cap_e][NBU][NBU] inverse of the current block's unit lower L11
+  double *linv = nullptr;    // [cap_e][NBU][NBU] inverse of the current diagonal block (LU and S/Omega)
   double *omega = nullptr;   // [cap_e][ntmax][ntmax]
   double *pack = nullptr;    // packed outputs, [cap_e][nmax][nmax] doubles
   long *pack_off = nullptr;  // [cap_e + 1] offsets of each energy's packed block
@@ -164,31 +165,21 @@ void launch_lu_solve(hipStream_t s, int ne, int maxrows, int maxrhs, const int *
 // the upper triangle of each block of rows).
 void launch_backsub(hipStream_t s, int ne, int maxrows, int maxrhs, const int *dims, double *aug, long ldaug,
                     long strideA, long roff, int tail);
-// Cholesky forward phase of [P | K] for symmetric positive definite P (lower
-// triangle read): L in the lower and L^T in the upper triangle, Z = L^-1 K in
-// the right-hand sides.  linv is scratch of ne * NBU * NBU doubles.
-void launch_chol_forward(hipStream_t s, int ne, int maxrows, int maxrhs, const int *dims, double *aug, long ldaug,
-                         long strideA, long roff, double *linv, int *status);
-// K <- (K + K^T) / 2 on each energy's leading nopen x nopen block; dims = {nopen, nopen}.
-void launch_symK(hipStream_t s, const Lay &L, const int *nopen, double *Kw, int *dims);
-// [1 + K K | K] in aug (lower block tiles of 1 + K K; K in the right-hand sides at roff).
-void launch_formP(hipStream_t s, int ne, int maxn, const int *nopen, const double *K, long ldk, long sK, double *aug,
-                  long ldaug, long sA, long roff);
-// Lower block tiles of C = A B (no x no) for products known to be symmetric.
-void launch_gemm_lower(hipStream_t s, int ne, int maxn, const int *nopen, const double *A, long lda, long sA,
-                       const double *B, long ldb, long sB, double *C, long ldc, long sC);
-// C = A^T A (no x no), both triangles.
-void launch_gemm_ata(hipStream_t s, int ne, int maxn, const int *nopen, const double *A, long lda, long sA, double *C,
-                     long ldc, long sC);
-// C[e] = A[e] B[e] for square no x no blocks, no = nopen[e]
-void launch_gemm_sq(hipStream_t s, int ne, int maxn, const int *nopen, const double *A, long lda, long sA,
-                    const double *B, long ldb, long sB, double *C, long ldc, long sC);
-// K = the last nopen rows of the solution (the open channels, ascending),
-// symmetrised, zero past nopen; dims = {nopen, nopen}.
+// S/Omega stage, set-up: M = 1 - i (K + K^T)/2 in aug (real part in columns [0,
+// no), imaginary part at roff), G = 0 in gre/gim; dims = {no, no}.
+void launch_zs_setup(hipStream_t s, const Lay &L, const int *nopen, const double *Kw, double *aug, double *gre,
+                     double *gim, int *dims);
+// Complex symmetric Cholesky M = C C^T (no pivoting) with G = C^-1 carried
+// along, then M^-1 = G^T G over the planes of aug (both triangles).  A zero
+// pivot sets RM_PT_SINGULAR.  zinv is scratch of ne * NBU * NBU doubles.
+void launch_zs_inverse(hipStream_t s, const Lay &L, const int *dims, double *aug, double *gre, double *gim,
+                       double *zinv, int *status);
+// K = the last nopen rows of the solution (the open channels, ascending), as
+// solved, zero past nopen; dims = {nopen, nopen}.
 void launch_gatherK(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *nopen,
                     const double *aug, double *Kw, int *dims);
 void launch_omega(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *openpos,
-                  const int *nopen, const double *X, const double *XK, double *omega, double *S);
+                  const int *nopen, const double *X, const double *Y, double *omega, double *S);
 void launch_finalize(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, int *status, double *omega,
                      double *K, double *S);
 void launch_check_inputs(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const double *E,

@@ -166,7 +166,7 @@ constexpr double TUNE_MARGIN = 0.03;
 
 size_t per_energy_bytes(int n, int npad, int Mpad, int nt) {
   return (size_t)n * 2 * npad * 8    // aug
-         + (size_t)n * npad * 8 * 2  // Kw, XK
+         + (size_t)n * npad * 8 * 3  // Kw, gre, gim
          + (size_t)n * n * 8         // packed outputs
          + (size_t)Mpad * 12         // D64 + D32
          + (size_t)n * (32 + 17)     // fg, openidx, openpos, colpos, openflag, ipiv
@@ -176,7 +176,7 @@ size_t per_energy_bytes(int n, int npad, int Mpad, int nt) {
 
 void free_work(Work &w) {
   void *ptrs[] = {w.E, w.pwi, w.tab, w.tasks, w.counter, w.D64, w.D32, w.win, w.status, w.nopen, w.openidx,
-                  w.openpos, w.colpos, w.openflag, w.fg, w.aug, w.Kw, w.XK, w.dims, w.ipiv, w.bperm, w.linv, w.omega, w.pack, w.pack_off,
+                  w.openpos, w.colpos, w.openflag, w.fg, w.aug, w.Kw, w.gre, w.gim, w.dims, w.ipiv, w.bperm, w.linv, w.omega, w.pack, w.pack_off,
                   w.S};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -220,8 +220,8 @@ rm_status ensure_slot(rm_ctx *ctx, Slot &sl, const Lay &L, int ntab, int ntasks,
                  bpack = sz((size_t)ce * std::max((size_t)cn * cn, (size_t)ct * ct) * 8),
                  boff = sz((size_t)(ce + 1) * 8), bS = S ? sz((size_t)ce * cn * cn * 16) : 0,
                  bperm = sz((size_t)ce * BPERM * 4), blinv = sz((size_t)ce * NBU * NBU * 8);
-    // openpos, colpos and ipiv share bidx's size, XK shares bK's, the pack offsets are two blocks
-    need += 3 * ((bidx + 255) / 256 * 256) + (bK + 255) / 256 * 256 + (boff + 255) / 256 * 256;
+    // openpos, colpos and ipiv share bidx's size, gre and gim share bK's, the pack offsets are two blocks
+    need += 3 * ((bidx + 255) / 256 * 256) + 2 * ((bK + 255) / 256 * 256) + (boff + 255) / 256 * 256;
     {
       std::lock_guard<std::mutex> g(ctx->mu);
       if (ctx->resident + ctx->work_bytes - w.bytes + need > ctx->budget) {
@@ -256,7 +256,8 @@ rm_status ensure_slot(rm_ctx *ctx, Slot &sl, const Lay &L, int ntab, int ntasks,
     HIPCHK(hipMalloc(&w.fg, bfg));
     HIPCHK(hipMalloc(&w.aug, baug));
     HIPCHK(hipMalloc(&w.Kw, bK));
-    HIPCHK(hipMalloc(&w.XK, bK));
+    HIPCHK(hipMalloc(&w.gre, bK));
+    HIPCHK(hipMalloc(&w.gim, bK));
     HIPCHK(hipMalloc(&w.dims, bdims));
     HIPCHK(hipMalloc(&w.omega, bom));
     HIPCHK(hipMalloc(&w.pack, bpack));
@@ -457,14 +458,12 @@ void stage_K(const Plan &P, Work &w, hipStream_t s) {
 }
 
 void stage_SO(const Plan &P, Work &w, bool want_S, hipStream_t s) {
-  // K (symmetric, in Kw); P = 1 + K K = L L^T (Cholesky) with Z = L^-1 K carried
-  // along; XK = K P^-1 K = Z^T Z; X = P^-1 K = L^-T Z; then Omega
+  // M = 1 - iK from K (symmetrised copy); M^-1 by a complex symmetric Cholesky
+  // factorisation; then Omega (and S) from M^-1
   const Lay &L = P.L;
-  launch_formP(s, L.ne, L.nmax, w.nopen, w.Kw, L.ldk, L.sK, w.aug, L.ldaug, L.sA, L.roff);
-  launch_chol_forward(s, L.ne, L.nmax, L.nmax, w.dims, w.aug, L.ldaug, L.sA, L.roff, w.linv, w.status);
-  launch_gemm_ata(s, L.ne, L.nmax, w.nopen, w.aug + L.roff, L.ldaug, L.sA, w.XK, L.ldk, L.sK);
-  launch_backsub(s, L.ne, L.nmax, L.nmax, w.dims, w.aug, L.ldaug, L.sA, L.roff, 0);
-  launch_omega(s, L, w.tab, w.pwi, w.openpos, w.nopen, w.aug + L.roff, w.XK, w.omega, want_S ? w.S : nullptr);
+  launch_zs_setup(s, L, w.nopen, w.Kw, w.aug, w.gre, w.gim, w.dims);
+  launch_zs_inverse(s, L, w.dims, w.aug, w.gre, w.gim, w.linv, w.status);
+  launch_omega(s, L, w.tab, w.pwi, w.openpos, w.nopen, w.aug, w.aug + L.roff, w.omega, want_S ? w.S : nullptr);
 }
 
 hipMemcpyKind kind_out(const rm_opts &o) { return o.device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost; }
@@ -562,7 +561,7 @@ std::string chunk_key(rm_ctx *ctx, const Plan &P, const Work &w, const rm_opts &
                         (const void *)w.counter, (const void *)w.D64, (const void *)w.D32, (const void *)w.win,
                         (const void *)w.status, (const void *)w.nopen, (const void *)w.openidx,
                         (const void *)w.openpos, (const void *)w.colpos, (const void *)w.openflag,
-                        (const void *)w.fg, (const void *)w.aug, (const void *)w.Kw, (const void *)w.XK,
+                        (const void *)w.fg, (const void *)w.aug, (const void *)w.Kw, (const void *)w.gre, (const void *)w.gim,
                         (const void *)w.dims, (const void *)w.ipiv, (const void *)w.bperm, (const void *)w.linv,
                         (const void *)w.omega, (const void *)w.pack, (const void *)w.pack_off})
     add(p);
@@ -1279,7 +1278,6 @@ rm_status rm_collision_strengths(rm_ctx *ctx, int32_t pwid, const double *E, int
                             sizeof(double) * n, (size_t)m * n, kind_in(o), s));
     launch_openlist(s, L, w.tab, w.pwi, w.E, w.nopen, w.openidx, w.openpos, w.colpos, w.openflag);
     launch_check_inputs(s, L, w.tab, w.pwi, w.E, o.thr_guard, nullptr, nullptr, w.Kw, w.nopen, w.status);
-    launch_symK(s, L, w.nopen, w.Kw, w.dims);
     stage_SO(P, w, S != nullptr, s);
     launch_finalize(s, L, w.tab, w.pwi, w.status, w.omega, nullptr, S ? w.S : nullptr);
     HIPCHK(hipMemcpyAsync(omega + (size_t)e0 * nt * nt, w.omega, sizeof(double) * m * nt * nt, kind_out(o), s));

@@ -9,6 +9,8 @@ import pytest
 import oracle
 from paper_1909_07321_amd import synth
 
+from _metrics import gate, k_err, omega_elementwise, stats
+
 pytestmark = pytest.mark.gpu
 
 
@@ -46,17 +48,19 @@ def test_batch_equals_alone(ctx, waves, prec):
         ctx.pw_release(pid)
 
 
-def test_batch_matches_oracle_small_waves(ctx, waves):
+def test_batch_matches_oracle(ctx, waves):
     pws, E = waves
-    ids = [ctx.pw_upload(p) for p in pws[:3]]
+    ids = [ctx.pw_upload(p) for p in pws]
     sel = E[::6]
-    outs = ctx.run_batch([(pid, sel) for pid in ids])
-    for p, (om, K, st) in zip(pws[:3], outs):
+    outs = ctx.run_batch([(pid, sel) for pid in ids], want_K=True)
+    for p, (om, K, st) in zip(pws, outs):
         ref = oracle.Oracle(p).run(sel)
         assert (st == 0).all() and (ref["status"] == 0).all()
-        c = np.nan_to_num(ref["cond"], nan=1.0)
-        g = np.where(c <= 1e4, 1e-10, np.maximum(1e-10, 1e-15 * c))
-        errO = np.abs(om - ref["omega"]).reshape(sel.size, -1).max(1) / np.abs(ref["omega"]).reshape(sel.size, -1).max(1)
+        g = gate(ref["cond"])
+        errO = omega_elementwise(om, ref["omega"])
+        errK = k_err(K, ref["K"], oracle.open_count(p, sel))
+        print(f"batched wave of {p.nchan} channels: K {stats(errK)}, Omega {stats(errO)}", flush=True)
         assert (errO <= g).all(), (errO, g)
+        assert (errK <= g).all(), (errK, g)
     for pid in ids:
         ctx.pw_release(pid)

@@ -10,6 +10,8 @@ import pytest
 import oracle
 from paper_1909_07321_amd import synth
 
+from _metrics import GATE, SPLIT_K, SPLIT_OMEGA, SPLIT_R, gate, k_err, normwise, omega_elementwise
+
 pytestmark = pytest.mark.gpu
 
 
@@ -59,7 +61,7 @@ def test_c4_R_sampled_entries(ctx, c4, c4_pid, prec):
         scale = np.abs(R).reshape(sel.size, -1).max(axis=1)   # normwise per energy
         worst = max(worst, (np.abs(R[:, i, j] - ref) / scale).max())
     _say(f"c4 R sampled entries worst normwise {worst:.2e}")
-    assert worst < (1e-10 if prec == 0 else 1e-5)
+    assert worst < (GATE if prec == 0 else SPLIT_R)
 
 
 def test_c4_full_energy_vs_oracle(ctx, c4, c4_pid):
@@ -67,39 +69,39 @@ def test_c4_full_energy_vs_oracle(ctx, c4, c4_pid):
     sel = E[[500]]
     om, K, st = ctx.run(c4_pid, sel)
     res = oracle.Oracle(pw, nthreads=16).run(sel)
-    no = oracle.open_count(pw, sel)[0]
+    no = oracle.open_count(pw, sel)
     assert st[0] == 0 and res["status"][0] == 0
-    Ko = res["K"][0, :no, :no]
-    errK = np.abs(K[0, :no, :no] - Ko).max() / max(1, np.abs(Ko).max())
-    floor = 1e-12 * res["omega"].max()
-    errO = (np.abs(om - res["omega"]) / np.maximum(np.abs(res["omega"]), floor)).max()
-    _say(f"c4 E={sel[0]:.3f} no={no} cond={res['cond'][0]:.2e} K err {errK:.2e} Omega err {errO:.2e}")
-    g = 1e-10 if res["cond"][0] <= 1e4 else max(1e-10, 1e-15 * res["cond"][0])
-    errO = np.abs(om - res["omega"]).max() / np.abs(res["omega"]).max()
-    _say(f"c4 normwise Omega err {errO:.2e}, gate {g:.1e}")
+    errK = k_err(K, res["K"], no)[0]
+    errO = omega_elementwise(om, res["omega"])[0]
+    g = gate(res["cond"])[0]
+    _say(f"c4 E={sel[0]:.3f} no={no[0]} cond={res['cond'][0]:.2e} K err {errK:.2e} Omega elementwise err"
+         f" {errO:.2e}, gate {g:.1e}")
     assert errK <= g and errO <= g
-    # split mode on the same energy: stated tolerance
+    # split mode on the same energy: the stated tolerance
     om2, K2, st2 = ctx.run(c4_pid, sel, prec=1)
-    errK2 = np.abs(K2[0, :no, :no] - Ko).max() / max(1, np.abs(Ko).max())
-    errO2 = np.abs(om2 - res["omega"]).max() / np.abs(res["omega"]).max()
+    errK2 = k_err(K2, res["K"], no)[0]
+    errO2 = normwise(om2, res["omega"])[0]
     _say(f"c4 split K err {errK2:.2e} Omega err {errO2:.2e} (normwise; cond {res['cond'][0]:.1e})")
-    assert errK2 <= 1e-5 * max(1.0, res["cond"][0]) and errO2 <= 1e-5 * max(1.0, res["cond"][0])
+    assert errK2 <= SPLIT_K and errO2 <= SPLIT_OMEGA
 
 
 def test_c4_run_properties(ctx, c4, c4_pid):
     """Properties at full size (every 16th energy): finite, non-negative and
-    symmetric Omega, symmetric K.  The matching matrices here have condition
-    estimates up to ~1e8, so symmetry holds to ~1e-15 * cond."""
+    symmetric Omega (to rounding: the diagonal tiles of M^-1 and the two orders
+    of each Omega pair sum the same products in different orders), and the
+    solved K symmetric to the accuracy of the solve (the matching matrices
+    here have condition estimates up to ~1e8, so ~1e-15 * cond)."""
     pw, E = c4
     sel = E[::16]
     om, K, st = ctx.run(c4_pid, sel)
     assert (st == 0).all(), st
     assert np.isfinite(om).all() and om.min() >= 0
-    assert np.abs(om - np.transpose(om, (0, 2, 1))).max() <= 1e-6 * om.max()
+    sym = np.abs(om - np.transpose(om, (0, 2, 1))).max() / om.max()
     no = oracle.open_count(pw, sel)
     asym = max(np.abs(K[e, :no[e], :no[e]] - K[e, :no[e], :no[e]].T).max() / max(1, np.abs(K[e]).max())
                for e in range(sel.size) if no[e])
-    _say(f"c4 K asymmetry max {asym:.2e}")
+    _say(f"c4 Omega asymmetry {sym:.2e} (relative to max Omega), K asymmetry max {asym:.2e}")
+    assert sym <= 1e-12
     assert asym < 1e-6
 
 
@@ -151,13 +153,12 @@ def test_widest_panels_vs_oracle(ctx):
     res = oracle.Oracle(pw, nthreads=16).run(E)
     assert (st == 0).all() and (res["status"] == 0).all()
     no = oracle.open_count(pw, E)
+    errK = k_err(K, res["K"], no)
+    errO = omega_elementwise(om, res["omega"])
+    g = gate(res["cond"])
     for e in range(E.size):
-        Ko = res["K"][e, :no[e], :no[e]]
-        errK = np.abs(K[e, :no[e], :no[e]] - Ko).max() / max(1, np.abs(Ko).max())
-        errO = np.abs(om[e] - res["omega"][e]).max() / np.abs(res["omega"][e]).max()
-        g = 1e-10 if res["cond"][e] <= 1e4 else max(1e-10, 1e-15 * res["cond"][e])
-        _say(f"n=1700 E={E[e]} no={no[e]} cond={res['cond'][e]:.1e} K err {errK:.2e} Omega err {errO:.2e}")
-        assert errK <= g and errO <= g
+        _say(f"n=1700 E={E[e]} no={no[e]} cond={res['cond'][e]:.1e} K err {errK[e]:.2e} Omega err {errO[e]:.2e}")
+    assert (errK <= g).all() and (errO <= g).all()
     outs = ctx.run_batch([(sid, E), (pid, E)], prec=rm.FP64, want_K=True)
     assert np.array_equal(outs[1][0], om) and np.array_equal(outs[1][1], K)
     ctx.pw_release(pid)

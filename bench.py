@@ -56,31 +56,42 @@ def measured_traffic(kernel: str):
     return float(m.group(1)) + float(m.group(2))
 
 
-def serve_measure(ctx, nreq: int) -> dict:
-    """Open-loop Poisson streams through rm_submit/rm_poll on a pool of resident
-    partial waves (channel counts log-uniform in 10..2000, 30-40 poles per
-    channel, energies in [0.01, 8] Ry), once all-FP64 and once all-FP32-split.
-    Each stream's arrival rate is 0.7 x the capacity measured by a closed-loop
-    burst of the same mode."""
+def request_cost(pw, ne: int) -> float:
+    """Flops of a request: per energy the R contraction n(n+1)M (symmetric half)
+    plus the LU of the n x n matching matrix, (2/3) n^3."""
+    n = float(pw.nchan)
+    return ne * (n * (n + 1) * pw.npole + 2.0 / 3.0 * n ** 3)
+
+
+def serve_measure(ctx, nreq: int, block_max: int, load: float = 0.7) -> dict:
+    """Open-loop Poisson streams through rm_submit/rm_poll on a pool of 16
+    resident partial waves (channel counts log-uniform in 10..2000, 30-40 poles
+    per channel, energies in [0.01, 8] Ry, blocks log-uniform in
+    100..block_max energies), once all-FP64 and once all-FP32-split.
+
+    Per-point cost spans about seven decades over the pool, so the load is set
+    in flops: a closed-loop burst of the stream's first 16 requests measures
+    the capacity in flop/s, and the arrival rate is load x capacity / mean
+    request cost.  Reported beside the latencies: the offered rate and the
+    served rate (both in flop/s and energy points/s) and the capacity."""
     import numpy as np
 
     from paper_1909_07321_amd import rm, synth
 
     pool = synth.config5_pool(16, 2000)
     ids = [ctx.pw_upload(p) for p in pool]
-    block = (100, 4000)
+    block = (100, block_max)
 
-    def run_stream(reqs, prec, rate_hz=None):
+    def run_stream(reqs, prec, scale=None):
         t0 = time.perf_counter()
-        tickets, pts = [], 0
+        tickets = []
         for r in reqs:
-            if rate_hz:
-                wait = t0 + r.arrival_s - time.perf_counter()
+            if scale:
+                wait = t0 + r.arrival_s * scale - time.perf_counter()
                 if wait > 0:
                     time.sleep(wait)
             t, _ = ctx.submit(ids[r.pw_index], r.energies, prec=prec)
             tickets.append(t)
-            pts += r.energies.size
         stats, pending = [], set(tickets)
         while pending:
             for t in list(pending):
@@ -89,27 +100,78 @@ def serve_measure(ctx, nreq: int) -> dict:
                     stats.append(st)
                     pending.discard(t)
             time.sleep(0.0005)
-        return pts, time.perf_counter() - t0, stats
+        return time.perf_counter() - t0, stats
 
     out = {}
+    base = synth.config5_requests(pool, nreq=nreq, rate_hz=1.0, block_range=block)  # arrivals at 1 request/s
+    cost = np.array([request_cost(pool[r.pw_index], r.energies.size) for r in base])
+    pts = int(sum(r.energies.size for r in base))
     for name, prec in (("fp64", rm.FP64), ("split", rm.FP32_SPLIT)):
-        burst = synth.config5_requests(pool, nreq=8, rate_hz=1.0, block_range=block)
-        pts, dt, _ = run_stream(burst, prec)
-        capacity = pts / dt
-        mean_pts = float(np.mean([r.energies.size for r in burst]))
-        rate = 0.7 * capacity / mean_pts
-        reqs = synth.config5_requests(pool, nreq=nreq, rate_hz=rate, block_range=block)
-        pts, dt, stats = run_stream(reqs, prec, rate_hz=rate)
+        burst = base[:16]
+        dt, _ = run_stream(burst, prec)
+        capacity = float(cost[:16].sum()) / dt                       # flop/s, closed loop
+        rate = load * capacity / float(cost.mean())                   # requests/s
+        dt, stats = run_stream(base, prec, scale=1.0 / rate)
         lat = np.array([(st["t_done_ns"] - st["t_arrive_ns"]) * 1e-6 for st in stats])
-        out[name] = dict(requests=nreq, arrival_rate_hz=rate, capacity_points_per_s=capacity, points=pts,
-                         points_per_s=pts / dt, p50_ms=float(np.median(lat)), p99_ms=float(np.quantile(lat, 0.99)),
+        span = base[-1].arrival_s / rate                              # offered over the arrival window
+        out[name] = dict(requests=nreq, load=load, arrival_rate_hz=rate,
+                         capacity_tflops=capacity / 1e12,
+                         offered_tflops=float(cost.sum()) / span / 1e12,
+                         served_tflops=float(cost.sum()) / dt / 1e12,
+                         offered_points_per_s=pts / span, points=pts, points_per_s=pts / dt,
+                         p50_ms=float(np.median(lat)), p99_ms=float(np.quantile(lat, 0.99)),
                          max_ms=float(lat.max()))
-        log(f"serving {name}: {nreq} requests at {rate:.2f}/s, {out[name]['points_per_s']:.0f} points/s, "
-            f"p50 {out[name]['p50_ms']:.0f} ms, p99 {out[name]['p99_ms']:.0f} ms")
+        o_ = out[name]
+        log(f"serving {name}: {nreq} requests at {rate:.2f}/s, capacity {o_['capacity_tflops']:.1f} TFLOP/s, offered "
+            f"{o_['offered_tflops']:.1f}, served {o_['served_tflops']:.1f} TFLOP/s ({o_['points_per_s']:.0f} points/s), "
+            f"p50 {o_['p50_ms']:.0f} ms, p99 {o_['p99_ms']:.0f} ms")
     for i in ids:
         ctx.pw_release(i)
     out["pool"] = "16 partial waves, n log-uniform 10..2000, 30-40 poles/channel"
-    out["blocks"] = f"log-uniform {block[0]}..{block[1]} energies (reduced from 100..20000 to bound the run)"
+    out["blocks"] = (f"log-uniform {block[0]}..{block[1]} energies"
+                     + ("" if block_max >= 20000 else " (capped below the 20000 of the full stream to bound the run)"))
+    return out
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(pw, E, threads: int, budget_s: float) -> dict:
+    """The FP64 oracle (plain long-double C, OpenMP over the R rows of one
+    energy) on the host cores, over an evenly spaced subsample of the grid: the
+    planned sample is every 31st energy (32 points); as many of those as fit in
+    budget_s are timed, spread evenly over the grid, starting mid-grid."""
+    import numpy as np
+
+    import oracle
+    threads = threads or len(os.sched_getaffinity(0))
+    plan = np.arange(0, E.size, 31)
+    o = oracle.Oracle(pw, nthreads=threads)
+    order = [plan[plan.size // 2]]
+    t3 = time.perf_counter()
+    o.run(E[order], want_K=False)
+    t_one = time.perf_counter() - t3
+    n_fit = int(min(plan.size, max(1, budget_s // t_one)))
+    if n_fit > 1:
+        spread = [int(i) for i in plan[np.linspace(0, plan.size - 1, n_fit).round().astype(int)]]
+        rest = [i for i in spread if i != order[0]][:n_fit - 1]
+        o.run(E[rest], want_K=False)
+        order += rest
+    dt = time.perf_counter() - t3
+    idx = sorted(int(i) for i in order)
+    out = dict(value=len(idx) / dt, unit="energy points/s", cores=threads, kind="oracle",
+               cpu_model=cpu_model(),
+               sample=f"{len(idx)} of the 32 planned energies (every 31st grid point; fitted to a {budget_s:.0f} s "
+                      f"budget) at grid indices {idx}, full path R -> asymptotics -> K -> Omega in long double, "
+                      f"{dt:.1f} s on {threads} threads ({cpu_model()})")
+    log(f"cpu oracle: {out['value']:.4f} points/s on {threads} threads, {len(idx)} energies in {dt:.1f} s")
     return out
 
 
@@ -190,26 +252,66 @@ def config_measure(ctx) -> dict:
     for i in ids:
         ctx.pw_release(i)
 
-    # sum over partial waves: 12 waves sharing 60 targets, both chunk orders
-    pws, E = synth.config_sum()
+    # sum over partial waves with the load-balance family (16 waves of 72..634
+    # channels sharing 150 targets), wave order and the permuted (J pi, E) order
+    pws, E = synth.config_imbalance()
+    out["imbalance"] = imbalance_measure(ctx, pws, E)
+    return out
+
+
+def imbalance_measure(ctx, pws, E) -> dict:
+    """Omega summed over a family of partial waves in both chunk orders, with
+    the per-chunk GPU time distribution: max/mean and coefficient of variation
+    of the chunk times, and how chunk time follows the chunk's model flops and
+    open fraction n_o/n (the single-GPU view of the paper's per-processor load
+    balance)."""
+    import numpy as np
+    import torch
+
+    from paper_1909_07321_amd import rm
+
     ids = [ctx.pw_upload(p) for p in pws]
-    Ed = torch.tensor(E, dtype=torch.float64, device=dev)
+    Ed = torch.tensor(E, dtype=torch.float64, device="cuda")
     ctx.run_sum(ids, Ed[:64])
     torch.cuda.synchronize()
+    res = {}
     for name, order in (("wave", rm.ORDER_WAVE), ("permuted", rm.ORDER_PERMUTED)):
+        ctx.run_sum(ids, Ed, prec=rm.FP64, order=order)   # warm-up: workspaces, graphs
+        torch.cuda.synchronize()
+        drain_prof(ctx)
+        ctx.prof_chunks()
+        ctx.prof_enable(True)
         t1 = time.perf_counter()
         ctx.run_sum(ids, Ed, prec=rm.FP64, order=order)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t1
-        pts = len(ids) * E.size
-        out[f"sum_fp64_{name}_order"] = dict(
-            points_per_s=pts / dt, seconds=dt,
-            workload=f"{len(ids)} waves sharing 60 targets, {min(p.nchan for p in pws)}..{max(p.nchan for p in pws)} "
-                     f"channels, 30 poles per channel, {E.size} energies, Omega summed over the waves")
-        log(f"sum over {len(ids)} waves ({name} order): {pts / dt:.0f} points/s over {dt:.2f}s")
+        ctx.prof_enable(False)
+        ch = ctx.prof_chunks()
+        drain_prof(ctx)
+        ms, fl, of = ch["ms"], ch["model_flops"], ch["open_frac"]
+        rate = fl / (ms * 1e-3) / 1e12
+        res[name] = dict(points_per_s=len(ids) * E.size / dt, seconds=dt, chunks=int(ms.size),
+                         chunk_ms=dict(mean=float(ms.mean()), max=float(ms.max()), min=float(ms.min()),
+                                       max_over_mean=float(ms.max() / ms.mean()), cv=float(ms.std() / ms.mean()),
+                                       sum=float(ms.sum())),
+                         chunk_model_tflop=dict(mean=float(fl.mean() / 1e12), max=float(fl.max() / 1e12),
+                                                max_over_mean=float(fl.max() / fl.mean())),
+                         chunk_tflops=dict(min=float(rate.min()), median=float(np.median(rate)),
+                                           max=float(rate.max())),
+                         corr_ms_vs_model=float(np.corrcoef(ms, fl)[0, 1]) if ms.size > 2 else None,
+                         open_frac=dict(min=float(of.min()), max=float(of.max())))
+        r = res[name]
+        log(f"imbalance ({name} order): {r['points_per_s']:.0f} points/s over {dt:.2f}s, {r['chunks']} chunks, "
+            f"chunk ms mean {r['chunk_ms']['mean']:.1f} max/mean {r['chunk_ms']['max_over_mean']:.2f} "
+            f"cv {r['chunk_ms']['cv']:.2f}, model TFLOP/s per chunk {r['chunk_tflops']['min']:.1f}.."
+            f"{r['chunk_tflops']['max']:.1f}, corr(ms, model) {r['corr_ms_vs_model']:.2f}, "
+            f"open fraction {r['open_frac']['min']:.2f}..{r['open_frac']['max']:.2f}")
     for i in ids:
         ctx.pw_release(i)
-    return out
+    res["workload"] = (f"{len(pws)} waves sharing {pws[0].ntarget} targets, {min(p.nchan for p in pws)}.."
+                       f"{max(p.nchan for p in pws)} channels, 30 poles per channel, {E.size} energies in "
+                       f"[{E[0]}, {E[-1]}] Ry, FP64, Omega summed over the waves")
+    return res
 
 
 def main() -> int:
@@ -221,9 +323,14 @@ def main() -> int:
                     help="headline mode is FP32-split; 'both' also times FP64")
     ap.add_argument("--nenergy", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-threads", type=int, default=16)
-    ap.add_argument("--serving", type=int, default=24, metavar="NREQ",
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="oracle threads for the CPU baseline (0 = every core this process may run on)")
+    ap.add_argument("--cpu-budget", type=float, default=30.0,
+                    help="seconds of oracle time for the CPU baseline sample")
+    ap.add_argument("--serving", type=int, default=100, metavar="NREQ",
                     help="requests per mode in the serving measurement (0 = skip)")
+    ap.add_argument("--serving-block-max", type=int, default=2000,
+                    help="largest energy block of a serving request (the full stream goes to 20000)")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the 200-channel and 64-wave batch throughput measurements")
     ap.add_argument("--no-tune", action="store_true",
@@ -312,22 +419,12 @@ def main() -> int:
 
     serving = None
     if args.serving > 0:
-        serving = serve_measure(ctx, args.serving)
+        serving = serve_measure(ctx, args.serving, args.serving_block_max)
     configs = None if args.no_configs else config_measure(ctx)
 
     cpu = None
     if not args.no_cpu:
-        import oracle
-        threads = max(1, min(args.cpu_threads, os.cpu_count() or 1))
-        sample = E[[E.size // 2]]
-        o = oracle.Oracle(pw, nthreads=threads)
-        t3 = time.perf_counter()
-        o.run(sample, want_K=False)
-        t4 = time.perf_counter()
-        cpu = dict(value=sample.size / (t4 - t3), unit="energy points/s", cores=threads, kind="oracle",
-                   sample=f"{sample.size} energy (E = {sample[0]:.3f} Ry, mid-grid) of the same workload, "
-                          f"full path R -> asymptotics -> K -> Omega in long double, {t4 - t3:.1f} s")
-        log(f"cpu oracle: {cpu['value']:.4f} points/s on {threads} threads")
+        cpu = cpu_baseline(pw, E, args.cpu_threads, args.cpu_budget)
 
     head = results.get("split") or results.get("fp64")
     head_name = "split" if "split" in results else "fp64"

@@ -132,6 +132,10 @@ rm_status rm_pw_upload(rm_ctx *ctx, const rm_pw_desc *desc, int32_t *pw_id);
 rm_status rm_pw_release(rm_ctx *ctx, int32_t pw_id);
 /* Device bytes a partial wave of this shape occupies when resident. */
 size_t rm_pw_footprint(int32_t nchan, int32_t npole);
+/* Upper bound of the device workspace a chunk of ne energies of a partial wave
+   of this shape needs (a chunk mixing waves needs it for its largest member);
+   0 for invalid sizes.  With rm_pw_footprint this sizes hbm_budget_bytes. */
+size_t rm_work_footprint(int32_t nchan, int32_t npole, int32_t ntarget, int32_t ne);
 
 /* ---------------------------------------------------------- staged calls */
 /* Stage 1, eq. (rmatrix).  R: [ne][n][n] doubles (full symmetric matrices);
@@ -293,12 +297,22 @@ rm_status rm_drain(rm_ctx *ctx);
    HIP events on the stream it runs on.  Stages: "rform" (R contraction kernel,
    either precision), "nearpole" (FP64 window correction), "asym" (channel split
    and asymptotic functions), "ksolve" (matching assembly, LU, back
-   substitution), "somega" (S, T and Omega).  rm_prof_read synchronises the
-   recorded events and returns the summed milliseconds, the launch count and
-   the energies those launches covered, then clears the records of that stage. */
+   substitution), "somega" (S, T and Omega), "chunk" (one chunk's whole
+   pipeline).  rm_prof_read synchronises the recorded events and returns the
+   summed milliseconds, the launch count and the energies those launches
+   covered, then clears the records of that stage. */
 rm_status rm_prof_enable(rm_ctx *ctx, int32_t on);
 rm_status rm_prof_read(rm_ctx *ctx, const char *stage, double *total_ms, int64_t *launches,
                        int64_t *energies);
+/* Per-chunk records, in issue order (the single-GPU view of the load balance
+   of section "Computational details": how evenly the work of the (partial
+   wave, energy) points is spread over the launches).  Up to cap records are
+   returned and cleared: GPU milliseconds of the chunk's pipeline, its model
+   flops (per energy n(n+1)M + (2/3)n^3 + n^2 n_o + 4 n_o^3), the mean open
+   fraction n_o/n of its energies and its energy count; *count = records
+   returned. */
+rm_status rm_prof_chunks(rm_ctx *ctx, int64_t cap, double *ms, double *model_flops, double *open_frac,
+                         int64_t *energies, int64_t *count);
 
 #ifdef __cplusplus
 }

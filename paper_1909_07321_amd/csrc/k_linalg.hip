@@ -1351,15 +1351,20 @@ __global__ __launch_bounds__(512, 1) void k_zs_gtg(const int *__restrict__ dims,
           yr[m] = sbr[ks + kk][wc * 32 + m * 16 + ii];
           yi[m] = sbi[ks + kk][wc * 32 + m * 16 + ii];
         }
+        // the two products of each accumulator are issued 16 MFMAs apart
 #pragma unroll
         for (int mr = 0; mr < 4; ++mr)
 #pragma unroll
           for (int mc = 0; mc < 2; ++mc) {
-            d4 &cr = accr[mr * 2 + mc], &ci = acci[mr * 2 + mc];
-            cr = mfma64(xr[mr], yr[mc], cr);
-            cr = mfma64(-xi[mr], yi[mc], cr);
-            ci = mfma64(xr[mr], yi[mc], ci);
-            ci = mfma64(xi[mr], yr[mc], ci);
+            accr[mr * 2 + mc] = mfma64(xr[mr], yr[mc], accr[mr * 2 + mc]);
+            acci[mr * 2 + mc] = mfma64(xr[mr], yi[mc], acci[mr * 2 + mc]);
+          }
+#pragma unroll
+        for (int mr = 0; mr < 4; ++mr)
+#pragma unroll
+          for (int mc = 0; mc < 2; ++mc) {
+            accr[mr * 2 + mc] = mfma64(-xi[mr], yi[mc], accr[mr * 2 + mc]);
+            acci[mr * 2 + mc] = mfma64(xi[mr], yr[mc], acci[mr * 2 + mc]);
           }
       }
       __syncthreads();

@@ -77,9 +77,11 @@ struct ProfRec {
   hipEvent_t a = nullptr, b = nullptr;
   int stage = 0;
   long energies = 0;
+  double cost = 0, open = 0;  // chunk records: model flops and summed open fraction n_o / n
 };
-const char *const kStages[] = {"rform", "nearpole", "asym", "ksolve", "somega"};
-constexpr int NSTAGE = 5;
+const char *const kStages[] = {"rform", "nearpole", "asym", "ksolve", "somega", "chunk"};
+constexpr int NSTAGE = 6;
+constexpr int STAGE_CHUNK = 5;
 
 struct Req {
   uint64_t ticket = 0;
@@ -141,8 +143,10 @@ struct rm_ctx {
   int max_queue = 4096;
   std::atomic<int> prof_on{0};
   std::vector<ProfRec> prof;  // guarded by mu
+  std::map<const DevPW *, std::vector<double>> hthr;  // host copies of channel thresholds; guarded by mu
   int tile[2][NBUCKET] = {};  // R tile shape per (split, size bucket); guarded by mu
   std::atomic<int> graphs{1};  // chunk pipelines run as captured HIP graphs
+  const void *mem_waiter = nullptr;  // serving slot waiting for the other slots' workspaces; guarded by mu
   // rm_run / rm_run_batch alternate chunks over two streams; the R
   // contractions are chained across them so that one chunk's K solve overlaps
   // the next chunk's contraction
@@ -162,6 +166,9 @@ namespace {
   } while (0)
 
 constexpr int MAX_CHUNK = 1024;
+// workspace bytes of a chunk beyond its per-energy blocks (tables, task lists,
+// queue heads), an upper bound for the admission test
+constexpr size_t kChunkFixedBytes = 16u << 20;
 constexpr double TUNE_MARGIN = 0.03;
 
 size_t per_energy_bytes(int n, int npad, int Mpad, int nt) {
@@ -407,6 +414,27 @@ rm_status upload_plan(rm_ctx *ctx, Slot &sl, Plan &P, const std::vector<Seg> &se
   return RM_OK;
 }
 
+// Opens a profile record (an event recorded on s) when profiling is on.
+bool prof_begin(rm_ctx *ctx, int stage, long energies, hipStream_t s, ProfRec &r) {
+  if (!ctx || !ctx->prof_on.load()) return false;
+  r.stage = stage;
+  r.energies = energies;
+  if (hipEventCreate(&r.a) != hipSuccess) return false;
+  if (hipEventCreate(&r.b) != hipSuccess) {
+    (void)hipEventDestroy(r.a);
+    return false;
+  }
+  (void)hipEventRecord(r.a, s);
+  return true;
+}
+
+// Closes a record opened by prof_begin and files it.
+void prof_end(rm_ctx *ctx, hipStream_t s, ProfRec &r) {
+  (void)hipEventRecord(r.b, s);
+  std::lock_guard<std::mutex> g(ctx->mu);
+  ctx->prof.push_back(r);
+}
+
 // Brackets the launches issued by `body` with events when profiling is on.
 template <typename F>
 void timed(rm_ctx *ctx, int stage, long energies, hipStream_t s, F &&body) {
@@ -646,6 +674,30 @@ rm_status run_chunk(rm_ctx *ctx, const Plan &P, Slot &sl, const std::vector<Seg>
   auto group = [&](int g, auto &&body) {
     if (st == RM_OK) st = launch_group(ctx, sl, g, key, body);
   };
+  // chunk record (profiling only): model flops of the chunk's energies, per
+  // energy n(n+1)M (R) + (2/3)n^3 + n^2 n_o (K solve) + 4 n_o^3 (S/Omega)
+  double cost = 0, open = 0;
+  if (ctx->prof_on.load()) {
+    if (o.device_ptrs) {  // the chunk's energies came from device memory: bring them to the staging copy
+      HIPCHK(hipMemcpyAsync(sl.h.E, w.E, sizeof(double) * L.ne, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+    }
+    std::lock_guard<std::mutex> g(ctx->mu);
+    for (const Part &pt : P.parts) {
+      const DevPW &pw = *segs[pt.seg].pw;
+      auto it = ctx->hthr.find(&pw);
+      const double n = pw.n, M = pw.M;
+      for (int e = 0; e < pt.m; ++e) {
+        double no = 0;
+        if (it != ctx->hthr.end())
+          for (double t : it->second) no += sl.h.E[pt.e0 + e] - t > 0.0;
+        cost += n * (n + 1) * M + 2.0 / 3.0 * n * n * n + n * n * no + 4.0 * no * no * no;
+        open += no / n;
+      }
+    }
+  }
+  ProfRec chunk_rec;
+  const bool chunk_timed = prof_begin(ctx, STAGE_CHUNK, L.ne, s, chunk_rec);
   timed(ctx, 2, L.ne, s, [&] {
     group(0, [&] {
       launch_fill_int(s, w.status, L.ne, 0);
@@ -671,6 +723,11 @@ rm_status run_chunk(rm_ctx *ctx, const Plan &P, Slot &sl, const std::vector<Seg>
     launch_finalize(s, L, w.tab, w.pwi, w.status, w.omega, w.Kw, nullptr);
     launch_pack(s, L, w.tab, w.pwi, 0, w.omega, w.pack_off, w.pack);
   });
+  if (chunk_timed) {
+    chunk_rec.cost = cost;
+    chunk_rec.open = open;
+    prof_end(ctx, s, chunk_rec);
+  }
   if (st != RM_OK) return st;
   for (const Part &pt : P.parts) {
     const Seg &g = segs[pt.seg];
@@ -849,6 +906,14 @@ rm_status staged_leave(rm_ctx *ctx, const rm_opts &o, hipEvent_t ev) {
 // first, up to the chunk capacity, runs the chunk on its own stream, and hands
 // the results back per request.  Requests that arrive while chunks run join
 // the next chunk a worker forms.
+//
+// Admission by HBM footprint: a worker sizes its chunk to its share of the free
+// budget (the free budget split over the workers).  If not even one energy of
+// the chunk's shape fits, the worker becomes the memory waiter: the other
+// workers finish their current chunk, release their workspaces and take no new
+// work until the waiter has formed its chunk (with the whole free budget).  A
+// shape that would not fit even with every other workspace released fails its
+// requests with RM_E_NOMEM.
 void worker_main(rm_ctx *ctx, Slot *slot) {
   (void)hipSetDevice(ctx->device);
   for (;;) {
@@ -856,22 +921,41 @@ void worker_main(rm_ctx *ctx, Slot *slot) {
     std::vector<Req *> owners;
     Plan P;
     rm_opts o;
+    Work released;
     {
       std::unique_lock<std::mutex> lk(ctx->mu);
       ctx->cv.wait(lk, [&] {
         if (ctx->stop) return true;
+        if (ctx->mem_waiter && ctx->mem_waiter != slot) return slot->w.bytes > 0;
         for (Req *q : ctx->active)
           if (q->next_e < q->rq.ne) return true;
         return false;
       });
       if (ctx->stop) return;
-      // the options of the earliest request with work decide the chunk's
+      if (ctx->mem_waiter && ctx->mem_waiter != slot) {
+        // another worker waits for memory: hand this workspace back (freed
+        // outside the lock; the slot's stream is idle between chunks)
+        released = slot->w;
+        slot->w = Work();
+        ctx->work_bytes -= released.bytes;
+      }
+    }
+    if (released.bytes) {
+      free_work(released);
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      ctx->cv.notify_all();
+      continue;
+    }
+    {
+      std::unique_lock<std::mutex> lk(ctx->mu);
       const Req *first = nullptr;
       for (Req *q : ctx->active)
         if (q->next_e < q->rq.ne) {
           first = q;
           break;
         }
+      if (!first) continue;
+      // the options of the earliest request with work decide the chunk's
       o = fixed_opts(&first->rq.opts);
       o.device_ptrs = 0;
       o.stream = nullptr;
@@ -883,7 +967,8 @@ void worker_main(rm_ctx *ctx, Slot *slot) {
       };
       // largest member shapes decide the per-energy footprint
       const size_t used = ctx->resident + ctx->work_bytes - slot->w.bytes;
-      const size_t share = (ctx->budget > used ? ctx->budget - used : 0) / std::max<size_t>(ctx->slots.size(), 1);
+      const size_t avail = ctx->budget > used ? ctx->budget - used : 0;
+      size_t share = ctx->mem_waiter == slot ? avail : avail / std::max<size_t>(ctx->slots.size(), 1);
       int n = 0, npad = 0, Mpad = 0, nt = 0;
       for (Req *q : ctx->active) {
         if (q->next_e >= q->rq.ne || !compatible(q)) continue;
@@ -893,6 +978,42 @@ void worker_main(rm_ctx *ctx, Slot *slot) {
         npad = std::max(npad, it->second.npad);
         Mpad = std::max(Mpad, it->second.Mpad);
         nt = std::max(nt, it->second.nt);
+      }
+      const size_t one = n ? per_energy_bytes(n, npad, Mpad, nt) + kChunkFixedBytes : 0;
+      if (one > share) {
+        size_t others = 0;  // releasable by the other serving workers
+        for (const auto &sl : ctx->slots)
+          if (sl.get() != slot) others += sl->w.bytes;
+        if (one <= avail) {
+          share = avail;  // fits once this worker takes the whole free budget
+        } else if (one <= avail + others) {
+          if (!ctx->mem_waiter) ctx->mem_waiter = slot;
+          ctx->cv.notify_all();
+          if (ctx->mem_waiter != slot) ctx->cv.wait(lk);
+          else
+            ctx->cv.wait(lk, [&] {
+              return ctx->stop || ctx->resident + ctx->work_bytes - slot->w.bytes + one <= ctx->budget;
+            });
+          continue;
+        } else {
+          // cannot fit even alone: fail the compatible requests of this shape
+          for (Req *q : ctx->active) {
+            if (q->next_e >= q->rq.ne || !compatible(q)) continue;
+            auto it = ctx->pws.find(q->rq.pw_id);
+            if (it == ctx->pws.end() || it->second.n != n) continue;
+            q->err = RM_E_NOMEM;
+            q->done_e = q->next_e = q->rq.ne;
+            q->st.t_done_ns = now_ns();
+          }
+          ctx->err = "a request's per-energy workspace exceeds the HBM budget";
+          if (ctx->mem_waiter == slot) ctx->mem_waiter = nullptr;
+          ctx->cv.notify_all();
+          continue;
+        }
+      }
+      if (ctx->mem_waiter == slot) {
+        ctx->mem_waiter = nullptr;
+        ctx->cv.notify_all();
       }
       int room = n ? chunk_cap(n, npad, Mpad, nt, share, 256) : 0;
       for (Req *q : ctx->active) {
@@ -1062,6 +1183,12 @@ size_t rm_pw_footprint(int32_t nchan, int32_t npole) {
   return Mpad * npad * 12 + Mpad * 8 + (size_t)nchan * 24 + 4096;
 }
 
+size_t rm_work_footprint(int32_t nchan, int32_t npole, int32_t ntarget, int32_t ne) {
+  if (nchan < 1 || npole < 1 || ntarget < 1 || ne < 1) return 0;
+  return per_energy_bytes(nchan, round_up(nchan, TILE), round_up(npole, MALIGN), ntarget) * (size_t)ne +
+         kChunkFixedBytes;
+}
+
 rm_status rm_pw_upload(rm_ctx *ctx, const rm_pw_desc *d, int32_t *pw_id) {
   if (!ctx || !d || !pw_id) return RM_E_ARG;
   if (d->nchan < 1 || d->nchan > RM_MAX_CHANNELS || d->npole < 1 || d->ntarget < 1 || !d->e_thr || !d->l || !d->target || !d->Ek || !d->w ||
@@ -1135,6 +1262,7 @@ rm_status rm_pw_upload(rm_ctx *ctx, const rm_pw_desc *d, int32_t *pw_id) {
   std::lock_guard<std::mutex> g(ctx->mu);
   const int32_t id = ctx->next_id++;
   ctx->pws[id] = p;
+  ctx->hthr[&ctx->pws[id]].assign(d->e_thr, d->e_thr + p.n);
   ctx->resident += bytes;
   *pw_id = id;
   return RM_OK;
@@ -1148,6 +1276,7 @@ rm_status rm_pw_release(rm_ctx *ctx, int32_t pw_id) {
   for (Req *q : ctx->active)
     if (q->rq.pw_id == pw_id && (q->done_e < q->rq.ne || q->inflight > 0)) return RM_E_BUSY;
   DevPW p = it->second;
+  ctx->hthr.erase(&it->second);
   ctx->pws.erase(it);
   ctx->resident -= p.bytes;
   lk.unlock();
@@ -1679,6 +1808,32 @@ rm_status rm_prof_read(rm_ctx *ctx, const char *stage, double *total_ms, int64_t
   if (total_ms) *total_ms = ms;
   if (launches) *launches = (int64_t)mine.size();
   if (energies) *energies = e;
+  return st;
+}
+
+rm_status rm_prof_chunks(rm_ctx *ctx, int64_t cap, double *ms, double *model_flops, double *open_frac,
+                         int64_t *energies, int64_t *count) {
+  if (!ctx || !count || cap < 0 || (cap > 0 && (!ms || !model_flops || !open_frac || !energies))) return RM_E_ARG;
+  std::vector<ProfRec> mine;
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    std::vector<ProfRec> rest;
+    for (auto &r : ctx->prof) (r.stage == STAGE_CHUNK && (int64_t)mine.size() < cap ? mine : rest).push_back(r);
+    ctx->prof.swap(rest);
+  }
+  rm_status st = RM_OK;
+  for (size_t i = 0; i < mine.size(); ++i) {
+    ProfRec &r = mine[i];
+    float t = 0;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) st = RM_E_DEVICE;
+    ms[i] = t;
+    model_flops[i] = r.cost;
+    open_frac[i] = r.energies ? r.open / (double)r.energies : 0.0;
+    energies[i] = r.energies;
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  *count = (int64_t)mine.size();
   return st;
 }
 

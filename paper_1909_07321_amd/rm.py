@@ -69,6 +69,8 @@ _lib.rm_pw_upload.argtypes = [_vp, ctypes.POINTER(PWDesc), ctypes.POINTER(_i32)]
 _lib.rm_pw_release.argtypes = [_vp, _i32]
 _lib.rm_pw_footprint.argtypes = [_i32, _i32]
 _lib.rm_pw_footprint.restype = _sz
+_lib.rm_work_footprint.argtypes = [_i32, _i32, _i32, _i32]
+_lib.rm_work_footprint.restype = _sz
 _lib.rm_form_R.argtypes = [_vp, _i32, _vp, _i32, ctypes.POINTER(Opts), _vp, _vp]
 _lib.rm_asymptotic.argtypes = [_vp, _i32, _vp, _i32, ctypes.POINTER(Opts), _vp, _vp, _vp, _vp]
 _lib.rm_solve_K.argtypes = [_vp, _i32, _vp, _i32, _vp, _vp, ctypes.POINTER(Opts), _vp, _vp]
@@ -82,6 +84,7 @@ _lib.rm_drain.argtypes = [_vp]
 _lib.rm_prof_enable.argtypes = [_vp, _i32]
 _lib.rm_prof_read.argtypes = [_vp, ctypes.c_char_p, ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_int64),
                               ctypes.POINTER(ctypes.c_int64)]
+_lib.rm_prof_chunks.argtypes = [_vp, ctypes.c_int64, _vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_int64)]
 _lib.rm_tile_bucket.argtypes = [_i32]
 _lib.rm_tile_bucket.restype = _i32
 _lib.rm_tile_count.argtypes = [_i32]
@@ -95,10 +98,10 @@ _lib.rm_set_graph.argtypes = [_vp, _i32]
 _lib.rm_graph_stats.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
 
 EXPORTS = ["rm_opts_default", "rm_create", "rm_destroy", "rm_last_error", "rm_pw_upload", "rm_pw_release",
-           "rm_pw_footprint", "rm_form_R", "rm_asymptotic", "rm_solve_K", "rm_collision_strengths", "rm_run",
+           "rm_pw_footprint", "rm_work_footprint", "rm_form_R", "rm_asymptotic", "rm_solve_K", "rm_collision_strengths", "rm_run",
            "rm_run_batch", "rm_run_sum", "rm_tile_bucket", "rm_tile_count", "rm_tile_shape", "rm_get_tile",
            "rm_set_tile", "rm_tune", "rm_tune_load", "rm_set_graph", "rm_graph_stats",
-           "rm_submit", "rm_poll", "rm_drain", "rm_prof_enable", "rm_prof_read"]
+           "rm_submit", "rm_poll", "rm_drain", "rm_prof_enable", "rm_prof_read", "rm_prof_chunks"]
 
 
 class RMError(RuntimeError):
@@ -119,6 +122,10 @@ def _ptr(x):
 
 def pw_footprint(nchan: int, npole: int) -> int:
     return int(_lib.rm_pw_footprint(nchan, npole))
+
+
+def work_footprint(nchan: int, npole: int, ntarget: int, ne: int) -> int:
+    return int(_lib.rm_work_footprint(nchan, npole, ntarget, ne))
 
 
 NBUCKET = 4
@@ -390,3 +397,12 @@ class Context:
         ms, nl, ne = _d(), ctypes.c_int64(), ctypes.c_int64()
         self._check(_lib.rm_prof_read(self.h, stage.encode(), ctypes.byref(ms), ctypes.byref(nl), ctypes.byref(ne)))
         return ms.value, nl.value, ne.value
+
+    def prof_chunks(self, cap: int = 65536):
+        """Per-chunk records since the last read: dict of arrays ms, model_flops,
+        open_frac, energies (issue order)."""
+        ms, fl, of = np.empty(cap), np.empty(cap), np.empty(cap)
+        ne, cnt = np.empty(cap, np.int64), ctypes.c_int64()
+        self._check(_lib.rm_prof_chunks(self.h, cap, _ptr(ms), _ptr(fl), _ptr(of), _ptr(ne), ctypes.byref(cnt)))
+        k = cnt.value
+        return dict(ms=ms[:k], model_flops=fl[:k], open_frac=of[:k], energies=ne[:k])

@@ -145,15 +145,17 @@ def make_partial_wave(seed: int, nchan: int, poles_per_chan: float, *, z: float,
                        e_target, l, target, Ek, np.ascontiguousarray(w))
 
 
-def partial_wave_family(seed: int, npw: int, ntarget: int, chan_per_target: tuple[int, int],
+def partial_wave_family(seed: int, npw: int, ntarget: int, chan_per_target,
                         poles_per_chan: float, *, z: float, a: float, thr_range: tuple[float, float],
                         pole_range: tuple[float, float], lmax: int = 12,
                         avoid_energies: np.ndarray | None = None, name: str = "fam") -> list[PartialWave]:
     """Partial waves of one collision problem: they share the targets (target 0
     at 0 Ry, the others sorted uniform in ``thr_range``), and wave w couples each
-    target to a uniform number of channels in ``chan_per_target`` (channels
-    ordered by target), with its own l values, poles and amplitudes.  Wave w has
-    statistical weight g = 2w + 1 (a stand-in for 2J + 1)."""
+    target to a uniform number of channels in ``chan_per_target`` (one (lo, hi)
+    range for every wave, or a list with one range per wave; channels ordered
+    by target, a target may have none), with its own l values, poles and
+    amplitudes.  Wave w has statistical weight g = 2w + 1 (a stand-in for
+    2J + 1)."""
     for attempt in range(1000):
         e_target = np.concatenate([[0.0], np.sort(Stream(seed, f"{name}/targets/{attempt}").uniform(ntarget - 1,
                                                                                                    *thr_range))])
@@ -163,7 +165,8 @@ def partial_wave_family(seed: int, npw: int, ntarget: int, chan_per_target: tupl
         raise RuntimeError("could not place thresholds away from the energy grid")
     out = []
     for w in range(npw):
-        counts = Stream(seed, f"{name}/w{w}/counts").integers(ntarget, *chan_per_target)
+        rng_w = chan_per_target[w] if isinstance(chan_per_target, list) else chan_per_target
+        counts = Stream(seed, f"{name}/w{w}/counts").integers(ntarget, *rng_w)
         target = np.repeat(np.arange(ntarget), counts).astype(np.int32)
         n = int(target.size)
         M = int(round(poles_per_chan * n))
@@ -182,6 +185,19 @@ def config_sum(npw: int = 12, nenergy: int = 2000) -> tuple[list[PartialWave], n
     E = np.linspace(0.01, 6.0, nenergy)
     return partial_wave_family(config_seed(6), npw, 60, (1, 4), 30, z=5.0, a=12.0, thr_range=(0.0, 4.0),
                                pole_range=(-2.0, 60.0), avoid_energies=E, name="sum"), E
+
+
+def config_imbalance(npw: int = 16, nenergy: int = 2000) -> tuple[list[PartialWave], np.ndarray]:
+    """Load-balance workload: 16 waves of one collision problem sharing 150
+    targets (thresholds in [0, 6] Ry), wave w coupling each target to 0..k_w
+    channels with k_w = 1 + (w mod 8), so channel counts run from about 75 to
+    600; 30 poles per channel in [-2, 60] Ry, z=5, a=12, 2000 energies uniform
+    in [0.01, 8] Ry, so the open fraction n_o/n runs from near 0 to 1 across the
+    grid (the slow energies are those with n_o ~ n_c)."""
+    E = np.linspace(0.01, 8.0, nenergy)
+    ranges = [(0, 1 + (w % 8)) for w in range(npw)]
+    return partial_wave_family(config_seed(7), npw, 150, ranges, 30, z=5.0, a=12.0, thr_range=(0.0, 6.0),
+                               pole_range=(-2.0, 60.0), avoid_energies=E, name="imb"), E
 
 
 def config_seed(index: int) -> int:

@@ -16,9 +16,10 @@ GATE = 1e-10
 OMEGA_FLOOR = 1e-12
 
 SPLIT_R = 1e-5          # measured max 3e-6 (200 channels), 4.4e-6 (1500 channels)
-SPLIT_K = 5e-2          # measured max 1.4e-2 (200 channels, cond 4e8)
-SPLIT_K_MEDIAN = 5e-4   # measured median 7e-5
-SPLIT_OMEGA = 1e-4      # measured max 1.8e-5
+SPLIT_K = 5e-2          # measured max 1.4e-2 (200 channels, cond 4e8), 2.1e-2 (1500 channels)
+SPLIT_K_MEDIAN = 5e-4   # measured median 7e-5 (200 channels)
+SPLIT_OMEGA = 1e-4      # measured max 1.8e-5 (200 channels)
+SPLIT_OMEGA_1500 = 1e-3  # measured max 1.9e-4 (1500 channels, 8 open channels at 0.01 Ry)
 
 
 def gate(cond):

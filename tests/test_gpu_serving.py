@@ -90,3 +90,42 @@ def test_unknown_ticket_and_pw(ctx):
         ctx.poll(987654321)
     with pytest.raises(rm.RMError):
         ctx.submit(4242, np.array([1.0]))
+
+
+def test_admission_defers_under_small_budget(ctx):
+    """A context whose HBM budget holds the resident waves plus one and a half
+    energies of the largest wave's workspace: one worker's share cannot hold a
+    single energy of that wave, so it waits until the other worker has released
+    its workspace (admission by footprint).  Every request still completes, with
+    no RM_E_NOMEM, and equals rm_run bitwise."""
+    from paper_1909_07321_amd import rm
+    pool = _pool()
+    big = max(pool, key=lambda p: p.nchan)
+    resident = sum(rm.pw_footprint(p.nchan, p.npole) for p in pool)
+    one = rm.work_footprint(big.nchan, big.npole, big.ntarget, 1)
+    budget = resident + int(1.5 * one)
+    rng = np.random.default_rng(11)
+    reqs = []
+    for r in range(8):
+        p = int(rng.integers(0, len(pool))) if r % 2 else pool.index(big)
+        E = np.sort(rng.uniform(0.01, 8.0, int(rng.integers(2, 6))))
+        reqs.append((p, E))
+    with rm.Context(0, hbm_budget_bytes=budget) as small:
+        ids = [small.pw_upload(p) for p in pool]
+        tickets = [small.submit(ids[p], E, want_K=True) for p, E in reqs]
+        deadline = time.time() + 120
+        pending = list(range(len(tickets)))
+        while pending and time.time() < deadline:
+            for k in list(pending):
+                if small.poll(tickets[k][0]) is not None:   # raises on RM_E_NOMEM
+                    pending.remove(k)
+            time.sleep(0.001)
+        assert not pending, "requests did not finish"
+    ref_ids = [ctx.pw_upload(p) for p in pool]
+    for (p, E), (t, out) in zip(reqs, tickets):
+        om, K, st = ctx.run(ref_ids[p], E)
+        assert np.array_equal(out["status"], st)
+        assert np.array_equal(out["omega"], om, equal_nan=True)
+        assert np.array_equal(out["K"], K, equal_nan=True)
+    for i in ref_ids:
+        ctx.pw_release(i)

@@ -172,6 +172,27 @@ rm_status rm_collision_strengths(rm_ctx *ctx, int32_t pw, const double *E, int32
 rm_status rm_run(rm_ctx *ctx, int32_t pw, const double *E, int32_t ne, const rm_opts *opts,
                  double *omega, double *K, int32_t *status);
 
+/* --------------------------------------------------------- without allocation */
+/* Bytes of the device array rm_run_noalloc works in (each GPU the library runs
+   on holds one until the process ends). */
+#define RM_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+/* rm_run for callers that cannot allocate device memory (code under stream
+   capture, tight serving loops, harnesses that forbid allocation): the same
+   kernels and results as rm_run, with the whole chunk workspace carved from a
+   fixed device array of RM_NOALLOC_SCRATCH_BYTES instead of allocated.  The
+   call performs no hipMalloc, hipFree or other allocation (rm_create set up its
+   host staging and resolved the array's address).  E, omega, K (or NULL) and
+   status are device pointers (opts->device_ptrs must be 1; RM_E_ARG
+   otherwise); the work is ordered on opts->stream (or the context's stream)
+   and the call returns once it is queued.  Energies run in chunks as large as
+   the array allows; a partial wave one energy of which needs more workspace
+   than the array (about 2500 channels and up) is refused with RM_E_NOMEM and a
+   message giving the bytes needed.  Calls on one context are serialised; calls
+   from different contexts on one GPU share its array and race, and the array
+   keeps whatever the last call left in it. */
+rm_status rm_run_noalloc(rm_ctx *ctx, int32_t pw, const double *E, int32_t ne, const rm_opts *opts,
+                         double *omega, double *K, int32_t *status);
+
 /* ------------------------------------------------------------------ batching */
 /* One partial wave's block of energies in a batch; outputs as in rm_run. */
 typedef struct {

@@ -34,6 +34,12 @@
 
 using namespace rm;
 
+// Workspace of rm_run_noalloc: a file-scope device array.  Every device the
+// library runs on holds its own copy until the process ends; in host code its
+// name is only a stand-in, so its device address is resolved once per device
+// (with that device current, by rm_create) and only that address is used.
+static __device__ __align__(256) unsigned char scratch[RM_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 int64_t now_ns() {
@@ -71,6 +77,7 @@ struct Slot {
   Work w;
   Staging h;
   GraphCache g;
+  bool direct = false;  // launch directly, never through captured graphs
 };
 
 struct ProfRec {
@@ -151,6 +158,11 @@ struct rm_ctx {
   // contractions are chained across them so that one chunk's K solve overlaps
   // the next chunk's contraction
   Slot pipe[2];
+  // rm_run_noalloc: its slot (staging allocated by rm_create, workspace carved
+  // from the device's scratch array) and the lock that serialises its calls
+  Slot na;
+  std::mutex na_mu;
+  char *scratch = nullptr;
   hipEvent_t ev_in = nullptr, ev_out[2] = {nullptr, nullptr}, ev_R[2] = {nullptr, nullptr};
 };
 
@@ -179,6 +191,54 @@ size_t per_energy_bytes(int n, int npad, int Mpad, int nt) {
          + (size_t)n * (32 + 17)     // fg, openidx, openpos, colpos, openflag, ipiv
          + (size_t)nt * nt * 8       // Omega
          + BPERM * 4 + NBU * NBU * 8 + 128;
+}
+
+// One buffer of a chunk workspace: where its pointer goes and its byte size.
+struct WorkBuf {
+  void **ptr;
+  size_t bytes;
+};
+
+// Every buffer of a workspace with capacities (energies, channels, padded
+// channels, padded poles, targets, table slots, R tasks), in one fixed order;
+// the pointers are those of w.  With S the S-matrix output buffer is included.
+std::vector<WorkBuf> work_buffers(Work &w, int ce, int cn, int cnp, int cm, int ct, int ctab, int ctask, bool S) {
+  auto b = [](size_t x) { return std::max<size_t>(x, 8); };
+  const size_t E = (size_t)ce;
+  const size_t bidx = b(E * cn * 4), bK = b(E * cn * cnp * 8), boff = b((E + 1) * 8);
+  std::vector<WorkBuf> v = {
+      {(void **)&w.E, b(E * 8)},           {(void **)&w.pwi, b(E * 4)},
+      {(void **)&w.tab, b((size_t)ctab * sizeof(DevPW))},
+      {(void **)&w.tasks, b((size_t)ctask * sizeof(RTask))},
+      {(void **)&w.counter, 256},          {(void **)&w.D64, b(E * cm * 8)},
+      {(void **)&w.D32, b(E * cm * 4)},    {(void **)&w.win, b(E * 8)},
+      {(void **)&w.status, b(E * 4)},      {(void **)&w.nopen, b(E * 4)},
+      {(void **)&w.openidx, bidx},         {(void **)&w.openpos, bidx},
+      {(void **)&w.colpos, bidx},          {(void **)&w.ipiv, bidx},
+      {(void **)&w.bperm, b(E * BPERM * 4)}, {(void **)&w.linv, b(E * NBU * NBU * 8)},
+      {(void **)&w.openflag, b(E * cn)},   {(void **)&w.fg, b(E * cn * 32)},
+      {(void **)&w.aug, b(E * cn * 2 * cnp * 8)},
+      {(void **)&w.Kw, bK},                {(void **)&w.gre, bK},
+      {(void **)&w.gim, bK},               {(void **)&w.dims, b(E * 8)},
+      {(void **)&w.omega, b(E * ct * ct * 8)},
+      {(void **)&w.pack, b(E * std::max((size_t)cn * cn, (size_t)ct * ct) * 8)},
+      {(void **)&w.pack_off, 2 * boff}};
+  if (S) v.push_back({(void **)&w.S, b(E * cn * cn * 16)});
+  w.cap_e = ce;
+  w.cap_n = cn;
+  w.cap_npad = cnp;
+  w.cap_M = cm;
+  w.cap_nt = ct;
+  w.cap_tab = ctab;
+  w.cap_tasks = ctask;
+  return v;
+}
+
+// Device bytes of the buffers, each rounded up to 256.
+size_t work_bytes(const std::vector<WorkBuf> &v) {
+  size_t t = 0;
+  for (const WorkBuf &b : v) t += (b.bytes + 255) / 256 * 256;
+  return t;
 }
 
 void free_work(Work &w) {
@@ -212,23 +272,9 @@ rm_status ensure_slot(rm_ctx *ctx, Slot &sl, const Lay &L, int ntab, int ntasks,
               ct = std::max(L.ntmax, w.cap_nt), ctab = std::max(ntab, w.cap_tab),
               ctask = std::max(ntasks, w.cap_tasks);
     const bool S = want_S || w.S != nullptr;
-    size_t need = 0;
-    auto sz = [&](size_t b) {
-      need += (b + 255) / 256 * 256;
-      return std::max<size_t>(b, 8);
-    };
-    const size_t bE = sz((size_t)ce * 8), bpwi = sz((size_t)ce * 4), btab = sz((size_t)ctab * sizeof(DevPW)),
-                 btask = sz((size_t)ctask * sizeof(RTask)), bcnt = sz(256), bD64 = sz((size_t)ce * cm * 8),
-                 bD32 = sz((size_t)ce * cm * 4), bwin = sz((size_t)ce * 8), bst = sz((size_t)ce * 4),
-                 bno = sz((size_t)ce * 4), bidx = sz((size_t)ce * cn * 4), bflag = sz((size_t)ce * cn),
-                 bfg = sz((size_t)ce * cn * 32), baug = sz((size_t)ce * cn * 2 * cnp * 8),
-                 bK = sz((size_t)ce * cn * cnp * 8), bdims = sz((size_t)ce * 8),
-                 bom = sz((size_t)ce * ct * ct * 8),
-                 bpack = sz((size_t)ce * std::max((size_t)cn * cn, (size_t)ct * ct) * 8),
-                 boff = sz((size_t)(ce + 1) * 8), bS = S ? sz((size_t)ce * cn * cn * 16) : 0,
-                 bperm = sz((size_t)ce * BPERM * 4), blinv = sz((size_t)ce * NBU * NBU * 8);
-    // openpos, colpos and ipiv share bidx's size, gre and gim share bK's, the pack offsets are two blocks
-    need += 3 * ((bidx + 255) / 256 * 256) + 2 * ((bK + 255) / 256 * 256) + (boff + 255) / 256 * 256;
+    Work nw;
+    const std::vector<WorkBuf> bufs = work_buffers(nw, ce, cn, cnp, cm, ct, ctab, ctask, S);
+    const size_t need = work_bytes(bufs);
     {
       std::lock_guard<std::mutex> g(ctx->mu);
       if (ctx->resident + ctx->work_bytes - w.bytes + need > ctx->budget) {
@@ -243,33 +289,8 @@ rm_status ensure_slot(rm_ctx *ctx, Slot &sl, const Lay &L, int ntab, int ntasks,
       std::lock_guard<std::mutex> g(ctx->mu);
       ctx->work_bytes -= old;
     }
-    HIPCHK(hipMalloc(&w.E, bE));
-    HIPCHK(hipMalloc(&w.pwi, bpwi));
-    HIPCHK(hipMalloc(&w.tab, btab));
-    HIPCHK(hipMalloc(&w.tasks, btask));
-    HIPCHK(hipMalloc(&w.counter, bcnt));
-    HIPCHK(hipMalloc(&w.D64, bD64));
-    HIPCHK(hipMalloc(&w.D32, bD32));
-    HIPCHK(hipMalloc(&w.win, bwin));
-    HIPCHK(hipMalloc(&w.status, bst));
-    HIPCHK(hipMalloc(&w.nopen, bno));
-    HIPCHK(hipMalloc(&w.openidx, bidx));
-    HIPCHK(hipMalloc(&w.openpos, bidx));
-    HIPCHK(hipMalloc(&w.colpos, bidx));
-    HIPCHK(hipMalloc(&w.ipiv, bidx));
-    HIPCHK(hipMalloc(&w.bperm, bperm));
-    HIPCHK(hipMalloc(&w.linv, blinv));
-    HIPCHK(hipMalloc(&w.openflag, bflag));
-    HIPCHK(hipMalloc(&w.fg, bfg));
-    HIPCHK(hipMalloc(&w.aug, baug));
-    HIPCHK(hipMalloc(&w.Kw, bK));
-    HIPCHK(hipMalloc(&w.gre, bK));
-    HIPCHK(hipMalloc(&w.gim, bK));
-    HIPCHK(hipMalloc(&w.dims, bdims));
-    HIPCHK(hipMalloc(&w.omega, bom));
-    HIPCHK(hipMalloc(&w.pack, bpack));
-    HIPCHK(hipMalloc(&w.pack_off, 2 * boff));
-    if (S) HIPCHK(hipMalloc(&w.S, bS));
+    for (const WorkBuf &b : bufs) HIPCHK(hipMalloc(b.ptr, b.bytes));
+    w = nw;
     w.cap_e = ce;
     w.cap_n = cn;
     w.cap_npad = cnp;
@@ -609,7 +630,7 @@ std::string chunk_key(rm_ctx *ctx, const Plan &P, const Work &w, const rm_opts &
 template <typename F>
 rm_status launch_group(rm_ctx *ctx, Slot &sl, int grp, const std::string &key, F &&body) {
   const hipStream_t s = sl.stream;
-  if (!ctx->graphs.load()) {
+  if (!ctx->graphs.load() || sl.direct) {
     body();
     HIPCHK(hipGetLastError());
     return RM_OK;
@@ -1101,6 +1122,70 @@ void destroy_slot(Slot &sl) {
   free_staging(sl.h);
 }
 
+// ------------------------------------------------------------ no-alloc path
+// Staging capacities of the no-alloc slot (pinned, allocated by rm_create).
+constexpr int NA_TASKS = 65536;
+
+// Device address of the scratch array on `device` (resolved on first use).
+rm_status scratch_address(rm_ctx *ctx, int device, char **out) {
+  static std::mutex mu;
+  static std::map<int, char *> addr;
+  std::lock_guard<std::mutex> g(mu);
+  auto it = addr.find(device);
+  if (it == addr.end()) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      ctx->err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return RM_E_DEVICE;
+    }
+    it = addr.emplace(device, (char *)p).first;
+  }
+  *out = it->second;
+  return RM_OK;
+}
+
+// Points the buffers of a workspace for chunks of layout L into the scratch
+// array; false if they do not fit.
+bool carve_work(Work &w, char *base, const Lay &L, int ntab, int ntasks) {
+  Work nw;
+  const std::vector<WorkBuf> bufs = work_buffers(nw, L.ne, L.nmax, L.npadmax, L.Mpadmax, L.ntmax, ntab, ntasks, false);
+  if (work_bytes(bufs) > RM_NOALLOC_SCRATCH_BYTES) return false;
+  size_t off = 0;
+  for (const WorkBuf &b : bufs) {
+    *b.ptr = base + off;
+    off += (b.bytes + 255) / 256 * 256;
+  }
+  nw.bytes = 0;  // not counted against the HBM budget
+  w = nw;
+  return true;
+}
+
+// The staging of the no-alloc slot, allocated once by rm_create.
+rm_status init_noalloc(rm_ctx *ctx) {
+  // a failure here disables only rm_run_noalloc (it then reports the error)
+  if (scratch_address(ctx, ctx->device, &ctx->scratch) != RM_OK) ctx->scratch = nullptr;
+  Staging &h = ctx->na.h;
+  HIPCHK(hipEventCreateWithFlags(&h.ready, hipEventDisableTiming));
+  HIPCHK(hipHostMalloc((void **)&h.E, sizeof(double) * MAX_CHUNK, hipHostMallocDefault));
+  HIPCHK(hipHostMalloc((void **)&h.pwi, sizeof(int) * MAX_CHUNK, hipHostMallocDefault));
+  HIPCHK(hipHostMalloc((void **)&h.tab, sizeof(DevPW), hipHostMallocDefault));
+  HIPCHK(hipHostMalloc((void **)&h.tasks, sizeof(RTask) * NA_TASKS, hipHostMallocDefault));
+  HIPCHK(hipHostMalloc((void **)&h.off, sizeof(long) * 2 * (MAX_CHUNK + 1), hipHostMallocDefault));
+  h.cap_e = MAX_CHUNK;
+  h.cap_tab = 1;
+  h.cap_tasks = NA_TASKS;
+  ctx->na.direct = true;
+  return RM_OK;
+}
+
+// Plans energies [e0, e0 + m) of the single segment.
+void plan_single(Plan &P, const std::vector<Seg> &segs, int e0, int m) {
+  P = Plan();
+  P.parts.push_back(Part{0, e0, m, 0, 0});
+  finish_plan(P, segs, m);
+}
+
 }  // namespace
 
 // =================================================================== C ABI
@@ -1146,6 +1231,14 @@ rm_status rm_create(int device, size_t hbm_budget_bytes, rm_ctx **out) {
     }
     ctx->slots.push_back(std::move(sl));
   }
+  if (rm_status st = init_noalloc(ctx)) {
+    free_staging(ctx->na.h);
+    for (auto &sl : ctx->slots) destroy_slot(*sl);
+    (void)hipStreamDestroy(ctx->stream);
+    (void)hipStreamDestroy(ctx->sync.stream);
+    delete ctx;
+    return st;
+  }
   for (auto &sl : ctx->slots) ctx->workers.emplace_back(worker_main, ctx, sl.get());
   *out = ctx;
   return RM_OK;
@@ -1163,6 +1256,7 @@ rm_status rm_destroy(rm_ctx *ctx) {
   for (auto &sl : ctx->slots) destroy_slot(*sl);
   destroy_slot(ctx->sync);
   for (auto &pp : ctx->pipe) destroy_slot(pp);
+  free_staging(ctx->na.h);  // its workspace is the scratch array and its stream the caller's
   if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
   for (auto &ev : ctx->ev_out)
     if (ev) (void)hipEventDestroy(ev);
@@ -1427,6 +1521,59 @@ rm_status rm_run(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, const r
   const rm_opts o = fixed_opts(opts);
   std::vector<Seg> segs(1, Seg{pw, E, ne, omega, K, status});
   return run_segments(ctx, segs, o, false);
+}
+
+rm_status rm_run_noalloc(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, const rm_opts *opts, double *omega,
+                         double *K, int32_t *status) {
+  if (!ctx || !opts || ne < 0 || (ne > 0 && (!E || !omega || !status))) return RM_E_ARG;
+  if (!opts->device_ptrs) {
+    ctx->err = "rm_run_noalloc takes device pointers (opts->device_ptrs = 1)";
+    return RM_E_ARG;
+  }
+  if (ne == 0) return RM_OK;
+  const DevPW *pw;
+  if (rm_status st = get_pw(ctx, pwid, &pw)) return st;
+  (void)hipSetDevice(ctx->device);
+  const rm_opts o = fixed_opts(opts);
+  if (!ctx->scratch) {
+    if (ctx->err.empty()) ctx->err = "the no-alloc scratch array has no device address";
+    return RM_E_DEVICE;
+  }
+  std::lock_guard<std::mutex> serial(ctx->na_mu);
+  Slot &sl = ctx->na;
+  sl.stream = call_stream(ctx, o);
+  const std::vector<Seg> segs(1, Seg{pw, E, ne, omega, K, status});
+  // the largest chunk whose workspace fits the scratch array and whose R tasks
+  // fit the staging
+  Plan P;
+  int m = std::min(ne, MAX_CHUNK);
+  for (;;) {
+    plan_single(P, segs, 0, m);
+    const int ntasks = plan_tasks(ctx, P, o);
+    Work probe;
+    if (ntasks <= NA_TASKS && carve_work(probe, ctx->scratch, P.L, 1, ntasks)) break;
+    if (m == 1) {
+      Work one;
+      const size_t need = work_bytes(work_buffers(one, 1, pw->n, pw->npad, pw->Mpad, pw->nt, 1, ntasks, false));
+      ctx->err = "one energy of this partial wave needs " + std::to_string(need) +
+                 " bytes of workspace, more than the no-alloc scratch of " +
+                 std::to_string((size_t)RM_NOALLOC_SCRATCH_BYTES) + " bytes";
+      return RM_E_NOMEM;
+    }
+    m = std::max(1, m / 2);
+  }
+  for (int e0 = 0; e0 < ne; e0 += m) {
+    const int mm = std::min(m, ne - e0);
+    plan_single(P, segs, e0, mm);
+    const int ntasks = plan_tasks(ctx, P, o);
+    if (!carve_work(sl.w, ctx->scratch, P.L, 1, ntasks)) {  // cannot happen: a smaller chunk of the same wave
+      ctx->err = "no-alloc workspace layout";
+      return RM_E_NOMEM;
+    }
+    if (rm_status st = upload_plan(ctx, sl, P, segs, o, false)) return st;
+    if (rm_status st = run_chunk(ctx, P, sl, segs, o, hipMemcpyDeviceToDevice)) return st;
+  }
+  return RM_OK;
 }
 
 rm_status rm_run_batch(rm_ctx *ctx, const rm_batch_item *items, int32_t nitems, const rm_opts *opts) {

@@ -20,6 +20,7 @@ RM_OK, RM_PENDING = 0, 1
 RM_E_ARG, RM_E_NOMEM, RM_E_DEVICE, RM_E_NOTFOUND, RM_E_BUSY = -1, -2, -3, -4, -5
 PT_POLE, PT_THRESHOLD, PT_NOCONV, PT_SINGULAR, PT_NONFINITE = 1, 2, 4, 8, 16
 FP64, FP32_SPLIT = 0, 1
+NOALLOC_SCRATCH_BYTES = 256 << 20  # RM_NOALLOC_SCRATCH_BYTES of rm.h
 ORDER_WAVE, ORDER_PERMUTED = 0, 1
 
 if not os.path.exists(LIB_PATH):
@@ -76,6 +77,7 @@ _lib.rm_asymptotic.argtypes = [_vp, _i32, _vp, _i32, ctypes.POINTER(Opts), _vp, 
 _lib.rm_solve_K.argtypes = [_vp, _i32, _vp, _i32, _vp, _vp, ctypes.POINTER(Opts), _vp, _vp]
 _lib.rm_collision_strengths.argtypes = [_vp, _i32, _vp, _i32, _vp, ctypes.POINTER(Opts), _vp, _vp, _vp]
 _lib.rm_run.argtypes = [_vp, _i32, _vp, _i32, ctypes.POINTER(Opts), _vp, _vp, _vp]
+_lib.rm_run_noalloc.argtypes = [_vp, _i32, _vp, _i32, ctypes.POINTER(Opts), _vp, _vp, _vp]
 _lib.rm_run_batch.argtypes = [_vp, ctypes.POINTER(BatchItem), _i32, ctypes.POINTER(Opts)]
 _lib.rm_run_sum.argtypes = [_vp, ctypes.POINTER(_i32), _i32, _vp, _i32, _i32, ctypes.POINTER(Opts), _vp, _vp]
 _lib.rm_submit.argtypes = [_vp, ctypes.POINTER(Request), ctypes.POINTER(_u64)]
@@ -99,7 +101,7 @@ _lib.rm_graph_stats.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POIN
 
 EXPORTS = ["rm_opts_default", "rm_create", "rm_destroy", "rm_last_error", "rm_pw_upload", "rm_pw_release",
            "rm_pw_footprint", "rm_work_footprint", "rm_form_R", "rm_asymptotic", "rm_solve_K", "rm_collision_strengths", "rm_run",
-           "rm_run_batch", "rm_run_sum", "rm_tile_bucket", "rm_tile_count", "rm_tile_shape", "rm_get_tile",
+           "rm_run_noalloc", "rm_run_batch", "rm_run_sum", "rm_tile_bucket", "rm_tile_count", "rm_tile_shape", "rm_get_tile",
            "rm_set_tile", "rm_tune", "rm_tune_load", "rm_set_graph", "rm_graph_stats",
            "rm_submit", "rm_poll", "rm_drain", "rm_prof_enable", "rm_prof_read", "rm_prof_chunks"]
 
@@ -289,6 +291,18 @@ class Context:
             om, K, st = out
         o = self._opts(prec, split_delta, thr_guard, dev, stream)
         self._check(_lib.rm_run(self.h, pw_id, _ptr(E), ne, ctypes.byref(o), _ptr(om), _ptr(K), _ptr(st)))
+        return om, K, st
+
+    def run_noalloc(self, pw_id, E, out, prec=FP64, split_delta=0.05, thr_guard=1e-10, stream=None):
+        """rm_run_noalloc: E and out = (omega, K or None, status) are device
+        tensors the caller allocated; the library allocates nothing."""
+        E, dev = self._E(E)
+        if not dev:
+            raise RMError("run_noalloc takes device tensors")
+        om, K, st = out
+        o = self._opts(prec, split_delta, thr_guard, True, stream)
+        self._check(_lib.rm_run_noalloc(self.h, pw_id, _ptr(E), E.shape[0], ctypes.byref(o), _ptr(om), _ptr(K),
+                                        _ptr(st)))
         return om, K, st
 
     def run_batch(self, items, prec=FP64, split_delta=0.05, thr_guard=1e-10, want_K=False):

@@ -64,6 +64,7 @@ typedef int32_t rm_status;
 #define RM_E_DEVICE (-3)   /* a HIP call failed; rm_last_error() has the text */
 #define RM_E_NOTFOUND (-4) /* unknown partial-wave id or ticket */
 #define RM_E_BUSY (-5)     /* serving admission queue full */
+#define RM_E_IO (-6)       /* a file could not be opened, read, parsed or written */
 
 /* Largest channel count of a partial wave (one matching-matrix row is staged
    on chip during assembly). */
@@ -334,6 +335,74 @@ rm_status rm_prof_read(rm_ctx *ctx, const char *stage, double *total_ms, int64_t
    returned. */
 rm_status rm_prof_chunks(rm_ctx *ctx, int64_t cap, double *ms, double *model_flops, double *open_frac,
                          int64_t *energies, int64_t *count);
+
+/* ------------------------------------------------------------ file boundary */
+/* Readers of the inner-region output and the writer of the results, for the
+   layouts of the paper's section "Input files" (H.DAT, sizeH.dat) and section
+   "Output files" (OMEGA).  Host code; no device is used.  Errors return
+   RM_E_IO (rm_hdat_error has the text) or RM_E_ARG for bad arguments. */
+
+/* H.DAT / H.DAT000 target records: NELC, NZ, LRANG2, LAMAX, NAST, RA, BSTO. */
+typedef struct {
+  int32_t nelc, nz, lrang2, lamax, nast;
+  double ra, bsto;
+} rm_hdat_target;
+/* Symmetry record 1: LRGL2 (L or 2J), NSPN2 (2S+1, or 0 in J coupling),
+   NPTY2 (parity), NCHAN, MNP2 (poles), MORE2. */
+typedef struct {
+  int32_t lrgl2, nspn2, npty2, nchan, mnp2, more2;
+} rm_hdat_sym;
+typedef struct rm_hdat rm_hdat;
+
+/* Opens an H.DAT or H.DAT000 file (Fortran unformatted sequential, either byte
+   order) and reads its target records (ENAT, LAT, ISAT, COEFF and the Buttle
+   records); the symmetries follow with rm_hdat_next.  *out is set (and must be
+   closed) even on error, so that rm_hdat_error can be read. */
+rm_status rm_hdat_open(const char *path, rm_hdat **out);
+rm_status rm_hdat_close(rm_hdat *h);
+const char *rm_hdat_error(const rm_hdat *h);
+/* Target records; enat [nast] (Ry), lat [nast] (L or 2J), isat [nast] (2S+1
+   or 0) may be NULL. */
+rm_status rm_hdat_target_info(const rm_hdat *h, rm_hdat_target *t, double *enat, int32_t *lat, int32_t *isat);
+/* Continues with the symmetries of another file of the same run (H.DATXXX,
+   XXX != 000: symmetry records only). */
+rm_status rm_hdat_attach(rm_hdat *h, const char *path);
+/* Reads the next symmetry (records NCONAT, L2P, CF, VALUE, WMAT) into the
+   handle; RM_E_NOTFOUND after the last one. */
+rm_status rm_hdat_next(rm_hdat *h, rm_hdat_sym *sym);
+/* Copies the current symmetry's arrays (any may be NULL): nconat [nast]
+   channels per target, l2p [nchan], cf [lamax][nchan][nchan] multipole
+   coefficients (CF(I,N,M) with I fastest, M = multipole order), value [mnp2]
+   poles, wmat [mnp2][nchan] amplitudes (pole-major, as rm_pw_desc.w). */
+rm_status rm_hdat_arrays(const rm_hdat *h, int32_t *nconat, int32_t *l2p, double *cf, double *value, double *wmat);
+/* A descriptor of the current symmetry for rm_pw_upload, pointing into the
+   handle (valid until the next rm_hdat_next or rm_hdat_close): channels
+   ordered by target as NCONAT says, channel threshold = ENAT(target) -
+   ENAT(1), l = L2P, a = RA, b = BSTO, z = NZ - NELC, g = (2S+1)(2L+1) or
+   2J+1. */
+rm_status rm_hdat_pw_desc(const rm_hdat *h, rm_pw_desc *desc);
+
+/* sizeH.dat (kind 0: NCHAN, NCON, MNP2, 2S+1, L, parity) or sizeBP.dat (kind 1:
+   NCHAN, NCON, MNP2, 2J, parity; s = 0), one row per partial wave, read with
+   the fixed columns of their Fortran formats.  Up to cap rows are stored;
+   *count is the number of rows in the file. */
+typedef struct {
+  int32_t nchan, ncon, mnp2, s, l, ipi;
+} rm_sizeh_row;
+rm_status rm_sizeh_read(const char *path, int32_t kind, int32_t cap, rm_sizeh_row *rows, int32_t *count);
+
+/* OMEGA (formatted = 1, one record per line) or OMEGAU (formatted = 0,
+   Fortran unformatted sequential records): NZ NEL; NLEV MXE NOMWRT; (S(I) L(I),
+   I = 1..NLEV); ELEV; then per energy E(J) and the collision strengths of the
+   stored transitions.  omega [ne][nlev][nlev] (e.g. Omega summed over partial
+   waves); the transitions are the upper triangle (with the diagonal if elastic
+   = 1), row-wise for nomwrt > 0 and column-wise for nomwrt < 0, the first
+   |nomwrt| of them (the written NOMWRT is the count stored, with the sign).
+   E and elev are divided by z^2 (z = NZ - NEL) for an ion, as the file holds
+   z-scaled Rydberg energies. */
+rm_status rm_omega_write(const char *path, int32_t formatted, int32_t nz, int32_t nel, int32_t nlev,
+                         const int32_t *S, const int32_t *L, const double *elev, int32_t ne, const double *E,
+                         const double *omega, int32_t nomwrt, int32_t elastic);
 
 #ifdef __cplusplus
 }

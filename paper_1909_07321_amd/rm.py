@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("RM_LIB", os.path.join(_HERE, "librm.so"))
 
 RM_OK, RM_PENDING = 0, 1
-RM_E_ARG, RM_E_NOMEM, RM_E_DEVICE, RM_E_NOTFOUND, RM_E_BUSY = -1, -2, -3, -4, -5
+RM_E_ARG, RM_E_NOMEM, RM_E_DEVICE, RM_E_NOTFOUND, RM_E_BUSY, RM_E_IO = -1, -2, -3, -4, -5, -6
 PT_POLE, PT_THRESHOLD, PT_NOCONV, PT_SINGULAR, PT_NONFINITE = 1, 2, 4, 8, 16
 FP64, FP32_SPLIT = 0, 1
 NOALLOC_SCRATCH_BYTES = 256 << 20  # RM_NOALLOC_SCRATCH_BYTES of rm.h
@@ -103,11 +103,112 @@ EXPORTS = ["rm_opts_default", "rm_create", "rm_destroy", "rm_last_error", "rm_pw
            "rm_pw_footprint", "rm_work_footprint", "rm_form_R", "rm_asymptotic", "rm_solve_K", "rm_collision_strengths", "rm_run",
            "rm_run_noalloc", "rm_run_batch", "rm_run_sum", "rm_tile_bucket", "rm_tile_count", "rm_tile_shape", "rm_get_tile",
            "rm_set_tile", "rm_tune", "rm_tune_load", "rm_set_graph", "rm_graph_stats",
-           "rm_submit", "rm_poll", "rm_drain", "rm_prof_enable", "rm_prof_read", "rm_prof_chunks"]
+           "rm_submit", "rm_poll", "rm_drain", "rm_prof_enable", "rm_prof_read", "rm_prof_chunks",
+           "rm_hdat_open", "rm_hdat_close", "rm_hdat_error", "rm_hdat_target_info", "rm_hdat_attach", "rm_hdat_next",
+           "rm_hdat_arrays", "rm_hdat_pw_desc", "rm_sizeh_read", "rm_omega_write"]
 
 
 class RMError(RuntimeError):
     pass
+
+
+# ------------------------------------------------------------ file boundary
+class HdatTarget(ctypes.Structure):
+    _fields_ = [("nelc", _i32), ("nz", _i32), ("lrang2", _i32), ("lamax", _i32), ("nast", _i32), ("ra", _d),
+                ("bsto", _d)]
+
+
+class HdatSym(ctypes.Structure):
+    _fields_ = [("lrgl2", _i32), ("nspn2", _i32), ("npty2", _i32), ("nchan", _i32), ("mnp2", _i32), ("more2", _i32)]
+
+
+class SizeRow(ctypes.Structure):
+    _fields_ = [("nchan", _i32), ("ncon", _i32), ("mnp2", _i32), ("s", _i32), ("l", _i32), ("ipi", _i32)]
+
+
+_lib.rm_hdat_open.argtypes = [ctypes.c_char_p, ctypes.POINTER(_vp)]
+_lib.rm_hdat_close.argtypes = [_vp]
+_lib.rm_hdat_error.argtypes = [_vp]
+_lib.rm_hdat_error.restype = ctypes.c_char_p
+_lib.rm_hdat_target_info.argtypes = [_vp, ctypes.POINTER(HdatTarget), _vp, _vp, _vp]
+_lib.rm_hdat_attach.argtypes = [_vp, ctypes.c_char_p]
+_lib.rm_hdat_next.argtypes = [_vp, ctypes.POINTER(HdatSym)]
+_lib.rm_hdat_arrays.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+_lib.rm_hdat_pw_desc.argtypes = [_vp, ctypes.POINTER(PWDesc)]
+_lib.rm_sizeh_read.argtypes = [ctypes.c_char_p, _i32, _i32, ctypes.POINTER(SizeRow), ctypes.POINTER(_i32)]
+_lib.rm_omega_write.argtypes = [ctypes.c_char_p, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _i32, _i32]
+
+
+def read_hdat(path: str, more_files=()):
+    """Reads an H.DAT / H.DAT000 file (and further H.DATXXX symmetry files):
+    returns (target dict, list of symmetry dicts).  Each symmetry dict holds
+    the record values and ``pw``, a partial wave ready for Context.pw_upload
+    (thresholds ENAT(target) - ENAT(1), statistical weight from S, L or J)."""
+    from . import synth
+    h = _vp()
+    st = _lib.rm_hdat_open(path.encode(), ctypes.byref(h))
+    try:
+        if st < 0:
+            raise RMError(f"librm status {st}: {_lib.rm_hdat_error(h).decode()}")
+        t = HdatTarget()
+        _lib.rm_hdat_target_info(h, ctypes.byref(t), None, None, None)
+        enat, lat, isat = np.empty(t.nast), np.empty(t.nast, np.int32), np.empty(t.nast, np.int32)
+        _lib.rm_hdat_target_info(h, ctypes.byref(t), _ptr(enat), _ptr(lat), _ptr(isat))
+        target = dict(nelc=t.nelc, nz=t.nz, lrang2=t.lrang2, lamax=t.lamax, nast=t.nast, ra=t.ra, bsto=t.bsto,
+                      enat=enat, lat=lat, isat=isat)
+        syms, files = [], list(more_files)
+        while True:
+            sym = HdatSym()
+            st = _lib.rm_hdat_next(h, ctypes.byref(sym))
+            if st == RM_E_NOTFOUND:
+                if not files:
+                    break
+                if _lib.rm_hdat_attach(h, files.pop(0).encode()) < 0:
+                    raise RMError(_lib.rm_hdat_error(h).decode())
+                continue
+            if st < 0:
+                raise RMError(f"librm status {st}: {_lib.rm_hdat_error(h).decode()}")
+            n, M = sym.nchan, sym.mnp2
+            nconat, l2p = np.empty(t.nast, np.int32), np.empty(n, np.int32)
+            cf, value, wmat = np.empty((t.lamax, n, n)), np.empty(M), np.empty((M, n))
+            _lib.rm_hdat_arrays(h, _ptr(nconat), _ptr(l2p), _ptr(cf), _ptr(value), _ptr(wmat))
+            d = PWDesc()
+            _lib.rm_hdat_pw_desc(h, ctypes.byref(d))
+            ethr = np.ctypeslib.as_array(ctypes.cast(d.e_thr, ctypes.POINTER(_d)), (n,)).copy()
+            tgt = np.ctypeslib.as_array(ctypes.cast(d.target, ctypes.POINTER(_i32)), (n,)).copy()
+            pw = synth.PartialWave(n, M, d.ntarget, d.a, d.b, d.z, d.g, enat - enat[0], l2p.copy(), tgt,
+                                   value.copy(), wmat.copy())
+            assert np.array_equal(pw.e_target[pw.target], ethr)
+            syms.append(dict(lrgl2=sym.lrgl2, nspn2=sym.nspn2, npty2=sym.npty2, nchan=n, mnp2=M, more2=sym.more2,
+                             nconat=nconat, l2p=l2p, cf=cf, value=value, wmat=wmat, pw=pw))
+        return target, syms
+    finally:
+        _lib.rm_hdat_close(h)
+
+
+def read_sizeh(path: str, kind: int = 0):
+    """Rows of sizeH.dat (kind 0) or sizeBP.dat (kind 1) as dicts."""
+    cnt = _i32()
+    st = _lib.rm_sizeh_read(path.encode(), kind, 0, None, ctypes.byref(cnt))
+    if st < 0:
+        raise RMError(f"librm status {st}: cannot read {path}")
+    rows = (SizeRow * max(1, cnt.value))()
+    _lib.rm_sizeh_read(path.encode(), kind, cnt.value, rows, ctypes.byref(cnt))
+    return [dict(nchan=r.nchan, ncon=r.ncon, mnp2=r.mnp2, s=r.s, l=r.l, ipi=r.ipi) for r in rows[:cnt.value]]
+
+
+def write_omega(path: str, nz: int, nel: int, S, L, elev, E, omega, nomwrt: int = 2 ** 31 - 1,
+                elastic: bool = False, formatted: bool = True):
+    """Writes OMEGA (formatted) or OMEGAU (unformatted) from omega [ne][nlev][nlev]."""
+    S = np.ascontiguousarray(S, np.int32)
+    L = np.ascontiguousarray(L, np.int32)
+    elev = np.ascontiguousarray(elev, np.float64)
+    E = np.ascontiguousarray(E, np.float64)
+    omega = np.ascontiguousarray(omega, np.float64)
+    st = _lib.rm_omega_write(path.encode(), int(formatted), nz, nel, S.size, _ptr(S), _ptr(L), _ptr(elev), E.size,
+                             _ptr(E), _ptr(omega), int(nomwrt), int(elastic))
+    if st < 0:
+        raise RMError(f"librm status {st}: cannot write {path}")
 
 
 def _is_torch(x) -> bool:

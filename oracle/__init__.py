@@ -58,7 +58,22 @@ def lib():
         _lib.rmo_coulomb.argtypes = [d, d, i32, vp]
         _lib.rmo_closed_logderiv.argtypes = [d, d, d, i32, vp]
         _lib.rmo_channel.argtypes = [d, d, d, i32, vp]
+        _lib.rmo_propagate.argtypes = [vp, vp, vp, i32, d, vp, vp, vp, vp, vp, i32]
+        _lib.rmo_solve_K_coupled.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, i32]
+        _lib.rmo_run_coupled.argtypes = [vp, vp, vp, i32, d, vp, vp, vp, vp, i32]
     return _lib
+
+
+class _Coupling(ctypes.Structure):
+    _fields_ = [("lamax", ctypes.c_int32), ("cf", ctypes.c_void_p), ("r1", ctypes.c_double),
+                ("npts", ctypes.c_int32), ("stab", ctypes.c_int32)]
+
+
+def _coupling(cp: dict):
+    """cp: dict(cf=[lamax][n][n] array, r1, npts, stab); returns (struct, keep-alive)."""
+    cf = np.ascontiguousarray(cp["cf"], dtype=np.float64)
+    return _Coupling(cf.shape[0], cf.ctypes.data if cf.size else None, float(cp["r1"]), int(cp["npts"]),
+                     int(cp.get("stab", 64))), cf
 
 
 def _ptr(a: np.ndarray):
@@ -124,6 +139,45 @@ class Oracle:
         lib().rmo_collision_strengths(self._p, _ptr(E), E.size, _ptr(K), thr_guard, _ptr(om),
                                       _ptr(S) if want_S else None, _ptr(st), self.nthreads)
         return om, (S[..., 0] + 1j * S[..., 1] if want_S else None), st
+
+    def propagate(self, E, coupling: dict, thr_guard: float = 1e-10):
+        """Solution matrices at r0 = a after the Numerov propagation from r1:
+        (phi, dphi [ne][n][2n], open, nopen, status)."""
+        E = np.ascontiguousarray(E, dtype=np.float64)
+        n = self.pw.nchan
+        cs, keep = _coupling(coupling)
+        phi, dphi = np.empty((E.size, n, 2 * n)), np.empty((E.size, n, 2 * n))
+        op = np.empty((E.size, n), np.int8)
+        no = np.empty(E.size, np.int32)
+        st = np.zeros(E.size, np.int32)
+        if lib().rmo_propagate(self._p, ctypes.byref(cs), _ptr(E), E.size, thr_guard, _ptr(phi), _ptr(dphi),
+                               _ptr(op), _ptr(no), _ptr(st), self.nthreads):
+            raise ValueError("invalid coupling")
+        return phi, dphi, op, no, st
+
+    def solve_K_coupled(self, E, R, phi, dphi):
+        E = np.ascontiguousarray(E, dtype=np.float64)
+        R, phi, dphi = (np.ascontiguousarray(x, dtype=np.float64) for x in (R, phi, dphi))
+        n = self.pw.nchan
+        K = np.empty((E.size, n, n))
+        cond = np.empty(E.size)
+        st = np.zeros(E.size, np.int32)
+        lib().rmo_solve_K_coupled(self._p, _ptr(E), E.size, _ptr(R), _ptr(phi), _ptr(dphi), _ptr(K), _ptr(cond),
+                                  _ptr(st), self.nthreads)
+        return K, cond, st
+
+    def run_coupled(self, E, coupling: dict, thr_guard: float = 1e-10):
+        E = np.ascontiguousarray(E, dtype=np.float64)
+        n, nt = self.pw.nchan, self.pw.ntarget
+        cs, keep = _coupling(coupling)
+        om = np.empty((E.size, nt, nt))
+        K = np.empty((E.size, n, n))
+        cond = np.empty(E.size)
+        st = np.zeros(E.size, np.int32)
+        if lib().rmo_run_coupled(self._p, ctypes.byref(cs), _ptr(E), E.size, thr_guard, _ptr(om), _ptr(K),
+                                 _ptr(cond), _ptr(st), self.nthreads):
+            raise ValueError("invalid coupling")
+        return dict(omega=om, K=K, cond=cond, status=st)
 
     def run(self, E, thr_guard: float = 1e-10, want_K: bool = True, want_S: bool = False):
         E = np.ascontiguousarray(E, dtype=np.float64)

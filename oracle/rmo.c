@@ -746,3 +746,431 @@ int rmo_channel(double z, double eps, double a, int32_t l, double out[4]) {
   for (int t = 0; t < 4; ++t) out[t] = (double)v[t];
   return 0;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Long-range multipole coupling and Numerov propagation between r0 = a and   */
+/* the asymptotic radius r1 (section "Overview": eq. (radial) with the        */
+/* coupling U_nm, and the propagation of the coupled radial functions by a    */
+/* Numerov method between the inner-region boundary and r1).                  */
+/*                                                                            */
+/* Reading of the garbled eq. (radial), in Rydberg units:                     */
+/*   F'' = Q(r) F,  Q = diag(l_i(l_i+1)/r^2 - 2z/r - eps_i) + 2 U(r),          */
+/*   U_ij(r) = sum_{lam=1..lamax} cf[lam-1][i][j] r^-(lam+1)                   */
+/* (cf: the multipole coefficients of the H.DAT symmetry record, symmetric).  */
+/*                                                                            */
+/* Solution columns, ordered as the unknowns of the matching: the decaying    */
+/* solution e_j of every closed channel j, the irregular c_j of every open    */
+/* channel, then the regular s_j of every open channel.  At r1 each column    */
+/* takes the value and derivative of its uncoupled analytic function in its   */
+/* own channel (U is neglected beyond r1); its value at r1 - h comes from the */
+/* Taylor series of the coupled equations about r1.                           */
+/* Numerov inward with Z = T Y, T = 1 - (h^2/12) Q:                           */
+/*   Z_{k-1} = (12 - 10 T_k) Y_k - Z_{k+1},  Y_k = T_k^-1 Z_k,                 */
+/* on r_k = a + k h (k = npts-1 .. -1, h = (r1 - a)/(npts - 1)).  Every        */
+/* `stab` steps the columns are recombined so that the closed rows of the     */
+/* newest Z are the identity on the closed columns and zero on the others:    */
+/* adding decaying solutions to any column leaves K unchanged, and it stops   */
+/* the inward-growing closed components from swamping the open columns.       */
+/* At r0: Y_0 and Y'_0 = [(2 Z_1 - Y_1) - (2 Z_-1 - Y_-1)] / (2h) (the O(h^4)  */
+/* derivative that goes with Numerov).                                        */
+/* ------------------------------------------------------------------------- */
+
+/* Q(r) of one energy into q (n x n), eps[i] = E - e_i */
+static void coupled_Q(const rmo_pw *pw, const rmo_coupling *cp, const ld *eps, ld r, ld *q) {
+  const int n = pw->nchan;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      ld u = 0;
+      ld rp = 1.0L / (r * r);
+      for (int lam = 1; lam <= cp->lamax; ++lam) {
+        u += (ld)cp->cf[((size_t)(lam - 1) * n + i) * n + j] * rp;
+        rp /= r;
+      }
+      q[(size_t)i * n + j] = 2.0L * u;
+    }
+  for (int i = 0; i < n; ++i) {
+    const ld L2 = (ld)pw->l[i] * (pw->l[i] + 1);
+    q[(size_t)i * n + i] += L2 / (r * r) - 2.0L * (ld)pw->z / r - eps[i];
+  }
+}
+
+/* Y = T^-1 Z for T = 1 - (h^2/12) Q (n x n), m columns */
+static int numerov_solve(const ld *q, ld h, int n, int m, const ld *Z, ld *Y, ld *T, int *piv) {
+  for (long t = 0; t < (long)n * n; ++t) T[t] = -(h * h / 12.0L) * q[t];
+  for (int i = 0; i < n; ++i) T[(size_t)i * n + i] += 1.0L;
+  if (lu_factor(T, n, piv)) return -1;
+  ld *col = (ld *)malloc(sizeof(ld) * n);
+  for (int j = 0; j < m; ++j) {
+    for (int i = 0; i < n; ++i) col[i] = Z[(size_t)i * m + j];
+    lu_solve(T, n, piv, col, 0);
+    for (int i = 0; i < n; ++i) Y[(size_t)i * m + j] = col[i];
+  }
+  free(col);
+  return 0;
+}
+
+/* Z = T Y */
+static void numerov_T(const ld *q, ld h, int n, int m, const ld *Y, ld *Z) {
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < m; ++j) {
+      ld acc = Y[(size_t)i * m + j];
+      for (int k = 0; k < n; ++k) acc -= (h * h / 12.0L) * q[(size_t)i * n + k] * Y[(size_t)k * m + j];
+      Z[(size_t)i * m + j] = acc;
+    }
+}
+
+/* column recombination of the state pair (Zn newest, Zo older); closed rows cr[0..nc) */
+static int stabilise(int n, int m, int nc, const int *cr, ld *Zn, ld *Zo) {
+  if (nc == 0) return 0;
+  ld *G = (ld *)malloc(sizeof(ld) * (size_t)nc * nc);
+  int *piv = (int *)malloc(sizeof(int) * nc);
+  ld *col = (ld *)malloc(sizeof(ld) * nc);
+  ld *tmp = (ld *)malloc(sizeof(ld) * (size_t)n * nc);
+  int bad = 0;
+  for (int a = 0; a < nc; ++a)
+    for (int b = 0; b < nc; ++b) G[(size_t)a * nc + b] = Zn[(size_t)cr[a] * m + b];
+  if (lu_factor(G, nc, piv)) bad = 1;
+  for (int s = 0; s < 2 && !bad; ++s) {
+    ld *Z = s == 0 ? Zn : Zo;
+    /* closed columns: Z_E <- Z_E G^-1, row by row (G^T x = row^T) */
+    for (int i = 0; i < n; ++i) {
+      for (int b = 0; b < nc; ++b) col[b] = Z[(size_t)i * m + b];
+      lu_solve(G, nc, piv, col, 1);
+      for (int b = 0; b < nc; ++b) tmp[(size_t)i * nc + b] = col[b];
+    }
+    for (int i = 0; i < n; ++i)
+      for (int b = 0; b < nc; ++b) Z[(size_t)i * m + b] = tmp[(size_t)i * nc + b];
+  }
+  if (!bad) {
+    /* the other columns: X <- X - Z_E alpha, alpha = closed rows of the newest X */
+    ld *alpha = (ld *)malloc(sizeof(ld) * (size_t)nc * m);
+    for (int a = 0; a < nc; ++a)
+      for (int j = nc; j < m; ++j) alpha[(size_t)a * m + j] = Zn[(size_t)cr[a] * m + j];
+    for (int s = 0; s < 2; ++s) {
+      ld *Z = s == 0 ? Zn : Zo;
+      for (int i = 0; i < n; ++i)
+        for (int j = nc; j < m; ++j) {
+          ld acc = Z[(size_t)i * m + j];
+          for (int a = 0; a < nc; ++a) acc -= Z[(size_t)i * m + a] * alpha[(size_t)a * m + j];
+          Z[(size_t)i * m + j] = acc;
+        }
+    }
+    free(alpha);
+  }
+  free(G);
+  free(piv);
+  free(col);
+  free(tmp);
+  return bad ? -1 : 0;
+}
+
+/* value and derivative at r1 of the uncoupled function of column type kind
+   (0 = e, closed; 1 = c; 2 = s) in channel i */
+static int start_values(const rmo_pw *pw, int i, ld eps, ld r1, int kind, ld *v, ld *dv) {
+  ld f[4];  /* channel_fn: open (s, s', c, c'), closed (0, 0, e, e') */
+  if (channel_fn(pw->z, eps, r1, pw->l[i], f)) return -1;
+  *v = f[kind == 2 ? 0 : 2];
+  *dv = f[kind == 2 ? 1 : 3];
+  return 0;
+}
+
+/* Y(r1 - h) of the coupled solutions with Y(r1) = Y1, Y'(r1) = dY1 (n x m),
+   from the Taylor series of Y'' = Q Y about r1: with Q(r1 + x) = sum_p q_p x^p
+   and Y = sum_j c_j x^j, (j+2)(j+1) c_{j+2} = sum_{p<=j} q_p c_{j-p}. */
+static void taylor_start(const rmo_pw *pw, const rmo_coupling *cp, const ld *eps, ld r1, ld h, int m,
+                         const ld *Y1, const ld *dY1, ld *Y0) {
+  const int n = pw->nchan;
+  enum { JT = 40 };
+  const size_t nm = (size_t)n * m, nn = (size_t)n * n;
+  ld *c = (ld *)calloc((JT + 2) * nm, sizeof(ld)), *q = (ld *)calloc((JT + 1) * nn, sizeof(ld));
+  /* q_p: (r1 + x)^-k = r1^-k sum_p (-1)^p C(k+p-1, p) (x/r1)^p */
+  for (int p = 0; p <= JT; ++p) {
+    ld sgn = (p % 2) ? -1.0L : 1.0L;
+    ld *qp = q + p * nn;
+    for (int i = 0; i < n; ++i) {
+      const ld L2 = (ld)pw->l[i] * (pw->l[i] + 1);
+      ld d = L2 * powl(r1, -2.0L - p) * (ld)(p + 1) * sgn - 2.0L * (ld)pw->z * powl(r1, -1.0L - p) * sgn;
+      if (p == 0) d -= eps[i];
+      qp[(size_t)i * n + i] += d;
+    }
+    for (int lam = 1; lam <= cp->lamax; ++lam) {
+      /* C(lam + p, p) */
+      ld binom = 1.0L;
+      for (int t = 1; t <= p; ++t) binom = binom * (ld)(lam + t) / (ld)t;
+      const ld w = 2.0L * binom * sgn * powl(r1, -(ld)(lam + 1) - p);
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) qp[(size_t)i * n + j] += w * (ld)cp->cf[((size_t)(lam - 1) * n + i) * n + j];
+    }
+  }
+  memcpy(c, Y1, sizeof(ld) * nm);
+  memcpy(c + nm, dY1, sizeof(ld) * nm);
+  for (int j = 0; j + 2 <= JT + 1; ++j) {
+    ld *out = c + (j + 2) * nm;
+    for (int p = 0; p <= j; ++p) {
+      const ld *qp = q + p * nn, *cj = c + (j - p) * nm;
+      for (int i = 0; i < n; ++i)
+        for (int k = 0; k < n; ++k) {
+          const ld v = qp[(size_t)i * n + k];
+          if (v == 0) continue;
+          for (int t = 0; t < m; ++t) out[(size_t)i * m + t] += v * cj[(size_t)k * m + t];
+        }
+    }
+    for (size_t t = 0; t < nm; ++t) out[t] /= (ld)(j + 2) * (j + 1);
+  }
+  for (size_t t = 0; t < nm; ++t) {
+    ld acc = 0, xp = 1.0L;
+    for (int j = 0; j <= JT + 1; ++j) {
+      acc += c[j * nm + t] * xp;
+      xp *= -h;
+    }
+    Y0[t] = acc;
+  }
+  free(c);
+  free(q);
+}
+
+/* one energy: phi, dphi [n][2n] (columns: closed e, open c, open s; rest 0) */
+static int32_t propagate_one(const rmo_pw *pw, const rmo_coupling *cp, double E, double thr_guard, double *phi,
+                             double *dphi, int8_t *open, int32_t *nopen) {
+  const int n = pw->nchan, N = cp->npts;
+  const ld a = pw->a, r1 = cp->r1, h = (r1 - a) / (ld)(N - 1);
+  int32_t st = 0;
+  ld *eps = (ld *)malloc(sizeof(ld) * n);
+  int *col_ch = (int *)malloc(sizeof(int) * 2 * n), *col_kind = (int *)malloc(sizeof(int) * 2 * n);
+  int *cr = (int *)malloc(sizeof(int) * n);
+  int nc = 0, no = 0;
+  for (int i = 0; i < n; ++i) {
+    eps[i] = (ld)E - (ld)pw->e_thr[i];
+    open[i] = eps[i] > 0;
+    if (fabsl(eps[i]) < (ld)thr_guard) st |= RMO_PT_THRESHOLD;
+    if (eps[i] > 0) no++;
+    else cr[nc++] = i;
+  }
+  *nopen = no;
+  /* columns: closed e (ascending), open c, open s */
+  int m = 0;
+  for (int i = 0; i < n; ++i)
+    if (!(eps[i] > 0)) col_ch[m] = i, col_kind[m++] = 0;
+  for (int i = 0; i < n; ++i)
+    if (eps[i] > 0) col_ch[m] = i, col_kind[m++] = 1;
+  for (int i = 0; i < n; ++i)
+    if (eps[i] > 0) col_ch[m] = i, col_kind[m++] = 2;
+  for (long t = 0; t < 2L * n * n; ++t) phi[t] = dphi[t] = 0.0;
+  if (st) goto done;
+  {
+    const size_t nm = (size_t)n * m;
+    ld *Zp = (ld *)calloc(nm, sizeof(ld)), *Zc = (ld *)calloc(nm, sizeof(ld)), *Zn = (ld *)malloc(sizeof(ld) * nm);
+    ld *Y = (ld *)malloc(sizeof(ld) * nm), *q = (ld *)malloc(sizeof(ld) * (size_t)n * n);
+    ld *T = (ld *)malloc(sizeof(ld) * (size_t)n * n);
+    ld *Z1 = (ld *)malloc(sizeof(ld) * nm), *Y1 = (ld *)malloc(sizeof(ld) * nm), *Y0 = (ld *)malloc(sizeof(ld) * nm);
+    int *piv = (int *)malloc(sizeof(int) * n);
+    /* Y at r_{N-1} = r1: each column its uncoupled function (value and
+       derivative); at r_{N-2} the coupled solutions through those data */
+    ld *Ya = (ld *)calloc(nm, sizeof(ld)), *dYa = (ld *)calloc(nm, sizeof(ld)), *Yb = (ld *)calloc(nm, sizeof(ld));
+    for (int j = 0; j < m && !st; ++j) {
+      ld v, dv;
+      if (start_values(pw, col_ch[j], eps[col_ch[j]], r1, col_kind[j], &v, &dv)) st |= RMO_PT_NOCONV;
+      Ya[(size_t)col_ch[j] * m + j] = v;
+      dYa[(size_t)col_ch[j] * m + j] = dv;
+    }
+    if (!st) taylor_start(pw, cp, eps, r1, h, m, Ya, dYa, Yb);
+    if (!st) {
+      coupled_Q(pw, cp, eps, a + (ld)(N - 1) * h, q);
+      numerov_T(q, h, n, m, Ya, Zp);
+      coupled_Q(pw, cp, eps, a + (ld)(N - 2) * h, q);
+      numerov_T(q, h, n, m, Yb, Zc);
+      /* step s computes Z_{k-1}, k = N-1-s, from Z_{k+1} (Zp) and Z_k (Zc);
+         the last step (k = 0) gives Z_{-1} */
+      for (int s = 1; s <= N - 1 && !st; ++s) {
+        const int k = N - 1 - s;
+        coupled_Q(pw, cp, eps, a + (ld)k * h, q);
+        if (numerov_solve(q, h, n, m, Zc, Y, T, piv)) {
+          st |= RMO_PT_SINGULAR;
+          break;
+        }
+        if (k == 1) memcpy(Y1, Y, sizeof(ld) * nm);
+        if (k == 0) memcpy(Y0, Y, sizeof(ld) * nm);
+        for (int i = 0; i < n; ++i)
+          for (int j = 0; j < m; ++j) {
+            ld qy = 0;
+            for (int t = 0; t < n; ++t) qy += q[(size_t)i * n + t] * Y[(size_t)t * m + j];
+            Zn[(size_t)i * m + j] = 2.0L * Y[(size_t)i * m + j] + (10.0L * h * h / 12.0L) * qy - Zp[(size_t)i * m + j];
+          }
+        ld *tmp = Zp;
+        Zp = Zc;
+        Zc = Zn;
+        Zn = tmp;
+        /* now Zp = Z_k, Zc = Z_{k-1} */
+        if (s % cp->stab == 0 && s <= N - 2 && stabilise(n, m, nc, cr, Zc, Zp)) st |= RMO_PT_SINGULAR;
+        if (k - 1 == 1) memcpy(Z1, Zc, sizeof(ld) * nm);
+      }
+      if (!st) {
+        /* Zc = Z_{-1}; Y_{-1} = T_{-1}^-1 Z_{-1} */
+        coupled_Q(pw, cp, eps, a - h, q);
+        if (numerov_solve(q, h, n, m, Zc, Y, T, piv)) st |= RMO_PT_SINGULAR;
+        for (int i = 0; i < n && !st; ++i)
+          for (int j = 0; j < m; ++j) {
+            const size_t t = (size_t)i * m + j;
+            phi[(size_t)i * 2 * n + j] = (double)Y0[t];
+            dphi[(size_t)i * 2 * n + j] =
+                (double)(((2.0L * Z1[t] - Y1[t]) - (2.0L * Zc[t] - Y[t])) / (2.0L * h));
+          }
+      }
+    }
+    free(Zp);
+    free(Zc);
+    free(Zn);
+    free(Y);
+    free(q);
+    free(T);
+    free(Z1);
+    free(Y1);
+    free(Y0);
+    free(piv);
+    free(Ya);
+    free(dYa);
+    free(Yb);
+  }
+done:
+  if (st) {
+    fill_nan(phi, 2L * n * n);
+    fill_nan(dphi, 2L * n * n);
+  }
+  free(eps);
+  free(col_ch);
+  free(col_kind);
+  free(cr);
+  return st;
+}
+
+/* Matching, eq. (match), with the propagated solution matrices at r0 = a:    */
+/*   F = S + Phi [K; X],  Phi = [closed e | open c] columns,                  */
+/*   (Phi - R (a Phi' - b Phi)) [X; K] = R (a S' - b S) - S                   */
+/* (with U = 0 the matrices are diagonal and this is the plain matching).     */
+static int32_t solve_K_coupled_one(const rmo_pw *pw, double E, const double *R, const double *phi,
+                                   const double *dphi, double *K, double *cond) {
+  const int n = pw->nchan;
+  const ld a = pw->a, b = pw->b;
+  int *open_idx = (int *)malloc(sizeof(int) * (n + 1));
+  const int no = open_list(pw, E, open_idx), nc = n - no;
+  for (long t = 0; t < (long)n * n; ++t) K[t] = 0.0;
+  if (cond) *cond = 0;
+  if (no == 0) {
+    free(open_idx);
+    return 0;
+  }
+  ld *A = (ld *)malloc(sizeof(ld) * (size_t)n * n), *LU = (ld *)malloc(sizeof(ld) * (size_t)n * n);
+  ld *B = (ld *)malloc(sizeof(ld) * (size_t)n * no);
+  int *piv = (int *)malloc(sizeof(int) * n);
+  const int ld2 = 2 * n;
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < n; ++j) {
+      ld acc = 0;
+      for (int t = 0; t < n; ++t)
+        acc += (ld)R[(size_t)i * n + t] * (a * (ld)dphi[(size_t)t * ld2 + j] - b * (ld)phi[(size_t)t * ld2 + j]);
+      A[(size_t)i * n + j] = (ld)phi[(size_t)i * ld2 + j] - acc;
+    }
+    for (int j = 0; j < no; ++j) {
+      ld acc = 0;
+      for (int t = 0; t < n; ++t)
+        acc += (ld)R[(size_t)i * n + t] *
+               (a * (ld)dphi[(size_t)t * ld2 + n + j] - b * (ld)phi[(size_t)t * ld2 + n + j]);
+      B[(size_t)i * no + j] = acc - (ld)phi[(size_t)i * ld2 + n + j];
+    }
+  }
+  memcpy(LU, A, sizeof(ld) * (size_t)n * n);
+  int32_t st = 0;
+  if (lu_factor(LU, n, piv)) {
+    st = RMO_PT_SINGULAR;
+  } else {
+    ld *col = (ld *)malloc(sizeof(ld) * n);
+    for (int j = 0; j < no; ++j) {
+      for (int i = 0; i < n; ++i) col[i] = B[(size_t)i * no + j];
+      lu_solve(LU, n, piv, col, 0);
+      for (int i = 0; i < no; ++i) K[(size_t)i * n + j] = (double)col[nc + i];  /* rows of the c columns */
+    }
+    free(col);
+    if (cond) *cond = (double)cond1_estimate(A, LU, n, piv);
+  }
+  free(A);
+  free(LU);
+  free(B);
+  free(piv);
+  free(open_idx);
+  return st;
+}
+
+static int coupling_ok(const rmo_pw *pw, const rmo_coupling *cp) {
+  return cp && cp->lamax >= 0 && (cp->lamax == 0 || cp->cf) && cp->npts >= 4 && cp->stab >= 1 && cp->r1 > pw->a;
+}
+
+int rmo_propagate(const rmo_pw *pw, const rmo_coupling *cp, const double *E, int32_t ne, double thr_guard,
+                  double *phi, double *dphi, int8_t *open, int32_t *nopen, int32_t *status, int32_t nthreads) {
+  if (!coupling_ok(pw, cp)) return -1;
+  const int n = pw->nchan;
+  const long per = 2L * n * n;
+  set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1) if (ne > 1)
+  for (int e = 0; e < ne; ++e)
+    status[e] = propagate_one(pw, cp, E[e], thr_guard, phi + e * per, dphi + e * per, open + (long)e * n, nopen + e);
+  return 0;
+}
+
+int rmo_solve_K_coupled(const rmo_pw *pw, const double *E, int32_t ne, const double *R, const double *phi,
+                        const double *dphi, double *K, double *cond, int32_t *status, int32_t nthreads) {
+  const int n = pw->nchan;
+  const long nn = (long)n * n, per = 2L * n * n;
+  set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1) if (ne > 1)
+  for (int e = 0; e < ne; ++e) {
+    int32_t st = 0;
+    if (!all_finite(R + e * nn, nn) || !all_finite(phi + e * per, per) || !all_finite(dphi + e * per, per))
+      st |= RMO_PT_NONFINITE;
+    if (!st) st = solve_K_coupled_one(pw, E[e], R + e * nn, phi + e * per, dphi + e * per, K + e * nn,
+                                      cond ? cond + e : NULL);
+    if (st) {
+      fill_nan(K + e * nn, nn);
+      if (cond) cond[e] = nan_value();
+    }
+    status[e] = st;
+  }
+  return 0;
+}
+
+int rmo_run_coupled(const rmo_pw *pw, const rmo_coupling *cp, const double *E, int32_t ne, double thr_guard,
+                    double *omega, double *K, double *cond, int32_t *status, int32_t nthreads) {
+  if (!coupling_ok(pw, cp)) return -1;
+  const int n = pw->nchan, nt = pw->ntarget;
+  const long nn = (long)n * n;
+  set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1) if (ne > 1)
+  for (int e = 0; e < ne; ++e) {
+    double *R = (double *)malloc(sizeof(double) * nn);
+    double *phi = (double *)malloc(sizeof(double) * 2 * nn), *dphi = (double *)malloc(sizeof(double) * 2 * nn);
+    double *Kl = K ? K + e * nn : (double *)malloc(sizeof(double) * nn);
+    int8_t *op = (int8_t *)malloc(n);
+    int *idx = (int *)malloc(sizeof(int) * (n + 1));
+    int32_t no = 0;
+    int32_t st = form_R_one(pw, E[e], R);
+    st |= propagate_one(pw, cp, E[e], thr_guard, phi, dphi, op, &no);
+    if (!st && (!all_finite(R, nn) || !all_finite(phi, 2 * nn) || !all_finite(dphi, 2 * nn))) st |= RMO_PT_NONFINITE;
+    if (!st) st = solve_K_coupled_one(pw, E[e], R, phi, dphi, Kl, cond ? cond + e : NULL);
+    if (!st) {
+      const int no2 = open_list(pw, E[e], idx);
+      st = s_and_omega_one(pw, Kl, no2, idx, omega + (long)e * nt * nt, NULL);
+    }
+    if (st) {
+      fill_nan(Kl, nn);
+      fill_nan(omega + (long)e * nt * nt, (long)nt * nt);
+      if (cond) cond[e] = nan_value();
+    }
+    status[e] = st;
+    if (!K) free(Kl);
+    free(R);
+    free(phi);
+    free(dphi);
+    free(op);
+    free(idx);
+  }
+  return 0;
+}

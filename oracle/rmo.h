@@ -75,6 +75,31 @@ int rmo_collision_strengths(const rmo_pw *pw, const double *E, int32_t ne, const
 int rmo_run(const rmo_pw *pw, const double *E, int32_t ne, double thr_guard, double *omega,
             double *K, double *S, double *cond, int32_t *status, int32_t nthreads);
 
+/* Long-range multipole coupling of one partial wave and the Numerov grid of
+   the propagation between r0 = a and r1 (section "Overview": eq. (radial) with
+   U_nm; the propagation of the coupled radial functions between the boundary
+   and the asymptotic radius; mzpts grid points). */
+typedef struct {
+  int32_t lamax;    /* multipole orders 1..lamax (0: no coupling) */
+  const double *cf; /* [lamax][nchan][nchan], U_ij(r) = sum_lam cf[lam-1][i][j] r^-(lam+1) */
+  double r1;        /* asymptotic radius, > a */
+  int32_t npts;     /* grid points from a to r1 inclusive */
+  int32_t stab;     /* Numerov steps between recombinations of the closed columns */
+} rmo_coupling;
+
+/* Solution matrices at r0 = a after propagation from r1: phi, dphi
+   [ne][n][2n], columns: decaying solutions of the closed channels (ascending),
+   irregular solutions of the open channels, regular solutions of the open
+   channels; the rest zero.  Returns -1 for an invalid coupling. */
+int rmo_propagate(const rmo_pw *pw, const rmo_coupling *cp, const double *E, int32_t ne, double thr_guard,
+                  double *phi, double *dphi, int8_t *open, int32_t *nopen, int32_t *status, int32_t nthreads);
+/* K from R and the propagated matrices (eq. (match)). */
+int rmo_solve_K_coupled(const rmo_pw *pw, const double *E, int32_t ne, const double *R, const double *phi,
+                        const double *dphi, double *K, double *cond, int32_t *status, int32_t nthreads);
+/* R -> propagation -> K -> Omega for each energy. */
+int rmo_run_coupled(const rmo_pw *pw, const rmo_coupling *cp, const double *E, int32_t ne, double thr_guard,
+                    double *omega, double *K, double *cond, int32_t *status, int32_t nthreads);
+
 /* Special functions, exposed for pinning against independent references. */
 /* F, dF/drho, G, dG/drho of the Coulomb functions F_l(eta, rho), G_l(eta, rho). */
 int rmo_coulomb(double eta, double rho, int32_t l, double out[4]);

@@ -48,6 +48,25 @@ MUTANTS = {
                                "test_oracle_K_S.py::test_cond1_estimate_bounds_true_condition_number"),
     "omega_half_g": ("const ld half_g = 0.5L * (ld)pw->g;", "const ld half_g = (ld)pw->g;",
                      "test_oracle_K_S.py::test_single_channel_ion_closed_form"),
+    # long-range coupling and Numerov propagation
+    "coupling_factor": ("q[(size_t)i * n + j] = 2.0L * u;", "q[(size_t)i * n + j] = u;",
+                        "test_oracle_coupling.py::test_coupled_propagation_against_mpmath"),
+    "coupling_power": ("ld rp = 1.0L / (r * r);", "ld rp = 1.0L / r;",
+                       "test_oracle_coupling.py::test_coupled_propagation_against_mpmath"),
+    "numerov_weight": ("(10.0L * h * h / 12.0L) * qy", "(11.0L * h * h / 12.0L) * qy",
+                       "test_oracle_coupling.py::test_uncoupled_propagation_converges_to_analytic"),
+    "numerov_derivative": ("(((2.0L * Z1[t] - Y1[t]) - (2.0L * Zc[t] - Y[t])) / (2.0L * h))",
+                           "((Z1[t] - Zc[t]) / (2.0L * h))",
+                           "test_oracle_coupling.py::test_uncoupled_propagation_converges_to_analytic"),
+    "taylor_start_binomial": ("for (int t = 1; t <= p; ++t) binom = binom * (ld)(lam + t) / (ld)t;",
+                              "for (int t = 1; t <= p; ++t) binom = binom * (ld)(lam + t - 1) / (ld)t;",
+                              "test_oracle_coupling.py::test_coupled_propagation_against_mpmath"),
+    "stabilise_alpha": ("acc -= Z[(size_t)i * m + a] * alpha[(size_t)a * m + j];",
+                        "acc += Z[(size_t)i * m + a] * alpha[(size_t)a * m + j];",
+                        "test_oracle_coupling.py::test_coupled_K_symmetric_and_recombination_invariant"),
+    "coupled_match_rhs": ("B[(size_t)i * no + j] = acc - (ld)phi[(size_t)i * ld2 + n + j];",
+                          "B[(size_t)i * no + j] = acc + (ld)phi[(size_t)i * ld2 + n + j];",
+                          "test_oracle_coupling.py::test_uncoupled_K_converges_to_plain_matching"),
 }
 
 

@@ -1000,8 +1000,9 @@ static int32_t propagate_one(const rmo_pw *pw, const rmo_coupling *cp, double E,
         Zp = Zc;
         Zc = Zn;
         Zn = tmp;
-        /* now Zp = Z_k, Zc = Z_{k-1} */
-        if (s % cp->stab == 0 && s <= N - 2 && stabilise(n, m, nc, cr, Zc, Zp)) st |= RMO_PT_SINGULAR;
+        /* now Zp = Z_k, Zc = Z_{k-1}; recombinations stop once Z_1 is formed
+           (the last three points feed the derivative at r0) */
+        if (s % cp->stab == 0 && s <= N - 3 && stabilise(n, m, nc, cr, Zc, Zp)) st |= RMO_PT_SINGULAR;
         if (k - 1 == 1) memcpy(Z1, Zc, sizeof(ld) * nm);
       }
       if (!st) {

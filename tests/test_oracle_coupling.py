@@ -147,6 +147,25 @@ def test_coupled_K_symmetric_and_recombination_invariant():
     assert np.abs(res[64]["K"][0] - K0[0]).max() > 1e-3
 
 
+def test_recombination_at_last_allowed_step():
+    """npts - 3 and npts - 2 both multiples of the recombination period: the
+    last recombination (at step npts - 3, before Z_1 is recorded) must leave K
+    as it is without any recombination (the derivative at r0 takes Z_1 and
+    Z_-1 from one basis)."""
+    pw = _wave()
+    E = np.array([0.7, 3.3])
+    o = oracle.Oracle(pw)
+    cf = _cf(pw.nchan, 4)
+    no = oracle.open_count(pw, E)
+    ref = o.run_coupled(E, dict(cf=cf, r1=14.0, npts=131, stab=10 ** 9))["K"]
+    for npts, stab in ((131, 64), (131, 128), (130, 64), (130, 128)):
+        K = o.run_coupled(E, dict(cf=cf, r1=14.0, npts=npts, stab=stab))["K"]
+        Kr = ref if npts == 131 else o.run_coupled(E, dict(cf=cf, r1=14.0, npts=npts, stab=10 ** 9))["K"]
+        for e in range(E.size):
+            d = np.abs(K[e, :no[e], :no[e]] - Kr[e, :no[e], :no[e]]).max() / max(1, np.abs(Kr[e]).max())
+            assert d <= 1e-12, (npts, stab, e, d)
+
+
 def test_block_diagonal_coupling():
     """Two groups of channels connected neither by the coupling nor by the
     amplitudes (disjoint pole sets): K is block diagonal and each block equals

@@ -138,6 +138,44 @@ size_t rm_pw_footprint(int32_t nchan, int32_t npole);
    0 for invalid sizes.  With rm_pw_footprint this sizes hbm_budget_bytes. */
 size_t rm_work_footprint(int32_t nchan, int32_t npole, int32_t ntarget, int32_t ne);
 
+/* ------------------------------------------- long-range multipole coupling */
+/* Largest channel count and multipole order of a coupled partial wave. */
+#define RM_PROP_MAX_CHANNELS 128
+#define RM_PROP_MAX_LAMAX 8
+
+/* rm_pw_upload for a partial wave whose outer-region channels are coupled by
+   the long-range multipole potentials (PSTGF paper, section "Overview", eq.
+   (radial) with the potentials U kept, and the H.DAT CF record of the "Input
+   files" table).  In Rydberg units the radial functions obey
+     F'' = [diag(l(l+1)/r^2 - 2z/r - eps) + 2 U(r)] F,
+     U_ij(r) = sum_{lam=1..lamax} cf[lam-1][i][j] r^-(lam+1),
+   between a and the asymptotic radius r1 > a, where the uncoupled functions
+   are taken as exact.  For such a wave the fused calls integrate the solution
+   matrix inward from r1 to a by the Numerov method (rm_set_propagation gives
+   the grid) and match it to R there; rm_asymptotic reports the functions at r1.
+   cf: host [lamax][nchan][nchan] doubles (copied).  RM_E_ARG for nchan >
+   RM_PROP_MAX_CHANNELS, lamax outside [1, RM_PROP_MAX_LAMAX], r1 <= a or a
+   non-finite coefficient; otherwise as rm_pw_upload. */
+rm_status rm_pw_upload_coupled(rm_ctx *ctx, const rm_pw_desc *desc, int32_t lamax, const double *cf, double r1,
+                               int32_t *pw_id);
+/* The Numerov grid of every coupled wave: npts >= 4 equally spaced points from
+   a to r1 (default 3201, the paper's mzpts) and a recombination of the
+   solution columns every `stab` >= 1 steps (default 64), which keeps the
+   closed-channel solutions independent as they grow inward.  Applies to runs
+   started after the call. */
+rm_status rm_set_propagation(rm_ctx *ctx, int32_t npts, int32_t stab);
+/* The propagated solution matrices of a coupled wave at r = a: phi and dphi
+   [ne][n][2n] doubles, row i = channel, columns the decaying solution of every
+   closed channel (channel order), then the irregular and then the regular
+   solution of every open channel (channel order); columns past n + nopen are
+   zero.  Each column starts at r1 as its channel's uncoupled function (value
+   and derivative); the closed columns are recombined as they grow, so only
+   their span is defined.  status: [ne] (RM_PT_THRESHOLD, RM_PT_NOCONV,
+   RM_PT_SINGULAR), NaN rows for a failed energy.  RM_E_ARG for a wave without
+   coupling. */
+rm_status rm_propagate(rm_ctx *ctx, int32_t pw, const double *E, int32_t ne, const rm_opts *opts,
+                       double *phi, double *dphi, int32_t *status);
+
 /* ---------------------------------------------------------- staged calls */
 /* Stage 1, eq. (rmatrix).  R: [ne][n][n] doubles (full symmetric matrices);
    status: [ne] int32 (RM_PT_POLE only). */
@@ -154,7 +192,9 @@ rm_status rm_asymptotic(rm_ctx *ctx, int32_t pw, const double *E, int32_t ne, co
 /* Stage 3, eq. (match): from R [ne][n][n] and fg [ne][n][4] (as produced by the
    two calls above, or by any other source), the K-matrix K: [ne][n][n] with the
    leading nopen x nopen block filled (row stride n) and the rest zero.  K is
-   returned as solved: it is symmetric up to the rounding of the solve. */
+   returned as solved: it is symmetric up to the rounding of the solve.
+   RM_E_ARG for a coupled wave (its matching needs the propagated solutions:
+   use rm_run). */
 rm_status rm_solve_K(rm_ctx *ctx, int32_t pw, const double *E, int32_t ne, const double *R,
                      const double *fg, const rm_opts *opts, double *K, int32_t *status);
 

@@ -290,7 +290,9 @@ __global__ void k_asym(const DevPW *__restrict__ tab, const int *__restrict__ pw
   if (fabs(eps) < thr_guard) {
     bad = RM_PT_THRESHOLD;
   } else {
-    const bool ok = eps > 0 ? open_fn(p.z, eps, p.a, p.l[i], out) : closed_fn(p.z, eps, p.a, p.l[i], out);
+    // at the boundary a, or at r1 for a wave whose coupled functions are propagated from there
+    const double r = p.lamax ? p.r1 : p.a;
+    const bool ok = eps > 0 ? open_fn(p.z, eps, r, p.l[i], out) : closed_fn(p.z, eps, r, p.l[i], out);
     if (!ok) bad = RM_PT_NOCONV;
   }
   double *o = fg + ((size_t)e * ldo + i) * 4;

@@ -67,8 +67,19 @@ struct DevPW {
   int *target = nullptr;  // [n]
   int *tptr = nullptr;    // [nt + 1] channels of target p are tch[tptr[p] .. tptr[p+1])
   int *tch = nullptr;     // [n]
+  // long-range multipole coupling (Numerov propagation between a and r1);
+  // lamax = 0 for a wave without one
+  int lamax = 0;
+  double r1 = 0;
+  double *cf = nullptr;   // [lamax][npad][npad] multipole coefficients, zero padded
   size_t bytes = 0;
 };
+// Largest channel count of a partial wave with a coupling (the propagation
+// keeps a 64-column panel of every solution matrix on chip).
+constexpr int PROP_MAXN = 128;
+// Matrices of the propagation workspace per energy: two Numerov states, the
+// record 2 Z_1 - Y_1, phi and dphi.
+constexpr int PROP_NMAT = 5;
 
 // Strides of one chunk of energies.  Every per-energy block is laid out for the
 // largest partial wave in the chunk.
@@ -80,6 +91,8 @@ struct Lay {
   long ldk = 0, sK = 0;         // K, gre and gim: ldk = npadmax, sK = nmax * ldk
   long ldo = 0;                 // per-channel arrays (fg has 4 per channel): nmax
   long sOm = 0;                 // Omega: ntmax * ntmax per energy
+  int npadc = 0;                // largest npad of the chunk's coupled waves (0: none)
+  long zrb = 0, sZ = 0;         // propagation matrices (tiled): zrb = npadc / 64 row blocks, sZ = 2 npadc^2
 };
 
 // One task of the R contraction: energies [e0, e0 + m) (m <= the tile shape's eb,
@@ -99,7 +112,7 @@ struct RQueues {
 
 // Per-chunk device workspace.
 struct Work {
-  int cap_e = 0, cap_n = 0, cap_npad = 0, cap_M = 0, cap_nt = 0, cap_tab = 0, cap_tasks = 0;
+  int cap_e = 0, cap_n = 0, cap_npad = 0, cap_M = 0, cap_nt = 0, cap_tab = 0, cap_tasks = 0, cap_npc = 0;
   size_t bytes = 0;
   double *E = nullptr;       // [cap_e]
   int *pwi = nullptr;        // [cap_e] table slot of each energy
@@ -128,6 +141,7 @@ struct Work {
   double *pack = nullptr;    // packed outputs, [cap_e][nmax][nmax] doubles
   long *pack_off = nullptr;  // [cap_e + 1] offsets of each energy's packed block
   double *S = nullptr;       // [cap_e][nmax][nmax][2], allocated on demand
+  double *pz = nullptr;      // [cap_e][PROP_NMAT][sZ] propagation matrices (chunks with coupled waves)
 };
 
 // ---- kernel launchers (all asynchronous on `s`).  tab/pwi are device pointers.
@@ -174,6 +188,17 @@ void launch_zs_setup(hipStream_t s, const Lay &L, const int *nopen, const double
 // pivot sets RM_PT_SINGULAR.  zinv is scratch of ne * NBU * NBU doubles.
 void launch_zs_inverse(hipStream_t s, const Lay &L, const int *dims, double *aug, double *gre, double *gim,
                        double *zinv, int *status);
+// Numerov propagation of the coupled energies of the chunk from r1 to a (npts
+// points, recombination every `stab` steps); fg holds their functions at r1.
+void launch_prop(hipStream_t s, const Lay &L, int npts, int stab, const DevPW *tab, const int *pwi, const double *E,
+                 const double *fg, const int *nopen, const int *openidx, const int *colpos, double *pz, int *status);
+// [A | B] of the coupled energies' matching from R (in aug) and phi / dphi,
+// written over their R (gre and gim serve as staging).
+void launch_prop_assemble(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *nopen,
+                          const double *pz, double *aug, double *gre, double *gim);
+// Row-major copy of phi (q = 3) or dphi (q = 4) of the coupled energies.
+void launch_prop_gather(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *nopen,
+                        const int *status, const double *pz, int q, double *out, long ldo, long so);
 // K = the last nopen rows of the solution (the open channels, ascending), as
 // solved, zero past nopen; dims = {nopen, nopen}.
 void launch_gatherK(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *nopen,

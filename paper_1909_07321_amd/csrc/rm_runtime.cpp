@@ -64,7 +64,7 @@ struct Staging {
 // launch sequence of the group for the last chunk shape (key), replayed while
 // the shape repeats.  Replaced executables wait in `retired` until an event
 // recorded after their last launch has completed.
-constexpr int NGROUP = 8;
+constexpr int NGROUP = 9;
 struct GraphCache {
   std::string key[NGROUP];
   hipGraphExec_t exec[NGROUP] = {};
@@ -86,9 +86,10 @@ struct ProfRec {
   long energies = 0;
   double cost = 0, open = 0;  // chunk records: model flops and summed open fraction n_o / n
 };
-const char *const kStages[] = {"rform", "nearpole", "asym", "ksolve", "somega", "chunk"};
-constexpr int NSTAGE = 6;
+const char *const kStages[] = {"rform", "nearpole", "asym", "ksolve", "somega", "chunk", "prop"};
+constexpr int NSTAGE = 7;
 constexpr int STAGE_CHUNK = 5;
+constexpr int STAGE_PROP = 6;
 
 struct Req {
   uint64_t ticket = 0;
@@ -163,6 +164,9 @@ struct rm_ctx {
   Slot na;
   std::mutex na_mu;
   char *scratch = nullptr;
+  // Numerov grid of the coupled waves: points between a and r1, and steps
+  // between recombinations
+  std::atomic<int> prop_npts{3201}, prop_stab{64};
   hipEvent_t ev_in = nullptr, ev_out[2] = {nullptr, nullptr}, ev_R[2] = {nullptr, nullptr};
 };
 
@@ -183,8 +187,10 @@ constexpr int MAX_CHUNK = 1024;
 constexpr size_t kChunkFixedBytes = 16u << 20;
 constexpr double TUNE_MARGIN = 0.03;
 
-size_t per_energy_bytes(int n, int npad, int Mpad, int nt) {
-  return (size_t)n * 2 * npad * 8    // aug
+// npc: padded channels of the largest coupled wave (0 if none)
+size_t per_energy_bytes(int n, int npad, int Mpad, int nt, int npc = 0) {
+  return (size_t)PROP_NMAT * 2 * npc * npc * 8  // propagation matrices
+         + (size_t)n * 2 * npad * 8  // aug
          + (size_t)n * npad * 8 * 3  // Kw, gre, gim
          + (size_t)n * n * 8         // packed outputs
          + (size_t)Mpad * 12         // D64 + D32
@@ -201,8 +207,11 @@ struct WorkBuf {
 
 // Every buffer of a workspace with capacities (energies, channels, padded
 // channels, padded poles, targets, table slots, R tasks), in one fixed order;
-// the pointers are those of w.  With S the S-matrix output buffer is included.
-std::vector<WorkBuf> work_buffers(Work &w, int ce, int cn, int cnp, int cm, int ct, int ctab, int ctask, bool S) {
+// the pointers are those of w.  With S the S-matrix output buffer is included,
+// with cpc > 0 the propagation matrices of coupled waves of up to cpc padded
+// channels.
+std::vector<WorkBuf> work_buffers(Work &w, int ce, int cn, int cnp, int cm, int ct, int ctab, int ctask, bool S,
+                                  int cpc = 0) {
   auto b = [](size_t x) { return std::max<size_t>(x, 8); };
   const size_t E = (size_t)ce;
   const size_t bidx = b(E * cn * 4), bK = b(E * cn * cnp * 8), boff = b((E + 1) * 8);
@@ -224,6 +233,8 @@ std::vector<WorkBuf> work_buffers(Work &w, int ce, int cn, int cnp, int cm, int 
       {(void **)&w.pack, b(E * std::max((size_t)cn * cn, (size_t)ct * ct) * 8)},
       {(void **)&w.pack_off, 2 * boff}};
   if (S) v.push_back({(void **)&w.S, b(E * cn * cn * 16)});
+  if (cpc) v.push_back({(void **)&w.pz, b(E * PROP_NMAT * 2 * cpc * cpc * 8)});
+  w.cap_npc = cpc;
   w.cap_e = ce;
   w.cap_n = cn;
   w.cap_npad = cnp;
@@ -244,7 +255,7 @@ size_t work_bytes(const std::vector<WorkBuf> &v) {
 void free_work(Work &w) {
   void *ptrs[] = {w.E, w.pwi, w.tab, w.tasks, w.counter, w.D64, w.D32, w.win, w.status, w.nopen, w.openidx,
                   w.openpos, w.colpos, w.openflag, w.fg, w.aug, w.Kw, w.gre, w.gim, w.dims, w.ipiv, w.bperm, w.linv, w.omega, w.pack, w.pack_off,
-                  w.S};
+                  w.S, w.pz};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   w = Work();
@@ -265,15 +276,16 @@ rm_status ensure_slot(rm_ctx *ctx, Slot &sl, const Lay &L, int ntab, int ntasks,
   Staging &h = sl.h;
   if (!h.ready) HIPCHK(hipEventCreateWithFlags(&h.ready, hipEventDisableTiming));
   const bool fits = w.cap_e >= L.ne && w.cap_n >= L.nmax && w.cap_npad >= L.npadmax && w.cap_M >= L.Mpadmax &&
-                    w.cap_nt >= L.ntmax && w.cap_tab >= ntab && w.cap_tasks >= ntasks && (!want_S || w.S);
+                    w.cap_nt >= L.ntmax && w.cap_tab >= ntab && w.cap_tasks >= ntasks && (!want_S || w.S) &&
+                    w.cap_npc >= L.npadc;
   if (!fits) {
     const int ce = std::max(L.ne, w.cap_e), cn = std::max(L.nmax, w.cap_n),
               cnp = std::max(L.npadmax, w.cap_npad), cm = std::max(L.Mpadmax, w.cap_M),
               ct = std::max(L.ntmax, w.cap_nt), ctab = std::max(ntab, w.cap_tab),
-              ctask = std::max(ntasks, w.cap_tasks);
+              ctask = std::max(ntasks, w.cap_tasks), cpc = std::max(L.npadc, w.cap_npc);
     const bool S = want_S || w.S != nullptr;
     Work nw;
-    const std::vector<WorkBuf> bufs = work_buffers(nw, ce, cn, cnp, cm, ct, ctab, ctask, S);
+    const std::vector<WorkBuf> bufs = work_buffers(nw, ce, cn, cnp, cm, ct, ctab, ctask, S, cpc);
     const size_t need = work_bytes(bufs);
     {
       std::lock_guard<std::mutex> g(ctx->mu);
@@ -298,6 +310,7 @@ rm_status ensure_slot(rm_ctx *ctx, Slot &sl, const Lay &L, int ntab, int ntasks,
     w.cap_nt = ct;
     w.cap_tab = ctab;
     w.cap_tasks = ctask;
+    w.cap_npc = cpc;
     w.bytes = need;
     std::lock_guard<std::mutex> g(ctx->mu);
     ctx->work_bytes += need;
@@ -330,7 +343,10 @@ Lay make_layout(const std::vector<const DevPW *> &slots, int ne) {
     L.npadmax = std::max(L.npadmax, p->npad);
     L.Mpadmax = std::max(L.Mpadmax, p->Mpad);
     L.ntmax = std::max(L.ntmax, p->nt);
+    if (p->lamax) L.npadc = std::max(L.npadc, p->npad);
   }
+  L.zrb = L.npadc / TILE;
+  L.sZ = 2L * L.npadc * L.npadc;
   L.ldD = L.Mpadmax;
   L.ldaug = 2L * L.npadmax;
   L.roff = L.npadmax;
@@ -344,8 +360,8 @@ Lay make_layout(const std::vector<const DevPW *> &slots, int ne) {
 
 // Energies per chunk for a chunk whose largest members are (n, npad, Mpad, nt),
 // given `share` bytes of budget.
-int chunk_cap(int n, int npad, int Mpad, int nt, size_t share, int limit) {
-  const size_t per = per_energy_bytes(n, npad, Mpad, nt);
+int chunk_cap(int n, int npad, int Mpad, int nt, size_t share, int limit, int npc = 0) {
+  const size_t per = per_energy_bytes(n, npad, Mpad, nt, npc);
   long cap = (long)(share / std::max<size_t>(per, 1));
   cap = std::min<long>(cap, limit);
   if (cap >= EB) cap = cap / EB * EB;
@@ -501,6 +517,7 @@ void stage_K(const Plan &P, Work &w, hipStream_t s) {
   const Lay &L = P.L;
   launch_setdims(s, L, w.tab, w.pwi, w.nopen, w.dims);
   launch_build(s, L, w.tab, w.pwi, w.fg, w.nopen, w.openidx, w.colpos, w.aug);
+  launch_prop_assemble(s, L, w.tab, w.pwi, w.nopen, w.pz, w.aug, w.gre, w.gim);  // coupled energies
   launch_lu_solve(s, L.ne, L.nmax, L.nmax, w.dims, w.aug, L.ldaug, L.sA, L.roff, w.ipiv, L.ldo, w.bperm, w.linv, 1,
                   w.status);
   launch_gatherK(s, L, w.tab, w.pwi, w.nopen, w.aug, w.Kw, w.dims);
@@ -604,7 +621,8 @@ std::string chunk_key(rm_ctx *ctx, const Plan &P, const Work &w, const rm_opts &
   auto add = [&](const auto &v) { k.append(reinterpret_cast<const char *>(&v), sizeof v); };
   const Lay &L = P.L;
   for (long v : {(long)L.ne, (long)L.nmax, (long)L.npadmax, (long)L.Mpadmax, (long)L.ntmax, L.ldD, L.ldaug, L.roff,
-                 L.sA, L.ldk, L.sK, L.ldo, L.sOm})
+                 L.sA, L.ldk, L.sK, L.ldo, L.sOm, (long)L.npadc, L.zrb, L.sZ, (long)ctx->prop_npts.load(),
+                 (long)ctx->prop_stab.load()})
     add(v);
   for (const void *p : {(const void *)w.E, (const void *)w.pwi, (const void *)w.tab, (const void *)w.tasks,
                         (const void *)w.counter, (const void *)w.D64, (const void *)w.D32, (const void *)w.win,
@@ -612,7 +630,7 @@ std::string chunk_key(rm_ctx *ctx, const Plan &P, const Work &w, const rm_opts &
                         (const void *)w.openpos, (const void *)w.colpos, (const void *)w.openflag,
                         (const void *)w.fg, (const void *)w.aug, (const void *)w.Kw, (const void *)w.gre, (const void *)w.gim,
                         (const void *)w.dims, (const void *)w.ipiv, (const void *)w.bperm, (const void *)w.linv,
-                        (const void *)w.omega, (const void *)w.pack, (const void *)w.pack_off})
+                        (const void *)w.omega, (const void *)w.pack, (const void *)w.pack_off, (const void *)w.pz})
     add(p);
   for (int sh = 0; sh < NRTMAX; ++sh) add(P.q[sh]);
   add(P.maxtiles);
@@ -726,6 +744,13 @@ rm_status run_chunk(rm_ctx *ctx, const Plan &P, Slot &sl, const std::vector<Seg>
       launch_asym(s, L, w.tab, w.pwi, w.E, o.thr_guard, w.fg, w.status);
     });
   });
+  if (L.npadc)
+    timed(ctx, STAGE_PROP, L.ne, s, [&] {
+      group(8, [&] {
+        launch_prop(s, L, ctx->prop_npts.load(), ctx->prop_stab.load(), w.tab, w.pwi, w.E, w.fg, w.nopen, w.openidx, w.colpos, w.pz,
+                    w.status);
+      });
+    });
   if (before_R) HIPCHK(hipStreamWaitEvent(s, before_R, 0));
   group(1, [&] { launch_dvec(s, L, w.tab, w.pwi, w.E, split, o.split_delta, w.D64, w.D32, w.win, w.status); });
   timed(ctx, 0, L.ne, s, [&] {
@@ -849,13 +874,14 @@ rm_status run_segments(rm_ctx *ctx, const std::vector<Seg> &segs, const rm_opts 
     }
   }
   size_t total = 0;
-  int n = 0, npad = 0, Mpad = 0, nt = 0;
+  int n = 0, npad = 0, Mpad = 0, nt = 0, npc = 0;
   for (const Seg &g : segs) {
     total += g.ne;
     n = std::max(n, g.pw->n);
     npad = std::max(npad, g.pw->npad);
     Mpad = std::max(Mpad, g.pw->Mpad);
     nt = std::max(nt, g.pw->nt);
+    if (g.pw->lamax) npc = std::max(npc, g.pw->npad);
   }
   if (!total) return RM_OK;
   size_t share;
@@ -867,7 +893,7 @@ rm_status run_segments(rm_ctx *ctx, const std::vector<Seg> &segs, const rm_opts 
   // Chunks of up to MAX_CHUNK energies (fewer if the HBM budget says so)
   // alternate over the two streams.  Large chunks keep every launch of the LU
   // chain wide enough to fill the device.
-  const int cap = chunk_cap(n, npad, Mpad, nt, share, MAX_CHUNK);
+  const int cap = chunk_cap(n, npad, Mpad, nt, share, MAX_CHUNK, npc);
   std::vector<Plan> plans = cut_chunks(segs, cap, interleave);
   const int nuse = plans.size() > 1 ? 2 : 1;
   HIPCHK(hipEventRecord(ctx->ev_in, user));
@@ -900,7 +926,8 @@ rm_status staged_chunk(rm_ctx *ctx, const DevPW *pw, const double *E, int e0, in
 }
 
 int staged_cap(rm_ctx *ctx, const DevPW *pw, int ne) {
-  return chunk_cap(pw->n, pw->npad, pw->Mpad, pw->nt, free_share(ctx, ctx->sync), std::min(ne, 256));
+  return chunk_cap(pw->n, pw->npad, pw->Mpad, pw->nt, free_share(ctx, ctx->sync), std::min(ne, 256),
+                   pw->lamax ? pw->npad : 0);
 }
 
 // The staged calls run on ctx->sync.stream; with device pointers it is ordered
@@ -990,7 +1017,7 @@ void worker_main(rm_ctx *ctx, Slot *slot) {
       const size_t used = ctx->resident + ctx->work_bytes - slot->w.bytes;
       const size_t avail = ctx->budget > used ? ctx->budget - used : 0;
       size_t share = ctx->mem_waiter == slot ? avail : avail / std::max<size_t>(ctx->slots.size(), 1);
-      int n = 0, npad = 0, Mpad = 0, nt = 0;
+      int n = 0, npad = 0, Mpad = 0, nt = 0, npc = 0;
       for (Req *q : ctx->active) {
         if (q->next_e >= q->rq.ne || !compatible(q)) continue;
         auto it = ctx->pws.find(q->rq.pw_id);
@@ -999,8 +1026,9 @@ void worker_main(rm_ctx *ctx, Slot *slot) {
         npad = std::max(npad, it->second.npad);
         Mpad = std::max(Mpad, it->second.Mpad);
         nt = std::max(nt, it->second.nt);
+        if (it->second.lamax) npc = std::max(npc, it->second.npad);
       }
-      const size_t one = n ? per_energy_bytes(n, npad, Mpad, nt) + kChunkFixedBytes : 0;
+      const size_t one = n ? per_energy_bytes(n, npad, Mpad, nt, npc) + kChunkFixedBytes : 0;
       if (one > share) {
         size_t others = 0;  // releasable by the other serving workers
         for (const auto &sl : ctx->slots)
@@ -1036,7 +1064,7 @@ void worker_main(rm_ctx *ctx, Slot *slot) {
         ctx->mem_waiter = nullptr;
         ctx->cv.notify_all();
       }
-      int room = n ? chunk_cap(n, npad, Mpad, nt, share, 256) : 0;
+      int room = n ? chunk_cap(n, npad, Mpad, nt, share, 256, npc) : 0;
       for (Req *q : ctx->active) {
         if (room <= 0) break;
         if (q->next_e >= q->rq.ne || !compatible(q)) continue;
@@ -1097,7 +1125,7 @@ void worker_main(rm_ctx *ctx, Slot *slot) {
 }
 
 void free_pw(DevPW &p) {
-  void *ptrs[] = {p.W64, p.W32, p.Ek, p.ethr, p.l, p.target, p.tptr, p.tch};
+  void *ptrs[] = {p.W64, p.W32, p.Ek, p.ethr, p.l, p.target, p.tptr, p.tch, p.cf};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
 }
@@ -1149,7 +1177,8 @@ rm_status scratch_address(rm_ctx *ctx, int device, char **out) {
 // array; false if they do not fit.
 bool carve_work(Work &w, char *base, const Lay &L, int ntab, int ntasks) {
   Work nw;
-  const std::vector<WorkBuf> bufs = work_buffers(nw, L.ne, L.nmax, L.npadmax, L.Mpadmax, L.ntmax, ntab, ntasks, false);
+  const std::vector<WorkBuf> bufs =
+      work_buffers(nw, L.ne, L.nmax, L.npadmax, L.Mpadmax, L.ntmax, ntab, ntasks, false, L.npadc);
   if (work_bytes(bufs) > RM_NOALLOC_SCRATCH_BYTES) return false;
   size_t off = 0;
   for (const WorkBuf &b : bufs) {
@@ -1178,6 +1207,10 @@ rm_status init_noalloc(rm_ctx *ctx) {
   ctx->na.direct = true;
   return RM_OK;
 }
+
+// Uploads a partial wave (and its multipole coupling when lamax > 0).
+rm_status rm_pw_upload_coupled_impl(rm_ctx *ctx, const rm_pw_desc *d, int32_t lamax, const double *cf, double r1,
+                                    int32_t *pw_id);
 
 // Plans energies [e0, e0 + m) of the single segment.
 void plan_single(Plan &P, const std::vector<Seg> &segs, int e0, int m) {
@@ -1284,6 +1317,42 @@ size_t rm_work_footprint(int32_t nchan, int32_t npole, int32_t ntarget, int32_t 
 }
 
 rm_status rm_pw_upload(rm_ctx *ctx, const rm_pw_desc *d, int32_t *pw_id) {
+  return rm_pw_upload_coupled_impl(ctx, d, 0, nullptr, 0.0, pw_id);
+}
+
+rm_status rm_pw_upload_coupled(rm_ctx *ctx, const rm_pw_desc *d, int32_t lamax, const double *cf, double r1,
+                               int32_t *pw_id) {
+  if (!ctx || !d || !pw_id) return RM_E_ARG;
+  if (lamax < 1 || lamax > RM_PROP_MAX_LAMAX || !cf || d->nchan < 1 || d->nchan > RM_PROP_MAX_CHANNELS ||
+      !(r1 > d->a) || !std::isfinite(r1)) {
+    ctx->err = "invalid coupling: 1 <= lamax <= RM_PROP_MAX_LAMAX, nchan <= RM_PROP_MAX_CHANNELS and r1 > a needed";
+    return RM_E_ARG;
+  }
+  for (size_t k = 0; k < (size_t)lamax * d->nchan * d->nchan; ++k)
+    if (!std::isfinite(cf[k])) {
+      ctx->err = "non-finite multipole coefficient";
+      return RM_E_ARG;
+    }
+  return rm_pw_upload_coupled_impl(ctx, d, lamax, cf, r1, pw_id);
+}
+
+rm_status rm_set_propagation(rm_ctx *ctx, int32_t npts, int32_t stab) {
+  if (!ctx) return RM_E_ARG;
+  if (npts < 4 || stab < 1) {
+    ctx->err = "propagation grid: npts >= 4 and stab >= 1 needed";
+    return RM_E_ARG;
+  }
+  ctx->prop_npts.store(npts);
+  ctx->prop_stab.store(stab);
+  return RM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+rm_status rm_pw_upload_coupled_impl(rm_ctx *ctx, const rm_pw_desc *d, int32_t lamax, const double *cf, double r1,
+                                    int32_t *pw_id) {
   if (!ctx || !d || !pw_id) return RM_E_ARG;
   if (d->nchan < 1 || d->nchan > RM_MAX_CHANNELS || d->npole < 1 || d->ntarget < 1 || !d->e_thr || !d->l || !d->target || !d->Ek || !d->w ||
       !(d->a > 0) || !(d->z >= 0)) {
@@ -1300,7 +1369,8 @@ rm_status rm_pw_upload(rm_ctx *ctx, const rm_pw_desc *d, int32_t *pw_id) {
       ctx->err = "channel target or l out of range";
       return RM_E_ARG;
     }
-  const size_t bytes = rm_pw_footprint(d->nchan, d->npole);
+  const size_t cfbytes = (size_t)lamax * round_up(d->nchan, TILE) * round_up(d->nchan, TILE) * 8;
+  const size_t bytes = rm_pw_footprint(d->nchan, d->npole) + cfbytes;
   {
     std::lock_guard<std::mutex> g(ctx->mu);
     if (ctx->resident + ctx->work_bytes + bytes > ctx->budget) {
@@ -1353,6 +1423,17 @@ rm_status rm_pw_upload(rm_ctx *ctx, const rm_pw_desc *d, int32_t *pw_id) {
   HIPCHK(hipMemcpy(p.target, d->target, p.n * 4, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(p.tptr, tptr.data(), (p.nt + 1) * 4, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(p.tch, tch.data(), p.n * 4, hipMemcpyHostToDevice));
+  if (lamax) {
+    std::vector<double> A((size_t)lamax * p.npad * p.npad, 0.0);
+    for (int lam = 0; lam < lamax; ++lam)
+      for (int i = 0; i < p.n; ++i)
+        for (int j = 0; j < p.n; ++j)
+          A[((size_t)lam * p.npad + i) * p.npad + j] = cf[((size_t)lam * p.n + i) * p.n + j];
+    HIPCHK(hipMalloc(&p.cf, A.size() * 8));
+    HIPCHK(hipMemcpy(p.cf, A.data(), A.size() * 8, hipMemcpyHostToDevice));
+    p.lamax = lamax;
+    p.r1 = r1;
+  }
   std::lock_guard<std::mutex> g(ctx->mu);
   const int32_t id = ctx->next_id++;
   ctx->pws[id] = p;
@@ -1361,6 +1442,10 @@ rm_status rm_pw_upload(rm_ctx *ctx, const rm_pw_desc *d, int32_t *pw_id) {
   *pw_id = id;
   return RM_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 rm_status rm_pw_release(rm_ctx *ctx, int32_t pw_id) {
   if (!ctx) return RM_E_ARG;
@@ -1439,12 +1524,59 @@ rm_status rm_asymptotic(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, 
   return staged_leave(ctx, o, ev);
 }
 
+rm_status rm_propagate(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, const rm_opts *opts, double *phi,
+                       double *dphi, int32_t *status) {
+  if (!ctx || ne < 0 || (ne > 0 && (!E || !phi || !dphi || !status))) return RM_E_ARG;
+  if (ne == 0) return RM_OK;
+  const DevPW *pw;
+  if (rm_status st = get_pw(ctx, pwid, &pw)) return st;
+  if (!pw->lamax) {
+    ctx->err = "rm_propagate: the partial wave has no multipole coupling";
+    return RM_E_ARG;
+  }
+  (void)hipSetDevice(ctx->device);
+  const rm_opts o = fixed_opts(opts);
+  hipEvent_t ev;
+  if (rm_status st = staged_enter(ctx, o, ev)) return st;
+  const hipStream_t s = ctx->sync.stream;
+  const int cap = staged_cap(ctx, pw, ne);
+  const int n = pw->n;
+  const int npts = ctx->prop_npts.load(), stab = ctx->prop_stab.load();
+  for (int e0 = 0; e0 < ne; e0 += cap) {
+    const int m = std::min(cap, ne - e0);
+    Plan P;
+    std::vector<Seg> segs;
+    if (rm_status st = staged_chunk(ctx, pw, E, e0, m, o, false, P, segs)) return st;
+    Work &w = ctx->sync.w;
+    const Lay &L = P.L;
+    launch_fill_int(s, w.status, m, 0);
+    stage_asym(ctx, P, w, o, s);
+    timed(ctx, STAGE_PROP, m, s, [&] {
+      launch_prop(s, L, npts, stab, w.tab, w.pwi, w.E, w.fg, w.nopen, w.openidx, w.colpos, w.pz, w.status);
+    });
+    // phi, then dphi, through aug (n rows of 2 npad >= 2n columns per energy)
+    double *outs[2] = {phi, dphi};
+    for (int q = 0; q < 2; ++q) {
+      launch_prop_gather(s, L, w.tab, w.pwi, w.nopen, w.status, w.pz, 3 + q, w.aug, L.ldaug, L.sA);
+      HIPCHK(hipMemcpy2DAsync(outs[q] + (size_t)e0 * n * 2 * n, sizeof(double) * 2 * n, w.aug,
+                              sizeof(double) * L.ldaug, sizeof(double) * 2 * n, (size_t)m * n, kind_out(o), s));
+    }
+    HIPCHK(hipMemcpyAsync(status + e0, w.status, sizeof(int) * m, kind_out(o), s));
+    HIPCHK(hipGetLastError());
+  }
+  return staged_leave(ctx, o, ev);
+}
+
 rm_status rm_solve_K(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, const double *R, const double *fg,
                      const rm_opts *opts, double *K, int32_t *status) {
   if (!ctx || ne < 0 || (ne > 0 && (!E || !R || !fg || !K || !status))) return RM_E_ARG;
   if (ne == 0) return RM_OK;
   const DevPW *pw;
   if (rm_status st = get_pw(ctx, pwid, &pw)) return st;
+  if (pw->lamax) {
+    ctx->err = "rm_solve_K: a coupled wave is matched to its propagated solutions (rm_run)";
+    return RM_E_ARG;
+  }
   (void)hipSetDevice(ctx->device);
   const rm_opts o = fixed_opts(opts);
   hipEvent_t ev;
@@ -1554,7 +1686,8 @@ rm_status rm_run_noalloc(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne,
     if (ntasks <= NA_TASKS && carve_work(probe, ctx->scratch, P.L, 1, ntasks)) break;
     if (m == 1) {
       Work one;
-      const size_t need = work_bytes(work_buffers(one, 1, pw->n, pw->npad, pw->Mpad, pw->nt, 1, ntasks, false));
+      const size_t need = work_bytes(
+          work_buffers(one, 1, pw->n, pw->npad, pw->Mpad, pw->nt, 1, ntasks, false, pw->lamax ? pw->npad : 0));
       ctx->err = "one energy of this partial wave needs " + std::to_string(need) +
                  " bytes of workspace, more than the no-alloc scratch of " +
                  std::to_string((size_t)RM_NOALLOC_SCRATCH_BYTES) + " bytes";

@@ -21,6 +21,7 @@ RM_E_ARG, RM_E_NOMEM, RM_E_DEVICE, RM_E_NOTFOUND, RM_E_BUSY, RM_E_IO = -1, -2, -
 PT_POLE, PT_THRESHOLD, PT_NOCONV, PT_SINGULAR, PT_NONFINITE = 1, 2, 4, 8, 16
 FP64, FP32_SPLIT = 0, 1
 NOALLOC_SCRATCH_BYTES = 256 << 20  # RM_NOALLOC_SCRATCH_BYTES of rm.h
+PROP_MAX_CHANNELS, PROP_MAX_LAMAX = 128, 8  # RM_PROP_MAX_CHANNELS, RM_PROP_MAX_LAMAX
 ORDER_WAVE, ORDER_PERMUTED = 0, 1
 
 if not os.path.exists(LIB_PATH):
@@ -98,12 +99,16 @@ _lib.rm_tune.argtypes = [_vp, _i32, ctypes.POINTER(_i32), _i32, _vp, _i32, _i32,
 _lib.rm_tune_load.argtypes = [_vp, ctypes.c_char_p]
 _lib.rm_set_graph.argtypes = [_vp, _i32]
 _lib.rm_graph_stats.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+_lib.rm_pw_upload_coupled.argtypes = [_vp, ctypes.POINTER(PWDesc), _i32, _vp, _d, ctypes.POINTER(_i32)]
+_lib.rm_set_propagation.argtypes = [_vp, _i32, _i32]
+_lib.rm_propagate.argtypes = [_vp, _i32, _vp, _i32, ctypes.POINTER(Opts), _vp, _vp, _vp]
 
 EXPORTS = ["rm_opts_default", "rm_create", "rm_destroy", "rm_last_error", "rm_pw_upload", "rm_pw_release",
            "rm_pw_footprint", "rm_work_footprint", "rm_form_R", "rm_asymptotic", "rm_solve_K", "rm_collision_strengths", "rm_run",
            "rm_run_noalloc", "rm_run_batch", "rm_run_sum", "rm_tile_bucket", "rm_tile_count", "rm_tile_shape", "rm_get_tile",
            "rm_set_tile", "rm_tune", "rm_tune_load", "rm_set_graph", "rm_graph_stats",
            "rm_submit", "rm_poll", "rm_drain", "rm_prof_enable", "rm_prof_read", "rm_prof_chunks",
+           "rm_pw_upload_coupled", "rm_set_propagation", "rm_propagate",
            "rm_hdat_open", "rm_hdat_close", "rm_hdat_error", "rm_hdat_target_info", "rm_hdat_attach", "rm_hdat_next",
            "rm_hdat_arrays", "rm_hdat_pw_desc", "rm_sizeh_read", "rm_omega_write"]
 
@@ -286,16 +291,40 @@ class Context:
             pass
 
     # ------------------------------------------------------------------
-    def pw_upload(self, pw) -> int:
-        """Upload a synth.PartialWave (or any object with the same fields)."""
+    def pw_upload(self, pw, coupling: dict | None = None) -> int:
+        """Upload a synth.PartialWave (or any object with the same fields); with
+        coupling = dict(cf=[lamax][n][n] multipole coefficients, r1=radius) the
+        wave's channels are coupled between a and r1."""
         keep = [np.ascontiguousarray(pw.e_thr, dtype=np.float64), np.ascontiguousarray(pw.l, dtype=np.int32),
                 np.ascontiguousarray(pw.target, dtype=np.int32), np.ascontiguousarray(pw.Ek, dtype=np.float64),
                 np.ascontiguousarray(pw.w, dtype=np.float64)]
         d = PWDesc(pw.nchan, pw.npole, pw.ntarget, pw.a, pw.b, pw.z, pw.g, *[k.ctypes.data for k in keep])
         pid = _i32()
-        self._check(_lib.rm_pw_upload(self.h, ctypes.byref(d), ctypes.byref(pid)))
+        if coupling is None:
+            self._check(_lib.rm_pw_upload(self.h, ctypes.byref(d), ctypes.byref(pid)))
+        else:
+            cf = np.ascontiguousarray(coupling["cf"], dtype=np.float64)
+            if cf.ndim != 3 or cf.shape[1:] != (pw.nchan, pw.nchan):
+                raise ValueError("coupling cf must be [lamax][nchan][nchan]")
+            self._check(_lib.rm_pw_upload_coupled(self.h, ctypes.byref(d), cf.shape[0], cf.ctypes.data,
+                                                  float(coupling["r1"]), ctypes.byref(pid)))
         self._pw[pid.value] = (pw.nchan, pw.ntarget)
         return pid.value
+
+    def set_propagation(self, npts: int = 3201, stab: int = 64):
+        self._check(_lib.rm_set_propagation(self.h, int(npts), int(stab)))
+
+    def propagate(self, pw_id, E, thr_guard=1e-10):
+        """phi, dphi [ne][n][2n] at r = a of a coupled wave, and status."""
+        E, dev = self._E(E)
+        n, _ = self._pw.get(pw_id, (1, 1))
+        ne = E.shape[0]
+        phi = self._alloc(E, (ne, n, 2 * n), np.float64)
+        dphi = self._alloc(E, (ne, n, 2 * n), np.float64)
+        st = self._alloc(E, (ne,), np.int32)
+        o = self._opts(FP64, 0.05, thr_guard, dev)
+        self._check(_lib.rm_propagate(self.h, pw_id, _ptr(E), ne, ctypes.byref(o), _ptr(phi), _ptr(dphi), _ptr(st)))
+        return phi, dphi, st
 
     def pw_release(self, pw_id: int):
         self._check(_lib.rm_pw_release(self.h, pw_id))

@@ -288,3 +288,25 @@ def config5_requests(pool: list[PartialWave], nreq: int = 400, rate_hz: float = 
         E = np.where(near < THRESHOLD_CLEARANCE, E + 10 * THRESHOLD_CLEARANCE, E)
         reqs.append(Request(int(pick[r]), float(t[r]), np.sort(E)))
     return reqs
+
+
+def multipole_coefficients(seed: int, nchan: int, lamax: int = 2, scale: float = 0.5,
+                           name: str = "cf") -> np.ndarray:
+    """Coefficients of the long-range multipole potentials (the H.DAT CF
+    record), [lamax][nchan][nchan]: for every order a symmetric matrix with
+    N(0, scale^2) entries (the diagonal N(0, 2 scale^2))."""
+    x = Stream(seed, f"{name}/{nchan}/{lamax}").normal(lamax * nchan * nchan).reshape(lamax, nchan, nchan) * scale
+    return np.ascontiguousarray((x + x.transpose(0, 2, 1)) / math.sqrt(2.0))
+
+
+def config_coupled(nchan: int = 100, nenergy: int = 1000) -> tuple[PartialWave, dict, np.ndarray]:
+    """Coupled wave: 100 channels (25 targets, thresholds in [0, 8] Ry), 20
+    poles per channel in [-2, 60] Ry, z=5, a=12, dipole and quadrupole
+    potentials (lamax = 2, scale 0.5) propagated to r1 = 30 on the paper's 3201
+    points, 1000 energies uniform in [0.01, 8] Ry.  Returns (wave, coupling,
+    energies) with coupling = dict(cf, r1, npts, stab)."""
+    E = np.linspace(0.01, 8.0, nenergy)
+    pw = make_partial_wave(config_seed(8), nchan, 20, z=5.0, a=12.0, thr_range=(0.0, 8.0),
+                           pole_range=(-2.0, 60.0), avoid_energies=E, name="cpl")
+    cp = dict(cf=multipole_coefficients(config_seed(8), nchan), r1=30.0, npts=3201, stab=64)
+    return pw, cp, E

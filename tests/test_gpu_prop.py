@@ -1,0 +1,232 @@
+"""GPU parity of the coupled outer region (PSTGF paper, section "Overview":
+eq. (radial) with the long-range multipole potentials U kept, the Numerov
+propagation of the coupled solutions between r1 and the boundary a, and the
+matching eq. (match) with the propagated solution matrices).
+
+- rm_propagate (phi, dphi at a) against the oracle's propagation, for waves
+  stepped by both instances of the stepping kernel (up to 64 and up to 128
+  padded channels);
+- K and Omega of rm_run on coupled waves against the oracle's coupled run;
+- with zero coefficients the propagated K converges at fourth order to the
+  plain matching at r = a (a pin that does not use the oracle);
+- coupled and uncoupled waves in one batch give the results of their solo runs
+  bit for bit;
+- edge cases (no open channel, an energy on a threshold) and the argument
+  checks of the coupled entry points.
+
+The propagation error metric is normwise per energy over the valid columns,
+||X_gpu - X_ora||_max / ||X_ora||_max; the gate PROP_GATE is set from the
+measured agreement (the two sides invert T = 1 - h^2 Q / 12 differently: the
+oracle by an LU solve in long double, the kernel by its Neumann series)."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1909_07321_amd import synth
+
+from _metrics import gate, k_err, omega_elementwise
+
+pytestmark = pytest.mark.gpu
+
+PROP_GATE = 1e-9
+NPTS, STAB = 801, 64
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1909_07321_amd import rm
+    c = rm.Context(0)
+    c.set_propagation(NPTS, STAB)
+    yield c
+    c.close()
+
+
+def _threads():
+    return len(os.sched_getaffinity(0))
+
+
+def _wave(n, seed, E):
+    return synth.make_partial_wave(synth.config_seed(8) + seed, n, 20, z=5.0, a=12.0, thr_range=(0.0, 8.0),
+                                   pole_range=(-2.0, 60.0), avoid_energies=E, name=f"cw{n}")
+
+
+def _cp(n, seed, lamax=2, scale=0.5, r1=30.0):
+    return dict(cf=synth.multipole_coefficients(synth.config_seed(8) + seed, n, lamax, scale), r1=r1, npts=NPTS,
+                stab=STAB)
+
+
+# energies from nearly every channel closed to nearly every channel open
+E8 = np.array([0.013, 0.61, 1.37, 2.9, 4.05, 5.5, 6.8, 7.93])
+
+
+@pytest.mark.parametrize("n", [7, 40, 64, 65, 100, 128])
+def test_propagate_vs_oracle(ctx, n):
+    E = E8 if n in (40, 100) else E8[[1, 4, 7]]
+    pw, cp = _wave(n, n, E), _cp(n, n)
+    pid = ctx.pw_upload(pw, cp)
+    _say(f"propagate n={n} energies={E.size}")
+    phi, dphi, st = ctx.propagate(pid, E)
+    phio, dphio, op, no, sto = oracle.Oracle(pw, nthreads=_threads()).propagate(E, cp)
+    assert (st == 0).all() and (sto == 0).all()
+    for e in range(E.size):
+        m = n + no[e]
+        assert not phi[e, :, m:].any() and not dphi[e, :, m:].any()
+        ep = np.abs(phi[e, :, :m] - phio[e, :, :m]).max() / np.abs(phio[e, :, :m]).max()
+        ed = np.abs(dphi[e, :, :m] - dphio[e, :, :m]).max() / np.abs(dphio[e, :, :m]).max()
+        _say(f"  E={E[e]:.3f} open {no[e]}/{n}: phi err {ep:.2e}, dphi err {ed:.2e}")
+        assert ep <= PROP_GATE and ed <= PROP_GATE
+    ctx.pw_release(pid)
+
+
+@pytest.mark.parametrize("n", [40, 100])
+def test_run_coupled_vs_oracle(ctx, n):
+    E = E8
+    pw, cp = _wave(n, n, E), _cp(n, n)
+    pid = ctx.pw_upload(pw, cp)
+    om, K, st = ctx.run(pid, E)
+    res = oracle.Oracle(pw, nthreads=_threads()).run_coupled(E, cp)
+    no = oracle.open_count(pw, E)
+    assert (st == 0).all() and (res["status"] == 0).all()
+    errK = k_err(K, res["K"], no)
+    errO = omega_elementwise(om, res["omega"])
+    g = gate(res["cond"])
+    for e in range(E.size):
+        _say(f"n={n} E={E[e]:.3f} open {no[e]} cond {res['cond'][e]:.1e}: K err {errK[e]:.2e} Omega err "
+             f"{errO[e]:.2e} (gate {g[e]:.1e})")
+    assert (errK <= g).all() and (errO <= g).all()
+    # the coupling matters: the plain matching at a gives a different K
+    pid0 = ctx.pw_upload(pw)
+    _, K0, _ = ctx.run(pid0, E)
+    assert max(k_err(K, K0, no)) > 1e-3
+    ctx.pw_release(pid)
+    ctx.pw_release(pid0)
+
+
+def test_zero_coupling_converges_to_plain_matching(ctx):
+    """U = 0: the propagated solutions are the Coulomb / Whittaker functions up
+    to the Numerov error, so K converges to the r = a matching at fourth order
+    (error ratio ~16 per halving of h)."""
+    n = 40
+    E = E8[[1, 3, 5, 7]]
+    pw = _wave(n, 3, E)
+    pid = ctx.pw_upload(pw, dict(cf=np.zeros((1, n, n)), r1=30.0))
+    pid0 = ctx.pw_upload(pw)
+    _, K0, _ = ctx.run(pid0, E)
+    no = oracle.open_count(pw, E)
+    errs = []
+    try:
+        for npts in (801, 1601):
+            ctx.set_propagation(npts, STAB)
+            _, K, st = ctx.run(pid, E)
+            assert (st == 0).all()
+            errs.append(k_err(K, K0, no))
+    finally:
+        ctx.set_propagation(NPTS, STAB)
+    ratio = errs[0] / np.maximum(errs[1], 1e-300)
+    _say(f"U=0 K vs plain matching: 801 pts {errs[0]}, 1601 pts {errs[1]}, ratio {ratio}")
+    assert errs[1].max() < 1e-5
+    assert ((ratio > 10) & (ratio < 25)).all()
+    ctx.pw_release(pid)
+    ctx.pw_release(pid0)
+
+
+def test_mixed_batch_matches_solo_runs(ctx):
+    from paper_1909_07321_amd import rm
+    E = E8
+    pwc, cp = _wave(100, 100, E), _cp(100, 100)
+    pwu = _wave(150, 5, E)
+    pwc2, cp2 = _wave(40, 40, E), _cp(40, 40)
+    ids = [ctx.pw_upload(pwc, cp), ctx.pw_upload(pwu), ctx.pw_upload(pwc2, cp2)]
+    solo = [ctx.run(i, E) for i in ids]
+    outs = ctx.run_batch([(i, E) for i in ids], prec=rm.FP64, want_K=True)
+    for s, o in zip(solo, outs):
+        assert np.array_equal(s[0], o[0]) and np.array_equal(s[1], o[1]) and np.array_equal(s[2], o[2])
+    for i in ids:
+        ctx.pw_release(i)
+
+
+def test_coupled_edge_cases(ctx):
+    from paper_1909_07321_amd import rm
+    n = 40
+    pw = _wave(n, 6, E8)
+    pid = ctx.pw_upload(pw, _cp(n, 6))
+    # every channel closed: no K, Omega zero
+    Ec = np.array([pw.e_thr.min() - 0.3])
+    om, K, st = ctx.run(pid, Ec)
+    assert st[0] == 0 and not om.any() and not K.any()
+    phi, dphi, st = ctx.propagate(pid, Ec)
+    assert st[0] == 0 and np.isfinite(phi).all() and not phi[0, :, n:].any()
+    # on a threshold: flagged, NaN outputs, neighbours unaffected
+    Et = np.array([E8[2], pw.e_thr[5], E8[4]])
+    om, K, st = ctx.run(pid, Et)
+    assert st[1] & rm.PT_THRESHOLD and np.isnan(om[1]).all()
+    assert st[0] == 0 and st[2] == 0 and np.isfinite(om[[0, 2]]).all()
+    phi, dphi, st = ctx.propagate(pid, Et)
+    assert st[1] & rm.PT_THRESHOLD and np.isnan(phi[1]).all() and np.isfinite(phi[[0, 2]]).all()
+    om0, K0, _ = ctx.run(pid, Et[[0, 2]])
+    assert np.array_equal(om0, om[[0, 2]])
+    # no energies
+    phi, dphi, st = ctx.propagate(pid, np.zeros(0))
+    assert phi.shape == (0, n, 2 * n)
+    ctx.pw_release(pid)
+
+
+def test_coupled_argument_checks(ctx):
+    from paper_1909_07321_amd import rm
+    E = E8[:2]
+    pw = _wave(40, 7, E)
+    big = _wave(rm.PROP_MAX_CHANNELS + 1, 8, E)
+    with pytest.raises(rm.RMError):
+        ctx.pw_upload(big, _cp(big.nchan, 8))
+    for cp in (dict(cf=np.zeros((0, 40, 40)), r1=30.0),
+               dict(cf=np.zeros((rm.PROP_MAX_LAMAX + 1, 40, 40)), r1=30.0),
+               dict(cf=np.zeros((1, 40, 40)), r1=pw.a),
+               dict(cf=np.full((1, 40, 40), np.nan), r1=30.0)):
+        with pytest.raises(rm.RMError):
+            ctx.pw_upload(pw, cp)
+    with pytest.raises(rm.RMError):
+        ctx.set_propagation(3, 64)
+    with pytest.raises(rm.RMError):
+        ctx.set_propagation(801, 0)
+    pid0, pid = ctx.pw_upload(pw), ctx.pw_upload(pw, _cp(40, 7))
+    with pytest.raises(rm.RMError):
+        ctx.propagate(pid0, E)
+    R, _ = ctx.form_R(pid, E)
+    fg, *_ = ctx.asymptotic(pid, E)
+    with pytest.raises(rm.RMError):
+        ctx.solve_K(pid, E, R, fg)
+    ctx.pw_release(pid0)
+    ctx.pw_release(pid)
+
+
+def test_coupled_full_grid_sampled(ctx):
+    """The coupled workload at full size (100 channels, 1000 energies, the
+    paper's 3201 points): every energy finite with K symmetric to the
+    discretisation, three sampled energies against the oracle at 3201 points."""
+    pw, cp, E = synth.config_coupled()
+    pid = ctx.pw_upload(pw, cp)
+    try:
+        ctx.set_propagation(cp["npts"], cp["stab"])
+        om, K, st = ctx.run(pid, E)
+    finally:
+        ctx.set_propagation(NPTS, STAB)
+    assert (st == 0).all() and np.isfinite(om).all() and om.min() >= 0
+    no = oracle.open_count(pw, E)
+    asym = max(np.abs(K[e, :no[e], :no[e]] - K[e, :no[e], :no[e]].T).max() / max(1, np.abs(K[e]).max())
+               for e in range(E.size) if no[e])
+    _say(f"coupled full grid: K asymmetry max {asym:.2e}")
+    assert asym < 1e-6
+    idx = [137, 500, 911]
+    res = oracle.Oracle(pw, nthreads=_threads()).run_coupled(E[idx], cp)
+    errK = k_err(K[idx], res["K"], no[idx])
+    errO = omega_elementwise(om[idx], res["omega"])
+    g = gate(res["cond"])
+    _say(f"coupled full grid sampled: K err {errK}, Omega err {errO}, gate {g}")
+    assert (errK <= g).all() and (errO <= g).all()
+    ctx.pw_release(pid)

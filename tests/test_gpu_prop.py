@@ -28,9 +28,19 @@ from paper_1909_07321_amd import synth
 
 from _metrics import gate, k_err, omega_elementwise
 
+
+def _omega_ref(o, E, K):
+    """The oracle's Omega from its symmetrised K.  A propagated K is symmetric
+    only up to the Numerov error (~1e-8 relative at 801 points); the library
+    forms S and Omega from (K + K^T)/2, so the reference does too."""
+    om, _, st = o.collision_strengths(E, 0.5 * (K + np.transpose(K, (0, 2, 1))))
+    assert (st == 0).all()
+    return om
+
+
 pytestmark = pytest.mark.gpu
 
-PROP_GATE = 1e-9
+PROP_GATE = 1e-9  # measured max 1.6e-11 (100 channels, 801 points)
 NPTS, STAB = 801, 64
 
 
@@ -90,11 +100,12 @@ def test_run_coupled_vs_oracle(ctx, n):
     pw, cp = _wave(n, n, E), _cp(n, n)
     pid = ctx.pw_upload(pw, cp)
     om, K, st = ctx.run(pid, E)
-    res = oracle.Oracle(pw, nthreads=_threads()).run_coupled(E, cp)
+    o = oracle.Oracle(pw, nthreads=_threads())
+    res = o.run_coupled(E, cp)
     no = oracle.open_count(pw, E)
     assert (st == 0).all() and (res["status"] == 0).all()
     errK = k_err(K, res["K"], no)
-    errO = omega_elementwise(om, res["omega"])
+    errO = omega_elementwise(om, _omega_ref(o, E, res["K"]))
     g = gate(res["cond"])
     for e in range(E.size):
         _say(f"n={n} E={E[e]:.3f} open {no[e]} cond {res['cond'][e]:.1e}: K err {errK[e]:.2e} Omega err "
@@ -223,9 +234,10 @@ def test_coupled_full_grid_sampled(ctx):
     _say(f"coupled full grid: K asymmetry max {asym:.2e}")
     assert asym < 1e-6
     idx = [137, 500, 911]
-    res = oracle.Oracle(pw, nthreads=_threads()).run_coupled(E[idx], cp)
+    o = oracle.Oracle(pw, nthreads=_threads())
+    res = o.run_coupled(E[idx], cp)
     errK = k_err(K[idx], res["K"], no[idx])
-    errO = omega_elementwise(om[idx], res["omega"])
+    errO = omega_elementwise(om[idx], _omega_ref(o, E[idx], res["K"]))
     g = gate(res["cond"])
     _say(f"coupled full grid sampled: K err {errK}, Omega err {errO}, gate {g}")
     assert (errK <= g).all() and (errO <= g).all()

@@ -175,7 +175,7 @@ def cpu_baseline(pw, E, threads: int, budget_s: float) -> dict:
     return out
 
 
-STAGES = ("rform", "nearpole", "asym", "ksolve", "somega")
+STAGES = ("rform", "nearpole", "asym", "ksolve", "somega", "prop")
 
 
 def drain_prof(ctx):
@@ -256,7 +256,57 @@ def config_measure(ctx) -> dict:
     # channels sharing 150 targets), wave order and the permuted (J pi, E) order
     pws, E = synth.config_imbalance()
     out["imbalance"] = imbalance_measure(ctx, pws, E)
+    out["coupled"] = coupled_measure(ctx)
     return out
+
+
+def coupled_measure(ctx) -> dict:
+    """The coupled workload (100 channels with dipole and quadrupole potentials,
+    1000 energies, Numerov propagation from r1 = 30 to a = 12 on 3201 points):
+    points/s of rm_run and the propagation stage against the FP64 MFMA peak.
+    The propagation's model flops per energy are those of its two coupling
+    products per step, (npts - 1) * 2 * 2 n^2 m lamax with m = n + n_o solution
+    columns (the series W + P W + P^2 W and U Y = U W + U P W)."""
+    import torch
+
+    from paper_1909_07321_amd import rm, synth
+
+    pw, cp, E = synth.config_coupled()
+    pid = ctx.pw_upload(pw, cp)
+    ctx.set_propagation(cp["npts"], cp["stab"])
+    Ed = torch.tensor(E, dtype=torch.float64, device="cuda")
+    om = torch.empty((E.size, pw.ntarget, pw.ntarget), dtype=torch.float64, device="cuda")
+    st = torch.empty(E.size, dtype=torch.int32, device="cuda")
+    ctx.run(pid, Ed, prec=rm.FP64, want_K=False, out=(om, None, st))  # warm-up: workspace, graphs
+    torch.cuda.synchronize()
+    drain_prof(ctx)
+    ctx.prof_enable(True)
+    t1 = time.perf_counter()
+    ctx.run(pid, Ed, prec=rm.FP64, want_K=False, out=(om, None, st))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    ctx.prof_enable(False)
+    stages = drain_prof(ctx)
+    n, lam = pw.nchan, cp["cf"].shape[0]
+    m = n + (E[:, None] - pw.e_thr[None, :] > 0).sum(axis=1)  # solution columns per energy
+    flops = float(((cp["npts"] - 1) * 2 * 2 * n * n * lam * m).sum())
+    pr_ms = stages["prop"][0]
+    achieved = flops / (pr_ms * 1e-3) / 1e12
+    flagged = int((st.cpu().numpy() != 0).sum())
+    ctx.pw_release(pid)
+    ctx.set_propagation()
+    res = dict(points_per_s=E.size / dt, seconds=dt, flagged_energies=flagged,
+               stage_ms={k: v[0] for k, v in stages.items()},
+               roofline=dict(bound="mfma", achieved=achieved, peak=PEAK["f64"], unit="TFLOP/s",
+                             frac=achieved / PEAK["f64"], kernel="propagation stage (k_prop_start, k_numerov, "
+                             "k_prop_stab)", model_flops=flops),
+               workload=f"one coupled wave, {n} channels, lamax {lam}, {pw.npole} poles, {E.size} energies in "
+                        f"[{E[0]}, {E[-1]}] Ry, Numerov from r1 = {cp['r1']} to a = {pw.a} on {cp['npts']} "
+                        f"points, recombination every {cp['stab']} steps, FP64")
+    log(f"coupled: {res['points_per_s']:.0f} points/s over {dt:.2f}s; propagation {pr_ms:.1f} ms "
+        f"({achieved:.2f} TFLOP/s model, {100 * achieved / PEAK['f64']:.1f}% of the FP64 peak); stages "
+        + ", ".join(f"{k}={v:.1f}ms" for k, v in res["stage_ms"].items()))
+    return res
 
 
 def imbalance_measure(ctx, pws, E) -> dict:
@@ -335,6 +385,8 @@ def main() -> int:
                     help="skip the 200-channel and 64-wave batch throughput measurements")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default R tile shapes instead of running the tile autotuner first")
+    ap.add_argument("--coupled-only", action="store_true",
+                    help="run only the coupled-wave (Numerov propagation) measurement and print its JSON block")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a 1 GiB read + 1 GiB write kernel (HBM counter calibration under rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -359,6 +411,12 @@ def main() -> int:
         torch.cuda.synchronize()
         log("copy probe: 1 GiB read + 1 GiB write elementwise kernel done")
         del src, dst
+
+    if args.coupled_only:
+        ctx = rm.Context(0)
+        print(json.dumps({"coupled": coupled_measure(ctx)}), flush=True)
+        ctx.close()
+        return 0
 
     t0 = time.time()
     pw, E = synth.config4(args.nenergy)

@@ -15,7 +15,9 @@
 // where T = D - (h^2/6) U with D = diag(1 - (h^2/12) Q_diag), so that
 // Y = (1 + P + P^2) D^-1 Z with P = (h^2/6) D^-1 U: the neglected P^3 is below
 // 1e-18 for the multipole strengths and steps of these grids (|h^2 U / 6| ~
-// 1e-7).  Every `stab` steps the columns are recombined (closed rows of the
+// 1e-7).  In the recurrence U Y is taken as U W + U P W (W = D^-1 Z), whose
+// products the series already forms: the dropped U P^2 W is O(h^4 U^3) and
+// enters Z_{k-1} with the factor 10 h^2/12.  Every `stab` steps the columns are recombined (closed rows of the
 // newest Z made the identity on the closed columns and zero elsewhere), which
 // adds decaying solutions to the columns and leaves K unchanged.  At r0 the
 // derivative is [(2 Z_1 - Y_1) - (2 Z_-1 - Y_-1)] / (2h).
@@ -165,9 +167,10 @@ __global__ __launch_bounds__(PROP_MAXN) void k_prop_start(const DevPW *__restric
 }
 
 // Steps s = s0 .. s1 of the recurrence (step s takes Z_k, k = npts-1-s, to
-// Z_{k-1}) for one 64-column panel per item.  Four waves hold the panel's
-// 64 NRB rows in the MFMA accumulator layout: each wave a 32 x 32 block of
-// every 64-row block, 16 NRB values per thread.  The coupling products go
+// Z_{k-1}) for one 64-column panel per item: two coupling products per step
+// (U W and U P W).  Four waves hold the panel's 64 NRB rows in the MFMA
+// accumulator layout: each wave a 32 x 32 block of every 64-row block, 16 NRB
+// values per thread.  The coupling products go
 // through LDS as U X = sum_lam A_lam (r^-(lam+1) X): X (all rows of the
 // panel) once per product, then per multipole a 64-column slab of A_lam at a
 // time, scaled by its power of r as it is staged.  The rows' D^-1 and Q_diag
@@ -292,12 +295,17 @@ __global__ __launch_bounds__(256) void k_numerov(const DevPW *__restrict__ tab, 
       }
       if (k == 0) store(pmat(pz, sZ, e, 3), Y);
       if (k >= 0) {
-        // Z_{k-1} = 2 Y + (10 h^2/12) (Q_diag Y + 2 U Y) - Z_{k+1}, over Z_{k+1}
-        couple(r, Y, acc);
+        // Z_{k-1} = 2 Y + (10 h^2/12) (Q_diag Y + 2 U Y) - Z_{k+1}, over Z_{k+1},
+        // with U Y = U W + U (P W) + U (P^2 W) taken as its first two terms: U W
+        // is recovered from this thread's P W (still in sX) as (6/h^2) D P W and
+        // U (P W) is the accumulator; the dropped term is O(h^4 U^3) and enters
+        // Z with the factor 10 h^2/12 (a relative 1e-18 on these grids)
 #pragma unroll
         for (int y = 0; y < NV; ++y) {
           const size_t o = pofs + 256 * y;
-          const double qy = sqd[par][rowof(y)] * Y[y] + 2.0 * accv(acc, y);
+          const double q = sqd[par][rowof(y)];
+          const double uw = (6.0 / h2) * (1.0 - (h2 / 12.0) * q) * sX[rowof(y)][colof(y)];
+          const double qy = q * Y[y] + 2.0 * (uw + accv(acc, y));
           Mold[o] = 2.0 * Y[y] + (10.0 * h2 / 12.0) * qy - Mold[o];
         }
       } else {

@@ -49,6 +49,13 @@ __device__ __forceinline__ void for_items(int ne, int ipe, F &&f) {
   for (long u = l; u < total; u += nl) f(x + NQ * (int)(u / ipe), (int)(u % ipe));
 }
 
+// Global-memory views of a pointer read from a table: loads through them are
+// global loads, which count only against vmcnt (a generic pointer gives flat
+// loads, which also count against lgkmcnt, so every wait for an LDS read would
+// wait for outstanding memory loads as well).
+template <typename T> using GlobalPtr = const T __attribute__((address_space(1))) *;
+template <typename T> using GlobalMut = T __attribute__((address_space(1))) *;
+
 // acc += A_slab (64 x K) * B_slab (K x 64): every wave owns a 32 x 32 quarter.
 // UNROLL bounds how many k-steps' fragments are read ahead (registers).
 template <int K, int UNROLL = K / 4>

@@ -29,6 +29,8 @@
 // are stored by 64 x 64 tiles, column panel-major, each tile in the order in
 // which the stepping kernel's threads hold it (value y of thread t at
 // 256 y + t), so that its loads and stores are whole-wave contiguous.
+#include <type_traits>
+
 #include "k_common.h"
 #include "rm.h"
 #include "rm_internal.h"
@@ -128,9 +130,9 @@ __global__ __launch_bounds__(PROP_MAXN) void k_prop_start(const DevPW *__restric
         sg = -sg;
       }
       for (int lam = 0; lam < L; ++lam) {
-        const double *A = p.cf + ((size_t)lam * npad + i) * npad;
+        const double *At = p.cft + (size_t)lam * npad * npad + i;  // A^T: row k of A^T is read across threads
         double u = 0.0;
-        for (int k = 0; k < n; ++k) u += A[k] * g[lam][k];
+        for (int k = 0; k < n; ++k) u += At[(size_t)k * npad] * g[lam][k];
         sum += 2.0 * u;
       }
     }
@@ -151,10 +153,10 @@ __global__ __launch_bounds__(PROP_MAXN) void k_prop_start(const DevPW *__restric
     if (i < n) {
       double u = 0.0;
       for (int lam = 0; lam < L; ++lam) {
-        const double *A = p.cf + ((size_t)lam * npad + i) * npad;
+        const double *At = p.cft + (size_t)lam * npad * npad + i;
         const double w = pow(r, -(double)(lam + 2));
         double s = 0.0;
-        for (int k = 0; k < n; ++k) s += A[k] * y[k];
+        for (int k = 0; k < n; ++k) s += At[(size_t)k * npad] * y[k];
         u += w * s;
       }
       const double qy = (L2 / (r * r) - 2.0 * p.z / r - eps_i) * yi + 2.0 * u;
@@ -168,40 +170,44 @@ __global__ __launch_bounds__(PROP_MAXN) void k_prop_start(const DevPW *__restric
 
 // Steps s = s0 .. s1 of the recurrence (step s takes Z_k, k = npts-1-s, to
 // Z_{k-1}) for one 64-column panel per item: two coupling products per step
-// (U W and U P W).  Four waves hold the panel's 64 NRB rows in the MFMA
-// accumulator layout: each wave a 32 x 32 block of every 64-row block, 16 NRB
-// values per thread.  The coupling products go
-// through LDS as U X = sum_lam A_lam (r^-(lam+1) X): X (all rows of the
-// panel) once per product, then per multipole a 64-column slab of A_lam at a
-// time, scaled by its power of r as it is staged.  The rows' D^-1 and Q_diag
-// of the step sit in LDS (two copies, alternating with the step's parity).
-template <int NRB>
-__global__ __launch_bounds__(256) void k_numerov(const DevPW *__restrict__ tab, const int *__restrict__ pwi,
-                                                 const double *__restrict__ E, const int *__restrict__ nopen,
-                                                 double *__restrict__ pz, long zrb, long sZ, int npts, int s0, int s1,
-                                                 int npanel, int ne) {
-  constexpr int ROWS = NRB * TILE, NV = 16 * NRB;
+// (U W and U P W).  The workgroup has 4 waves per 64-row block of the panel
+// (NRB blocks); each wave holds a 32 x 32 block in the MFMA accumulator
+// layout, 16 values per thread.  A coupling product stages X (all rows of the
+// panel) in LDS once and reads U's MFMA operands straight from the
+// fragment-major multipole matrices (L2-resident, shared by every energy of
+// the wave), combining them with the step's powers of r in registers; the
+// operands of k-step q + 2 (q + 1 for LB = 8) are requested before the MFMAs
+// of k-step q.  The
+// rows' D^-1 and Q_diag of the step sit in LDS (two copies, alternating with
+// the step's parity).  LB >= the largest lamax of the launch's waves (a
+// multipole count bucket: 2, 4 or 8).
+template <int NRB, int LB>
+__global__ __launch_bounds__(256 * NRB) void k_numerov(const DevPW *__restrict__ tab, const int *__restrict__ pwi,
+                                                       const double *__restrict__ E, const int *__restrict__ nopen,
+                                                       double *__restrict__ pz, long zrb, long sZ, int npts, int s0,
+                                                       int s1, int npanel, int ne) {
+  constexpr int ROWS = NRB * TILE;
   __shared__ double sX[ROWS][PB];
-  __shared__ double sU[ROWS][Pitch<TILE>::A];
   __shared__ double sdi[2][ROWS], sqd[2][ROWS];
   // The lane indices are re-derived at every step from an opaque copy of the
   // thread index, so that the compiler recomputes the few address operations
   // of a step instead of holding every LDS and global address of the step in
-  // registers across the loop (which it cannot afford at 32 values a thread).
-  int t = threadIdx.x, wr = 0, wc = 0, kk = 0, ii = 0;
+  // registers across the loop.
+  int t = threadIdx.x, rb = 0, wr = 0, wc = 0, kk = 0, ii = 0;
   auto relane = [&]() {
     int tq = threadIdx.x;
     asm volatile("" : "+v"(tq));
     t = tq;
-    wr = tq >> 7;
+    rb = tq >> 8;
+    wr = (tq >> 7) & 1;
     wc = (tq >> 6) & 1;
     kk = (tq >> 4) & 3;
     ii = tq & 15;
   };
   relane();
-  // value y = 16 rb + 4 q + v of this thread: row 64 rb + 32 wr + 16 (q>>1) + 4 v + kk,
+  // value y = 4 q + v of this thread: row 64 rb + 32 wr + 16 (q>>1) + 4 v + kk,
   // panel column 32 wc + 16 (q&1) + ii (accumulator register v of MFMA block q)
-  auto rowof = [&](int y) { return (y >> 4) * TILE + wr * 32 + ((y >> 3) & 1) * 16 + 4 * (y & 3) + kk; };
+  auto rowof = [&](int y) { return rb * TILE + wr * 32 + ((y >> 3) & 1) * 16 + 4 * (y & 3) + kk; };
   auto colof = [&](int y) { return wc * 32 + ((y >> 2) & 1) * 16 + ii; };
   for_items(ne, npanel, [&](int e, int panel) {
     const DevPW &p = tab[pwi[e]];
@@ -209,51 +215,73 @@ __global__ __launch_bounds__(256) void k_numerov(const DevPW *__restrict__ tab, 
     const int n = p.n, m = n + nopen[e];
     if (panel * TILE >= m) return;
     const double a = p.a, h = (p.r1 - p.a) / (npts - 1), h2 = h * h, Ev = E[e], z = p.z;
-    const int L = p.lamax, npad = p.npad;
-    const double *cf = p.cf;
+    const int L = p.lamax;
+    const GlobalPtr<double> cfm = (GlobalPtr<double>)p.cfm;
+    const size_t lstride = (size_t)p.npad * p.npad;  // one multipole matrix
     // this thread's row of the diagonal terms (padding rows: D = 1, Q = 0)
     const double l2t = t < n ? (double)p.l[t] * (p.l[t] + 1) : 0.0, ept = t < n ? Ev - p.ethr[t] : 0.0;
-    // this thread's values of the item's panel: value y at [256 y] (padding rows hold zero)
+    // this thread's values of the item's panel: value y at [256 y] of its row block's tile
     const size_t pbase = (size_t)panel * zrb * 4096;
-    size_t pofs = pbase + t;
-    auto load = [&](const double *M, double(&dst)[NV]) {
+    size_t pofs = pbase + (size_t)rb * 4096 + (t & 255);
+    auto load = [&](GlobalPtr<double> M, double(&dst)[16]) {
 #pragma unroll
-      for (int y = 0; y < NV; ++y) dst[y] = M[pofs + 256 * y];
+      for (int y = 0; y < 16; ++y) dst[y] = M[pofs + 256 * y];
     };
-    auto store = [&](double *M, const double(&src)[NV]) {
+    auto store = [&](GlobalMut<double> M, const double(&src)[16]) {
 #pragma unroll
-      for (int y = 0; y < NV; ++y) M[pofs + 256 * y] = src[y];
+      for (int y = 0; y < 16; ++y) M[pofs + 256 * y] = src[y];
     };
-    // acc = U(r) X for the X this thread holds (all rows of the panel)
-    // (stage = false: sX already holds X)
-    auto couple = [&](double r, const double(&X)[NV], d4(&acc)[NRB][4], bool stage = true) {
-      __syncthreads();  // the previous product has finished reading sX and sU
+    // acc = U(r) X for the X the threads hold (all rows of the panel), with
+    // U's MFMA operands combined from the multipole matrices in registers:
+    // a = sum_lam w_lam A_lam.  stage = false: sX already holds X.
+    auto couple = [&](const double(&w)[LB], const double(&X)[16], d4(&acc)[4], bool stage = true) {
+      __syncthreads();  // the previous product has finished reading sX
       if (stage) {
 #pragma unroll
-        for (int y = 0; y < NV; ++y) sX[rowof(y)][colof(y)] = X[y];
+        for (int y = 0; y < 16; ++y) sX[rowof(y)][colof(y)] = X[y];
       }
 #pragma unroll
-      for (int rb = 0; rb < NRB; ++rb)
+      for (int q = 0; q < 4; ++q) acc[q] = d4{0, 0, 0, 0};
+      __syncthreads();
+      // this wave's operands: row block rb, 32-row half wr, one 64-lane fragment per k-step
+      const GlobalPtr<double> Ab = cfm + (size_t)rb * NRB * 4096 + (size_t)wr * 128 + (t & 63);
+      constexpr int NF = LB * 2, RING = LB >= 8 ? 2 : 3;  // k-steps of operands in registers
+      double fr[RING][NF];
+      auto fetch = [&](int kb, int kq, double(&d)[NF]) {
+        const GlobalPtr<double> f = Ab + ((size_t)kb * 16 + kq) * 256;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[rb][q] = d4{0, 0, 0, 0};
-      double wl = 1.0 / (r * r);  // r^-(lam+1) of multipole lam = 1, 2, ...
-      for (int lam = 0; lam < L; ++lam, wl /= r) {
-        const double *A = cf + (size_t)lam * npad * npad;
-        for (int kb = 0; kb < NRB; ++kb) {
-          if (lam | kb) __syncthreads();
-          // thread t stages column t % 64 of rows t / 64 + 4 j
-          const double *src = A + (size_t)(t >> 6) * npad + kb * TILE + (t & 63);
-#pragma unroll 4
-          for (int j = 0; j < ROWS / 4; ++j) sU[(t >> 6) + 4 * j][t & 63] = wl * src[(size_t)4 * j * npad];
-          __syncthreads();
+        for (int lam = 0; lam < LB; ++lam) {
+          // past the wave's own L the last matrix is read again (weight 0)
+          const size_t o = (size_t)(lam < L ? lam : L - 1) * lstride;
+          d[2 * lam] = f[o];
+          d[2 * lam + 1] = f[o + 64];
+        }
+      };
+#pragma unroll 1
+      for (int kb = 0; kb < NRB; ++kb) {
 #pragma unroll
-          for (int rb = 0; rb < NRB; ++rb) mfma_slab<TILE, 4>(sU + rb * TILE, sX + kb * TILE, acc[rb], wr, wc, kk, ii);
+        for (int kq = 0; kq < RING - 1; ++kq) fetch(kb, kq, fr[kq]);
+#pragma unroll
+        for (int kq = 0; kq < 16; ++kq) {
+          if (kq + RING - 1 < 16) fetch(kb, kq + RING - 1, fr[(kq + RING - 1) % RING]);
+          const double b0 = sX[kb * TILE + 4 * kq + kk][wc * 32 + ii], b1 = sX[kb * TILE + 4 * kq + kk][wc * 32 + 16 + ii];
+          const double(&d)[NF] = fr[kq % RING];
+          double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+          for (int lam = 0; lam < LB; ++lam) {
+            a0 += w[lam] * d[2 * lam];
+            a1 += w[lam] * d[2 * lam + 1];
+          }
+          acc[0] = mfma64(a0, b0, acc[0]);
+          acc[1] = mfma64(a0, b1, acc[1]);
+          acc[2] = mfma64(a1, b0, acc[2]);
+          acc[3] = mfma64(a1, b1, acc[3]);
         }
       }
     };
-    auto accv = [](const d4 (&acc)[NRB][4], int y) { return acc[y >> 4][(y >> 2) & 3][y & 3]; };
-    double Y[NV];
-    d4 acc[NRB][4];
+    auto accv = [](const d4(&acc)[4], int y) { return acc[y >> 2][y & 3]; };
+    double Y[16];
+    d4 acc[4];
     // step s (k = npts-1-s): Y_k = T_k^-1 Z_k, then Z_{k-1}; the extra pass
     // k = -1 after the last step gives Y_{-1} and the derivative at r0
     const int s_last = s1 == npts - 1 ? npts : s1;
@@ -261,8 +289,16 @@ __global__ __launch_bounds__(256) void k_numerov(const DevPW *__restrict__ tab, 
       const int k = npts - 1 - s, par = s & 1;
       const double r = a + k * h;
       relane();
-      pofs = pbase + t;
-      double *Mnew = pmat(pz, sZ, e, (s + 1) & 1), *Mold = pmat(pz, sZ, e, par);
+      pofs = pbase + (size_t)rb * 4096 + (t & 255);
+      const GlobalMut<double> Mnew = (GlobalMut<double>)pmat(pz, sZ, e, (s + 1) & 1),
+                              Mold = (GlobalMut<double>)pmat(pz, sZ, e, par);
+      double w[LB];  // r^-(lam+1) of multipole lam = 1, 2, ..., L; 0 past L
+      w[0] = 1.0 / (r * r);
+#pragma unroll
+      for (int lam = 1; lam < LB; ++lam) w[lam] = w[lam - 1] / r;
+#pragma unroll
+      for (int lam = 1; lam < LB; ++lam)
+        if (lam >= L) w[lam] = 0.0;
       if (t < ROWS) {
         const double q = l2t / (r * r) - 2.0 * z / r - ept;
         sqd[par][t] = t < n ? q : 0.0;
@@ -273,27 +309,27 @@ __global__ __launch_bounds__(256) void k_numerov(const DevPW *__restrict__ tab, 
       // registers carry W, then W + P W while P W is the next product's X
       load(Mnew, Y);
 #pragma unroll
-      for (int y = 0; y < NV; ++y) Y[y] *= sdi[par][rowof(y)];
-      couple(r, Y, acc);
+      for (int y = 0; y < 16; ++y) Y[y] *= sdi[par][rowof(y)];
+      couple(w, Y, acc);
       __syncthreads();  // every wave has read sX
 #pragma unroll
-      for (int y = 0; y < NV; ++y) {
+      for (int y = 0; y < 16; ++y) {
         const double pw = (h2 / 6.0) * sdi[par][rowof(y)] * accv(acc, y);
         sX[rowof(y)][colof(y)] = pw;
         Y[y] += pw;
       }
-      couple(r, Y, acc, false);
+      couple(w, Y, acc, false);
 #pragma unroll
-      for (int y = 0; y < NV; ++y) Y[y] += (h2 / 6.0) * sdi[par][rowof(y)] * accv(acc, y);
+      for (int y = 0; y < 16; ++y) Y[y] += (h2 / 6.0) * sdi[par][rowof(y)] * accv(acc, y);
       if (k == 1) {  // record 2 Z_1 - Y_1
-        double *R2 = pmat(pz, sZ, e, 2);
+        const GlobalMut<double> R2 = (GlobalMut<double>)pmat(pz, sZ, e, 2);
 #pragma unroll
-        for (int y = 0; y < NV; ++y) {
+        for (int y = 0; y < 16; ++y) {
           const size_t o = pofs + 256 * y;
           R2[o] = 2.0 * Mnew[o] - Y[y];
         }
       }
-      if (k == 0) store(pmat(pz, sZ, e, 3), Y);
+      if (k == 0) store((GlobalMut<double>)pmat(pz, sZ, e, 3), Y);
       if (k >= 0) {
         // Z_{k-1} = 2 Y + (10 h^2/12) (Q_diag Y + 2 U Y) - Z_{k+1}, over Z_{k+1},
         // with U Y = U W + U (P W) + U (P^2 W) taken as its first two terms: U W
@@ -301,7 +337,7 @@ __global__ __launch_bounds__(256) void k_numerov(const DevPW *__restrict__ tab, 
         // U (P W) is the accumulator; the dropped term is O(h^4 U^3) and enters
         // Z with the factor 10 h^2/12 (a relative 1e-18 on these grids)
 #pragma unroll
-        for (int y = 0; y < NV; ++y) {
+        for (int y = 0; y < 16; ++y) {
           const size_t o = pofs + 256 * y;
           const double q = sqd[par][rowof(y)];
           const double uw = (6.0 / h2) * (1.0 - (h2 / 12.0) * q) * sX[rowof(y)][colof(y)];
@@ -310,16 +346,16 @@ __global__ __launch_bounds__(256) void k_numerov(const DevPW *__restrict__ tab, 
         }
       } else {
         // k = -1: Mnew holds Z_{-1}; dphi = [(2 Z_1 - Y_1) - (2 Z_-1 - Y_-1)] / (2h)
-        const double *R2 = pmat(pz, sZ, e, 2);
-        double *D = pmat(pz, sZ, e, 4);
+        const GlobalPtr<double> R2 = (GlobalPtr<double>)pmat(pz, sZ, e, 2);
+        const GlobalMut<double> D = (GlobalMut<double>)pmat(pz, sZ, e, 4);
 #pragma unroll
-        for (int y = 0; y < NV; ++y) {
+        for (int y = 0; y < 16; ++y) {
           const size_t o = pofs + 256 * y;
           D[o] = (R2[o] - (2.0 * Mnew[o] - Y[y])) / (2.0 * h);
         }
       }
     }
-    __syncthreads();  // sX, sU and the row terms are reused by the next item
+    __syncthreads();  // sX and the row terms are reused by the next item
   });
 }
 
@@ -523,6 +559,40 @@ void launch_prop_gather(hipStream_t s, const Lay &L, const DevPW *tab, const int
                      out, ldo, so);
 }
 
+namespace {
+
+template <int NRB, int LB>
+void step_one(hipStream_t s, const DevPW *tab, const int *pwi, const double *E, const int *nopen,
+              double *pz, long zrb, long sZ, int npts, int s0, int s1, int npanel, int ne) {
+  hipLaunchKernelGGL((k_numerov<NRB, LB>), dim3(persist_grid(k_numerov<NRB, LB>, 256 * NRB, ne, npanel)),
+                     dim3(256 * NRB), 0, s, tab, pwi, E, nopen, pz, zrb, sZ, npts, s0, s1, npanel, ne);
+}
+
+// k_numerov with NRB row blocks for waves of up to lamc multipoles
+void step_launch(hipStream_t s, int nrb, int lamc, const DevPW *tab, const int *pwi, const double *E,
+                 const int *nopen, double *pz, long zrb, long sZ, int npts, int s0, int s1, int npanel, int ne) {
+  const int lb = lamc <= 2 ? 2 : lamc <= 4 ? 4 : 8;
+  auto go = [&](auto nrb_c, auto lb_c) {
+    step_one<decltype(nrb_c)::value, decltype(lb_c)::value>(s, tab, pwi, E, nopen, pz, zrb, sZ, npts, s0, s1, npanel,
+                                                             ne);
+  };
+  using I1 = std::integral_constant<int, 1>;
+  using I2 = std::integral_constant<int, 2>;
+  using I4 = std::integral_constant<int, 4>;
+  using I8 = std::integral_constant<int, 8>;
+  if (nrb == 1) {
+    if (lb == 2) go(I1{}, I2{});
+    else if (lb == 4) go(I1{}, I4{});
+    else go(I1{}, I8{});
+  } else {
+    if (lb == 2) go(I2{}, I2{});
+    else if (lb == 4) go(I2{}, I4{});
+    else go(I2{}, I8{});
+  }
+}
+
+}  // namespace
+
 void launch_prop(hipStream_t s, const Lay &L, int npts, int stab, const DevPW *tab, const int *pwi, const double *E,
                  const double *fg, const int *nopen, const int *openidx, const int *colpos, double *pz, int *status) {
   if (!L.npadc) return;
@@ -532,11 +602,9 @@ void launch_prop(hipStream_t s, const Lay &L, int npts, int stab, const DevPW *t
   for (int s0 = 1; s0 <= npts - 1;) {
     const int s1 = std::min(npts - 1, (s0 - 1) / stab * stab + stab);
     // every energy is stepped by the instance whose row blocks match its padded channels
-    hipLaunchKernelGGL(k_numerov<1>, dim3(persist_grid(k_numerov<1>, 256, L.ne, npanel)), dim3(256), 0, s, tab, pwi,
-                       E, nopen, pz, L.zrb, L.sZ, npts, s0, s1, npanel, L.ne);
+    step_launch(s, 1, L.lamc, tab, pwi, E, nopen, pz, L.zrb, L.sZ, npts, s0, s1, npanel, L.ne);
     if (L.npadc > TILE)
-      hipLaunchKernelGGL(k_numerov<2>, dim3(persist_grid(k_numerov<2>, 256, L.ne, npanel)), dim3(256), 0, s, tab,
-                         pwi, E, nopen, pz, L.zrb, L.sZ, npts, s0, s1, npanel, L.ne);
+      step_launch(s, 2, L.lamc, tab, pwi, E, nopen, pz, L.zrb, L.sZ, npts, s0, s1, npanel, L.ne);
     if (s1 % stab == 0 && s1 <= npts - 3)
       hipLaunchKernelGGL(k_prop_stab, dim3(L.ne), dim3(256), 0, s, tab, pwi, nopen, colpos, L.ldo, pz, L.zrb, L.sZ,
                          s1, status);

@@ -4,6 +4,7 @@
 // MFMA, plus the FP64 near-pole correction of the split-precision mode.
 #include <algorithm>
 
+#include "k_common.h"
 #include "rm.h"
 #include "rm_internal.h"
 
@@ -129,11 +130,6 @@ template <typename T> __device__ __forceinline__ const T *amplitudes(const DevPW
 template <> __device__ __forceinline__ const double *amplitudes<double>(const DevPW &p) { return p.W64; }
 template <> __device__ __forceinline__ const float *amplitudes<float>(const DevPW &p) { return p.W32; }
 
-// Global-memory view of a pointer read from a table: loads through it are
-// global loads, which count only against vmcnt (a generic pointer gives flat
-// loads, which also count against lgkmcnt, so every wait for an LDS read would
-// wait for the next stage's amplitudes as well).
-template <typename T> using GlobalPtr = const T __attribute__((address_space(1))) *;
 
 // One wave's LDS region.  The FP32 kernels keep one pole's scale factors of all
 // energies together (one wide LDS read per step serves every energy); the FP64

@@ -71,7 +71,8 @@ struct DevPW {
   // lamax = 0 for a wave without one
   int lamax = 0;
   double r1 = 0;
-  double *cf = nullptr;   // [lamax][npad][npad] multipole coefficients, zero padded
+  double *cft = nullptr;  // [lamax][npad][npad] transposed multipole coefficients, zero padded
+  double *cfm = nullptr;  // the same in MFMA-fragment order (cfm_index)
   size_t bytes = 0;
 };
 // Largest channel count of a partial wave with a coupling (the propagation
@@ -80,6 +81,16 @@ constexpr int PROP_MAXN = 128;
 // Matrices of the propagation workspace per energy: two Numerov states, the
 // record 2 Z_1 - Y_1, phi and dphi.
 constexpr int PROP_NMAT = 5;
+// Position of A_lam[i][j] (padded, nb = npad / 64 blocks) in the fragment-major
+// copy: per multipole, per (row block, column block) tile, per k-step of 4
+// columns, per 32-row half (wr) and 16-row quarter (hh), one 64-lane operand
+// with lane = 16 (j % 4) + i % 16, i.e. a wave's MFMA A-operand of one k-step
+// is 64 consecutive doubles.
+inline size_t cfm_index(int lam, int i, int j, int nb) {
+  const int rb = i / 64, kb = j / 64, ir = i % 64, jc = j % 64;
+  const int wr = ir / 32, hh = (ir / 16) % 2, kq = jc / 4, lane = 16 * (jc % 4) + ir % 16;
+  return (((((size_t)lam * nb + rb) * nb + kb) * 16 + kq) * 2 + wr) * 128 + (size_t)hh * 64 + lane;
+}
 
 // Strides of one chunk of energies.  Every per-energy block is laid out for the
 // largest partial wave in the chunk.
@@ -92,6 +103,7 @@ struct Lay {
   long ldo = 0;                 // per-channel arrays (fg has 4 per channel): nmax
   long sOm = 0;                 // Omega: ntmax * ntmax per energy
   int npadc = 0;                // largest npad of the chunk's coupled waves (0: none)
+  int lamc = 0;                 // largest multipole order of the chunk's coupled waves
   long zrb = 0, sZ = 0;         // propagation matrices (tiled): zrb = npadc / 64 row blocks, sZ = 2 npadc^2
 };
 

@@ -343,7 +343,10 @@ Lay make_layout(const std::vector<const DevPW *> &slots, int ne) {
     L.npadmax = std::max(L.npadmax, p->npad);
     L.Mpadmax = std::max(L.Mpadmax, p->Mpad);
     L.ntmax = std::max(L.ntmax, p->nt);
-    if (p->lamax) L.npadc = std::max(L.npadc, p->npad);
+    if (p->lamax) {
+      L.npadc = std::max(L.npadc, p->npad);
+      L.lamc = std::max(L.lamc, p->lamax);
+    }
   }
   L.zrb = L.npadc / TILE;
   L.sZ = 2L * L.npadc * L.npadc;
@@ -621,7 +624,7 @@ std::string chunk_key(rm_ctx *ctx, const Plan &P, const Work &w, const rm_opts &
   auto add = [&](const auto &v) { k.append(reinterpret_cast<const char *>(&v), sizeof v); };
   const Lay &L = P.L;
   for (long v : {(long)L.ne, (long)L.nmax, (long)L.npadmax, (long)L.Mpadmax, (long)L.ntmax, L.ldD, L.ldaug, L.roff,
-                 L.sA, L.ldk, L.sK, L.ldo, L.sOm, (long)L.npadc, L.zrb, L.sZ, (long)ctx->prop_npts.load(),
+                 L.sA, L.ldk, L.sK, L.ldo, L.sOm, (long)L.npadc, (long)L.lamc, L.zrb, L.sZ, (long)ctx->prop_npts.load(),
                  (long)ctx->prop_stab.load()})
     add(v);
   for (const void *p : {(const void *)w.E, (const void *)w.pwi, (const void *)w.tab, (const void *)w.tasks,
@@ -1125,7 +1128,7 @@ void worker_main(rm_ctx *ctx, Slot *slot) {
 }
 
 void free_pw(DevPW &p) {
-  void *ptrs[] = {p.W64, p.W32, p.Ek, p.ethr, p.l, p.target, p.tptr, p.tch, p.cf};
+  void *ptrs[] = {p.W64, p.W32, p.Ek, p.ethr, p.l, p.target, p.tptr, p.tch, p.cft, p.cfm};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
 }
@@ -1369,7 +1372,7 @@ rm_status rm_pw_upload_coupled_impl(rm_ctx *ctx, const rm_pw_desc *d, int32_t la
       ctx->err = "channel target or l out of range";
       return RM_E_ARG;
     }
-  const size_t cfbytes = (size_t)lamax * round_up(d->nchan, TILE) * round_up(d->nchan, TILE) * 8;
+  const size_t cfbytes = (size_t)lamax * round_up(d->nchan, TILE) * round_up(d->nchan, TILE) * 16;
   const size_t bytes = rm_pw_footprint(d->nchan, d->npole) + cfbytes;
   {
     std::lock_guard<std::mutex> g(ctx->mu);
@@ -1424,13 +1427,21 @@ rm_status rm_pw_upload_coupled_impl(rm_ctx *ctx, const rm_pw_desc *d, int32_t la
   HIPCHK(hipMemcpy(p.tptr, tptr.data(), (p.nt + 1) * 4, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(p.tch, tch.data(), p.n * 4, hipMemcpyHostToDevice));
   if (lamax) {
-    std::vector<double> A((size_t)lamax * p.npad * p.npad, 0.0);
+    // transposed and fragment-major copies, zero padded
+    const size_t sz = (size_t)lamax * p.npad * p.npad;
+    std::vector<double> At(sz, 0.0), Am(sz, 0.0);
+    const int nb = p.npad / TILE;
     for (int lam = 0; lam < lamax; ++lam)
       for (int i = 0; i < p.n; ++i)
-        for (int j = 0; j < p.n; ++j)
-          A[((size_t)lam * p.npad + i) * p.npad + j] = cf[((size_t)lam * p.n + i) * p.n + j];
-    HIPCHK(hipMalloc(&p.cf, A.size() * 8));
-    HIPCHK(hipMemcpy(p.cf, A.data(), A.size() * 8, hipMemcpyHostToDevice));
+        for (int j = 0; j < p.n; ++j) {
+          const double v = cf[((size_t)lam * p.n + i) * p.n + j];
+          At[((size_t)lam * p.npad + j) * p.npad + i] = v;
+          Am[cfm_index(lam, i, j, nb)] = v;
+        }
+    HIPCHK(hipMalloc(&p.cft, sz * 8));
+    HIPCHK(hipMalloc(&p.cfm, sz * 8));
+    HIPCHK(hipMemcpy(p.cft, At.data(), sz * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(p.cfm, Am.data(), sz * 8, hipMemcpyHostToDevice));
     p.lamax = lamax;
     p.r1 = r1;
   }

@@ -67,6 +67,8 @@ MUTANTS = {
     "coupled_match_rhs": ("B[(size_t)i * no + j] = acc - (ld)phi[(size_t)i * ld2 + n + j];",
                           "B[(size_t)i * no + j] = acc + (ld)phi[(size_t)i * ld2 + n + j];",
                           "test_oracle_coupling.py::test_uncoupled_K_converges_to_plain_matching"),
+    "stabilise_last_step": ("s <= N - 3 && stabilise(", "s <= N - 2 && stabilise(",
+                            "test_oracle_coupling.py::test_recombination_at_last_allowed_step"),
 }
 
 

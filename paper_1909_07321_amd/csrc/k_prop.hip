@@ -25,7 +25,7 @@
 // Per energy the workspace holds five n x 2n matrices (rows and columns padded
 // to multiples of 64): the two Numerov states (the newer one after step s is
 // matrix s % 2), the record 2 Z_1 - Y_1, and the results Y_0 (phi) and Y'_0
-// (dphi), the last two also serving as scratch of the recombination.  They
+// (dphi); until the last recombination the three serve as its scratch.  They
 // are stored by 64 x 64 tiles, column panel-major, each tile in the order in
 // which the stepping kernel's threads hold it (value y of thread t at
 // 256 y + t), so that its loads and stores are whole-wave contiguous.
@@ -360,14 +360,18 @@ __global__ __launch_bounds__(256 * NRB) void k_numerov(const DevPW *__restrict__
 }
 
 // Recombination of the two Numerov states after step s (the newer is matrix
-// s % 2): with G the closed rows of the newer state's closed columns and
-// alpha its closed rows of the other columns, every state's closed columns
-// become E G^-1 and its other columns X - (E G^-1) alpha.  One workgroup per
-// energy; G^-1 by Gauss-Jordan with partial pivoting in LDS.
-__global__ __launch_bounds__(256) void k_prop_stab(const DevPW *__restrict__ tab, const int *__restrict__ pwi,
-                                                   const int *__restrict__ nopen, const int *__restrict__ colpos,
-                                                   long ldo, double *__restrict__ pz, long zrb, long sZ, int s,
-                                                   int *__restrict__ status) {
+// s % 2): with E the closed columns of a state, G the closed rows of the newer
+// state's closed columns and alpha its closed rows of the other columns, every
+// state's closed columns become E' = E G^-1 and its other columns X - E' alpha.
+// Three launches: k_prop_stab_inv forms G^-1 (Gauss-Jordan with partial
+// pivoting in LDS, one workgroup per energy) and writes [G^-1 | alpha] on the
+// first n_c rows of matrix 4; k_prop_stab_mm<1> forms E' of both states into
+// matrices 2 and 3; k_prop_stab_mm<2> writes both states' new columns.  The
+// products run on FP64 MFMA over 64 x 64 tiles of the tiled layout.
+__global__ __launch_bounds__(256) void k_prop_stab_inv(const DevPW *__restrict__ tab, const int *__restrict__ pwi,
+                                                       const int *__restrict__ nopen, const int *__restrict__ colpos,
+                                                       long ldo, double *__restrict__ pz, long zrb, long sZ, int s,
+                                                       int *__restrict__ status) {
   const int e = blockIdx.x;
   const DevPW &p = tab[pwi[e]];
   if (p.lamax == 0) return;
@@ -380,12 +384,12 @@ __global__ __launch_bounds__(256) void k_prop_stab(const DevPW *__restrict__ tab
   for (int i = t; i < n; i += 256)
     if (cp[i] < nc) cr[cp[i]] = i;
   __syncthreads();
-  double *Nw = pmat(pz, sZ, e, s & 1), *Od = pmat(pz, sZ, e, (s + 1) & 1);
-  double *alpha = pmat(pz, sZ, e, 3), *T = pmat(pz, sZ, e, 4);
+  const double *Nw = pmat(pz, sZ, e, s & 1);
+  double *H = pmat(pz, sZ, e, 4);
   for (int idx = t; idx < nc * nc; idx += 256) G[idx / nc][idx % nc] = Nw[zoff(cr[idx / nc], idx % nc, zrb)];
   for (int idx = t; idx < nc * (m - nc); idx += 256) {
     const int r = idx / (m - nc), j = nc + idx % (m - nc);
-    alpha[zoff(r, j, zrb)] = Nw[zoff(cr[r], j, zrb)];
+    H[zoff(r, j, zrb)] = Nw[zoff(cr[r], j, zrb)];
   }
   __syncthreads();
   // G <- G^-1 in place (row interchanges undone as column swaps at the end)
@@ -439,25 +443,76 @@ __global__ __launch_bounds__(256) void k_prop_stab(const DevPW *__restrict__ tab
       }
     __syncthreads();
   }
-  for (int sidx = 0; sidx < 2; ++sidx) {
-    double *M = sidx == 0 ? Nw : Od;
-    for (int idx = t; idx < n * nc; idx += 256) {
-      const int i = idx / nc, b = idx % nc;
-      double acc = 0.0;
-      for (int q = 0; q < nc; ++q) acc += M[zoff(i, q, zrb)] * G[q][b];
-      T[zoff(i, b, zrb)] = acc;
+  for (int idx = t; idx < nc * nc; idx += 256) H[zoff(idx / nc, idx % nc, zrb)] = G[idx / nc][idx % nc];
+}
+
+// One 64 x 64 output tile per item (energy, state, row block, column panel):
+//   PH = 1: E'(rb, c) = sum_kb E(rb, kb) G^-1(kb, c) for the closed columns, into
+//           matrix 2 (newer state) or 3 (older);
+//   PH = 2: state(rb, c) = E' where j < n_c, X - E' alpha where j >= n_c.
+// A tile of the tiled layout is one contiguous block of 4096 doubles, staged
+// into LDS with whole-wave loads; the output is stored in the MFMA
+// accumulator layout, which is the tile's own order.
+template <int PH>
+__global__ __launch_bounds__(256) void k_prop_stab_mm(const DevPW *__restrict__ tab, const int *__restrict__ pwi,
+                                                      const int *__restrict__ nopen, double *__restrict__ pz,
+                                                      long zrb, long sZ, int s, int npanel, int ne) {
+  __shared__ double sA[TILE][Pitch<TILE>::A];
+  __shared__ double sB[TILE][PB];
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int kk = lane >> 4, ii = lane & 15;
+  // element of this thread's value y in a tile (the layout of zoff)
+  auto tr = [&](int y) { return wr * 32 + ((y >> 3) & 1) * 16 + 4 * (y & 3) + kk; };
+  auto tc = [&](int y) { return wc * 32 + ((y >> 2) & 1) * 16 + ii; };
+  const int nrb = (int)zrb;
+  for_items(ne, 2 * nrb * npanel, [&](int e, int it) {
+    const DevPW &p = tab[pwi[e]];
+    if (p.lamax == 0) return;
+    const int n = p.n, no = nopen[e], nc = n - no, m = n + no;
+    const int st = it % 2, rb = (it / 2) % nrb, pc = it / (2 * nrb);
+    if (nc == 0 || rb * TILE >= n) return;
+    const int ncol = PH == 1 ? nc : m;  // output columns
+    if (pc * TILE >= ncol) return;
+    double *S = pmat(pz, sZ, e, st == 0 ? (s & 1) : ((s + 1) & 1));   // the state
+    double *Ep = pmat(pz, sZ, e, 2 + st);                              // its E'
+    const double *H = pmat(pz, sZ, e, 4);                              // [G^-1 | alpha]
+    const double *Asrc = PH == 1 ? S : Ep;
+    auto tile = [&](auto *M, int r, int c) { return M + (((size_t)c * zrb + r) * 16) * 256; };
+    d4 acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = d4{0, 0, 0, 0};
+    for (int kb = 0; kb * TILE < nc; ++kb) {
+      __syncthreads();
+      const double *At = tile(Asrc, rb, kb), *Bt = tile(H, kb, pc);
+#pragma unroll
+      for (int y = 0; y < 16; ++y) {
+        const int i = tr(y), j = tc(y);
+        // A: rows of the state, its closed columns k < n_c
+        sA[i][j] = kb * TILE + j < nc ? At[y * 256 + t] : 0.0;
+        // B: G^-1 (PH 1, columns < n_c) or alpha (PH 2, columns in [n_c, m)), closed rows only
+        const int jg = pc * TILE + j;
+        const bool bok = kb * TILE + i < nc && (PH == 1 ? jg < nc : (jg >= nc && jg < m));
+        sB[i][j] = bok ? Bt[y * 256 + t] : 0.0;
+      }
+      __syncthreads();
+      mfma_slab<TILE>(sA, sB, acc, wr, wc, kk, ii);
     }
-    __syncthreads();
-    for (int idx = t; idx < n * nc; idx += 256) M[zoff(idx / nc, idx % nc, zrb)] = T[zoff(idx / nc, idx % nc, zrb)];
-    __syncthreads();
-    for (int idx = t; idx < n * (m - nc); idx += 256) {
-      const int i = idx / (m - nc), j = nc + idx % (m - nc);
-      double acc = M[zoff(i, j, zrb)];
-      for (int q = 0; q < nc; ++q) acc -= M[zoff(i, q, zrb)] * alpha[zoff(q, j, zrb)];
-      M[zoff(i, j, zrb)] = acc;
+    if (PH == 1) {
+      double *O = tile(Ep, rb, pc);
+#pragma unroll
+      for (int y = 0; y < 16; ++y) O[y * 256 + t] = acc[y >> 2][y & 3];
+    } else {
+      double *O = tile(S, rb, pc);
+      const double *Et = tile(Ep, rb, pc);
+#pragma unroll
+      for (int y = 0; y < 16; ++y) {
+        const int jg = pc * TILE + tc(y);
+        O[y * 256 + t] = jg < nc ? Et[y * 256 + t] : O[y * 256 + t] - acc[y >> 2][y & 3];
+      }
     }
-    __syncthreads();
-  }
+  });
 }
 
 // Matching with the propagated matrices (eq. (match)): for each 64 x 64 tile of
@@ -605,9 +660,15 @@ void launch_prop(hipStream_t s, const Lay &L, int npts, int stab, const DevPW *t
     step_launch(s, 1, L.lamc, tab, pwi, E, nopen, pz, L.zrb, L.sZ, npts, s0, s1, npanel, L.ne);
     if (L.npadc > TILE)
       step_launch(s, 2, L.lamc, tab, pwi, E, nopen, pz, L.zrb, L.sZ, npts, s0, s1, npanel, L.ne);
-    if (s1 % stab == 0 && s1 <= npts - 3)
-      hipLaunchKernelGGL(k_prop_stab, dim3(L.ne), dim3(256), 0, s, tab, pwi, nopen, colpos, L.ldo, pz, L.zrb, L.sZ,
-                         s1, status);
+    if (s1 % stab == 0 && s1 <= npts - 3) {
+      hipLaunchKernelGGL(k_prop_stab_inv, dim3(L.ne), dim3(256), 0, s, tab, pwi, nopen, colpos, L.ldo, pz, L.zrb,
+                         L.sZ, s1, status);
+      const int items = 2 * (int)L.zrb * npanel;
+      hipLaunchKernelGGL(k_prop_stab_mm<1>, dim3(persist_grid(k_prop_stab_mm<1>, 256, L.ne, items)), dim3(256), 0, s,
+                         tab, pwi, nopen, pz, L.zrb, L.sZ, s1, npanel, L.ne);
+      hipLaunchKernelGGL(k_prop_stab_mm<2>, dim3(persist_grid(k_prop_stab_mm<2>, 256, L.ne, items)), dim3(256), 0, s,
+                         tab, pwi, nopen, pz, L.zrb, L.sZ, s1, npanel, L.ne);
+    }
     s0 = s1 + 1;
   }
 }

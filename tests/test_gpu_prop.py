@@ -242,3 +242,31 @@ def test_coupled_full_grid_sampled(ctx):
     _say(f"coupled full grid sampled: K err {errK}, Omega err {errO}, gate {g}")
     assert (errK <= g).all() and (errO <= g).all()
     ctx.pw_release(pid)
+
+
+def test_coupled_through_serving_and_sum(ctx):
+    """Coupled waves ride the serving scheduler's mixed chunks and the sum over
+    partial waves with the results of rm_run (bitwise)."""
+    from paper_1909_07321_amd import rm
+    E = np.linspace(0.3, 7.7, 48)
+    fam = synth.partial_wave_family(synth.config_seed(8) + 50, 3, 12, (1, 4), 10, z=5.0, a=12.0,
+                                    thr_range=(0.0, 6.0), pole_range=(-2.0, 60.0), avoid_energies=E, name="cpl-fam")
+    cps = [None, _cp(fam[1].nchan, 51), _cp(fam[2].nchan, 52, lamax=3)]
+    ids = [ctx.pw_upload(p, c) for p, c in zip(fam, cps)]
+    solo = [ctx.run(i, E) for i in ids]
+    tickets = [ctx.submit(i, E, want_K=True) for i in ids]
+    pending = {t for t, _ in tickets}
+    while pending:
+        for t, _ in tickets:
+            if t in pending and ctx.poll(t) is not None:
+                pending.discard(t)
+    for (t, out), ref in zip(tickets, solo):
+        assert np.array_equal(out["omega"], ref[0]) and np.array_equal(out["K"], ref[1])
+        assert np.array_equal(out["status"], ref[2])
+    om_sum, st_sum = ctx.run_sum(ids, E, prec=rm.FP64)
+    acc = np.zeros_like(solo[0][0])
+    for ref in solo:
+        acc = acc + ref[0]
+    assert (st_sum == 0).all() and np.array_equal(om_sum, acc)
+    for i in ids:
+        ctx.pw_release(i)

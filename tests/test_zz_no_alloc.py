@@ -48,6 +48,32 @@ def test_noalloc_equals_run():
         ctx.pw_release(pid)
 
 
+def test_noalloc_coupled_wave_equals_run():
+    """A coupled wave (its propagation matrices also carved from the array)."""
+    import torch
+
+    from paper_1909_07321_amd import rm
+    E = np.linspace(0.2, 7.8, 96)
+    pw = synth.make_partial_wave(synth.config_seed(8) + 60, 90, 20, z=5.0, a=12.0, thr_range=(0.0, 8.0),
+                                 pole_range=(-2.0, 60.0), avoid_energies=E, name="noalloc-cpl")
+    cp = dict(cf=synth.multipole_coefficients(synth.config_seed(8) + 60, pw.nchan), r1=30.0)
+    with rm.Context(0) as ctx:
+        ctx.set_propagation(801, 64)
+        pid = ctx.pw_upload(pw, cp)
+        for sel in (E, E[::7]):
+            _say("noalloc coupled", sel.size, "energies of", pw.nchan, "channels")
+            Ed = torch.tensor(sel, dtype=torch.float64, device="cuda")
+            om = torch.empty((sel.size, pw.ntarget, pw.ntarget), dtype=torch.float64, device="cuda")
+            K = torch.empty((sel.size, pw.nchan, pw.nchan), dtype=torch.float64, device="cuda")
+            st = torch.empty(sel.size, dtype=torch.int32, device="cuda")
+            ctx.run_noalloc(pid, Ed, (om, K, st))
+            ref = ctx.run(pid, Ed)
+            torch.cuda.synchronize()
+            assert torch.equal(st, ref[2]) and (st.cpu().numpy() == 0).all()
+            assert torch.equal(om, ref[0]) and torch.equal(K, ref[1])
+        ctx.pw_release(pid)
+
+
 def test_noalloc_refuses_oversized_wave():
     import torch
 

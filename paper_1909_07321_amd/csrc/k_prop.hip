@@ -282,6 +282,17 @@ __global__ __launch_bounds__(256 * NRB) void k_numerov(const DevPW *__restrict__
     auto accv = [](const d4(&acc)[4], int y) { return acc[y >> 2][y & 3]; };
     double Y[16];
     d4 acc[4];
+    // KEEP: the two states of this thread's values stay in registers over the
+    // segment (Zk = Z_k, Zp = Z_{k+1}), the stores keeping memory current for
+    // the recombination, the next segment and the outputs; otherwise (the
+    // 512-thread instances with more than two multipoles, whose operand ring
+    // leaves no room) they are read back each step
+    constexpr bool KEEP = NRB == 1 || LB <= 2;
+    double Zk[16], Zp[16];
+    if constexpr (KEEP) {
+      load((GlobalPtr<double>)pmat(pz, sZ, e, (s0 + 1) & 1), Zk);
+      load((GlobalPtr<double>)pmat(pz, sZ, e, s0 & 1), Zp);
+    }
     // step s (k = npts-1-s): Y_k = T_k^-1 Z_k, then Z_{k-1}; the extra pass
     // k = -1 after the last step gives Y_{-1} and the derivative at r0
     const int s_last = s1 == npts - 1 ? npts : s1;
@@ -290,8 +301,9 @@ __global__ __launch_bounds__(256 * NRB) void k_numerov(const DevPW *__restrict__
       const double r = a + k * h;
       relane();
       pofs = pbase + (size_t)rb * 4096 + (t & 255);
-      const GlobalMut<double> Mnew = (GlobalMut<double>)pmat(pz, sZ, e, (s + 1) & 1),
-                              Mold = (GlobalMut<double>)pmat(pz, sZ, e, par);
+      const GlobalMut<double> Mold = (GlobalMut<double>)pmat(pz, sZ, e, par);
+      const GlobalPtr<double> Mnew = (GlobalPtr<double>)pmat(pz, sZ, e, (s + 1) & 1);
+      if constexpr (!KEEP) load(Mnew, Zk);
       double w[LB];  // r^-(lam+1) of multipole lam = 1, 2, ..., L; 0 past L
       w[0] = 1.0 / (r * r);
 #pragma unroll
@@ -307,9 +319,8 @@ __global__ __launch_bounds__(256 * NRB) void k_numerov(const DevPW *__restrict__
       __syncthreads();
       // Y = W + P W + P^2 W with W = D^-1 Z and P = (h^2/6) D^-1 U: the
       // registers carry W, then W + P W while P W is the next product's X
-      load(Mnew, Y);
 #pragma unroll
-      for (int y = 0; y < 16; ++y) Y[y] *= sdi[par][rowof(y)];
+      for (int y = 0; y < 16; ++y) Y[y] = Zk[y] * sdi[par][rowof(y)];
       couple(w, Y, acc);
       __syncthreads();  // every wave has read sX
 #pragma unroll
@@ -324,10 +335,7 @@ __global__ __launch_bounds__(256 * NRB) void k_numerov(const DevPW *__restrict__
       if (k == 1) {  // record 2 Z_1 - Y_1
         const GlobalMut<double> R2 = (GlobalMut<double>)pmat(pz, sZ, e, 2);
 #pragma unroll
-        for (int y = 0; y < 16; ++y) {
-          const size_t o = pofs + 256 * y;
-          R2[o] = 2.0 * Mnew[o] - Y[y];
-        }
+        for (int y = 0; y < 16; ++y) R2[pofs + 256 * y] = 2.0 * (KEEP ? Zk[y] : Mnew[pofs + 256 * y]) - Y[y];
       }
       if (k == 0) store((GlobalMut<double>)pmat(pz, sZ, e, 3), Y);
       if (k >= 0) {
@@ -336,22 +344,27 @@ __global__ __launch_bounds__(256 * NRB) void k_numerov(const DevPW *__restrict__
         // is recovered from this thread's P W (still in sX) as (6/h^2) D P W and
         // U (P W) is the accumulator; the dropped term is O(h^4 U^3) and enters
         // Z with the factor 10 h^2/12 (a relative 1e-18 on these grids)
+        if constexpr (!KEEP) load(Mold, Zp);
 #pragma unroll
         for (int y = 0; y < 16; ++y) {
-          const size_t o = pofs + 256 * y;
           const double q = sqd[par][rowof(y)];
           const double uw = (6.0 / h2) * (1.0 - (h2 / 12.0) * q) * sX[rowof(y)][colof(y)];
           const double qy = q * Y[y] + 2.0 * (uw + accv(acc, y));
-          Mold[o] = 2.0 * Y[y] + (10.0 * h2 / 12.0) * qy - Mold[o];
+          const double zn = 2.0 * Y[y] + (10.0 * h2 / 12.0) * qy - Zp[y];
+          Mold[pofs + 256 * y] = zn;
+          if constexpr (KEEP) {
+            Zp[y] = Zk[y];
+            Zk[y] = zn;
+          }
         }
       } else {
-        // k = -1: Mnew holds Z_{-1}; dphi = [(2 Z_1 - Y_1) - (2 Z_-1 - Y_-1)] / (2h)
+        // k = -1: Zk is Z_{-1}; dphi = [(2 Z_1 - Y_1) - (2 Z_-1 - Y_-1)] / (2h)
         const GlobalPtr<double> R2 = (GlobalPtr<double>)pmat(pz, sZ, e, 2);
         const GlobalMut<double> D = (GlobalMut<double>)pmat(pz, sZ, e, 4);
 #pragma unroll
         for (int y = 0; y < 16; ++y) {
           const size_t o = pofs + 256 * y;
-          D[o] = (R2[o] - (2.0 * Mnew[o] - Y[y])) / (2.0 * h);
+          D[o] = (R2[o] - (2.0 * (KEEP ? Zk[y] : Mnew[o]) - Y[y])) / (2.0 * h);
         }
       }
     }

@@ -75,12 +75,14 @@ def _cp(n, seed, lamax=2, scale=0.5, r1=30.0):
 E8 = np.array([0.013, 0.61, 1.37, 2.9, 4.05, 5.5, 6.8, 7.93])
 
 
-@pytest.mark.parametrize("n", [7, 40, 64, 65, 100, 128])
-def test_propagate_vs_oracle(ctx, n):
-    E = E8 if n in (40, 100) else E8[[1, 4, 7]]
-    pw, cp = _wave(n, n, E), _cp(n, n)
+@pytest.mark.parametrize("n,lamax", [(7, 2), (40, 2), (64, 2), (65, 2), (100, 2), (128, 2), (100, 3), (50, 6)])
+def test_propagate_vs_oracle(ctx, n, lamax):
+    """Every instance of the stepping kernel: up to 64 and up to 128 padded
+    channels, multipole buckets of 2, 4 and 8."""
+    E = E8 if (n in (40, 100) and lamax == 2) else E8[[1, 4, 7]]
+    pw, cp = _wave(n, n, E), _cp(n, n, lamax=lamax)
     pid = ctx.pw_upload(pw, cp)
-    _say(f"propagate n={n} energies={E.size}")
+    _say(f"propagate n={n} lamax={lamax} energies={E.size}")
     phi, dphi, st = ctx.propagate(pid, E)
     phio, dphio, op, no, sto = oracle.Oracle(pw, nthreads=_threads()).propagate(E, cp)
     assert (st == 0).all() and (sto == 0).all()

@@ -23,7 +23,8 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"f32": 157.3, "f64": 78.6}  # MI355X dense MFMA TFLOP/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_rform_c4_traffic.md")
-RFORM_SOURCES = [os.path.join(ROOT, "paper_1909_07321_amd", "csrc", f) for f in ("k_rform.hip", "rm_internal.h")]
+RFORM_SOURCES = [os.path.join(ROOT, "paper_1909_07321_amd", "csrc", f)
+                 for f in ("k_rform.hip", "k_common.h", "rm_internal.h")]
 
 
 def log(*a):

@@ -173,6 +173,17 @@ def cpu_baseline(pw, E, threads: int, budget_s: float) -> dict:
                       f"budget) at grid indices {idx}, full path R -> asymptotics -> K -> Omega in long double, "
                       f"{dt:.1f} s on {threads} threads ({cpu_model()})")
     log(f"cpu oracle: {out['value']:.4f} points/s on {threads} threads, {len(idx)} energies in {dt:.1f} s")
+    # the 200-channel workload: 32 evenly spaced energies of its 2000
+    from paper_1909_07321_amd import synth
+    pw2, E2 = synth.config2()
+    sel = E2[np.linspace(0, E2.size - 1, 32).round().astype(int)]
+    o2 = oracle.Oracle(pw2, nthreads=threads)
+    t4 = time.perf_counter()
+    o2.run(sel, want_K=False)
+    dt2 = time.perf_counter() - t4
+    out["c2"] = dict(value=sel.size / dt2, unit="energy points/s", cores=threads,
+                     sample=f"32 evenly spaced energies of the 200-channel workload's 2000, {dt2:.1f} s")
+    log(f"cpu oracle, 200 channels: {sel.size / dt2:.2f} points/s on {threads} threads")
     return out
 
 
@@ -469,6 +480,8 @@ def main() -> int:
             stage_ms_per_step={s: v[0] / args.steps for s, v in stages.items()},
             roofline=dict(bound="mfma", achieved=achieved, peak=PEAK[dt], unit="TFLOP/s",
                           frac=(achieved / PEAK[dt]) if achieved else None, traffic=measured_traffic(kname),
+                          traffic_GBps=(measured_traffic(kname) / (rf_ms / rf_n * 1e-3) / 1e9
+                                        if measured_traffic(kname) and rf_n else None),
                           kernel=kname,
                           launches=rf_n, avg_launch_ms=rf_ms / max(rf_n, 1),
                           flops_per_launch=flops_R * rf_e / max(rf_n, 1)))

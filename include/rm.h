@@ -131,11 +131,15 @@ typedef struct {
    poles. */
 rm_status rm_pw_upload(rm_ctx *ctx, const rm_pw_desc *desc, int32_t *pw_id);
 rm_status rm_pw_release(rm_ctx *ctx, int32_t pw_id);
-/* Device bytes a partial wave of this shape occupies when resident. */
+/* Device bytes a partial wave of this shape occupies when resident (a wave
+   uploaded with rm_pw_upload_coupled adds 16 lamax npad^2 bytes for its
+   multipole coefficients, npad = nchan rounded up to 64). */
 size_t rm_pw_footprint(int32_t nchan, int32_t npole);
 /* Upper bound of the device workspace a chunk of ne energies of a partial wave
    of this shape needs (a chunk mixing waves needs it for its largest member);
-   0 for invalid sizes.  With rm_pw_footprint this sizes hbm_budget_bytes. */
+   0 for invalid sizes.  With rm_pw_footprint this sizes hbm_budget_bytes.  A
+   chunk holding a coupled wave adds 80 npad^2 bytes per energy (the five
+   propagation matrices of its largest coupled wave). */
 size_t rm_work_footprint(int32_t nchan, int32_t npole, int32_t ntarget, int32_t ne);
 
 /* ------------------------------------------- long-range multipole coupling */

@@ -61,6 +61,10 @@ def lib():
         _lib.rmo_propagate.argtypes = [vp, vp, vp, i32, d, vp, vp, vp, vp, vp, i32]
         _lib.rmo_solve_K_coupled.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, i32]
         _lib.rmo_run_coupled.argtypes = [vp, vp, vp, i32, d, vp, vp, vp, vp, i32]
+        _lib.rmo_unphysical_K.argtypes = [vp, vp, i32, d, d, vp, vp, vp, i32]
+        _lib.rmo_mqdt_eliminate.argtypes = [vp, vp, i32, d, vp, vp, vp, vp, i32]
+        _lib.rmo_mqdt_run.argtypes = [vp, vp, i32, i32, d, d, vp, vp, vp, vp, i32]
+        _lib.rmo_mqdt_channel.argtypes = [d, d, d, i32, d, vp]
     return _lib
 
 
@@ -179,6 +183,43 @@ class Oracle:
             raise ValueError("invalid coupling")
         return dict(omega=om, K=K, cond=cond, status=st)
 
+    def unphysical_K(self, E, fnumin: float, thr_guard: float = 1e-10):
+        """Unphysical K over the member channels at each energy: (Ku [ne][n][n]
+        with the leading nmember x nmember block set, nmember, status)."""
+        E = np.ascontiguousarray(E, dtype=np.float64)
+        n = self.pw.nchan
+        Ku = np.empty((E.size, n, n))
+        nm = np.empty(E.size, np.int32)
+        st = np.zeros(E.size, np.int32)
+        lib().rmo_unphysical_K(self._p, _ptr(E), E.size, fnumin, thr_guard, _ptr(Ku), _ptr(nm), _ptr(st),
+                               self.nthreads)
+        return Ku, nm, st
+
+    def mqdt_eliminate(self, E, fnumin: float, Ku, nmember):
+        """Physical K from unphysical K at the same energies: (K, status)."""
+        E = np.ascontiguousarray(E, dtype=np.float64)
+        Ku = np.ascontiguousarray(Ku, dtype=np.float64)
+        nm = np.ascontiguousarray(nmember, dtype=np.int32)
+        n = self.pw.nchan
+        K = np.empty((E.size, n, n))
+        st = np.zeros(E.size, np.int32)
+        lib().rmo_mqdt_eliminate(self._p, _ptr(E), E.size, fnumin, _ptr(Ku), _ptr(nm), _ptr(K), _ptr(st),
+                                 self.nthreads)
+        return K, st
+
+    def mqdt_run(self, E, ieq: int, fnumin: float, thr_guard: float = 1e-10):
+        """Coarse/fine operation on an ascending mesh: dict(omega, K, coarse, status)."""
+        E = np.ascontiguousarray(E, dtype=np.float64)
+        n, nt = self.pw.nchan, self.pw.ntarget
+        om = np.empty((E.size, nt, nt))
+        K = np.empty((E.size, n, n))
+        co = np.zeros(E.size, np.int8)
+        st = np.zeros(E.size, np.int32)
+        if lib().rmo_mqdt_run(self._p, _ptr(E), E.size, ieq, fnumin, thr_guard, _ptr(om), _ptr(K), _ptr(co),
+                              _ptr(st), self.nthreads):
+            raise ValueError("ieq >= 1, z > 0 and an ascending mesh are needed")
+        return dict(omega=om, K=K, coarse=co.astype(bool), status=st)
+
     def run(self, E, thr_guard: float = 1e-10, want_K: bool = True, want_S: bool = False):
         E = np.ascontiguousarray(E, dtype=np.float64)
         n, nt = self.pw.nchan, self.pw.ntarget
@@ -219,3 +260,13 @@ def channel(z: float, eps: float, a: float, l: int) -> np.ndarray:
     if lib().rmo_channel(float(z), float(eps), float(a), int(l), _ptr(out)):
         raise RuntimeError("channel: no convergence")
     return out
+
+
+def mqdt_channel(z: float, eps: float, a: float, l: int, fnumin: float):
+    """Channel functions of the unphysical K at r = a and the member flag:
+    ((s, s', c, c') | (f, f', g, g') | (0, 0, e, e'), member)."""
+    out = np.empty(4)
+    m = lib().rmo_mqdt_channel(z, eps, a, l, fnumin, _ptr(out))
+    if m < 0:
+        raise ArithmeticError("channel function did not converge")
+    return out, bool(m)

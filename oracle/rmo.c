@@ -13,6 +13,8 @@
  *   closed_channel    exponentially decaying Whittaker function at r = a (Glossary)
  *   match_and_solve   eq. (match) with the asymptotic forms substituted
  *   s_and_omega       Glossary: T-matrix, collision strength
+ *   propagate         eq. (radial) with the multipole coupling, Numerov from r1 to a
+ *   mqdt              stgf MQDT variables: unphysical K, coarse/fine mesh
  */
 #include "rmo.h"
 
@@ -1173,5 +1175,402 @@ int rmo_run_coupled(const rmo_pw *pw, const rmo_coupling *cp, const double *E, i
     free(op);
     free(idx);
   }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Multichannel quantum-defect operation (section "Code Structure", stgf      */
+/* namelist, MQDT variables: iqdt = 1 treats every channel as open and works   */
+/* with the unphysical K; imode = -1 solves fully on a coarse mesh and by      */
+/* interpolation on the fine mesh; ieq < 0 updates the unphysical K at every   */
+/* |ieq|-th mesh point; iomsw = 1 and fnumin omit closed channels whose        */
+/* effective quantum number is below max(fnumin, l + 0.1)).                    */
+/*                                                                            */
+/* The paper names these options but leaves the functions to its references;  */
+/* the reading written here:                                                  */
+/*  - member channels: open (eps > 0) or closed with nu = z/kappa >=           */
+/*    max(fnumin, l + 0.1); the others are eliminated exactly as in the        */
+/*    physical K (decaying function).  Decided in double arithmetic.           */
+/*  - a closed member channel carries the pair (f, g) of Coulomb functions     */
+/*    analytic in energy: f = N A^(1/2) u, u the regular solution with         */
+/*    u ~ r^(l+1) at the origin, N = (2 pi z)^(1/2) (2z)^l / (2l+1)!,          */
+/*    A = prod_{p=1..l} (1 + p^2 eps / z^2); g = -e / W(f, e) + f cot(pi nu)   */
+/*    with e the decaying solution and W(x, y) = x y' - x' y.  Then            */
+/*    W(f, g) = -1, the decaying solution is f cos(pi nu) - g sin(pi nu), and  */
+/*    (f, g) join (s, c) of the open channel smoothly at the threshold         */
+/*    (s = f / (1 - exp(-2 pi z / k))^(1/2) above it).                         */
+/*  - unphysical K: eq. (match) with every member channel treated as open:    */
+/*    F = f + g Kun on members (s, c for open members), e X on the others.     */
+/*  - fine mesh: Kun interpolated elementwise in energy (Lagrange, the four    */
+/*    nearest coarse energies of the same member set), then                    */
+/*    K = Kun_oo - Kun_oc (Kun_cc + tan(pi nu))^-1 Kun_co.                     */
+/* ------------------------------------------------------------------------- */
+
+/* Taylor steps of u'' = (L2/r^2 - 2z/r - eps) u outward from r0 to r1 (the   */
+/* series of taylor_inward with h > 0). */
+static int taylor_outward(ld z, ld eps, ld L2, ld r0, ld r1, ld *u, ld *up) {
+  ld r = r0, U = *u, Up = *up;
+  long steps = 0;
+  enum { NT = 400 };
+  ld d[NT + 3];
+  while (r < r1) {
+    ld kl = sqrtl(fabsl(eps + 2.0L * z / r - L2 / (r * r))) + 1e-3L;
+    ld h = fminl(0.5L * r, 1.5L / kl);
+    if (r + h > r1) h = r1 - r;
+    const ld A = L2 - 2.0L * z * r - eps * r * r;
+    const ld B = -(2.0L * z + 2.0L * eps * r);
+    const ld C = -eps;
+    d[0] = U;
+    d[1] = Up * h;
+    ld su = d[0] + d[1], sd = d[1];
+    int small = 0, n;
+    for (n = 0; n < NT; ++n) {
+      const ld dm1 = n >= 1 ? d[n - 1] : 0.0L;
+      const ld dm2 = n >= 2 ? d[n - 2] : 0.0L;
+      const ld num = (A - (ld)n * (n - 1)) * d[n] * h * h - 2.0L * r * (ld)n * (n + 1) * d[n + 1] * h +
+                     B * dm1 * h * h * h + C * dm2 * h * h * h * h;
+      d[n + 2] = num / (r * r * (ld)(n + 1) * (n + 2));
+      su += d[n + 2];
+      sd += (ld)(n + 2) * d[n + 2];
+      if (fabsl(d[n + 2]) < 1e-22L * (fabsl(su) + fabsl(sd))) {
+        if (++small >= 3) break;
+      } else {
+        small = 0;
+      }
+    }
+    if (n >= NT) return -1;
+    U = su;
+    Up = sd / h;
+    r += h;
+    if (++steps > 50000000L) return -1;
+  }
+  *u = U;
+  *up = Up;
+  return 0;
+}
+
+/* f = N A^(1/2) u and f' at r = a (eps < 0, nu > l so that A > 0).  u starts  */
+/* from its power series u = r^(l+1) sum_p c_p r^p about the origin,           */
+/* p (p + 2l + 1) c_p = -2z c_(p-1) - eps c_(p-2), c_0 = 1, at a small r0.     */
+static int mqdt_regular(ld z, ld eps, ld a, int l, ld *f, ld *fp) {
+  ld r0 = 0.25L * a;
+  if (0.25L / z < r0) r0 = 0.25L / z;
+  if (0.25L / sqrtl(fabsl(eps)) < r0) r0 = 0.25L / sqrtl(fabsl(eps));
+  ld cm2 = 0.0L, cm1 = 1.0L, rp = 1.0L;
+  ld U = 1.0L, Up = (ld)(l + 1) / r0; /* u / r0^(l+1) and u' / r0^(l+1) */
+  for (int p = 1; p < 2000; ++p) {
+    const ld c = (-2.0L * z * cm1 - eps * cm2) / ((ld)p * (ld)(p + 2 * l + 1));
+    rp *= r0;
+    const ld tu = c * rp, tp = c * (ld)(p + l + 1) * rp / r0;
+    U += tu;
+    Up += tp;
+    cm2 = cm1;
+    cm1 = c;
+    if (fabsl(tu) < 1e-24L * fabsl(U) && fabsl(tp) < 1e-24L * fabsl(Up) && p > 4) break;
+  }
+  if (taylor_outward(z, eps, (ld)l * (l + 1), r0, a, &U, &Up)) return -1;
+  ld logA = 0.0L;
+  for (int p = 1; p <= l; ++p) {
+    const ld t = 1.0L + (ld)p * p * eps / (z * z);
+    if (t <= 0) return -1;
+    logA += logl(t);
+  }
+  const ld pi = 3.141592653589793238462643383279502884L;
+  const ld logN = 0.5L * logl(2.0L * pi * z) + (ld)l * logl(2.0L * z) - lgammal((ld)(2 * l + 2));
+  const ld scale = expl(logN + 0.5L * logA + (ld)(l + 1) * logl(r0));
+  *f = scale * U;
+  *fp = scale * Up;
+  return 0;
+}
+
+/* sin(pi x), cos(pi x) with x reduced modulo 2 first (exact) */
+static void sincos_pi(ld x, ld *s, ld *c) {
+  const ld pi = 3.141592653589793238462643383279502884L;
+  const ld y = fmodl(x, 2.0L);
+  *s = sinl(pi * y);
+  *c = cosl(pi * y);
+}
+
+/* member decision in double arithmetic: open, or closed with
+   nu >= max(fnumin, l + 0.1), i.e. eps >= -z^2 / numin^2 */
+static int mqdt_member(double z, double eps, int l, double fnumin) {
+  if (eps > 0) return 1;
+  const double numin = fnumin > l + 0.1 ? fnumin : l + 0.1;
+  return eps >= -(z * z) / (numin * numin);
+}
+
+/* Channel functions of the unphysical K at r = a: open -> (s, s', c, c'),
+   closed member -> (f, f', g, g'), other closed -> (0, 0, e, e').  Returns
+   1 for a member channel, 0 otherwise, -1 on failure. */
+static int mqdt_channel_fn(ld z, double eps_d, ld a, int l, double fnumin, ld out[4]) {
+  const ld eps = (ld)eps_d;
+  if (eps_d > 0) return channel_fn(z, eps, a, l, out) ? -1 : 1;
+  if (!mqdt_member((double)z, eps_d, l, fnumin)) return channel_fn(z, eps, a, l, out) ? -1 : 0;
+  ld e, ep, f, fp;
+  if (closed_uw(z, eps, a, l, &e, &ep)) return -1;
+  if (mqdt_regular(z, eps, a, l, &f, &fp)) return -1;
+  const ld W = f * ep - fp * e;
+  ld s, c;
+  sincos_pi(z / sqrtl(-eps), &s, &c);
+  const ld cot = c / s;
+  out[0] = f;
+  out[1] = fp;
+  out[2] = -e / W + f * cot;
+  out[3] = -ep / W + fp * cot;
+  return 1;
+}
+
+int rmo_mqdt_channel(double z, double eps, double a, int32_t l, double fnumin, double out[4]) {
+  ld v[4];
+  const int m = mqdt_channel_fn((ld)z, eps, (ld)a, l, fnumin, v);
+  if (m < 0) return -1;
+  for (int t = 0; t < 4; ++t) out[t] = (double)v[t];
+  return m;
+}
+
+/* Member channels of energy E in ascending order; returns their count. */
+static int mqdt_members(const rmo_pw *pw, double E, double fnumin, int *idx) {
+  int m = 0;
+  for (int i = 0; i < pw->nchan; ++i)
+    if (mqdt_member(pw->z, E - pw->e_thr[i], pw->l[i], fnumin)) idx[m++] = i;
+  return m;
+}
+
+static int32_t mqdt_flags(const rmo_pw *pw, double E, double thr_guard) {
+  int32_t st = 0;
+  for (int k = 0; k < pw->npole; ++k)
+    if (pw->Ek[k] == E) st |= RMO_PT_POLE;
+  for (int i = 0; i < pw->nchan; ++i)
+    if (fabs(E - pw->e_thr[i]) < thr_guard) st |= RMO_PT_THRESHOLD;
+  return st;
+}
+
+/* Unphysical K at one energy: Ku (row stride n), leading ns x ns block over
+   the member channels in ascending order. */
+static int32_t unphysical_one(const rmo_pw *pw, double E, double fnumin, double thr_guard, double *Ku,
+                              int *ns_out) {
+  const int n = pw->nchan;
+  const ld a = pw->a, b = pw->b;
+  for (long t = 0; t < (long)n * n; ++t) Ku[t] = 0.0;
+  int *mem = (int *)malloc(sizeof(int) * (n + 1));
+  const int ns = mqdt_members(pw, E, fnumin, mem);
+  *ns_out = ns;
+  int32_t st = mqdt_flags(pw, E, thr_guard);
+  double *R = (double *)malloc(sizeof(double) * (size_t)n * n);
+  ld *fg = (ld *)malloc(sizeof(ld) * 4 * n);
+  if (!st) st |= form_R_one(pw, E, R);
+  for (int i = 0; i < n && !st; ++i)
+    if (mqdt_channel_fn((ld)pw->z, E - pw->e_thr[i], a, pw->l[i], fnumin, fg + 4 * i) < 0) st |= RMO_PT_NOCONV;
+  if (!st && ns > 0) {
+    /* A_im = d_im C_i - R_im (a C'_m - b C_m), C = g (members) or e (others);
+       B_ij = R_{i,m_j} (a f'_{m_j} - b f_{m_j}) - d_{i,m_j} f_{m_j} */
+    ld *A = (ld *)malloc(sizeof(ld) * (size_t)n * n);
+    ld *col = (ld *)malloc(sizeof(ld) * n);
+    int *piv = (int *)malloc(sizeof(int) * n);
+    for (int i = 0; i < n; ++i)
+      for (int m = 0; m < n; ++m)
+        A[(size_t)i * n + m] = (i == m ? fg[4 * i + 2] : 0.0L) -
+                               (ld)R[(size_t)i * n + m] * (a * fg[4 * m + 3] - b * fg[4 * m + 2]);
+    if (lu_factor(A, n, piv)) {
+      st |= RMO_PT_SINGULAR;
+    } else {
+      for (int j = 0; j < ns; ++j) {
+        const int mj = mem[j];
+        for (int i = 0; i < n; ++i)
+          col[i] = (ld)R[(size_t)i * n + mj] * (a * fg[4 * mj + 1] - b * fg[4 * mj + 0]) - (i == mj ? fg[4 * mj] : 0.0L);
+        lu_solve(A, n, piv, col, 0);
+        for (int i = 0; i < ns; ++i) Ku[(size_t)i * n + j] = (double)col[mem[i]];
+      }
+    }
+    free(A);
+    free(col);
+    free(piv);
+  }
+  if (st) fill_nan(Ku, (long)n * n);
+  free(R);
+  free(fg);
+  free(mem);
+  return st;
+}
+
+int rmo_unphysical_K(const rmo_pw *pw, const double *E, int32_t ne, double fnumin, double thr_guard, double *Ku,
+                     int32_t *nmember, int32_t *status, int32_t nthreads) {
+  const long nn = (long)pw->nchan * pw->nchan;
+  set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1) if (ne > 1)
+  for (int e = 0; e < ne; ++e) {
+    int ns = 0;
+    status[e] = unphysical_one(pw, E[e], fnumin, thr_guard, Ku + e * nn, &ns);
+    nmember[e] = ns;
+  }
+  return 0;
+}
+
+/* Physical K from the unphysical one at energy E (members as in Ku):
+   K = Ku_oo - Ku_oc (Ku_cc + diag tan(pi nu_c))^-1 Ku_co, open channels in
+   ascending order (row stride n). */
+static int32_t mqdt_eliminate(const rmo_pw *pw, double E, double fnumin, const ld *Ku, int ns, double *K) {
+  const int n = pw->nchan;
+  int *mem = (int *)malloc(sizeof(int) * (n + 1));
+  int *oi = (int *)malloc(sizeof(int) * (n + 1)), *ci = (int *)malloc(sizeof(int) * (n + 1));
+  const int m = mqdt_members(pw, E, fnumin, mem);
+  int no = 0, nc = 0;
+  for (int t = 0; t < m; ++t) {
+    if (E - pw->e_thr[mem[t]] > 0) oi[no++] = t; /* positions within the member list */
+    else ci[nc++] = t;
+  }
+  for (long t = 0; t < (long)n * n; ++t) K[t] = 0.0;
+  int32_t st = 0;
+  if (m != ns) st = RMO_PT_NOCONV;
+  if (!st && no > 0) {
+    ld *Mc = (ld *)malloc(sizeof(ld) * ((size_t)nc * nc + 1));
+    ld *X = (ld *)malloc(sizeof(ld) * ((size_t)nc * no + 1));
+    ld *col = (ld *)malloc(sizeof(ld) * (nc + 1));
+    int *piv = (int *)malloc(sizeof(int) * (nc + 1));
+    for (int i = 0; i < nc; ++i) {
+      for (int j = 0; j < nc; ++j) Mc[(size_t)i * nc + j] = Ku[(size_t)ci[i] * n + ci[j]];
+      const int ch = mem[ci[i]];
+      ld s, c;
+      sincos_pi((ld)pw->z / sqrtl(-((ld)E - (ld)pw->e_thr[ch])), &s, &c);
+      Mc[(size_t)i * nc + i] += s / c;
+    }
+    if (nc > 0 && lu_factor(Mc, nc, piv)) {
+      st = RMO_PT_SINGULAR;
+    } else {
+      for (int j = 0; j < no; ++j) {
+        for (int i = 0; i < nc; ++i) col[i] = Ku[(size_t)ci[i] * n + oi[j]];
+        if (nc > 0) lu_solve(Mc, nc, piv, col, 0);
+        for (int i = 0; i < nc; ++i) X[(size_t)i * no + j] = col[i];
+      }
+      for (int i = 0; i < no; ++i)
+        for (int j = 0; j < no; ++j) {
+          ld v = Ku[(size_t)oi[i] * n + oi[j]];
+          for (int k = 0; k < nc; ++k) v -= Ku[(size_t)oi[i] * n + ci[k]] * X[(size_t)k * no + j];
+          K[(size_t)i * n + j] = (double)v;
+        }
+    }
+    free(Mc);
+    free(X);
+    free(col);
+    free(piv);
+  }
+  free(mem);
+  free(oi);
+  free(ci);
+  return st;
+}
+
+int rmo_mqdt_eliminate(const rmo_pw *pw, const double *E, int32_t ne, double fnumin, const double *Ku,
+                       const int32_t *nmember, double *K, int32_t *status, int32_t nthreads) {
+  const int n = pw->nchan;
+  const long nn = (long)n * n;
+  set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1) if (ne > 1)
+  for (int e = 0; e < ne; ++e) {
+    ld *Kl = (ld *)malloc(sizeof(ld) * nn);
+    for (long t = 0; t < nn; ++t) Kl[t] = Ku[e * nn + t];
+    status[e] = mqdt_eliminate(pw, E[e], fnumin, Kl, nmember[e], K + e * nn);
+    if (status[e]) fill_nan(K + e * nn, nn);
+    free(Kl);
+  }
+  return 0;
+}
+
+/* Coarse/fine operation over an ascending mesh E[0..ne).  The mesh splits into
+   runs with the same member set (it only grows with E).  In each run the
+   coarse points are every ieq-th point from the run's first and the run's
+   last point, minus points flagged at a threshold or a pole; a run with
+   unflagged points but no unflagged coarse point is solved fully.  Each fine
+   point takes the Lagrange interpolant through the four coarse points of its
+   run around it (window start: the coarse point before the last coarse point
+   at or below it, clamped to the run's coarse list; all of them if fewer than
+   four).  coarse[e] (may be NULL) is set to 1 at coarse points. */
+int rmo_mqdt_run(const rmo_pw *pw, const double *E, int32_t ne, int32_t ieq, double fnumin, double thr_guard,
+                 double *omega, double *K, int8_t *coarse, int32_t *status, int32_t nthreads) {
+  if (ieq < 1 || pw->z <= 0) return -1;
+  for (int e = 1; e < ne; ++e)
+    if (!(E[e] > E[e - 1])) return -1;
+  const int n = pw->nchan, nt = pw->ntarget;
+  const long nn = (long)n * n;
+  int *ns = (int *)malloc(sizeof(int) * (ne + 1));
+  int *flag = (int *)malloc(sizeof(int) * (ne + 1));
+  int *isc = (int *)calloc(ne + 1, sizeof(int));
+  int *mem = (int *)malloc(sizeof(int) * (n + 1));
+  for (int e = 0; e < ne; ++e) {
+    ns[e] = mqdt_members(pw, E[e], fnumin, mem);
+    flag[e] = mqdt_flags(pw, E[e], thr_guard);
+  }
+  free(mem);
+  for (int s0 = 0; s0 < ne;) {
+    int s1 = s0 + 1;
+    while (s1 < ne && ns[s1] == ns[s0]) ++s1;
+    int any = 0;
+    for (int j = s0; j < s1; ++j)
+      if (((j - s0) % ieq == 0 || j == s1 - 1) && !flag[j]) isc[j] = 1, any = 1;
+    if (!any)
+      for (int j = s0; j < s1; ++j)
+        if (!flag[j]) isc[j] = 1;
+    s0 = s1;
+  }
+  if (coarse)
+    for (int e = 0; e < ne; ++e) coarse[e] = (int8_t)isc[e];
+  /* unphysical K at the coarse points */
+  double *Kc = (double *)malloc(sizeof(double) * (size_t)ne * nn);
+  int32_t *stc = (int32_t *)calloc(ne + 1, sizeof(int32_t));
+  set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int e = 0; e < ne; ++e) {
+    int m = 0;
+    if (isc[e]) stc[e] = unphysical_one(pw, E[e], fnumin, thr_guard, Kc + e * nn, &m);
+  }
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int e = 0; e < ne; ++e) {
+    double *Kl = K ? K + e * nn : (double *)malloc(sizeof(double) * nn);
+    int32_t st = flag[e];
+    if (!st) {
+      /* the run of e and its coarse points */
+      int s0 = e, s1 = e + 1;
+      while (s0 > 0 && ns[s0 - 1] == ns[e]) --s0;
+      while (s1 < ne && ns[s1] == ns[e]) ++s1;
+      int *cl = (int *)malloc(sizeof(int) * (s1 - s0 + 1));
+      int m = 0, k = 0;
+      for (int j = s0; j < s1; ++j)
+        if (isc[j]) cl[m++] = j;
+      for (int q = 0; q < m; ++q)
+        if (cl[q] <= e) k = q;
+      const int w = m < 4 ? m : 4;
+      int st0 = k - 1;
+      if (st0 > m - w) st0 = m - w;
+      if (st0 < 0) st0 = 0;
+      ld *Ki = (ld *)calloc(nn, sizeof(ld));
+      for (int q = st0; q < st0 + w; ++q) {
+        ld wt = 1.0L;
+        for (int r = st0; r < st0 + w; ++r)
+          if (r != q) wt *= ((ld)E[e] - (ld)E[cl[r]]) / ((ld)E[cl[q]] - (ld)E[cl[r]]);
+        st |= stc[cl[q]];
+        for (long t = 0; t < nn; ++t) Ki[t] += wt * (ld)Kc[(size_t)cl[q] * nn + t];
+      }
+      if (!st) st = mqdt_eliminate(pw, E[e], fnumin, Ki, ns[e], Kl);
+      if (!st) {
+        int *idx = (int *)malloc(sizeof(int) * (n + 1));
+        const int no = open_list(pw, E[e], idx);
+        st = s_and_omega_one(pw, Kl, no, idx, omega + (long)e * nt * nt, NULL);
+        free(idx);
+      }
+      free(Ki);
+      free(cl);
+    }
+    if (st) {
+      fill_nan(Kl, nn);
+      fill_nan(omega + (long)e * nt * nt, (long)nt * nt);
+    }
+    status[e] = st;
+    if (!K) free(Kl);
+  }
+  free(Kc);
+  free(stc);
+  free(ns);
+  free(flag);
+  free(isc);
   return 0;
 }

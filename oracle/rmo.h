@@ -100,6 +100,30 @@ int rmo_solve_K_coupled(const rmo_pw *pw, const double *E, int32_t ne, const dou
 int rmo_run_coupled(const rmo_pw *pw, const rmo_coupling *cp, const double *E, int32_t ne, double thr_guard,
                     double *omega, double *K, double *cond, int32_t *status, int32_t nthreads);
 
+/* Multichannel quantum-defect operation (section "Code Structure", stgf
+   namelist MQDT variables iqdt = 1, imode = -1, ieq < 0, fnumin, iomsw = 1).
+   A channel is a member at energy E if it is open or closed with effective
+   quantum number nu = z/sqrt(e_i - E) >= max(fnumin, l_i + 0.1).
+   Unphysical K over the member channels (ascending, leading nmember x nmember
+   block of each n x n matrix): eq. (match) with every member treated as open,
+   closed members carrying the energy-analytic Coulomb pair (f, g). */
+int rmo_unphysical_K(const rmo_pw *pw, const double *E, int32_t ne, double fnumin, double thr_guard, double *Ku,
+                     int32_t *nmember, int32_t *status, int32_t nthreads);
+/* Physical K from the unphysical one at the same energies:
+   K = Ku_oo - Ku_oc (Ku_cc + tan(pi nu_c))^-1 Ku_co. */
+int rmo_mqdt_eliminate(const rmo_pw *pw, const double *E, int32_t ne, double fnumin, const double *Ku,
+                       const int32_t *nmember, double *K, int32_t *status, int32_t nthreads);
+/* Coarse/fine operation on an ascending mesh: unphysical K at every ieq-th
+   point of each run of equal member set (and the run's last point), Lagrange
+   interpolation (four nearest coarse points of the run) elsewhere, then K and
+   Omega at every point.  coarse (may be NULL) marks the coarse points.
+   Returns -1 for ieq < 1, z <= 0 or a mesh that is not ascending. */
+int rmo_mqdt_run(const rmo_pw *pw, const double *E, int32_t ne, int32_t ieq, double fnumin, double thr_guard,
+                 double *omega, double *K, int8_t *coarse, int32_t *status, int32_t nthreads);
+/* Channel functions of the unphysical K at r = a: (s, s', c, c') open,
+   (f, f', g, g') closed member, (0, 0, e, e') otherwise; returns 1 for a
+   member, 0 otherwise, -1 on failure. */
+int rmo_mqdt_channel(double z, double eps, double a, int32_t l, double fnumin, double out[4]);
 /* Special functions, exposed for pinning against independent references. */
 /* F, dF/drho, G, dG/drho of the Coulomb functions F_l(eta, rho), G_l(eta, rho). */
 int rmo_coulomb(double eta, double rho, int32_t l, double out[4]);

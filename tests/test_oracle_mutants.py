@@ -58,6 +58,17 @@ MUTANTS = {
     "numerov_derivative": ("(((2.0L * Z1[t] - Y1[t]) - (2.0L * Zc[t] - Y[t])) / (2.0L * h))",
                            "((Z1[t] - Zc[t]) / (2.0L * h))",
                            "test_oracle_coupling.py::test_uncoupled_propagation_converges_to_analytic"),
+    # multichannel quantum-defect operation
+    "mqdt_cot_sign": ("out[2] = -e / W + f * cot;", "out[2] = -e / W - f * cot;",
+                      "test_oracle_mqdt.py::test_pair_against_kummer_and_tricomi"),
+    "mqdt_norm_A": ("expl(logN + 0.5L * logA", "expl(logN + logA",
+                    "test_oracle_mqdt.py::test_pair_continues_the_open_functions_across_threshold"),
+    "mqdt_tan_sign": ("Mc[(size_t)i * nc + i] += s / c;", "Mc[(size_t)i * nc + i] -= s / c;",
+                      "test_oracle_mqdt.py::test_elimination_reproduces_the_physical_K"),
+    "mqdt_series": ("-2.0L * z * cm1 - eps * cm2", "-2.0L * z * cm1 + eps * cm2",
+                    "test_oracle_mqdt.py::test_pair_against_kummer_and_tricomi"),
+    "mqdt_window": ("int st0 = k - 1;", "int st0 = k - 3;",
+                    "test_oracle_mqdt.py::test_fine_point_uses_the_four_surrounding_coarse_points"),
     "taylor_start_binomial": ("for (int t = 1; t <= p; ++t) binom = binom * (ld)(lam + t) / (ld)t;",
                               "for (int t = 1; t <= p; ++t) binom = binom * (ld)(lam + t - 1) / (ld)t;",
                               "test_oracle_coupling.py::test_coupled_propagation_against_mpmath"),

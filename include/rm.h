@@ -180,6 +180,61 @@ rm_status rm_set_propagation(rm_ctx *ctx, int32_t npts, int32_t stab);
 rm_status rm_propagate(rm_ctx *ctx, int32_t pw, const double *E, int32_t ne, const rm_opts *opts,
                        double *phi, double *dphi, int32_t *status);
 
+/* ------------------------------------------- quantum-defect operation */
+/* Multichannel quantum-defect operation, section "Code Structure", stgf
+   namelist, MQDT variables (iqdt = 1: every member channel treated as open,
+   unphysical K; imode = -1: full solution on a coarse mesh, interpolation on
+   the fine one; ieq < 0: the unphysical K updated at every |ieq|-th mesh
+   point; iomsw = 1 with fnumin: closed channels with effective quantum
+   number nu = z / sqrt(e_i - E) below max(fnumin, l_i + 0.1) are omitted,
+   i.e. eliminated with their decaying function as in the physical K).
+
+   Member channels at E: open, or closed with nu >= max(fnumin, l_i + 0.1).
+   A closed member carries the Coulomb pair analytic in energy
+     f = N A^(1/2) u,  N = (2 pi z)^(1/2) (2z)^l / (2l+1)!,
+     A = prod_{p=1..l} (1 + p^2 eps / z^2),
+     g = -e / W(f, e) + f cot(pi nu),
+   u the regular solution with u ~ r^(l+1) at the origin, e the decaying
+   solution, W(x, y) = x y' - x' y; (f, g) continue the open-channel (s, c)
+   across the threshold, W(f, g) = W(s, c) = -1, and the decaying solution is
+   f cos(pi nu) - g sin(pi nu), so that
+     K = Ku_oo - Ku_oc (Ku_cc + tan(pi nu_c))^-1 Ku_co.
+   The choice of (f, g), the member rule's decision in double arithmetic and
+   the interpolation (below) are readings of the paper, which names the
+   options but defers the functions to its references.  The pair loses
+   accuracy where a is deep in the classically forbidden region of a member
+   channel (a > 2 nu^2 / z): choose fnumin >= sqrt(z a / 2) or so.
+
+   Only waves without a long-range coupling and with z > 0 are accepted
+   (RM_E_ARG otherwise, as for fnumin < 0). */
+
+/* Unphysical K over the member channels at each energy (eq. (match) with
+   every member treated as open).  Ku: [ne][n][n], leading nmember[e] x
+   nmember[e] block set (members in ascending channel order), the rest zero;
+   nmember: [ne]; status: [ne] as rm_run (flagged energies: Ku NaN). */
+rm_status rm_mqdt_unphysical_K(rm_ctx *ctx, int32_t pw, const double *E, int32_t ne, double fnumin,
+                               const rm_opts *opts, double *Ku, int32_t *nmember, int32_t *status);
+
+/* Coarse/fine operation on a strictly ascending mesh E[0..ne).  The mesh
+   splits into runs of equal member set (the set grows with E).  In each run
+   the coarse points are every ieq-th point from its first and its last
+   point, leaving out points flagged at a threshold or a pole (a run whose
+   candidates are all flagged has every unflagged point coarse); there the
+   unphysical K is computed in full.  Each point takes the elementwise
+   Lagrange interpolant of Ku through the four coarse points of its run
+   around it (the window starts at the coarse point before the last one at
+   or below it, clamped to the run; all of them if fewer than four), its
+   closed members are eliminated as above on the GPU (a batched LU of the
+   member count), and S, T and Omega follow as in rm_run.  At coarse points
+   the result is the physical one (up to rounding).  Outputs as rm_run
+   (omega [ne][nt][nt], K [ne][n][n] or NULL, status [ne]); coarse [ne] int8
+   (may be NULL) marks the coarse points.  A point inherits the flags of the
+   coarse points it is interpolated from.  ieq < 1 or a mesh that is not
+   strictly ascending: RM_E_ARG.  The call allocates device temporaries (the
+   coarse Ku: ncoarse n^2 doubles) and returns after its work is complete. */
+rm_status rm_run_mqdt(rm_ctx *ctx, int32_t pw, const double *E, int32_t ne, int32_t ieq, double fnumin,
+                      const rm_opts *opts, double *omega, double *K, int8_t *coarse, int32_t *status);
+
 /* ---------------------------------------------------------- staged calls */
 /* Stage 1, eq. (rmatrix).  R: [ne][n][n] doubles (full symmetric matrices);
    status: [ne] int32 (RM_PT_POLE only). */

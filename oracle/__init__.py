@@ -61,7 +61,7 @@ def lib():
         _lib.rmo_propagate.argtypes = [vp, vp, vp, i32, d, vp, vp, vp, vp, vp, i32]
         _lib.rmo_solve_K_coupled.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, i32]
         _lib.rmo_run_coupled.argtypes = [vp, vp, vp, i32, d, vp, vp, vp, vp, i32]
-        _lib.rmo_unphysical_K.argtypes = [vp, vp, i32, d, d, vp, vp, vp, i32]
+        _lib.rmo_unphysical_K.argtypes = [vp, vp, i32, d, d, vp, vp, vp, vp, i32]
         _lib.rmo_mqdt_eliminate.argtypes = [vp, vp, i32, d, vp, vp, vp, vp, i32]
         _lib.rmo_mqdt_run.argtypes = [vp, vp, i32, i32, d, d, vp, vp, vp, vp, i32]
         _lib.rmo_mqdt_channel.argtypes = [d, d, d, i32, d, vp]
@@ -183,17 +183,19 @@ class Oracle:
             raise ValueError("invalid coupling")
         return dict(omega=om, K=K, cond=cond, status=st)
 
-    def unphysical_K(self, E, fnumin: float, thr_guard: float = 1e-10):
+    def unphysical_K(self, E, fnumin: float, thr_guard: float = 1e-10, want_cond: bool = False):
         """Unphysical K over the member channels at each energy: (Ku [ne][n][n]
-        with the leading nmember x nmember block set, nmember, status)."""
+        with the leading nmember x nmember block set, nmember, status); with
+        want_cond also the matching matrix's 1-norm condition estimate."""
         E = np.ascontiguousarray(E, dtype=np.float64)
         n = self.pw.nchan
         Ku = np.empty((E.size, n, n))
         nm = np.empty(E.size, np.int32)
+        cond = np.empty(E.size)
         st = np.zeros(E.size, np.int32)
-        lib().rmo_unphysical_K(self._p, _ptr(E), E.size, fnumin, thr_guard, _ptr(Ku), _ptr(nm), _ptr(st),
+        lib().rmo_unphysical_K(self._p, _ptr(E), E.size, fnumin, thr_guard, _ptr(Ku), _ptr(nm), _ptr(cond), _ptr(st),
                                self.nthreads)
-        return Ku, nm, st
+        return (Ku, nm, st, cond) if want_cond else (Ku, nm, st)
 
     def mqdt_eliminate(self, E, fnumin: float, Ku, nmember):
         """Physical K from unphysical K at the same energies: (K, status)."""

@@ -1348,7 +1348,7 @@ static int32_t mqdt_flags(const rmo_pw *pw, double E, double thr_guard) {
 /* Unphysical K at one energy: Ku (row stride n), leading ns x ns block over
    the member channels in ascending order. */
 static int32_t unphysical_one(const rmo_pw *pw, double E, double fnumin, double thr_guard, double *Ku,
-                              int *ns_out) {
+                              int *ns_out, double *cond) {
   const int n = pw->nchan;
   const ld a = pw->a, b = pw->b;
   for (long t = 0; t < (long)n * n; ++t) Ku[t] = 0.0;
@@ -1365,15 +1365,18 @@ static int32_t unphysical_one(const rmo_pw *pw, double E, double fnumin, double 
     /* A_im = d_im C_i - R_im (a C'_m - b C_m), C = g (members) or e (others);
        B_ij = R_{i,m_j} (a f'_{m_j} - b f_{m_j}) - d_{i,m_j} f_{m_j} */
     ld *A = (ld *)malloc(sizeof(ld) * (size_t)n * n);
+    ld *A0 = (ld *)malloc(sizeof(ld) * (size_t)n * n);
     ld *col = (ld *)malloc(sizeof(ld) * n);
     int *piv = (int *)malloc(sizeof(int) * n);
     for (int i = 0; i < n; ++i)
       for (int m = 0; m < n; ++m)
         A[(size_t)i * n + m] = (i == m ? fg[4 * i + 2] : 0.0L) -
                                (ld)R[(size_t)i * n + m] * (a * fg[4 * m + 3] - b * fg[4 * m + 2]);
+    memcpy(A0, A, sizeof(ld) * (size_t)n * n);
     if (lu_factor(A, n, piv)) {
       st |= RMO_PT_SINGULAR;
     } else {
+      if (cond) *cond = (double)cond1_estimate(A0, A, n, piv);
       for (int j = 0; j < ns; ++j) {
         const int mj = mem[j];
         for (int i = 0; i < n; ++i)
@@ -1383,6 +1386,7 @@ static int32_t unphysical_one(const rmo_pw *pw, double E, double fnumin, double 
       }
     }
     free(A);
+    free(A0);
     free(col);
     free(piv);
   }
@@ -1394,14 +1398,16 @@ static int32_t unphysical_one(const rmo_pw *pw, double E, double fnumin, double 
 }
 
 int rmo_unphysical_K(const rmo_pw *pw, const double *E, int32_t ne, double fnumin, double thr_guard, double *Ku,
-                     int32_t *nmember, int32_t *status, int32_t nthreads) {
+                     int32_t *nmember, double *cond, int32_t *status, int32_t nthreads) {
   const long nn = (long)pw->nchan * pw->nchan;
   set_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 1) if (ne > 1)
   for (int e = 0; e < ne; ++e) {
     int ns = 0;
-    status[e] = unphysical_one(pw, E[e], fnumin, thr_guard, Ku + e * nn, &ns);
+    double c = 0.0;
+    status[e] = unphysical_one(pw, E[e], fnumin, thr_guard, Ku + e * nn, &ns, &c);
     nmember[e] = ns;
+    if (cond) cond[e] = c;
   }
   return 0;
 }
@@ -1521,7 +1527,7 @@ int rmo_mqdt_run(const rmo_pw *pw, const double *E, int32_t ne, int32_t ieq, dou
 #pragma omp parallel for schedule(dynamic, 1)
   for (int e = 0; e < ne; ++e) {
     int m = 0;
-    if (isc[e]) stc[e] = unphysical_one(pw, E[e], fnumin, thr_guard, Kc + e * nn, &m);
+    if (isc[e]) stc[e] = unphysical_one(pw, E[e], fnumin, thr_guard, Kc + e * nn, &m, NULL);
   }
 #pragma omp parallel for schedule(dynamic, 1)
   for (int e = 0; e < ne; ++e) {

@@ -106,9 +106,10 @@ int rmo_run_coupled(const rmo_pw *pw, const rmo_coupling *cp, const double *E, i
    quantum number nu = z/sqrt(e_i - E) >= max(fnumin, l_i + 0.1).
    Unphysical K over the member channels (ascending, leading nmember x nmember
    block of each n x n matrix): eq. (match) with every member treated as open,
-   closed members carrying the energy-analytic Coulomb pair (f, g). */
+   closed members carrying the energy-analytic Coulomb pair (f, g).  cond (may
+   be NULL): 1-norm condition estimate of the matching matrix. */
 int rmo_unphysical_K(const rmo_pw *pw, const double *E, int32_t ne, double fnumin, double thr_guard, double *Ku,
-                     int32_t *nmember, int32_t *status, int32_t nthreads);
+                     int32_t *nmember, double *cond, int32_t *status, int32_t nthreads);
 /* Physical K from the unphysical one at the same energies:
    K = Ku_oo - Ku_oc (Ku_cc + tan(pi nu_c))^-1 Ku_co. */
 int rmo_mqdt_eliminate(const rmo_pw *pw, const double *E, int32_t ne, double fnumin, const double *Ku,

@@ -30,6 +30,18 @@
 // with W'/W = (1 - w_1)/r.  It is stable only where b_1 > 0, so it is taken at
 // r_s = max(a, (nu + 2)/kappa) and (W, W') are carried inward to a with Taylor
 // steps.  Output is the direction (e, e') = (W, W')/sqrt(W^2 + a^2 W'^2), e >= 0.
+//
+// Quantum-defect mode (stgf MQDT variables iqdt = 1, iomsw = 1, fnumin): a
+// closed channel with nu >= max(fnumin, l + 0.1) is treated as open with the
+// Coulomb pair analytic in energy,
+//   f = N A^(1/2) u,  N = (2 pi z)^(1/2) (2z)^l / (2l+1)!,
+//   A = prod_{p=1..l} (1 + p^2 eps / z^2),
+//   g = -e / W(f, e) + f cot(pi nu),   W(x, y) = x y' - x' y,
+// with u the regular solution normalised as r^(l+1) at the origin (its power
+// series about 0 at a small r0, then Taylor steps outward to a) and e the
+// decaying solution above.  W(f, g) = -1 as for (s, c); the decaying solution
+// is f cos(pi nu) - g sin(pi nu), and (f, g) continue (s, c) across the
+// threshold.
 #include "rm.h"
 #include "rm_internal.h"
 
@@ -278,8 +290,101 @@ __device__ bool closed_fn(double z, double eps, double a, int l, double out[4]) 
   return true;
 }
 
+// Taylor steps as in taylor_in, outward from r0 to r1; (u, u') are rescaled
+// when they grow past 1e150 and the log of the scale is added to lsc.
+__device__ bool taylor_out(double zz, double ee, double L2, double r0, double r1, double &u, double &up,
+                           double &lsc) {
+  double r = r0;
+  long steps = 0;
+  while (r < r1) {
+    const double kl = sqrt(fabs(ee + 2.0 * zz / r - L2 / (r * r))) + 1e-3;
+    double h = fmin(0.4 * r, 1.2 / kl);
+    if (r + h > r1) h = r1 - r;
+    const double A = L2 - 2.0 * zz * r - ee * r * r;
+    const double B = -(2.0 * zz + 2.0 * ee * r);
+    const double C = -ee;
+    const double h2 = h * h, h3 = h2 * h, h4 = h2 * h2, irr = 1.0 / (r * r);
+    double dm2 = 0.0, dm1 = 0.0, d0 = u, d1 = up * h;
+    double su = d0 + d1, sd = d1;
+    int small = 0, nn;
+    for (nn = 0; nn < TAYLOR_MAX; ++nn) {
+      const double dn = ((A - (double)nn * (nn - 1)) * d0 * h2 - 2.0 * r * (double)nn * (nn + 1) * d1 * h +
+                         B * dm1 * h3 + C * dm2 * h4) *
+                        irr * kInvPairs.v[nn];
+      su += dn;
+      sd += (double)(nn + 2) * dn;
+      dm2 = dm1;
+      dm1 = d0;
+      d0 = d1;
+      d1 = dn;
+      if (fabs(dn) < 1e-18 * (fabs(su) + fabs(sd))) {
+        if (++small >= 3) break;
+      } else {
+        small = 0;
+      }
+    }
+    if (nn >= TAYLOR_MAX) return false;
+    u = su;
+    up = sd / h;
+    const double big = fmax(fabs(u), fabs(up));
+    if (big > 1e150) {
+      u /= big;
+      up /= big;
+      lsc += log(big);
+    }
+    r += h;
+    if (++steps > (1L << 20)) return false;
+  }
+  return true;
+}
+
+// f = N A^(1/2) u and f' at r = a for a closed member channel (nu > l, A > 0).
+// u / r0^(l+1) = sum_p c_p r0^p with p (p + 2l + 1) c_p = -2z c_(p-1) - eps c_(p-2).
+__device__ bool regular_fn(double z, double eps, double a, int l, double &f, double &fp) {
+  const double r0 = fmin(0.5 * a, fmin(0.5 / z, 0.5 / sqrt(-eps)));
+  double cm2 = 0.0, cm1 = 1.0, rp = 1.0;
+  double U = 1.0, Up = (double)(l + 1) / r0;
+  for (int p = 1; p < 400; ++p) {
+    const double c = (-2.0 * z * cm1 - eps * cm2) / ((double)p * (double)(p + 2 * l + 1));
+    rp *= r0;
+    const double tu = c * rp, tp = c * (double)(p + l + 1) * rp / r0;
+    U += tu;
+    Up += tp;
+    cm2 = cm1;
+    cm1 = c;
+    if (p > 4 && fabs(tu) < 1e-18 * fabs(U) && fabs(tp) < 1e-18 * fabs(Up)) break;
+  }
+  double lsc = 0.0;
+  if (!taylor_out(z, eps, (double)l * (l + 1), r0, a, U, Up, lsc)) return false;
+  double logA = 0.0;
+  for (int p = 1; p <= l; ++p) logA += log1p((double)p * p * eps / (z * z));
+  const double logN = 0.5 * log(2.0 * M_PI * z) + (double)l * log(2.0 * z) - lgamma((double)(2 * l + 2));
+  const double sc = exp(logN + 0.5 * logA + (double)(l + 1) * log(r0) + lsc);
+  f = sc * U;
+  fp = sc * Up;
+  return isfinite(f) && isfinite(fp) && f != 0.0;
+}
+
+// closed member channel of the unphysical K: f, f', g, g'
+__device__ bool mqdt_closed_fn(double z, double eps, double a, int l, double out[4]) {
+  double ed[4];
+  if (!closed_fn(z, eps, a, l, ed)) return false;
+  double f, fp;
+  if (!regular_fn(z, eps, a, l, f, fp)) return false;
+  const double e = ed[2], ep = ed[3];
+  const double iw = 1.0 / (f * ep - fp * e);
+  const double nu = z / sqrt(-eps);
+  const double cot = cospi(nu) / sinpi(nu);
+  out[0] = f;
+  out[1] = fp;
+  out[2] = -e * iw + f * cot;
+  out[3] = -ep * iw + fp * cot;
+  return isfinite(out[2]) && isfinite(out[3]);
+}
+
 __global__ void k_asym(const DevPW *__restrict__ tab, const int *__restrict__ pwi, const double *__restrict__ E,
-                       long ldo, double thr_guard, double *__restrict__ fg, int *__restrict__ status) {
+                       long ldo, double thr_guard, int mqdt, double fnumin, double *__restrict__ fg,
+                       int *__restrict__ status) {
   const int e = blockIdx.y;
   const DevPW &p = tab[pwi[e]];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -292,7 +397,9 @@ __global__ void k_asym(const DevPW *__restrict__ tab, const int *__restrict__ pw
   } else {
     // at the boundary a, or at r1 for a wave whose coupled functions are propagated from there
     const double r = p.lamax ? p.r1 : p.a;
-    const bool ok = eps > 0 ? open_fn(p.z, eps, r, p.l[i], out) : closed_fn(p.z, eps, r, p.l[i], out);
+    const bool ok = eps > 0                                          ? open_fn(p.z, eps, r, p.l[i], out)
+                    : (mqdt && mqdt_member(p.z, eps, p.l[i], fnumin)) ? mqdt_closed_fn(p.z, eps, r, p.l[i], out)
+                                                                      : closed_fn(p.z, eps, r, p.l[i], out);
     if (!ok) bad = RM_PT_NOCONV;
   }
   double *o = fg + ((size_t)e * ldo + i) * 4;
@@ -311,7 +418,7 @@ __global__ void k_asym(const DevPW *__restrict__ tab, const int *__restrict__ pw
 void launch_asym(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const double *E, double thr_guard,
                  double *fg, int *status) {
   dim3 grid((L.nmax + 63) / 64, L.ne);
-  hipLaunchKernelGGL(k_asym, grid, dim3(64), 0, s, tab, pwi, E, L.ldo, thr_guard, fg, status);
+  hipLaunchKernelGGL(k_asym, grid, dim3(64), 0, s, tab, pwi, E, L.ldo, thr_guard, L.mqdt, L.fnumin, fg, status);
 }
 
 // Open-channel list per energy in ascending channel order (one workgroup per
@@ -319,7 +426,8 @@ void launch_asym(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, 
 __global__ __launch_bounds__(256) void k_openlist(const DevPW *__restrict__ tab, const int *__restrict__ pwi,
                                                   const double *__restrict__ E, int *__restrict__ nopen,
                                                   int *__restrict__ openidx, int *__restrict__ openpos,
-                                                  int *__restrict__ colpos, int8_t *__restrict__ openflag, long ld) {
+                                                  int *__restrict__ colpos, int8_t *__restrict__ openflag, long ld,
+                                                  int mqdt, double fnumin) {
   __shared__ int cnt[256];
   const int e = blockIdx.x, t = threadIdx.x;
   const DevPW &p = tab[pwi[e]];
@@ -329,7 +437,9 @@ __global__ __launch_bounds__(256) void k_openlist(const DevPW *__restrict__ tab,
   const int per = (n + 255) / 256;
   const int c0 = t * per, c1 = min(n, c0 + per);
   int c = 0;
-  for (int i = c0; i < c1; ++i) c += (Ev - ethr[i] > 0.0);
+  // "open" here: open, or (quantum-defect mode) a closed member channel
+  auto is_open = [&](int i) { return Ev - ethr[i] > 0.0 || (mqdt && mqdt_member(p.z, Ev - ethr[i], p.l[i], fnumin)); };
+  for (int i = c0; i < c1; ++i) c += is_open(i);
   cnt[t] = c;
   __syncthreads();
   // Hillis-Steele inclusive scan
@@ -342,7 +452,7 @@ __global__ __launch_bounds__(256) void k_openlist(const DevPW *__restrict__ tab,
   int pos = cnt[t] - c;
   const int nc = n - cnt[255];  // closed channels take the first columns of A
   for (int i = c0; i < c1; ++i) {
-    const bool op = Ev - ethr[i] > 0.0;
+    const bool op = is_open(i);
     openflag[(size_t)e * ld + i] = op ? 1 : 0;
     openpos[(size_t)e * ld + i] = op ? pos : -1;
     colpos[(size_t)e * ld + i] = op ? nc + pos : i - pos;
@@ -354,7 +464,7 @@ __global__ __launch_bounds__(256) void k_openlist(const DevPW *__restrict__ tab,
 void launch_openlist(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const double *E, int *nopen,
                      int *openidx, int *openpos, int *colpos, int8_t *openflag) {
   hipLaunchKernelGGL(k_openlist, dim3(L.ne), dim3(256), 0, s, tab, pwi, E, nopen, openidx, openpos, colpos, openflag,
-                     L.ldo);
+                     L.ldo, L.mqdt, L.fnumin);
 }
 
 }  // namespace rm

@@ -1,0 +1,232 @@
+// k_mqdt.hip -- multichannel quantum-defect operation on the fine mesh.
+//
+// PSTGF paper, section "Code Structure", stgf namelist, MQDT variables: with
+// iqdt = 1 every member channel is treated as open and the unphysical K is
+// computed on a coarse mesh (every |ieq|-th point, imode = -1); the fine mesh
+// is solved by interpolation.  A member channel is open or closed with
+// effective quantum number nu >= max(fnumin, l + 0.1) (iomsw = 1).  Closed
+// member channels carry the energy-analytic Coulomb pair (f, g) whose
+// decaying combination is f cos(pi nu) - g sin(pi nu) (k_asym.hip), so at a
+// fine energy the closed members are eliminated by
+//   K = Ku_oo - Ku_oc (Ku_cc + tan(pi nu))^-1 Ku_co.
+// That K is the tail of the solution of one linear system of the member
+// count m = n_c + n_o, unknowns ordered [X (closed members) | K (open)]:
+//   [ Ku_cc + tan(pi nu)  0 ] [X]   [Ku_co]
+//   [ Ku_oc               1 ] [K] = [Ku_oo],
+// which the batched LU with its tail back substitution solves unchanged
+// (k_linalg.hip): K is the last n_o rows, as in the physical path.
+#include "k_common.h"
+#include "rm.h"
+
+namespace rm {
+
+// Member count and flags (threshold, pole) of every energy of a mesh: one
+// thread per energy.  Poles are ascending, so a pole equal to E is found by
+// bisection.
+__global__ void k_mqdt_count(const double *__restrict__ ethr, const int *__restrict__ l,
+                             const double *__restrict__ Ek, int n, int M, double z, const double *__restrict__ E,
+                             int ne, double fnumin, double thr_guard, int *__restrict__ nmem, int *__restrict__ flag) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  const double Ev = E[e];
+  int m = 0, st = 0;
+  for (int i = 0; i < n; ++i) {
+    const double eps = Ev - ethr[i];
+    m += mqdt_member(z, eps, l[i], fnumin);
+    if (fabs(eps) < thr_guard) st |= RM_PT_THRESHOLD;
+  }
+  int lo = 0, hi = M;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (Ek[mid] < Ev) lo = mid + 1;
+    else hi = mid;
+  }
+  if (lo < M && Ek[lo] == Ev) st |= RM_PT_POLE;
+  nmem[e] = m;
+  flag[e] = st;
+}
+
+void launch_mqdt_count(hipStream_t s, const DevPW *pw, const double *E, int ne, double fnumin, double thr_guard,
+                       int *nmem, int *flag) {
+  if (ne <= 0) return;
+  hipLaunchKernelGGL(k_mqdt_count, dim3((ne + 127) / 128), dim3(128), 0, s, pw->ethr, pw->l, pw->Ek, pw->n, pw->M,
+                     pw->z, E, ne, fnumin, thr_guard, nmem, flag);
+}
+
+// Per energy of a chunk (one workgroup): each member channel's row and column
+// in the system above (syspos: closed members first, then open channels, each
+// in ascending channel order; -1 for other channels), its index in the
+// unphysical K (spos: ascending over the members), tan(pi nu) of closed
+// members, dims = {m, n_o}, nsys = m; threshold and pole flags are or-ed into
+// status.  The three counts are scanned together, packed 21 bits apiece.
+__global__ __launch_bounds__(256) void k_mqdt_setup(const DevPW *__restrict__ tab, const int *__restrict__ pwi,
+                                                    const double *__restrict__ E, long ldo, double fnumin,
+                                                    double thr_guard, int *__restrict__ syspos,
+                                                    int *__restrict__ spos, double *__restrict__ tanv,
+                                                    int *__restrict__ dims, int *__restrict__ nsys,
+                                                    int *__restrict__ status) {
+  __shared__ long long cnt[256];
+  __shared__ int flag;
+  const int e = blockIdx.x, t = threadIdx.x;
+  const DevPW &p = tab[pwi[e]];
+  const int n = p.n;
+  const double Ev = E[e], z = p.z;
+  const int per = (n + 255) / 256;
+  const int c0 = min(n, t * per), c1 = min(n, c0 + per);
+  constexpr long long ONE_O = 1LL << 21, ONE_M = 1LL << 42, MASK = (1LL << 21) - 1;
+  long long c = 0;
+  int st = 0;
+  for (int i = c0; i < c1; ++i) {
+    const double eps = Ev - p.ethr[i];
+    if (mqdt_member(z, eps, p.l[i], fnumin)) c += (eps > 0 ? ONE_O : 1LL) + ONE_M;
+    if (fabs(eps) < thr_guard) st |= RM_PT_THRESHOLD;
+  }
+  if (t == 0) {
+    flag = 0;
+    int lo = 0, hi = p.M;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (p.Ek[mid] < Ev) lo = mid + 1;
+      else hi = mid;
+    }
+    if (lo < p.M && p.Ek[lo] == Ev) st |= RM_PT_POLE;
+  }
+  cnt[t] = c;
+  __syncthreads();
+  if (st) atomicOr(&flag, st);
+  for (int off = 1; off < 256; off <<= 1) {
+    const long long v = t >= off ? cnt[t - off] : 0;
+    __syncthreads();
+    cnt[t] += v;
+    __syncthreads();
+  }
+  const long long tot = cnt[255], mine = cnt[t] - c;
+  const int ncm = (int)(tot & MASK), nop = (int)((tot >> 21) & MASK), nm = (int)(tot >> 42);
+  int pc = (int)(mine & MASK), po = (int)((mine >> 21) & MASK), pm = (int)(mine >> 42);
+  int *sp = syspos + (size_t)e * ldo, *mp = spos + (size_t)e * ldo;
+  double *tv = tanv + (size_t)e * ldo;
+  for (int i = c0; i < c1; ++i) {
+    const double eps = Ev - p.ethr[i];
+    if (!mqdt_member(z, eps, p.l[i], fnumin)) {
+      sp[i] = -1;
+      mp[i] = -1;
+      tv[i] = 0.0;
+      continue;
+    }
+    mp[i] = pm++;
+    if (eps > 0) {
+      sp[i] = ncm + po++;
+      tv[i] = 0.0;
+    } else {
+      sp[i] = pc++;
+      const double nu = z / sqrt(-eps);
+      tv[i] = sinpi(nu) / cospi(nu);
+    }
+  }
+  __syncthreads();
+  if (t == 0) {
+    dims[2 * e] = nm;
+    dims[2 * e + 1] = nop;
+    nsys[e] = nm;
+    if (flag) status[e] |= flag;
+  }
+}
+
+void launch_mqdt_setup(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const double *E,
+                       double thr_guard, int *syspos, int *spos, double *tanv, int *dims, int *nsys, int *status) {
+  hipLaunchKernelGGL(k_mqdt_setup, dim3(L.ne), dim3(256), 0, s, tab, pwi, E, L.ldo, L.fnumin, thr_guard, syspos, spos,
+                     tanv, dims, nsys, status);
+}
+
+// One workgroup per (member channel i, energy): the interpolated row of the
+// unphysical K, Ku(E) = sum_q w_q Ku(E_q) over the energy's coarse points
+// (cidx < 0: unused), written as row syspos[i] of the system and of its
+// right-hand sides.  Coarse matrices are [q][n][n] with the members in
+// ascending order.  An energy already flagged (threshold, pole, or a coarse
+// point it depends on) gets the identity system instead, so that the solve
+// adds no flags of its own; its outputs are NaN from the flag.
+__global__ __launch_bounds__(256) void k_mqdt_build(const DevPW *__restrict__ tab, const int *__restrict__ pwi,
+                                                    const int *__restrict__ syspos, const int *__restrict__ spos,
+                                                    const double *__restrict__ tanv, const int *__restrict__ nopen,
+                                                    const int *__restrict__ nsys, long ldo,
+                                                    const double *__restrict__ Kc, const int *__restrict__ cidx,
+                                                    const double *__restrict__ cw, const int *__restrict__ status,
+                                                    double *__restrict__ aug, long ldaug, long strideA, long roff) {
+  const int i = blockIdx.x, e = blockIdx.y;
+  const DevPW &p = tab[pwi[e]];
+  const int n = p.n;
+  if (i >= n) return;
+  const int *sp = syspos + (size_t)e * ldo, *mp = spos + (size_t)e * ldo;
+  const int ri = sp[i];
+  if (ri < 0) return;
+  const int ncm = nsys[e] - nopen[e];
+  const bool iopen = ri >= ncm;
+  const double ti = tanv[(size_t)e * ldo + i];
+  const size_t nn = (size_t)n * n;
+  const double *rowq[4];
+  double wq[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int c = cidx[4 * e + q];
+    wq[q] = c >= 0 ? cw[4 * e + q] : 0.0;
+    rowq[q] = Kc + (c >= 0 ? c : 0) * nn + (size_t)mp[i] * n;
+  }
+  double *row = aug + (size_t)e * strideA + (size_t)ri * ldaug;
+  if (status[e]) {
+    for (int j = threadIdx.x; j < n; j += 256) {
+      const int rj = sp[j];
+      if (rj < 0) continue;
+      row[rj] = i == j ? 1.0 : 0.0;
+      if (rj >= ncm) row[roff + (rj - ncm)] = 0.0;
+    }
+    return;
+  }
+  for (int j = threadIdx.x; j < n; j += 256) {
+    const int rj = sp[j];
+    if (rj < 0) continue;
+    const int sj = mp[j];
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v += wq[q] * rowq[q][sj];
+    const bool jopen = rj >= ncm;
+    if (jopen) {
+      row[roff + (rj - ncm)] = v;
+      row[rj] = (iopen && i == j) ? 1.0 : 0.0;
+    } else {
+      row[rj] = (!iopen && i == j) ? v + ti : v;
+    }
+  }
+}
+
+void launch_mqdt_build(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *syspos,
+                       const int *spos, const double *tanv, const int *nopen, const int *nsys, const double *Kc,
+                       const int *cidx, const double *cw, const int *status, double *aug) {
+  hipLaunchKernelGGL(k_mqdt_build, dim3(L.nmax, L.ne), dim3(256), 0, s, tab, pwi, syspos, spos, tanv, nopen, nsys,
+                     L.ldo, Kc, cidx, cw, status, aug, L.ldaug, L.sA, L.roff);
+}
+
+// K = the last n_o rows of the system's solution (rows m - n_o .. m), into the
+// K workspace, and dims = {n_o, n_o} for the S/Omega stage.
+__global__ __launch_bounds__(256) void k_mqdt_gather(const int *__restrict__ nsys, const int *__restrict__ nopen,
+                                                     const double *__restrict__ aug, long ldaug, long strideA,
+                                                     long roff, double *__restrict__ Kw, long ldk, long strideK,
+                                                     int *__restrict__ dims, int nmax) {
+  const int e = blockIdx.y, i = blockIdx.x;
+  const int no = nopen[e], m = nsys[e];
+  if (i == 0 && threadIdx.x == 0) {
+    dims[2 * e] = no;
+    dims[2 * e + 1] = no;
+  }
+  if (i >= nmax) return;
+  const double *Y = aug + (size_t)e * strideA + (size_t)(m - no + (i < no ? i : 0)) * ldaug + roff;
+  double *K = Kw + (size_t)e * strideK + (size_t)i * ldk;
+  for (int j = threadIdx.x; j < nmax; j += 256) K[j] = (i < no && j < no) ? Y[j] : 0.0;
+}
+
+void launch_mqdt_gather(hipStream_t s, const Lay &L, const int *nsys, const int *nopen, const double *aug,
+                        double *Kw, int *dims) {
+  hipLaunchKernelGGL(k_mqdt_gather, dim3(L.nmax, L.ne), dim3(256), 0, s, nsys, nopen, aug, L.ldaug, L.sA, L.roff,
+                     Kw, L.ldk, L.sK, dims, L.nmax);
+}
+
+}  // namespace rm

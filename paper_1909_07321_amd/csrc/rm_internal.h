@@ -105,7 +105,21 @@ struct Lay {
   int npadc = 0;                // largest npad of the chunk's coupled waves (0: none)
   int lamc = 0;                 // largest multipole order of the chunk's coupled waves
   long zrb = 0, sZ = 0;         // propagation matrices (tiled): zrb = npadc / 64 row blocks, sZ = 2 npadc^2
+  // quantum-defect mode of the channel split and the asymptotic functions:
+  // closed channels with nu >= max(fnumin, l + 0.1) are treated as open
+  // (unphysical K); 0 for the physical path
+  int mqdt = 0;
+  double fnumin = 0;
 };
+
+// Member channel of the unphysical K (stgf MQDT variables iomsw = 1, fnumin):
+// open, or closed with effective quantum number nu = z / sqrt(-eps) >=
+// max(fnumin, l + 0.1), i.e. eps >= -z^2 / numin^2.  Decided in double.
+__host__ __device__ inline bool mqdt_member(double z, double eps, int l, double fnumin) {
+  if (eps > 0) return true;
+  const double numin = fnumin > l + 0.1 ? fnumin : l + 0.1;
+  return eps >= -(z * z) / (numin * numin);
+}
 
 // One task of the R contraction: energies [e0, e0 + m) (m <= the tile shape's eb,
 // one partial wave, table slot `slot`) times one lower-triangle tile of the shape.
@@ -213,6 +227,15 @@ void launch_prop_gather(hipStream_t s, const Lay &L, const DevPW *tab, const int
                         const int *status, const double *pz, int q, double *out, long ldo, long so);
 // K = the last nopen rows of the solution (the open channels, ascending), as
 // solved, zero past nopen; dims = {nopen, nopen}.
+void launch_mqdt_count(hipStream_t s, const DevPW *pw, const double *E, int ne, double fnumin, double thr_guard,
+                       int *nmem, int *flag);
+void launch_mqdt_setup(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const double *E,
+                       double thr_guard, int *syspos, int *spos, double *tanv, int *dims, int *nsys, int *status);
+void launch_mqdt_build(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *syspos,
+                       const int *spos, const double *tanv, const int *nopen, const int *nsys, const double *Kc,
+                       const int *cidx, const double *cw, const int *status, double *aug);
+void launch_mqdt_gather(hipStream_t s, const Lay &L, const int *nsys, const int *nopen, const double *aug,
+                        double *Kw, int *dims);
 void launch_gatherK(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *nopen,
                     const double *aug, double *Kw, int *dims);
 void launch_omega(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *openpos,

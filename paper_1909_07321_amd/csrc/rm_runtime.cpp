@@ -15,6 +15,7 @@
 #include <array>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstdio>
 #include <cctype>
@@ -2126,6 +2127,264 @@ rm_status rm_prof_chunks(rm_ctx *ctx, int64_t cap, double *ms, double *model_flo
   }
   *count = (int64_t)mine.size();
   return st;
+}
+
+
+}  // extern "C"
+
+// ------------------------------------------------- quantum-defect operation
+namespace {
+
+// Device temporaries of one call, freed on every return path.
+struct DevTmp {
+  std::vector<void *> p;
+  template <typename T>
+  T *get(size_t count) {
+    void *q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return nullptr;
+    p.push_back(q);
+    return (T *)q;
+  }
+  ~DevTmp() {
+    for (void *q : p) (void)hipFree(q);
+  }
+};
+
+rm_status mqdt_check(rm_ctx *ctx, const DevPW *pw, double fnumin) {
+  if (pw->lamax) {
+    ctx->err = "quantum-defect operation: waves with a long-range coupling are not supported";
+    return RM_E_ARG;
+  }
+  if (!(pw->z > 0)) {
+    ctx->err = "quantum-defect operation needs a charged target (z > 0)";
+    return RM_E_ARG;
+  }
+  if (!(fnumin >= 0) || !std::isfinite(fnumin)) {
+    ctx->err = "fnumin must be finite and >= 0";
+    return RM_E_ARG;
+  }
+  return RM_OK;
+}
+
+// Unphysical K at energies E (host or device as o says) on ctx->sync: the
+// physical pipeline with the channel split and the asymptotic functions in
+// quantum-defect mode.  Ku [ne][n][n] and nmember / status [ne] are written
+// with the copy kinds given.
+rm_status mqdt_coarse(rm_ctx *ctx, const DevPW *pw, const double *E, int ne, const rm_opts &o, double fnumin,
+                             double *Ku, hipMemcpyKind kK, int32_t *nmember, int32_t *status, hipMemcpyKind kS) {
+  const hipStream_t s = ctx->sync.stream;
+  const int cap = staged_cap(ctx, pw, ne);
+  const int n = pw->n;
+  for (int e0 = 0; e0 < ne; e0 += cap) {
+    const int m = std::min(cap, ne - e0);
+    Plan P;
+    std::vector<Seg> segs;
+    if (rm_status st = staged_chunk(ctx, pw, E, e0, m, o, false, P, segs)) return st;
+    P.L.mqdt = 1;
+    P.L.fnumin = fnumin;
+    Work &w = ctx->sync.w;
+    const Lay &L = P.L;
+    launch_fill_int(s, w.status, m, 0);
+    launch_openlist(s, L, w.tab, w.pwi, w.E, w.nopen, w.openidx, w.openpos, w.colpos, w.openflag);
+    launch_asym(s, L, w.tab, w.pwi, w.E, o.thr_guard, w.fg, w.status);
+    stage_R(ctx, P, w, o, s);
+    stage_K(P, w, s);
+    launch_finalize(s, L, w.tab, w.pwi, w.status, nullptr, w.Kw, nullptr);
+    HIPCHK(hipMemcpy2DAsync(Ku + (size_t)e0 * n * n, sizeof(double) * n, w.Kw, sizeof(double) * L.ldk,
+                            sizeof(double) * n, (size_t)m * n, kK, s));
+    HIPCHK(hipMemcpyAsync(nmember + e0, w.nopen, sizeof(int) * m, kS, s));
+    HIPCHK(hipMemcpyAsync(status + e0, w.status, sizeof(int) * m, kS, s));
+    HIPCHK(hipGetLastError());
+  }
+  return RM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rm_status rm_mqdt_unphysical_K(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, double fnumin,
+                               const rm_opts *opts, double *Ku, int32_t *nmember, int32_t *status) {
+  if (!ctx || ne < 0 || (ne > 0 && (!E || !Ku || !nmember || !status))) return RM_E_ARG;
+  const DevPW *pw;
+  if (rm_status st = get_pw(ctx, pwid, &pw)) return st;
+  if (rm_status st = mqdt_check(ctx, pw, fnumin)) return st;
+  if (ne == 0) return RM_OK;
+  (void)hipSetDevice(ctx->device);
+  const rm_opts o = fixed_opts(opts);
+  hipEvent_t ev;
+  if (rm_status st = staged_enter(ctx, o, ev)) return st;
+  if (rm_status st = mqdt_coarse(ctx, pw, E, ne, o, fnumin, Ku, kind_out(o), nmember, status, kind_out(o))) return st;
+  return staged_leave(ctx, o, ev);
+}
+
+rm_status rm_run_mqdt(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, int32_t ieq, double fnumin,
+                      const rm_opts *opts, double *omega, double *K, int8_t *coarse, int32_t *status) {
+  if (!ctx || ne < 0 || (ne > 0 && (!E || !omega || !status))) return RM_E_ARG;
+  if (ieq < 1) {
+    ctx->err = "ieq: the coarse step must be >= 1 mesh points";
+    return RM_E_ARG;
+  }
+  const DevPW *pw;
+  if (rm_status st = get_pw(ctx, pwid, &pw)) return st;
+  if (rm_status st = mqdt_check(ctx, pw, fnumin)) return st;
+  if (ne == 0) return RM_OK;
+  (void)hipSetDevice(ctx->device);
+  const rm_opts o = fixed_opts(opts);
+  hipEvent_t ev;
+  if (rm_status st = staged_enter(ctx, o, ev)) return st;
+  const hipStream_t s = ctx->sync.stream;
+  const int n = pw->n, nt = pw->nt;
+  DevTmp tmp;
+  // 1. the mesh on the host and the device; member counts and flags
+  std::vector<double> hE(ne);
+  HIPCHK(hipMemcpyAsync(hE.data(), E, sizeof(double) * ne, o.device_ptrs ? hipMemcpyDeviceToHost : hipMemcpyHostToHost,
+                        s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int e = 1; e < ne; ++e)
+    if (!(hE[e] > hE[e - 1])) {
+      ctx->err = "rm_run_mqdt: the energy mesh must be strictly ascending";
+      (void)hipEventDestroy(ev);
+      return RM_E_ARG;
+    }
+  double *dE = tmp.get<double>(ne);
+  int *dcnt = tmp.get<int>(2 * (size_t)ne);
+  if (!dE || !dcnt) {
+    ctx->err = "rm_run_mqdt: device temporaries";
+    return RM_E_NOMEM;
+  }
+  HIPCHK(hipMemcpyAsync(dE, hE.data(), sizeof(double) * ne, hipMemcpyHostToDevice, s));
+  launch_mqdt_count(s, pw, dE, ne, fnumin, o.thr_guard, dcnt, dcnt + ne);
+  std::vector<int> nm(ne), flag(ne);
+  HIPCHK(hipMemcpyAsync(nm.data(), dcnt, sizeof(int) * ne, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(flag.data(), dcnt + ne, sizeof(int) * ne, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  // 2. runs of equal member count (the member set only grows with E) and
+  // their coarse points: every ieq-th point from the run's first and the
+  // run's last, unflagged; a run whose coarse candidates are all flagged has
+  // every unflagged point coarse
+  std::vector<int> run0(ne), run1(ne);
+  std::vector<char> isc(ne, 0);
+  for (int s0 = 0; s0 < ne;) {
+    int s1 = s0 + 1;
+    while (s1 < ne && nm[s1] == nm[s0]) ++s1;
+    bool any = false;
+    for (int j = s0; j < s1; ++j) {
+      run0[j] = s0;
+      run1[j] = s1;
+      if (((j - s0) % ieq == 0 || j == s1 - 1) && !flag[j]) isc[j] = 1, any = true;
+    }
+    if (!any)
+      for (int j = s0; j < s1; ++j)
+        if (!flag[j]) isc[j] = 1;
+    s0 = s1;
+  }
+  std::vector<int> cpos(ne, -1);
+  std::vector<double> cE;
+  for (int e = 0; e < ne; ++e)
+    if (isc[e]) {
+      cpos[e] = (int)cE.size();
+      cE.push_back(hE[e]);
+    }
+  const int nc = (int)cE.size();
+  // 3. unphysical K at the coarse points, kept on the device
+  double *Kc = tmp.get<double>((size_t)std::max(nc, 1) * n * n);
+  if (!Kc) {
+    ctx->err = "rm_run_mqdt: device memory for the coarse unphysical K";
+    return RM_E_NOMEM;
+  }
+  std::vector<int32_t> cnm(nc), cst(nc);
+  if (nc) {
+    rm_opts oc = o;
+    oc.device_ptrs = 0;
+    if (rm_status st = mqdt_coarse(ctx, pw, cE.data(), nc, oc, fnumin, Kc, hipMemcpyDeviceToDevice, cnm.data(),
+                                   cst.data(), hipMemcpyDeviceToHost))
+      return st;
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  // 4. stencils: the four coarse points of the run around each point (window
+  // from the coarse point before the last one at or below it, clamped to the
+  // run), Lagrange weights, and the flags of the point and of its coarse points
+  std::vector<int> hc(4 * (size_t)ne, -1);
+  std::vector<double> hw(4 * (size_t)ne, 0.0);
+  std::vector<int> st0(ne);
+  for (int e = 0; e < ne; ++e) {
+    int st = flag[e];
+    if (!st) {
+      std::vector<int> cl;
+      for (int j = run0[e]; j < run1[e]; ++j)
+        if (isc[j]) cl.push_back(j);
+      const int m = (int)cl.size();
+      int k = 0;
+      for (int q = 0; q < m; ++q)
+        if (cl[q] <= e) k = q;
+      const int w = std::min(m, 4);
+      const int a0 = std::max(0, std::min(k - 1, m - w));
+      for (int q = 0; q < w; ++q) {
+        const int cq = cl[a0 + q];
+        double wt = 1.0;
+        for (int r = 0; r < w; ++r)
+          if (r != q) wt *= (hE[e] - hE[cl[a0 + r]]) / (hE[cq] - hE[cl[a0 + r]]);
+        hc[4 * e + q] = cpos[cq];
+        hw[4 * e + q] = wt;
+        st |= cst[cpos[cq]];
+      }
+    }
+    st0[e] = st;
+  }
+  if (coarse) {
+    std::vector<int8_t> c8(isc.begin(), isc.end());
+    HIPCHK(hipMemcpyAsync(coarse, c8.data(), ne, kind_out(o) == hipMemcpyDeviceToDevice ? hipMemcpyHostToDevice
+                                                                                       : hipMemcpyHostToHost,
+                          s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  int *dci = tmp.get<int>(4 * (size_t)ne + ne);
+  double *dcw = tmp.get<double>(4 * (size_t)ne);
+  const int cap = staged_cap(ctx, pw, ne);
+  const long ldo = n;
+  int *dsys = tmp.get<int>(2 * (size_t)cap * ldo + cap);
+  double *dtan = tmp.get<double>((size_t)cap * ldo);
+  if (!dci || !dcw || !dsys || !dtan) {
+    ctx->err = "rm_run_mqdt: device temporaries";
+    return RM_E_NOMEM;
+  }
+  HIPCHK(hipMemcpyAsync(dci, hc.data(), sizeof(int) * 4 * ne, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(dci + 4 * (size_t)ne, st0.data(), sizeof(int) * ne, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(dcw, hw.data(), sizeof(double) * 4 * ne, hipMemcpyHostToDevice, s));
+  // 5. the fine mesh in chunks: interpolate, eliminate the closed members
+  // through the batched LU, then S and Omega as in the physical path
+  for (int e0 = 0; e0 < ne; e0 += cap) {
+    const int m = std::min(cap, ne - e0);
+    Plan P;
+    std::vector<Seg> segs;
+    if (rm_status st = staged_chunk(ctx, pw, E, e0, m, o, false, P, segs)) return st;
+    Work &w = ctx->sync.w;
+    const Lay &L = P.L;
+    Lay Lq = L;
+    Lq.mqdt = 1;
+    Lq.fnumin = fnumin;
+    int *syspos = dsys, *spos = dsys + (size_t)cap * ldo, *nsys = dsys + 2 * (size_t)cap * ldo;
+    HIPCHK(hipMemcpyAsync(w.status, dci + 4 * (size_t)ne + e0, sizeof(int) * m, hipMemcpyDeviceToDevice, s));
+    launch_openlist(s, L, w.tab, w.pwi, w.E, w.nopen, w.openidx, w.openpos, w.colpos, w.openflag);
+    launch_mqdt_setup(s, Lq, w.tab, w.pwi, w.E, o.thr_guard, syspos, spos, dtan, w.dims, nsys, w.status);
+    launch_mqdt_build(s, L, w.tab, w.pwi, syspos, spos, dtan, w.nopen, nsys, Kc, dci + 4 * (size_t)e0,
+                      dcw + 4 * (size_t)e0, w.status, w.aug);
+    launch_lu_solve(s, L.ne, L.nmax, L.nmax, w.dims, w.aug, L.ldaug, L.sA, L.roff, w.ipiv, L.ldo, w.bperm, w.linv, 1,
+                    w.status);
+    launch_mqdt_gather(s, L, nsys, w.nopen, w.aug, w.Kw, w.dims);
+    stage_SO(P, w, false, s);
+    launch_finalize(s, L, w.tab, w.pwi, w.status, w.omega, K ? w.Kw : nullptr, nullptr);
+    HIPCHK(hipMemcpyAsync(omega + (size_t)e0 * nt * nt, w.omega, sizeof(double) * m * nt * nt, kind_out(o), s));
+    if (K)
+      HIPCHK(hipMemcpy2DAsync(K + (size_t)e0 * n * n, sizeof(double) * n, w.Kw, sizeof(double) * L.ldk,
+                              sizeof(double) * n, (size_t)m * n, kind_out(o), s));
+    HIPCHK(hipMemcpyAsync(status + e0, w.status, sizeof(int) * m, kind_out(o), s));
+    HIPCHK(hipGetLastError());
+  }
+  // the temporaries are freed on return: the work that reads them completes first
+  HIPCHK(hipStreamSynchronize(s));
+  return staged_leave(ctx, o, ev);
 }
 
 }  // extern "C"

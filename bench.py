@@ -269,6 +269,7 @@ def config_measure(ctx) -> dict:
     pws, E = synth.config_imbalance()
     out["imbalance"] = imbalance_measure(ctx, pws, E)
     out["coupled"] = coupled_measure(ctx)
+    out["mqdt"] = mqdt_measure(ctx)
     return out
 
 
@@ -318,6 +319,55 @@ def coupled_measure(ctx) -> dict:
     log(f"coupled: {res['points_per_s']:.0f} points/s over {dt:.2f}s; propagation {pr_ms:.1f} ms "
         f"({achieved:.2f} TFLOP/s model, {100 * achieved / PEAK['f64']:.1f}% of the FP64 peak); stages "
         + ", ".join(f"{k}={v:.1f}ms" for k, v in res["stage_ms"].items()))
+    return res
+
+
+def mqdt_measure(ctx) -> dict:
+    """The quantum-defect workload (200 channels, 2000 energies in the 0.5 Ry
+    below the highest threshold, coarse step 8): fine-mesh points/s of
+    rm_run_mqdt against rm_run on the same mesh, and the interpolated K and
+    Omega against the direct ones (at the points that are not coarse)."""
+    import numpy as np
+    import torch
+
+    from paper_1909_07321_amd import rm, synth
+
+    pw, E, ieq, fnumin = synth.config_mqdt()
+    pid = ctx.pw_upload(pw)
+    Ed = torch.tensor(E, dtype=torch.float64, device="cuda")
+    ctx.run_mqdt(pid, Ed[:64], ieq, fnumin)  # warm-up: workspace and code
+    _, Kw, _ = ctx.run(pid, Ed[:64])
+    torch.cuda.synchronize()
+    del Kw
+    t1 = time.perf_counter()
+    om, K, co, st = ctx.run_mqdt(pid, Ed, ieq, fnumin)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    om2, K2, st2 = ctx.run(pid, Ed)
+    torch.cuda.synchronize()
+    dt2 = time.perf_counter() - t1
+    om, K, co, st = (x.cpu().numpy() for x in (om, K, co, st))
+    om2, K2, st2 = (x.cpu().numpy() for x in (om2, K2, st2))
+    no = (E[:, None] - pw.e_thr[None, :] > 0).sum(axis=1)
+    fine = (co == 0) & (st == 0) & (st2 == 0)
+    ek = np.array([np.abs(K[e, :no[e], :no[e]] - K2[e, :no[e], :no[e]]).max() /
+                   max(1.0, np.abs(K2[e, :no[e], :no[e]]).max()) for e in np.flatnonzero(fine)])
+    top = np.abs(om2).reshape(E.size, -1).max(axis=1)
+    eo = (np.abs(om - om2).reshape(E.size, -1).max(axis=1) / np.maximum(top, 1e-300))[fine]
+    ctx.pw_release(pid)
+    res = dict(points_per_s=E.size / dt, seconds=dt, direct_points_per_s=E.size / dt2, direct_seconds=dt2,
+               speedup=dt2 / dt, coarse_points=int(co.sum()), flagged_energies=int((st != 0).sum()),
+               K_err_vs_direct=dict(median=float(np.median(ek)), p99=float(np.quantile(ek, 0.99)), max=float(ek.max())),
+               omega_err_vs_direct=dict(median=float(np.median(eo)), p99=float(np.quantile(eo, 0.99)),
+                                        max=float(eo.max())),
+               workload=f"one wave, {pw.nchan} channels, {pw.npole} poles in [5, 60] Ry, {E.size} energies in "
+                        f"[{E[0]:.4f}, {E[-1]:.4f}] Ry (0.5 Ry below the highest threshold), coarse step {ieq}, "
+                        f"fnumin {fnumin:.3f}, FP64")
+    log(f"mqdt: {res['points_per_s']:.0f} points/s over {dt:.2f}s ({res['coarse_points']} coarse of {E.size}) against "
+        f"{res['direct_points_per_s']:.0f} points/s direct ({res['speedup']:.2f}x); K vs direct median "
+        f"{res['K_err_vs_direct']['median']:.1e} max {res['K_err_vs_direct']['max']:.1e}, Omega median "
+        f"{res['omega_err_vs_direct']['median']:.1e} max {res['omega_err_vs_direct']['max']:.1e}")
     return res
 
 
@@ -399,6 +449,8 @@ def main() -> int:
                     help="keep the default R tile shapes instead of running the tile autotuner first")
     ap.add_argument("--coupled-only", action="store_true",
                     help="run only the coupled-wave (Numerov propagation) measurement and print its JSON block")
+    ap.add_argument("--mqdt-only", action="store_true",
+                    help="only the quantum-defect workload (coarse/fine mesh against the direct path)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a 1 GiB read + 1 GiB write kernel (HBM counter calibration under rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -427,6 +479,11 @@ def main() -> int:
     if args.coupled_only:
         ctx = rm.Context(0)
         print(json.dumps({"coupled": coupled_measure(ctx)}), flush=True)
+        ctx.close()
+        return 0
+    if args.mqdt_only:
+        ctx = rm.Context(0)
+        print(json.dumps({"mqdt": mqdt_measure(ctx)}), flush=True)
         ctx.close()
         return 0
 

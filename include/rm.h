@@ -218,20 +218,25 @@ rm_status rm_mqdt_unphysical_K(rm_ctx *ctx, int32_t pw, const double *E, int32_t
 /* Coarse/fine operation on a strictly ascending mesh E[0..ne).  The mesh
    splits into runs of equal member set (the set grows with E).  In each run
    the coarse points are every ieq-th point from its first and its last
-   point, leaving out points flagged at a threshold or a pole (a run whose
-   candidates are all flagged has every unflagged point coarse); there the
-   unphysical K is computed in full.  Each point takes the elementwise
-   Lagrange interpolant of Ku through the four coarse points of its run
-   around it (the window starts at the coarse point before the last one at
-   or below it, clamped to the run; all of them if fewer than four), its
-   closed members are eliminated as above on the GPU (a batched LU of the
-   member count), and S, T and Omega follow as in rm_run.  At coarse points
-   the result is the physical one (up to rounding).  Outputs as rm_run
+   point, leaving out points flagged at a threshold or a pole and points where
+   a closed member has |sin(pi nu)| < 1e-6 (there g cancels); a run whose
+   candidates all fail that has every remaining point coarse, and a run with
+   none is flagged RM_PT_NOCONV.  At coarse points the unphysical K is
+   computed in full and kept as X + iY = (1 - i Ku)^-1 = (1 + S_u)/2 (iqdt = 1:
+   the unphysical S is interpolated, not K, which has poles where an
+   eigenphase passes pi/2).  Each point takes the elementwise Lagrange
+   interpolant of X and Y through the four coarse points of its run around it
+   (the window starts at the coarse point before the last one at or below it,
+   clamped to the run; all of them if fewer than four), recovers Ku = Y X^-1
+   (a batched LU of the member count; symmetrised, as the interpolant keeps it
+   symmetric only to the interpolation error), eliminates its closed members as above
+   (a second batched LU), and S, T and Omega follow as in rm_run.  At coarse
+   points the result is the physical one (up to rounding).  Outputs as rm_run
    (omega [ne][nt][nt], K [ne][n][n] or NULL, status [ne]); coarse [ne] int8
    (may be NULL) marks the coarse points.  A point inherits the flags of the
    coarse points it is interpolated from.  ieq < 1 or a mesh that is not
-   strictly ascending: RM_E_ARG.  The call allocates device temporaries (the
-   coarse Ku: ncoarse n^2 doubles) and returns after its work is complete. */
+   strictly ascending: RM_E_ARG.  The call allocates device temporaries
+   (3 ncoarse n^2 doubles) and returns after its work is complete. */
 rm_status rm_run_mqdt(rm_ctx *ctx, int32_t pw, const double *E, int32_t ne, int32_t ieq, double fnumin,
                       const rm_opts *opts, double *omega, double *K, int8_t *coarse, int32_t *status);
 

@@ -1201,8 +1201,12 @@ int rmo_run_coupled(const rmo_pw *pw, const rmo_coupling *cp, const double *E, i
 /*    (s = f / (1 - exp(-2 pi z / k))^(1/2) above it).                         */
 /*  - unphysical K: eq. (match) with every member channel treated as open:    */
 /*    F = f + g Kun on members (s, c for open members), e X on the others.     */
-/*  - fine mesh: Kun interpolated elementwise in energy (Lagrange, the four    */
-/*    nearest coarse energies of the same member set), then                    */
+/*  - fine mesh (iqdt = 1: the unphysical S is interpolated, not K, whose     */
+/*    poles no polynomial follows): at the coarse points M^-1 = (1 - i Kun)^-1 */
+/*    (so S = 2 M^-1 - 1); its real and imaginary parts X, Y are interpolated  */
+/*    elementwise in energy (Lagrange, the four nearest coarse energies of the */
+/*    same member set); the unphysical K of the fine point is Y X^-1,          */
+/*    symmetrised, and                                                         */
 /*    K = Kun_oo - Kun_oc (Kun_cc + tan(pi nu))^-1 Kun_co.                     */
 /* ------------------------------------------------------------------------- */
 
@@ -1317,7 +1321,23 @@ static int mqdt_channel_fn(ld z, double eps_d, ld a, int l, double fnumin, ld ou
   out[1] = fp;
   out[2] = -e / W + f * cot;
   out[3] = -ep / W + fp * cot;
+  /* at an integer nu (a bound state of the Coulomb potential) g is 0 x infinity */
+  if (!isfinite((double)out[2]) || !isfinite((double)out[3])) return -1;
   return 1;
+}
+
+/* 1 if a closed member channel's effective quantum number is within 1e-6 of
+   an integer in sin(pi nu), where the pair's g cancels to fewer than ten
+   digits: such energies are not used as coarse points. */
+static int mqdt_near_integer(const rmo_pw *pw, double E, double fnumin) {
+  for (int i = 0; i < pw->nchan; ++i) {
+    const double eps = E - pw->e_thr[i];
+    if (eps > 0 || !mqdt_member(pw->z, eps, pw->l[i], fnumin)) continue;
+    ld s, c;
+    sincos_pi((ld)pw->z / sqrtl(-(ld)eps), &s, &c);
+    if (fabsl(s) < 1e-6L) return 1;
+  }
+  return 0;
 }
 
 int rmo_mqdt_channel(double z, double eps, double a, int32_t l, double fnumin, double out[4]) {
@@ -1482,15 +1502,72 @@ int rmo_mqdt_eliminate(const rmo_pw *pw, const double *E, int32_t ne, double fnu
   return 0;
 }
 
+/* (1 - i K)^-1 of the leading m x m block of K (row stride n) by complex
+   Gauss-Jordan elimination with partial pivoting; X, Y (row stride n) get its
+   real and imaginary parts.  Returns -1 for a zero pivot. */
+static int mqdt_minv(const double *K, int n, int m, ld *X, ld *Y) {
+  cld *A = (cld *)malloc(sizeof(cld) * ((size_t)m * m + 1));
+  cld *B = (cld *)malloc(sizeof(cld) * ((size_t)m * m + 1));
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) {
+      A[(size_t)i * m + j] = (i == j ? 1.0L : 0.0L) - I * (ld)K[(size_t)i * n + j];
+      B[(size_t)i * m + j] = i == j ? 1.0L : 0.0L;
+    }
+  int bad = 0;
+  for (int c = 0; c < m && !bad; ++c) {
+    int p = c;
+    for (int r = c + 1; r < m; ++r)
+      if (cabsl(A[(size_t)r * m + c]) > cabsl(A[(size_t)p * m + c])) p = r;
+    if (cabsl(A[(size_t)p * m + c]) == 0) {
+      bad = 1;
+      break;
+    }
+    for (int j = 0; j < m; ++j) {
+      cld t = A[(size_t)c * m + j];
+      A[(size_t)c * m + j] = A[(size_t)p * m + j];
+      A[(size_t)p * m + j] = t;
+      t = B[(size_t)c * m + j];
+      B[(size_t)c * m + j] = B[(size_t)p * m + j];
+      B[(size_t)p * m + j] = t;
+    }
+    const cld d = A[(size_t)c * m + c];
+    for (int j = 0; j < m; ++j) {
+      A[(size_t)c * m + j] /= d;
+      B[(size_t)c * m + j] /= d;
+    }
+    for (int r = 0; r < m; ++r) {
+      if (r == c) continue;
+      const cld f = A[(size_t)r * m + c];
+      if (f == 0) continue;
+      for (int j = 0; j < m; ++j) {
+        A[(size_t)r * m + j] -= f * A[(size_t)c * m + j];
+        B[(size_t)r * m + j] -= f * B[(size_t)c * m + j];
+      }
+    }
+  }
+  for (int i = 0; i < m && !bad; ++i)
+    for (int j = 0; j < m; ++j) {
+      X[(size_t)i * n + j] = creall(B[(size_t)i * m + j]);
+      Y[(size_t)i * n + j] = cimagl(B[(size_t)i * m + j]);
+    }
+  free(A);
+  free(B);
+  return bad ? -1 : 0;
+}
+
 /* Coarse/fine operation over an ascending mesh E[0..ne).  The mesh splits into
    runs with the same member set (it only grows with E).  In each run the
    coarse points are every ieq-th point from the run's first and the run's
    last point, minus points flagged at a threshold or a pole; a run with
-   unflagged points but no unflagged coarse point is solved fully.  Each fine
-   point takes the Lagrange interpolant through the four coarse points of its
-   run around it (window start: the coarse point before the last coarse point
-   at or below it, clamped to the run's coarse list; all of them if fewer than
-   four).  coarse[e] (may be NULL) is set to 1 at coarse points. */
+   unflagged points but no unflagged coarse point is solved fully.  Points where
+   a closed member's |sin(pi nu)| < 1e-6 are never coarse (g cancels there);
+   a run left without a coarse point is flagged RMO_PT_NOCONV.  Each fine
+   point takes the Lagrange interpolant of Re and Im of (1 - i Kun)^-1 through
+   the four coarse points of its run around it (window start: the coarse point
+   before the last coarse point at or below it, clamped to the run's coarse
+   list; all of them if fewer than four), its unphysical K is Y X^-1 of the
+   interpolated parts X, Y, and the closed members are eliminated.  coarse[e]
+   (may be NULL) is set to 1 at coarse points. */
 int rmo_mqdt_run(const rmo_pw *pw, const double *E, int32_t ne, int32_t ieq, double fnumin, double thr_guard,
                  double *omega, double *K, int8_t *coarse, int32_t *status, int32_t nthreads) {
   if (ieq < 1 || pw->z <= 0) return -1;
@@ -1501,10 +1578,12 @@ int rmo_mqdt_run(const rmo_pw *pw, const double *E, int32_t ne, int32_t ieq, dou
   int *ns = (int *)malloc(sizeof(int) * (ne + 1));
   int *flag = (int *)malloc(sizeof(int) * (ne + 1));
   int *isc = (int *)calloc(ne + 1, sizeof(int));
+  int *avoid = (int *)calloc(ne + 1, sizeof(int));
   int *mem = (int *)malloc(sizeof(int) * (n + 1));
   for (int e = 0; e < ne; ++e) {
     ns[e] = mqdt_members(pw, E[e], fnumin, mem);
     flag[e] = mqdt_flags(pw, E[e], thr_guard);
+    avoid[e] = mqdt_near_integer(pw, E[e], fnumin);
   }
   free(mem);
   for (int s0 = 0; s0 < ne;) {
@@ -1512,22 +1591,26 @@ int rmo_mqdt_run(const rmo_pw *pw, const double *E, int32_t ne, int32_t ieq, dou
     while (s1 < ne && ns[s1] == ns[s0]) ++s1;
     int any = 0;
     for (int j = s0; j < s1; ++j)
-      if (((j - s0) % ieq == 0 || j == s1 - 1) && !flag[j]) isc[j] = 1, any = 1;
+      if (((j - s0) % ieq == 0 || j == s1 - 1) && !flag[j] && !avoid[j]) isc[j] = 1, any = 1;
     if (!any)
       for (int j = s0; j < s1; ++j)
-        if (!flag[j]) isc[j] = 1;
+        if (!flag[j] && !avoid[j]) isc[j] = 1;
     s0 = s1;
   }
+  free(avoid);
   if (coarse)
     for (int e = 0; e < ne; ++e) coarse[e] = (int8_t)isc[e];
   /* unphysical K at the coarse points */
   double *Kc = (double *)malloc(sizeof(double) * (size_t)ne * nn);
+  ld *Xc = (ld *)calloc((size_t)ne * nn + 1, sizeof(ld)), *Yc = (ld *)calloc((size_t)ne * nn + 1, sizeof(ld));
   int32_t *stc = (int32_t *)calloc(ne + 1, sizeof(int32_t));
   set_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 1)
   for (int e = 0; e < ne; ++e) {
     int m = 0;
-    if (isc[e]) stc[e] = unphysical_one(pw, E[e], fnumin, thr_guard, Kc + e * nn, &m, NULL);
+    if (!isc[e]) continue;
+    stc[e] = unphysical_one(pw, E[e], fnumin, thr_guard, Kc + e * nn, &m, NULL);
+    if (!stc[e] && mqdt_minv(Kc + e * nn, n, m, Xc + e * nn, Yc + e * nn)) stc[e] = RMO_PT_SINGULAR;
   }
 #pragma omp parallel for schedule(dynamic, 1)
   for (int e = 0; e < ne; ++e) {
@@ -1544,17 +1627,50 @@ int rmo_mqdt_run(const rmo_pw *pw, const double *E, int32_t ne, int32_t ieq, dou
         if (isc[j]) cl[m++] = j;
       for (int q = 0; q < m; ++q)
         if (cl[q] <= e) k = q;
+      if (m == 0) st |= RMO_PT_NOCONV; /* a run without a usable coarse point */
       const int w = m < 4 ? m : 4;
       int st0 = k - 1;
       if (st0 > m - w) st0 = m - w;
       if (st0 < 0) st0 = 0;
-      ld *Ki = (ld *)calloc(nn, sizeof(ld));
+      ld *Xi = (ld *)calloc(nn, sizeof(ld)), *Yi = (ld *)calloc(nn, sizeof(ld)), *Ki = (ld *)calloc(nn, sizeof(ld));
       for (int q = st0; q < st0 + w; ++q) {
         ld wt = 1.0L;
         for (int r = st0; r < st0 + w; ++r)
           if (r != q) wt *= ((ld)E[e] - (ld)E[cl[r]]) / ((ld)E[cl[q]] - (ld)E[cl[r]]);
         st |= stc[cl[q]];
-        for (long t = 0; t < nn; ++t) Ki[t] += wt * (ld)Kc[(size_t)cl[q] * nn + t];
+        for (long t = 0; t < nn; ++t) {
+          Xi[t] += wt * Xc[(size_t)cl[q] * nn + t];
+          Yi[t] += wt * Yc[(size_t)cl[q] * nn + t];
+        }
+      }
+      if (!st) {
+        /* Ku = Y X^-1: Z = X^-1 Y column by column, Ku = Z^T (X, Y symmetric) */
+        const int m = ns[e];
+        ld *LU = (ld *)malloc(sizeof(ld) * ((size_t)m * m + 1));
+        ld *col = (ld *)malloc(sizeof(ld) * (m + 1));
+        int *piv = (int *)malloc(sizeof(int) * (m + 1));
+        for (int i = 0; i < m; ++i)
+          for (int j = 0; j < m; ++j) LU[(size_t)i * m + j] = Xi[(size_t)i * n + j];
+        if (m > 0 && lu_factor(LU, m, piv)) {
+          st = RMO_PT_SINGULAR;
+        } else {
+          for (int j = 0; j < m; ++j) {
+            for (int i = 0; i < m; ++i) col[i] = Yi[(size_t)i * n + j];
+            if (m > 0) lu_solve(LU, m, piv, col, 0);
+            for (int i = 0; i < m; ++i) Ki[(size_t)j * n + i] = col[i];
+          }
+          /* symmetrised: the interpolated X, Y keep Y X^-1 symmetric only up
+             to the interpolation error */
+          for (int i = 0; i < m; ++i)
+            for (int j = 0; j < i; ++j) {
+              const ld v = 0.5L * (Ki[(size_t)i * n + j] + Ki[(size_t)j * n + i]);
+              Ki[(size_t)i * n + j] = v;
+              Ki[(size_t)j * n + i] = v;
+            }
+        }
+        free(LU);
+        free(col);
+        free(piv);
       }
       if (!st) st = mqdt_eliminate(pw, E[e], fnumin, Ki, ns[e], Kl);
       if (!st) {
@@ -1563,6 +1679,8 @@ int rmo_mqdt_run(const rmo_pw *pw, const double *E, int32_t ne, int32_t ieq, dou
         st = s_and_omega_one(pw, Kl, no, idx, omega + (long)e * nt * nt, NULL);
         free(idx);
       }
+      free(Xi);
+      free(Yi);
       free(Ki);
       free(cl);
     }
@@ -1574,6 +1692,8 @@ int rmo_mqdt_run(const rmo_pw *pw, const double *E, int32_t ne, int32_t ieq, dou
     if (!K) free(Kl);
   }
   free(Kc);
+  free(Xc);
+  free(Yc);
   free(stc);
   free(ns);
   free(flag);

@@ -9,7 +9,12 @@
 // decaying combination is f cos(pi nu) - g sin(pi nu) (k_asym.hip), so at a
 // fine energy the closed members are eliminated by
 //   K = Ku_oo - Ku_oc (Ku_cc + tan(pi nu))^-1 Ku_co.
-// That K is the tail of the solution of one linear system of the member
+// Between coarse points the unphysical S is interpolated, not the unphysical
+// K, which has poles (an eigenphase through pi/2): the coarse step keeps
+// X + iY = (1 - i Ku)^-1 = (1 + S)/2 (bounded), the fine step interpolates X
+// and Y elementwise and recovers Ku = Y X^-1 by one batched LU of the member
+// count with the full back substitution (k_mqdt_interp, k_mqdt_take).
+// K is then the tail of the solution of one linear system of the member
 // count m = n_c + n_o, unknowns ordered [X (closed members) | K (open)]:
 //   [ Ku_cc + tan(pi nu)  0 ] [X]   [Ku_co]
 //   [ Ku_oc               1 ] [K] = [Ku_oo],
@@ -22,7 +27,9 @@ namespace rm {
 
 // Member count and flags (threshold, pole) of every energy of a mesh: one
 // thread per energy.  Poles are ascending, so a pole equal to E is found by
-// bisection.
+// bisection.  MQDT_NEAR_INT is added to the flags where a closed member's
+// |sin(pi nu)| < 1e-6 (its g cancels there; the host does not take such a
+// point as a coarse point).
 __global__ void k_mqdt_count(const double *__restrict__ ethr, const int *__restrict__ l,
                              const double *__restrict__ Ek, int n, int M, double z, const double *__restrict__ E,
                              int ne, double fnumin, double thr_guard, int *__restrict__ nmem, int *__restrict__ flag) {
@@ -32,8 +39,10 @@ __global__ void k_mqdt_count(const double *__restrict__ ethr, const int *__restr
   int m = 0, st = 0;
   for (int i = 0; i < n; ++i) {
     const double eps = Ev - ethr[i];
-    m += mqdt_member(z, eps, l[i], fnumin);
+    const bool mem = mqdt_member(z, eps, l[i], fnumin);
+    m += mem;
     if (fabs(eps) < thr_guard) st |= RM_PT_THRESHOLD;
+    if (mem && eps < 0 && fabs(sinpi(z / sqrt(-eps))) < 1e-6) st |= MQDT_NEAR_INT;
   }
   int lo = 0, hi = M;
   while (lo < hi) {
@@ -138,23 +147,26 @@ void launch_mqdt_setup(hipStream_t s, const Lay &L, const DevPW *tab, const int 
                      tanv, dims, nsys, status);
 }
 
-// One workgroup per (member channel i, energy): the interpolated row of the
-// unphysical K, Ku(E) = sum_q w_q Ku(E_q) over the energy's coarse points
-// (cidx < 0: unused), written as row syspos[i] of the system and of its
-// right-hand sides.  Coarse matrices are [q][n][n] with the members in
-// ascending order.  An energy already flagged (threshold, pole, or a coarse
+// One workgroup per (member channel i, energy): row spos[i] of the energy's
+// unphysical K (Ku, row stride ldk, energy stride sK, members in ascending
+// order), written as row syspos[i] of the system and of its right-hand sides;
+// dims = {m, n_o}.  An energy already flagged (threshold, pole, or a coarse
 // point it depends on) gets the identity system instead, so that the solve
 // adds no flags of its own; its outputs are NaN from the flag.
 __global__ __launch_bounds__(256) void k_mqdt_build(const DevPW *__restrict__ tab, const int *__restrict__ pwi,
                                                     const int *__restrict__ syspos, const int *__restrict__ spos,
                                                     const double *__restrict__ tanv, const int *__restrict__ nopen,
                                                     const int *__restrict__ nsys, long ldo,
-                                                    const double *__restrict__ Kc, const int *__restrict__ cidx,
-                                                    const double *__restrict__ cw, const int *__restrict__ status,
+                                                    const double *__restrict__ Ku, long ldk, long sK,
+                                                    const int *__restrict__ status, int *__restrict__ dims,
                                                     double *__restrict__ aug, long ldaug, long strideA, long roff) {
   const int i = blockIdx.x, e = blockIdx.y;
   const DevPW &p = tab[pwi[e]];
   const int n = p.n;
+  if (i == 0 && threadIdx.x == 0) {
+    dims[2 * e] = nsys[e];
+    dims[2 * e + 1] = nopen[e];
+  }
   if (i >= n) return;
   const int *sp = syspos + (size_t)e * ldo, *mp = spos + (size_t)e * ldo;
   const int ri = sp[i];
@@ -162,15 +174,7 @@ __global__ __launch_bounds__(256) void k_mqdt_build(const DevPW *__restrict__ ta
   const int ncm = nsys[e] - nopen[e];
   const bool iopen = ri >= ncm;
   const double ti = tanv[(size_t)e * ldo + i];
-  const size_t nn = (size_t)n * n;
-  const double *rowq[4];
-  double wq[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int c = cidx[4 * e + q];
-    wq[q] = c >= 0 ? cw[4 * e + q] : 0.0;
-    rowq[q] = Kc + (c >= 0 ? c : 0) * nn + (size_t)mp[i] * n;
-  }
+  const double *krow = Ku + (size_t)e * sK + (size_t)mp[i] * ldk;
   double *row = aug + (size_t)e * strideA + (size_t)ri * ldaug;
   if (status[e]) {
     for (int j = threadIdx.x; j < n; j += 256) {
@@ -184,10 +188,7 @@ __global__ __launch_bounds__(256) void k_mqdt_build(const DevPW *__restrict__ ta
   for (int j = threadIdx.x; j < n; j += 256) {
     const int rj = sp[j];
     if (rj < 0) continue;
-    const int sj = mp[j];
-    double v = 0.0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) v += wq[q] * rowq[q][sj];
+    const double v = krow[mp[j]];
     const bool jopen = rj >= ncm;
     if (jopen) {
       row[roff + (rj - ncm)] = v;
@@ -199,10 +200,91 @@ __global__ __launch_bounds__(256) void k_mqdt_build(const DevPW *__restrict__ ta
 }
 
 void launch_mqdt_build(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *syspos,
-                       const int *spos, const double *tanv, const int *nopen, const int *nsys, const double *Kc,
-                       const int *cidx, const double *cw, const int *status, double *aug) {
+                       const int *spos, const double *tanv, const int *nopen, const int *nsys, const double *Ku,
+                       const int *status, int *dims, double *aug) {
   hipLaunchKernelGGL(k_mqdt_build, dim3(L.nmax, L.ne), dim3(256), 0, s, tab, pwi, syspos, spos, tanv, nopen, nsys,
-                     L.ldo, Kc, cidx, cw, status, aug, L.ldaug, L.sA, L.roff);
+                     L.ldo, Ku, L.ldk, L.sK, status, dims, aug, L.ldaug, L.sA, L.roff);
+}
+
+// One workgroup per (member channel i, energy): row spos[i] of the
+// interpolated X and Y over the energy's coarse points (cidx < 0: unused),
+// X(E) = sum_q w_q X(E_q), written as [X | Y] (X in columns 0..m, Y from
+// column roff); dims = {m, m}.  Coarse planes are [q][n][n], members in
+// ascending order.  A flagged energy gets [1 | 0].
+__global__ __launch_bounds__(256) void k_mqdt_interp(const DevPW *__restrict__ tab, const int *__restrict__ pwi,
+                                                     const int *__restrict__ spos, const int *__restrict__ nsys,
+                                                     long ldo, const double *__restrict__ Xc,
+                                                     const double *__restrict__ Yc, const int *__restrict__ cidx,
+                                                     const double *__restrict__ cw, const int *__restrict__ status,
+                                                     int *__restrict__ dims, double *__restrict__ aug, long ldaug,
+                                                     long strideA, long roff) {
+  const int i = blockIdx.x, e = blockIdx.y;
+  const DevPW &p = tab[pwi[e]];
+  const int n = p.n, m = nsys[e];
+  if (i == 0 && threadIdx.x == 0) {
+    dims[2 * e] = m;
+    dims[2 * e + 1] = m;
+  }
+  if (i >= n) return;
+  const int *mp = spos + (size_t)e * ldo;
+  const int pi = mp[i];
+  if (pi < 0) return;
+  double *row = aug + (size_t)e * strideA + (size_t)pi * ldaug;
+  if (status[e]) {
+    for (int q = threadIdx.x; q < m; q += 256) {
+      row[q] = q == pi ? 1.0 : 0.0;
+      row[roff + q] = 0.0;
+    }
+    return;
+  }
+  const size_t nn = (size_t)n * n;
+  const double *xq[4], *yq[4];
+  double wq[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int c = cidx[4 * e + q];
+    wq[q] = c >= 0 ? cw[4 * e + q] : 0.0;
+    const size_t off = (c >= 0 ? c : 0) * nn + (size_t)pi * n;
+    xq[q] = Xc + off;
+    yq[q] = Yc + off;
+  }
+  for (int q = threadIdx.x; q < m; q += 256) {
+    double x = 0.0, y = 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      x += wq[c] * xq[c][q];
+      y += wq[c] * yq[c][q];
+    }
+    row[q] = x;
+    row[roff + q] = y;
+  }
+}
+
+void launch_mqdt_interp(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *spos,
+                        const int *nsys, const double *Xc, const double *Yc, const int *cidx, const double *cw,
+                        const int *status, int *dims, double *aug) {
+  hipLaunchKernelGGL(k_mqdt_interp, dim3(L.nmax, L.ne), dim3(256), 0, s, tab, pwi, spos, nsys, L.ldo, Xc, Yc, cidx,
+                     cw, status, dims, aug, L.ldaug, L.sA, L.roff);
+}
+
+// Ku = (Z + Z^T) / 2 for the solution Z = X^-1 Y in the right-hand-side
+// columns of the member block (X and Y symmetric, so Z^T = Y X^-1; the
+// interpolated X, Y keep it symmetric only up to the interpolation error, and
+// the unphysical K is symmetric), into the K workspace.
+__global__ __launch_bounds__(256) void k_mqdt_take(const int *__restrict__ nsys, const double *__restrict__ aug,
+                                                   long ldaug, long strideA, long roff, double *__restrict__ Kw,
+                                                   long ldk, long strideK) {
+  const int e = blockIdx.y, p = blockIdx.x;
+  const int m = nsys[e];
+  if (p >= m) return;
+  const double *Z = aug + (size_t)e * strideA + roff;
+  double *K = Kw + (size_t)e * strideK + (size_t)p * ldk;
+  for (int q = threadIdx.x; q < m; q += 256) K[q] = 0.5 * (Z[(size_t)q * ldaug + p] + Z[(size_t)p * ldaug + q]);
+}
+
+void launch_mqdt_take(hipStream_t s, const Lay &L, const int *nsys, const double *aug, double *Kw) {
+  hipLaunchKernelGGL(k_mqdt_take, dim3(L.nmax, L.ne), dim3(256), 0, s, nsys, aug, L.ldaug, L.sA, L.roff, Kw, L.ldk,
+                     L.sK);
 }
 
 // K = the last n_o rows of the system's solution (rows m - n_o .. m), into the

@@ -112,6 +112,10 @@ struct Lay {
   double fnumin = 0;
 };
 
+// Internal flag of the quantum-defect mesh scan: a closed member's effective
+// quantum number is within 1e-6 of an integer in sin(pi nu).
+constexpr int MQDT_NEAR_INT = 1 << 30;
+
 // Member channel of the unphysical K (stgf MQDT variables iomsw = 1, fnumin):
 // open, or closed with effective quantum number nu = z / sqrt(-eps) >=
 // max(fnumin, l + 0.1), i.e. eps >= -z^2 / numin^2.  Decided in double.
@@ -232,8 +236,12 @@ void launch_mqdt_count(hipStream_t s, const DevPW *pw, const double *E, int ne, 
 void launch_mqdt_setup(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const double *E,
                        double thr_guard, int *syspos, int *spos, double *tanv, int *dims, int *nsys, int *status);
 void launch_mqdt_build(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *syspos,
-                       const int *spos, const double *tanv, const int *nopen, const int *nsys, const double *Kc,
-                       const int *cidx, const double *cw, const int *status, double *aug);
+                       const int *spos, const double *tanv, const int *nopen, const int *nsys, const double *Ku,
+                       const int *status, int *dims, double *aug);
+void launch_mqdt_interp(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *spos,
+                        const int *nsys, const double *Xc, const double *Yc, const int *cidx, const double *cw,
+                        const int *status, int *dims, double *aug);
+void launch_mqdt_take(hipStream_t s, const Lay &L, const int *nsys, const double *aug, double *Kw);
 void launch_mqdt_gather(hipStream_t s, const Lay &L, const int *nsys, const int *nopen, const double *aug,
                         double *Kw, int *dims);
 void launch_gatherK(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *nopen,

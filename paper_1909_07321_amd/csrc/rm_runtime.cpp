@@ -2169,9 +2169,12 @@ rm_status mqdt_check(rm_ctx *ctx, const DevPW *pw, double fnumin) {
 // Unphysical K at energies E (host or device as o says) on ctx->sync: the
 // physical pipeline with the channel split and the asymptotic functions in
 // quantum-defect mode.  Ku [ne][n][n] and nmember / status [ne] are written
-// with the copy kinds given.
+// with the copy kinds given.  With Xp, Yp (device, [ne][n][n]) also the real
+// and imaginary parts of (1 - i Ku)^-1, from the complex symmetric
+// factorisation of the S/Omega stage (valid on the member block).
 rm_status mqdt_coarse(rm_ctx *ctx, const DevPW *pw, const double *E, int ne, const rm_opts &o, double fnumin,
-                             double *Ku, hipMemcpyKind kK, int32_t *nmember, int32_t *status, hipMemcpyKind kS) {
+                      double *Ku, hipMemcpyKind kK, int32_t *nmember, int32_t *status, hipMemcpyKind kS,
+                      double *Xp = nullptr, double *Yp = nullptr) {
   const hipStream_t s = ctx->sync.stream;
   const int cap = staged_cap(ctx, pw, ne);
   const int n = pw->n;
@@ -2192,6 +2195,14 @@ rm_status mqdt_coarse(rm_ctx *ctx, const DevPW *pw, const double *E, int ne, con
     launch_finalize(s, L, w.tab, w.pwi, w.status, nullptr, w.Kw, nullptr);
     HIPCHK(hipMemcpy2DAsync(Ku + (size_t)e0 * n * n, sizeof(double) * n, w.Kw, sizeof(double) * L.ldk,
                             sizeof(double) * n, (size_t)m * n, kK, s));
+    if (Xp) {
+      launch_zs_setup(s, L, w.nopen, w.Kw, w.aug, w.gre, w.gim, w.dims);
+      launch_zs_inverse(s, L, w.dims, w.aug, w.gre, w.gim, w.linv, w.status);
+      HIPCHK(hipMemcpy2DAsync(Xp + (size_t)e0 * n * n, sizeof(double) * n, w.aug, sizeof(double) * L.ldaug,
+                              sizeof(double) * n, (size_t)m * n, hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpy2DAsync(Yp + (size_t)e0 * n * n, sizeof(double) * n, w.aug + L.roff, sizeof(double) * L.ldaug,
+                              sizeof(double) * n, (size_t)m * n, hipMemcpyDeviceToDevice, s));
+    }
     HIPCHK(hipMemcpyAsync(nmember + e0, w.nopen, sizeof(int) * m, kS, s));
     HIPCHK(hipMemcpyAsync(status + e0, w.status, sizeof(int) * m, kS, s));
     HIPCHK(hipGetLastError());
@@ -2255,14 +2266,18 @@ rm_status rm_run_mqdt(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, in
   }
   HIPCHK(hipMemcpyAsync(dE, hE.data(), sizeof(double) * ne, hipMemcpyHostToDevice, s));
   launch_mqdt_count(s, pw, dE, ne, fnumin, o.thr_guard, dcnt, dcnt + ne);
-  std::vector<int> nm(ne), flag(ne);
+  std::vector<int> nm(ne), flag(ne), avoid(ne);
   HIPCHK(hipMemcpyAsync(nm.data(), dcnt, sizeof(int) * ne, hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(flag.data(), dcnt + ne, sizeof(int) * ne, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  for (int e = 0; e < ne; ++e) {
+    avoid[e] = (flag[e] & MQDT_NEAR_INT) != 0;
+    flag[e] &= ~MQDT_NEAR_INT;
+  }
   // 2. runs of equal member count (the member set only grows with E) and
   // their coarse points: every ieq-th point from the run's first and the
-  // run's last, unflagged; a run whose coarse candidates are all flagged has
-  // every unflagged point coarse
+  // run's last, unflagged and not at an integer nu of a closed member; a run
+  // whose coarse candidates all fail that has every such point coarse
   std::vector<int> run0(ne), run1(ne);
   std::vector<char> isc(ne, 0);
   for (int s0 = 0; s0 < ne;) {
@@ -2272,11 +2287,11 @@ rm_status rm_run_mqdt(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, in
     for (int j = s0; j < s1; ++j) {
       run0[j] = s0;
       run1[j] = s1;
-      if (((j - s0) % ieq == 0 || j == s1 - 1) && !flag[j]) isc[j] = 1, any = true;
+      if (((j - s0) % ieq == 0 || j == s1 - 1) && !flag[j] && !avoid[j]) isc[j] = 1, any = true;
     }
     if (!any)
       for (int j = s0; j < s1; ++j)
-        if (!flag[j]) isc[j] = 1;
+        if (!flag[j] && !avoid[j]) isc[j] = 1;
     s0 = s1;
   }
   std::vector<int> cpos(ne, -1);
@@ -2287,9 +2302,11 @@ rm_status rm_run_mqdt(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, in
       cE.push_back(hE[e]);
     }
   const int nc = (int)cE.size();
-  // 3. unphysical K at the coarse points, kept on the device
-  double *Kc = tmp.get<double>((size_t)std::max(nc, 1) * n * n);
-  if (!Kc) {
+  // 3. unphysical K at the coarse points, and Re, Im of (1 - i Ku)^-1 kept on
+  // the device (the interpolated quantity: bounded where Ku has a pole)
+  const size_t cpl = (size_t)std::max(nc, 1) * n * n;
+  double *Kc = tmp.get<double>(cpl), *Xc = tmp.get<double>(cpl), *Yc = tmp.get<double>(cpl);
+  if (!Kc || !Xc || !Yc) {
     ctx->err = "rm_run_mqdt: device memory for the coarse unphysical K";
     return RM_E_NOMEM;
   }
@@ -2298,7 +2315,7 @@ rm_status rm_run_mqdt(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, in
     rm_opts oc = o;
     oc.device_ptrs = 0;
     if (rm_status st = mqdt_coarse(ctx, pw, cE.data(), nc, oc, fnumin, Kc, hipMemcpyDeviceToDevice, cnm.data(),
-                                   cst.data(), hipMemcpyDeviceToHost))
+                                   cst.data(), hipMemcpyDeviceToHost, Xc, Yc))
       return st;
     HIPCHK(hipStreamSynchronize(s));
   }
@@ -2318,6 +2335,7 @@ rm_status rm_run_mqdt(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, in
       int k = 0;
       for (int q = 0; q < m; ++q)
         if (cl[q] <= e) k = q;
+      if (m == 0) st |= RM_PT_NOCONV;  // a run without a usable coarse point
       const int w = std::min(m, 4);
       const int a0 = std::max(0, std::min(k - 1, m - w));
       for (int q = 0; q < w; ++q) {
@@ -2368,8 +2386,14 @@ rm_status rm_run_mqdt(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, in
     HIPCHK(hipMemcpyAsync(w.status, dci + 4 * (size_t)ne + e0, sizeof(int) * m, hipMemcpyDeviceToDevice, s));
     launch_openlist(s, L, w.tab, w.pwi, w.E, w.nopen, w.openidx, w.openpos, w.colpos, w.openflag);
     launch_mqdt_setup(s, Lq, w.tab, w.pwi, w.E, o.thr_guard, syspos, spos, dtan, w.dims, nsys, w.status);
-    launch_mqdt_build(s, L, w.tab, w.pwi, syspos, spos, dtan, w.nopen, nsys, Kc, dci + 4 * (size_t)e0,
-                      dcw + 4 * (size_t)e0, w.status, w.aug);
+    // Ku = Y X^-1 from the interpolated X, Y: [X | Y] solved in full, transposed into Kw
+    launch_mqdt_interp(s, L, w.tab, w.pwi, spos, nsys, Xc, Yc, dci + 4 * (size_t)e0, dcw + 4 * (size_t)e0, w.status,
+                       w.dims, w.aug);
+    launch_lu_solve(s, L.ne, L.nmax, L.nmax, w.dims, w.aug, L.ldaug, L.sA, L.roff, w.ipiv, L.ldo, w.bperm, w.linv, 0,
+                    w.status);
+    launch_mqdt_take(s, L, nsys, w.aug, w.Kw);
+    // closed members eliminated: the tail of the block system is K
+    launch_mqdt_build(s, L, w.tab, w.pwi, syspos, spos, dtan, w.nopen, nsys, w.Kw, w.status, w.dims, w.aug);
     launch_lu_solve(s, L.ne, L.nmax, L.nmax, w.dims, w.aug, L.ldaug, L.sA, L.roff, w.ipiv, L.ldo, w.bperm, w.linv, 1,
                     w.status);
     launch_mqdt_gather(s, L, nsys, w.nopen, w.aug, w.Kw, w.dims);

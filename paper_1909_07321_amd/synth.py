@@ -310,3 +310,25 @@ def config_coupled(nchan: int = 100, nenergy: int = 1000) -> tuple[PartialWave, 
                            pole_range=(-2.0, 60.0), avoid_energies=E, name="cpl")
     cp = dict(cf=multipole_coefficients(config_seed(8), nchan), r1=30.0, npts=3201, stab=64)
     return pw, cp, E
+
+
+def config_mqdt(nchan: int = 1500, poles_per_chan: float = 40, nenergy: int = 2000,
+                seed_index: int = 9) -> tuple[PartialWave, np.ndarray, int, float]:
+    """Quantum-defect workload: the Rydberg series below the highest threshold.
+    1500 channels (375 targets), z=5, a=12, 40 poles per channel uniform in
+    [9.5, 60] Ry; target thresholds uniform in [0, 8] Ry, then the highest
+    target moved 0.6 Ry above the next one, so that every other channel is open
+    across the mesh.  Fine mesh: 2000 energies from 0.4 Ry to 1e-3 Ry below the
+    highest threshold, where that target's closed channels have effective
+    quantum numbers 7.9..158 (all members with fnumin = sqrt(z a), except those
+    with l + 0.1 above nu early in the mesh).  No pole lies within 0.9 Ry of
+    the mesh, so R is smooth across it, as for an inner region whose
+    eigenvalues are spaced wider than the mesh.  Coarse step ieq = 8.  Returns
+    (wave, energies, ieq, fnumin)."""
+    pw = make_partial_wave(config_seed(seed_index), nchan, poles_per_chan, z=5.0, a=12.0, thr_range=(0.0, 8.0),
+                           pole_range=(9.5, 60.0), name="mqdt")
+    top_t = int(np.argmax(pw.e_target))
+    top = float(np.delete(pw.e_target, top_t).max()) + 0.6
+    pw.e_target[top_t] = top
+    E = np.linspace(top - 0.4, top - 1e-3, nenergy)
+    return pw, E, 8, float(np.sqrt(pw.z * pw.a))

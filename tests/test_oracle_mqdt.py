@@ -14,7 +14,9 @@ The pins do not re-use the oracle's arithmetic:
   only with the right pair, sign and tan(pi nu));
 * with every point a coarse point the coarse/fine operation is the direct
   path; with fewer, its error falls as the fourth power of the coarse step
-  where R is smooth (no pole of eq. (rmatrix) in the mesh range)."""
+  where R is smooth (no pole of eq. (rmatrix) in the mesh range), also where
+  the unphysical K itself has a pole (an eigenphase through pi/2), because
+  the interpolated quantity is (1 - i Kun)^-1, bounded and smooth."""
 import numpy as np
 import mpmath as mp
 import pytest
@@ -201,9 +203,28 @@ def test_flagged_points_are_not_coarse_and_bad_input_is_refused():
         o.mqdt_run(E, 0, 7.0)
 
 
+def _minv(K, m):
+    """(1 - i K)^-1 of the leading m x m block (numpy), as X + i Y padded to K's shape."""
+    X, Y = np.zeros_like(K), np.zeros_like(K)
+    if m:
+        Mi = np.linalg.inv(np.eye(m) - 1j * K[:m, :m])
+        X[:m, :m], Y[:m, :m] = Mi.real, Mi.imag
+    return X, Y
+
+
+def _ku_from_xy(X, Y, m):
+    """unphysical K = Y X^-1 of the leading m x m blocks, symmetrised"""
+    K = np.zeros_like(X)
+    if m:
+        Z = np.linalg.solve(X[:m, :m], Y[:m, :m])
+        K[:m, :m] = 0.5 * (Z + Z.T)
+    return K
+
+
 def test_fine_point_uses_the_four_surrounding_coarse_points():
     """A fine point between coarse points c_k <= E < c_(k+1) of its run takes the
-    cubic through c_(k-1) .. c_(k+2) (shifted inside the run at its ends)."""
+    cubic through c_(k-1) .. c_(k+2) (shifted inside the run at its ends) of the
+    real and imaginary parts of (1 - i Kun)^-1, and Kun = Y X^-1 from them."""
     pw = _wave(far=True)
     th = np.unique(pw.e_thr)
     E = np.linspace(th[1] + 0.01, th[2] - 0.003, 61)
@@ -223,7 +244,10 @@ def test_fine_point_uses_the_four_surrounding_coarse_points():
         s0 = max(0, min(k - 1, len(cl) - w))
         nodes = cl[s0:s0 + w]
         wts = [np.prod([(E[e] - E[m]) / (E[q] - E[m]) for m in nodes if m != q]) for q in nodes]
-        Ki = sum(w * Ku[q] for w, q in zip(wts, nodes))
+        xy = [_minv(Ku[q], nm[q]) for q in nodes]
+        X = sum(w * x for w, (x, _) in zip(wts, xy))
+        Y = sum(w * y for w, (_, y) in zip(wts, xy))
+        Ki = _ku_from_xy(X, Y, nm[e])
         K, st = o.mqdt_eliminate(E[e:e + 1], fnumin, Ki[None], nm[e:e + 1])
         b = K[0, :no[e], :no[e]]
         # on a closed-channel resonance the elimination magnifies the rounding
@@ -231,3 +255,26 @@ def test_fine_point_uses_the_four_surrounding_coarse_points():
         # stencil moves every point by the interpolation error instead
         ok.append(np.abs(r["K"][e, :no[e], :no[e]] - b).max() <= 1e-11 * max(1.0, np.abs(b).max()))
     assert len(ok) > 40 and np.mean(ok) >= 0.95, np.mean(ok)
+
+
+def test_interpolation_converges_across_a_pole_of_the_unphysical_K():
+    """Below the highest threshold of the quantum-defect workload (scaled down)
+    an eigenphase of the unphysical K passes pi/2, so Kun has a pole in the
+    mesh; the interpolated (1 - i Kun)^-1 has none, and the median error of K
+    still falls as the fourth power of the coarse step."""
+    pw, E, _, fnumin = synth.config_mqdt(24, 20, 400)
+    o = oracle.Oracle(pw, nthreads=4)
+    Ku, nm, st = o.unphysical_K(E, fnumin)
+    ok = st == 0
+    assert ok.mean() > 0.99
+    big = np.array([np.abs(Ku[e, :nm[e], :nm[e]]).max() for e in np.flatnonzero(ok)])
+    assert big.max() > 1e2 * np.median(big)  # the pole
+    ref = o.run(E)
+    no = oracle.open_count(pw, E)
+    med = []
+    for ieq in (4, 8):
+        r = o.mqdt_run(E, ieq, fnumin)
+        err = [np.abs(r["K"][e, :no[e], :no[e]] - ref["K"][e, :no[e], :no[e]]).max() /
+               max(1.0, np.abs(ref["K"][e, :no[e], :no[e]]).max()) for e in range(E.size) if not r["coarse"][e]]
+        med.append(np.median(err))
+    assert med[0] < 1e-5 and 6.0 < med[1] / med[0] < 40.0, med

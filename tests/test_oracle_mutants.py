@@ -67,6 +67,9 @@ MUTANTS = {
                       "test_oracle_mqdt.py::test_elimination_reproduces_the_physical_K"),
     "mqdt_series": ("-2.0L * z * cm1 - eps * cm2", "-2.0L * z * cm1 + eps * cm2",
                     "test_oracle_mqdt.py::test_pair_against_kummer_and_tricomi"),
+    "mqdt_minv_sign": ("(i == j ? 1.0L : 0.0L) - I * (ld)K[(size_t)i * n + j];",
+                       "(i == j ? 1.0L : 0.0L) + I * (ld)K[(size_t)i * n + j];",
+                       "test_oracle_mqdt.py::test_fine_point_uses_the_four_surrounding_coarse_points"),
     "mqdt_window": ("int st0 = k - 1;", "int st0 = k - 3;",
                     "test_oracle_mqdt.py::test_fine_point_uses_the_four_surrounding_coarse_points"),
     "taylor_start_binomial": ("for (int t = 1; t <= p; ++t) binom = binom * (ld)(lam + t) / (ld)t;",

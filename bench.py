@@ -323,51 +323,53 @@ def coupled_measure(ctx) -> dict:
 
 
 def mqdt_measure(ctx) -> dict:
-    """The quantum-defect workload (200 channels, 2000 energies in the 0.5 Ry
-    below the highest threshold, coarse step 8): fine-mesh points/s of
-    rm_run_mqdt against rm_run on the same mesh, and the interpolated K and
-    Omega against the direct ones (at the points that are not coarse)."""
+    """The quantum-defect workload (the Rydberg series below the highest
+    threshold: 1500 channels, 60000 poles, 2000 energies in the 0.4 Ry below
+    it, coarse step 8): fine-mesh points/s of rm_run_mqdt against rm_run on
+    the same mesh, both FP64 with Omega only, and Omega of the interpolated
+    points against the direct one (elementwise above 1e-12 of each energy's
+    largest entry, the points that are not coarse)."""
     import numpy as np
     import torch
 
     from paper_1909_07321_amd import rm, synth
 
+    t0 = time.time()
     pw, E, ieq, fnumin = synth.config_mqdt()
+    log(f"mqdt workload generated in {time.time() - t0:.1f}s")
     pid = ctx.pw_upload(pw)
     Ed = torch.tensor(E, dtype=torch.float64, device="cuda")
-    ctx.run_mqdt(pid, Ed[:64], ieq, fnumin)  # warm-up: workspace and code
-    _, Kw, _ = ctx.run(pid, Ed[:64])
+    ctx.run_mqdt(pid, Ed[:64], ieq, fnumin, want_K=False)  # warm-up: workspace and code
+    ctx.run(pid, Ed[:64], want_K=False)
     torch.cuda.synchronize()
-    del Kw
     t1 = time.perf_counter()
-    om, K, co, st = ctx.run_mqdt(pid, Ed, ieq, fnumin)
+    om, _, co, st = ctx.run_mqdt(pid, Ed, ieq, fnumin, want_K=False)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t1
     t1 = time.perf_counter()
-    om2, K2, st2 = ctx.run(pid, Ed)
+    om2, _, st2 = ctx.run(pid, Ed, want_K=False)
     torch.cuda.synchronize()
     dt2 = time.perf_counter() - t1
-    om, K, co, st = (x.cpu().numpy() for x in (om, K, co, st))
-    om2, K2, st2 = (x.cpu().numpy() for x in (om2, K2, st2))
-    no = (E[:, None] - pw.e_thr[None, :] > 0).sum(axis=1)
-    fine = (co == 0) & (st == 0) & (st2 == 0)
-    ek = np.array([np.abs(K[e, :no[e], :no[e]] - K2[e, :no[e], :no[e]]).max() /
-                   max(1.0, np.abs(K2[e, :no[e], :no[e]]).max()) for e in np.flatnonzero(fine)])
-    top = np.abs(om2).reshape(E.size, -1).max(axis=1)
-    eo = (np.abs(om - om2).reshape(E.size, -1).max(axis=1) / np.maximum(top, 1e-300))[fine]
+    fine = ((co == 0) & (st == 0) & (st2 == 0)).cpu().numpy()
+    a = om.reshape(E.size, -1)
+    b = om2.reshape(E.size, -1)
+    top = b.abs().amax(dim=1, keepdim=True)
+    den = torch.maximum(b.abs(), 1e-12 * top)
+    eo = ((a - b).abs() / den).amax(dim=1).cpu().numpy()[fine]
+    co_n, st_n = int(co.sum().item()), int((st != 0).sum().item())
+    del om, om2, a, b, den
     ctx.pw_release(pid)
     res = dict(points_per_s=E.size / dt, seconds=dt, direct_points_per_s=E.size / dt2, direct_seconds=dt2,
-               speedup=dt2 / dt, coarse_points=int(co.sum()), flagged_energies=int((st != 0).sum()),
-               K_err_vs_direct=dict(median=float(np.median(ek)), p99=float(np.quantile(ek, 0.99)), max=float(ek.max())),
+               speedup=dt2 / dt, coarse_points=co_n, flagged_energies=st_n,
                omega_err_vs_direct=dict(median=float(np.median(eo)), p99=float(np.quantile(eo, 0.99)),
                                         max=float(eo.max())),
-               workload=f"one wave, {pw.nchan} channels, {pw.npole} poles in [5, 60] Ry, {E.size} energies in "
-                        f"[{E[0]:.4f}, {E[-1]:.4f}] Ry (0.5 Ry below the highest threshold), coarse step {ieq}, "
+               workload=f"one wave, {pw.nchan} channels, {pw.npole} poles in [9.5, 60] Ry, {E.size} energies in "
+                        f"[{E[0]:.4f}, {E[-1]:.4f}] Ry (0.4 Ry below the highest threshold), coarse step {ieq}, "
                         f"fnumin {fnumin:.3f}, FP64")
-    log(f"mqdt: {res['points_per_s']:.0f} points/s over {dt:.2f}s ({res['coarse_points']} coarse of {E.size}) against "
-        f"{res['direct_points_per_s']:.0f} points/s direct ({res['speedup']:.2f}x); K vs direct median "
-        f"{res['K_err_vs_direct']['median']:.1e} max {res['K_err_vs_direct']['max']:.1e}, Omega median "
-        f"{res['omega_err_vs_direct']['median']:.1e} max {res['omega_err_vs_direct']['max']:.1e}")
+    log(f"mqdt: {res['points_per_s']:.0f} points/s over {dt:.2f}s ({co_n} coarse of {E.size}) against "
+        f"{res['direct_points_per_s']:.0f} points/s direct ({res['speedup']:.2f}x); Omega vs direct median "
+        f"{res['omega_err_vs_direct']['median']:.1e} p99 {res['omega_err_vs_direct']['p99']:.1e} max "
+        f"{res['omega_err_vs_direct']['max']:.1e}")
     return res
 
 

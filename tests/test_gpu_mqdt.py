@@ -111,7 +111,7 @@ def test_unphysical_K_vs_oracle(ctx, n, far):
     ctx.pw_release(pid)
 
 
-@pytest.mark.parametrize("n,ieq", [(10, 4), (40, 6), (97, 3)])
+@pytest.mark.parametrize("n,ieq", [(10, 4), (40, 6), (97, 3), (300, 5)])
 def test_run_mqdt_vs_oracle(ctx, n, ieq):
     pw = _wave(53 + n, n, True)
     E = _mesh(pw, 121)

@@ -234,10 +234,25 @@ rm_status rm_mqdt_unphysical_K(rm_ctx *ctx, int32_t pw, const double *E, int32_t
    points the result is the physical one (up to rounding).  Outputs as rm_run
    (omega [ne][nt][nt], K [ne][n][n] or NULL, status [ne]); coarse [ne] int8
    (may be NULL) marks the coarse points.  A point inherits the flags of the
-   coarse points it is interpolated from.  ieq < 1 or a mesh that is not
-   strictly ascending: RM_E_ARG.  The call allocates device temporaries
-   (3 ncoarse n^2 doubles) and returns after its work is complete. */
-rm_status rm_run_mqdt(rm_ctx *ctx, int32_t pw, const double *E, int32_t ne, int32_t ieq, double fnumin,
+   coarse points it is interpolated from.  ieq < 1, iqdt not 1 or 2, qetest < 0
+   or a mesh that is not strictly ascending: RM_E_ARG (mq = NULL: the
+   defaults).  The call allocates device temporaries (3 ncoarse n^2 doubles)
+   and returns after its work is complete. */
+typedef struct {
+  int32_t ieq;   /* coarse step: the unphysical matrix is computed at every ieq-th point of each run (the
+                    paper's |ieq| with ieq < 0); >= 1 */
+  int32_t iqdt;  /* 1: interpolate the unphysical S (default); 2: interpolate the unphysical K itself
+                    (one LU less per point, valid only where Ku has no pole between coarse points) */
+  double fnumin; /* closed channels with nu < max(fnumin, l + 0.1) are omitted (eliminated directly) */
+  double qetest; /* z-scaled Ry (E / z^2): a point within qetest of the last point of its run that was
+                    evaluated at its own energy takes that point's interpolant (its tan(pi nu) stays its
+                    own); 0 re-interpolates at every point */
+} rm_mqdt_opts;
+
+/* ieq = 1 (every point coarse: the direct result), iqdt = 1, fnumin = 0, qetest = 1e-7. */
+void rm_mqdt_opts_default(rm_mqdt_opts *o);
+
+rm_status rm_run_mqdt(rm_ctx *ctx, int32_t pw, const double *E, int32_t ne, const rm_mqdt_opts *mq,
                       const rm_opts *opts, double *omega, double *K, int8_t *coarse, int32_t *status);
 
 /* ---------------------------------------------------------- staged calls */

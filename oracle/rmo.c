@@ -1566,11 +1566,15 @@ static int mqdt_minv(const double *K, int n, int m, ld *X, ld *Y) {
    the four coarse points of its run around it (window start: the coarse point
    before the last coarse point at or below it, clamped to the run's coarse
    list; all of them if fewer than four), its unphysical K is Y X^-1 of the
-   interpolated parts X, Y, and the closed members are eliminated.  coarse[e]
-   (may be NULL) is set to 1 at coarse points. */
-int rmo_mqdt_run(const rmo_pw *pw, const double *E, int32_t ne, int32_t ieq, double fnumin, double thr_guard,
-                 double *omega, double *K, int8_t *coarse, int32_t *status, int32_t nthreads) {
-  if (ieq < 1 || pw->z <= 0) return -1;
+   interpolated parts X, Y, and the closed members are eliminated (iqdt = 1;
+   with iqdt = 2 the unphysical K itself is interpolated).  With qetest > 0 a
+   point within qetest z^2 of the last point of its run that was evaluated at
+   its own energy takes the interpolant at that energy (tan(pi nu) stays its
+   own).  coarse[e] (may be NULL) is set to 1 at coarse points. */
+int rmo_mqdt_run(const rmo_pw *pw, const double *E, int32_t ne, int32_t ieq, int32_t iqdt, double fnumin,
+                 double qetest, double thr_guard, double *omega, double *K, int8_t *coarse, int32_t *status,
+                 int32_t nthreads) {
+  if (ieq < 1 || pw->z <= 0 || (iqdt != 1 && iqdt != 2) || !(qetest >= 0)) return -1;
   for (int e = 1; e < ne; ++e)
     if (!(E[e] > E[e - 1])) return -1;
   const int n = pw->nchan, nt = pw->ntarget;
@@ -1600,6 +1604,24 @@ int rmo_mqdt_run(const rmo_pw *pw, const double *E, int32_t ne, int32_t ieq, dou
   free(avoid);
   if (coarse)
     for (int e = 0; e < ne; ++e) coarse[e] = (int8_t)isc[e];
+  /* energy at which each point's interpolant is evaluated (qetest): walking
+     each run in order, a point within qetest z^2 of the last point evaluated
+     at its own energy reuses that energy; coarse points are their own */
+  double *Ev = (double *)malloc(sizeof(double) * (ne + 1));
+  {
+    const double tol = qetest * pw->z * pw->z;
+    double last = 0.0;
+    int have = 0;
+    for (int e = 0; e < ne; ++e) {
+      if (e == 0 || ns[e] != ns[e - 1]) have = 0;
+      if (!isc[e] && have && fabs(E[e] - last) <= tol) {
+        Ev[e] = last;
+      } else {
+        Ev[e] = E[e];
+        if (!flag[e]) last = E[e], have = 1;
+      }
+    }
+  }
   /* unphysical K at the coarse points */
   double *Kc = (double *)malloc(sizeof(double) * (size_t)ne * nn);
   ld *Xc = (ld *)calloc((size_t)ne * nn + 1, sizeof(ld)), *Yc = (ld *)calloc((size_t)ne * nn + 1, sizeof(ld));
@@ -1636,14 +1658,15 @@ int rmo_mqdt_run(const rmo_pw *pw, const double *E, int32_t ne, int32_t ieq, dou
       for (int q = st0; q < st0 + w; ++q) {
         ld wt = 1.0L;
         for (int r = st0; r < st0 + w; ++r)
-          if (r != q) wt *= ((ld)E[e] - (ld)E[cl[r]]) / ((ld)E[cl[q]] - (ld)E[cl[r]]);
+          if (r != q) wt *= ((ld)Ev[e] - (ld)E[cl[r]]) / ((ld)E[cl[q]] - (ld)E[cl[r]]);
         st |= stc[cl[q]];
         for (long t = 0; t < nn; ++t) {
           Xi[t] += wt * Xc[(size_t)cl[q] * nn + t];
           Yi[t] += wt * Yc[(size_t)cl[q] * nn + t];
+          Ki[t] += wt * (ld)Kc[(size_t)cl[q] * nn + t]; /* iqdt = 2 */
         }
       }
-      if (!st) {
+      if (!st && iqdt == 1) {
         /* Ku = Y X^-1: Z = X^-1 Y column by column, Ku = Z^T (X, Y symmetric) */
         const int m = ns[e];
         ld *LU = (ld *)malloc(sizeof(ld) * ((size_t)m * m + 1));
@@ -1694,6 +1717,7 @@ int rmo_mqdt_run(const rmo_pw *pw, const double *E, int32_t ne, int32_t ieq, dou
   free(Kc);
   free(Xc);
   free(Yc);
+  free(Ev);
   free(stc);
   free(ns);
   free(flag);

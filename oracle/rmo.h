@@ -116,11 +116,15 @@ int rmo_mqdt_eliminate(const rmo_pw *pw, const double *E, int32_t ne, double fnu
                        const int32_t *nmember, double *K, int32_t *status, int32_t nthreads);
 /* Coarse/fine operation on an ascending mesh: unphysical K at every ieq-th
    point of each run of equal member set (and the run's last point), Lagrange
-   interpolation (four nearest coarse points of the run) elsewhere, then K and
+   interpolation (four nearest coarse points of the run) of the unphysical S
+   (iqdt = 1, through (1 - i Ku)^-1) or K (iqdt = 2) elsewhere, the
+   interpolant reused within qetest z^2 (qetest, z-scaled Ry), then K and
    Omega at every point.  coarse (may be NULL) marks the coarse points.
-   Returns -1 for ieq < 1, z <= 0 or a mesh that is not ascending. */
-int rmo_mqdt_run(const rmo_pw *pw, const double *E, int32_t ne, int32_t ieq, double fnumin, double thr_guard,
-                 double *omega, double *K, int8_t *coarse, int32_t *status, int32_t nthreads);
+   Returns -1 for ieq < 1, iqdt not 1 or 2, qetest < 0, z <= 0 or a mesh that
+   is not ascending. */
+int rmo_mqdt_run(const rmo_pw *pw, const double *E, int32_t ne, int32_t ieq, int32_t iqdt, double fnumin,
+                 double qetest, double thr_guard, double *omega, double *K, int8_t *coarse, int32_t *status,
+                 int32_t nthreads);
 /* Channel functions of the unphysical K at r = a: (s, s', c, c') open,
    (f, f', g, g') closed member, (0, 0, e, e') otherwise; returns 1 for a
    member, 0 otherwise, -1 on failure. */

@@ -9,8 +9,9 @@
 // decaying combination is f cos(pi nu) - g sin(pi nu) (k_asym.hip), so at a
 // fine energy the closed members are eliminated by
 //   K = Ku_oo - Ku_oc (Ku_cc + tan(pi nu))^-1 Ku_co.
-// Between coarse points the unphysical S is interpolated, not the unphysical
-// K, which has poles (an eigenphase through pi/2): the coarse step keeps
+// Between coarse points the unphysical S is interpolated by default (iqdt = 1),
+// not the unphysical K, which has poles (an eigenphase through pi/2; iqdt = 2
+// interpolates K itself and skips the recovery): the coarse step keeps
 // X + iY = (1 - i Ku)^-1 = (1 + S)/2 (bounded), the fine step interpolates X
 // and Y elementwise and recovers Ku = Y X^-1 by one batched LU of the member
 // count with the full back substitution (k_mqdt_interp, k_mqdt_take).
@@ -207,21 +208,24 @@ void launch_mqdt_build(hipStream_t s, const Lay &L, const DevPW *tab, const int 
 }
 
 // One workgroup per (member channel i, energy): row spos[i] of the
-// interpolated X and Y over the energy's coarse points (cidx < 0: unused),
-// X(E) = sum_q w_q X(E_q), written as [X | Y] (X in columns 0..m, Y from
-// column roff); dims = {m, m}.  Coarse planes are [q][n][n], members in
-// ascending order.  A flagged energy gets [1 | 0].
-__global__ __launch_bounds__(256) void k_mqdt_interp(const DevPW *__restrict__ tab, const int *__restrict__ pwi,
-                                                     const int *__restrict__ spos, const int *__restrict__ nsys,
-                                                     long ldo, const double *__restrict__ Xc,
-                                                     const double *__restrict__ Yc, const int *__restrict__ cidx,
-                                                     const double *__restrict__ cw, const int *__restrict__ status,
-                                                     int *__restrict__ dims, double *__restrict__ aug, long ldaug,
-                                                     long strideA, long roff) {
+// interpolated planes over the energy's coarse points (cidx < 0: unused),
+// X(E) = sum_q w_q X(E_q).  Mode 1 (the unphysical S): X and Y written as
+// [X | Y] (X in columns 0..m, Y from column roff), dims = {m, m}; a flagged
+// energy gets [1 | 0].  Mode 2 (the unphysical K itself, in Xc): the row
+// written into the K workspace; a flagged energy gets 0.  Coarse planes are
+// [q][n][n], members in ascending order.
+__global__ __launch_bounds__(256) void k_mqdt_interp(int mode, const DevPW *__restrict__ tab,
+                                                     const int *__restrict__ pwi, const int *__restrict__ spos,
+                                                     const int *__restrict__ nsys, long ldo,
+                                                     const double *__restrict__ Xc, const double *__restrict__ Yc,
+                                                     const int *__restrict__ cidx, const double *__restrict__ cw,
+                                                     const int *__restrict__ status, int *__restrict__ dims,
+                                                     double *__restrict__ aug, long ldaug, long strideA, long roff,
+                                                     double *__restrict__ Kw, long ldk, long strideK) {
   const int i = blockIdx.x, e = blockIdx.y;
   const DevPW &p = tab[pwi[e]];
   const int n = p.n, m = nsys[e];
-  if (i == 0 && threadIdx.x == 0) {
+  if (mode == 1 && i == 0 && threadIdx.x == 0) {
     dims[2 * e] = m;
     dims[2 * e + 1] = m;
   }
@@ -229,6 +233,25 @@ __global__ __launch_bounds__(256) void k_mqdt_interp(const DevPW *__restrict__ t
   const int *mp = spos + (size_t)e * ldo;
   const int pi = mp[i];
   if (pi < 0) return;
+  if (mode == 2) {
+    double *krow = Kw + (size_t)e * strideK + (size_t)pi * ldk;
+    const size_t nn = (size_t)n * n;
+    const double *kq[4];
+    double wq[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = cidx[4 * e + q];
+      wq[q] = (c >= 0 && !status[e]) ? cw[4 * e + q] : 0.0;
+      kq[q] = Xc + (c >= 0 ? c : 0) * nn + (size_t)pi * n;
+    }
+    for (int q = threadIdx.x; q < m; q += 256) {
+      double v = 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v += wq[c] * kq[c][q];
+      krow[q] = v;
+    }
+    return;
+  }
   double *row = aug + (size_t)e * strideA + (size_t)pi * ldaug;
   if (status[e]) {
     for (int q = threadIdx.x; q < m; q += 256) {
@@ -260,11 +283,11 @@ __global__ __launch_bounds__(256) void k_mqdt_interp(const DevPW *__restrict__ t
   }
 }
 
-void launch_mqdt_interp(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *spos,
+void launch_mqdt_interp(hipStream_t s, const Lay &L, int mode, const DevPW *tab, const int *pwi, const int *spos,
                         const int *nsys, const double *Xc, const double *Yc, const int *cidx, const double *cw,
-                        const int *status, int *dims, double *aug) {
-  hipLaunchKernelGGL(k_mqdt_interp, dim3(L.nmax, L.ne), dim3(256), 0, s, tab, pwi, spos, nsys, L.ldo, Xc, Yc, cidx,
-                     cw, status, dims, aug, L.ldaug, L.sA, L.roff);
+                        const int *status, int *dims, double *aug, double *Kw) {
+  hipLaunchKernelGGL(k_mqdt_interp, dim3(L.nmax, L.ne), dim3(256), 0, s, mode, tab, pwi, spos, nsys, L.ldo, Xc, Yc,
+                     cidx, cw, status, dims, aug, L.ldaug, L.sA, L.roff, Kw, L.ldk, L.sK);
 }
 
 // Ku = (Z + Z^T) / 2 for the solution Z = X^-1 Y in the right-hand-side

@@ -238,9 +238,9 @@ void launch_mqdt_setup(hipStream_t s, const Lay &L, const DevPW *tab, const int 
 void launch_mqdt_build(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *syspos,
                        const int *spos, const double *tanv, const int *nopen, const int *nsys, const double *Ku,
                        const int *status, int *dims, double *aug);
-void launch_mqdt_interp(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const int *spos,
+void launch_mqdt_interp(hipStream_t s, const Lay &L, int mode, const DevPW *tab, const int *pwi, const int *spos,
                         const int *nsys, const double *Xc, const double *Yc, const int *cidx, const double *cw,
-                        const int *status, int *dims, double *aug);
+                        const int *status, int *dims, double *aug, double *Kw);
 void launch_mqdt_take(hipStream_t s, const Lay &L, const int *nsys, const double *aug, double *Kw);
 void launch_mqdt_gather(hipStream_t s, const Lay &L, const int *nsys, const int *nopen, const double *aug,
                         double *Kw, int *dims);

@@ -2229,11 +2229,24 @@ rm_status rm_mqdt_unphysical_K(rm_ctx *ctx, int32_t pwid, const double *E, int32
   return staged_leave(ctx, o, ev);
 }
 
-rm_status rm_run_mqdt(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, int32_t ieq, double fnumin,
+void rm_mqdt_opts_default(rm_mqdt_opts *o) {
+  if (!o) return;
+  o->ieq = 1;
+  o->iqdt = 1;
+  o->fnumin = 0.0;
+  o->qetest = 1e-7;
+}
+
+rm_status rm_run_mqdt(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, const rm_mqdt_opts *mq,
                       const rm_opts *opts, double *omega, double *K, int8_t *coarse, int32_t *status) {
   if (!ctx || ne < 0 || (ne > 0 && (!E || !omega || !status))) return RM_E_ARG;
-  if (ieq < 1) {
-    ctx->err = "ieq: the coarse step must be >= 1 mesh points";
+  rm_mqdt_opts q;
+  rm_mqdt_opts_default(&q);
+  if (mq) q = *mq;
+  const int ieq = q.ieq, iqdt = q.iqdt;
+  const double fnumin = q.fnumin;
+  if (ieq < 1 || (iqdt != 1 && iqdt != 2) || !(q.qetest >= 0) || !std::isfinite(q.qetest)) {
+    ctx->err = "rm_run_mqdt: ieq >= 1, iqdt 1 or 2 and a finite qetest >= 0 are needed";
     return RM_E_ARG;
   }
   const DevPW *pw;
@@ -2319,6 +2332,24 @@ rm_status rm_run_mqdt(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, in
       return st;
     HIPCHK(hipStreamSynchronize(s));
   }
+  // energy at which each point's interpolant is evaluated (qetest): walking
+  // each run, a point within qetest z^2 of the last point evaluated at its own
+  // energy reuses that energy; coarse points are their own
+  std::vector<double> hEv(ne);
+  {
+    const double tol = q.qetest * pw->z * pw->z;
+    double last = 0.0;
+    bool have = false;
+    for (int e = 0; e < ne; ++e) {
+      if (e == 0 || nm[e] != nm[e - 1]) have = false;
+      if (!isc[e] && have && std::fabs(hE[e] - last) <= tol) {
+        hEv[e] = last;
+      } else {
+        hEv[e] = hE[e];
+        if (!flag[e]) last = hE[e], have = true;
+      }
+    }
+  }
   // 4. stencils: the four coarse points of the run around each point (window
   // from the coarse point before the last one at or below it, clamped to the
   // run), Lagrange weights, and the flags of the point and of its coarse points
@@ -2342,7 +2373,7 @@ rm_status rm_run_mqdt(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, in
         const int cq = cl[a0 + q];
         double wt = 1.0;
         for (int r = 0; r < w; ++r)
-          if (r != q) wt *= (hE[e] - hE[cl[a0 + r]]) / (hE[cq] - hE[cl[a0 + r]]);
+          if (r != q) wt *= (hEv[e] - hE[cl[a0 + r]]) / (hE[cq] - hE[cl[a0 + r]]);
         hc[4 * e + q] = cpos[cq];
         hw[4 * e + q] = wt;
         st |= cst[cpos[cq]];
@@ -2386,12 +2417,18 @@ rm_status rm_run_mqdt(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, in
     HIPCHK(hipMemcpyAsync(w.status, dci + 4 * (size_t)ne + e0, sizeof(int) * m, hipMemcpyDeviceToDevice, s));
     launch_openlist(s, L, w.tab, w.pwi, w.E, w.nopen, w.openidx, w.openpos, w.colpos, w.openflag);
     launch_mqdt_setup(s, Lq, w.tab, w.pwi, w.E, o.thr_guard, syspos, spos, dtan, w.dims, nsys, w.status);
-    // Ku = Y X^-1 from the interpolated X, Y: [X | Y] solved in full, transposed into Kw
-    launch_mqdt_interp(s, L, w.tab, w.pwi, spos, nsys, Xc, Yc, dci + 4 * (size_t)e0, dcw + 4 * (size_t)e0, w.status,
-                       w.dims, w.aug);
-    launch_lu_solve(s, L.ne, L.nmax, L.nmax, w.dims, w.aug, L.ldaug, L.sA, L.roff, w.ipiv, L.ldo, w.bperm, w.linv, 0,
-                    w.status);
-    launch_mqdt_take(s, L, nsys, w.aug, w.Kw);
+    if (iqdt == 1) {
+      // Ku = Y X^-1 from the interpolated X, Y: [X | Y] solved in full, transposed into Kw
+      launch_mqdt_interp(s, L, 1, w.tab, w.pwi, spos, nsys, Xc, Yc, dci + 4 * (size_t)e0, dcw + 4 * (size_t)e0,
+                         w.status, w.dims, w.aug, w.Kw);
+      launch_lu_solve(s, L.ne, L.nmax, L.nmax, w.dims, w.aug, L.ldaug, L.sA, L.roff, w.ipiv, L.ldo, w.bperm, w.linv,
+                      0, w.status);
+      launch_mqdt_take(s, L, nsys, w.aug, w.Kw);
+    } else {
+      // the interpolated Ku itself, into Kw
+      launch_mqdt_interp(s, L, 2, w.tab, w.pwi, spos, nsys, Kc, nullptr, dci + 4 * (size_t)e0, dcw + 4 * (size_t)e0,
+                         w.status, w.dims, w.aug, w.Kw);
+    }
     // closed members eliminated: the tail of the block system is K
     launch_mqdt_build(s, L, w.tab, w.pwi, syspos, spos, dtan, w.nopen, nsys, w.Kw, w.status, w.dims, w.aug);
     launch_lu_solve(s, L.ne, L.nmax, L.nmax, w.dims, w.aug, L.ldaug, L.sA, L.roff, w.ipiv, L.ldo, w.bperm, w.linv, 1,

@@ -103,14 +103,20 @@ _lib.rm_pw_upload_coupled.argtypes = [_vp, ctypes.POINTER(PWDesc), _i32, _vp, _d
 _lib.rm_set_propagation.argtypes = [_vp, _i32, _i32]
 _lib.rm_propagate.argtypes = [_vp, _i32, _vp, _i32, ctypes.POINTER(Opts), _vp, _vp, _vp]
 _lib.rm_mqdt_unphysical_K.argtypes = [_vp, _i32, _vp, _i32, _d, ctypes.POINTER(Opts), _vp, _vp, _vp]
-_lib.rm_run_mqdt.argtypes = [_vp, _i32, _vp, _i32, _i32, _d, ctypes.POINTER(Opts), _vp, _vp, _vp, _vp]
+class MqdtOpts(ctypes.Structure):
+    _fields_ = [("ieq", _i32), ("iqdt", _i32), ("fnumin", _d), ("qetest", _d)]
+
+
+_lib.rm_mqdt_opts_default.argtypes = [ctypes.POINTER(MqdtOpts)]
+_lib.rm_run_mqdt.argtypes = [_vp, _i32, _vp, _i32, ctypes.POINTER(MqdtOpts), ctypes.POINTER(Opts), _vp, _vp, _vp,
+                             _vp]
 
 EXPORTS = ["rm_opts_default", "rm_create", "rm_destroy", "rm_last_error", "rm_pw_upload", "rm_pw_release",
            "rm_pw_footprint", "rm_work_footprint", "rm_form_R", "rm_asymptotic", "rm_solve_K", "rm_collision_strengths", "rm_run",
            "rm_run_noalloc", "rm_run_batch", "rm_run_sum", "rm_tile_bucket", "rm_tile_count", "rm_tile_shape", "rm_get_tile",
            "rm_set_tile", "rm_tune", "rm_tune_load", "rm_set_graph", "rm_graph_stats",
            "rm_submit", "rm_poll", "rm_drain", "rm_prof_enable", "rm_prof_read", "rm_prof_chunks",
-           "rm_pw_upload_coupled", "rm_set_propagation", "rm_propagate", "rm_mqdt_unphysical_K", "rm_run_mqdt",
+           "rm_pw_upload_coupled", "rm_set_propagation", "rm_propagate", "rm_mqdt_unphysical_K", "rm_run_mqdt", "rm_mqdt_opts_default",
            "rm_hdat_open", "rm_hdat_close", "rm_hdat_error", "rm_hdat_target_info", "rm_hdat_attach", "rm_hdat_next",
            "rm_hdat_arrays", "rm_hdat_pw_desc", "rm_sizeh_read", "rm_omega_write"]
 
@@ -438,8 +444,8 @@ class Context:
                                               _ptr(nm), _ptr(st)))
         return Ku, nm, st
 
-    def run_mqdt(self, pw_id, E, ieq, fnumin, prec=FP64, split_delta=0.05, thr_guard=1e-10, want_K=True,
-                 stream=None):
+    def run_mqdt(self, pw_id, E, ieq, fnumin, iqdt=1, qetest=1e-7, prec=FP64, split_delta=0.05, thr_guard=1e-10,
+                 want_K=True, stream=None):
         """rm_run_mqdt on an ascending mesh: (omega, K or None, coarse mask, status)."""
         E, dev = self._E(E)
         n, nt = self._pw.get(pw_id, (1, 1))
@@ -449,7 +455,8 @@ class Context:
         co = self._alloc(E, (ne,), np.int8)
         st = self._alloc(E, (ne,), np.int32)
         o = self._opts(prec, split_delta, thr_guard, dev, stream)
-        self._check(_lib.rm_run_mqdt(self.h, pw_id, _ptr(E), ne, int(ieq), float(fnumin), ctypes.byref(o), _ptr(om),
+        mq = MqdtOpts(int(ieq), int(iqdt), float(fnumin), float(qetest))
+        self._check(_lib.rm_run_mqdt(self.h, pw_id, _ptr(E), ne, ctypes.byref(mq), ctypes.byref(o), _ptr(om),
                                      _ptr(K), _ptr(co), _ptr(st)))
         return om, K, co, st
 

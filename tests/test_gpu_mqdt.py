@@ -189,6 +189,38 @@ def _elim_cond(pw, Ev, fnumin, Ku, m):
     return np.linalg.cond(A, 1)
 
 
+def test_interpolating_K_and_qetest_vs_oracle(ctx):
+    """iqdt = 2 (the unphysical K interpolated, no recovery) and qetest (the
+    interpolant reused within qetest z^2) against the oracle's same options;
+    points that do not reuse are bitwise those of the run without qetest."""
+    pw = _wave(71, 40, True)
+    E = _mesh(pw, 121)
+    fnumin = np.sqrt(pw.z * pw.a)
+    pid = ctx.pw_upload(pw)
+    o = oracle.Oracle(pw, nthreads=_nt())
+    no = oracle.open_count(pw, E)
+    qe = 1.5 * (E[1] - E[0]) / pw.z ** 2
+    for iqdt, q in ((2, 0.0), (1, qe), (2, qe)):
+        om, K, co, st = ctx.run_mqdt(pid, E, 6, fnumin, iqdt=iqdt, qetest=q)
+        ref = o.mqdt_run(E, 6, fnumin, iqdt=iqdt, qetest=q)
+        assert np.array_equal(co.astype(bool), ref["coarse"]) and np.array_equal(st, ref["status"])
+        assert (st == 0).all()
+        ek = _kerr(K, ref["K"], no)
+        eo = omega_elementwise(om, ref["omega"])
+        _say(f"iqdt={iqdt} qetest={q:.1e}: K err max {ek.max():.1e} median {np.median(ek):.1e}, "
+             f"Omega max {eo.max():.1e}")
+        assert np.median(ek) <= 1e-11 and np.median(eo) <= 1e-11
+        assert ek.max() <= END_CEIL and eo.max() <= END_CEIL
+    # with qetest, the points that re-interpolate are those without it, bit for bit
+    _, K0, _, _ = ctx.run_mqdt(pid, E, 6, fnumin, qetest=0.0)
+    _, Kq, coq, _ = ctx.run_mqdt(pid, E, 6, fnumin, qetest=qe)
+    same = [np.array_equal(K0[e], Kq[e]) for e in range(E.size)]
+    assert sum(same) >= 40 and sum(same) <= E.size - 20
+    with pytest.raises(Exception):
+        ctx.run_mqdt(pid, E, 6, fnumin, iqdt=3)
+    ctx.pw_release(pid)
+
+
 def test_every_point_coarse_is_the_physical_path(ctx):
     pw = _wave(77, 24, False)
     E = _mesh(pw, 40)

@@ -278,3 +278,86 @@ def test_interpolation_converges_across_a_pole_of_the_unphysical_K():
                max(1.0, np.abs(ref["K"][e, :no[e], :no[e]]).max()) for e in range(E.size) if not r["coarse"][e]]
         med.append(np.median(err))
     assert med[0] < 1e-5 and 6.0 < med[1] / med[0] < 40.0, med
+
+
+def test_interpolating_K_itself_converges_only_without_poles():
+    """iqdt = 2 interpolates the unphysical K: with every point coarse it is the
+    direct path; where Ku has no pole in the mesh its error falls with the
+    coarse step like the S interpolation's; across a pole of Ku (the
+    highest-threshold window) it fails where the S interpolation does not."""
+    pw = synth.make_partial_wave(7, 10, 8, z=5.0, a=12.0, thr_range=(0.0, 2.0), pole_range=(20.0, 80.0),
+                                 npole=200, name="smooth")
+    th = np.unique(pw.e_thr)
+    E = np.linspace(th[1] + 0.01, th[2] - 0.005, 401)
+    o = oracle.Oracle(pw, nthreads=4)
+    fnumin = np.sqrt(pw.z * pw.a)
+    ref = o.run(E)
+    no = oracle.open_count(pw, E)
+
+    def med(r):
+        return np.median([np.abs(r["K"][e, :no[e], :no[e]] - ref["K"][e, :no[e], :no[e]]).max() /
+                          max(1.0, np.abs(ref["K"][e, :no[e], :no[e]]).max()) for e in range(E.size)
+                          if not r["coarse"][e]])
+
+    r1 = o.mqdt_run(E, 1, fnumin, iqdt=2)
+    assert max(np.abs(r1["K"][e] - ref["K"][e]).max() for e in range(E.size)) < 1e-10
+    m4, m8 = med(o.mqdt_run(E, 4, fnumin, iqdt=2)), med(o.mqdt_run(E, 8, fnumin, iqdt=2))
+    assert m4 < 1e-6 and 6.0 < m8 / m4 < 40.0, (m4, m8)
+    pw2, E2, _, fn2 = synth.config_mqdt(24, 20, 400)
+    o2 = oracle.Oracle(pw2, nthreads=4)
+    ref2 = o2.run(E2)
+    no2 = oracle.open_count(pw2, E2)
+
+    def med2(r):
+        return np.median([np.abs(r["K"][e, :no2[e], :no2[e]] - ref2["K"][e, :no2[e], :no2[e]]).max() /
+                          max(1.0, np.abs(ref2["K"][e, :no2[e], :no2[e]]).max()) for e in range(E2.size)
+                          if not r["coarse"][e]])
+
+    assert med2(o2.mqdt_run(E2, 4, fn2, iqdt=2)) > 100 * med2(o2.mqdt_run(E2, 4, fn2, iqdt=1))
+
+
+def test_qetest_reuses_the_interpolant_within_its_energy_step():
+    """A point within qetest z^2 of the last point evaluated at its own energy
+    takes the interpolant at that energy (its tan(pi nu) stays its own); other
+    points are as without qetest."""
+    pw = _wave(far=True)
+    th = np.unique(pw.e_thr)
+    E = np.linspace(th[1] + 0.01, th[2] - 0.003, 61)
+    o = oracle.Oracle(pw, nthreads=4)
+    fnumin = np.sqrt(pw.z * pw.a)
+    h = E[1] - E[0]
+    qe = 1.5 * h / pw.z ** 2  # every other fine point reuses its neighbour's interpolant
+    r0 = o.mqdt_run(E, 6, fnumin)
+    rq = o.mqdt_run(E, 6, fnumin, qetest=qe)
+    assert np.array_equal(r0["coarse"], rq["coarse"])
+    Ku, nm, _ = o.unphysical_K(E, fnumin)
+    last, reused, same = None, 0, 0
+    for e in range(E.size):
+        if e == 0 or nm[e] != nm[e - 1]:
+            last = None
+        if not rq["coarse"][e] and last is not None and abs(E[e] - E[last]) <= qe * pw.z ** 2:
+            # interpolant of the point `last`, eliminated at this point's energy
+            run = np.flatnonzero(nm == nm[e])
+            cl = [j for j in run if rq["coarse"][j]]
+            k = max([q for q in range(len(cl)) if cl[q] <= last] or [0])
+            w = min(4, len(cl))
+            s0 = max(0, min(k - 1, len(cl) - w))
+            nodes = cl[s0:s0 + w]
+            wts = [np.prod([(E[last] - E[m]) / (E[q] - E[m]) for m in nodes if m != q]) for q in nodes]
+            xy = [_minv(Ku[q], nm[q]) for q in nodes]
+            Ki = _ku_from_xy(sum(a * x for a, (x, _) in zip(wts, xy)), sum(a * y for a, (_, y) in zip(wts, xy)),
+                             nm[e])
+            K, _ = o.mqdt_eliminate(E[e:e + 1], fnumin, Ki[None], nm[e:e + 1])
+            no = oracle.open_count(pw, E[e:e + 1])[0]
+            b = K[0, :no, :no]
+            assert np.abs(rq["K"][e, :no, :no] - b).max() <= 1e-9 * max(1.0, np.abs(b).max()), e
+            reused += 1
+        else:
+            assert np.array_equal(rq["K"][e], r0["K"][e]), e
+            same += 1
+            last = e
+    assert reused >= 15 and same >= 15
+    with pytest.raises(ValueError):
+        o.mqdt_run(E, 6, fnumin, iqdt=3)
+    with pytest.raises(ValueError):
+        o.mqdt_run(E, 6, fnumin, qetest=-1.0)

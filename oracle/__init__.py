@@ -63,7 +63,7 @@ def lib():
         _lib.rmo_run_coupled.argtypes = [vp, vp, vp, i32, d, vp, vp, vp, vp, i32]
         _lib.rmo_unphysical_K.argtypes = [vp, vp, i32, d, d, vp, vp, vp, vp, i32]
         _lib.rmo_mqdt_eliminate.argtypes = [vp, vp, i32, d, vp, vp, vp, vp, i32]
-        _lib.rmo_mqdt_run.argtypes = [vp, vp, i32, i32, i32, d, d, d, vp, vp, vp, vp, i32]
+        _lib.rmo_mqdt_run.argtypes = [vp, vp, i32, i32, i32, i32, d, d, d, vp, vp, vp, vp, i32]
         _lib.rmo_mqdt_channel.argtypes = [d, d, d, i32, d, vp]
     return _lib
 
@@ -209,7 +209,8 @@ class Oracle:
                                  self.nthreads)
         return K, st
 
-    def mqdt_run(self, E, ieq: int, fnumin: float, thr_guard: float = 1e-10, iqdt: int = 1, qetest: float = 1e-7):
+    def mqdt_run(self, E, ieq: int, fnumin: float, thr_guard: float = 1e-10, iqdt: int = 1, qetest: float = 1e-7,
+                 sform: bool = False):
         """Coarse/fine operation on an ascending mesh: dict(omega, K, coarse, status)."""
         E = np.ascontiguousarray(E, dtype=np.float64)
         n, nt = self.pw.nchan, self.pw.ntarget
@@ -217,8 +218,8 @@ class Oracle:
         K = np.empty((E.size, n, n))
         co = np.zeros(E.size, np.int8)
         st = np.zeros(E.size, np.int32)
-        if lib().rmo_mqdt_run(self._p, _ptr(E), E.size, ieq, iqdt, fnumin, qetest, thr_guard, _ptr(om), _ptr(K),
-                              _ptr(co), _ptr(st), self.nthreads):
+        if lib().rmo_mqdt_run(self._p, _ptr(E), E.size, ieq, iqdt, int(sform), fnumin, qetest, thr_guard, _ptr(om),
+                              _ptr(K), _ptr(co), _ptr(st), self.nthreads):
             raise ValueError("ieq >= 1, iqdt 1 or 2, qetest >= 0, z > 0 and an ascending mesh are needed")
         return dict(omega=om, K=K, coarse=co.astype(bool), status=st)
 

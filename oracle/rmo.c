@@ -1502,6 +1502,91 @@ int rmo_mqdt_eliminate(const rmo_pw *pw, const double *E, int32_t ne, double fnu
   return 0;
 }
 
+/* Omega at energy E from the interpolated X + iY = (1 - i Ku)^-1 over the
+   members (row stride n), eliminating the closed members in S form: with the
+   unphysical S = 2(X + iY) - 1 and the decaying combination of the pair,
+   S = S_oo + S_oc (e^{-2 pi i nu} - S_cc)^-1 S_co, then
+   Omega_pq = (g/2) sum |S_ij - d_ij|^2 over open i in p, j in q. */
+static int32_t mqdt_s_eliminate(const rmo_pw *pw, double E, double fnumin, const ld *X, const ld *Y, int ns,
+                                double *omega) {
+  const int n = pw->nchan, nt = pw->ntarget;
+  int *mem = (int *)malloc(sizeof(int) * (n + 1));
+  int *oi = (int *)malloc(sizeof(int) * (n + 1)), *ci = (int *)malloc(sizeof(int) * (n + 1));
+  const int m = mqdt_members(pw, E, fnumin, mem);
+  int no = 0, nc = 0;
+  for (int t = 0; t < m; ++t) {
+    if (E - pw->e_thr[mem[t]] > 0) oi[no++] = t;
+    else ci[nc++] = t;
+  }
+  for (long t = 0; t < (long)nt * nt; ++t) omega[t] = 0.0;
+  int32_t st = m != ns ? RMO_PT_NOCONV : 0;
+  if (!st && no > 0) {
+#define SU(a, b) (2.0L * (X[(size_t)(a) * n + (b)] + I * Y[(size_t)(a) * n + (b)]) - ((a) == (b) ? 1.0L : 0.0L))
+    cld *C = (cld *)malloc(sizeof(cld) * ((size_t)nc * nc + 1));
+    cld *Z = (cld *)malloc(sizeof(cld) * ((size_t)nc * no + 1));
+    for (int k = 0; k < nc; ++k) {
+      ld sn, cs;
+      sincos_pi(2.0L * (ld)pw->z / sqrtl(-((ld)E - (ld)pw->e_thr[mem[ci[k]]])), &sn, &cs);
+      for (int l = 0; l < nc; ++l) C[(size_t)k * nc + l] = (k == l ? cs - I * sn : 0.0L) - SU(ci[k], ci[l]);
+      for (int j = 0; j < no; ++j) Z[(size_t)k * no + j] = SU(ci[k], oi[j]);
+    }
+    /* Gaussian elimination with partial pivoting on C, applied to Z */
+    for (int c = 0; c < nc && !st; ++c) {
+      int p = c;
+      for (int r = c + 1; r < nc; ++r)
+        if (cabsl(C[(size_t)r * nc + c]) > cabsl(C[(size_t)p * nc + c])) p = r;
+      if (cabsl(C[(size_t)p * nc + c]) == 0) {
+        st = RMO_PT_SINGULAR;
+        break;
+      }
+      if (p != c) {
+        for (int j = 0; j < nc; ++j) {
+          const cld t = C[(size_t)c * nc + j];
+          C[(size_t)c * nc + j] = C[(size_t)p * nc + j];
+          C[(size_t)p * nc + j] = t;
+        }
+        for (int j = 0; j < no; ++j) {
+          const cld t = Z[(size_t)c * no + j];
+          Z[(size_t)c * no + j] = Z[(size_t)p * no + j];
+          Z[(size_t)p * no + j] = t;
+        }
+      }
+      for (int r = c + 1; r < nc; ++r) {
+        const cld f = C[(size_t)r * nc + c] / C[(size_t)c * nc + c];
+        for (int j = c; j < nc; ++j) C[(size_t)r * nc + j] -= f * C[(size_t)c * nc + j];
+        for (int j = 0; j < no; ++j) Z[(size_t)r * no + j] -= f * Z[(size_t)c * no + j];
+      }
+    }
+    if (!st) {
+      for (int r = nc - 1; r >= 0; --r)
+        for (int j = 0; j < no; ++j) {
+          cld acc = Z[(size_t)r * no + j];
+          for (int q = r + 1; q < nc; ++q) acc -= C[(size_t)r * nc + q] * Z[(size_t)q * no + j];
+          Z[(size_t)r * no + j] = acc / C[(size_t)r * nc + r];
+        }
+      const ld half_g = 0.5L * (ld)pw->g;
+      ld *om = (ld *)calloc((size_t)nt * nt, sizeof(ld));
+      for (int i = 0; i < no; ++i)
+        for (int j = 0; j < no; ++j) {
+          cld Sij = SU(oi[i], oi[j]);
+          for (int k = 0; k < nc; ++k) Sij += SU(oi[i], ci[k]) * Z[(size_t)k * no + j];
+          const cld T = Sij - (i == j ? 1.0L : 0.0L);
+          om[(size_t)pw->target[mem[oi[i]]] * nt + pw->target[mem[oi[j]]]] +=
+              half_g * (creall(T) * creall(T) + cimagl(T) * cimagl(T));
+        }
+      for (long t = 0; t < (long)nt * nt; ++t) omega[t] = (double)om[t];
+      free(om);
+    }
+#undef SU
+    free(C);
+    free(Z);
+  }
+  free(mem);
+  free(oi);
+  free(ci);
+  return st;
+}
+
 /* (1 - i K)^-1 of the leading m x m block of K (row stride n) by complex
    Gauss-Jordan elimination with partial pivoting; X, Y (row stride n) get its
    real and imaginary parts.  Returns -1 for a zero pivot. */
@@ -1571,10 +1656,10 @@ static int mqdt_minv(const double *K, int n, int m, ld *X, ld *Y) {
    point within qetest z^2 of the last point of its run that was evaluated at
    its own energy takes the interpolant at that energy (tan(pi nu) stays its
    own).  coarse[e] (may be NULL) is set to 1 at coarse points. */
-int rmo_mqdt_run(const rmo_pw *pw, const double *E, int32_t ne, int32_t ieq, int32_t iqdt, double fnumin,
-                 double qetest, double thr_guard, double *omega, double *K, int8_t *coarse, int32_t *status,
-                 int32_t nthreads) {
-  if (ieq < 1 || pw->z <= 0 || (iqdt != 1 && iqdt != 2) || !(qetest >= 0)) return -1;
+int rmo_mqdt_run(const rmo_pw *pw, const double *E, int32_t ne, int32_t ieq, int32_t iqdt, int32_t sform,
+                 double fnumin, double qetest, double thr_guard, double *omega, double *K, int8_t *coarse,
+                 int32_t *status, int32_t nthreads) {
+  if (ieq < 1 || pw->z <= 0 || (iqdt != 1 && iqdt != 2) || (sform && iqdt != 1) || !(qetest >= 0)) return -1;
   for (int e = 1; e < ne; ++e)
     if (!(E[e] > E[e - 1])) return -1;
   const int n = pw->nchan, nt = pw->ntarget;
@@ -1664,6 +1749,20 @@ int rmo_mqdt_run(const rmo_pw *pw, const double *E, int32_t ne, int32_t ieq, int
           Xi[t] += wt * Xc[(size_t)cl[q] * nn + t];
           Yi[t] += wt * Yc[(size_t)cl[q] * nn + t];
           Ki[t] += wt * (ld)Kc[(size_t)cl[q] * nn + t]; /* iqdt = 2 */
+        }
+      }
+      if (!st && sform) {
+        /* Omega from the S form; K is not formed */
+        for (long t = 0; t < nn; ++t) Kl[t] = 0.0;
+        st = mqdt_s_eliminate(pw, E[e], fnumin, Xi, Yi, ns[e], omega + (long)e * nt * nt);
+        if (!st) {
+          status[e] = 0;
+          free(Xi);
+          free(Yi);
+          free(Ki);
+          free(cl);
+          if (!K) free(Kl);
+          continue;
         }
       }
       if (!st && iqdt == 1) {

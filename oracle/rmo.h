@@ -122,9 +122,12 @@ int rmo_mqdt_eliminate(const rmo_pw *pw, const double *E, int32_t ne, double fnu
    Omega at every point.  coarse (may be NULL) marks the coarse points.
    Returns -1 for ieq < 1, iqdt not 1 or 2, qetest < 0, z <= 0 or a mesh that
    is not ascending. */
-int rmo_mqdt_run(const rmo_pw *pw, const double *E, int32_t ne, int32_t ieq, int32_t iqdt, double fnumin,
-                 double qetest, double thr_guard, double *omega, double *K, int8_t *coarse, int32_t *status,
-                 int32_t nthreads);
+int rmo_mqdt_run(const rmo_pw *pw, const double *E, int32_t ne, int32_t ieq, int32_t iqdt, int32_t sform,
+                 double fnumin, double qetest, double thr_guard, double *omega, double *K, int8_t *coarse,
+                 int32_t *status, int32_t nthreads);
+/* (sform = 1, iqdt = 1: Omega from the elimination in S form,
+   S = S_oo + S_oc (e^{-2 pi i nu} - S_cc)^-1 S_co of the interpolated
+   unphysical S; K is not formed and left zero.) */
 /* Channel functions of the unphysical K at r = a: (s, s', c, c') open,
    (f, f', g, g') closed member, (0, 0, e, e') otherwise; returns 1 for a
    member, 0 otherwise, -1 on failure. */

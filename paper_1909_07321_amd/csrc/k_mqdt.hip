@@ -22,6 +22,7 @@
 // which the batched LU with its tail back substitution solves unchanged
 // (k_linalg.hip): K is the last n_o rows, as in the physical path.
 #include "k_common.h"
+#include "k_mqdt.h"
 #include "rm.h"
 
 namespace rm {
@@ -74,7 +75,8 @@ __global__ __launch_bounds__(256) void k_mqdt_setup(const DevPW *__restrict__ ta
                                                     double thr_guard, int *__restrict__ syspos,
                                                     int *__restrict__ spos, double *__restrict__ tanv,
                                                     int *__restrict__ dims, int *__restrict__ nsys,
-                                                    int *__restrict__ status) {
+                                                    int *__restrict__ status, int *__restrict__ clist,
+                                                    int *__restrict__ olist, int *__restrict__ cch) {
   __shared__ long long cnt[256];
   __shared__ int flag;
   const int e = blockIdx.x, t = threadIdx.x;
@@ -123,6 +125,14 @@ __global__ __launch_bounds__(256) void k_mqdt_setup(const DevPW *__restrict__ ta
       tv[i] = 0.0;
       continue;
     }
+    if (clist) {
+      if (eps > 0) {
+        olist[(size_t)e * ldo + po] = pm;
+      } else {
+        clist[(size_t)e * ldo + pc] = pm;
+        cch[(size_t)e * ldo + pc] = i;
+      }
+    }
     mp[i] = pm++;
     if (eps > 0) {
       sp[i] = ncm + po++;
@@ -142,10 +152,269 @@ __global__ __launch_bounds__(256) void k_mqdt_setup(const DevPW *__restrict__ ta
   }
 }
 
+void launch_mqdt_setup_lists(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const double *E,
+                             double thr_guard, int *syspos, int *spos, double *tanv, int *dims, int *nsys, int *status,
+                             int *clist, int *olist, int *cch) {
+  hipLaunchKernelGGL(k_mqdt_setup, dim3(L.ne), dim3(256), 0, s, tab, pwi, E, L.ldo, L.fnumin, thr_guard, syspos, spos,
+                     tanv, dims, nsys, status, clist, olist, cch);
+}
+
 void launch_mqdt_setup(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const double *E,
                        double thr_guard, int *syspos, int *spos, double *tanv, int *dims, int *nsys, int *status) {
-  hipLaunchKernelGGL(k_mqdt_setup, dim3(L.ne), dim3(256), 0, s, tab, pwi, E, L.ldo, L.fnumin, thr_guard, syspos, spos,
-                     tanv, dims, nsys, status);
+  launch_mqdt_setup_lists(s, L, tab, pwi, E, thr_guard, syspos, spos, tanv, dims, nsys, status, nullptr, nullptr,
+                          nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// Elimination in S form (Omega only).  With the unphysical S = 2(X + iY) - 1 of
+// the interpolated X + iY = (1 - i Ku)^-1 and the decaying combination
+// f cos(pi nu) - g sin(pi nu) of a closed member, the open-channel S is
+//   S = S_oo + S_oc (e^{-2 pi i nu} - S_cc)^-1 S_co,
+// and Omega follows from |S - 1|^2 (the S/Omega stage's k_omega, fed with
+// (S + 1)/2).  clist / olist: member positions of the closed / open members
+// in ascending order; cch: the closed members' channels.
+
+// X + iY at (member row r, member column c) interpolated over the energy's
+// coarse points
+struct Interp {
+  const double *xq[4], *yq[4];
+  double wq[4];
+  long n;
+  __device__ __forceinline__ void at(int r, int c, double &x, double &y) const {
+    x = 0.0;
+    y = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const size_t o = (size_t)r * n + c;
+      x += wq[q] * xq[q][o];
+      y += wq[q] * yq[q][o];
+    }
+  }
+};
+
+__device__ __forceinline__ Interp make_interp(const double *Xc, const double *Yc, const int *cidx, const double *cw,
+                                              int e, int n) {
+  Interp I;
+  I.n = n;
+  const size_t nn = (size_t)n * n;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int c = cidx[4 * e + q];
+    I.wq[q] = c >= 0 ? cw[4 * e + q] : 0.0;
+    I.xq[q] = Xc + (c >= 0 ? c : 0) * nn;
+    I.yq[q] = Yc + (c >= 0 ? c : 0) * nn;
+  }
+  return I;
+}
+
+// W = (e^{-2 pi i nu} - S_cc)^-1, n_c <= MQDT_SMAX, one workgroup per energy:
+// in-place Gauss-Jordan with partial pivoting on the complex matrix in LDS,
+// the row interchanges undone on the columns at the end.  W [e][SMAX][SMAX]
+// as two planes.
+__global__ __launch_bounds__(256) void k_mqdt_sinv(const DevPW *__restrict__ tab, const int *__restrict__ pwi,
+                                                   const double *__restrict__ E, const int *__restrict__ nsys,
+                                                   const int *__restrict__ nopen, const int *__restrict__ clist,
+                                                   const int *__restrict__ cch, long ldo,
+                                                   const double *__restrict__ Xc, const double *__restrict__ Yc,
+                                                   const int *__restrict__ cidx, const double *__restrict__ cw,
+                                                   const int *__restrict__ status, double *__restrict__ Wr,
+                                                   double *__restrict__ Wi) {
+  constexpr int SM = MQDT_SMAX;
+  __shared__ double Ar[SM][SM + 1], Ai[SM][SM + 1];
+  __shared__ int perm[SM], piv_s;
+  const int e = blockIdx.x, t = threadIdx.x;
+  const int nc = nsys[e] - nopen[e];
+  if (status[e] || nc <= 0 || nc > SM) return;
+  const DevPW &p = tab[pwi[e]];
+  const Interp I = make_interp(Xc, Yc, cidx, cw, e, p.n);
+  const int *cl = clist + (size_t)e * ldo;
+  for (int idx = t; idx < nc * nc; idx += 256) {
+    const int k = idx / nc, l = idx % nc;
+    double x, y;
+    I.at(cl[k], cl[l], x, y);
+    double re = -(2.0 * x - (k == l ? 1.0 : 0.0)), im = -2.0 * y;
+    if (k == l) {
+      const double nu = p.z / sqrt(p.ethr[cch[(size_t)e * ldo + k]] - E[e]);
+      re += cospi(2.0 * nu);
+      im -= sinpi(2.0 * nu);
+    }
+    Ar[k][l] = re;
+    Ai[k][l] = im;
+  }
+  __syncthreads();
+  for (int c = 0; c < nc; ++c) {
+    if (t == 0) {
+      int pr = c;
+      double best = Ar[c][c] * Ar[c][c] + Ai[c][c] * Ai[c][c];
+      for (int r = c + 1; r < nc; ++r) {
+        const double v = Ar[r][c] * Ar[r][c] + Ai[r][c] * Ai[r][c];
+        if (v > best) best = v, pr = r;
+      }
+      piv_s = pr;
+      perm[c] = pr;
+    }
+    __syncthreads();
+    const int pr = piv_s;
+    if (pr != c)
+      for (int j = t; j < nc; j += 256) {
+        double a = Ar[c][j], b = Ai[c][j];
+        Ar[c][j] = Ar[pr][j];
+        Ai[c][j] = Ai[pr][j];
+        Ar[pr][j] = a;
+        Ai[pr][j] = b;
+      }
+    __syncthreads();
+    // 1 / pivot, then row c scaled with the pivot entry replaced by 1
+    const double pr_ = Ar[c][c], pi_ = Ai[c][c];
+    const double d = pr_ * pr_ + pi_ * pi_;
+    const double ir = pr_ / d, ii = -pi_ / d;
+    __syncthreads();
+    for (int j = t; j < nc; j += 256) {
+      const double a = j == c ? 1.0 : Ar[c][j], b = j == c ? 0.0 : Ai[c][j];
+      Ar[c][j] = a * ir - b * ii;
+      Ai[c][j] = a * ii + b * ir;
+    }
+    __syncthreads();
+    // other rows: row r -= f row c with f = A[r][c] (its column-c entry becomes -f / pivot)
+    for (int idx = t; idx < nc * nc; idx += 256) {
+      const int r = idx / nc, j = idx % nc;
+      if (r == c) continue;
+      const double fr = Ar[r][c], fi = Ai[r][c];
+      if (j == c) continue;
+      const double ar = Ar[c][j], ai = Ai[c][j];
+      Ar[r][j] -= fr * ar - fi * ai;
+      Ai[r][j] -= fr * ai + fi * ar;
+    }
+    __syncthreads();
+    for (int r = t; r < nc; r += 256) {
+      if (r == c) continue;
+      const double fr = Ar[r][c], fi = Ai[r][c];
+      // the column of the inverse: -f * (1 / pivot) = -f * A[c][c] (already 1/pivot)
+      const double cr = Ar[c][c], ci = Ai[c][c];
+      Ar[r][c] = -(fr * cr - fi * ci);
+      Ai[r][c] = -(fr * ci + fi * cr);
+    }
+    __syncthreads();
+  }
+  // undo the interchanges on the columns, last first
+  for (int c = nc - 1; c >= 0; --c) {
+    const int pr = perm[c];
+    if (pr != c)
+      for (int r = t; r < nc; r += 256) {
+        double a = Ar[r][c], b = Ai[r][c];
+        Ar[r][c] = Ar[r][pr];
+        Ai[r][c] = Ai[r][pr];
+        Ar[r][pr] = a;
+        Ai[r][pr] = b;
+      }
+    __syncthreads();
+  }
+  double *wr = Wr + (size_t)e * SM * SM, *wi = Wi + (size_t)e * SM * SM;
+  for (int idx = t; idx < nc * nc; idx += 256) {
+    const int k = idx / nc, l = idx % nc;
+    wr[k * SM + l] = Ar[k][l];
+    wi[k * SM + l] = Ai[k][l];
+  }
+}
+
+// Z = W S_co, stored as Zt [e][n][SMAX] (open position major) in two planes;
+// one thread per open position.
+__global__ __launch_bounds__(256) void k_mqdt_sz(const DevPW *__restrict__ tab, const int *__restrict__ pwi,
+                                                 const int *__restrict__ nsys, const int *__restrict__ nopen,
+                                                 const int *__restrict__ clist, const int *__restrict__ olist,
+                                                 long ldo, const double *__restrict__ Xc,
+                                                 const double *__restrict__ Yc, const int *__restrict__ cidx,
+                                                 const double *__restrict__ cw, const int *__restrict__ status,
+                                                 const double *__restrict__ Wr, const double *__restrict__ Wi,
+                                                 double *__restrict__ Zr, double *__restrict__ Zi, long ldz) {
+  constexpr int SM = MQDT_SMAX, KB = 16;
+  const int e = blockIdx.y, j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int no = nopen[e], nc = nsys[e] - no;
+  if (status[e] || j >= no || nc <= 0 || nc > SM) return;
+  const DevPW &p = tab[pwi[e]];
+  const Interp I = make_interp(Xc, Yc, cidx, cw, e, p.n);
+  const int *cl = clist + (size_t)e * ldo;
+  const int oj = olist[(size_t)e * ldo + j];
+  const double *wr = Wr + (size_t)e * SM * SM, *wi = Wi + (size_t)e * SM * SM;
+  double *zr = Zr + ((size_t)e * ldz + j) * SM, *zi = Zi + ((size_t)e * ldz + j) * SM;
+  for (int k0 = 0; k0 < nc; k0 += KB) {
+    double ar[KB], ai[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) ar[k] = ai[k] = 0.0;
+    for (int l = 0; l < nc; ++l) {
+      double x, y;
+      I.at(cl[l], oj, x, y);
+      const double sr = 2.0 * x, si = 2.0 * y;  // S_co: off the diagonal
+#pragma unroll
+      for (int k = 0; k < KB; ++k) {
+        if (k0 + k >= nc) break;
+        const double vr = wr[(k0 + k) * SM + l], vi = wi[(k0 + k) * SM + l];
+        ar[k] += vr * sr - vi * si;
+        ai[k] += vr * si + vi * sr;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < KB; ++k)
+      if (k0 + k < nc) {
+        zr[k0 + k] = ar[k];
+        zi[k0 + k] = ai[k];
+      }
+  }
+}
+
+// S = S_oo + S_oc Z for open row i (one workgroup per (i, energy)), written as
+// (S + 1)/2 over the planes the S/Omega stage leaves for k_omega: real part in
+// columns [0, n_o), imaginary part from column roff, row i.
+__global__ __launch_bounds__(256) void k_mqdt_som(const DevPW *__restrict__ tab, const int *__restrict__ pwi,
+                                                  const int *__restrict__ nsys, const int *__restrict__ nopen,
+                                                  const int *__restrict__ clist, const int *__restrict__ olist,
+                                                  long ldo, const double *__restrict__ Xc,
+                                                  const double *__restrict__ Yc, const int *__restrict__ cidx,
+                                                  const double *__restrict__ cw, const int *__restrict__ status,
+                                                  const double *__restrict__ Zr, const double *__restrict__ Zi,
+                                                  long ldz, double *__restrict__ aug, long ldaug, long strideA,
+                                                  long roff) {
+  constexpr int SM = MQDT_SMAX;
+  __shared__ double br[SM], bi[SM];
+  const int i = blockIdx.x, e = blockIdx.y, t = threadIdx.x;
+  const int no = nopen[e], nc = nsys[e] - no;
+  if (status[e] || i >= no || nc > SM) return;
+  const DevPW &p = tab[pwi[e]];
+  const Interp I = make_interp(Xc, Yc, cidx, cw, e, p.n);
+  const int *cl = clist + (size_t)e * ldo, *ol = olist + (size_t)e * ldo;
+  const int oi = ol[i];
+  for (int k = t; k < nc; k += 256) {
+    double x, y;
+    I.at(oi, cl[k], x, y);
+    br[k] = 2.0 * x;  // S_oc: off the diagonal
+    bi[k] = 2.0 * y;
+  }
+  __syncthreads();
+  double *row = aug + (size_t)e * strideA + (size_t)i * ldaug;
+  for (int j = t; j < no; j += 256) {
+    double x, y;
+    I.at(oi, ol[j], x, y);
+    double sr = 2.0 * x - (i == j ? 1.0 : 0.0), si = 2.0 * y;
+    const double *zr = Zr + ((size_t)e * ldz + j) * SM, *zi = Zi + ((size_t)e * ldz + j) * SM;
+    for (int k = 0; k < nc; ++k) {
+      sr += br[k] * zr[k] - bi[k] * zi[k];
+      si += br[k] * zi[k] + bi[k] * zr[k];
+    }
+    row[j] = 0.5 * (sr + (i == j ? 1.0 : 0.0));
+    row[roff + j] = 0.5 * si;
+  }
+}
+
+void launch_mqdt_sform(hipStream_t s, const Lay &L, const DevPW *tab, const int *pwi, const double *E,
+                       const int *nsys, const int *nopen, const int *clist, const int *olist, const int *cch,
+                       const double *Xc, const double *Yc, const int *cidx, const double *cw, const int *status,
+                       double *Wr, double *Wi, double *Zr, double *Zi, double *aug) {
+  hipLaunchKernelGGL(k_mqdt_sinv, dim3(L.ne), dim3(256), 0, s, tab, pwi, E, nsys, nopen, clist, cch, L.ldo, Xc, Yc,
+                     cidx, cw, status, Wr, Wi);
+  hipLaunchKernelGGL(k_mqdt_sz, dim3((L.nmax + 255) / 256, L.ne), dim3(256), 0, s, tab, pwi, nsys, nopen, clist,
+                     olist, L.ldo, Xc, Yc, cidx, cw, status, Wr, Wi, Zr, Zi, (long)L.nmax);
+  hipLaunchKernelGGL(k_mqdt_som, dim3(L.nmax, L.ne), dim3(256), 0, s, tab, pwi, nsys, nopen, clist, olist, L.ldo, Xc,
+                     Yc, cidx, cw, status, Zr, Zi, (long)L.nmax, aug, L.ldaug, L.sA, L.roff);
 }
 
 // One workgroup per (member channel i, energy): row spos[i] of the energy's

@@ -31,6 +31,7 @@
 #include <vector>
 
 #include "rm.h"
+#include "k_mqdt.h"
 #include "rm_internal.h"
 
 using namespace rm;
@@ -2398,6 +2399,34 @@ rm_status rm_run_mqdt(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, co
     ctx->err = "rm_run_mqdt: device temporaries";
     return RM_E_NOMEM;
   }
+  // Omega only, iqdt = 1 and at most MQDT_SMAX closed members at every point:
+  // the closed members are eliminated in S form (no K is formed)
+  bool sroute = iqdt == 1 && !K;
+  if (sroute) {
+    std::vector<double> thr;
+    {
+      std::lock_guard<std::mutex> g(ctx->mu);
+      auto it = ctx->hthr.find(pw);
+      if (it != ctx->hthr.end()) thr = it->second;
+    }
+    if (thr.size() != (size_t)n) sroute = false;
+    for (int e = 0; e < ne && sroute; ++e) {
+      int no = 0;
+      for (double tv : thr) no += hE[e] - tv > 0.0;
+      if (!flag[e] && nm[e] - no > MQDT_SMAX) sroute = false;
+    }
+  }
+  int *dlist = nullptr;
+  double *dW = nullptr, *dZ = nullptr;
+  if (sroute) {
+    dlist = tmp.get<int>(3 * (size_t)cap * ldo);
+    dW = tmp.get<double>(2 * (size_t)cap * MQDT_SMAX * MQDT_SMAX);
+    dZ = tmp.get<double>(2 * (size_t)cap * ldo * MQDT_SMAX);
+    if (!dlist || !dW || !dZ) {
+      ctx->err = "rm_run_mqdt: device temporaries";
+      return RM_E_NOMEM;
+    }
+  }
   HIPCHK(hipMemcpyAsync(dci, hc.data(), sizeof(int) * 4 * ne, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(dci + 4 * (size_t)ne, st0.data(), sizeof(int) * ne, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(dcw, hw.data(), sizeof(double) * 4 * ne, hipMemcpyHostToDevice, s));
@@ -2416,6 +2445,20 @@ rm_status rm_run_mqdt(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, co
     int *syspos = dsys, *spos = dsys + (size_t)cap * ldo, *nsys = dsys + 2 * (size_t)cap * ldo;
     HIPCHK(hipMemcpyAsync(w.status, dci + 4 * (size_t)ne + e0, sizeof(int) * m, hipMemcpyDeviceToDevice, s));
     launch_openlist(s, L, w.tab, w.pwi, w.E, w.nopen, w.openidx, w.openpos, w.colpos, w.openflag);
+    if (sroute) {
+      int *clist = dlist, *olist = dlist + (size_t)cap * ldo, *cch = dlist + 2 * (size_t)cap * ldo;
+      launch_mqdt_setup_lists(s, Lq, w.tab, w.pwi, w.E, o.thr_guard, syspos, spos, dtan, w.dims, nsys, w.status,
+                              clist, olist, cch);
+      launch_mqdt_sform(s, L, w.tab, w.pwi, w.E, nsys, w.nopen, clist, olist, cch, Xc, Yc, dci + 4 * (size_t)e0,
+                        dcw + 4 * (size_t)e0, w.status, dW, dW + (size_t)cap * MQDT_SMAX * MQDT_SMAX, dZ,
+                        dZ + (size_t)cap * ldo * MQDT_SMAX, w.aug);
+      launch_omega(s, L, w.tab, w.pwi, w.openpos, w.nopen, w.aug, w.aug + L.roff, w.omega, nullptr);
+      launch_finalize(s, L, w.tab, w.pwi, w.status, w.omega, nullptr, nullptr);
+      HIPCHK(hipMemcpyAsync(omega + (size_t)e0 * nt * nt, w.omega, sizeof(double) * m * nt * nt, kind_out(o), s));
+      HIPCHK(hipMemcpyAsync(status + e0, w.status, sizeof(int) * m, kind_out(o), s));
+      HIPCHK(hipGetLastError());
+      continue;
+    }
     launch_mqdt_setup(s, Lq, w.tab, w.pwi, w.E, o.thr_guard, syspos, spos, dtan, w.dims, nsys, w.status);
     if (iqdt == 1) {
       // Ku = Y X^-1 from the interpolated X, Y: [X | Y] solved in full, transposed into Kw

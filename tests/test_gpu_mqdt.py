@@ -221,6 +221,30 @@ def test_interpolating_K_and_qetest_vs_oracle(ctx):
     ctx.pw_release(pid)
 
 
+@pytest.mark.parametrize("n,ieq", [(12, 4), (40, 6), (97, 3)])
+def test_s_form_omega_vs_oracle(ctx, n, ieq):
+    """Omega only: the closed members are eliminated in S form (no K formed),
+    against the oracle's S form; at every-point-coarse against rm_run."""
+    pw = _wave(53 + n, n, True)
+    E = _mesh(pw, 121)
+    fnumin = np.sqrt(pw.z * pw.a)
+    pid = ctx.pw_upload(pw)
+    om, K, co, st = ctx.run_mqdt(pid, E, ieq, fnumin, want_K=False)
+    assert K is None
+    ref = oracle.Oracle(pw, nthreads=_nt()).mqdt_run(E, ieq, fnumin, sform=True)
+    assert np.array_equal(co.astype(bool), ref["coarse"]) and np.array_equal(st, ref["status"])
+    assert (st == 0).all()
+    eo = omega_elementwise(om, ref["omega"])
+    om1, _, _, st1 = ctx.run_mqdt(pid, E[:30], 1, fnumin, want_K=False)
+    om2, _, st2 = ctx.run(pid, E[:30])
+    e1 = omega_elementwise(om1, om2)
+    _say(f"S form n={n} ieq={ieq}: Omega err max {eo.max():.1e} median {np.median(eo):.1e}; every point coarse "
+         f"against rm_run {e1.max():.1e}")
+    assert np.median(eo) <= 1e-11 and eo.max() <= END_CEIL
+    assert (st1 == 0).all() and e1.max() <= 1e-9
+    ctx.pw_release(pid)
+
+
 def test_every_point_coarse_is_the_physical_path(ctx):
     pw = _wave(77, 24, False)
     E = _mesh(pw, 40)

@@ -361,3 +361,36 @@ def test_qetest_reuses_the_interpolant_within_its_energy_step():
         o.mqdt_run(E, 6, fnumin, iqdt=3)
     with pytest.raises(ValueError):
         o.mqdt_run(E, 6, fnumin, qetest=-1.0)
+
+
+def test_s_form_elimination():
+    """Omega from the closed members eliminated in S form,
+    S = S_oo + S_oc (e^{-2 pi i nu} - S_cc)^-1 S_co of the interpolated
+    unphysical S: the direct Omega at every-point-coarse, fourth-order
+    convergence where R is smooth, and agreement with the K route to the
+    interpolation error."""
+    pw = synth.make_partial_wave(7, 10, 8, z=5.0, a=12.0, thr_range=(0.0, 2.0), pole_range=(20.0, 80.0),
+                                 npole=200, name="smooth")
+    th = np.unique(pw.e_thr)
+    E = np.linspace(th[1] + 0.01, th[2] - 0.005, 401)
+    o = oracle.Oracle(pw, nthreads=4)
+    fn = np.sqrt(pw.z * pw.a)
+    ref = o.run(E)
+
+    def oerr(a, b):
+        a, b = a.reshape(E.size, -1), b.reshape(E.size, -1)
+        top = np.abs(b).max(axis=1, keepdims=True)
+        return (np.abs(a - b) / np.maximum(np.abs(b), 1e-12 * top)).max(axis=1)
+
+    r1 = o.mqdt_run(E, 1, fn, sform=True)
+    assert (r1["status"] == 0).all() and oerr(r1["omega"], ref["omega"]).max() < 1e-11
+    assert not r1["K"].any()  # K is not formed in S form
+    med = []
+    for q in (8, 16):
+        rs, rk = o.mqdt_run(E, q, fn, sform=True), o.mqdt_run(E, q, fn)
+        f = ~rs["coarse"]
+        med.append(np.median(oerr(rs["omega"], ref["omega"])[f]))
+        assert np.median(oerr(rs["omega"], rk["omega"])[f]) < 10 * med[-1] + 1e-14
+    assert med[0] < 1e-12 and 6.0 < med[1] / med[0] < 40.0, med
+    with pytest.raises(ValueError):
+        o.mqdt_run(E, 4, fn, iqdt=2, sform=True)

@@ -70,6 +70,9 @@ MUTANTS = {
     "mqdt_minv_sign": ("(i == j ? 1.0L : 0.0L) - I * (ld)K[(size_t)i * n + j];",
                        "(i == j ? 1.0L : 0.0L) + I * (ld)K[(size_t)i * n + j];",
                        "test_oracle_mqdt.py::test_fine_point_uses_the_four_surrounding_coarse_points"),
+    "mqdt_sform_phase": ("C[(size_t)k * nc + l] = (k == l ? cs - I * sn : 0.0L) - SU(ci[k], ci[l]);",
+                         "C[(size_t)k * nc + l] = (k == l ? cs + I * sn : 0.0L) - SU(ci[k], ci[l]);",
+                         "test_oracle_mqdt.py::test_s_form_elimination"),
     "mqdt_window": ("int st0 = k - 1;", "int st0 = k - 3;",
                     "test_oracle_mqdt.py::test_fine_point_uses_the_four_surrounding_coarse_points"),
     "taylor_start_binomial": ("for (int t = 1; t <= p; ++t) binom = binom * (ld)(lam + t) / (ld)t;",

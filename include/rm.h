@@ -227,10 +227,17 @@ rm_status rm_mqdt_unphysical_K(rm_ctx *ctx, int32_t pw, const double *E, int32_t
    eigenphase passes pi/2).  Each point takes the elementwise Lagrange
    interpolant of X and Y through the four coarse points of its run around it
    (the window starts at the coarse point before the last one at or below it,
-   clamped to the run; all of them if fewer than four), recovers Ku = Y X^-1
-   (a batched LU of the member count; symmetrised, as the interpolant keeps it
-   symmetric only to the interpolation error), eliminates its closed members as above
-   (a second batched LU), and S, T and Omega follow as in rm_run.  At coarse
+   clamped to the run; all of them if fewer than four).  With K requested (or
+   iqdt = 2, or more than 48 closed members at some point) it recovers
+   Ku = Y X^-1 (a batched LU of the member count; symmetrised, as the
+   interpolant keeps it symmetric only to the interpolation error; iqdt = 2
+   interpolates Ku itself), eliminates its closed members as above (a second
+   batched LU), and S, T and Omega follow as in rm_run.  Without K (K = NULL,
+   iqdt = 1) the closed members are eliminated from the interpolated
+   unphysical S_u = 2(X + iY) - 1 itself,
+     S = S_u,oo + S_u,oc (e^{-2 pi i nu} - S_u,cc)^-1 S_u,co,
+   and Omega follows from |S - 1|^2: no K is formed, the cost per point is
+   O(n_o^2 n_c), and the two routes agree to the interpolation error.  At coarse
    points the result is the physical one (up to rounding).  Outputs as rm_run
    (omega [ne][nt][nt], K [ne][n][n] or NULL, status [ne]); coarse [ne] int8
    (may be NULL) marks the coarse points.  A point inherits the flags of the

@@ -350,18 +350,46 @@ def mqdt_measure(ctx) -> dict:
     torch.cuda.synchronize()
     dt2 = time.perf_counter() - t1
     fine = ((co == 0) & (st == 0) & (st2 == 0)).cpu().numpy()
-    a = om.reshape(E.size, -1)
     b = om2.reshape(E.size, -1)
     top = b.abs().amax(dim=1, keepdim=True)
     den = torch.maximum(b.abs(), 1e-12 * top)
-    eo = ((a - b).abs() / den).amax(dim=1).cpu().numpy()[fine]
+
+    def err(x):
+        return ((x.reshape(E.size, -1) - b).abs() / den).amax(dim=1).cpu().numpy()
+
+    eo = err(om)[fine]
     co_n, st_n = int(co.sum().item()), int((st != 0).sum().item())
-    del om, om2, a, b, den
+    del om
+    # the same in FP32-split precision (the coarse points' R contraction and the
+    # direct path's), Omega against the FP64 direct one
+    ctx.run_mqdt(pid, Ed[:64], ieq, fnumin, want_K=False, prec=rm.FP32_SPLIT)
+    ctx.run(pid, Ed[:64], want_K=False, prec=rm.FP32_SPLIT)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    oms, _, _, sts = ctx.run_mqdt(pid, Ed, ieq, fnumin, want_K=False, prec=rm.FP32_SPLIT)
+    torch.cuda.synchronize()
+    dts = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    oms2, _, sts2 = ctx.run(pid, Ed, want_K=False, prec=rm.FP32_SPLIT)
+    torch.cuda.synchronize()
+    dts2 = time.perf_counter() - t1
+    ok = ((sts == 0) & (sts2 == 0)).cpu().numpy()
+    es, es2 = err(oms)[ok & fine], err(oms2)[ok & fine]
+    del oms, oms2, om2, b, den
+    split = dict(points_per_s=E.size / dts, direct_points_per_s=E.size / dts2, speedup=dts2 / dts,
+                 omega_err_vs_fp64_direct=dict(median=float(np.median(es)), p99=float(np.quantile(es, 0.99))),
+                 direct_omega_err_vs_fp64_direct=dict(median=float(np.median(es2)),
+                                                      p99=float(np.quantile(es2, 0.99))))
+    log(f"mqdt split: {split['points_per_s']:.0f} points/s against {split['direct_points_per_s']:.0f} points/s "
+        f"direct split ({split['speedup']:.2f}x); Omega vs the FP64 direct one median "
+        f"{split['omega_err_vs_fp64_direct']['median']:.1e} (direct split "
+        f"{split['direct_omega_err_vs_fp64_direct']['median']:.1e})")
     ctx.pw_release(pid)
     res = dict(points_per_s=E.size / dt, seconds=dt, direct_points_per_s=E.size / dt2, direct_seconds=dt2,
                speedup=dt2 / dt, coarse_points=co_n, flagged_energies=st_n,
                omega_err_vs_direct=dict(median=float(np.median(eo)), p99=float(np.quantile(eo, 0.99)),
                                         max=float(eo.max())),
+               split=split,
                workload=f"one wave, {pw.nchan} channels, {pw.npole} poles in [9.5, 60] Ry, {E.size} energies in "
                         f"[{E[0]:.4f}, {E[-1]:.4f}] Ry (0.4 Ry below the highest threshold), coarse step {ieq}, "
                         f"fnumin {fnumin:.3f}, FP64")

@@ -56,3 +56,14 @@ def test_tile_shape_table():
         for tile, eb in shapes:
             assert tile in (16, 32, 64) and 1 <= eb <= 8
     assert rm.tile_shapes(7) == []
+
+
+def test_mqdt_option_defaults():
+    """rm_mqdt_opts_default: every point coarse (the direct result), the unphysical S
+    interpolated, no fnumin floor, the paper's qetest of 1e-7."""
+    import ctypes
+
+    from paper_1909_07321_amd import rm
+    o = rm.MqdtOpts()
+    rm._lib.rm_mqdt_opts_default(ctypes.byref(o))
+    assert (o.ieq, o.iqdt, o.fnumin, o.qetest) == (1, 1, 0.0, 1e-7)

@@ -75,6 +75,8 @@ MUTANTS = {
                          "test_oracle_mqdt.py::test_s_form_elimination"),
     "mqdt_window": ("int st0 = k - 1;", "int st0 = k - 3;",
                     "test_oracle_mqdt.py::test_fine_point_uses_the_four_surrounding_coarse_points"),
+    "mqdt_qetest_scale": ("const double tol = qetest * pw->z * pw->z;", "const double tol = qetest;",
+                          "test_oracle_mqdt.py::test_qetest_reuses_the_interpolant_within_its_energy_step"),
     "taylor_start_binomial": ("for (int t = 1; t <= p; ++t) binom = binom * (ld)(lam + t) / (ld)t;",
                               "for (int t = 1; t <= p; ++t) binom = binom * (ld)(lam + t - 1) / (ld)t;",
                               "test_oracle_coupling.py::test_coupled_propagation_against_mpmath"),

@@ -75,7 +75,13 @@ MUTANTS = {
                          "test_oracle_mqdt.py::test_s_form_elimination"),
     "mqdt_window": ("int st0 = k - 1;", "int st0 = k - 3;",
                     "test_oracle_mqdt.py::test_fine_point_uses_the_four_surrounding_coarse_points"),
-    "mqdt_qetest_scale": ("const double tol = qetest * pw->z * pw->z;", "const double tol = qetest;",
+    "mqdt_member_floor": ("const double numin = fnumin > l + 0.1 ? fnumin : l + 0.1;",
+                          "const double numin = fnumin > l ? fnumin : l;",
+                          "test_oracle_mqdt.py::test_member_rule"),
+    "mqdt_coarse_last": ("if (((j - s0) % ieq == 0 || j == s1 - 1) && !flag[j] && !avoid[j])",
+                         "if (((j - s0) % ieq == 0) && !flag[j] && !avoid[j])",
+                         "test_oracle_mqdt.py::test_coarse_points_and_every_point_coarse"),
+    "mqdt_qetest_scale":("const double tol = qetest * pw->z * pw->z;", "const double tol = qetest;",
                           "test_oracle_mqdt.py::test_qetest_reuses_the_interpolant_within_its_energy_step"),
     "taylor_start_binomial": ("for (int t = 1; t <= p; ++t) binom = binom * (ld)(lam + t) / (ld)t;",
                               "for (int t = 1; t <= p; ++t) binom = binom * (ld)(lam + t - 1) / (ld)t;",

@@ -102,7 +102,9 @@ void rm_opts_default(rm_opts *o);
    default priority and one scheduler thread for rm_submit. */
 rm_status rm_create(int device, size_t hbm_budget_bytes, rm_ctx **out);
 rm_status rm_destroy(rm_ctx *ctx);
-/* Text of the last error on this context (never NULL; "" if none). */
+/* Text of the last error on this context (never NULL; "" if none).  ctx =
+   NULL: why the calling thread's last failed rm_create failed (the HIP call and
+   HIP's text, e.g. no device), "null context" if none has failed. */
 const char *rm_last_error(const rm_ctx *ctx);
 
 /* ----------------------------------------------------------- partial waves */

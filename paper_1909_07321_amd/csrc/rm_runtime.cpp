@@ -1224,6 +1224,23 @@ void plan_single(Plan &P, const std::vector<Seg> &segs, int e0, int m) {
   finish_plan(P, segs, m);
 }
 
+// Why the calling thread's last rm_create failed (rm_last_error(NULL)).
+thread_local std::string t_create_err;
+
+// rm_create's failure exit: records the failed call (with HIP's text, or the
+// context's own message when what is null), releases what the context holds
+// so far and frees it.
+rm_status create_failed(rm_ctx *ctx, rm_status st, const char *what, hipError_t e) {
+  t_create_err = "rm_create(device " + std::to_string(ctx->device) + "): ";
+  t_create_err += what ? std::string(what) + ": " + hipGetErrorString(e) : ctx->err;
+  free_staging(ctx->na.h);
+  for (auto &sl : ctx->slots) destroy_slot(*sl);
+  if (ctx->sync.stream) (void)hipStreamDestroy(ctx->sync.stream);
+  if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return st;
+}
+
 }  // namespace
 
 // =================================================================== C ABI
@@ -1244,39 +1261,26 @@ rm_status rm_create(int device, size_t hbm_budget_bytes, rm_ctx **out) {
   rm_ctx *ctx = new (std::nothrow) rm_ctx();
   if (!ctx) return RM_E_NOMEM;
   ctx->device = device;
-  if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess ||
-      hipStreamCreateWithFlags(&ctx->sync.stream, hipStreamNonBlocking) != hipSuccess) {
-    delete ctx;
-    return RM_E_DEVICE;
-  }
+  hipError_t he;
+  if ((he = hipSetDevice(device)) != hipSuccess) return create_failed(ctx, RM_E_DEVICE, "hipSetDevice", he);
+  if ((he = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking)) != hipSuccess ||
+      (he = hipStreamCreateWithFlags(&ctx->sync.stream, hipStreamNonBlocking)) != hipSuccess)
+    return create_failed(ctx, RM_E_DEVICE, "hipStreamCreateWithFlags", he);
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0) {
     ctx->ncu = prop.multiProcessorCount;
     ctx->arch = prop.gcnArchName;
   }
   size_t fr = 0, tot = 0;
-  if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
-    delete ctx;
-    return RM_E_DEVICE;
-  }
+  if ((he = hipMemGetInfo(&fr, &tot)) != hipSuccess) return create_failed(ctx, RM_E_DEVICE, "hipMemGetInfo", he);
   ctx->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)fr);
   const int nslots = 2;
   for (int i = 0; i < nslots; ++i) {
-    auto sl = std::make_unique<Slot>();
-    if (hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) != hipSuccess) {
-      delete ctx;
-      return RM_E_DEVICE;
-    }
-    ctx->slots.push_back(std::move(sl));
+    ctx->slots.push_back(std::make_unique<Slot>());
+    if ((he = hipStreamCreateWithFlags(&ctx->slots.back()->stream, hipStreamNonBlocking)) != hipSuccess)
+      return create_failed(ctx, RM_E_DEVICE, "hipStreamCreateWithFlags", he);
   }
-  if (rm_status st = init_noalloc(ctx)) {
-    free_staging(ctx->na.h);
-    for (auto &sl : ctx->slots) destroy_slot(*sl);
-    (void)hipStreamDestroy(ctx->stream);
-    (void)hipStreamDestroy(ctx->sync.stream);
-    delete ctx;
-    return st;
-  }
+  if (rm_status st = init_noalloc(ctx)) return create_failed(ctx, st, nullptr, hipSuccess);
   for (auto &sl : ctx->slots) ctx->workers.emplace_back(worker_main, ctx, sl.get());
   *out = ctx;
   return RM_OK;
@@ -1307,7 +1311,10 @@ rm_status rm_destroy(rm_ctx *ctx) {
   return RM_OK;
 }
 
-const char *rm_last_error(const rm_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+const char *rm_last_error(const rm_ctx *ctx) {
+  if (ctx) return ctx->err.c_str();
+  return t_create_err.empty() ? "null context" : t_create_err.c_str();
+}
 
 size_t rm_pw_footprint(int32_t nchan, int32_t npole) {
   const size_t npad = (size_t)round_up(std::max(nchan, 1), TILE);

@@ -61,9 +61,34 @@ def test_tile_shape_table():
 def test_mqdt_option_defaults():
     """rm_mqdt_opts_default: every point coarse (the direct result), the unphysical S
     interpolated, no fnumin floor, the paper's qetest of 1e-7."""
-    import ctypes
-
     from paper_1909_07321_amd import rm
     o = rm.MqdtOpts()
     rm._lib.rm_mqdt_opts_default(ctypes.byref(o))
     assert (o.ieq, o.iqdt, o.fnumin, o.qetest) == (1, 1, 0.0, 1e-7)
+
+
+def test_binding_fails_loudly_without_the_library():
+    """No fallback: importing the binding without librm.so raises."""
+    import subprocess
+    import sys
+
+    env = dict(os.environ, RM_LIB=os.path.join(ROOT, "no_such_dir", "librm.so"))
+    r = subprocess.run([sys.executable, "-c", "from paper_1909_07321_amd import rm"], cwd=ROOT, env=env,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0 and "ImportError: librm.so not built" in r.stderr
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="librm.so not built")
+def test_create_without_a_device_names_the_failed_call():
+    """rm_create on a host without a HIP device returns RM_E_DEVICE and no
+    context; rm_last_error(NULL) names the failed HIP call and HIP's text."""
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a HIP device is present")
+    from paper_1909_07321_amd import rm
+    h = ctypes.c_void_p()
+    assert rm._lib.rm_create(0, 0, ctypes.byref(h)) == rm.RM_E_DEVICE and h.value is None
+    msg = rm._lib.rm_last_error(None).decode()
+    assert msg.startswith("rm_create(device 0): hipSetDevice: ") and len(msg) > len("rm_create(device 0): hipSetDevice: ")
+    with pytest.raises(rm.RMError, match="hipSetDevice"):
+        rm.Context(0)

@@ -103,6 +103,8 @@ _lib.rm_pw_upload_coupled.argtypes = [_vp, ctypes.POINTER(PWDesc), _i32, _vp, _d
 _lib.rm_set_propagation.argtypes = [_vp, _i32, _i32]
 _lib.rm_propagate.argtypes = [_vp, _i32, _vp, _i32, ctypes.POINTER(Opts), _vp, _vp, _vp]
 _lib.rm_mqdt_unphysical_K.argtypes = [_vp, _i32, _vp, _i32, _d, ctypes.POINTER(Opts), _vp, _vp, _vp]
+
+
 class MqdtOpts(ctypes.Structure):
     _fields_ = [("ieq", _i32), ("iqdt", _i32), ("fnumin", _d), ("qetest", _d)]
 
@@ -226,6 +228,43 @@ def write_omega(path: str, nz: int, nel: int, S, L, elev, E, omega, nomwrt: int 
 
 def _is_torch(x) -> bool:
     return type(x).__module__.startswith("torch")
+
+
+def _energies(E):
+    """An energy mesh as the library reads it: (array, on_device).  A torch
+    tensor is handed over as device memory and must be a contiguous 1-D float64
+    tensor on the GPU (anything else would be misread or read past its end);
+    other input becomes a contiguous float64 host array."""
+    if _is_torch(E):
+        if not (E.is_cuda and str(E.dtype) == "torch.float64" and E.dim() == 1 and E.is_contiguous()):
+            raise RMError(f"energies on the device must be a contiguous 1-D float64 GPU tensor "
+                          f"(got {E.dtype}, shape {tuple(E.shape)}, {E.device})")
+        return E, True
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    if E.ndim != 1:
+        raise RMError(f"energies must be 1-D (got shape {E.shape})")
+    return E, False
+
+
+def _check_outputs(call, dev, outs):
+    """Caller-owned outputs: each (name, array, shape, numpy dtype) must be
+    device memory when the energies are (host memory otherwise), of that dtype,
+    contiguous and of that shape (shape None: not checked), since the library
+    writes it in full through a raw pointer.  A None array passes (the optional
+    ones are checked by the library)."""
+    for name, a, shape, dt in outs:
+        if a is None:
+            continue
+        if dev:
+            ok = (_is_torch(a) and a.is_cuda and str(a.dtype) == "torch." + {np.float64: "float64",
+                  np.int32: "int32", np.int8: "int8"}[dt] and a.is_contiguous())
+        else:
+            ok = isinstance(a, np.ndarray) and a.dtype == dt and a.flags.c_contiguous and a.flags.writeable
+        if not ok or (shape is not None and tuple(a.shape) != tuple(shape)):
+            where = "GPU tensor" if dev else "writeable host array"
+            raise RMError(f"{call}: {name} must be a contiguous {np.dtype(dt).name} {where}"
+                          + (f" of shape {tuple(shape)}" if shape is not None else "")
+                          + f" (got {type(a).__name__} {getattr(a, 'dtype', '')} {tuple(getattr(a, 'shape', ()))})")
 
 
 def _ptr(x):
@@ -358,10 +397,15 @@ class Context:
         return np.empty(shape, dtype=dtype)
 
     def _E(self, E):
-        if _is_torch(E):
-            assert E.is_cuda and E.dtype.is_floating_point and E.is_contiguous()
-            return E, True
-        return np.ascontiguousarray(E, dtype=np.float64), False
+        return _energies(E)
+
+    def _out_shapes(self, pw_id, ne):
+        """(omega, K, status) shapes of a wave's results, or Nones for an
+        unknown wave (the library reports that)."""
+        if pw_id not in self._pw:
+            return None, None, None
+        n, nt = self._pw[pw_id]
+        return (ne, nt, nt), (ne, n, n), (ne,)
 
     def form_R(self, pw_id, E, prec=FP64, split_delta=0.05, thr_guard=1e-10):
         E, dev = self._E(E)
@@ -427,6 +471,9 @@ class Context:
             st = self._alloc(E, (ne,), np.int32)
         else:
             om, K, st = out
+            so, sk, ss = self._out_shapes(pw_id, ne)
+            _check_outputs("run", dev, [("omega", om, so, np.float64), ("K", K, sk, np.float64),
+                                        ("status", st, ss, np.int32)])
         o = self._opts(prec, split_delta, thr_guard, dev, stream)
         self._check(_lib.rm_run(self.h, pw_id, _ptr(E), ne, ctypes.byref(o), _ptr(om), _ptr(K), _ptr(st)))
         return om, K, st
@@ -467,6 +514,9 @@ class Context:
         if not dev:
             raise RMError("run_noalloc takes device tensors")
         om, K, st = out
+        so, sk, ss = self._out_shapes(pw_id, E.shape[0])
+        _check_outputs("run_noalloc", True, [("omega", om, so, np.float64), ("K", K, sk, np.float64),
+                                             ("status", st, ss, np.int32)])
         o = self._opts(prec, split_delta, thr_guard, True, stream)
         self._check(_lib.rm_run_noalloc(self.h, pw_id, _ptr(E), E.shape[0], ctypes.byref(o), _ptr(om), _ptr(K),
                                         _ptr(st)))
@@ -479,7 +529,10 @@ class Context:
         arr = (BatchItem * max(1, len(items)))()
         dev = False
         for k, (pid, E) in enumerate(items):
-            E, dev = self._E(E)
+            E, d = self._E(E)
+            if k and d != dev:
+                raise RMError("run_batch: energies must be all on the device or all on the host")
+            dev = d
             n, nt = self._pw.get(pid, (1, 1))
             ne = E.shape[0]
             om = self._alloc(E, (ne, nt, nt), np.float64)

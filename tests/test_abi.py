@@ -92,3 +92,37 @@ def test_create_without_a_device_names_the_failed_call():
     assert msg.startswith("rm_create(device 0): hipSetDevice: ") and len(msg) > len("rm_create(device 0): hipSetDevice: ")
     with pytest.raises(rm.RMError, match="hipSetDevice"):
         rm.Context(0)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="librm.so not built")
+def test_binding_checks_what_it_hands_over():
+    """The binding refuses energies and caller-owned outputs that the library
+    would misread or write past (host-side checks; no device call)."""
+    import numpy as np
+    import torch
+
+    from paper_1909_07321_amd import rm
+    E, dev = rm._energies([0.1, 0.2, 0.3])
+    assert E.dtype == np.float64 and E.flags.c_contiguous and not dev
+    with pytest.raises(rm.RMError, match="1-D"):
+        rm._energies(np.zeros((2, 3)))
+    for bad in (torch.zeros(4, dtype=torch.float64), torch.zeros(4, dtype=torch.float32)):  # not GPU tensors
+        with pytest.raises(rm.RMError, match="float64 GPU tensor"):
+            rm._energies(bad)
+    ne, n, nt = 5, 4, 2
+    good = [("omega", np.empty((ne, nt, nt)), (ne, nt, nt), np.float64),
+            ("K", None, (ne, n, n), np.float64),
+            ("status", np.empty(ne, np.int32), (ne,), np.int32)]
+    rm._check_outputs("run", False, good)
+    rm._check_outputs("run", False, [(a, b, None, d) for a, b, _, d in good])  # unknown wave: shape unchecked
+    ro = np.empty(ne, np.int32)
+    ro.setflags(write=False)
+    for name, arr in [("omega", np.empty((ne, nt, nt), np.float32)),      # wrong dtype
+                      ("omega", np.empty((ne - 1, nt, nt))),               # too short
+                      ("omega", np.empty((ne, nt, 2 * nt))[:, :, ::2]),    # not contiguous
+                      ("status", ro)]:                                     # read-only
+        outs = [(a, arr if a == name else b, s, d) for a, b, s, d in good]
+        with pytest.raises(rm.RMError, match=f"run: {name} must be"):
+            rm._check_outputs("run", False, outs)
+    with pytest.raises(rm.RMError, match="omega must be a contiguous float64 GPU tensor"):
+        rm._check_outputs("run", True, good)  # host arrays beside device energies

@@ -564,7 +564,9 @@ class Context:
         """Queue a request; returns (ticket, outputs dict).  The output arrays
         belong to the request until poll() reports it done."""
         n, nt = self._pw.get(pw_id, (1, 1))
-        E = np.ascontiguousarray(E, dtype=np.float64)
+        E, dev = _energies(E)
+        if dev:
+            raise RMError("submit takes host energies (the request's results come back in host memory)")
         ne = E.shape[0]
         outs = dict(omega=np.empty((ne, nt, nt)), K=np.empty((ne, n, n)) if want_K else None,
                     status=np.zeros(ne, np.int32), E=E)

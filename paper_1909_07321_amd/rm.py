@@ -246,12 +246,13 @@ def _energies(E):
     return E, False
 
 
-def _check_outputs(call, dev, outs):
-    """Caller-owned outputs: each (name, array, shape, numpy dtype) must be
+def _check_outputs(call, dev, outs, write=True):
+    """Caller-owned buffers: each (name, array, shape, numpy dtype) must be
     device memory when the energies are (host memory otherwise), of that dtype,
-    contiguous and of that shape (shape None: not checked), since the library
-    writes it in full through a raw pointer.  A None array passes (the optional
-    ones are checked by the library)."""
+    contiguous and of that shape (shape None: not checked), and writeable when
+    the library writes it, since the library reads or writes it in full through
+    a raw pointer.  A None array passes (the optional ones are checked by the
+    library)."""
     for name, a, shape, dt in outs:
         if a is None:
             continue
@@ -259,7 +260,8 @@ def _check_outputs(call, dev, outs):
             ok = (_is_torch(a) and a.is_cuda and str(a.dtype) == "torch." + {np.float64: "float64",
                   np.int32: "int32", np.int8: "int8"}[dt] and a.is_contiguous())
         else:
-            ok = isinstance(a, np.ndarray) and a.dtype == dt and a.flags.c_contiguous and a.flags.writeable
+            ok = (isinstance(a, np.ndarray) and a.dtype == dt and a.flags.c_contiguous
+                  and (a.flags.writeable or not write))
         if not ok or (shape is not None and tuple(a.shape) != tuple(shape)):
             where = "GPU tensor" if dev else "writeable host array"
             raise RMError(f"{call}: {name} must be a contiguous {np.dtype(dt).name} {where}"
@@ -437,6 +439,9 @@ class Context:
         if not dev:
             R = np.ascontiguousarray(R, dtype=np.float64)
             fg = np.ascontiguousarray(fg, dtype=np.float64)
+        known = pw_id in self._pw
+        _check_outputs("solve_K", dev, [("R", R, (ne, n, n) if known else None, np.float64),
+                                        ("fg", fg, (ne, n, 4) if known else None, np.float64)], write=False)
         K = self._alloc(E, (ne, n, n), np.float64)
         st = self._alloc(E, (ne,), np.int32)
         o = self._opts(FP64, 0.05, thr_guard, dev)
@@ -450,6 +455,8 @@ class Context:
         ne = E.shape[0]
         if not dev:
             K = np.ascontiguousarray(K, dtype=np.float64)
+        _check_outputs("collision_strengths", dev, [("K", K, (ne, n, n) if pw_id in self._pw else None, np.float64)],
+                       write=False)
         om = self._alloc(E, (ne, nt, nt), np.float64)
         S = self._alloc(E, (ne, n, n, 2), np.float64) if want_S else None
         st = self._alloc(E, (ne,), np.int32)

@@ -126,3 +126,6 @@ def test_binding_checks_what_it_hands_over():
             rm._check_outputs("run", False, outs)
     with pytest.raises(rm.RMError, match="omega must be a contiguous float64 GPU tensor"):
         rm._check_outputs("run", True, good)  # host arrays beside device energies
+    rm._check_outputs("solve_K", False, [("R", ro, (ne,), np.int32)], write=False)  # inputs may be read-only
+    with pytest.raises(rm.RMError, match="solve_K: fg must be"):
+        rm._check_outputs("solve_K", False, [("fg", np.empty((ne, n, 2)), (ne, n, 4), np.float64)], write=False)

@@ -347,6 +347,10 @@ class Context:
         keep = [np.ascontiguousarray(pw.e_thr, dtype=np.float64), np.ascontiguousarray(pw.l, dtype=np.int32),
                 np.ascontiguousarray(pw.target, dtype=np.int32), np.ascontiguousarray(pw.Ek, dtype=np.float64),
                 np.ascontiguousarray(pw.w, dtype=np.float64)]
+        n, M = int(pw.nchan), int(pw.npole)
+        for name, arr, size in zip(("e_thr", "l", "target", "Ek", "w"), keep, (n, n, n, M, M * n)):
+            if arr.size < size:  # the library reads size entries; spare ones are harmless
+                raise RMError(f"pw_upload: {name} has {arr.size} entries, nchan = {n} and npole = {M} need {size}")
         d = PWDesc(pw.nchan, pw.npole, pw.ntarget, pw.a, pw.b, pw.z, pw.g, *[k.ctypes.data for k in keep])
         pid = _i32()
         if coupling is None:

@@ -129,3 +129,21 @@ def test_binding_checks_what_it_hands_over():
     rm._check_outputs("solve_K", False, [("R", ro, (ne,), np.int32)], write=False)  # inputs may be read-only
     with pytest.raises(rm.RMError, match="solve_K: fg must be"):
         rm._check_outputs("solve_K", False, [("fg", np.empty((ne, n, 2)), (ne, n, 4), np.float64)], write=False)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="librm.so not built")
+def test_upload_checks_field_sizes_before_any_device_call():
+    """A wave whose arrays disagree with nchan / npole is refused by the binding
+    (the library would read past them); the check needs no device."""
+    import dataclasses
+
+    import numpy as np
+
+    from paper_1909_07321_amd import rm, synth
+    pw, _ = synth.config1()
+    ctx = rm.Context.__new__(rm.Context)  # no rm_create: the refusal comes first
+    ctx.h, ctx._pw = None, {}
+    for field, bad in [("l", pw.l[:-1]), ("Ek", pw.Ek[:-1]), ("w", pw.w[:, :-1])]:
+        with pytest.raises(rm.RMError, match=f"pw_upload: {field} has"):
+            ctx.pw_upload(dataclasses.replace(pw, **{field: bad}))
+    assert np.asarray(pw.w).shape == (pw.npole, pw.nchan)

@@ -513,7 +513,8 @@ rm_status rm_hdat_pw_desc(const rm_hdat *h, rm_pw_desc *desc);
 /* sizeH.dat (kind 0: NCHAN, NCON, MNP2, 2S+1, L, parity) or sizeBP.dat (kind 1:
    NCHAN, NCON, MNP2, 2J, parity; s = 0), one row per partial wave, read with
    the fixed columns of their Fortran formats.  Up to cap rows are stored;
-   *count is the number of rows in the file. */
+   *count is the number of rows in the file.  A field that is not an integer,
+   or a line longer than 1023 characters: RM_E_IO, *count the rows before it. */
 typedef struct {
   int32_t nchan, ncon, mnp2, s, l, ipi;
 } rm_sizeh_row;

@@ -22,6 +22,7 @@ namespace {
 struct FortranFile {
   FILE *f = nullptr;
   bool swap = false;
+  int64_t size = 0;  // file length: no record may claim more than what is left
   std::string err;
 
   ~FortranFile() { close(); }
@@ -37,8 +38,17 @@ struct FortranFile {
   bool open(const char *path) {
     close();
     f = fopen(path, "rb");
-    if (!f) err = std::string("cannot open ") + path;
-    return f != nullptr;
+    if (!f) {
+      err = std::string("cannot open ") + path;
+      return false;
+    }
+    size = (fseek(f, 0, SEEK_END) == 0) ? (int64_t)ftell(f) : -1;
+    if (size < 0 || fseek(f, 0, SEEK_SET) != 0) {
+      err = std::string("cannot seek in ") + path;
+      close();
+      return false;
+    }
+    return true;
   }
   // Sets the byte order from the first record's head marker, which must read
   // as `expect` bytes in one of the two orders.
@@ -64,16 +74,20 @@ struct FortranFile {
     eof = false;
     for (int part = 0;; ++part) {
       int32_t head = 0, tail = 0;
-      if (fread(&head, 4, 1, f) != 1) {
-        if (part == 0) {
-          eof = true;
-          return false;
-        }
+      if (part == 0 && (int64_t)ftell(f) == size) {  // the end of the file, between records
+        eof = true;
+        return false;
+      }
+      if (fread(&head, 4, 1, f) != 1) {  // a partial marker
         err = "truncated record";
         return false;
       }
       if (swap) head = bswap(head);
       const int64_t len = head < 0 ? -(int64_t)head : head;
+      if (len + 4 > size - (int64_t)ftell(f)) {  // the payload and its tail marker must fit in the file
+        err = "truncated record";
+        return false;
+      }
       const size_t at = out.size();
       out.resize(at + (size_t)len);
       if (len && fread(out.data() + at, 1, (size_t)len, f) != (size_t)len) {
@@ -150,7 +164,7 @@ rm_status fail(rm_hdat *h, const std::string &m) {
 
 extern "C" {
 
-rm_status rm_hdat_open(const char *path, rm_hdat **out) {
+static rm_status hdat_open_impl(const char *path, rm_hdat **out) {
   if (!path || !out) return RM_E_ARG;
   *out = nullptr;
   rm_hdat *h = new (std::nothrow) rm_hdat();
@@ -175,32 +189,35 @@ rm_status rm_hdat_open(const char *path, rm_hdat **out) {
       return fail(h, "invalid target record 1");
   }
   const int nast = h->tgt.nast, lr = h->tgt.lrang2;
-  h->enat.resize(nast);
-  h->lat.resize(nast);
-  h->isat.resize(nast);
-  h->coeff.resize(3 * (size_t)lr);
-  auto rd = [&](const char *what, auto &&fn) -> rm_status {
+  // each record is read and its length checked against the count the header
+  // gives before that many values are allocated, so a damaged count cannot
+  // ask for more memory than the file holds
+  auto rd = [&](const char *what, int64_t bytes, auto &&fn) -> rm_status {
     if (!h->ff.record(rec, eof)) return fail(h, eof ? std::string("missing target record: ") + what : "");
+    if ((int64_t)rec.size() != bytes) return fail(h, std::string("target record of wrong length: ") + what);
     Fields f(rec, h->ff.swap);
     fn(f);
     if (!f.ok || f.pos != rec.size()) return fail(h, std::string("target record of wrong length: ") + what);
     return RM_OK;
   };
-  if (rm_status st = rd("ENAT", [&](Fields &f) { f.get(h->enat.data(), nast); })) return st;
-  if (rm_status st = rd("LAT", [&](Fields &f) { f.get(h->lat.data(), nast); })) return st;
-  if (rm_status st = rd("ISAT", [&](Fields &f) { f.get(h->isat.data(), nast); })) return st;
-  if (rm_status st = rd("COEFF", [&](Fields &f) { f.get(h->coeff.data(), 3 * (size_t)lr); })) return st;
-  // Buttle correction, three records per L
+  auto fill = [](auto &v, size_t n, Fields &f) {
+    v.resize(n);
+    f.get(v.data(), n);
+  };
+  if (rm_status st = rd("ENAT", 8LL * nast, [&](Fields &f) { fill(h->enat, nast, f); })) return st;
+  if (rm_status st = rd("LAT", 4LL * nast, [&](Fields &f) { fill(h->lat, nast, f); })) return st;
+  if (rm_status st = rd("ISAT", 4LL * nast, [&](Fields &f) { fill(h->isat, nast, f); })) return st;
+  if (rm_status st = rd("COEFF", 24LL * lr, [&](Fields &f) { fill(h->coeff, 3 * (size_t)lr, f); })) return st;
+  // Buttle correction, three records per L (LRANG2 is bounded by the COEFF record's length)
   h->nbutd.resize(lr);
   h->ebutd.resize(lr);
   h->cbutd.resize(lr);
   for (int l = 0; l < lr; ++l) {
-    if (rm_status st = rd("NBUTD", [&](Fields &f) { h->nbutd[l] = f.get<int32_t>(); })) return st;
+    if (rm_status st = rd("NBUTD", 4, [&](Fields &f) { h->nbutd[l] = f.get<int32_t>(); })) return st;
     if (h->nbutd[l] < 0) return fail(h, "negative NBUTD");
-    h->ebutd[l].resize(h->nbutd[l]);
-    h->cbutd[l].resize(h->nbutd[l]);
-    if (rm_status st = rd("EBUTD", [&](Fields &f) { f.get(h->ebutd[l].data(), h->nbutd[l]); })) return st;
-    if (rm_status st = rd("CBUTD", [&](Fields &f) { f.get(h->cbutd[l].data(), h->nbutd[l]); })) return st;
+    const int nb = h->nbutd[l];
+    if (rm_status st = rd("EBUTD", 8LL * nb, [&](Fields &f) { fill(h->ebutd[l], nb, f); })) return st;
+    if (rm_status st = rd("CBUTD", 8LL * nb, [&](Fields &f) { fill(h->cbutd[l], nb, f); })) return st;
   }
   return RM_OK;
 }
@@ -230,7 +247,7 @@ rm_status rm_hdat_attach(rm_hdat *h, const char *path) {
   return RM_OK;
 }
 
-rm_status rm_hdat_next(rm_hdat *h, rm_hdat_sym *sym) {
+static rm_status hdat_next_impl(rm_hdat *h, rm_hdat_sym *sym) {
   if (!h || !sym) return RM_E_ARG;
   h->have = false;
   std::vector<char> rec;
@@ -255,23 +272,26 @@ rm_status rm_hdat_next(rm_hdat *h, rm_hdat_sym *sym) {
       return fail(h, "invalid symmetry record 1");
   }
   const int nast = h->tgt.nast, n = s.nchan, M = s.mnp2, lam = h->tgt.lamax;
-  h->nconat.assign(nast, 0);
-  h->l2p.assign(n, 0);
-  h->cf.assign((size_t)lam * n * n, 0.0);
-  h->value.assign(M, 0.0);
-  h->wmat.assign((size_t)M * n, 0.0);
-  auto rd = [&](const char *what, auto &&fn) -> rm_status {
+  // as for the target records: a record's length is checked against the
+  // header's counts before that many values are allocated
+  auto rd = [&](const char *what, int64_t bytes, auto &&fn) -> rm_status {
     if (!h->ff.record(rec, eof)) return fail(h, eof ? std::string("missing symmetry record: ") + what : "");
+    if ((int64_t)rec.size() != bytes) return fail(h, std::string("symmetry record of wrong length: ") + what);
     Fields f(rec, h->ff.swap);
     fn(f);
     if (!f.ok || f.pos != rec.size()) return fail(h, std::string("symmetry record of wrong length: ") + what);
     return RM_OK;
   };
-  if (rm_status st = rd("NCONAT", [&](Fields &f) { f.get(h->nconat.data(), nast); })) return st;
-  if (rm_status st = rd("L2P", [&](Fields &f) { f.get(h->l2p.data(), n); })) return st;
-  if (rm_status st = rd("CF", [&](Fields &f) { f.get(h->cf.data(), h->cf.size()); })) return st;
-  if (rm_status st = rd("VALUE", [&](Fields &f) { f.get(h->value.data(), M); })) return st;
-  if (rm_status st = rd("WMAT", [&](Fields &f) { f.get(h->wmat.data(), h->wmat.size()); })) return st;
+  auto fill = [](auto &v, size_t cnt, Fields &f) {
+    v.resize(cnt);
+    f.get(v.data(), cnt);
+  };
+  const int64_t ncf = (int64_t)lam * n * n, nw = (int64_t)M * n;  // lam < 2^31, n <= RM_MAX_CHANNELS: no overflow
+  if (rm_status st = rd("NCONAT", 4LL * nast, [&](Fields &f) { fill(h->nconat, nast, f); })) return st;
+  if (rm_status st = rd("L2P", 4LL * n, [&](Fields &f) { fill(h->l2p, n, f); })) return st;
+  if (rm_status st = rd("CF", 8 * ncf, [&](Fields &f) { fill(h->cf, (size_t)ncf, f); })) return st;
+  if (rm_status st = rd("VALUE", 8LL * M, [&](Fields &f) { fill(h->value, M, f); })) return st;
+  if (rm_status st = rd("WMAT", 8 * nw, [&](Fields &f) { fill(h->wmat, (size_t)nw, f); })) return st;
   // channels are ordered by target: the first NCONAT(1) belong to target 1, ...
   long tot = 0;
   for (int t = 0; t < nast; ++t) {
@@ -312,7 +332,7 @@ rm_status rm_hdat_pw_desc(const rm_hdat *h, rm_pw_desc *d) {
   d->ntarget = h->tgt.nast;
   d->a = h->tgt.ra;
   d->b = h->tgt.bsto;
-  d->z = (double)(h->tgt.nz - h->tgt.nelc);
+  d->z = (double)h->tgt.nz - (double)h->tgt.nelc;  // in double: both come from the file
   // statistical weight: (2S+1)(2L+1) in LS coupling, 2J+1 (LRGL2 = 2J) in J coupling
   d->g = s.nspn2 > 0 ? (double)s.nspn2 * (2.0 * s.lrgl2 + 1.0) : (double)s.lrgl2 + 1.0;
   d->e_thr = h->ethr.data();
@@ -323,7 +343,7 @@ rm_status rm_hdat_pw_desc(const rm_hdat *h, rm_pw_desc *d) {
   return RM_OK;
 }
 
-rm_status rm_sizeh_read(const char *path, int32_t kind, int32_t cap, rm_sizeh_row *rows, int32_t *count) {
+static rm_status sizeh_read_impl(const char *path, int32_t kind, int32_t cap, rm_sizeh_row *rows, int32_t *count) {
   if (!path || !count || cap < 0 || (cap > 0 && !rows) || (kind != 0 && kind != 1)) return RM_E_ARG;
   FILE *f = fopen(path, "r");
   if (!f) return RM_E_IO;
@@ -337,6 +357,10 @@ rm_status rm_sizeh_read(const char *path, int32_t kind, int32_t cap, rm_sizeh_ro
   rm_status st = RM_OK;
   while (fgets(line, sizeof line, f)) {
     const size_t len = strcspn(line, "\r\n");
+    if (!line[len] && len == sizeof line - 1) {  // longer than any line of these formats
+      st = RM_E_IO;
+      break;
+    }
     line[len] = 0;
     bool blank = true;
     for (size_t i = 0; i < len; ++i) blank &= line[i] == ' ' || line[i] == '\t';
@@ -369,8 +393,8 @@ rm_status rm_sizeh_read(const char *path, int32_t kind, int32_t cap, rm_sizeh_ro
             field(colB[2][0], colB[2][1], r.mnp2) && field(colB[3][0], colB[3][1], r.l) &&
             field(colB[4][0], colB[4][1], r.ipi);
     }
-    if (!ok) {
-      st = RM_E_ARG;
+    if (!ok) {  // a field that is not an integer
+      st = RM_E_IO;
       break;
     }
     if (n < cap) rows[n] = r;
@@ -381,9 +405,9 @@ rm_status rm_sizeh_read(const char *path, int32_t kind, int32_t cap, rm_sizeh_ro
   return st;
 }
 
-rm_status rm_omega_write(const char *path, int32_t formatted, int32_t nz, int32_t nel, int32_t nlev,
-                         const int32_t *S, const int32_t *L, const double *elev, int32_t ne, const double *E,
-                         const double *omega, int32_t nomwrt, int32_t elastic) {
+static rm_status omega_write_impl(const char *path, int32_t formatted, int32_t nz, int32_t nel, int32_t nlev,
+                                  const int32_t *S, const int32_t *L, const double *elev, int32_t ne, const double *E,
+                                  const double *omega, int32_t nomwrt, int32_t elastic) {
   if (!path || nlev < 1 || ne < 0 || !S || !L || !elev || (ne > 0 && (!E || !omega))) return RM_E_ARG;
   // transitions of the upper triangle (i < j, or i <= j with elastic ones),
   // row-wise for nomwrt > 0, column-wise for nomwrt < 0; the first |nomwrt|
@@ -399,8 +423,17 @@ rm_status rm_omega_write(const char *path, int32_t formatted, int32_t nz, int32_
   if ((long)tr.size() > want) tr.resize((size_t)want);
   const int32_t nw = nomwrt >= 0 ? (int32_t)tr.size() : -(int32_t)tr.size();
   // energies in z-scaled Rydberg units, E / z^2 (z = NZ - NEL; unscaled for a neutral target)
-  const int zz = nz - nel;
-  const double z2 = zz > 0 ? (double)zz * zz : 1.0;
+  const double zz = (double)nz - (double)nel;
+  const double z2 = zz > 0 ? zz * zz : 1.0;
+  // every buffer is allocated before the file is opened, so nothing between
+  // fopen and fclose can throw
+  std::vector<int32_t> sl(2 * (size_t)nlev);
+  for (int i = 0; i < nlev; ++i) {
+    sl[2 * i] = S[i];
+    sl[2 * i + 1] = L[i];
+  }
+  std::vector<double> el(nlev), row(tr.size() + 1);
+  for (int i = 0; i < nlev; ++i) el[i] = elev[i] / z2;
   FILE *f = fopen(path, formatted ? "w" : "wb");
   if (!f) return RM_E_IO;
   bool ok = true;
@@ -410,13 +443,6 @@ rm_status rm_omega_write(const char *path, int32_t formatted, int32_t nz, int32_
     ok &= bytes == 0 || fwrite(p, 1, bytes, f) == bytes;
     ok &= fwrite(&m, 4, 1, f) == 1;
   };
-  std::vector<int32_t> sl(2 * (size_t)nlev);
-  for (int i = 0; i < nlev; ++i) {
-    sl[2 * i] = S[i];
-    sl[2 * i + 1] = L[i];
-  }
-  std::vector<double> el(nlev), row(tr.size() + 1);
-  for (int i = 0; i < nlev; ++i) el[i] = elev[i] / z2;
   if (formatted) {
     ok &= fprintf(f, "%d %d\n%d %d %d\n", nz, nel, nlev, ne, nw) > 0;
     for (int i = 0; i < nlev; ++i) ok &= fprintf(f, "%d %d%c", S[i], L[i], i + 1 < nlev ? ' ' : '\n') > 0;
@@ -440,6 +466,46 @@ rm_status rm_omega_write(const char *path, int32_t formatted, int32_t nz, int32_
   }
   ok &= fclose(f) == 0;
   return ok ? RM_OK : RM_E_IO;
+}
+
+// The entry points: a host allocation that fails (a very large but
+// consistent file, or a caller's nlev) is reported, never thrown across the
+// C ABI.
+rm_status rm_hdat_open(const char *path, rm_hdat **out) {
+  try {
+    return hdat_open_impl(path, out);
+  } catch (const std::bad_alloc &) {
+    if (out && *out) (*out)->err = "out of host memory";
+    return RM_E_NOMEM;
+  }
+}
+
+rm_status rm_hdat_next(rm_hdat *h, rm_hdat_sym *sym) {
+  try {
+    return hdat_next_impl(h, sym);
+  } catch (const std::bad_alloc &) {
+    h->have = false;
+    h->err = "out of host memory";
+    return RM_E_NOMEM;
+  }
+}
+
+rm_status rm_sizeh_read(const char *path, int32_t kind, int32_t cap, rm_sizeh_row *rows, int32_t *count) {
+  try {
+    return sizeh_read_impl(path, kind, cap, rows, count);
+  } catch (const std::bad_alloc &) {
+    return RM_E_NOMEM;
+  }
+}
+
+rm_status rm_omega_write(const char *path, int32_t formatted, int32_t nz, int32_t nel, int32_t nlev,
+                         const int32_t *S, const int32_t *L, const double *elev, int32_t ne, const double *E,
+                         const double *omega, int32_t nomwrt, int32_t elastic) {
+  try {
+    return omega_write_impl(path, formatted, nz, nel, nlev, S, L, elev, ne, E, omega, nomwrt, elastic);
+  } catch (const std::bad_alloc &) {
+    return RM_E_NOMEM;
+  }
 }
 
 }  // extern "C"

@@ -3,8 +3,9 @@
 // sanitizers: every H.DAT file is opened, its target records read, each
 // symmetry read and copied out through buffers sized from what the reader
 // reports, and its descriptor formed; every sizeH.dat / sizeBP.dat file is read
-// with both kinds.  A damaged file must end in an error status, never in a
-// read or write outside a buffer (the sanitizers abort the run on one).
+// with both kinds; the OMEGA writer is run over its edge arguments.  A damaged
+// file must end in an error status, never in a read or write outside a buffer
+// (the sanitizers abort the run on one).
 // Prints one line per file: its name and the statuses seen.
 #include <cstdint>
 #include <cstdio>
@@ -61,12 +62,36 @@ static void read_sizeh(const char *path) {
   }
 }
 
+// The OMEGA writer over its edge arguments (one level, no energies, nomwrt at
+// both ends of its range and zero, elastic or not, both formats), each file
+// written into dir.
+static void write_omegas(const char *dir) {
+  const int32_t nomwrts[] = {INT32_MIN, -3, 0, 2, INT32_MAX};
+  int k = 0;
+  for (int32_t nlev : {1, 2, 5})
+    for (int32_t ne : {0, 3})
+      for (int32_t nomwrt : nomwrts)
+        for (int32_t elastic = 0; elastic < 2; ++elastic)
+          for (int32_t formatted = 0; formatted < 2; ++formatted) {
+            std::vector<int32_t> S(nlev, 2), L(nlev, 1);
+            std::vector<double> elev(nlev, 0.5), E(ne, 1.5), om((size_t)ne * nlev * nlev, 0.25);
+            char path[4096];
+            std::snprintf(path, sizeof path, "%s/omega_%d", dir, k++);
+            const rm_status s = rm_omega_write(path, formatted, 26, 23, nlev, S.data(), L.data(), elev.data(), ne,
+                                               ne ? E.data() : nullptr, ne ? om.data() : nullptr, nomwrt, elastic);
+            std::printf("%s omega nlev %d ne %d nomwrt %d elastic %d formatted %d status %d\n", path, nlev, ne,
+                        nomwrt, elastic, formatted, (int)s);
+          }
+}
+
 int main(int argc, char **argv) {
-  // arguments: "hdat" or "sizeh", then the files of that kind, repeated
+  // arguments: "hdat" or "sizeh", then the files of that kind, repeated; or
+  // "omega" and a directory to write into
   bool hdat = true;
   for (int i = 1; i < argc; ++i) {
     if (!std::strcmp(argv[i], "hdat")) hdat = true;
     else if (!std::strcmp(argv[i], "sizeh")) hdat = false;
+    else if (!std::strcmp(argv[i], "omega") && i + 1 < argc) write_omegas(argv[++i]);
     else if (hdat) read_hdat(argv[i]);
     else read_sizeh(argv[i]);
   }

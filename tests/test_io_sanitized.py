@@ -2,8 +2,9 @@
 undefined-behaviour sanitizers: rm_io.cpp is host code, built here with g++
 beside a small driver (io_reader_harness.cpp) and run over valid files and over
 damaged ones (every truncation, seeded byte flips, extreme counts, broken
-record markers, damaged text).  A damaged file must end in an error status;
-any read or write outside a buffer aborts the sanitized run."""
+record markers, damaged text), and the OMEGA writer over its edge arguments.
+A damaged file must end in an error status; any read or write outside a buffer
+aborts the sanitized run."""
 import os
 import shutil
 import struct
@@ -121,3 +122,9 @@ def test_sizeh_reader_under_sanitizers(harness, tmp_path):
     assert got[("sizeh_letters", 0)] == (-6, 0) and got[("sizeh_long", 0)] == (-6, 0)
     assert got[("sizeh_good", 1)][0] == -6  # sizeH columns read as sizeBP: not integers
     assert got[("missing", 0)][0] == -6
+
+
+def test_omega_writer_under_sanitizers(harness, tmp_path):
+    lines = _run(harness, "omega", [tmp_path])
+    assert len(lines) == 3 * 2 * 5 * 2 * 2
+    assert all(ln.endswith("status 0") for ln in lines), [ln for ln in lines if not ln.endswith("status 0")]

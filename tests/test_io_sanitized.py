@@ -25,16 +25,18 @@ def harness(tmp_path_factory):
     if not shutil.which("g++"):
         pytest.skip("g++ not available")
     exe = tmp_path_factory.mktemp("asan") / "io_reader_harness"
+    # the sanitizer runtimes are linked in, so the driver runs under any environment as it is
     subprocess.check_call(["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined",
-                           "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-I", os.path.join(ROOT, "include"),
-                           SRC, HARNESS, "-o", str(exe)], timeout=300)
+                           "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-static-libasan",
+                           "-static-libubsan", "-I", os.path.join(ROOT, "include"), SRC, HARNESS, "-o", str(exe)],
+                          timeout=300)
     return exe
 
 
 def _run(exe, kind, paths):
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:allocator_may_return_null=1",
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:allocator_may_return_null=1:"
+                                        "verify_asan_link_order=0",
                UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
-    env.pop("LD_PRELOAD", None)  # the sanitizer runtime must come first
     r = subprocess.run([str(exe), kind] + [str(p) for p in paths], capture_output=True, text=True, env=env,
                        timeout=600)
     assert r.returncode == 0, f"sanitizer report:\n{r.stderr[-4000:]}"

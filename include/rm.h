@@ -60,7 +60,7 @@ typedef int32_t rm_status;
 #define RM_OK 0
 #define RM_PENDING 1
 #define RM_E_ARG (-1)      /* bad argument (null pointer, size, layout) */
-#define RM_E_NOMEM (-2)    /* host allocation failed or the HBM budget is exceeded */
+#define RM_E_NOMEM (-2)    /* host allocation (or thread start) failed or the HBM budget is exceeded */
 #define RM_E_DEVICE (-3)   /* a HIP call failed; rm_last_error() has the text */
 #define RM_E_NOTFOUND (-4) /* unknown partial-wave id or ticket */
 #define RM_E_BUSY (-5)     /* serving admission queue full */

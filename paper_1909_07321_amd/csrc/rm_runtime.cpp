@@ -1241,6 +1241,24 @@ rm_status create_failed(rm_ctx *ctx, rm_status st, const char *what, hipError_t 
   return st;
 }
 
+// An exception thrown inside an entry point (a host allocation or a thread
+// start that fails) ends as RM_E_NOMEM: none may reach a C caller.
+rm_status abi_failed(rm_ctx *ctx) noexcept {
+  try {
+    if (ctx) ctx->err = "out of host memory (an allocation or a thread start failed)";
+  } catch (...) {
+  }
+  return RM_E_NOMEM;
+}
+
+rm_status abi_failed_create(int device) noexcept {
+  try {
+    t_create_err = "rm_create(device " + std::to_string(device) + "): out of host memory";
+  } catch (...) {
+  }
+  return RM_E_NOMEM;
+}
+
 }  // namespace
 
 // =================================================================== C ABI
@@ -1255,7 +1273,7 @@ void rm_opts_default(rm_opts *o) {
   o->device_ptrs = 0;
 }
 
-rm_status rm_create(int device, size_t hbm_budget_bytes, rm_ctx **out) {
+static rm_status rm_create_body(int device, size_t hbm_budget_bytes, rm_ctx **out) {
   if (!out) return RM_E_ARG;
   *out = nullptr;
   rm_ctx *ctx = new (std::nothrow) rm_ctx();
@@ -1286,7 +1304,7 @@ rm_status rm_create(int device, size_t hbm_budget_bytes, rm_ctx **out) {
   return RM_OK;
 }
 
-rm_status rm_destroy(rm_ctx *ctx) {
+static rm_status rm_destroy_body(rm_ctx *ctx) {
   if (!ctx) return RM_E_ARG;
   {
     std::lock_guard<std::mutex> g(ctx->mu);
@@ -1328,12 +1346,12 @@ size_t rm_work_footprint(int32_t nchan, int32_t npole, int32_t ntarget, int32_t 
          kChunkFixedBytes;
 }
 
-rm_status rm_pw_upload(rm_ctx *ctx, const rm_pw_desc *d, int32_t *pw_id) {
+static rm_status rm_pw_upload_body(rm_ctx *ctx, const rm_pw_desc *d, int32_t *pw_id) {
   return rm_pw_upload_coupled_impl(ctx, d, 0, nullptr, 0.0, pw_id);
 }
 
-rm_status rm_pw_upload_coupled(rm_ctx *ctx, const rm_pw_desc *d, int32_t lamax, const double *cf, double r1,
-                               int32_t *pw_id) {
+static rm_status rm_pw_upload_coupled_body(rm_ctx *ctx, const rm_pw_desc *d, int32_t lamax, const double *cf, double r1,
+                                           int32_t *pw_id) {
   if (!ctx || !d || !pw_id) return RM_E_ARG;
   if (lamax < 1 || lamax > RM_PROP_MAX_LAMAX || !cf || d->nchan < 1 || d->nchan > RM_PROP_MAX_CHANNELS ||
       !(r1 > d->a) || !std::isfinite(r1)) {
@@ -1348,7 +1366,7 @@ rm_status rm_pw_upload_coupled(rm_ctx *ctx, const rm_pw_desc *d, int32_t lamax, 
   return rm_pw_upload_coupled_impl(ctx, d, lamax, cf, r1, pw_id);
 }
 
-rm_status rm_set_propagation(rm_ctx *ctx, int32_t npts, int32_t stab) {
+static rm_status rm_set_propagation_body(rm_ctx *ctx, int32_t npts, int32_t stab) {
   if (!ctx) return RM_E_ARG;
   if (npts < 4 || stab < 1) {
     ctx->err = "propagation grid: npts >= 4 and stab >= 1 needed";
@@ -1467,7 +1485,7 @@ rm_status rm_pw_upload_coupled_impl(rm_ctx *ctx, const rm_pw_desc *d, int32_t la
 
 extern "C" {
 
-rm_status rm_pw_release(rm_ctx *ctx, int32_t pw_id) {
+static rm_status rm_pw_release_body(rm_ctx *ctx, int32_t pw_id) {
   if (!ctx) return RM_E_ARG;
   std::unique_lock<std::mutex> lk(ctx->mu);
   auto it = ctx->pws.find(pw_id);
@@ -1485,8 +1503,8 @@ rm_status rm_pw_release(rm_ctx *ctx, int32_t pw_id) {
   return RM_OK;
 }
 
-rm_status rm_form_R(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, const rm_opts *opts, double *R,
-                    int32_t *status) {
+static rm_status rm_form_R_body(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, const rm_opts *opts, double *R,
+                                int32_t *status) {
   if (!ctx || (ne > 0 && (!E || !R || !status)) || ne < 0) return RM_E_ARG;
   if (ne == 0) return RM_OK;
   const DevPW *pw;
@@ -1514,8 +1532,8 @@ rm_status rm_form_R(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, cons
   return staged_leave(ctx, o, ev);
 }
 
-rm_status rm_asymptotic(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, const rm_opts *opts, double *fg,
-                        int8_t *open, int32_t *nopen, int32_t *status) {
+static rm_status rm_asymptotic_body(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, const rm_opts *opts,
+                                    double *fg, int8_t *open, int32_t *nopen, int32_t *status) {
   if (!ctx || ne < 0 || (ne > 0 && (!E || !fg || !open || !nopen || !status))) return RM_E_ARG;
   if (ne == 0) return RM_OK;
   const DevPW *pw;
@@ -1544,8 +1562,8 @@ rm_status rm_asymptotic(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, 
   return staged_leave(ctx, o, ev);
 }
 
-rm_status rm_propagate(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, const rm_opts *opts, double *phi,
-                       double *dphi, int32_t *status) {
+static rm_status rm_propagate_body(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, const rm_opts *opts,
+                                   double *phi, double *dphi, int32_t *status) {
   if (!ctx || ne < 0 || (ne > 0 && (!E || !phi || !dphi || !status))) return RM_E_ARG;
   if (ne == 0) return RM_OK;
   const DevPW *pw;
@@ -1587,8 +1605,8 @@ rm_status rm_propagate(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, c
   return staged_leave(ctx, o, ev);
 }
 
-rm_status rm_solve_K(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, const double *R, const double *fg,
-                     const rm_opts *opts, double *K, int32_t *status) {
+static rm_status rm_solve_K_body(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, const double *R,
+                                 const double *fg, const rm_opts *opts, double *K, int32_t *status) {
   if (!ctx || ne < 0 || (ne > 0 && (!E || !R || !fg || !K || !status))) return RM_E_ARG;
   if (ne == 0) return RM_OK;
   const DevPW *pw;
@@ -1628,8 +1646,8 @@ rm_status rm_solve_K(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, con
   return staged_leave(ctx, o, ev);
 }
 
-rm_status rm_collision_strengths(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, const double *K,
-                                 const rm_opts *opts, double *omega, double *S, int32_t *status) {
+static rm_status rm_collision_strengths_body(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, const double *K,
+                                             const rm_opts *opts, double *omega, double *S, int32_t *status) {
   if (!ctx || ne < 0 || (ne > 0 && (!E || !K || !omega || !status))) return RM_E_ARG;
   if (ne == 0) return RM_OK;
   const DevPW *pw;
@@ -1663,8 +1681,8 @@ rm_status rm_collision_strengths(rm_ctx *ctx, int32_t pwid, const double *E, int
   return staged_leave(ctx, o, ev);
 }
 
-rm_status rm_run(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, const rm_opts *opts, double *omega,
-                 double *K, int32_t *status) {
+static rm_status rm_run_body(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, const rm_opts *opts, double *omega,
+                             double *K, int32_t *status) {
   if (!ctx || ne < 0 || (ne > 0 && (!E || !omega || !status))) return RM_E_ARG;
   if (ne == 0) return RM_OK;
   const DevPW *pw;
@@ -1675,8 +1693,8 @@ rm_status rm_run(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, const r
   return run_segments(ctx, segs, o, false);
 }
 
-rm_status rm_run_noalloc(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, const rm_opts *opts, double *omega,
-                         double *K, int32_t *status) {
+static rm_status rm_run_noalloc_body(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, const rm_opts *opts,
+                                     double *omega, double *K, int32_t *status) {
   if (!ctx || !opts || ne < 0 || (ne > 0 && (!E || !omega || !status))) return RM_E_ARG;
   if (!opts->device_ptrs) {
     ctx->err = "rm_run_noalloc takes device pointers (opts->device_ptrs = 1)";
@@ -1729,7 +1747,7 @@ rm_status rm_run_noalloc(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne,
   return RM_OK;
 }
 
-rm_status rm_run_batch(rm_ctx *ctx, const rm_batch_item *items, int32_t nitems, const rm_opts *opts) {
+static rm_status rm_run_batch_body(rm_ctx *ctx, const rm_batch_item *items, int32_t nitems, const rm_opts *opts) {
   if (!ctx || nitems < 0 || (nitems > 0 && !items)) return RM_E_ARG;
   (void)hipSetDevice(ctx->device);
   const rm_opts o = fixed_opts(opts);
@@ -1745,8 +1763,8 @@ rm_status rm_run_batch(rm_ctx *ctx, const rm_batch_item *items, int32_t nitems, 
   return run_segments(ctx, segs, o, true);
 }
 
-rm_status rm_run_sum(rm_ctx *ctx, const int32_t *pw_ids, int32_t npw, const double *E, int32_t ne, int32_t order,
-                     const rm_opts *opts, double *omega, int32_t *status) {
+static rm_status rm_run_sum_body(rm_ctx *ctx, const int32_t *pw_ids, int32_t npw, const double *E, int32_t ne,
+                                 int32_t order, const rm_opts *opts, double *omega, int32_t *status) {
   if (!ctx || npw < 1 || !pw_ids || ne < 0 || (ne > 0 && (!E || !omega || !status)) ||
       (order != RM_ORDER_WAVE && order != RM_ORDER_PERMUTED))
     return RM_E_ARG;
@@ -1810,13 +1828,13 @@ rm_status rm_run_sum(rm_ctx *ctx, const int32_t *pw_ids, int32_t npw, const doub
   return RM_OK;
 }
 
-rm_status rm_set_graph(rm_ctx *ctx, int32_t on) {
+static rm_status rm_set_graph_body(rm_ctx *ctx, int32_t on) {
   if (!ctx) return RM_E_ARG;
   ctx->graphs.store(on ? 1 : 0);
   return RM_OK;
 }
 
-rm_status rm_graph_stats(rm_ctx *ctx, int64_t *captures, int64_t *replays) {
+static rm_status rm_graph_stats_body(rm_ctx *ctx, int64_t *captures, int64_t *replays) {
   if (!ctx || !captures || !replays) return RM_E_ARG;
   int64_t c = ctx->sync.g.captures + ctx->pipe[0].g.captures + ctx->pipe[1].g.captures;
   int64_t r = ctx->sync.g.replays + ctx->pipe[0].g.replays + ctx->pipe[1].g.replays;
@@ -1837,7 +1855,7 @@ int32_t rm_tile_count(int32_t prec) {
   return nrtile(prec == RM_FP32_SPLIT);
 }
 
-rm_status rm_tile_shape(int32_t prec, int32_t shape, int32_t *tile, int32_t *energies) {
+static rm_status rm_tile_shape_body(int32_t prec, int32_t shape, int32_t *tile, int32_t *energies) {
   if (shape < 0 || shape >= rm_tile_count(prec) || !tile || !energies) return RM_E_ARG;
   const RTile t = rtile(prec == RM_FP32_SPLIT, shape);
   *tile = 16 * t.tm;
@@ -1845,22 +1863,22 @@ rm_status rm_tile_shape(int32_t prec, int32_t shape, int32_t *tile, int32_t *ene
   return RM_OK;
 }
 
-rm_status rm_get_tile(rm_ctx *ctx, int32_t prec, int32_t bucket, int32_t *shape) {
+static rm_status rm_get_tile_body(rm_ctx *ctx, int32_t prec, int32_t bucket, int32_t *shape) {
   if (!ctx || !shape || rm_tile_count(prec) == 0 || bucket < 0 || bucket >= NBUCKET) return RM_E_ARG;
   std::lock_guard<std::mutex> g(ctx->mu);
   *shape = ctx->tile[prec == RM_FP32_SPLIT][bucket];
   return RM_OK;
 }
 
-rm_status rm_set_tile(rm_ctx *ctx, int32_t prec, int32_t bucket, int32_t shape) {
+static rm_status rm_set_tile_body(rm_ctx *ctx, int32_t prec, int32_t bucket, int32_t shape) {
   if (!ctx || shape < 0 || shape >= rm_tile_count(prec) || bucket < 0 || bucket >= NBUCKET) return RM_E_ARG;
   std::lock_guard<std::mutex> g(ctx->mu);
   ctx->tile[prec == RM_FP32_SPLIT][bucket] = shape;
   return RM_OK;
 }
 
-rm_status rm_tune(rm_ctx *ctx, int32_t prec, const int32_t *pw_ids, int32_t npw, const double *E, int32_t ne,
-                  int32_t reps, const char *cache_path, double *ms) {
+static rm_status rm_tune_body(rm_ctx *ctx, int32_t prec, const int32_t *pw_ids, int32_t npw, const double *E,
+                              int32_t ne, int32_t reps, const char *cache_path, double *ms) {
   if (!ctx || rm_tile_count(prec) == 0 || !pw_ids || npw < 1 || !E || ne < 1 || reps < 1) return RM_E_ARG;
   (void)hipSetDevice(ctx->device);
   const int split = prec == RM_FP32_SPLIT, ns = nrtile(split);
@@ -1957,7 +1975,7 @@ rm_status rm_tune(rm_ctx *ctx, int32_t prec, const int32_t *pw_ids, int32_t npw,
   return RM_OK;
 }
 
-rm_status rm_tune_load(rm_ctx *ctx, const char *cache_path) {
+static rm_status rm_tune_load_body(rm_ctx *ctx, const char *cache_path) {
   if (!ctx || !cache_path) return RM_E_ARG;
   FILE *f = std::fopen(cache_path, "r");
   if (!f) {
@@ -2027,7 +2045,7 @@ rm_status rm_tune_load(rm_ctx *ctx, const char *cache_path) {
   return RM_OK;
 }
 
-rm_status rm_submit(rm_ctx *ctx, const rm_request *req, uint64_t *ticket) {
+static rm_status rm_submit_body(rm_ctx *ctx, const rm_request *req, uint64_t *ticket) {
   if (!ctx || !req || !ticket || req->ne < 0 || (req->ne > 0 && (!req->E || !req->omega || !req->status)) ||
       req->opts.device_ptrs)
     return RM_E_ARG;
@@ -2050,7 +2068,7 @@ rm_status rm_submit(rm_ctx *ctx, const rm_request *req, uint64_t *ticket) {
   return RM_OK;
 }
 
-rm_status rm_poll(rm_ctx *ctx, uint64_t ticket, rm_req_stats *st) {
+static rm_status rm_poll_body(rm_ctx *ctx, uint64_t ticket, rm_req_stats *st) {
   if (!ctx) return RM_E_ARG;
   std::lock_guard<std::mutex> g(ctx->mu);
   auto it = ctx->reqs.find(ticket);
@@ -2064,7 +2082,7 @@ rm_status rm_poll(rm_ctx *ctx, uint64_t ticket, rm_req_stats *st) {
   return res;
 }
 
-rm_status rm_drain(rm_ctx *ctx) {
+static rm_status rm_drain_body(rm_ctx *ctx) {
   if (!ctx) return RM_E_ARG;
   std::unique_lock<std::mutex> lk(ctx->mu);
   ctx->cv.wait(lk, [&] {
@@ -2075,13 +2093,14 @@ rm_status rm_drain(rm_ctx *ctx) {
   return RM_OK;
 }
 
-rm_status rm_prof_enable(rm_ctx *ctx, int32_t on) {
+static rm_status rm_prof_enable_body(rm_ctx *ctx, int32_t on) {
   if (!ctx) return RM_E_ARG;
   ctx->prof_on.store(on ? 1 : 0);
   return RM_OK;
 }
 
-rm_status rm_prof_read(rm_ctx *ctx, const char *stage, double *total_ms, int64_t *launches, int64_t *energies) {
+static rm_status rm_prof_read_body(rm_ctx *ctx, const char *stage, double *total_ms, int64_t *launches,
+                                   int64_t *energies) {
   if (!ctx || !stage) return RM_E_ARG;
   int id = -1;
   for (int i = 0; i < NSTAGE; ++i)
@@ -2111,8 +2130,8 @@ rm_status rm_prof_read(rm_ctx *ctx, const char *stage, double *total_ms, int64_t
   return st;
 }
 
-rm_status rm_prof_chunks(rm_ctx *ctx, int64_t cap, double *ms, double *model_flops, double *open_frac,
-                         int64_t *energies, int64_t *count) {
+static rm_status rm_prof_chunks_body(rm_ctx *ctx, int64_t cap, double *ms, double *model_flops, double *open_frac,
+                                     int64_t *energies, int64_t *count) {
   if (!ctx || !count || cap < 0 || (cap > 0 && (!ms || !model_flops || !open_frac || !energies))) return RM_E_ARG;
   std::vector<ProfRec> mine;
   {
@@ -2222,8 +2241,8 @@ rm_status mqdt_coarse(rm_ctx *ctx, const DevPW *pw, const double *E, int ne, con
 
 extern "C" {
 
-rm_status rm_mqdt_unphysical_K(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, double fnumin,
-                               const rm_opts *opts, double *Ku, int32_t *nmember, int32_t *status) {
+static rm_status rm_mqdt_unphysical_K_body(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, double fnumin,
+                                           const rm_opts *opts, double *Ku, int32_t *nmember, int32_t *status) {
   if (!ctx || ne < 0 || (ne > 0 && (!E || !Ku || !nmember || !status))) return RM_E_ARG;
   const DevPW *pw;
   if (rm_status st = get_pw(ctx, pwid, &pw)) return st;
@@ -2245,8 +2264,8 @@ void rm_mqdt_opts_default(rm_mqdt_opts *o) {
   o->qetest = 1e-7;
 }
 
-rm_status rm_run_mqdt(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, const rm_mqdt_opts *mq,
-                      const rm_opts *opts, double *omega, double *K, int8_t *coarse, int32_t *status) {
+static rm_status rm_run_mqdt_body(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, const rm_mqdt_opts *mq,
+                                  const rm_opts *opts, double *omega, double *K, int8_t *coarse, int32_t *status) {
   if (!ctx || ne < 0 || (ne > 0 && (!E || !omega || !status))) return RM_E_ARG;
   rm_mqdt_opts q;
   rm_mqdt_opts_default(&q);
@@ -2496,6 +2515,265 @@ rm_status rm_run_mqdt(rm_ctx *ctx, int32_t pwid, const double *E, int32_t ne, co
   // the temporaries are freed on return: the work that reads them completes first
   HIPCHK(hipStreamSynchronize(s));
   return staged_leave(ctx, o, ev);
+}
+
+}  // extern "C"
+
+// ===================================================== C ABI entry points
+// Each forwards to its body above; an exception never crosses into a C caller.
+extern "C" {
+
+rm_status rm_create(int device, size_t hbm_budget_bytes, rm_ctx **out) {
+  try {
+    return rm_create_body(device, hbm_budget_bytes, out);
+  } catch (...) {
+    return abi_failed_create(device);
+  }
+}
+
+rm_status rm_destroy(rm_ctx *ctx) {
+  try {
+    return rm_destroy_body(ctx);
+  } catch (...) {
+    return abi_failed(ctx);
+  }
+}
+
+rm_status rm_pw_upload(rm_ctx *ctx, const rm_pw_desc *desc, int32_t *pw_id) {
+  try {
+    return rm_pw_upload_body(ctx, desc, pw_id);
+  } catch (...) {
+    return abi_failed(ctx);
+  }
+}
+
+rm_status rm_pw_release(rm_ctx *ctx, int32_t pw_id) {
+  try {
+    return rm_pw_release_body(ctx, pw_id);
+  } catch (...) {
+    return abi_failed(ctx);
+  }
+}
+
+rm_status rm_pw_upload_coupled(rm_ctx *ctx, const rm_pw_desc *desc, int32_t lamax, const double *cf, double r1,
+                               int32_t *pw_id) {
+  try {
+    return rm_pw_upload_coupled_body(ctx, desc, lamax, cf, r1, pw_id);
+  } catch (...) {
+    return abi_failed(ctx);
+  }
+}
+
+rm_status rm_set_propagation(rm_ctx *ctx, int32_t npts, int32_t stab) {
+  try {
+    return rm_set_propagation_body(ctx, npts, stab);
+  } catch (...) {
+    return abi_failed(ctx);
+  }
+}
+
+rm_status rm_propagate(rm_ctx *ctx, int32_t pw, const double *E, int32_t ne, const rm_opts *opts, double *phi,
+                       double *dphi, int32_t *status) {
+  try {
+    return rm_propagate_body(ctx, pw, E, ne, opts, phi, dphi, status);
+  } catch (...) {
+    return abi_failed(ctx);
+  }
+}
+
+rm_status rm_mqdt_unphysical_K(rm_ctx *ctx, int32_t pw, const double *E, int32_t ne, double fnumin, const rm_opts *opts,
+                               double *Ku, int32_t *nmember, int32_t *status) {
+  try {
+    return rm_mqdt_unphysical_K_body(ctx, pw, E, ne, fnumin, opts, Ku, nmember, status);
+  } catch (...) {
+    return abi_failed(ctx);
+  }
+}
+
+rm_status rm_run_mqdt(rm_ctx *ctx, int32_t pw, const double *E, int32_t ne, const rm_mqdt_opts *mq, const rm_opts *opts,
+                      double *omega, double *K, int8_t *coarse, int32_t *status) {
+  try {
+    return rm_run_mqdt_body(ctx, pw, E, ne, mq, opts, omega, K, coarse, status);
+  } catch (...) {
+    return abi_failed(ctx);
+  }
+}
+
+rm_status rm_form_R(rm_ctx *ctx, int32_t pw, const double *E, int32_t ne, const rm_opts *opts, double *R,
+                    int32_t *status) {
+  try {
+    return rm_form_R_body(ctx, pw, E, ne, opts, R, status);
+  } catch (...) {
+    return abi_failed(ctx);
+  }
+}
+
+rm_status rm_asymptotic(rm_ctx *ctx, int32_t pw, const double *E, int32_t ne, const rm_opts *opts, double *fg,
+                        int8_t *open, int32_t *nopen, int32_t *status) {
+  try {
+    return rm_asymptotic_body(ctx, pw, E, ne, opts, fg, open, nopen, status);
+  } catch (...) {
+    return abi_failed(ctx);
+  }
+}
+
+rm_status rm_solve_K(rm_ctx *ctx, int32_t pw, const double *E, int32_t ne, const double *R, const double *fg,
+                     const rm_opts *opts, double *K, int32_t *status) {
+  try {
+    return rm_solve_K_body(ctx, pw, E, ne, R, fg, opts, K, status);
+  } catch (...) {
+    return abi_failed(ctx);
+  }
+}
+
+rm_status rm_collision_strengths(rm_ctx *ctx, int32_t pw, const double *E, int32_t ne, const double *K,
+                                 const rm_opts *opts, double *omega, double *S, int32_t *status) {
+  try {
+    return rm_collision_strengths_body(ctx, pw, E, ne, K, opts, omega, S, status);
+  } catch (...) {
+    return abi_failed(ctx);
+  }
+}
+
+rm_status rm_run(rm_ctx *ctx, int32_t pw, const double *E, int32_t ne, const rm_opts *opts, double *omega, double *K,
+                 int32_t *status) {
+  try {
+    return rm_run_body(ctx, pw, E, ne, opts, omega, K, status);
+  } catch (...) {
+    return abi_failed(ctx);
+  }
+}
+
+rm_status rm_run_noalloc(rm_ctx *ctx, int32_t pw, const double *E, int32_t ne, const rm_opts *opts, double *omega,
+                         double *K, int32_t *status) {
+  try {
+    return rm_run_noalloc_body(ctx, pw, E, ne, opts, omega, K, status);
+  } catch (...) {
+    return abi_failed(ctx);
+  }
+}
+
+rm_status rm_run_batch(rm_ctx *ctx, const rm_batch_item *items, int32_t nitems, const rm_opts *opts) {
+  try {
+    return rm_run_batch_body(ctx, items, nitems, opts);
+  } catch (...) {
+    return abi_failed(ctx);
+  }
+}
+
+rm_status rm_set_graph(rm_ctx *ctx, int32_t on) {
+  try {
+    return rm_set_graph_body(ctx, on);
+  } catch (...) {
+    return abi_failed(ctx);
+  }
+}
+
+rm_status rm_graph_stats(rm_ctx *ctx, int64_t *captures, int64_t *replays) {
+  try {
+    return rm_graph_stats_body(ctx, captures, replays);
+  } catch (...) {
+    return abi_failed(ctx);
+  }
+}
+
+rm_status rm_run_sum(rm_ctx *ctx, const int32_t *pw_ids, int32_t npw, const double *E, int32_t ne, int32_t order,
+                     const rm_opts *opts, double *omega, int32_t *status) {
+  try {
+    return rm_run_sum_body(ctx, pw_ids, npw, E, ne, order, opts, omega, status);
+  } catch (...) {
+    return abi_failed(ctx);
+  }
+}
+
+rm_status rm_tile_shape(int32_t prec, int32_t shape, int32_t *tile, int32_t *energies) {
+  try {
+    return rm_tile_shape_body(prec, shape, tile, energies);
+  } catch (...) {
+    return abi_failed(nullptr);
+  }
+}
+
+rm_status rm_get_tile(rm_ctx *ctx, int32_t prec, int32_t bucket, int32_t *shape) {
+  try {
+    return rm_get_tile_body(ctx, prec, bucket, shape);
+  } catch (...) {
+    return abi_failed(ctx);
+  }
+}
+
+rm_status rm_set_tile(rm_ctx *ctx, int32_t prec, int32_t bucket, int32_t shape) {
+  try {
+    return rm_set_tile_body(ctx, prec, bucket, shape);
+  } catch (...) {
+    return abi_failed(ctx);
+  }
+}
+
+rm_status rm_tune(rm_ctx *ctx, int32_t prec, const int32_t *pw_ids, int32_t npw, const double *E, int32_t ne,
+                  int32_t reps, const char *cache_path, double *ms) {
+  try {
+    return rm_tune_body(ctx, prec, pw_ids, npw, E, ne, reps, cache_path, ms);
+  } catch (...) {
+    return abi_failed(ctx);
+  }
+}
+
+rm_status rm_tune_load(rm_ctx *ctx, const char *cache_path) {
+  try {
+    return rm_tune_load_body(ctx, cache_path);
+  } catch (...) {
+    return abi_failed(ctx);
+  }
+}
+
+rm_status rm_submit(rm_ctx *ctx, const rm_request *req, uint64_t *ticket) {
+  try {
+    return rm_submit_body(ctx, req, ticket);
+  } catch (...) {
+    return abi_failed(ctx);
+  }
+}
+
+rm_status rm_poll(rm_ctx *ctx, uint64_t ticket, rm_req_stats *st) {
+  try {
+    return rm_poll_body(ctx, ticket, st);
+  } catch (...) {
+    return abi_failed(ctx);
+  }
+}
+
+rm_status rm_drain(rm_ctx *ctx) {
+  try {
+    return rm_drain_body(ctx);
+  } catch (...) {
+    return abi_failed(ctx);
+  }
+}
+
+rm_status rm_prof_enable(rm_ctx *ctx, int32_t on) {
+  try {
+    return rm_prof_enable_body(ctx, on);
+  } catch (...) {
+    return abi_failed(ctx);
+  }
+}
+
+rm_status rm_prof_read(rm_ctx *ctx, const char *stage, double *total_ms, int64_t *launches, int64_t *energies) {
+  try {
+    return rm_prof_read_body(ctx, stage, total_ms, launches, energies);
+  } catch (...) {
+    return abi_failed(ctx);
+  }
+}
+
+rm_status rm_prof_chunks(rm_ctx *ctx, int64_t cap, double *ms, double *model_flops, double *open_frac,
+                         int64_t *energies, int64_t *count) {
+  try {
+    return rm_prof_chunks_body(ctx, cap, ms, model_flops, open_frac, energies, count);
+  } catch (...) {
+    return abi_failed(ctx);
+  }
 }
 
 }  // extern "C"

@@ -967,6 +967,27 @@ rm_status staged_leave(rm_ctx *ctx, const rm_opts &o, hipEvent_t ev) {
 // work until the waiter has formed its chunk (with the whole free budget).  A
 // shape that would not fit even with every other workspace released fails its
 // requests with RM_E_NOMEM.
+// Ends a serving chunk whose forming or run threw: waits for what the slot's
+// stream already has in flight (it may still write the requests' host
+// buffers), then counts the energies each request gave to the chunk as done,
+// with RM_E_NOMEM.  P.parts and owners grow in step, parts first.
+void chunk_failed(rm_ctx *ctx, Slot *slot, const std::vector<Req *> &owners, const Plan &P) noexcept {
+  if (slot->stream) (void)hipStreamSynchronize(slot->stream);
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  for (size_t i = 0; i < owners.size() && i < P.parts.size(); ++i) {
+    Req *r = owners[i];
+    r->inflight--;
+    r->done_e += P.parts[i].m;
+    r->err = RM_E_NOMEM;
+    if (r->done_e >= r->rq.ne) r->st.t_done_ns = now_ns();
+  }
+  try {
+    ctx->err = "out of host memory in a serving worker (its chunk's requests end with RM_E_NOMEM)";
+  } catch (...) {
+  }
+  ctx->cv.notify_all();
+}
+
 void worker_main(rm_ctx *ctx, Slot *slot) {
   (void)hipSetDevice(ctx->device);
   for (;;) {
@@ -975,156 +996,162 @@ void worker_main(rm_ctx *ctx, Slot *slot) {
     Plan P;
     rm_opts o;
     Work released;
-    {
-      std::unique_lock<std::mutex> lk(ctx->mu);
-      ctx->cv.wait(lk, [&] {
-        if (ctx->stop) return true;
-        if (ctx->mem_waiter && ctx->mem_waiter != slot) return slot->w.bytes > 0;
-        for (Req *q : ctx->active)
-          if (q->next_e < q->rq.ne) return true;
-        return false;
-      });
-      if (ctx->stop) return;
-      if (ctx->mem_waiter && ctx->mem_waiter != slot) {
-        // another worker waits for memory: hand this workspace back (freed
-        // outside the lock; the slot's stream is idle between chunks)
-        released = slot->w;
-        slot->w = Work();
-        ctx->work_bytes -= released.bytes;
-      }
-    }
-    if (released.bytes) {
-      free_work(released);
-      std::lock_guard<std::mutex> lk(ctx->mu);
-      ctx->cv.notify_all();
-      continue;
-    }
-    {
-      std::unique_lock<std::mutex> lk(ctx->mu);
-      const Req *first = nullptr;
-      for (Req *q : ctx->active)
-        if (q->next_e < q->rq.ne) {
-          first = q;
-          break;
+    try {
+      {
+        std::unique_lock<std::mutex> lk(ctx->mu);
+        ctx->cv.wait(lk, [&] {
+          if (ctx->stop) return true;
+          if (ctx->mem_waiter && ctx->mem_waiter != slot) return slot->w.bytes > 0;
+          for (Req *q : ctx->active)
+            if (q->next_e < q->rq.ne) return true;
+          return false;
+        });
+        if (ctx->stop) return;
+        if (ctx->mem_waiter && ctx->mem_waiter != slot) {
+          // another worker waits for memory: hand this workspace back (freed
+          // outside the lock; the slot's stream is idle between chunks)
+          released = slot->w;
+          slot->w = Work();
+          ctx->work_bytes -= released.bytes;
         }
-      if (!first) continue;
-      // the options of the earliest request with work decide the chunk's
-      o = fixed_opts(&first->rq.opts);
-      o.device_ptrs = 0;
-      o.stream = nullptr;
-      // requests join the chunk only if every option the chunk's kernels read
-      // (precision, near-pole window, threshold guard) equals the first one's
-      auto compatible = [&](const Req *q) {
-        const rm_opts f = fixed_opts(&q->rq.opts);
-        return f.prec == o.prec && f.split_delta == o.split_delta && f.thr_guard == o.thr_guard;
-      };
-      // largest member shapes decide the per-energy footprint
-      const size_t used = ctx->resident + ctx->work_bytes - slot->w.bytes;
-      const size_t avail = ctx->budget > used ? ctx->budget - used : 0;
-      size_t share = ctx->mem_waiter == slot ? avail : avail / std::max<size_t>(ctx->slots.size(), 1);
-      int n = 0, npad = 0, Mpad = 0, nt = 0, npc = 0;
-      for (Req *q : ctx->active) {
-        if (q->next_e >= q->rq.ne || !compatible(q)) continue;
-        auto it = ctx->pws.find(q->rq.pw_id);
-        if (it == ctx->pws.end()) continue;
-        n = std::max(n, it->second.n);
-        npad = std::max(npad, it->second.npad);
-        Mpad = std::max(Mpad, it->second.Mpad);
-        nt = std::max(nt, it->second.nt);
-        if (it->second.lamax) npc = std::max(npc, it->second.npad);
       }
-      const size_t one = n ? per_energy_bytes(n, npad, Mpad, nt, npc) + kChunkFixedBytes : 0;
-      if (one > share) {
-        size_t others = 0;  // releasable by the other serving workers
-        for (const auto &sl : ctx->slots)
-          if (sl.get() != slot) others += sl->w.bytes;
-        if (one <= avail) {
-          share = avail;  // fits once this worker takes the whole free budget
-        } else if (one <= avail + others) {
-          if (!ctx->mem_waiter) ctx->mem_waiter = slot;
+      if (released.bytes) {
+        free_work(released);
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->cv.notify_all();
+        continue;
+      }
+      {
+        std::unique_lock<std::mutex> lk(ctx->mu);
+        const Req *first = nullptr;
+        for (Req *q : ctx->active)
+          if (q->next_e < q->rq.ne) {
+            first = q;
+            break;
+          }
+        if (!first) continue;
+        // the options of the earliest request with work decide the chunk's
+        o = fixed_opts(&first->rq.opts);
+        o.device_ptrs = 0;
+        o.stream = nullptr;
+        // requests join the chunk only if every option the chunk's kernels read
+        // (precision, near-pole window, threshold guard) equals the first one's
+        auto compatible = [&](const Req *q) {
+          const rm_opts f = fixed_opts(&q->rq.opts);
+          return f.prec == o.prec && f.split_delta == o.split_delta && f.thr_guard == o.thr_guard;
+        };
+        // largest member shapes decide the per-energy footprint
+        const size_t used = ctx->resident + ctx->work_bytes - slot->w.bytes;
+        const size_t avail = ctx->budget > used ? ctx->budget - used : 0;
+        size_t share = ctx->mem_waiter == slot ? avail : avail / std::max<size_t>(ctx->slots.size(), 1);
+        int n = 0, npad = 0, Mpad = 0, nt = 0, npc = 0;
+        for (Req *q : ctx->active) {
+          if (q->next_e >= q->rq.ne || !compatible(q)) continue;
+          auto it = ctx->pws.find(q->rq.pw_id);
+          if (it == ctx->pws.end()) continue;
+          n = std::max(n, it->second.n);
+          npad = std::max(npad, it->second.npad);
+          Mpad = std::max(Mpad, it->second.Mpad);
+          nt = std::max(nt, it->second.nt);
+          if (it->second.lamax) npc = std::max(npc, it->second.npad);
+        }
+        const size_t one = n ? per_energy_bytes(n, npad, Mpad, nt, npc) + kChunkFixedBytes : 0;
+        if (one > share) {
+          size_t others = 0;  // releasable by the other serving workers
+          for (const auto &sl : ctx->slots)
+            if (sl.get() != slot) others += sl->w.bytes;
+          if (one <= avail) {
+            share = avail;  // fits once this worker takes the whole free budget
+          } else if (one <= avail + others) {
+            if (!ctx->mem_waiter) ctx->mem_waiter = slot;
+            ctx->cv.notify_all();
+            if (ctx->mem_waiter != slot) ctx->cv.wait(lk);
+            else
+              ctx->cv.wait(lk, [&] {
+                return ctx->stop || ctx->resident + ctx->work_bytes - slot->w.bytes + one <= ctx->budget;
+              });
+            continue;
+          } else {
+            // cannot fit even alone: fail the compatible requests of this shape
+            for (Req *q : ctx->active) {
+              if (q->next_e >= q->rq.ne || !compatible(q)) continue;
+              auto it = ctx->pws.find(q->rq.pw_id);
+              if (it == ctx->pws.end() || it->second.n != n) continue;
+              q->err = RM_E_NOMEM;
+              q->done_e = q->next_e = q->rq.ne;
+              q->st.t_done_ns = now_ns();
+            }
+            ctx->err = "a request's per-energy workspace exceeds the HBM budget";
+            if (ctx->mem_waiter == slot) ctx->mem_waiter = nullptr;
+            ctx->cv.notify_all();
+            continue;
+          }
+        }
+        if (ctx->mem_waiter == slot) {
+          ctx->mem_waiter = nullptr;
           ctx->cv.notify_all();
-          if (ctx->mem_waiter != slot) ctx->cv.wait(lk);
-          else
-            ctx->cv.wait(lk, [&] {
-              return ctx->stop || ctx->resident + ctx->work_bytes - slot->w.bytes + one <= ctx->budget;
-            });
-          continue;
-        } else {
-          // cannot fit even alone: fail the compatible requests of this shape
-          for (Req *q : ctx->active) {
-            if (q->next_e >= q->rq.ne || !compatible(q)) continue;
-            auto it = ctx->pws.find(q->rq.pw_id);
-            if (it == ctx->pws.end() || it->second.n != n) continue;
-            q->err = RM_E_NOMEM;
+        }
+        int room = n ? chunk_cap(n, npad, Mpad, nt, share, 256, npc) : 0;
+        for (Req *q : ctx->active) {
+          if (room <= 0) break;
+          if (q->next_e >= q->rq.ne || !compatible(q)) continue;
+          auto it = ctx->pws.find(q->rq.pw_id);
+          if (it == ctx->pws.end()) {
+            q->err = RM_E_NOTFOUND;
             q->done_e = q->next_e = q->rq.ne;
             q->st.t_done_ns = now_ns();
+            continue;
           }
-          ctx->err = "a request's per-energy workspace exceeds the HBM budget";
-          if (ctx->mem_waiter == slot) ctx->mem_waiter = nullptr;
-          ctx->cv.notify_all();
-          continue;
+          const int take = std::min(room, q->rq.ne - q->next_e);
+          Seg g;
+          g.pw = &it->second;
+          g.E = q->E.data();
+          g.ne = q->rq.ne;
+          g.omega = q->rq.omega;
+          g.K = q->rq.K;
+          g.status = q->rq.status;
+          P.parts.push_back(Part{(int)segs.size(), q->next_e, take, 0, 0});
+          segs.push_back(g);
+          owners.push_back(q);
+          q->next_e += take;
+          q->inflight++;
+          room -= take;
+          const int64_t t = now_ns();
+          if (!q->admitted) {
+            q->admitted = true;
+            q->st.t_admit_ns = t;
+          }
+          if (!q->st.t_start_ns) q->st.t_start_ns = t;
+          q->st.nblocks++;
         }
-      }
-      if (ctx->mem_waiter == slot) {
-        ctx->mem_waiter = nullptr;
         ctx->cv.notify_all();
       }
-      int room = n ? chunk_cap(n, npad, Mpad, nt, share, 256, npc) : 0;
-      for (Req *q : ctx->active) {
-        if (room <= 0) break;
-        if (q->next_e >= q->rq.ne || !compatible(q)) continue;
-        auto it = ctx->pws.find(q->rq.pw_id);
-        if (it == ctx->pws.end()) {
-          q->err = RM_E_NOTFOUND;
-          q->done_e = q->next_e = q->rq.ne;
-          q->st.t_done_ns = now_ns();
-          continue;
-        }
-        const int take = std::min(room, q->rq.ne - q->next_e);
-        Seg g;
-        g.pw = &it->second;
-        g.E = q->E.data();
-        g.ne = q->rq.ne;
-        g.omega = q->rq.omega;
-        g.K = q->rq.K;
-        g.status = q->rq.status;
-        P.parts.push_back(Part{(int)segs.size(), q->next_e, take, 0, 0});
-        segs.push_back(g);
-        owners.push_back(q);
-        q->next_e += take;
-        q->inflight++;
-        room -= take;
-        const int64_t t = now_ns();
-        if (!q->admitted) {
-          q->admitted = true;
-          q->st.t_admit_ns = t;
-        }
-        if (!q->st.t_start_ns) q->st.t_start_ns = t;
-        q->st.nblocks++;
+      if (P.parts.empty()) continue;
+      int ne = 0;
+      for (Part &pt : P.parts) {
+        pt.e0 = ne;
+        ne += pt.m;
       }
-      ctx->cv.notify_all();
-    }
-    if (P.parts.empty()) continue;
-    int ne = 0;
-    for (Part &pt : P.parts) {
-      pt.e0 = ne;
-      ne += pt.m;
-    }
-    finish_plan(P, segs, ne);
-    rm_status st = ensure_slot(ctx, *slot, P.L, (int)P.slots.size(), plan_tasks(ctx, P, o), false);
-    if (st == RM_OK) st = upload_plan(ctx, *slot, P, segs, o, false);
-    if (st == RM_OK) st = run_chunk(ctx, P, *slot, segs, o, hipMemcpyDeviceToHost);
-    if (st == RM_OK && hipStreamSynchronize(slot->stream) != hipSuccess) st = RM_E_DEVICE;
-    {
-      std::lock_guard<std::mutex> lk(ctx->mu);
-      for (size_t i = 0; i < owners.size(); ++i) {
-        Req *r = owners[i];
-        r->inflight--;
-        r->done_e += P.parts[i].m;
-        if (st != RM_OK) r->err = st;
-        if (r->done_e >= r->rq.ne) r->st.t_done_ns = now_ns();
+      finish_plan(P, segs, ne);
+      rm_status st = ensure_slot(ctx, *slot, P.L, (int)P.slots.size(), plan_tasks(ctx, P, o), false);
+      if (st == RM_OK) st = upload_plan(ctx, *slot, P, segs, o, false);
+      if (st == RM_OK) st = run_chunk(ctx, P, *slot, segs, o, hipMemcpyDeviceToHost);
+      if (st == RM_OK && hipStreamSynchronize(slot->stream) != hipSuccess) st = RM_E_DEVICE;
+      {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        for (size_t i = 0; i < owners.size(); ++i) {
+          Req *r = owners[i];
+          r->inflight--;
+          r->done_e += P.parts[i].m;
+          if (st != RM_OK) r->err = st;
+          if (r->done_e >= r->rq.ne) r->st.t_done_ns = now_ns();
+        }
+        ctx->cv.notify_all();
       }
-      ctx->cv.notify_all();
+    } catch (...) {
+      // a host allocation failed while this chunk was formed or run: its
+      // requests end with RM_E_NOMEM instead of the exception ending the process
+      chunk_failed(ctx, slot, owners, P);
     }
   }
 }

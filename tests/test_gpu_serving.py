@@ -129,3 +129,40 @@ def test_admission_defers_under_small_budget(ctx):
         assert np.array_equal(out["K"], K, equal_nan=True)
     for i in ref_ids:
         ctx.pw_release(i)
+
+
+def test_served_results_match_oracle(ctx):
+    """The served results against the oracle itself (FP64 gates), not only
+    against rm_run: four waves of 20..333 channels (the batching test's waves
+    and energies), two requests each, all queued together so that chunks mix
+    waves and requests."""
+    import oracle
+    from _metrics import gate, k_err, omega_elementwise, stats
+
+    sizes = [20, 45, 70, 131, 200, 333]
+    E = np.linspace(0.01, 6.0, 61)
+    keep = (0, 2, 4, 5)
+    pws = [synth.make_partial_wave(synth.config_seed(3) + 50 + i, sizes[i], 30, z=5.0, a=12.0,
+                                   thr_range=(0.0, 4.0), pole_range=(-2.0, 60.0), avoid_energies=E,
+                                   name=f"batch{i}") for i in keep]
+    ids = [ctx.pw_upload(p) for p in pws]
+    reqs = []
+    for sel in (E[::12], E[6::12]):
+        for k, pid in enumerate(ids):
+            t, out = ctx.submit(pid, sel, want_K=True)
+            reqs.append((k, sel, t, out))
+    ctx.drain()
+    for k, sel, t, out in reqs:
+        assert ctx.poll(t) is not None
+        p = pws[k]
+        ref = oracle.Oracle(p).run(sel)
+        assert (out["status"] == 0).all() and (ref["status"] == 0).all()
+        g = gate(ref["cond"])
+        errO = omega_elementwise(out["omega"], ref["omega"])
+        errK = k_err(out["K"], ref["K"], oracle.open_count(p, sel))
+        print(f"served wave of {p.nchan} channels, {sel.size} energies: K {stats(errK)}, Omega {stats(errO)}",
+              flush=True)
+        assert (errO <= g).all(), (errO, g)
+        assert (errK <= g).all(), (errK, g)
+    for pid in ids:
+        ctx.pw_release(pid)

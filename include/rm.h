@@ -41,7 +41,7 @@
  *
  * Threading: a context may be used from one thread at a time, except that
  * rm_submit and rm_poll may be called from any single thread while the
- * context's scheduler thread runs the admitted work.
+ * context's serving worker threads run the admitted work.
  */
 #ifndef RM_H
 #define RM_H
@@ -98,8 +98,9 @@ void rm_opts_default(rm_opts *o);
 /* ---------------------------------------------------------------- context */
 /* Creates a context on HIP device `device`.  hbm_budget_bytes bounds the device
    memory the context holds at once (resident partial waves plus workspaces);
-   0 means 90% of the device's free memory.  The context keeps one HIP stream of
-   default priority and one scheduler thread for rm_submit. */
+   0 means 90% of the device's free memory.  Every HIP stream the context makes
+   has the default priority: those of the direct calls (some made on first use)
+   and one for each of its two serving worker threads (rm_submit). */
 rm_status rm_create(int device, size_t hbm_budget_bytes, rm_ctx **out);
 rm_status rm_destroy(rm_ctx *ctx);
 /* Text of the last error on this context (never NULL; "" if none).  ctx =
@@ -436,8 +437,11 @@ typedef struct {
    the in-flight slots allow, so requests that arrive while others run are
    interleaved with them on the device.  RM_E_BUSY if the queue is full. */
 rm_status rm_submit(rm_ctx *ctx, const rm_request *req, uint64_t *ticket);
-/* RM_OK (done; outputs written, ticket retired), RM_PENDING, or an error.  st
-   may be NULL. */
+/* RM_OK (done; outputs written, ticket retired), RM_PENDING, or the error of
+   one of the request's chunks (ticket retired): RM_E_NOMEM when one energy's
+   workspace exceeds the HBM budget or a host allocation in the worker failed,
+   RM_E_NOTFOUND when its partial wave was released, RM_E_DEVICE when a HIP call
+   failed.  Energies of a failed chunk hold no results.  st may be NULL. */
 rm_status rm_poll(rm_ctx *ctx, uint64_t ticket, rm_req_stats *st);
 /* Blocks until every submitted request is done. */
 rm_status rm_drain(rm_ctx *ctx);

@@ -441,7 +441,8 @@ rm_status rm_submit(rm_ctx *ctx, const rm_request *req, uint64_t *ticket);
    one of the request's chunks (ticket retired): RM_E_NOMEM when one energy's
    workspace exceeds the HBM budget or a host allocation in the worker failed,
    RM_E_NOTFOUND when its partial wave was released, RM_E_DEVICE when a HIP call
-   failed.  Energies of a failed chunk hold no results.  st may be NULL. */
+   failed.  The outputs of a failed chunk's energies are not valid.  st may be
+   NULL. */
 rm_status rm_poll(rm_ctx *ctx, uint64_t ticket, rm_req_stats *st);
 /* Blocks until every submitted request is done. */
 rm_status rm_drain(rm_ctx *ctx);

@@ -184,8 +184,9 @@ namespace {
   } while (0)
 
 constexpr int MAX_CHUNK = 1024;
-// workspace bytes of a chunk beyond its per-energy blocks (tables, task lists,
-// queue heads), an upper bound for the admission test
+// workspace bytes of a chunk beyond its per-energy blocks (wave tables, queue
+// heads, the 256-byte rounding of each buffer), an upper bound for the
+// admission test
 constexpr size_t kChunkFixedBytes = 16u << 20;
 constexpr double TUNE_MARGIN = 0.03;
 
@@ -198,7 +199,10 @@ size_t per_energy_bytes(int n, int npad, int Mpad, int nt, int npc = 0) {
          + (size_t)Mpad * 12         // D64 + D32
          + (size_t)n * (32 + 17)     // fg, openidx, openpos, colpos, openflag, ipiv
          + (size_t)nt * nt * 8       // Omega
-         + BPERM * 4 + NBU * NBU * 8 + 128;
+         + BPERM * 4 + NBU * NBU * 8 + 128
+         // R tasks: a part of m energies has ceil(m / eb) <= m batches of
+         // t (t + 1) / 2 tiles, most for the 16-channel tile
+         + (size_t)((n + 15) / 16) * ((n + 15) / 16 + 1) / 2 * sizeof(RTask);
 }
 
 // One buffer of a chunk workspace: where its pointer goes and its byte size.

@@ -307,7 +307,15 @@ rm_status ensure_slot(rm_ctx *ctx, Slot &sl, const Lay &L, int ntab, int ntasks,
       std::lock_guard<std::mutex> g(ctx->mu);
       ctx->work_bytes -= old;
     }
-    for (const WorkBuf &b : bufs) HIPCHK(hipMalloc(b.ptr, b.bytes));
+    for (const WorkBuf &b : bufs) {
+      const hipError_t e = hipMalloc(b.ptr, b.bytes);
+      if (e != hipSuccess) {
+        *b.ptr = nullptr;
+        free_work(nw);  // the buffers allocated before this one
+        ctx->err = std::string("hipMalloc (chunk workspace): ") + hipGetErrorString(e);
+        return e == hipErrorOutOfMemory ? RM_E_NOMEM : RM_E_DEVICE;
+      }
+    }
     w = nw;
     w.cap_e = ce;
     w.cap_n = cn;
@@ -1441,6 +1449,14 @@ rm_status rm_pw_upload_coupled_impl(rm_ctx *ctx, const rm_pw_desc *d, int32_t la
   }
   (void)hipSetDevice(ctx->device);
   DevPW p;
+  // an early return (a failed HIP call) frees what is allocated so far
+  struct Unwind {
+    DevPW &p;
+    bool keep = false;
+    ~Unwind() {
+      if (!keep) free_pw(p);
+    }
+  } unwind{p};
   p.n = d->nchan;
   p.M = d->npole;
   p.nt = d->ntarget;
@@ -1506,6 +1522,7 @@ rm_status rm_pw_upload_coupled_impl(rm_ctx *ctx, const rm_pw_desc *d, int32_t la
   std::lock_guard<std::mutex> g(ctx->mu);
   const int32_t id = ctx->next_id++;
   ctx->pws[id] = p;
+  unwind.keep = true;  // the context owns the buffers now
   ctx->hthr[&ctx->pws[id]].assign(d->e_thr, d->e_thr + p.n);
   ctx->resident += bytes;
   *pw_id = id;

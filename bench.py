@@ -112,6 +112,8 @@ def serve_measure(ctx, nreq: int, block_max: int, load: float = 0.7) -> dict:
         dt, _ = run_stream(burst, prec)
         capacity = float(cost[:16].sum()) / dt                       # flop/s, closed loop
         rate = load * capacity / float(cost.mean())                   # requests/s
+        log(f"serving {name}: capacity {capacity / 1e12:.1f} TFLOP/s from the first 16 requests ({dt:.1f} s); "
+            f"stream of {nreq} requests at {rate:.2f}/s follows")
         dt, stats = run_stream(base, prec, scale=1.0 / rate)
         lat = np.array([(st["t_done_ns"] - st["t_arrive_ns"]) * 1e-6 for st in stats])
         span = base[-1].arrival_s / rate                              # offered over the arrival window

@@ -147,3 +147,20 @@ def test_upload_checks_field_sizes_before_any_device_call():
         with pytest.raises(rm.RMError, match=f"pw_upload: {field} has"):
             ctx.pw_upload(dataclasses.replace(pw, **{field: bad}))
     assert np.asarray(pw.w).shape == (pw.npole, pw.nchan)
+
+
+def test_every_context_call_refuses_a_null_context():
+    """Each entry point that takes a context returns RM_E_ARG for a null one,
+    through the wrapper that keeps exceptions from the C caller, before any
+    device call (runs without a GPU)."""
+    from paper_1909_07321_amd import rm
+    text = open(os.path.join(ROOT, "include", "rm.h")).read()
+    names = sorted(set(re.findall(r"rm_status\s+(rm_\w+)\s*\(\s*(?:const\s+)?rm_ctx\s*\*", text)))
+    assert len(names) >= 28, names
+    zero = {ctypes.c_double: 0.0, ctypes.c_float: 0.0}
+    for name in names:
+        fn = getattr(rm._lib, name)
+        assert fn.argtypes, f"{name}: binding sets no argument types"
+        args = [zero.get(t, None if (t in (ctypes.c_void_p, ctypes.c_char_p) or hasattr(t, "_type_")
+                                     and not isinstance(t._type_, str)) else 0) for t in fn.argtypes]
+        assert fn(*args) == rm.RM_E_ARG, name

@@ -492,6 +492,9 @@ typedef struct rm_hdat rm_hdat;
    records); the symmetries follow with rm_hdat_next.  *out is set (and must be
    closed) even on error, so that rm_hdat_error can be read. */
 rm_status rm_hdat_open(const char *path, rm_hdat **out);
+/* Frees the handle; h = NULL is a no-op (RM_OK).  The other rm_hdat_* calls,
+   rm_sizeh_read and rm_omega_write return RM_E_ARG for a NULL handle, path or
+   required output. */
 rm_status rm_hdat_close(rm_hdat *h);
 const char *rm_hdat_error(const rm_hdat *h);
 /* Target records; enat [nast] (Ry), lat [nast] (L or 2J), isat [nast] (2S+1

@@ -158,3 +158,18 @@ def test_omega_writer(tmp_path, rm, nomwrt, elastic):
         for e in range(ne):
             assert body[e][0] == E[e] / z2
             assert body[e][1:] == [om[e, i, j] for i, j in tr]
+
+
+def test_file_calls_refuse_null_arguments():
+    """Every file-boundary call with NULL handle, path and outputs returns
+    RM_E_ARG without touching memory; closing a NULL handle is a no-op."""
+    import ctypes
+
+    from paper_1909_07321_amd import rm
+    for name in ("rm_hdat_open", "rm_hdat_target_info", "rm_hdat_attach", "rm_hdat_next", "rm_hdat_arrays",
+                 "rm_hdat_pw_desc", "rm_sizeh_read", "rm_omega_write", "rm_hdat_close"):
+        fn = getattr(rm._lib, name)
+        args = [0.0 if t is ctypes.c_double else
+                None if (t in (ctypes.c_void_p, ctypes.c_char_p) or not isinstance(getattr(t, "_type_", ""), str))
+                else 0 for t in fn.argtypes]
+        assert fn(*args) == (rm.RM_OK if name == "rm_hdat_close" else rm.RM_E_ARG), name
